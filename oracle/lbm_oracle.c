@@ -1,0 +1,515 @@
+/*
+ * FP64 CPU oracle for the D3Q27 cumulant lattice Boltzmann step on an
+ * obstructed channel.
+ *
+ * TEST INFRASTRUCTURE ONLY.  The product library never links, loads or calls
+ * this file; only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark do.  It shares no code, header or table with the GPU path.
+ *
+ * Structure: a plain two-lattice pull scheme.  Every step collides each fluid
+ * cell into a post-collision lattice, then pull-streams with the boundary
+ * substitutions into the next lattice.  All arithmetic is double precision.
+ *
+ * Passages followed (paper = "A Validated LBM Dataset and Pipeline for
+ * Surrogate Modeling of Turbulent 3D Obstructed Channel Flows"):
+ *   Sec. 3.1  channel 2x1x1, prescribed-velocity inlet, extrapolation outlet,
+ *             no-slip lateral walls, Re set through the lattice viscosity;
+ *   Sec. 3.2  D3Q27 cumulant collision; fourth-order parametrised variant
+ *             with limiter (switched off below Re_c 3000); interpolated
+ *             bounce-back using wall distances at the obstacle;
+ *   Sec. 2    mean velocity and pressure, snapshots every 25 steps, forces
+ *             on the object.
+ * The paper prints none of the operator's formulas (it cites the cumulant
+ * papers of Geier et al.); the readings taken here are listed in the design
+ * notes and restated at each function.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Lattice: c_i in {-1,0,1}^3, i = 9(cz+1) + 3(cy+1) + (cx+1), opposite 26-i.
+ * Weights are the tensor product of the 1D weights (1/6, 2/3, 1/6).          */
+static int CX[27], CY[27], CZ[27];
+static double WT[27];
+static int lattice_ready = 0;
+
+static void lattice_init(void) {
+  if (lattice_ready) return;
+  const double w1[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+  for (int i = 0; i < 27; ++i) {
+    int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+    CX[i] = cx; CY[i] = cy; CZ[i] = cz;
+    WT[i] = w1[cx + 1] * w1[cy + 1] * w1[cz + 1];
+  }
+  lattice_ready = 1;
+}
+
+void orc_lattice(int32_t* c, double* w) {
+  lattice_init();
+  for (int i = 0; i < 27; ++i) {
+    c[3 * i + 0] = CX[i]; c[3 * i + 1] = CY[i]; c[3 * i + 2] = CZ[i];
+    w[i] = WT[i];
+  }
+}
+
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t periodic[3];   /* 1 = periodic axis; else x: inlet/outlet, y,z: walls */
+  double omega1;         /* shear rate: 1/(3 nu + 1/2) */
+  double omega2;         /* bulk rate */
+  int32_t mode;          /* 0 plain cumulant, 1 fourth-order parametrised (K17) */
+  int32_t galilean;      /* 1 on, 0 off, -1 sign flipped (planted mistake) */
+  double lambda;         /* third-order limiter */
+  int32_t k17_given;     /* 1: take w3,w4,w5,A,B from k17[] */
+  double k17[5];
+  double u_in;           /* inlet velocity along +x */
+  double force[3];       /* uniform body force (tests only) */
+  int32_t obstacle_bc;   /* 0 halfway bounce-back, 1 linear interpolated */
+  int32_t emulate;       /* storage rounding: 0 none, 1 fp32, 2 fp16, 3 bf16 */
+  int32_t avg_start;     /* first step index sampled into the mean */
+  int32_t snap_every;    /* snapshot period (0 = none) */
+  int32_t snap_start;    /* first snapshot step index */
+} orc_params;
+
+/* ------------------------------------------------------------------------ */
+/* Equilibrium.  Product form of the discrete Maxwellian: its central moments
+ * are those of a Gaussian up to the lattice's representable orders, so every
+ * cumulant of order >= 3 vanishes (the cumulant method's equilibrium).       */
+static double phi1(int c, double a) {
+  if (c == 0) return 2.0 / 3.0 - a * a;
+  return 0.5 * (a * a + c * a + 1.0 / 3.0);
+}
+
+void orc_equilibrium(double rho, const double* u, double* fbar) {
+  lattice_init();
+  for (int i = 0; i < 27; ++i)
+    fbar[i] = rho * phi1(CX[i], u[0]) * phi1(CY[i], u[1]) * phi1(CZ[i], u[2]) - WT[i];
+}
+
+/* Central moments by definition: K_abc = sum_i f_i (cx-u)^a (cy-v)^b (cz-w)^c,
+ * stored at index 9a + 3b + c.                                               */
+void orc_central_moments(const double* f, const double* u, double* K) {
+  lattice_init();
+  for (int m = 0; m < 27; ++m) K[m] = 0.0;
+  for (int i = 0; i < 27; ++i) {
+    double dx = CX[i] - u[0], dy = CY[i] - u[1], dz = CZ[i] - u[2];
+    double px[3] = {1.0, dx, dx * dx}, py[3] = {1.0, dy, dy * dy}, pz[3] = {1.0, dz, dz * dz};
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        for (int c = 0; c < 3; ++c) K[9 * a + 3 * b + c] += f[i] * px[a] * py[b] * pz[c];
+  }
+}
+
+/* Inverse of the central-moment map.  The 27x27 map is the Kronecker product
+ * of one 3x3 map per axis; its inverse applies the inverse 3x3 map per axis:
+ * raw line moments r0 = m0, r1 = m1 + a m0, r2 = m2 + 2a m1 + a^2 m0, then
+ * f(0) = r0 - r2, f(+1) = (r2 + r1)/2, f(-1) = (r2 - r1)/2.                  */
+static void inv1d(double m0, double m1, double m2, double a, double* fm, double* f0, double* fp) {
+  double r0 = m0, r1 = m1 + a * m0, r2 = m2 + 2.0 * a * m1 + a * a * m0;
+  *f0 = r0 - r2;
+  *fp = 0.5 * (r2 + r1);
+  *fm = 0.5 * (r2 - r1);
+}
+
+void orc_populations_from_central(const double* K, const double* u, double* f) {
+  lattice_init();
+  double t1[27], t2[27];
+  /* axis x: exponent a -> velocity cx; t1[(cx+1)*9 + 3b + c] */
+  for (int b = 0; b < 3; ++b)
+    for (int c = 0; c < 3; ++c) {
+      double fm, f0, fp;
+      inv1d(K[0 * 9 + 3 * b + c], K[1 * 9 + 3 * b + c], K[2 * 9 + 3 * b + c], u[0], &fm, &f0, &fp);
+      t1[0 * 9 + 3 * b + c] = fm; t1[1 * 9 + 3 * b + c] = f0; t1[2 * 9 + 3 * b + c] = fp;
+    }
+  /* axis y */
+  for (int x = 0; x < 3; ++x)
+    for (int c = 0; c < 3; ++c) {
+      double fm, f0, fp;
+      inv1d(t1[9 * x + 0 + c], t1[9 * x + 3 + c], t1[9 * x + 6 + c], u[1], &fm, &f0, &fp);
+      t2[9 * x + 0 + c] = fm; t2[9 * x + 3 + c] = f0; t2[9 * x + 6 + c] = fp;
+    }
+  /* axis z, and scatter to population order i = 9(cz+1)+3(cy+1)+(cx+1) */
+  for (int x = 0; x < 3; ++x)
+    for (int y = 0; y < 3; ++y) {
+      double fm, f0, fp;
+      inv1d(t2[9 * x + 3 * y + 0], t2[9 * x + 3 * y + 1], t2[9 * x + 3 * y + 2], u[2], &fm, &f0, &fp);
+      f[0 * 9 + 3 * y + x] = fm; f[1 * 9 + 3 * y + x] = f0; f[2 * 9 + 3 * y + x] = fp;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cumulants from normalised central moments k = K/rho (index 9a+3b+c).
+ * Cumulant of a multiset of variables = sum over set partitions pi of
+ * (|pi|-1)! (-1)^(|pi|-1) prod_blocks E[prod]; first-order central moments
+ * are taken as zero in these products (they vanish without a body force,
+ * and with one they enter only the back-transform).  Orders 2 and 3 equal
+ * the moments; orders 4-6 are the partition sums written out.               */
+#define IX(a, b, c) (9 * (a) + 3 * (b) + (c))
+
+void orc_cumulants(const double* k, double* C) {
+  for (int m = 0; m < 27; ++m) C[m] = k[m];
+  const double k200 = k[IX(2,0,0)], k020 = k[IX(0,2,0)], k002 = k[IX(0,0,2)];
+  const double k110 = k[IX(1,1,0)], k101 = k[IX(1,0,1)], k011 = k[IX(0,1,1)];
+  /* order 4 */
+  C[IX(2,1,1)] = k[IX(2,1,1)] - k200 * k011 - 2.0 * k110 * k101;
+  C[IX(1,2,1)] = k[IX(1,2,1)] - k020 * k101 - 2.0 * k110 * k011;
+  C[IX(1,1,2)] = k[IX(1,1,2)] - k002 * k110 - 2.0 * k101 * k011;
+  C[IX(2,2,0)] = k[IX(2,2,0)] - k200 * k020 - 2.0 * k110 * k110;
+  C[IX(2,0,2)] = k[IX(2,0,2)] - k200 * k002 - 2.0 * k101 * k101;
+  C[IX(0,2,2)] = k[IX(0,2,2)] - k020 * k002 - 2.0 * k011 * k011;
+  /* order 5: minus all (pair, triple) partitions */
+  C[IX(2,2,1)] = k[IX(2,2,1)] - k200 * k[IX(0,2,1)] - k020 * k[IX(2,0,1)]
+               - 4.0 * k110 * k[IX(1,1,1)] - 2.0 * (k101 * k[IX(1,2,0)] + k011 * k[IX(2,1,0)]);
+  C[IX(2,1,2)] = k[IX(2,1,2)] - k200 * k[IX(0,1,2)] - k002 * k[IX(2,1,0)]
+               - 4.0 * k101 * k[IX(1,1,1)] - 2.0 * (k110 * k[IX(1,0,2)] + k011 * k[IX(2,0,1)]);
+  C[IX(1,2,2)] = k[IX(1,2,2)] - k020 * k[IX(1,0,2)] - k002 * k[IX(1,2,0)]
+               - 4.0 * k011 * k[IX(1,1,1)] - 2.0 * (k110 * k[IX(0,1,2)] + k101 * k[IX(0,2,1)]);
+  /* order 6 */
+  {
+    double p24 = k200 * k[IX(0,2,2)] + k020 * k[IX(2,0,2)] + k002 * k[IX(2,2,0)]
+               + 4.0 * (k110 * k[IX(1,1,2)] + k101 * k[IX(1,2,1)] + k011 * k[IX(2,1,1)]);
+    double p33 = 2.0 * (k[IX(2,1,0)] * k[IX(0,1,2)] + k[IX(2,0,1)] * k[IX(0,2,1)] + k[IX(1,2,0)] * k[IX(1,0,2)])
+               + 4.0 * k[IX(1,1,1)] * k[IX(1,1,1)];
+    double p222 = k200 * k020 * k002
+                + 2.0 * (k200 * k011 * k011 + k020 * k101 * k101 + k002 * k110 * k110)
+                + 8.0 * k110 * k101 * k011;
+    C[IX(2,2,2)] = k[IX(2,2,2)] - p24 - p33 + 2.0 * p222;
+  }
+}
+
+/* Moments from cumulants: E = sum over partitions (no singletons) of the
+ * product of the blocks' cumulants.                                          */
+void orc_moments_from_cumulants(const double* C, double* k) {
+  for (int m = 0; m < 27; ++m) k[m] = C[m];
+  const double c200 = C[IX(2,0,0)], c020 = C[IX(0,2,0)], c002 = C[IX(0,0,2)];
+  const double c110 = C[IX(1,1,0)], c101 = C[IX(1,0,1)], c011 = C[IX(0,1,1)];
+  k[IX(2,1,1)] = C[IX(2,1,1)] + c200 * c011 + 2.0 * c110 * c101;
+  k[IX(1,2,1)] = C[IX(1,2,1)] + c020 * c101 + 2.0 * c110 * c011;
+  k[IX(1,1,2)] = C[IX(1,1,2)] + c002 * c110 + 2.0 * c101 * c011;
+  k[IX(2,2,0)] = C[IX(2,2,0)] + c200 * c020 + 2.0 * c110 * c110;
+  k[IX(2,0,2)] = C[IX(2,0,2)] + c200 * c002 + 2.0 * c101 * c101;
+  k[IX(0,2,2)] = C[IX(0,2,2)] + c020 * c002 + 2.0 * c011 * c011;
+  k[IX(2,2,1)] = C[IX(2,2,1)] + c200 * C[IX(0,2,1)] + c020 * C[IX(2,0,1)]
+               + 4.0 * c110 * C[IX(1,1,1)] + 2.0 * (c101 * C[IX(1,2,0)] + c011 * C[IX(2,1,0)]);
+  k[IX(2,1,2)] = C[IX(2,1,2)] + c200 * C[IX(0,1,2)] + c002 * C[IX(2,1,0)]
+               + 4.0 * c101 * C[IX(1,1,1)] + 2.0 * (c110 * C[IX(1,0,2)] + c011 * C[IX(2,0,1)]);
+  k[IX(1,2,2)] = C[IX(1,2,2)] + c020 * C[IX(1,0,2)] + c002 * C[IX(1,2,0)]
+               + 4.0 * c011 * C[IX(1,1,1)] + 2.0 * (c110 * C[IX(0,1,2)] + c101 * C[IX(0,2,1)]);
+  {
+    double s24 = c200 * C[IX(0,2,2)] + c020 * C[IX(2,0,2)] + c002 * C[IX(2,2,0)]
+               + 4.0 * (c110 * C[IX(1,1,2)] + c101 * C[IX(1,2,1)] + c011 * C[IX(2,1,1)]);
+    double s33 = 2.0 * (C[IX(2,1,0)] * C[IX(0,1,2)] + C[IX(2,0,1)] * C[IX(0,2,1)] + C[IX(1,2,0)] * C[IX(1,0,2)])
+               + 4.0 * C[IX(1,1,1)] * C[IX(1,1,1)];
+    double s222 = c200 * c020 * c002
+                + 2.0 * (c200 * c011 * c011 + c020 * c101 * c101 + c002 * c110 * c110)
+                + 8.0 * c110 * c101 * c011;
+    k[IX(2,2,2)] = C[IX(2,2,2)] + s24 + s33 + s222;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rates of the fourth-order parametrised operator (Geier et al. 2017, cited
+ * in Sec. 3.2; the paper does not print them).  Closed forms in omega1 with
+ * omega2 entering as the bulk rate.                                          */
+void orc_k17_coefficients(double w1, double w2, double* out /* w3,w4,w5,A,B */) {
+  out[0] = 8.0 * (w1 - 2.0) * (w2 * (3.0 * w1 - 1.0) - 5.0 * w1)
+         / (8.0 * (5.0 - 2.0 * w1) * w1 + w2 * (8.0 + w1 * (9.0 * w1 - 26.0)));
+  out[1] = 8.0 * (w1 - 2.0) * (w1 + w2 * (3.0 * w1 - 7.0))
+         / (w2 * (56.0 - 42.0 * w1 + 9.0 * w1 * w1) - 8.0 * w1);
+  out[2] = 24.0 * (w1 - 2.0) * (4.0 * w1 * w1 + w1 * w2 * (18.0 - 13.0 * w1) + w2 * w2 * (2.0 + w1 * (6.0 * w1 - 11.0)))
+         / (16.0 * w1 * w1 * (w1 - 6.0) - 2.0 * w1 * w2 * (216.0 + 5.0 * w1 * (9.0 * w1 - 46.0))
+            + w2 * w2 * (w1 * (3.0 * w1 - 10.0) * (15.0 * w1 - 28.0) - 48.0));
+  out[3] = (4.0 * w1 * w1 + 2.0 * w1 * w2 * (w1 - 6.0) + w2 * w2 * (w1 * (10.0 - 3.0 * w1) - 4.0))
+         / ((w1 - w2) * (w2 * (2.0 + 3.0 * w1) - 8.0 * w1));
+  out[4] = (4.0 * w1 * w2 * (9.0 * w1 - 16.0) - 4.0 * w1 * w1 - 2.0 * w2 * w2 * (2.0 + 9.0 * w1 * (w1 - 2.0)))
+         / (3.0 * (w1 - w2) * (w2 * (2.0 + 3.0 * w1) - 8.0 * w1));
+}
+
+/* Limited rate: omega + (1 - omega) |c| / (lambda + |c|).                    */
+static double limited(double w, double c, double lambda) {
+  double a = fabs(c);
+  return w + (1.0 - w) * a / (lambda + a);
+}
+
+/* One collision of one cell.  fbar = f - w_i in, post-collision fbar out.
+ * Macroscopic: rho = sum f, u = (sum f c + F/2)/rho.  Cumulant relaxation:
+ *  - second order: omega1 on the deviatoric and off-diagonal parts, omega2 on
+ *    the trace, with the Galilean correction terms built from the velocity
+ *    gradients estimated out of the second-order non-equilibrium;
+ *  - plain mode: orders 3-6 relaxed to zero;
+ *  - K17 mode: third-order pair sums/differences and c111 relaxed with the
+ *    limited rates w3/w4/w5; fourth order set from the strain estimates
+ *    through A and B; orders 5-6 zero.
+ * First-order central moments flip sign (+F/2 after collision).              */
+void orc_collide(const orc_params* p, const double* fbar, double* fout, double* uout) {
+  lattice_init();
+  double f[27];
+  double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < 27; ++i) {
+    f[i] = fbar[i] + WT[i];
+    rho += f[i];
+    j[0] += f[i] * CX[i]; j[1] += f[i] * CY[i]; j[2] += f[i] * CZ[i];
+  }
+  double u[3];
+  for (int d = 0; d < 3; ++d) u[d] = (j[d] + 0.5 * p->force[d]) / rho;
+  if (uout) { uout[0] = u[0]; uout[1] = u[1]; uout[2] = u[2]; }
+
+  double K[27], k[27], C[27], Cs[27], ks[27], Ks[27];
+  orc_central_moments(f, u, K);
+  for (int m = 0; m < 27; ++m) k[m] = K[m] / rho;
+  orc_cumulants(k, C);
+
+  const double w1 = p->omega1, w2 = p->omega2;
+  const double G = (double)p->galilean;
+  for (int m = 0; m < 27; ++m) Cs[m] = 0.0;
+
+  /* second order */
+  const double c200 = C[IX(2,0,0)], c020 = C[IX(0,2,0)], c002 = C[IX(0,0,2)];
+  const double Dxu = -0.5 * w1 * (2.0 * c200 - c020 - c002) - 0.5 * w2 * (c200 + c020 + c002 - 1.0);
+  const double Dyv = Dxu + 1.5 * w1 * (c200 - c020);
+  const double Dzw = Dxu + 1.5 * w1 * (c200 - c002);
+  const double ux2 = u[0] * u[0], uy2 = u[1] * u[1], uz2 = u[2] * u[2];
+  const double m1 = c200 - c020, m2 = c200 - c002, a = c200 + c020 + c002;
+  const double m1s = (1.0 - w1) * m1 - G * 3.0 * (1.0 - 0.5 * w1) * (ux2 * Dxu - uy2 * Dyv);
+  const double m2s = (1.0 - w1) * m2 - G * 3.0 * (1.0 - 0.5 * w1) * (ux2 * Dxu - uz2 * Dzw);
+  const double as = a + w2 * (1.0 - a) - G * 3.0 * (1.0 - 0.5 * w2) * (ux2 * Dxu + uy2 * Dyv + uz2 * Dzw);
+  Cs[IX(2,0,0)] = (m1s + m2s + as) / 3.0;
+  Cs[IX(0,2,0)] = (as - 2.0 * m1s + m2s) / 3.0;
+  Cs[IX(0,0,2)] = (as + m1s - 2.0 * m2s) / 3.0;
+  Cs[IX(1,1,0)] = (1.0 - w1) * C[IX(1,1,0)];
+  Cs[IX(1,0,1)] = (1.0 - w1) * C[IX(1,0,1)];
+  Cs[IX(0,1,1)] = (1.0 - w1) * C[IX(0,1,1)];
+
+  if (p->mode == 1) {
+    double co[5];
+    if (p->k17_given) memcpy(co, p->k17, sizeof co);
+    else orc_k17_coefficients(w1, w2, co);
+    const double w3 = co[0], w4 = co[1], w5 = co[2], A = co[3], B = co[4];
+    const double lam = p->lambda;
+    /* third order: pairs with the same odd index */
+    const int pa[3][2] = {{IX(1,2,0), IX(1,0,2)}, {IX(2,1,0), IX(0,1,2)}, {IX(2,0,1), IX(0,2,1)}};
+    for (int q = 0; q < 3; ++q) {
+      double s = C[pa[q][0]] + C[pa[q][1]];
+      double d = C[pa[q][0]] - C[pa[q][1]];
+      double ss = (1.0 - limited(w3, s, lam)) * s;
+      double ds = (1.0 - limited(w4, d, lam)) * d;
+      Cs[pa[q][0]] = 0.5 * (ss + ds);
+      Cs[pa[q][1]] = 0.5 * (ss - ds);
+    }
+    Cs[IX(1,1,1)] = (1.0 - limited(w5, C[IX(1,1,1)], lam)) * C[IX(1,1,1)];
+    /* fourth order from strain estimates */
+    const double t = 1.0 / w1 - 0.5;
+    Cs[IX(2,2,0)] = -(2.0 / 3.0) * t * A * (Dxu + Dyv);
+    Cs[IX(2,0,2)] = -(2.0 / 3.0) * t * A * (Dxu + Dzw);
+    Cs[IX(0,2,2)] = -(2.0 / 3.0) * t * A * (Dyv + Dzw);
+    Cs[IX(2,1,1)] = -(1.0 / 3.0) * t * B * (-3.0 * w1 * C[IX(0,1,1)]);
+    Cs[IX(1,2,1)] = -(1.0 / 3.0) * t * B * (-3.0 * w1 * C[IX(1,0,1)]);
+    Cs[IX(1,1,2)] = -(1.0 / 3.0) * t * B * (-3.0 * w1 * C[IX(1,1,0)]);
+  }
+
+  orc_moments_from_cumulants(Cs, ks);
+  for (int m = 0; m < 27; ++m) Ks[m] = rho * ks[m];
+  Ks[IX(0,0,0)] = rho;
+  Ks[IX(1,0,0)] = -K[IX(1,0,0)];
+  Ks[IX(0,1,0)] = -K[IX(0,1,0)];
+  Ks[IX(0,0,1)] = -K[IX(0,0,1)];
+  double fs[27];
+  orc_populations_from_central(Ks, u, fs);
+  for (int i = 0; i < 27; ++i) fout[i] = fs[i] - WT[i];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Storage rounding (round to nearest, ties to even) for the precision
+ * variant: the value is rounded to the nearest multiple of the quantum of its
+ * binade; rint() rounds ties to even in the default rounding mode.           */
+static double round_fmt(double v, int fmt) {
+  if (fmt == 0 || v == 0.0 || !isfinite(v)) return v;
+  if (fmt == 1) return (double)(float)v;
+  int mant = (fmt == 2) ? 11 : 8;          /* significand bits incl. hidden */
+  int emin = (fmt == 2) ? -14 : -126;      /* smallest normal exponent */
+  double maxv = (fmt == 2) ? 65504.0 : 3.3895313892515355e38;
+  int e;
+  frexp(fabs(v), &e);                       /* |v| in [2^(e-1), 2^e) */
+  int eb = e - 1;
+  if (eb < emin) eb = emin;
+  double qnt = ldexp(1.0, eb - (mant - 1));
+  double r = rint(v / qnt) * qnt;
+  if (fabs(r) > maxv) r = copysign(INFINITY, v);
+  return r;
+}
+
+double orc_round(double v, int32_t fmt) { return round_fmt(v, fmt); }
+
+/* ------------------------------------------------------------------------ */
+/* Initial state: f = f_eq(rho, u) for fluid cells (rho = 1 if rho0 is NULL,
+ * u = 0 if u0 is NULL), zero for solid cells.                                */
+void orc_init(const orc_params* p, const uint8_t* solid, const double* rho0, const double* u0, double* fbar) {
+  lattice_init();
+  const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+  for (int64_t n = 0; n < N; ++n) {
+    double fe[27], u[3] = {0.0, 0.0, 0.0}, rho = rho0 ? rho0[n] : 1.0;
+    if (u0) { u[0] = u0[n]; u[1] = u0[N + n]; u[2] = u0[2 * N + n]; }
+    if (solid && solid[n]) { for (int i = 0; i < 27; ++i) fbar[i * N + n] = 0.0; continue; }
+    orc_equilibrium(rho, u, fe);
+    for (int i = 0; i < 27; ++i) fbar[i * N + n] = round_fmt(fe[i], p->emulate);
+  }
+}
+
+/* Neighbour classification of node (x,y,z) displaced by -c (pull source).
+ * Returns 0 fluid (index in *src), 1 wall, 2 inlet, 3 outlet ghost (index of
+ * the copied column Nx-1 in *src), 4 obstacle.  Walls take precedence over
+ * inlet and outlet.                                                          */
+enum { NB_FLUID = 0, NB_WALL = 1, NB_INLET = 2, NB_OUTLET = 3, NB_SOLID = 4 };
+
+static int classify(const orc_params* p, const uint8_t* solid, int x, int y, int z, int dx, int dy, int dz,
+                    int64_t* src) {
+  int sx = x + dx, sy = y + dy, sz = z + dz;
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  if (p->periodic[1]) sy = (sy + ny) % ny;
+  else if (sy < 0 || sy >= ny) return NB_WALL;
+  if (p->periodic[2]) sz = (sz + nz) % nz;
+  else if (sz < 0 || sz >= nz) return NB_WALL;
+  int kind = NB_FLUID;
+  if (p->periodic[0]) sx = (sx + nx) % nx;
+  else if (sx < 0) return NB_INLET;
+  else if (sx >= nx) { sx = nx - 1; kind = NB_OUTLET; }
+  *src = ((int64_t)sz * ny + sy) * nx + sx;
+  if (kind == NB_FLUID && solid && solid[*src]) return NB_SOLID;
+  return kind;
+}
+
+/* Macroscopic sample of a pre-collision state.                               */
+static void macroscopic(const orc_params* p, const double* fbar, int64_t N, int64_t n, double* out4) {
+  double d = 0.0, j[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < 27; ++i) {
+    double v = fbar[i * N + n];
+    d += v; j[0] += v * CX[i]; j[1] += v * CY[i]; j[2] += v * CZ[i];
+  }
+  double rho = 1.0 + d;
+  for (int k = 0; k < 3; ++k) out4[k] = (j[k] + 0.5 * p->force[k]) / rho;
+  out4[3] = d / 3.0;
+}
+
+/* Run nsteps steps from global step index step0.
+ *  fbar   [27][N] natural-layout shifted populations, in/out;
+ *  q      [27][N] wall-distance fractions for links x -> x+c_i into the
+ *         obstacle (used when obstacle_bc == 1), or NULL;
+ *  acc    [4][N] running sums of u, v, w, p (p = drho/3) over sampled steps;
+ *  count  number of sampled steps, in/out;
+ *  forces [nsteps][3] force on the obstacle per step, or NULL;
+ *  snaps  [snap_cap][4][N] snapshots (u, v, w, p), appended at *nsnaps.
+ * The sample of step n is the pre-collision state of step n.
+ * Force of step n: sum over fluid->obstacle links (x, j) of
+ *   c_j (f_jbar(x) before collision of step n + f*_j(x) after it).
+ * Returns 0, or 1 on a non-finite population.                                */
+int orc_run(const orc_params* p, const uint8_t* solid, const double* q, double* fbar, int64_t step0,
+            int64_t nsteps, double* acc, int64_t* count, double* forces, double* snaps, int32_t snap_cap,
+            int32_t* nsnaps) {
+  lattice_init();
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  const int64_t N = (int64_t)nx * ny * nz;
+  double* post = (double*)malloc(sizeof(double) * 27 * N);
+  double* next = (double*)malloc(sizeof(double) * 27 * N);
+  if (!post || !next) { free(post); free(next); return 2; }
+  int bad = 0;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    const int64_t step = step0 + s;
+    /* samples of the pre-collision state */
+    const int do_avg = acc && step >= p->avg_start;
+    const int do_snap = snaps && p->snap_every > 0 && step >= p->snap_start &&
+                        (step - p->snap_start) % p->snap_every == 0;
+    double* snap = NULL;
+    if (do_snap) {
+      if (*nsnaps >= snap_cap) { bad = 3; break; }
+      snap = snaps + (int64_t)(*nsnaps) * 4 * N;
+      ++*nsnaps;
+    }
+    if (do_avg || do_snap) {
+#pragma omp parallel for schedule(static)
+      for (int64_t n = 0; n < N; ++n) {
+        double m[4] = {0.0, 0.0, 0.0, 0.0};
+        if (!(solid && solid[n])) macroscopic(p, fbar, N, n, m);
+        for (int k = 0; k < 4; ++k) {
+          if (do_avg) acc[k * N + n] += m[k];
+          if (snap) snap[k * N + n] = m[k];
+        }
+      }
+      if (do_avg) ++*count;
+    }
+    /* collision */
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n) {
+      if (solid && solid[n]) { for (int i = 0; i < 27; ++i) post[i * N + n] = 0.0; continue; }
+      double fin[27], fo[27];
+      for (int i = 0; i < 27; ++i) fin[i] = fbar[i * N + n];
+      orc_collide(p, fin, fo, NULL);
+      for (int i = 0; i < 27; ++i) post[i * N + n] = fo[i];
+    }
+    /* pull streaming with boundary substitutions */
+    double F[3] = {0.0, 0.0, 0.0};
+#pragma omp parallel for schedule(static) reduction(+ : F[:3])
+    for (int z = 0; z < nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          const int64_t n = ((int64_t)z * ny + y) * nx + x;
+          if (solid && solid[n]) { for (int i = 0; i < 27; ++i) next[i * N + n] = 0.0; continue; }
+          for (int i = 0; i < 27; ++i) {
+            const int o = 26 - i;
+            int64_t src = 0;
+            int kind = classify(p, solid, x, y, z, -CX[i], -CY[i], -CZ[i], &src);
+            double v;
+            if (kind == NB_FLUID || kind == NB_OUTLET) {
+              v = post[i * N + src];
+            } else if (kind == NB_WALL) {
+              v = post[o * N + n];
+            } else if (kind == NB_INLET) {
+              v = post[o * N + n] + 6.0 * WT[i] * CX[i] * p->u_in;
+            } else { /* obstacle: link from x along o into the solid */
+              if (p->obstacle_bc == 1 && q) {
+                const double qq = q[(int64_t)o * N + n];
+                int64_t nb = 0;
+                int k2 = classify(p, solid, x, y, z, CX[i], CY[i], CZ[i], &nb);
+                if (qq < 0.5 && (k2 == NB_FLUID || k2 == NB_OUTLET)) {
+                  v = 2.0 * qq * post[o * N + n] + (1.0 - 2.0 * qq) * post[o * N + nb];
+                } else {
+                  v = post[o * N + n] / (2.0 * qq) + (2.0 * qq - 1.0) / (2.0 * qq) * post[i * N + n];
+                }
+              } else {
+                v = post[o * N + n];
+              }
+            }
+            next[i * N + n] = round_fmt(v, p->emulate);
+          }
+          /* momentum exchange on obstacle links x -> x + c_j */
+          if (forces) {
+            for (int jd = 0; jd < 27; ++jd) {
+              int64_t nb = 0;
+              if (classify(p, solid, x, y, z, CX[jd], CY[jd], CZ[jd], &nb) != NB_SOLID) continue;
+              const double fin = fbar[(26 - jd) * N + n] + WT[jd];
+              const double fo = post[jd * N + n] + WT[jd];
+              F[0] += CX[jd] * (fin + fo);
+              F[1] += CY[jd] * (fin + fo);
+              F[2] += CZ[jd] * (fin + fo);
+            }
+          }
+        }
+    if (forces) { forces[3 * s + 0] = F[0]; forces[3 * s + 1] = F[1]; forces[3 * s + 2] = F[2]; }
+    memcpy(fbar, next, sizeof(double) * 27 * N);
+    double chk = 0.0;
+    for (int64_t n = 0; n < N; n += 97) chk += fbar[n];
+    if (!isfinite(chk)) { bad = 1; break; }
+  }
+  free(post);
+  free(next);
+  return bad;
+}
+
+/* Threads the OpenMP runtime will use (for reporting the CPU baseline).      */
+#ifdef _OPENMP
+#include <omp.h>
+int orc_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_threads(void) { return 1; }
+#endif

@@ -1,0 +1,60 @@
+"""Seeded input generators: counter-based RNG and obstacle geometry."""
+import math
+
+import numpy as np
+
+from inputs import perturbation, random_obstacle, sphere_channel, spanwise_cylinder, splitmix64
+from inputs.geometry import directions
+
+
+def test_splitmix64_published_first_output():
+    # first output of SplitMix64 seeded with 0
+    assert int(splitmix64(0, 0)) == 0xE220A8397B1DCDAF
+
+
+def test_perturbation_is_seeded_and_bounded():
+    a = perturbation((8, 4, 4), 3, 5e-4)
+    b = perturbation((8, 4, 4), 3, 5e-4)
+    c = perturbation((8, 4, 4), 4, 5e-4)
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+    assert np.abs(a).max() <= 5e-4 and abs(a.mean()) < 1e-4
+
+
+def test_sphere_geometry_links_are_exact_distances():
+    g = sphere_channel((64, 32, 32), center=(16.0, 15.5, 15.5), radius=4.0)
+    zz, yy, xx = np.nonzero(g.solid)
+    d = np.sqrt((xx - 16.0) ** 2 + (yy - 15.5) ** 2 + (zz - 15.5) ** 2)
+    assert d.max() <= 4.0 and g.n_solid > 4 / 3 * math.pi * 3.0 ** 3
+    c = directions()
+    cell, dr, q = g.links
+    x, y, z = cell % 64, (cell // 64) % 32, cell // (64 * 32)
+    # the crossing point lies on the sphere
+    px = x + q * c[dr, 0]
+    py = y + q * c[dr, 1]
+    pz = z + q * c[dr, 2]
+    r = np.sqrt((px - 16.0) ** 2 + (py - 15.5) ** 2 + (pz - 15.5) ** 2)
+    assert np.abs(r - 4.0).max() < 1e-9
+    # every link starts in fluid and ends in solid
+    assert not g.solid.reshape(-1)[cell].any()
+    nb = ((z + c[dr, 2]) * 32 + (y + c[dr, 1])) * 64 + (x + c[dr, 0])
+    assert g.solid.reshape(-1)[nb].all()
+
+
+def test_random_obstacle_reproducible_and_placed():
+    g1 = random_obstacle((128, 64, 64), 5)
+    g2 = random_obstacle((128, 64, 64), 5)
+    assert np.array_equal(g1.solid, g2.solid)
+    assert g1.n_solid > 0
+    zz, yy, xx = np.nonzero(g1.solid)
+    assert abs(xx.mean() - 0.3 * 128) < 12
+    assert 1000 <= g1.params["re"] <= 10000 and -15 <= g1.params["aoa"] <= 15
+
+
+def test_spanwise_cylinder_links():
+    g = spanwise_cylinder((128, 64, 16), center=(38.4, 31.5), diameter=16.0)
+    assert g.solid[:, 31, 38] .all()
+    cell, dr, q = g.links
+    c = directions()
+    x, y = cell % 128, (cell // 128) % 64
+    px, py = x + q * c[dr, 0], y + q * c[dr, 1]
+    assert np.abs(np.hypot(px - 38.4, py - 31.5) - 8.0).max() < 1e-9
