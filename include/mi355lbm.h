@@ -1,0 +1,229 @@
+/*
+ * mi355lbm.h -- C ABI of the MI355X (gfx950) cumulant lattice Boltzmann
+ * solver and Fourier neural operator surrogate.
+ *
+ * The solver advances the D3Q27 cumulant lattice Boltzmann method on a 3D
+ * obstructed channel (paper Sec. 3.1-3.2): velocity inlet at x = -1/2,
+ * zero-gradient (extrapolation) outlet, no-slip lateral walls, halfway or
+ * linearly interpolated bounce-back at the obstacle, cumulant collision with
+ * the optional fourth-order parametrised mode and third-order limiter.  It
+ * records running means of u, v, w, p, snapshots and the force on the object
+ * (paper Sec. 2, data capture).  The surrogate is the 3D Fourier neural
+ * operator of paper Sec. 4 / App. A.2, predicting mean fields from geometry
+ * and Reynolds number.
+ *
+ * Conventions
+ *  - Lattice direction i = 9(cz+1) + 3(cy+1) + (cx+1), opposite 26 - i,
+ *    weights w = W(cx)W(cy)W(cz) with W(0) = 2/3, W(+-1) = 1/6.
+ *  - Fields use the natural layout [k][nz][ny][nx] with x fastest; N =
+ *    nx*ny*nz.  Populations are exchanged as shifted values fbar = f - w_i.
+ *  - Every call returns 0 (LBM_OK) or a positive error code; no call aborts
+ *    or throws.  lbm_last_error() gives the message of the last failure.
+ *  - Host pointers and device pointers are told apart by an explicit flag
+ *    argument where both are accepted; device pointers must be allocated on
+ *    the device the object was created on.
+ *  - All device work of an object is enqueued on the HIP stream given at
+ *    creation (NULL = the null stream).  Calls that return host data
+ *    synchronise that stream; lbm_step and fno_forward do not.
+ *  - The caller owns every buffer it passes; the library owns the
+ *    populations, accumulators, tables and workspaces it allocates, and
+ *    frees them in the destroy call.
+ *  - Objects are not thread-safe: one host thread at a time per object.
+ */
+#ifndef MI355LBM_H
+#define MI355LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = 1,    /* bad argument (shape, pointer, parameter range)          */
+  LBM_ENOMEM = 2,    /* device or host allocation failed                         */
+  LBM_EDEVICE = 3,   /* HIP runtime error; sticky                                */
+  LBM_EUNSTABLE = 4, /* non-finite mass found by the periodic check; sticky      */
+  LBM_ESTATE = 5     /* call not valid in the object's state                     */
+};
+
+/* Storage of the shifted populations fbar = f - w_i.  Collision arithmetic is
+ * FP64 for LBM_F64 and FP32 otherwise; means and forces are FP64 always.    */
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 };
+
+/* Collision mode (paper Sec. 3.2): plain cumulant (orders >= 3 relaxed to
+ * zero) or the fourth-order parametrised operator with limiter, which the
+ * paper switches off below Re_c = 3000.  AUTO picks K17 iff
+ * u_in * ny / nu >= 3000 (Reynolds number on the channel height).            */
+enum { LBM_MODE_AUTO = -1, LBM_MODE_PLAIN = 0, LBM_MODE_K17 = 1 };
+
+typedef struct lbm_sim lbm_sim;
+
+typedef struct {
+  int32_t nx, ny, nz;      /* cells; nx % 64 == 0, ny % 4 == 0, nz >= 1          */
+  int32_t storage;         /* LBM_F64 .. LBM_BF16S                                */
+  int32_t periodic[3];     /* 1: periodic axis.  0: x has the inlet (x = -1/2)
+                              and the outlet (x = nx - 1/2); y, z have no-slip
+                              walls at -1/2 and n - 1/2                           */
+  double u_in;             /* inlet velocity along +x, lattice units              */
+  double nu;               /* lattice viscosity; omega1 = 1/(3 nu + 1/2)          */
+  double omega2;           /* bulk relaxation rate (1.0)                          */
+  int32_t mode;            /* LBM_MODE_*                                          */
+  int32_t galilean;        /* 1: Galilean correction of the 2nd-order rates       */
+  double lambda;           /* third-order limiter of the K17 mode (0.01)          */
+  int32_t obstacle_bc;     /* 0 halfway bounce-back, 1 linear interpolated (q)    */
+  double body_force[3];    /* uniform body force (0 for the channel)              */
+  int64_t avg_start;       /* step index from which the mean is sampled; <0 off   */
+  int32_t snap_every;      /* snapshot period in steps (0 = no snapshots)         */
+  int32_t snap_count;      /* ring of the last snap_count snapshots               */
+  int64_t snap_start;      /* first step index eligible for a snapshot            */
+  int32_t force_every;     /* record the obstacle force every k steps (0 = off)   */
+  int32_t xcd_remap;       /* 1: map workgroups to XCD-contiguous tiles           */
+} lbm_params;
+
+/* Fill *p with defaults (F32, channel, omega2 = 1, Galilean on, lambda 0.01,
+ * halfway bounce-back, averaging from step 0, no snapshots, forces every
+ * step, XCD remap on) for an nx x ny x nz grid.                               */
+int lbm_default_params(lbm_params* p, int32_t nx, int32_t ny, int32_t nz);
+
+/* Create a solver (paper Sec. 3.1: obstacle in a channel, inlet velocity u_in,
+ * Re set through the lattice viscosity).
+ *  solid      host uint8 [N], 1 = obstacle cell (NULL: no obstacle).  The
+ *             obstacle must keep 3 cells clear of inlet and outlet.
+ *  nlinks, link_cell, link_dir, link_q
+ *             host arrays: wall-distance fractions q in (0, 1] for links from
+ *             fluid cell link_cell along direction link_dir into the obstacle
+ *             (paper Sec. 3.2, interpolated bounce-back); links not listed
+ *             take q = 1/2.  Ignored for halfway bounce-back.  May be 0/NULL.
+ *  u0         host double [3][N] initial velocity (NULL: rest); the initial
+ *             state is the equilibrium at rho = 1 and u0.
+ *  hip_stream hipStream_t cast to void* (NULL: null stream).
+ * On success *out owns device memory of about 27*N*sizeof(storage) bytes
+ * plus 32 B per cell when averaging is on.                                   */
+int lbm_create(const lbm_params* p, const uint8_t* solid, int64_t nlinks, const int64_t* link_cell,
+               const uint8_t* link_dir, const double* link_q, const double* u0, void* hip_stream, lbm_sim** out);
+
+/* Advance nsteps steps (asynchronous on the object's stream).  One step is
+ * one fused stream-and-collide launch (in-place AA pattern; the parity is
+ * tracked internally) plus a force reduction when a force sample is due.    */
+int lbm_step(lbm_sim* s, int64_t nsteps);
+
+/* Mean fields (paper Sec. 2: mean velocity and pressure).  out is [4][N]
+ * double (u, v, w, p = (rho - 1)/3) averaged over the sampled steps, zero in
+ * solid cells; out_on_device selects a device or host pointer.  *nsamples
+ * receives the number of sampled steps.  Synchronises.                       */
+int lbm_mean_fields(lbm_sim* s, double* out, int out_on_device, int64_t* nsamples);
+
+/* Snapshots (paper Sec. 2: 20 snapshots 25 steps apart).  out is
+ * [k][4][N] float (u, v, w, p), oldest first, k = min(taken, snap_count)
+ * written to *k; steps[j] (host int64, may be NULL) receives the step index
+ * of snapshot j.  Synchronises.                                              */
+int lbm_snapshots(lbm_sim* s, float* out, int out_on_device, int32_t* k, int64_t* steps);
+
+/* Force on the obstacle (paper Sec. 2: forces in x and y; all three given).
+ * Host double [n][3], the recorded samples in step order; the step index of
+ * sample j is returned in steps[j] when steps is not NULL.  Force of step n:
+ * sum over fluid->obstacle links (x, j) of c_j (f_jbar(x) entering step n
+ * + f*_j(x) leaving it).  Synchronises.                                      */
+int lbm_forces(lbm_sim* s, double* fxyz, int64_t cap, int64_t* n, int64_t* steps);
+
+/* Instantaneous (u, v, w, p) of the current state, float [4][N].            */
+int lbm_moments(lbm_sim* s, float* out, int out_on_device);
+
+/* Current pre-collision populations, natural layout, double fbar [27][N]
+ * (solid cells 0), whatever the AA parity.  Host pointer.  Synchronises.     */
+int lbm_get_populations(lbm_sim* s, double* fbar);
+
+/* Replace the state with natural-layout fbar [27][N] (host double, rounded
+ * to the storage type); resets the AA parity, keeps step count and
+ * accumulators.                                                              */
+int lbm_set_populations(lbm_sim* s, const double* fbar);
+
+/* Sum of rho - 1 over fluid cells (FP64) of the current state; sets the
+ * sticky LBM_EUNSTABLE state if it is not finite.  Synchronises.             */
+int lbm_mass(lbm_sim* s, double* mass);
+
+/* Raw checkpoint: populations in storage layout plus step count, parity,
+ * accumulators and snapshot ring.  lbm_export_state with blob == NULL
+ * reports the size in *used.  Restoring into an object created with the
+ * same parameters and geometry continues bitwise identically.               */
+int lbm_export_state(lbm_sim* s, void* blob, size_t cap, size_t* used);
+int lbm_import_state(lbm_sim* s, const void* blob, size_t n);
+
+/* Step counter, omega1 and the resolved mode.                                */
+int lbm_info(const lbm_sim* s, int64_t* steps, double* omega1, int32_t* mode);
+
+/* Kernel timing with HIP events on the object's stream: while enabled, every
+ * stream-and-collide launch is bracketed by events; lbm_profile_read returns
+ * the summed elapsed milliseconds and the number of launches (synchronises)
+ * and resets the counters.                                                   */
+int lbm_profile(lbm_sim* s, int enable);
+int lbm_profile_read(lbm_sim* s, double* total_ms, int64_t* launches);
+
+void lbm_destroy(lbm_sim* s);
+const char* lbm_last_error(const lbm_sim* s); /* s may be NULL: global error */
+
+/* ------------------------------------------------------------------------ */
+/* Fourier neural operator (paper Sec. 4 and App. A.2): lifting 4 -> width,
+ * `layers` Fourier layers (truncated 3D real DFT keeping kx, ky in
+ * {0..m-1, -m..-1} and kz in {0..m-1}, per-mode complex channel mixing,
+ * truncated inverse DFT, plus a pointwise linear map and bias, GELU after
+ * all but the last), projection width -> proj_hidden (GELU) -> cout.
+ * Contractions run as BF16 MFMA with FP32 accumulation.                      */
+typedef struct fno_net fno_net;
+
+typedef struct {
+  int32_t nx, ny, nz;       /* grid; multiples of 16, nz >= 2*mz              */
+  int32_t cin, cout;        /* input / output channels (4, 4)                 */
+  int32_t width;            /* channels of the Fourier layers (32)            */
+  int32_t layers;           /* Fourier layers (4)                             */
+  int32_t mx, my, mz;       /* retained modes per corner / half-spectrum (16)  */
+  int32_t proj_hidden;      /* projection hidden width (128)                  */
+  int32_t max_batch;        /* largest batch the workspaces are sized for     */
+} fno_params;
+
+/* Parameter vector layout (FP32, fno_param_count entries), in this order:
+ * lift W [width][cin], lift b [width]; per layer l: spectral weights
+ * [2*mx][2*my][mz][width_in][width_out][2] (re, im), pointwise W
+ * [width][width] (out, in), bias [width]; proj W1 [proj_hidden][width],
+ * b1 [proj_hidden], W2 [cout][proj_hidden], b2 [cout].                      */
+int64_t fno_param_count(const fno_params* p);
+
+/* Create with parameters initialised from seed (uniform fan-in scaling);
+ * allocates the BF16 working copy, FP32 master copy, Adam moments and the
+ * activation workspaces for max_batch.                                       */
+int fno_create(const fno_params* p, uint64_t seed, void* hip_stream, fno_net** out);
+
+/* Copy the FP32 parameter vector in or out (host pointers).                  */
+int fno_set_params(fno_net* n, const float* host_params, int64_t count);
+int fno_get_params(fno_net* n, float* host_params, int64_t count);
+
+/* Forward pass: x device BF16 (uint16 bit patterns) [B][cin][nx][ny][nz]
+ * (z fastest), y device FP32 [B][cout][nx][ny][nz].  Asynchronous.           */
+int fno_forward(fno_net* n, const uint16_t* x, int32_t B, float* y);
+
+/* Loss and gradients: masked mean squared error over cells where mask != 0
+ * (device uint8 [nx][ny][nz], shared by all samples and channels); target
+ * device FP32 [B][cout][nx][ny][nz].  Gradients land in the FP32 gradient
+ * buffer; host_grads (may be NULL) receives a copy; *loss (host, may be
+ * NULL) the loss.  Synchronises when either host output is requested.        */
+int fno_loss_grad(fno_net* n, const uint16_t* x, const float* target, const uint8_t* mask, int32_t B,
+                  float* loss, float* host_grads);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the gradients of the
+ * last fno_loss_grad call with learning rate lr.                             */
+int fno_adam_step(fno_net* n, float lr);
+
+/* fno_loss_grad followed by fno_adam_step.                                   */
+int fno_train_step(fno_net* n, const uint16_t* x, const float* target, const uint8_t* mask, int32_t B, float lr,
+                   float* loss);
+
+void fno_destroy(fno_net* n);
+const char* fno_last_error(const fno_net* n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MI355LBM_H */

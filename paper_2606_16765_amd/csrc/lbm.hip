@@ -1,0 +1,1159 @@
+// MI355X (gfx950) D3Q27 cumulant lattice Boltzmann solver behind the C ABI
+// of include/mi355lbm.h.
+//
+// One fused kernel per time step: in-place AA-pattern streaming over a
+// structure-of-arrays population field (x fastest, 64 cells per wave), the
+// central-moment / cumulant transforms and the collision in registers, the
+// boundary substitutions (walls, velocity inlet, zero-gradient outlet via a
+// ghost column, halfway or linearly interpolated bounce-back at the
+// obstacle), and the fused FP64 mean accumulation, snapshot and per-block
+// force partials (paper Sec. 2, 3.1, 3.2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm_device.h"
+#include "mi355lbm.h"
+
+using namespace mlbm;
+
+namespace {
+
+constexpr int TX = 64;   // cells along x per wave
+constexpr int TY = 4;    // waves (rows along y) per block
+constexpr int NTHREADS = TX * TY;
+
+struct StepArgs {
+  void* A;                  // populations, slot i at A + i*slot elements
+  int32_t nx, ny, nz;
+  int32_t pitch;            // elements per row (nx + 64: column nx is the outlet ghost)
+  int64_t slot;             // elements per population slot
+  int32_t per[3];           // periodic axes
+  const uint8_t* flag;      // [N] 0 fluid, 1 fluid next to obstacle, 2 solid
+  const int32_t* brow;      // [N] boundary row of flag-1 cells
+  const uint32_t* bmask;    // [nb] bit j: cell + c_j is obstacle
+  const double* bq;         // [nb][27] wall distance fractions
+  int32_t interp;           // 1: linear interpolated bounce-back
+  double u_in;
+  CollideParams cp;
+  double* acc;              // [4][N] running sums or null
+  float* snap;              // [4][N] snapshot slot or null
+  const int32_t* bslot;     // [ntiles] force slot of the tile or -1 (null: no forces)
+  double* fpart;            // [nslots][3]
+  int32_t tiles_x, tiles_y; // tile grid
+  int32_t ntiles;
+  int32_t remap;            // XCD-contiguous tile order
+};
+
+__device__ __forceinline__ int logical_tile(int b, int ntiles, int remap) {
+  if (!remap) return b;
+  // workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+  // contiguous run of tiles so neighbouring tiles share that XCD's L2
+  const int per = ntiles >> 3;
+  if (b >= (per << 3)) return b;
+  return (b & 7) * per + (b >> 3);
+}
+
+// Per-cell boundary context shared by the read and write phases.
+struct CellCtx {
+  int32_t x, y, z;
+  int64_t n;        // dense cell index
+  int64_t pc;       // pitched cell index
+  uint32_t rmask;   // bit i: pull source cell - c_i is not a fluid node (wall, inlet, obstacle)
+  uint32_t inlet;   // bit i: that source is the inlet
+  uint32_t om;      // bit j: cell + c_j is obstacle
+  int32_t row;      // boundary row or -1
+  int32_t off[3][3];// source offset per axis for c = -1, 0, +1 (source = cell - c)
+};
+
+__device__ __forceinline__ int src_off(int i, const CellCtx& c) {
+  return c.off[0][cx(i) + 1] + c.off[1][cy(i) + 1] + c.off[2][cz(i) + 1];
+}
+
+__device__ __forceinline__ void make_ctx(const StepArgs& a, int x, int y, int z, uint8_t fl, CellCtx& c) {
+  c.x = x; c.y = y; c.z = z;
+  c.n = ((int64_t)z * a.ny + y) * a.nx + x;
+  c.pc = ((int64_t)z * a.ny + y) * a.pitch + x;
+  const int rowp = a.pitch, plane = a.pitch * a.ny;
+  // x: source of c=+1 is x-1, of c=-1 is x+1 (x+1 = nx is the outlet ghost)
+  c.off[0][1] = 0; c.off[1][1] = 0; c.off[2][1] = 0;
+  c.off[0][2] = (a.per[0] && x == 0) ? (a.nx - 1) : -1;
+  c.off[0][0] = (a.per[0] && x == a.nx - 1) ? -(a.nx - 1) : 1;
+  c.off[1][2] = (a.per[1] && y == 0) ? (a.ny - 1) * rowp : -rowp;
+  c.off[1][0] = (a.per[1] && y == a.ny - 1) ? -(a.ny - 1) * rowp : rowp;
+  c.off[2][2] = (a.per[2] && z == 0) ? (a.nz - 1) * plane : -plane;
+  c.off[2][0] = (a.per[2] && z == a.nz - 1) ? -(a.nz - 1) * plane : plane;
+  uint32_t wall = 0;
+  if (!a.per[1]) {
+    if (y == 0) wall |= M_YP;
+    if (y == a.ny - 1) wall |= M_YN;
+  }
+  if (!a.per[2]) {
+    if (z == 0) wall |= M_ZP;
+    if (z == a.nz - 1) wall |= M_ZN;
+  }
+  c.inlet = (!a.per[0] && x == 0) ? (M_XP & ~wall) : 0u;
+  c.om = 0; c.row = -1;
+  if (fl == 1) {
+    c.row = a.brow[c.n];
+    c.om = a.bmask[c.row];
+  }
+  c.rmask = wall | c.inlet | reverse27(c.om);
+}
+
+// Pre-collision populations of a fluid cell for the given AA parity, with
+// the interpolated bounce-back completion (q < 1/2 links).
+template <typename S, bool ODD>
+__device__ __forceinline__ void load_cell(const StepArgs& a, const CellCtx& c, typename Storage<S>::T* g) {
+  using T = typename Storage<S>::T;
+  const S* A = (const S*)a.A;
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    int64_t addr;
+    if (!ODD) {
+      addr = (int64_t)i * a.slot + c.pc;
+    } else {
+      const bool r = (c.rmask >> i) & 1u;
+      addr = r ? ((int64_t)i * a.slot + c.pc) : ((int64_t)(26 - i) * a.slot + c.pc + src_off(i, c));
+    }
+    T v = Storage<S>::load(A + addr);
+    if (ODD && ((c.inlet >> i) & 1u)) v += T(6.0 * wgt(i) * cx(i) * a.u_in);
+    g[i] = v;
+  }
+  if (a.interp && c.om) {
+#pragma unroll
+    for (int j = 0; j < 27; ++j) {
+      if (((c.om >> j) & 1u) && !((c.rmask >> j) & 1u)) {
+        const T q = T(a.bq[(int64_t)c.row * 27 + j]);
+        if (q < T(0.5)) g[26 - j] += (T(1) - T(2) * q) * g[j];
+      }
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void macroscopic(const T* g, const double* force, T& drho, T& ux, T& uy, T& uz) {
+  // pairwise sums of opposite directions keep the momentum sums exact-ish
+  T d = g[13];
+  T jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int i = 0; i < 13; ++i) {
+    const T s = g[i] + g[26 - i], t = g[26 - i] - g[i];  // t carries c of direction 26-i
+    d += s;
+    const int o = 26 - i;
+    if (cx(o)) jx += cx(o) > 0 ? t : -t;
+    if (cy(o)) jy += cy(o) > 0 ? t : -t;
+    if (cz(o)) jz += cz(o) > 0 ? t : -t;
+  }
+  const T rho = T(1) + d;
+  const T ir = T(1) / rho;
+  drho = d;
+  ux = (jx + T(0.5 * force[0])) * ir;
+  uy = (jy + T(0.5 * force[1])) * ir;
+  uz = (jz + T(0.5 * force[2])) * ir;
+}
+
+template <typename S, bool ODD, int MODE>
+__global__ __launch_bounds__(NTHREADS) void lbm_step_kernel(StepArgs a) {
+  using T = typename Storage<S>::T;
+  const int tile = logical_tile(blockIdx.x, a.ntiles, a.remap);
+  const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
+  const int txi = tile % a.tiles_x;
+  const int rest = tile / a.tiles_x;
+  const int tyi = rest % a.tiles_y;
+  const int z = rest / a.tiles_y;
+  const int x = txi * TX + tx, y = tyi * TY + ty;
+  const int64_t n = ((int64_t)z * a.ny + y) * a.nx + x;
+  const uint8_t fl = a.flag[n];
+
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  if (fl != 2) {
+    CellCtx c;
+    make_ctx(a, x, y, z, fl, c);
+    T g[27];
+    load_cell<S, ODD>(a, c, g);
+
+    T drho, ux, uy, uz;
+    macroscopic(g, a.cp.force, drho, ux, uy, uz);
+    if (a.acc) {
+      const int64_t N = (int64_t)a.nx * a.ny * a.nz;
+      a.acc[n] += (double)ux;
+      a.acc[N + n] += (double)uy;
+      a.acc[2 * N + n] += (double)uz;
+      a.acc[3 * N + n] += (double)drho * (1.0 / 3.0);
+    }
+    if (a.snap) {
+      const int64_t N = (int64_t)a.nx * a.ny * a.nz;
+      a.snap[n] = (float)ux;
+      a.snap[N + n] = (float)uy;
+      a.snap[2 * N + n] = (float)uz;
+      a.snap[3 * N + n] = (float)(drho * T(1.0 / 3.0));
+    }
+    // incoming half of the momentum exchange on obstacle links
+    T Fx = 0, Fy = 0, Fz = 0;
+    if (c.om) {
+#pragma unroll
+      for (int j = 0; j < 27; ++j)
+        if ((c.om >> j) & 1u) {
+          const T v = g[26 - j];
+          if (cx(j)) Fx += cx(j) > 0 ? v : -v;
+          if (cy(j)) Fy += cy(j) > 0 ? v : -v;
+          if (cz(j)) Fz += cz(j) > 0 ? v : -v;
+        }
+    }
+
+    const T rho = T(1) + drho;
+    const T irho = T(1) / rho;
+    forward_transform(g, ux, uy, uz);
+    collide_moments<T, MODE>(g, drho, rho, irho, ux, uy, uz, a.cp);
+    inverse_transform(g, ux, uy, uz);
+
+    if (c.om) {
+#pragma unroll
+      for (int j = 0; j < 27; ++j)
+        if ((c.om >> j) & 1u) {
+          const T v = g[j];
+          if (cx(j)) Fx += cx(j) > 0 ? v : -v;
+          if (cy(j)) Fy += cy(j) > 0 ? v : -v;
+          if (cz(j)) Fz += cz(j) > 0 ? v : -v;
+        }
+      fx = (double)Fx; fy = (double)Fy; fz = (double)Fz;
+    }
+
+    // write phase
+    S* A = (S*)a.A;
+    const bool outlet = !a.per[0] && x == a.nx - 1;
+#pragma unroll
+    for (int j = 0; j < 27; ++j) {
+      const int o = 26 - j;
+      T v = g[j];
+      if (a.interp && ((c.om >> j) & 1u)) {
+        // linear interpolated bounce-back: pre-blend of the value that
+        // returns along o (completed on read when q < 1/2)
+        const T q = T(a.bq[(int64_t)c.row * 27 + j]);
+        if (q < T(0.5) && !((c.rmask >> j) & 1u)) v = T(2) * q * g[j];
+        else v = g[j] / (T(2) * q) + (T(2) * q - T(1)) / (T(2) * q) * g[o];
+      }
+      int64_t addr;
+      if (!ODD) {
+        addr = (int64_t)o * a.slot + c.pc;
+        Storage<S>::store(A + addr, v);
+        if (outlet && cx(j) == -1) Storage<S>::store(A + addr + 1, v);  // ghost column copy
+      } else {
+        const bool r = (c.rmask >> o) & 1u;
+        if (r) {
+          if ((c.inlet >> o) & 1u) v -= T(6.0 * wgt(j) * cx(j) * a.u_in);
+          addr = (int64_t)o * a.slot + c.pc;
+          Storage<S>::store(A + addr, v);
+        } else {
+          addr = (int64_t)j * a.slot + c.pc + src_off(o, c);
+          Storage<S>::store(A + addr, v);
+          // zero-gradient outlet: the column nx-1 receives the same value
+          if (outlet && cx(j) == -1) Storage<S>::store(A + addr + 1, v);
+        }
+      }
+    }
+  }
+
+  // per-block FP64 force partial, deterministic order
+  if (a.bslot) {
+    const int s = a.bslot[tile];
+    if (s >= 0) {
+      __shared__ double red[3][NTHREADS];
+      red[0][threadIdx.x] = fx; red[1][threadIdx.x] = fy; red[2][threadIdx.x] = fz;
+      __syncthreads();
+#pragma unroll
+      for (int w = NTHREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+          red[0][threadIdx.x] += red[0][threadIdx.x + w];
+          red[1][threadIdx.x] += red[1][threadIdx.x + w];
+          red[2][threadIdx.x] += red[2][threadIdx.x + w];
+        }
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) {
+        a.fpart[3 * s + 0] = red[0][0];
+        a.fpart[3 * s + 1] = red[1][0];
+        a.fpart[3 * s + 2] = red[2][0];
+      }
+    }
+  }
+}
+
+// Sum of the force partials in a fixed order, plus the constant weight part.
+__global__ __launch_bounds__(256) void force_reduce_kernel(const double* fpart, int nslots, double c0, double c1,
+                                                           double c2, double* out) {
+  __shared__ double red[3][256];
+  double s0 = 0, s1 = 0, s2 = 0;
+  for (int k = threadIdx.x; k < nslots; k += 256) {
+    s0 += fpart[3 * k]; s1 += fpart[3 * k + 1]; s2 += fpart[3 * k + 2];
+  }
+  red[0][threadIdx.x] = s0; red[1][threadIdx.x] = s1; red[2][threadIdx.x] = s2;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+      red[2][threadIdx.x] += red[2][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = red[0][0] + c0; out[1] = red[1][0] + c1; out[2] = red[2][0] + c2;
+  }
+}
+
+// Natural-layout state written into storage (even parity).  Slots of
+// interpolated bounce-back links with q < 1/2 hold the pre-blended part
+// f_obar - (1 - 2q) f_j: the read completes them with the incoming f_j.
+template <typename S>
+__device__ __forceinline__ void store_natural(const StepArgs& a, int x, int y, int z, uint8_t fl,
+                                              typename Storage<S>::T* g) {
+  using T = typename Storage<S>::T;
+  CellCtx c;
+  make_ctx(a, x, y, z, fl, c);
+  if (a.interp && c.om) {
+#pragma unroll
+    for (int j = 0; j < 27; ++j) {
+      if (((c.om >> j) & 1u) && !((c.rmask >> j) & 1u)) {
+        const T q = T(a.bq[(int64_t)c.row * 27 + j]);
+        if (q < T(0.5)) g[26 - j] -= (T(1) - T(2) * q) * g[j];
+      }
+    }
+  }
+  S* A = (S*)a.A;
+#pragma unroll
+  for (int i = 0; i < 27; ++i) Storage<S>::store(A + (int64_t)i * a.slot + c.pc, g[i]);
+}
+
+// Equilibrium initial state at rho = 1: fbar = w (Phi - 1) with Phi the
+// product of per-axis factors 1 + delta (delta(0) = -3a^2/2,
+// delta(+-1) = 3a^2 +- 3a), expanded so that no rest value is subtracted.
+template <typename S>
+__global__ __launch_bounds__(256) void init_kernel(StepArgs a, const double* u0) {
+  using T = typename Storage<S>::T;
+  const int64_t N = (int64_t)a.nx * a.ny * a.nz;
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  const int x = n % a.nx, y = (n / a.nx) % a.ny, z = n / ((int64_t)a.nx * a.ny);
+  const uint8_t fl = a.flag[n];
+  T g[27];
+  if (fl == 2) {
+    const int64_t pc = ((int64_t)z * a.ny + y) * a.pitch + x;
+    S* A = (S*)a.A;
+    for (int i = 0; i < 27; ++i) Storage<S>::store(A + (int64_t)i * a.slot + pc, T(0));
+    return;
+  }
+  T u[3] = {0, 0, 0};
+  if (u0) { u[0] = T(u0[n]); u[1] = T(u0[N + n]); u[2] = T(u0[2 * N + n]); }
+  T del[3][3];
+  for (int d = 0; d < 3; ++d) {
+    del[d][1] = T(-1.5) * u[d] * u[d];
+    del[d][0] = T(3) * u[d] * u[d] - T(3) * u[d];
+    del[d][2] = T(3) * u[d] * u[d] + T(3) * u[d];
+  }
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const T dx = del[0][cx(i) + 1], dy = del[1][cy(i) + 1], dz = del[2][cz(i) + 1];
+    const T ph = dx + dy + dz + dx * dy + dx * dz + dy * dz + dx * dy * dz;
+    g[i] = T(wgt(i)) * ph;
+  }
+  store_natural<S>(a, x, y, z, fl, g);
+}
+
+// Natural-layout export of the pre-collision state (any parity): populations
+// as double [27][N], and/or moments (u, v, w, p) as float [4][N], and/or the
+// per-block mass partial.
+template <typename S, bool ODD>
+__global__ __launch_bounds__(NTHREADS) void export_kernel(StepArgs a, double* pops, float* mom, double* mass_part) {
+  using T = typename Storage<S>::T;
+  const int tile = blockIdx.x;
+  const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
+  const int txi = tile % a.tiles_x;
+  const int rest = tile / a.tiles_x;
+  const int tyi = rest % a.tiles_y;
+  const int z = rest / a.tiles_y;
+  const int x = txi * TX + tx, y = tyi * TY + ty;
+  const int64_t N = (int64_t)a.nx * a.ny * a.nz;
+  const int64_t n = ((int64_t)z * a.ny + y) * a.nx + x;
+  const uint8_t fl = a.flag[n];
+  double dm = 0.0;
+  if (fl != 2) {
+    CellCtx c;
+    make_ctx(a, x, y, z, fl, c);
+    T g[27];
+    load_cell<S, ODD>(a, c, g);
+    if (pops)
+      for (int i = 0; i < 27; ++i) pops[(int64_t)i * N + n] = (double)g[i];
+    T drho, ux, uy, uz;
+    macroscopic(g, a.cp.force, drho, ux, uy, uz);
+    if (mom) {
+      mom[n] = (float)ux; mom[N + n] = (float)uy; mom[2 * N + n] = (float)uz;
+      mom[3 * N + n] = (float)(drho * T(1.0 / 3.0));
+    }
+    dm = (double)drho;
+  } else {
+    if (pops)
+      for (int i = 0; i < 27; ++i) pops[(int64_t)i * N + n] = 0.0;
+    if (mom)
+      for (int k = 0; k < 4; ++k) mom[k * N + n] = 0.f;
+  }
+  if (mass_part) {
+    __shared__ double red[NTHREADS];
+    red[threadIdx.x] = dm;
+    __syncthreads();
+    for (int w = NTHREADS / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) mass_part[tile] = red[0];
+  }
+}
+
+// Natural-layout import (even parity): double fbar [27][N] -> storage.
+template <typename S>
+__global__ __launch_bounds__(256) void import_kernel(StepArgs a, const double* pops) {
+  using T = typename Storage<S>::T;
+  const int64_t N = (int64_t)a.nx * a.ny * a.nz;
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  const int x = n % a.nx, y = (n / a.nx) % a.ny, z = n / ((int64_t)a.nx * a.ny);
+  const uint8_t fl = a.flag[n];
+  T g[27];
+  for (int i = 0; i < 27; ++i) g[i] = fl == 2 ? T(0) : T(pops[(int64_t)i * N + n]);
+  if (fl == 2) {
+    const int64_t pc = ((int64_t)z * a.ny + y) * a.pitch + x;
+    S* A = (S*)a.A;
+    for (int i = 0; i < 27; ++i) Storage<S>::store(A + (int64_t)i * a.slot + pc, T(0));
+    return;
+  }
+  store_natural<S>(a, x, y, z, fl, g);
+}
+
+// Mean fields = sums / count, zero in solid cells.
+__global__ __launch_bounds__(256) void mean_kernel(const double* acc, int64_t N, double inv, const uint8_t* flag,
+                                                   double* out) {
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  const bool sol = flag[n] == 2;
+  for (int k = 0; k < 4; ++k) out[k * N + n] = sol ? 0.0 : acc[k * N + n] * inv;
+}
+
+// Boundary tables: mark flag-1 cells and their rows.
+__global__ __launch_bounds__(256) void scatter_rows_kernel(const int64_t* cells, int64_t nb, uint8_t* flag,
+                                                           int32_t* brow) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= nb) return;
+  const int64_t n = cells[r];
+  flag[n] = 1;
+  brow[n] = (int32_t)r;
+}
+
+}  // namespace
+
+// ============================================================== host side
+struct lbm_sim {
+  lbm_params p{};
+  double omega1 = 0;
+  int mode = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t N = 0;
+  size_t esize = 0;
+  StepArgs args{};
+  void* A = nullptr;
+  uint8_t* d_flag = nullptr;
+  int32_t* d_brow = nullptr;
+  uint32_t* d_bmask = nullptr;
+  double* d_bq = nullptr;
+  int64_t nb = 0;
+  int32_t* d_bslot = nullptr;
+  int32_t nslots = 0;
+  double* d_fpart = nullptr;
+  double fconst[3] = {0, 0, 0};
+  double* d_forces = nullptr;
+  int64_t force_cap = 0, nforces = 0;
+  std::vector<int64_t> force_steps;
+  double* d_acc = nullptr;
+  int64_t nsamples = 0;
+  float* d_snap = nullptr;
+  int64_t snap_taken = 0;
+  std::vector<int64_t> snap_steps;
+  int64_t steps = 0;
+  int parity = 0;   // AA parity of the stored layout: 0 natural, 1 swapped
+  int sticky = 0;
+  std::string err;
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  double prof_ms = 0;
+  int64_t prof_launches = 0;
+};
+
+static std::string g_err;
+
+static int fail(lbm_sim* s, int code, const std::string& msg) {
+  if (s) {
+    s->err = msg;
+    if (code == LBM_EDEVICE || code == LBM_EUNSTABLE) s->sticky = code;
+  }
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(s, call)                                                                       \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail((s), e_ == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,                  \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                         \
+  } while (0)
+
+static size_t storage_size(int st) {
+  switch (st) {
+    case LBM_F64: return 8;
+    case LBM_F32: return 4;
+    case LBM_F16S: return 2;
+    case LBM_BF16S: return 2;
+  }
+  return 0;
+}
+
+extern "C" int lbm_default_params(lbm_params* p, int32_t nx, int32_t ny, int32_t nz) {
+  if (!p) return LBM_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->nx = nx; p->ny = ny; p->nz = nz;
+  p->storage = LBM_F32;
+  p->u_in = 0.05;
+  p->nu = 0.05 * ny / 5000.0;
+  p->omega2 = 1.0;
+  p->mode = LBM_MODE_AUTO;
+  p->galilean = 1;
+  p->lambda = 0.01;
+  p->obstacle_bc = 0;
+  p->avg_start = 0;
+  p->snap_every = 0;
+  p->snap_count = 20;
+  p->snap_start = 0;
+  p->force_every = 1;
+  p->xcd_remap = 1;
+  return LBM_OK;
+}
+
+static void k17_rates(double w1, double w2, double* o) {
+  o[0] = 8.0 * (w1 - 2.0) * (w2 * (3.0 * w1 - 1.0) - 5.0 * w1) /
+         (8.0 * (5.0 - 2.0 * w1) * w1 + w2 * (8.0 + w1 * (9.0 * w1 - 26.0)));
+  o[1] = 8.0 * (w1 - 2.0) * (w1 + w2 * (3.0 * w1 - 7.0)) / (w2 * (56.0 - 42.0 * w1 + 9.0 * w1 * w1) - 8.0 * w1);
+  o[2] = 24.0 * (w1 - 2.0) * (4.0 * w1 * w1 + w1 * w2 * (18.0 - 13.0 * w1) + w2 * w2 * (2.0 + w1 * (6.0 * w1 - 11.0))) /
+         (16.0 * w1 * w1 * (w1 - 6.0) - 2.0 * w1 * w2 * (216.0 + 5.0 * w1 * (9.0 * w1 - 46.0)) +
+          w2 * w2 * (w1 * (3.0 * w1 - 10.0) * (15.0 * w1 - 28.0) - 48.0));
+  o[3] = (4.0 * w1 * w1 + 2.0 * w1 * w2 * (w1 - 6.0) + w2 * w2 * (w1 * (10.0 - 3.0 * w1) - 4.0)) /
+         ((w1 - w2) * (w2 * (2.0 + 3.0 * w1) - 8.0 * w1));
+  o[4] = (4.0 * w1 * w2 * (9.0 * w1 - 16.0) - 4.0 * w1 * w1 - 2.0 * w2 * w2 * (2.0 + 9.0 * w1 * (w1 - 2.0))) /
+         (3.0 * (w1 - w2) * (w2 * (2.0 + 3.0 * w1) - 8.0 * w1));
+}
+
+template <typename S, bool ODD, int MODE>
+static void launch_step(const StepArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((lbm_step_kernel<S, ODD, MODE>), dim3(a.ntiles), dim3(NTHREADS), 0, st, a);
+}
+
+template <typename S>
+static void launch_step_s(const StepArgs& a, bool odd, int mode, hipStream_t st) {
+  if (odd) {
+    if (mode) launch_step<S, true, 1>(a, st); else launch_step<S, true, 0>(a, st);
+  } else {
+    if (mode) launch_step<S, false, 1>(a, st); else launch_step<S, false, 0>(a, st);
+  }
+}
+
+static void launch_step_any(int storage, const StepArgs& a, bool odd, int mode, hipStream_t st) {
+  switch (storage) {
+    case LBM_F64: launch_step_s<double>(a, odd, mode, st); break;
+    case LBM_F32: launch_step_s<float>(a, odd, mode, st); break;
+    case LBM_F16S: launch_step_s<f16s>(a, odd, mode, st); break;
+    case LBM_BF16S: launch_step_s<bf16s>(a, odd, mode, st); break;
+  }
+}
+
+template <typename S>
+static void launch_export_s(const StepArgs& a, bool odd, double* pops, float* mom, double* mp, hipStream_t st) {
+  StepArgs b = a;
+  if (odd) hipLaunchKernelGGL((export_kernel<S, true>), dim3(a.ntiles), dim3(NTHREADS), 0, st, b, pops, mom, mp);
+  else hipLaunchKernelGGL((export_kernel<S, false>), dim3(a.ntiles), dim3(NTHREADS), 0, st, b, pops, mom, mp);
+}
+
+static void launch_export(int storage, const StepArgs& a, bool odd, double* pops, float* mom, double* mp,
+                          hipStream_t st) {
+  switch (storage) {
+    case LBM_F64: launch_export_s<double>(a, odd, pops, mom, mp, st); break;
+    case LBM_F32: launch_export_s<float>(a, odd, pops, mom, mp, st); break;
+    case LBM_F16S: launch_export_s<f16s>(a, odd, pops, mom, mp, st); break;
+    case LBM_BF16S: launch_export_s<bf16s>(a, odd, pops, mom, mp, st); break;
+  }
+}
+
+static void launch_init(int storage, const StepArgs& a, const double* u0, hipStream_t st) {
+  const int64_t N = (int64_t)a.nx * a.ny * a.nz;
+  const dim3 g((unsigned)((N + 255) / 256));
+  switch (storage) {
+    case LBM_F64: hipLaunchKernelGGL(init_kernel<double>, g, dim3(256), 0, st, a, u0); break;
+    case LBM_F32: hipLaunchKernelGGL(init_kernel<float>, g, dim3(256), 0, st, a, u0); break;
+    case LBM_F16S: hipLaunchKernelGGL(init_kernel<f16s>, g, dim3(256), 0, st, a, u0); break;
+    case LBM_BF16S: hipLaunchKernelGGL(init_kernel<bf16s>, g, dim3(256), 0, st, a, u0); break;
+  }
+}
+
+static void launch_import(int storage, const StepArgs& a, const double* pops, hipStream_t st) {
+  const int64_t N = (int64_t)a.nx * a.ny * a.nz;
+  const dim3 g((unsigned)((N + 255) / 256));
+  switch (storage) {
+    case LBM_F64: hipLaunchKernelGGL(import_kernel<double>, g, dim3(256), 0, st, a, pops); break;
+    case LBM_F32: hipLaunchKernelGGL(import_kernel<float>, g, dim3(256), 0, st, a, pops); break;
+    case LBM_F16S: hipLaunchKernelGGL(import_kernel<f16s>, g, dim3(256), 0, st, a, pops); break;
+    case LBM_BF16S: hipLaunchKernelGGL(import_kernel<bf16s>, g, dim3(256), 0, st, a, pops); break;
+  }
+}
+
+static void free_all(lbm_sim* s) {
+  void* ptrs[] = {s->A, s->d_flag, s->d_brow, s->d_bmask, s->d_bq, s->d_bslot, s->d_fpart, s->d_forces, s->d_acc,
+                  s->d_snap};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (auto& e : s->events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  s->events.clear();
+}
+
+extern "C" int lbm_create(const lbm_params* pin, const uint8_t* solid, int64_t nlinks, const int64_t* link_cell,
+                          const uint8_t* link_dir, const double* link_q, const double* u0, void* hip_stream,
+                          lbm_sim** out) {
+  if (!pin || !out) return fail(nullptr, LBM_EINVAL, "null argument");
+  *out = nullptr;
+  const lbm_params& p = *pin;
+  if (p.nx <= 0 || p.ny <= 0 || p.nz <= 0 || p.nx % TX || p.ny % TY)
+    return fail(nullptr, LBM_EINVAL, "grid must have nx % 64 == 0 and ny % 4 == 0");
+  if (storage_size(p.storage) == 0) return fail(nullptr, LBM_EINVAL, "unknown storage type");
+  if (!(p.nu > 0.0) || !std::isfinite(p.nu)) return fail(nullptr, LBM_EINVAL, "viscosity must be positive");
+  if (!(p.omega2 > 0.0 && p.omega2 < 2.0)) return fail(nullptr, LBM_EINVAL, "omega2 must be in (0, 2)");
+  if (p.snap_every < 0 || p.snap_count < 0 || p.force_every < 0) return fail(nullptr, LBM_EINVAL, "negative period");
+  if (p.snap_every > 0 && p.snap_count <= 0) return fail(nullptr, LBM_EINVAL, "snap_count must be positive");
+  if (nlinks < 0 || (nlinks > 0 && (!link_cell || !link_dir || !link_q)))
+    return fail(nullptr, LBM_EINVAL, "bad link arrays");
+  const int64_t N = (int64_t)p.nx * p.ny * p.nz;
+  const int64_t pitch = (int64_t)p.nx + 64;
+  const int64_t slot = pitch * p.ny * p.nz;
+  if (slot >= (int64_t(1) << 31) || N >= (int64_t(1) << 31))
+    return fail(nullptr, LBM_EINVAL, "grid too large (per-slot index must fit 31 bits)");
+  const int64_t ntiles = (int64_t)(p.nx / TX) * (p.ny / TY) * p.nz;
+  if (ntiles >= (int64_t(1) << 31)) return fail(nullptr, LBM_EINVAL, "too many tiles");
+
+  lbm_sim* s = new (std::nothrow) lbm_sim();
+  if (!s) return fail(nullptr, LBM_ENOMEM, "host allocation failed");
+  s->p = p;
+  s->N = N;
+  s->esize = storage_size(p.storage);
+  s->stream = (hipStream_t)hip_stream;
+  s->omega1 = 1.0 / (3.0 * p.nu + 0.5);
+  const double re_c = p.u_in * p.ny / p.nu;
+  s->mode = p.mode == LBM_MODE_AUTO ? (re_c >= 3000.0 ? 1 : 0) : (p.mode ? 1 : 0);
+  (void)hipGetDevice(&s->device);
+  auto bail = [&](int code) {
+    free_all(s);
+    delete s;
+    return code;
+  };
+
+  // ---- obstacle tables from the solid mask (authoritative) ----
+  std::vector<uint64_t> pairs;  // (cell << 5) | j : cell + c_j is obstacle
+  double fc[3] = {0, 0, 0};
+  if (solid) {
+    for (int64_t n = 0; n < N; ++n) {
+      if (!solid[n]) continue;
+      const int x = (int)(n % p.nx), y = (int)((n / p.nx) % p.ny), z = (int)(n / ((int64_t)p.nx * p.ny));
+      if (!p.periodic[0] && (x < 3 || x > p.nx - 4)) {
+        fail(nullptr, LBM_EINVAL, "obstacle must keep 3 cells clear of inlet and outlet");
+        return bail(LBM_EINVAL);
+      }
+      for (int j = 0; j < 27; ++j) {
+        if (j == 13) continue;
+        int fx = x - cx(j), fy = y - cy(j), fz = z - cz(j);
+        if (p.periodic[0]) fx = (fx + p.nx) % p.nx; else if (fx < 0 || fx >= p.nx) continue;
+        if (p.periodic[1]) fy = (fy + p.ny) % p.ny; else if (fy < 0 || fy >= p.ny) continue;
+        if (p.periodic[2]) fz = (fz + p.nz) % p.nz; else if (fz < 0 || fz >= p.nz) continue;
+        const int64_t f = ((int64_t)fz * p.ny + fy) * p.nx + fx;
+        if (solid[f]) continue;
+        pairs.push_back(((uint64_t)f << 5) | (uint64_t)j);
+      }
+    }
+  }
+  std::sort(pairs.begin(), pairs.end());
+  std::vector<int64_t> rcell;
+  std::vector<uint32_t> rmask;
+  for (uint64_t pr : pairs) {
+    const int64_t cell = (int64_t)(pr >> 5);
+    const int j = (int)(pr & 31);
+    if (rcell.empty() || rcell.back() != cell) {
+      rcell.push_back(cell);
+      rmask.push_back(0);
+    }
+    rmask.back() |= 1u << j;
+    fc[0] += 2.0 * wgt(j) * cx(j);
+    fc[1] += 2.0 * wgt(j) * cy(j);
+    fc[2] += 2.0 * wgt(j) * cz(j);
+  }
+  s->nb = (int64_t)rcell.size();
+  std::vector<double> rq((size_t)std::max<int64_t>(s->nb, 1) * 27, 0.5);
+  for (int64_t k = 0; k < nlinks; ++k) {
+    const int64_t cell = link_cell[k];
+    const int j = link_dir[k];
+    if (j < 0 || j >= 27 || cell < 0 || cell >= N) {
+      fail(nullptr, LBM_EINVAL, "link out of range");
+      return bail(LBM_EINVAL);
+    }
+    const double q = link_q[k];
+    if (!(q > 0.0 && q <= 1.0)) {
+      fail(nullptr, LBM_EINVAL, "wall distance fraction must be in (0, 1]");
+      return bail(LBM_EINVAL);
+    }
+    auto it = std::lower_bound(rcell.begin(), rcell.end(), cell);
+    if (it != rcell.end() && *it == cell) rq[(size_t)(it - rcell.begin()) * 27 + j] = q;
+  }
+  s->fconst[0] = fc[0]; s->fconst[1] = fc[1]; s->fconst[2] = fc[2];
+
+  // force slots: tiles containing boundary rows
+  const int tiles_x = p.nx / TX, tiles_y = p.ny / TY;
+  std::vector<int32_t> bslot;
+  if (p.force_every > 0 && s->nb > 0) {
+    bslot.assign((size_t)ntiles, -1);
+    int32_t ns = 0;
+    for (int64_t cell : rcell) {
+      const int x = (int)(cell % p.nx), y = (int)((cell / p.nx) % p.ny), z = (int)(cell / ((int64_t)p.nx * p.ny));
+      const int64_t t = ((int64_t)z * tiles_y + y / TY) * tiles_x + x / TX;
+      if (bslot[(size_t)t] < 0) bslot[(size_t)t] = ns++;
+    }
+    s->nslots = ns;
+  }
+
+  // ---- device memory ----
+  hipError_t e = hipSuccess;
+  const size_t popbytes = (size_t)27 * slot * s->esize;
+  if ((e = hipMalloc(&s->A, popbytes)) != hipSuccess) {
+    fail(nullptr, e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "population allocation failed");
+    return bail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE);
+  }
+  auto dalloc = [&](void** ptr, size_t bytes) -> bool {
+    hipError_t ee = hipMalloc(ptr, bytes);
+    if (ee != hipSuccess) {
+      fail(nullptr, ee == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "device allocation failed");
+      return false;
+    }
+    return true;
+  };
+  if (!dalloc((void**)&s->d_flag, (size_t)N) || !dalloc((void**)&s->d_brow, (size_t)N * 4) ||
+      !dalloc((void**)&s->d_bmask, (size_t)std::max<int64_t>(s->nb, 1) * 4) ||
+      !dalloc((void**)&s->d_bq, (size_t)std::max<int64_t>(s->nb, 1) * 27 * 8))
+    return bail(LBM_ENOMEM);
+  hipStream_t st = s->stream;
+  (void)hipMemsetAsync(s->A, 0, popbytes, st);
+  (void)hipMemsetAsync(s->d_brow, 0xff, (size_t)N * 4, st);
+  if (solid) {
+    // flags: 2 solid, 0 fluid; the scatter kernel below marks boundary rows 1
+    std::vector<uint8_t> fl(solid, solid + N);
+    for (auto& v : fl) v = v ? 2 : 0;
+    (void)hipMemcpyAsync(s->d_flag, fl.data(), (size_t)N, hipMemcpyHostToDevice, st);
+    (void)hipStreamSynchronize(st);
+  } else {
+    (void)hipMemsetAsync(s->d_flag, 0, (size_t)N, st);
+  }
+  if (s->nb > 0) {
+    int64_t* d_cells = nullptr;
+    if (!dalloc((void**)&d_cells, (size_t)s->nb * 8)) return bail(LBM_ENOMEM);
+    (void)hipMemcpyAsync(d_cells, rcell.data(), (size_t)s->nb * 8, hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(s->d_bmask, rmask.data(), (size_t)s->nb * 4, hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(s->d_bq, rq.data(), (size_t)s->nb * 27 * 8, hipMemcpyHostToDevice, st);
+    hipLaunchKernelGGL(scatter_rows_kernel, dim3((unsigned)((s->nb + 255) / 256)), dim3(256), 0, st, d_cells, s->nb,
+                       s->d_flag, s->d_brow);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(d_cells);
+  }
+  if (s->nslots > 0) {
+    if (!dalloc((void**)&s->d_bslot, (size_t)ntiles * 4) || !dalloc((void**)&s->d_fpart, (size_t)s->nslots * 24))
+      return bail(LBM_ENOMEM);
+    (void)hipMemcpyAsync(s->d_bslot, bslot.data(), (size_t)ntiles * 4, hipMemcpyHostToDevice, st);
+  }
+  if (p.avg_start >= 0) {
+    if (!dalloc((void**)&s->d_acc, (size_t)N * 32)) return bail(LBM_ENOMEM);
+    (void)hipMemsetAsync(s->d_acc, 0, (size_t)N * 32, st);
+  }
+  if (p.snap_every > 0) {
+    if (!dalloc((void**)&s->d_snap, (size_t)p.snap_count * N * 16)) return bail(LBM_ENOMEM);
+    (void)hipMemsetAsync(s->d_snap, 0, (size_t)p.snap_count * N * 16, st);
+  }
+
+  StepArgs& a = s->args;
+  a.A = s->A;
+  a.nx = p.nx; a.ny = p.ny; a.nz = p.nz;
+  a.pitch = (int32_t)pitch;
+  a.slot = slot;
+  for (int d = 0; d < 3; ++d) a.per[d] = p.periodic[d] ? 1 : 0;
+  a.flag = s->d_flag;
+  a.brow = s->d_brow;
+  a.bmask = s->d_bmask;
+  a.bq = s->d_bq;
+  a.interp = p.obstacle_bc == 1 ? 1 : 0;
+  a.u_in = p.u_in;
+  a.cp.omega1 = s->omega1;
+  a.cp.omega2 = p.omega2;
+  a.cp.galilean = p.galilean;
+  a.cp.lambda = p.lambda;
+  k17_rates(s->omega1, p.omega2, a.cp.k17);
+  for (int d = 0; d < 3; ++d) a.cp.force[d] = p.body_force[d];
+  a.acc = nullptr;
+  a.snap = nullptr;
+  a.bslot = nullptr;
+  a.fpart = s->d_fpart;
+  a.tiles_x = tiles_x;
+  a.tiles_y = tiles_y;
+  a.ntiles = (int32_t)ntiles;
+  a.remap = p.xcd_remap ? 1 : 0;
+
+  double* d_u0 = nullptr;
+  if (u0) {
+    if (!dalloc((void**)&d_u0, (size_t)N * 24)) return bail(LBM_ENOMEM);
+    (void)hipMemcpyAsync(d_u0, u0, (size_t)N * 24, hipMemcpyHostToDevice, st);
+  }
+  launch_init(p.storage, a, d_u0, st);
+  e = hipStreamSynchronize(st);
+  if (d_u0) (void)hipFree(d_u0);
+  if (e != hipSuccess || (e = hipGetLastError()) != hipSuccess) {
+    fail(nullptr, LBM_EDEVICE, std::string("initialisation failed: ") + hipGetErrorString(e));
+    return bail(LBM_EDEVICE);
+  }
+  *out = s;
+  return LBM_OK;
+}
+
+static int ensure_force_cap(lbm_sim* s, int64_t need) {
+  if (need <= s->force_cap) return LBM_OK;
+  int64_t cap = std::max<int64_t>(need, 2 * s->force_cap);
+  cap = std::max<int64_t>(cap, 1024);
+  double* nb = nullptr;
+  HIPCHK(s, hipMalloc(&nb, (size_t)cap * 24));
+  if (s->d_forces) {
+    HIPCHK(s, hipMemcpyAsync(nb, s->d_forces, (size_t)s->nforces * 24, hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    (void)hipFree(s->d_forces);
+  }
+  s->d_forces = nb;
+  s->force_cap = cap;
+  return LBM_OK;
+}
+
+extern "C" int lbm_step(lbm_sim* s, int64_t nsteps) {
+  if (!s) return fail(nullptr, LBM_EINVAL, "null object");
+  if (s->sticky) return s->sticky;
+  if (nsteps < 0) return fail(s, LBM_EINVAL, "negative step count");
+  const lbm_params& p = s->p;
+  if (p.force_every > 0 && s->nslots > 0) {
+    const int64_t due = (s->steps + nsteps + p.force_every - 1) / p.force_every - (s->steps + p.force_every - 1) / p.force_every;
+    int rc = ensure_force_cap(s, s->nforces + due + 1);
+    if (rc) return rc;
+  }
+  for (int64_t k = 0; k < nsteps; ++k) {
+    const int64_t n = s->steps;
+    StepArgs a = s->args;
+    if (s->d_acc && n >= p.avg_start) {
+      a.acc = s->d_acc;
+      s->nsamples++;
+    }
+    if (s->d_snap && n >= p.snap_start && (n - p.snap_start) % p.snap_every == 0) {
+      const int64_t slotk = s->snap_taken % p.snap_count;
+      a.snap = s->d_snap + slotk * 4 * s->N;
+      if ((int64_t)s->snap_steps.size() < p.snap_count) s->snap_steps.push_back(n);
+      else s->snap_steps[(size_t)slotk] = n;
+      s->snap_taken++;
+    }
+    const bool do_force = p.force_every > 0 && s->nslots > 0 && n % p.force_every == 0;
+    if (do_force) a.bslot = s->d_bslot;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (s->profiling) {
+      HIPCHK(s, hipEventCreate(&e0));
+      HIPCHK(s, hipEventCreate(&e1));
+      HIPCHK(s, hipEventRecord(e0, s->stream));
+    }
+    launch_step_any(p.storage, a, s->parity != 0, s->mode, s->stream);
+    if (s->profiling) {
+      HIPCHK(s, hipEventRecord(e1, s->stream));
+      s->events.emplace_back(e0, e1);
+    }
+    if (do_force) {
+      hipLaunchKernelGGL(force_reduce_kernel, dim3(1), dim3(256), 0, s->stream, s->d_fpart, s->nslots, s->fconst[0],
+                         s->fconst[1], s->fconst[2], s->d_forces + 3 * s->nforces);
+      s->nforces++;
+      s->force_steps.push_back(n);
+    }
+    s->steps++;
+    s->parity ^= 1;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(s, LBM_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+  }
+  return LBM_OK;
+}
+
+extern "C" int lbm_mean_fields(lbm_sim* s, double* out, int out_on_device, int64_t* nsamples) {
+  if (!s || !out) return fail(s, LBM_EINVAL, "null argument");
+  if (s->sticky) return s->sticky;
+  if (!s->d_acc) return fail(s, LBM_ESTATE, "averaging is off (avg_start < 0)");
+  const int64_t N = s->N;
+  double* dst = out;
+  double* tmp = nullptr;
+  if (!out_on_device) {
+    HIPCHK(s, hipMalloc(&tmp, (size_t)N * 32));
+    dst = tmp;
+  }
+  const double inv = s->nsamples > 0 ? 1.0 / (double)s->nsamples : 0.0;
+  hipLaunchKernelGGL(mean_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s->stream, s->d_acc, N, inv,
+                     s->d_flag, dst);
+  if (tmp) {
+    HIPCHK(s, hipMemcpyAsync(out, tmp, (size_t)N * 32, hipMemcpyDeviceToHost, s->stream));
+  }
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (tmp) (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(s, LBM_EDEVICE, hipGetErrorString(e));
+  if (nsamples) *nsamples = s->nsamples;
+  return LBM_OK;
+}
+
+extern "C" int lbm_snapshots(lbm_sim* s, float* out, int out_on_device, int32_t* k, int64_t* steps) {
+  if (!s || !k) return fail(s, LBM_EINVAL, "null argument");
+  if (s->sticky) return s->sticky;
+  const int64_t taken = s->snap_taken;
+  const int64_t cnt = std::min<int64_t>(taken, s->p.snap_count);
+  *k = (int32_t)cnt;
+  if (!out || cnt == 0) return LBM_OK;
+  const size_t one = (size_t)s->N * 16;
+  const hipMemcpyKind kind = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  for (int64_t j = 0; j < cnt; ++j) {
+    const int64_t idx = taken - cnt + j;
+    const int64_t slotk = idx % s->p.snap_count;
+    HIPCHK(s, hipMemcpyAsync((char*)out + j * one, (char*)s->d_snap + slotk * one, one, kind, s->stream));
+    if (steps) steps[j] = s->snap_steps[(size_t)slotk];
+  }
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return LBM_OK;
+}
+
+extern "C" int lbm_forces(lbm_sim* s, double* fxyz, int64_t cap, int64_t* n, int64_t* steps) {
+  if (!s || !n) return fail(s, LBM_EINVAL, "null argument");
+  if (s->sticky) return s->sticky;
+  *n = s->nforces;
+  const int64_t m = std::min(cap, s->nforces);
+  if (fxyz && m > 0) {
+    HIPCHK(s, hipMemcpyAsync(fxyz, s->d_forces, (size_t)m * 24, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+  }
+  if (steps)
+    for (int64_t j = 0; j < m; ++j) steps[j] = s->force_steps[(size_t)j];
+  return LBM_OK;
+}
+
+extern "C" int lbm_moments(lbm_sim* s, float* out, int out_on_device) {
+  if (!s || !out) return fail(s, LBM_EINVAL, "null argument");
+  if (s->sticky) return s->sticky;
+  float* dst = out;
+  float* tmp = nullptr;
+  if (!out_on_device) {
+    HIPCHK(s, hipMalloc(&tmp, (size_t)s->N * 16));
+    dst = tmp;
+  }
+  launch_export(s->p.storage, s->args, s->parity != 0, nullptr, dst, nullptr, s->stream);
+  if (tmp) HIPCHK(s, hipMemcpyAsync(out, tmp, (size_t)s->N * 16, hipMemcpyDeviceToHost, s->stream));
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (tmp) (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(s, LBM_EDEVICE, hipGetErrorString(e));
+  return LBM_OK;
+}
+
+extern "C" int lbm_get_populations(lbm_sim* s, double* fbar) {
+  if (!s || !fbar) return fail(s, LBM_EINVAL, "null argument");
+  if (s->sticky) return s->sticky;
+  double* tmp = nullptr;
+  HIPCHK(s, hipMalloc(&tmp, (size_t)s->N * 27 * 8));
+  launch_export(s->p.storage, s->args, s->parity != 0, tmp, nullptr, nullptr, s->stream);
+  hipError_t e = hipMemcpyAsync(fbar, tmp, (size_t)s->N * 27 * 8, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(s, LBM_EDEVICE, hipGetErrorString(e));
+  return LBM_OK;
+}
+
+extern "C" int lbm_set_populations(lbm_sim* s, const double* fbar) {
+  if (!s || !fbar) return fail(s, LBM_EINVAL, "null argument");
+  if (s->sticky) return s->sticky;
+  double* tmp = nullptr;
+  HIPCHK(s, hipMalloc(&tmp, (size_t)s->N * 27 * 8));
+  hipError_t e = hipMemcpyAsync(tmp, fbar, (size_t)s->N * 27 * 8, hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) {
+    launch_import(s->p.storage, s->args, tmp, s->stream);
+    e = hipStreamSynchronize(s->stream);
+  }
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(s, LBM_EDEVICE, hipGetErrorString(e));
+  // the natural layout is the even-parity layout
+  s->parity = 0;
+  return LBM_OK;
+}
+
+extern "C" int lbm_mass(lbm_sim* s, double* mass) {
+  if (!s || !mass) return fail(s, LBM_EINVAL, "null argument");
+  if (s->sticky) return s->sticky;
+  double* part = nullptr;
+  const int nt = s->args.ntiles;
+  HIPCHK(s, hipMalloc(&part, (size_t)nt * 8));
+  launch_export(s->p.storage, s->args, s->parity != 0, nullptr, nullptr, part, s->stream);
+  std::vector<double> h((size_t)nt);
+  hipError_t e = hipMemcpyAsync(h.data(), part, (size_t)nt * 8, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  (void)hipFree(part);
+  if (e != hipSuccess) return fail(s, LBM_EDEVICE, hipGetErrorString(e));
+  double m = 0.0;
+  for (double v : h) m += v;
+  *mass = m;
+  if (!std::isfinite(m)) return fail(s, LBM_EUNSTABLE, "non-finite mass: the run is unstable");
+  return LBM_OK;
+}
+
+// checkpoint blob: header, raw populations, accumulators, snapshots, forces
+struct Blob {
+  char magic[8];
+  int32_t nx, ny, nz, storage;
+  int64_t steps, nsamples, snap_taken, nforces, parity;
+  int64_t popbytes, accbytes, snapbytes;
+};
+
+extern "C" int lbm_export_state(lbm_sim* s, void* blob, size_t cap, size_t* used) {
+  if (!s || !used) return fail(s, LBM_EINVAL, "null argument");
+  if (s->sticky) return s->sticky;
+  Blob h{};
+  std::memcpy(h.magic, "MLBMCKP1", 8);
+  h.nx = s->p.nx; h.ny = s->p.ny; h.nz = s->p.nz; h.storage = s->p.storage;
+  h.steps = s->steps; h.nsamples = s->nsamples; h.snap_taken = s->snap_taken; h.nforces = s->nforces;
+  h.parity = s->parity;
+  h.popbytes = (int64_t)(27 * s->args.slot * (int64_t)s->esize);
+  h.accbytes = s->d_acc ? s->N * 32 : 0;
+  h.snapbytes = s->d_snap ? (int64_t)s->p.snap_count * s->N * 16 : 0;
+  const size_t need = sizeof(Blob) + h.popbytes + h.accbytes + h.snapbytes + (size_t)h.nforces * 32 +
+                      s->snap_steps.size() * 8 + 8;
+  *used = need;
+  if (!blob) return LBM_OK;
+  if (cap < need) return fail(s, LBM_EINVAL, "checkpoint buffer too small");
+  char* b = (char*)blob;
+  std::memcpy(b, &h, sizeof h);
+  b += sizeof h;
+  HIPCHK(s, hipMemcpyAsync(b, s->A, (size_t)h.popbytes, hipMemcpyDeviceToHost, s->stream));
+  b += h.popbytes;
+  if (h.accbytes) HIPCHK(s, hipMemcpyAsync(b, s->d_acc, (size_t)h.accbytes, hipMemcpyDeviceToHost, s->stream));
+  b += h.accbytes;
+  if (h.snapbytes) HIPCHK(s, hipMemcpyAsync(b, s->d_snap, (size_t)h.snapbytes, hipMemcpyDeviceToHost, s->stream));
+  b += h.snapbytes;
+  if (h.nforces) HIPCHK(s, hipMemcpyAsync(b, s->d_forces, (size_t)h.nforces * 24, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  b += h.nforces * 24;
+  std::memcpy(b, s->force_steps.data(), (size_t)h.nforces * 8);
+  b += h.nforces * 8;
+  int64_t nss = (int64_t)s->snap_steps.size();
+  std::memcpy(b, &nss, 8);
+  b += 8;
+  std::memcpy(b, s->snap_steps.data(), (size_t)nss * 8);
+  return LBM_OK;
+}
+
+extern "C" int lbm_import_state(lbm_sim* s, const void* blob, size_t n) {
+  if (!s || !blob) return fail(s, LBM_EINVAL, "null argument");
+  if (s->sticky) return s->sticky;
+  if (n < sizeof(Blob)) return fail(s, LBM_EINVAL, "checkpoint too short");
+  Blob h;
+  std::memcpy(&h, blob, sizeof h);
+  if (std::memcmp(h.magic, "MLBMCKP1", 8) || h.nx != s->p.nx || h.ny != s->p.ny || h.nz != s->p.nz ||
+      h.storage != s->p.storage)
+    return fail(s, LBM_EINVAL, "checkpoint does not match this object");
+  const int64_t popbytes = (int64_t)(27 * s->args.slot * (int64_t)s->esize);
+  if (h.popbytes != popbytes || h.accbytes != (s->d_acc ? s->N * 32 : 0) ||
+      h.snapbytes != (s->d_snap ? (int64_t)s->p.snap_count * s->N * 16 : 0))
+    return fail(s, LBM_EINVAL, "checkpoint layout does not match this object");
+  const char* b = (const char*)blob + sizeof h;
+  size_t need = sizeof(Blob) + h.popbytes + h.accbytes + h.snapbytes + (size_t)h.nforces * 32 + 8;
+  if (n < need) return fail(s, LBM_EINVAL, "checkpoint truncated");
+  HIPCHK(s, hipMemcpyAsync(s->A, b, (size_t)h.popbytes, hipMemcpyHostToDevice, s->stream));
+  b += h.popbytes;
+  if (h.accbytes) HIPCHK(s, hipMemcpyAsync(s->d_acc, b, (size_t)h.accbytes, hipMemcpyHostToDevice, s->stream));
+  b += h.accbytes;
+  if (h.snapbytes) HIPCHK(s, hipMemcpyAsync(s->d_snap, b, (size_t)h.snapbytes, hipMemcpyHostToDevice, s->stream));
+  b += h.snapbytes;
+  if (h.nforces) {
+    int rc = ensure_force_cap(s, h.nforces + 1);
+    if (rc) return rc;
+    HIPCHK(s, hipMemcpyAsync(s->d_forces, b, (size_t)h.nforces * 24, hipMemcpyHostToDevice, s->stream));
+  }
+  b += h.nforces * 24;
+  s->force_steps.assign((const int64_t*)b, (const int64_t*)b + h.nforces);
+  b += h.nforces * 8;
+  int64_t nss;
+  std::memcpy(&nss, b, 8);
+  b += 8;
+  if (n < need + (size_t)nss * 8) return fail(s, LBM_EINVAL, "checkpoint truncated");
+  s->snap_steps.assign((const int64_t*)b, (const int64_t*)b + nss);
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  s->steps = h.steps; s->nsamples = h.nsamples; s->snap_taken = h.snap_taken; s->nforces = h.nforces;
+  s->parity = (int)h.parity;
+  return LBM_OK;
+}
+
+extern "C" int lbm_info(const lbm_sim* s, int64_t* steps, double* omega1, int32_t* mode) {
+  if (!s) return LBM_EINVAL;
+  if (steps) *steps = s->steps;
+  if (omega1) *omega1 = s->omega1;
+  if (mode) *mode = s->mode;
+  return LBM_OK;
+}
+
+extern "C" int lbm_profile(lbm_sim* s, int enable) {
+  if (!s) return LBM_EINVAL;
+  s->profiling = enable != 0;
+  return LBM_OK;
+}
+
+extern "C" int lbm_profile_read(lbm_sim* s, double* total_ms, int64_t* launches) {
+  if (!s) return LBM_EINVAL;
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  for (auto& e : s->events) {
+    float ms = 0.f;
+    HIPCHK(s, hipEventElapsedTime(&ms, e.first, e.second));
+    s->prof_ms += ms;
+    s->prof_launches++;
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  s->events.clear();
+  if (total_ms) *total_ms = s->prof_ms;
+  if (launches) *launches = s->prof_launches;
+  s->prof_ms = 0;
+  s->prof_launches = 0;
+  return LBM_OK;
+}
+
+extern "C" void lbm_destroy(lbm_sim* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->stream);
+  free_all(s);
+  delete s;
+}
+
+extern "C" const char* lbm_last_error(const lbm_sim* s) { return s ? s->err.c_str() : g_err.c_str(); }

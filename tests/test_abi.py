@@ -1,0 +1,53 @@
+"""C ABI: the library loads and exports every symbol the header declares;
+argument validation answers with error codes before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "mi355lbm.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*((?:lbm|fno)_[a-z_0-9]+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_path_entry_points():
+    names = header_functions()
+    for n in ("lbm_create", "lbm_step", "lbm_mean_fields", "fno_forward", "fno_train_step"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2606_16765_amd._lib import load
+    L = load()
+    missing = [n for n in header_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_invalid_parameters_rejected_without_device_work():
+    from paper_2606_16765_amd._lib import LbmParams, load
+    L = load()
+    p = LbmParams()
+    L.lbm_default_params(ctypes.byref(p), 63, 32, 32)
+    h = ctypes.c_void_p()
+    assert L.lbm_create(ctypes.byref(p), None, 0, None, None, None, None, None, ctypes.byref(h)) == 1
+    assert b"nx % 64" in L.lbm_last_error(None)
+    L.lbm_default_params(ctypes.byref(p), 64, 32, 32)
+    p.nu = -1.0
+    assert L.lbm_create(ctypes.byref(p), None, 0, None, None, None, None, None, ctypes.byref(h)) == 1
+    L.lbm_default_params(ctypes.byref(p), 64, 32, 32)
+    p.storage = 7
+    assert L.lbm_create(ctypes.byref(p), None, 0, None, None, None, None, None, ctypes.byref(h)) == 1
+    assert L.lbm_step(None, 1) == 1
+
+
+def test_binding_raises_on_error():
+    import paper_2606_16765_amd as P
+    from paper_2606_16765_amd._lib import HipError
+    with pytest.raises(HipError):
+        P.Lbm((63, 8, 8), nu=0.01)

@@ -1,0 +1,237 @@
+"""GPU lattice Boltzmann path (HIP library through the C ABI) against the
+FP64 CPU oracle, element by element on the same seeded inputs.
+
+Tolerances: FP64 storage and arithmetic 1e-11 relative (only the summation
+order differs between the two sides); FP32 1e-5 relative L2 on the mean
+fields (the target of the FP32 path); FP16/BF16 shifted storage against the
+storage-emulating oracle with the bounds stated in each test.
+"""
+import numpy as np
+import pytest
+
+from inputs import perturbation, sphere_channel
+from oracle import lbm as olbm
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import paper_2606_16765_amd as P
+    return P
+
+
+def rel_max(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def f64_err(a, b):
+    """Populations: max |a - b| against 1e-11 max|b| + 1e-14.  The absolute
+    floor is the oracle's own rounding: it works on unshifted f (up to 8/27),
+    so a few hundred operations leave ~1e-14 absolute noise even where the
+    shifted populations are tiny."""
+    return float(np.abs(a - b).max() / (1e-11 * np.abs(b).max() + 1e-14)) * 1e-11
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def pair(shape, steps, storage="f64", solid=None, links=None, u0=None, periodic=(0, 0, 0), nu=0.02, u_in=0.05,
+         mode="plain", obstacle_bc=0, body_force=(0, 0, 0), avg_start=0, snap_every=0, snap_count=20, emulate=None,
+         xcd_remap=1, force_every=1):
+    P = _gpu()
+    g = P.Lbm(shape, storage=storage, periodic=periodic, u_in=u_in, nu=nu, mode=mode, obstacle_bc=obstacle_bc,
+              body_force=body_force, avg_start=avg_start, snap_every=snap_every, snap_count=snap_count,
+              solid=solid, links=links, u0=u0, xcd_remap=xcd_remap, force_every=force_every)
+    g.step(steps)
+    p = olbm.make_params(shape, periodic=periodic, nu=nu, u_in=u_in, mode={"plain": 0, "k17": 1}[mode],
+                         obstacle_bc=obstacle_bc, force=body_force, avg_start=avg_start, snap_every=snap_every,
+                         emulate=emulate)
+    o = olbm.Run(p, solid=solid, links=links, u0=u0)
+    o.step(steps, snap_cap=(steps // snap_every + 1) if snap_every else 0)
+    return g, o
+
+
+# ------------------------------------------------------------------ small
+@pytest.mark.parametrize("steps", [20, 21])
+def test_periodic_box_f64_populations(steps):
+    shape = (64, 8, 4)
+    u0 = perturbation(shape, 11, 0.02)
+    g, o = pair(shape, steps, periodic=(1, 1, 1), nu=0.05, u0=u0, u_in=0.0)
+    err = f64_err(g.populations(), o.fbar)
+    assert err < 1e-11, err
+
+
+@pytest.mark.parametrize("steps", [30, 31])
+def test_walled_channel_f64_populations(steps):
+    shape = (64, 8, 8)
+    u0 = perturbation(shape, 3, 5e-4)
+    g, o = pair(shape, steps, u0=u0)
+    err = f64_err(g.populations(), o.fbar)
+    assert err < 1e-11, err
+    m, n = g.mean_fields()
+    assert n == steps
+    assert rel_max(m, o.mean_fields()) < 1e-11
+
+
+@pytest.mark.parametrize("mode", ["plain", "k17"])
+@pytest.mark.parametrize("obstacle_bc", [0, 1])
+def test_obstacle_channel_f64(mode, obstacle_bc):
+    shape = (64, 16, 16)
+    geo = sphere_channel(shape, center=(20.3, 7.6, 7.4), radius=3.3)
+    u0 = perturbation(shape, 5, 5e-4, geo.solid)
+    nu = 0.05 * 16 / 5000 if mode == "k17" else 0.01
+    g, o = pair(shape, 41, solid=geo.solid, links=geo.links, u0=u0, nu=nu, mode=mode, obstacle_bc=obstacle_bc)
+    err = f64_err(g.populations(), o.fbar)
+    assert err < 1e-11, err
+    fg, steps = g.forces()
+    fo = np.array(o.forces)
+    assert np.array_equal(steps, np.arange(41))
+    assert np.abs(fg - fo).max() < 1e-11 * np.abs(fo).max()
+
+
+def test_poiseuille_body_force_f64():
+    shape = (64, 16, 1)
+    g, o = pair(shape, 300, periodic=(1, 0, 1), nu=0.1, u_in=0.0, body_force=(1e-6, 0, 0))
+    err = f64_err(g.populations(), o.fbar)
+    assert err < 1e-11, err
+
+
+def test_snapshots_match_oracle():
+    shape = (64, 8, 8)
+    u0 = perturbation(shape, 9, 5e-4)
+    g, o = pair(shape, 60, storage="f64", u0=u0, snap_every=25, snap_count=2)
+    snaps, steps = g.snapshots()
+    assert list(steps) == [25, 50]
+    so = np.array(o.snaps).reshape((-1, 4) + shape[::-1])
+    # oracle keeps every snapshot (0, 25, 50); the ring keeps the last two
+    assert rel_max(snaps.astype(np.float64), so[1:3]) < 1e-6
+
+
+# ------------------------------------------------------------------ C0
+C0 = dict(shape=(64, 32, 32), steps=500, nu=0.05 * 8 / 1000, u_in=0.05)
+
+
+@pytest.fixture(scope="module")
+def c0_oracle():
+    geo = sphere_channel()
+    u0 = perturbation(geo.shape, 0, 0.01 * C0["u_in"], geo.solid)
+    p = olbm.make_params(geo.shape, nu=C0["nu"], u_in=C0["u_in"], mode=0, avg_start=0)
+    o = olbm.Run(p, solid=geo.solid, u0=u0)
+    o.step(C0["steps"])
+    return geo, u0, o
+
+
+def _c0_gpu(geo, u0, storage, xcd_remap=1):
+    P = _gpu()
+    g = P.Lbm(geo.shape, storage=storage, u_in=C0["u_in"], nu=C0["nu"], mode="plain", solid=geo.solid, u0=u0,
+              avg_start=0, xcd_remap=xcd_remap)
+    g.step(C0["steps"])
+    return g
+
+
+def test_c0_f64_mean_fields_and_drag(c0_oracle):
+    geo, u0, o = c0_oracle
+    g = _c0_gpu(geo, u0, "f64")
+    m, n = g.mean_fields()
+    assert n == C0["steps"]
+    mo = o.mean_fields()
+    assert rel_max(m, mo) < 1e-11
+    fg, _ = g.forces()
+    fo = np.array(o.forces)
+    assert np.abs(fg - fo).max() < 1e-11 * np.abs(fo).max()
+
+
+def test_c0_f32_mean_fields_within_1e5(c0_oracle):
+    geo, u0, o = c0_oracle
+    g = _c0_gpu(geo, u0, "f32")
+    m, _ = g.mean_fields()
+    mo = o.mean_fields()
+    vel = rel_l2(m[:3], mo[:3])
+    assert vel < 1e-5, vel
+    for k in range(4):
+        assert rel_l2(m[k], mo[k]) < 1e-4, (k, rel_l2(m[k], mo[k]))
+    fg, _ = g.forces()
+    fo = np.array(o.forces)
+    assert rel_l2(fg[:, 0], fo[:, 0]) < 1e-5
+
+
+def test_c0_f32_xcd_remap_is_bitwise_neutral(c0_oracle):
+    """Different workgroup-to-tile orders give bitwise identical results: the
+    in-place AA update has no cross-cell read-after-write hazard."""
+    geo, u0, _ = c0_oracle
+    a = _c0_gpu(geo, u0, "f32", xcd_remap=1)
+    b = _c0_gpu(geo, u0, "f32", xcd_remap=0)
+    assert np.array_equal(a.populations(), b.populations())
+    assert np.array_equal(a.mean_fields()[0], b.mean_fields()[0])
+
+
+# ------------------------------------------------------------------ precision
+@pytest.mark.parametrize("storage,bound", [("f16", 3e-3), ("bf16", 3e-2)])
+def test_shifted_low_precision_storage(storage, bound):
+    """FP16/BF16 storage of f - w_i with FP32 arithmetic against the oracle
+    that rounds the stored populations the same way (and against the plain
+    FP64 oracle): the relative L2 error of the mean velocity after 200
+    steps stays below a bound set by the storage precision."""
+    shape = (64, 16, 16)
+    geo = sphere_channel(shape, center=(20.0, 7.5, 7.5), radius=3.0)
+    u0 = perturbation(shape, 2, 5e-4, geo.solid)
+    g, o = pair(shape, 200, storage=storage, solid=geo.solid, u0=u0, nu=0.005, emulate=storage)
+    m, _ = g.mean_fields()
+    e_emul = rel_l2(m[:3], o.mean_fields()[:3])
+    p = olbm.make_params(shape, nu=0.005, u_in=0.05, mode=0)
+    o64 = olbm.Run(p, solid=geo.solid, u0=u0).step(200, forces=False)
+    e64 = rel_l2(m[:3], o64.mean_fields()[:3])
+    assert e_emul < bound and e64 < bound, (e_emul, e64)
+
+
+def test_f32_mass_conserved_periodic():
+    P = _gpu()
+    shape = (64, 16, 8)
+    u0 = perturbation(shape, 4, 0.02)
+    g = P.Lbm(shape, storage="f32", periodic=(1, 1, 1), nu=0.01, u_in=0.0, u0=u0, avg_start=None)
+    m0 = g.mass()
+    g.step(100)
+    m1 = g.mass()
+    assert abs(m1 - m0) < 1e-4 * 0.02 * shape[0] * shape[1] * shape[2] * 1e-2
+
+
+def test_checkpoint_resume_bitwise():
+    P = _gpu()
+    shape = (64, 16, 16)
+    geo = sphere_channel(shape, center=(20.0, 7.5, 7.5), radius=3.0)
+    u0 = perturbation(shape, 8, 5e-4, geo.solid)
+    kw = dict(storage="f32", nu=0.005, solid=geo.solid, u0=u0, snap_every=10, snap_count=3)
+    a = P.Lbm(shape, **kw).step(37)
+    blob = a.export_state()
+    a.step(40)
+    b = P.Lbm(shape, **kw)
+    b.import_state(blob)
+    b.step(40)
+    assert np.array_equal(a.populations(), b.populations())
+    assert np.array_equal(a.mean_fields()[0], b.mean_fields()[0])
+    assert np.array_equal(a.forces()[0], b.forces()[0])
+    assert np.array_equal(a.snapshots()[0], b.snapshots()[0])
+
+
+def test_set_populations_round_trip():
+    P = _gpu()
+    shape = (64, 8, 8)
+    g = P.Lbm(shape, storage="f64", nu=0.02, u0=perturbation(shape, 1, 5e-4))
+    g.step(7)
+    f = g.populations()
+    g.set_populations(f)
+    assert np.array_equal(g.populations(), f)
+
+
+def test_moments_match_populations():
+    P = _gpu()
+    shape = (64, 8, 8)
+    g = P.Lbm(shape, storage="f64", nu=0.02, u0=perturbation(shape, 1, 5e-4)).step(9)
+    f = g.populations().reshape(27, -1)
+    c, _ = olbm.lattice()
+    d = f.sum(0)
+    u = (c.T.astype(float) @ f) / (1 + d)
+    m = g.moments().reshape(4, -1)
+    assert np.abs(m[:3] - u).max() < 1e-7
+    assert np.abs(m[3] - d / 3).max() < 1e-7
