@@ -471,8 +471,14 @@ int orc_run(const orc_params* p, const uint8_t* solid, const double* q, double* 
                 const double qq = q[(int64_t)o * N + n];
                 int64_t nb = 0;
                 int k2 = classify(p, solid, x, y, z, CX[i], CY[i], CZ[i], &nb);
-                if (qq < 0.5 && (k2 == NB_FLUID || k2 == NB_OUTLET)) {
-                  v = 2.0 * qq * post[o * N + n] + (1.0 - 2.0 * qq) * post[o * N + nb];
+                if (qq < 0.5) {
+                  /* with no fluid node behind x the link falls back to
+                     halfway bounce-back (the q >= 1/2 formula would weight
+                     with 1/(2q) > 1 and a negative coefficient) */
+                  if (k2 == NB_FLUID || k2 == NB_OUTLET)
+                    v = 2.0 * qq * post[o * N + n] + (1.0 - 2.0 * qq) * post[o * N + nb];
+                  else
+                    v = post[o * N + n];
                 } else {
                   v = post[o * N + n] / (2.0 * qq) + (2.0 * qq - 1.0) / (2.0 * qq) * post[i * N + n];
                 }

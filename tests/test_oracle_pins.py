@@ -337,6 +337,21 @@ def test_interpolated_bounce_back_half_equals_halfway():
     assert np.allclose(np.array(runs[0].forces), np.array(runs[1].forces), rtol=1e-12, atol=1e-18)
 
 
+def test_interpolated_bounce_back_stable_where_obstacle_meets_wall():
+    """A spanwise cylinder touching the z walls with small wall distances
+    (q = 0.1): links with no fluid node behind them fall back to halfway
+    bounce-back, and the flow stays bounded (the q >= 1/2 formula applied at
+    q < 1/2 would amplify by 1/(2q))."""
+    from inputs import spanwise_cylinder
+    geo = spanwise_cylinder((64, 32, 16), center=(19.2, 15.5), diameter=8.0)
+    cell, d, q = geo.links
+    for qq in (0.1, 0.3):
+        p = lbm.make_params(geo.shape, nu=0.0008, u_in=0.05, obstacle_bc=1)
+        r = lbm.Run(p, solid=geo.solid, links=(cell, d, np.full_like(q, qq))).step(150, forces=False)
+        _, u = r.macroscopic()
+        assert np.abs(u).max() < 0.2
+
+
 def test_interpolated_poiseuille_second_order():
     """Plates at y = 1 - q and ny - 2 + q (off-lattice): the linear
     interpolated bounce-back converges at second order."""
