@@ -81,6 +81,13 @@ typedef struct {
   int64_t snap_start;      /* first step index eligible for a snapshot            */
   int32_t force_every;     /* record the obstacle force every k steps (0 = off)   */
   int32_t xcd_remap;       /* 1: map workgroups to XCD-contiguous tiles           */
+  uint64_t perturb_seed;   /* when u0 is NULL and perturb_amp != 0, the initial
+                              velocity of fluid cell n, component d, is
+                              perturb_amp * xi(seed, 3n + d), xi the uniform
+                              [-1, 1) variate of counter-based SplitMix64
+                              (output k = mix(seed + (k+1) * 0x9E3779B97F4A7C15),
+                              top 53 bits), generated on the device            */
+  double perturb_amp;
 } lbm_params;
 
 /* Fill *p with defaults (F32, channel, omega2 = 1, Galilean on, lambda 0.01,

@@ -23,6 +23,7 @@ class LbmParams(ctypes.Structure):
         ("snap_every", ctypes.c_int32), ("snap_count", ctypes.c_int32),
         ("snap_start", ctypes.c_int64),
         ("force_every", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
+        ("perturb_seed", ctypes.c_uint64), ("perturb_amp", ctypes.c_double),
     ]
 
 

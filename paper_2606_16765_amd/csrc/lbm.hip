@@ -28,19 +28,28 @@ constexpr int TX = 64;   // cells along x per wave
 constexpr int TY = 4;    // waves (rows along y) per block
 constexpr int NTHREADS = TX * TY;
 
+// Population layout, planes of slots: for each padded z plane, the 27 slots
+// of that plane follow each other, each a padded pitch x (ny + 2) sheet,
+// pitch = nx + 64.  Population i of cell (x, y, z) sits at
+//   (z + 1) zstride + i slotp + (y + 1) pitch + x,
+// slotp = pitch (ny + 2), zstride = 27 slotp.  Columns -1 and nx of every
+// row are the inlet and outlet ghosts; guard rows and planes keep every
+// neighbour address of a domain cell inside the array, so loads may be
+// issued before a boundary substitution replaces them.  Everything a tile
+// (64 x 4 cells of one z plane) touches lies within three consecutive
+// padded planes: one uniform base address plus 32-bit lane offsets.
 struct StepArgs {
-  void* A;                  // populations, slot i at A + i*slot elements
+  void* A;                  // populations
   int32_t nx, ny, nz;
-  int32_t pitch;            // elements per row (nx + 64: column nx is the outlet ghost)
-  int64_t slot;             // elements per population slot
+  int32_t pitch;            // elements per row
+  int32_t slotp;            // elements per slot sheet = pitch * (ny + 2)
+  int32_t zstride;          // elements per padded plane = 27 * slotp
   int32_t per[3];           // periodic axes
   const uint8_t* flag;      // [N] 0 fluid, 1 fluid next to obstacle, 2 solid
   const int32_t* brow;      // [N] boundary row of flag-1 cells
   const uint32_t* bmask;    // [nb] bit j: cell + c_j is obstacle
   const double* bq;         // [nb][27] wall distance fractions
   int32_t interp;           // 1: linear interpolated bounce-back
-  double u_in;
-  CollideParams cp;
   double* acc;              // [4][N] running sums or null
   float* snap;              // [4][N] snapshot slot or null
   const int32_t* bslot;     // [ntiles] force slot of the tile or -1 (null: no forces)
@@ -48,6 +57,13 @@ struct StepArgs {
   int32_t tiles_x, tiles_y; // tile grid
   int32_t ntiles;
   int32_t remap;            // XCD-contiguous tile order
+  uint64_t perturb_seed;    // device-generated initial perturbation
+  double perturb_amp;
+};
+
+struct Coefs {
+  Coef<float> f;
+  Coef<double> d;
 };
 
 __device__ __forceinline__ int logical_tile(int b, int ntiles, int remap) {
@@ -59,11 +75,27 @@ __device__ __forceinline__ int logical_tile(int b, int ntiles, int remap) {
   return (b & 7) * per + (b >> 3);
 }
 
-// Per-cell boundary context shared by the read and write phases.
+// element index of population slot 0 of cell (x, y, z)
+__device__ __forceinline__ int64_t cell_index(const StepArgs& a, int x, int y, int z) {
+  return (int64_t)(z + 1) * a.zstride + (int64_t)(y + 1) * a.pitch + x;
+}
+
+// element access through a uniform slot base and a 32-bit element offset
+// general element access: population slot of the cell whose slot-0 index is idx
+template <typename S>
+__device__ __forceinline__ typename Storage<S>::T ld(const StepArgs& a, int slot, int64_t idx) {
+  return Storage<S>::load((const S*)a.A + idx + (int64_t)slot * a.slotp);
+}
+template <typename S>
+__device__ __forceinline__ void st(const StepArgs& a, int slot, int64_t idx, typename Storage<S>::T v) {
+  Storage<S>::store((S*)a.A + idx + (int64_t)slot * a.slotp, v);
+}
+
+// Per-cell boundary context of the general path.
 struct CellCtx {
   int32_t x, y, z;
   int64_t n;        // dense cell index
-  int64_t pc;       // pitched cell index
+  int64_t pc;       // element index of slot 0 of the cell
   uint32_t rmask;   // bit i: pull source cell - c_i is not a fluid node (wall, inlet, obstacle)
   uint32_t inlet;   // bit i: that source is the inlet
   uint32_t om;      // bit j: cell + c_j is obstacle
@@ -78,8 +110,8 @@ __device__ __forceinline__ int src_off(int i, const CellCtx& c) {
 __device__ __forceinline__ void make_ctx(const StepArgs& a, int x, int y, int z, uint8_t fl, CellCtx& c) {
   c.x = x; c.y = y; c.z = z;
   c.n = ((int64_t)z * a.ny + y) * a.nx + x;
-  c.pc = ((int64_t)z * a.ny + y) * a.pitch + x;
-  const int rowp = a.pitch, plane = a.pitch * a.ny;
+  c.pc = cell_index(a, x, y, z);
+  const int rowp = a.pitch, plane = a.zstride;
   // x: source of c=+1 is x-1, of c=-1 is x+1 (x+1 = nx is the outlet ghost)
   c.off[0][1] = 0; c.off[1][1] = 0; c.off[2][1] = 0;
   c.off[0][2] = (a.per[0] && x == 0) ? (a.nx - 1) : -1;
@@ -106,23 +138,22 @@ __device__ __forceinline__ void make_ctx(const StepArgs& a, int x, int y, int z,
   c.rmask = wall | c.inlet | reverse27(c.om);
 }
 
-// Pre-collision populations of a fluid cell for the given AA parity, with
-// the interpolated bounce-back completion (q < 1/2 links).
+// Pre-collision populations of a fluid cell, general path (any boundary),
+// with the interpolated bounce-back completion of q < 1/2 links.
 template <typename S, bool ODD>
-__device__ __forceinline__ void load_cell(const StepArgs& a, const CellCtx& c, typename Storage<S>::T* g) {
+__device__ __forceinline__ void load_general(const StepArgs& a, const Coef<typename Storage<S>::T>& k,
+                                             const CellCtx& c, typename Storage<S>::T* g) {
   using T = typename Storage<S>::T;
-  const S* A = (const S*)a.A;
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
-    int64_t addr;
+    T v;
     if (!ODD) {
-      addr = (int64_t)i * a.slot + c.pc;
+      v = ld<S>(a, i, c.pc);
     } else {
       const bool r = (c.rmask >> i) & 1u;
-      addr = r ? ((int64_t)i * a.slot + c.pc) : ((int64_t)(26 - i) * a.slot + c.pc + src_off(i, c));
+      v = ld<S>(a, r ? i : 26 - i, r ? c.pc : c.pc + src_off(i, c));
+      if (cx(i) == 1 && ((c.inlet >> i) & 1u)) v += T(wgt(i)) * k.u6;
     }
-    T v = Storage<S>::load(A + addr);
-    if (ODD && ((c.inlet >> i) & 1u)) v += T(6.0 * wgt(i) * cx(i) * a.u_in);
     g[i] = v;
   }
   if (a.interp && c.om) {
@@ -136,9 +167,28 @@ __device__ __forceinline__ void load_cell(const StepArgs& a, const CellCtx& c, t
   }
 }
 
+// Interior fast path: no wall, obstacle or periodic wrap in the wave.  zb
+// is the uniform address of the padded plane below the tile's plane, p0 the
+// lane's byte offset within a slot sheet; the neighbour offsets are
+// compile-time combinations of the row, sheet and plane strides.
+template <typename S>
+__device__ __forceinline__ uint32_t fast_off(const StepArgs& a, uint32_t p0, int slot, int dx, int dy, int dz) {
+  return p0 + (uint32_t)(((1 + dz) * a.zstride + slot * a.slotp + dy * a.pitch + dx) * (int)sizeof(S));
+}
+
+template <typename S, bool ODD>
+__device__ __forceinline__ void load_fast(const StepArgs& a, const char* zb, uint32_t p0,
+                                          typename Storage<S>::T* g) {
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const uint32_t o = ODD ? fast_off<S>(a, p0, 26 - i, -cx(i), -cy(i), -cz(i)) : fast_off<S>(a, p0, i, 0, 0, 0);
+    g[i] = Storage<S>::load_nt((const S*)(zb + o));
+  }
+}
+
 template <typename T>
-__device__ __forceinline__ void macroscopic(const T* g, const double* force, T& drho, T& ux, T& uy, T& uz) {
-  // pairwise sums of opposite directions keep the momentum sums exact-ish
+__device__ __forceinline__ void macroscopic(const T* g, const Coef<T>& k, T& drho, T& ux, T& uy, T& uz) {
+  // pairwise sums of opposite directions
   T d = g[13];
   T jx = 0, jy = 0, jz = 0;
 #pragma unroll
@@ -150,17 +200,151 @@ __device__ __forceinline__ void macroscopic(const T* g, const double* force, T& 
     if (cy(o)) jy += cy(o) > 0 ? t : -t;
     if (cz(o)) jz += cz(o) > 0 ? t : -t;
   }
-  const T rho = T(1) + d;
-  const T ir = T(1) / rho;
+  const T irho = T(1) / (T(1) + d);
   drho = d;
-  ux = (jx + T(0.5 * force[0])) * ir;
-  uy = (jy + T(0.5 * force[1])) * ir;
-  uz = (jz + T(0.5 * force[2])) * ir;
+  ux = (jx + k.hf[0]) * irho;
+  uy = (jy + k.hf[1]) * irho;
+  uz = (jz + k.hf[2]) * irho;
 }
 
-template <typename S, bool ODD, int MODE>
-__global__ __launch_bounds__(NTHREADS) void lbm_step_kernel(StepArgs a) {
+// One cell update.  PATH 0: interior wave (no wall, obstacle, periodic wrap,
+// inlet or outlet column in the wave); PATH 1: interior wave of the first or
+// last x tile, with the inlet and outlet columns handled per lane; PATH 2:
+// general boundary path.
+//  inlet (x = -1/2): moving-wall bounce-back, rho_w = 1: a population leaving
+//    through it returns with 6 w_i (c_i . u_in) added;
+//  outlet: zero gradient, through the ghost column x = nx: after an even step
+//    the ghost holds copies of column nx - 1, after an odd step column nx - 1
+//    receives the populations streamed into column nx - 2 from its ghost.
+template <typename S, bool ODD, int MODE, int PATH>
+__device__ __forceinline__ void cell_update(const StepArgs& a, const Coef<typename Storage<S>::T>& k, int x, int y,
+                                            int z, int64_t n, uint8_t fl, double& fx, double& fy, double& fz) {
   using T = typename Storage<S>::T;
+  CellCtx c;
+  T g[27];
+  T Fx = 0, Fy = 0, Fz = 0;
+  const char* zb = (const char*)a.A + (size_t)z * (size_t)a.zstride * sizeof(S);
+  const uint32_t p0 = (uint32_t)(((y + 1) * a.pitch + x) * (int)sizeof(S));
+  const bool at_inlet = PATH == 1 && !a.per[0] && x == 0;
+  const bool outlet = PATH != 0 && !a.per[0] && x == a.nx - 1;
+  if (PATH < 2) {
+    load_fast<S, ODD>(a, zb, p0, g);
+    if (ODD && at_inlet) {
+#pragma unroll
+      for (int i = 0; i < 27; ++i)
+        if (cx(i) == 1) g[i] = Storage<S>::load((const S*)(zb + fast_off<S>(a, p0, i, 0, 0, 0))) + T(wgt(i)) * k.u6;
+    }
+  } else {
+    make_ctx(a, x, y, z, fl, c);
+    load_general<S, ODD>(a, k, c, g);
+    // incoming half of the momentum exchange on obstacle links
+    if (c.om) {
+#pragma unroll
+      for (int j = 0; j < 27; ++j)
+        if ((c.om >> j) & 1u) {
+          const T v = g[26 - j];
+          if (cx(j)) Fx += cx(j) > 0 ? v : -v;
+          if (cy(j)) Fy += cy(j) > 0 ? v : -v;
+          if (cz(j)) Fz += cz(j) > 0 ? v : -v;
+        }
+    }
+  }
+
+  T drho, rho, irho, ux, uy, uz;
+  macro_and_forward(g, k.hf, drho, rho, irho, ux, uy, uz);
+  if (a.acc) {
+    const int64_t N = (int64_t)a.nx * a.ny * a.nz;
+    a.acc[n] += (double)ux;
+    a.acc[N + n] += (double)uy;
+    a.acc[2 * N + n] += (double)uz;
+    a.acc[3 * N + n] += (double)drho * (1.0 / 3.0);
+  }
+  if (a.snap) {
+    const int64_t N = (int64_t)a.nx * a.ny * a.nz;
+    a.snap[n] = (float)ux;
+    a.snap[N + n] = (float)uy;
+    a.snap[2 * N + n] = (float)uz;
+    a.snap[3 * N + n] = (float)(drho * T(1.0 / 3.0));
+  }
+  collide_moments<T, MODE>(g, drho, rho, irho, ux, uy, uz, k);
+  inverse_transform(g, ux, uy, uz);
+
+  if (PATH == 0) {
+#pragma unroll
+    for (int j = 0; j < 27; ++j) {
+      const uint32_t o = ODD ? fast_off<S>(a, p0, j, cx(j), cy(j), cz(j)) : fast_off<S>(a, p0, 26 - j, 0, 0, 0);
+      Storage<S>::store_nt((S*)(zb + o), g[j]);
+    }
+  } else if (PATH == 1) {
+#pragma unroll
+    for (int j = 0; j < 27; ++j) {
+      if (!ODD) {
+        S* p = (S*)(zb + fast_off<S>(a, p0, 26 - j, 0, 0, 0));
+        Storage<S>::store_nt(p, g[j]);
+        if (cx(j) == -1 && outlet) Storage<S>::store(p + 1, g[j]);  // ghost column copy
+      } else {
+        if (cx(j) == -1 && at_inlet) {
+          Storage<S>::store((S*)(zb + fast_off<S>(a, p0, 26 - j, 0, 0, 0)), g[j] + T(wgt(j)) * k.u6);
+        } else {
+          S* p = (S*)(zb + fast_off<S>(a, p0, j, cx(j), cy(j), cz(j)));
+          Storage<S>::store_nt(p, g[j]);
+          // zero-gradient outlet: column nx-1 receives the same value
+          if (cx(j) == -1 && outlet) Storage<S>::store(p + 1, g[j]);
+        }
+      }
+    }
+  } else {
+    if (c.om) {
+#pragma unroll
+      for (int j = 0; j < 27; ++j)
+        if ((c.om >> j) & 1u) {
+          const T v = g[j];
+          if (cx(j)) Fx += cx(j) > 0 ? v : -v;
+          if (cy(j)) Fy += cy(j) > 0 ? v : -v;
+          if (cz(j)) Fz += cz(j) > 0 ? v : -v;
+        }
+      fx = (double)Fx; fy = (double)Fy; fz = (double)Fz;
+    }
+#pragma unroll
+    for (int j = 0; j < 27; ++j) {
+      const int o = 26 - j;
+      T v = g[j];
+      if (a.interp && ((c.om >> j) & 1u)) {
+        // linear interpolated bounce-back: pre-blend of the value that
+        // returns along o (completed on read when q < 1/2)
+        const T q = T(a.bq[(int64_t)c.row * 27 + j]);
+        if (q < T(0.5)) {
+          // no fluid node behind the cell: halfway bounce-back
+          if (!((c.rmask >> j) & 1u)) v = T(2) * q * g[j];
+        } else {
+          v = g[j] / (T(2) * q) + (T(2) * q - T(1)) / (T(2) * q) * g[o];
+        }
+      }
+      if (!ODD) {
+        st<S>(a, o, c.pc, v);
+        if (outlet && cx(j) == -1) st<S>(a, o, c.pc + 1, v);  // ghost column copy
+      } else {
+        const bool r = (c.rmask >> o) & 1u;
+        if (r) {
+          if (cx(j) == -1 && ((c.inlet >> o) & 1u)) v += T(wgt(j)) * k.u6;
+          st<S>(a, o, c.pc, v);
+        } else {
+          const int64_t d = c.pc + src_off(o, c);
+          st<S>(a, j, d, v);
+          // zero-gradient outlet: column nx-1 receives the same value
+          if (outlet && cx(j) == -1) st<S>(a, j, d + 1, v);
+        }
+      }
+    }
+  }
+}
+
+#ifndef MLBM_WAVES
+#define MLBM_WAVES 4
+#endif
+template <typename S, bool ODD, int MODE>
+__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(MLBM_WAVES, 8))) void lbm_step_kernel(
+    StepArgs a, Coef<typename Storage<S>::T> k) {
   const int tile = logical_tile(blockIdx.x, a.ntiles, a.remap);
   const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
   const int txi = tile % a.tiles_x;
@@ -173,90 +357,19 @@ __global__ __launch_bounds__(NTHREADS) void lbm_step_kernel(StepArgs a) {
 
   double fx = 0.0, fy = 0.0, fz = 0.0;
   if (fl != 2) {
-    CellCtx c;
-    make_ctx(a, x, y, z, fl, c);
-    T g[27];
-    load_cell<S, ODD>(a, c, g);
-
-    T drho, ux, uy, uz;
-    macroscopic(g, a.cp.force, drho, ux, uy, uz);
-    if (a.acc) {
-      const int64_t N = (int64_t)a.nx * a.ny * a.nz;
-      a.acc[n] += (double)ux;
-      a.acc[N + n] += (double)uy;
-      a.acc[2 * N + n] += (double)uz;
-      a.acc[3 * N + n] += (double)drho * (1.0 / 3.0);
-    }
-    if (a.snap) {
-      const int64_t N = (int64_t)a.nx * a.ny * a.nz;
-      a.snap[n] = (float)ux;
-      a.snap[N + n] = (float)uy;
-      a.snap[2 * N + n] = (float)uz;
-      a.snap[3 * N + n] = (float)(drho * T(1.0 / 3.0));
-    }
-    // incoming half of the momentum exchange on obstacle links
-    T Fx = 0, Fy = 0, Fz = 0;
-    if (c.om) {
-#pragma unroll
-      for (int j = 0; j < 27; ++j)
-        if ((c.om >> j) & 1u) {
-          const T v = g[26 - j];
-          if (cx(j)) Fx += cx(j) > 0 ? v : -v;
-          if (cy(j)) Fy += cy(j) > 0 ? v : -v;
-          if (cz(j)) Fz += cz(j) > 0 ? v : -v;
-        }
-    }
-
-    const T rho = T(1) + drho;
-    const T irho = T(1) / rho;
-    forward_transform(g, ux, uy, uz);
-    collide_moments<T, MODE>(g, drho, rho, irho, ux, uy, uz, a.cp);
-    inverse_transform(g, ux, uy, uz);
-
-    if (c.om) {
-#pragma unroll
-      for (int j = 0; j < 27; ++j)
-        if ((c.om >> j) & 1u) {
-          const T v = g[j];
-          if (cx(j)) Fx += cx(j) > 0 ? v : -v;
-          if (cy(j)) Fy += cy(j) > 0 ? v : -v;
-          if (cz(j)) Fz += cz(j) > 0 ? v : -v;
-        }
-      fx = (double)Fx; fy = (double)Fy; fz = (double)Fz;
-    }
-
-    // write phase
-    S* A = (S*)a.A;
-    const bool outlet = !a.per[0] && x == a.nx - 1;
-#pragma unroll
-    for (int j = 0; j < 27; ++j) {
-      const int o = 26 - j;
-      T v = g[j];
-      if (a.interp && ((c.om >> j) & 1u)) {
-        // linear interpolated bounce-back: pre-blend of the value that
-        // returns along o (completed on read when q < 1/2)
-        const T q = T(a.bq[(int64_t)c.row * 27 + j]);
-        if (q < T(0.5) && !((c.rmask >> j) & 1u)) v = T(2) * q * g[j];
-        else v = g[j] / (T(2) * q) + (T(2) * q - T(1)) / (T(2) * q) * g[o];
-      }
-      int64_t addr;
-      if (!ODD) {
-        addr = (int64_t)o * a.slot + c.pc;
-        Storage<S>::store(A + addr, v);
-        if (outlet && cx(j) == -1) Storage<S>::store(A + addr + 1, v);  // ghost column copy
-      } else {
-        const bool r = (c.rmask >> o) & 1u;
-        if (r) {
-          if ((c.inlet >> o) & 1u) v -= T(6.0 * wgt(j) * cx(j) * a.u_in);
-          addr = (int64_t)o * a.slot + c.pc;
-          Storage<S>::store(A + addr, v);
-        } else {
-          addr = (int64_t)j * a.slot + c.pc + src_off(o, c);
-          Storage<S>::store(A + addr, v);
-          // zero-gradient outlet: the column nx-1 receives the same value
-          if (outlet && cx(j) == -1) Storage<S>::store(A + addr + 1, v);
-        }
-      }
+    // periodic axes wrap at their faces and walls bounce back: both take
+    // the general path; the inlet and outlet columns take the edge path
+    const bool xin = a.per[0] ? (x > 0 && x < a.nx - 1) : true;
+    const bool interior = fl == 0 && xin && y > 0 && y < a.ny - 1 && z > 0 && z < a.nz - 1;
+#ifndef MLBM_EDGE_PATH
+#define MLBM_EDGE_PATH 1
+#endif
+    const bool edge_tile = !a.per[0] && (txi == 0 || txi == a.tiles_x - 1);
+    if (!__any(!interior)) {
+      if (edge_tile) cell_update<S, ODD, MODE, MLBM_EDGE_PATH>(a, k, x, y, z, n, fl, fx, fy, fz);
+      else cell_update<S, ODD, MODE, 0>(a, k, x, y, z, n, fl, fx, fy, fz);
+    } else {
+      cell_update<S, ODD, MODE, 2>(a, k, x, y, z, n, fl, fx, fy, fz);
     }
   }
 
@@ -326,9 +439,8 @@ __device__ __forceinline__ void store_natural(const StepArgs& a, int x, int y, i
       }
     }
   }
-  S* A = (S*)a.A;
 #pragma unroll
-  for (int i = 0; i < 27; ++i) Storage<S>::store(A + (int64_t)i * a.slot + c.pc, g[i]);
+  for (int i = 0; i < 27; ++i) st<S>(a, i, c.pc, g[i]);
 }
 
 // Equilibrium initial state at rho = 1: fbar = w (Phi - 1) with Phi the
@@ -344,13 +456,24 @@ __global__ __launch_bounds__(256) void init_kernel(StepArgs a, const double* u0)
   const uint8_t fl = a.flag[n];
   T g[27];
   if (fl == 2) {
-    const int64_t pc = ((int64_t)z * a.ny + y) * a.pitch + x;
-    S* A = (S*)a.A;
-    for (int i = 0; i < 27; ++i) Storage<S>::store(A + (int64_t)i * a.slot + pc, T(0));
+    const int64_t pc = cell_index(a, x, y, z);
+    for (int i = 0; i < 27; ++i) st<S>(a, i, pc, T(0));
     return;
   }
   T u[3] = {0, 0, 0};
-  if (u0) { u[0] = T(u0[n]); u[1] = T(u0[N + n]); u[2] = T(u0[2 * N + n]); }
+  if (u0) {
+    u[0] = T(u0[n]); u[1] = T(u0[N + n]); u[2] = T(u0[2 * N + n]);
+  } else if (a.perturb_amp != 0.0) {
+    for (int d = 0; d < 3; ++d) {
+      // counter-based SplitMix64 (Steele, Lea, Flood 2014), output 3n + d
+      uint64_t zz = a.perturb_seed + (uint64_t)(3 * n + d + 1) * 0x9E3779B97F4A7C15ull;
+      zz = (zz ^ (zz >> 30)) * 0xBF58476D1CE4E5B9ull;
+      zz = (zz ^ (zz >> 27)) * 0x94D049BB133111EBull;
+      zz ^= zz >> 31;
+      const double xi = (double)(zz >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+      u[d] = T(a.perturb_amp * xi);
+    }
+  }
   T del[3][3];
   for (int d = 0; d < 3; ++d) {
     del[d][1] = T(-1.5) * u[d] * u[d];
@@ -370,7 +493,8 @@ __global__ __launch_bounds__(256) void init_kernel(StepArgs a, const double* u0)
 // as double [27][N], and/or moments (u, v, w, p) as float [4][N], and/or the
 // per-block mass partial.
 template <typename S, bool ODD>
-__global__ __launch_bounds__(NTHREADS) void export_kernel(StepArgs a, double* pops, float* mom, double* mass_part) {
+__global__ __launch_bounds__(NTHREADS) void export_kernel(StepArgs a, Coef<typename Storage<S>::T> k, double* pops,
+                                                          float* mom, double* mass_part) {
   using T = typename Storage<S>::T;
   const int tile = blockIdx.x;
   const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
@@ -387,11 +511,11 @@ __global__ __launch_bounds__(NTHREADS) void export_kernel(StepArgs a, double* po
     CellCtx c;
     make_ctx(a, x, y, z, fl, c);
     T g[27];
-    load_cell<S, ODD>(a, c, g);
+    load_general<S, ODD>(a, k, c, g);
     if (pops)
       for (int i = 0; i < 27; ++i) pops[(int64_t)i * N + n] = (double)g[i];
     T drho, ux, uy, uz;
-    macroscopic(g, a.cp.force, drho, ux, uy, uz);
+    macroscopic(g, k, drho, ux, uy, uz);
     if (mom) {
       mom[n] = (float)ux; mom[N + n] = (float)uy; mom[2 * N + n] = (float)uz;
       mom[3 * N + n] = (float)(drho * T(1.0 / 3.0));
@@ -427,9 +551,8 @@ __global__ __launch_bounds__(256) void import_kernel(StepArgs a, const double* p
   T g[27];
   for (int i = 0; i < 27; ++i) g[i] = fl == 2 ? T(0) : T(pops[(int64_t)i * N + n]);
   if (fl == 2) {
-    const int64_t pc = ((int64_t)z * a.ny + y) * a.pitch + x;
-    S* A = (S*)a.A;
-    for (int i = 0; i < 27; ++i) Storage<S>::store(A + (int64_t)i * a.slot + pc, T(0));
+    const int64_t pc = cell_index(a, x, y, z);
+    for (int i = 0; i < 27; ++i) st<S>(a, i, pc, T(0));
     return;
   }
   store_natural<S>(a, x, y, z, fl, g);
@@ -466,6 +589,8 @@ struct lbm_sim {
   int64_t N = 0;
   size_t esize = 0;
   StepArgs args{};
+  Coefs coefs{};
+  int64_t pop_elems = 0;
   void* A = nullptr;
   uint8_t* d_flag = nullptr;
   int32_t* d_brow = nullptr;
@@ -557,43 +682,71 @@ static void k17_rates(double w1, double w2, double* o) {
          (3.0 * (w1 - w2) * (w2 * (2.0 + 3.0 * w1) - 8.0 * w1));
 }
 
+template <typename T>
+static void fill_coef(Coef<T>& k, double w1, double w2, double G, double lam, const double* k17, const double* force,
+                      double u_in) {
+  k.w1 = T(w1); k.w2 = T(w2);
+  k.omw1 = T(1.0 - w1); k.omw2 = T(1.0 - w2);
+  k.c1 = T(G * 3.0 * (1.0 - 0.5 * w1));
+  k.c2 = T(G * 3.0 * (1.0 - 0.5 * w2));
+  k.lam = T(lam);
+  k.l3 = T((1.0 - k17[0]) * lam);
+  k.l4 = T((1.0 - k17[1]) * lam);
+  k.l5 = T((1.0 - k17[2]) * lam);
+  const double t = 1.0 / w1 - 0.5;
+  k.a4 = T(-(2.0 / 3.0) * t * k17[3]);
+  k.b4 = T(t * k17[4] * w1);
+  for (int d = 0; d < 3; ++d) k.hf[d] = T(0.5 * force[d]);
+  k.u6 = T(6.0 * u_in);
+}
+
+template <typename S> static const Coef<typename Storage<S>::T>& coef_for(const Coefs& c);
+template <> const Coef<double>& coef_for<double>(const Coefs& c) { return c.d; }
+template <> const Coef<float>& coef_for<float>(const Coefs& c) { return c.f; }
+template <> const Coef<float>& coef_for<f16s>(const Coefs& c) { return c.f; }
+template <> const Coef<float>& coef_for<bf16s>(const Coefs& c) { return c.f; }
+
 template <typename S, bool ODD, int MODE>
-static void launch_step(const StepArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((lbm_step_kernel<S, ODD, MODE>), dim3(a.ntiles), dim3(NTHREADS), 0, st, a);
+static void launch_step(const StepArgs& a, const Coefs& c, hipStream_t st) {
+  hipLaunchKernelGGL((lbm_step_kernel<S, ODD, MODE>), dim3(a.ntiles), dim3(NTHREADS), 0, st, a, coef_for<S>(c));
 }
 
 template <typename S>
-static void launch_step_s(const StepArgs& a, bool odd, int mode, hipStream_t st) {
+static void launch_step_s(const StepArgs& a, const Coefs& c, bool odd, int mode, hipStream_t st) {
   if (odd) {
-    if (mode) launch_step<S, true, 1>(a, st); else launch_step<S, true, 0>(a, st);
+    if (mode) launch_step<S, true, 1>(a, c, st); else launch_step<S, true, 0>(a, c, st);
   } else {
-    if (mode) launch_step<S, false, 1>(a, st); else launch_step<S, false, 0>(a, st);
+    if (mode) launch_step<S, false, 1>(a, c, st); else launch_step<S, false, 0>(a, c, st);
   }
 }
 
-static void launch_step_any(int storage, const StepArgs& a, bool odd, int mode, hipStream_t st) {
+static void launch_step_any(int storage, const StepArgs& a, const Coefs& c, bool odd, int mode, hipStream_t st) {
   switch (storage) {
-    case LBM_F64: launch_step_s<double>(a, odd, mode, st); break;
-    case LBM_F32: launch_step_s<float>(a, odd, mode, st); break;
-    case LBM_F16S: launch_step_s<f16s>(a, odd, mode, st); break;
-    case LBM_BF16S: launch_step_s<bf16s>(a, odd, mode, st); break;
+    case LBM_F64: launch_step_s<double>(a, c, odd, mode, st); break;
+    case LBM_F32: launch_step_s<float>(a, c, odd, mode, st); break;
+    case LBM_F16S: launch_step_s<f16s>(a, c, odd, mode, st); break;
+    case LBM_BF16S: launch_step_s<bf16s>(a, c, odd, mode, st); break;
   }
 }
 
 template <typename S>
-static void launch_export_s(const StepArgs& a, bool odd, double* pops, float* mom, double* mp, hipStream_t st) {
-  StepArgs b = a;
-  if (odd) hipLaunchKernelGGL((export_kernel<S, true>), dim3(a.ntiles), dim3(NTHREADS), 0, st, b, pops, mom, mp);
-  else hipLaunchKernelGGL((export_kernel<S, false>), dim3(a.ntiles), dim3(NTHREADS), 0, st, b, pops, mom, mp);
+static void launch_export_s(const StepArgs& a, const Coefs& c, bool odd, double* pops, float* mom, double* mp,
+                            hipStream_t st) {
+  if (odd)
+    hipLaunchKernelGGL((export_kernel<S, true>), dim3(a.ntiles), dim3(NTHREADS), 0, st, a, coef_for<S>(c), pops, mom,
+                       mp);
+  else
+    hipLaunchKernelGGL((export_kernel<S, false>), dim3(a.ntiles), dim3(NTHREADS), 0, st, a, coef_for<S>(c), pops,
+                       mom, mp);
 }
 
-static void launch_export(int storage, const StepArgs& a, bool odd, double* pops, float* mom, double* mp,
-                          hipStream_t st) {
+static void launch_export(int storage, const StepArgs& a, const Coefs& c, bool odd, double* pops, float* mom,
+                          double* mp, hipStream_t st) {
   switch (storage) {
-    case LBM_F64: launch_export_s<double>(a, odd, pops, mom, mp, st); break;
-    case LBM_F32: launch_export_s<float>(a, odd, pops, mom, mp, st); break;
-    case LBM_F16S: launch_export_s<f16s>(a, odd, pops, mom, mp, st); break;
-    case LBM_BF16S: launch_export_s<bf16s>(a, odd, pops, mom, mp, st); break;
+    case LBM_F64: launch_export_s<double>(a, c, odd, pops, mom, mp, st); break;
+    case LBM_F32: launch_export_s<float>(a, c, odd, pops, mom, mp, st); break;
+    case LBM_F16S: launch_export_s<f16s>(a, c, odd, pops, mom, mp, st); break;
+    case LBM_BF16S: launch_export_s<bf16s>(a, c, odd, pops, mom, mp, st); break;
   }
 }
 
@@ -648,9 +801,11 @@ extern "C" int lbm_create(const lbm_params* pin, const uint8_t* solid, int64_t n
     return fail(nullptr, LBM_EINVAL, "bad link arrays");
   const int64_t N = (int64_t)p.nx * p.ny * p.nz;
   const int64_t pitch = (int64_t)p.nx + 64;
-  const int64_t slot = pitch * p.ny * p.nz;
-  if (slot >= (int64_t(1) << 31) || N >= (int64_t(1) << 31))
-    return fail(nullptr, LBM_EINVAL, "grid too large (per-slot index must fit 31 bits)");
+  const int64_t slotp = pitch * (p.ny + 2);
+  const int64_t zstride = 27 * slotp;
+  const int64_t pop_elems = zstride * (p.nz + 2);
+  if (3 * zstride * (int64_t)storage_size(p.storage) >= (int64_t(1) << 31) || N >= (int64_t(1) << 31))
+    return fail(nullptr, LBM_EINVAL, "grid too large (three padded planes must stay below 2 GiB)");
   const int64_t ntiles = (int64_t)(p.nx / TX) * (p.ny / TY) * p.nz;
   if (ntiles >= (int64_t(1) << 31)) return fail(nullptr, LBM_EINVAL, "too many tiles");
 
@@ -743,7 +898,8 @@ extern "C" int lbm_create(const lbm_params* pin, const uint8_t* solid, int64_t n
 
   // ---- device memory ----
   hipError_t e = hipSuccess;
-  const size_t popbytes = (size_t)27 * slot * s->esize;
+  const size_t popbytes = (size_t)pop_elems * s->esize;
+  s->pop_elems = pop_elems;
   if ((e = hipMalloc(&s->A, popbytes)) != hipSuccess) {
     fail(nullptr, e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "population allocation failed");
     return bail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE);
@@ -801,20 +957,20 @@ extern "C" int lbm_create(const lbm_params* pin, const uint8_t* solid, int64_t n
   a.A = s->A;
   a.nx = p.nx; a.ny = p.ny; a.nz = p.nz;
   a.pitch = (int32_t)pitch;
-  a.slot = slot;
+  a.slotp = (int32_t)slotp;
+  a.zstride = (int32_t)zstride;
   for (int d = 0; d < 3; ++d) a.per[d] = p.periodic[d] ? 1 : 0;
   a.flag = s->d_flag;
   a.brow = s->d_brow;
   a.bmask = s->d_bmask;
   a.bq = s->d_bq;
   a.interp = p.obstacle_bc == 1 ? 1 : 0;
-  a.u_in = p.u_in;
-  a.cp.omega1 = s->omega1;
-  a.cp.omega2 = p.omega2;
-  a.cp.galilean = p.galilean;
-  a.cp.lambda = p.lambda;
-  k17_rates(s->omega1, p.omega2, a.cp.k17);
-  for (int d = 0; d < 3; ++d) a.cp.force[d] = p.body_force[d];
+  {
+    double co[5];
+    k17_rates(s->omega1, p.omega2, co);
+    fill_coef(s->coefs.f, s->omega1, p.omega2, p.galilean, p.lambda, co, p.body_force, p.u_in);
+    fill_coef(s->coefs.d, s->omega1, p.omega2, p.galilean, p.lambda, co, p.body_force, p.u_in);
+  }
   a.acc = nullptr;
   a.snap = nullptr;
   a.bslot = nullptr;
@@ -823,6 +979,8 @@ extern "C" int lbm_create(const lbm_params* pin, const uint8_t* solid, int64_t n
   a.tiles_y = tiles_y;
   a.ntiles = (int32_t)ntiles;
   a.remap = p.xcd_remap ? 1 : 0;
+  a.perturb_seed = p.perturb_seed;
+  a.perturb_amp = p.perturb_amp;
 
   double* d_u0 = nullptr;
   if (u0) {
@@ -888,7 +1046,7 @@ extern "C" int lbm_step(lbm_sim* s, int64_t nsteps) {
       HIPCHK(s, hipEventCreate(&e1));
       HIPCHK(s, hipEventRecord(e0, s->stream));
     }
-    launch_step_any(p.storage, a, s->parity != 0, s->mode, s->stream);
+    launch_step_any(p.storage, a, s->coefs, s->parity != 0, s->mode, s->stream);
     if (s->profiling) {
       HIPCHK(s, hipEventRecord(e1, s->stream));
       s->events.emplace_back(e0, e1);
@@ -973,7 +1131,7 @@ extern "C" int lbm_moments(lbm_sim* s, float* out, int out_on_device) {
     HIPCHK(s, hipMalloc(&tmp, (size_t)s->N * 16));
     dst = tmp;
   }
-  launch_export(s->p.storage, s->args, s->parity != 0, nullptr, dst, nullptr, s->stream);
+  launch_export(s->p.storage, s->args, s->coefs, s->parity != 0, nullptr, dst, nullptr, s->stream);
   if (tmp) HIPCHK(s, hipMemcpyAsync(out, tmp, (size_t)s->N * 16, hipMemcpyDeviceToHost, s->stream));
   hipError_t e = hipStreamSynchronize(s->stream);
   if (tmp) (void)hipFree(tmp);
@@ -986,7 +1144,7 @@ extern "C" int lbm_get_populations(lbm_sim* s, double* fbar) {
   if (s->sticky) return s->sticky;
   double* tmp = nullptr;
   HIPCHK(s, hipMalloc(&tmp, (size_t)s->N * 27 * 8));
-  launch_export(s->p.storage, s->args, s->parity != 0, tmp, nullptr, nullptr, s->stream);
+  launch_export(s->p.storage, s->args, s->coefs, s->parity != 0, tmp, nullptr, nullptr, s->stream);
   hipError_t e = hipMemcpyAsync(fbar, tmp, (size_t)s->N * 27 * 8, hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   (void)hipFree(tmp);
@@ -1017,7 +1175,7 @@ extern "C" int lbm_mass(lbm_sim* s, double* mass) {
   double* part = nullptr;
   const int nt = s->args.ntiles;
   HIPCHK(s, hipMalloc(&part, (size_t)nt * 8));
-  launch_export(s->p.storage, s->args, s->parity != 0, nullptr, nullptr, part, s->stream);
+  launch_export(s->p.storage, s->args, s->coefs, s->parity != 0, nullptr, nullptr, part, s->stream);
   std::vector<double> h((size_t)nt);
   hipError_t e = hipMemcpyAsync(h.data(), part, (size_t)nt * 8, hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -1046,7 +1204,7 @@ extern "C" int lbm_export_state(lbm_sim* s, void* blob, size_t cap, size_t* used
   h.nx = s->p.nx; h.ny = s->p.ny; h.nz = s->p.nz; h.storage = s->p.storage;
   h.steps = s->steps; h.nsamples = s->nsamples; h.snap_taken = s->snap_taken; h.nforces = s->nforces;
   h.parity = s->parity;
-  h.popbytes = (int64_t)(27 * s->args.slot * (int64_t)s->esize);
+  h.popbytes = (int64_t)(s->pop_elems * (int64_t)s->esize);
   h.accbytes = s->d_acc ? s->N * 32 : 0;
   h.snapbytes = s->d_snap ? (int64_t)s->p.snap_count * s->N * 16 : 0;
   const size_t need = sizeof(Blob) + h.popbytes + h.accbytes + h.snapbytes + (size_t)h.nforces * 32 +
@@ -1084,7 +1242,7 @@ extern "C" int lbm_import_state(lbm_sim* s, const void* blob, size_t n) {
   if (std::memcmp(h.magic, "MLBMCKP1", 8) || h.nx != s->p.nx || h.ny != s->p.ny || h.nz != s->p.nz ||
       h.storage != s->p.storage)
     return fail(s, LBM_EINVAL, "checkpoint does not match this object");
-  const int64_t popbytes = (int64_t)(27 * s->args.slot * (int64_t)s->esize);
+  const int64_t popbytes = (int64_t)(s->pop_elems * (int64_t)s->esize);
   if (h.popbytes != popbytes || h.accbytes != (s->d_acc ? s->N * 32 : 0) ||
       h.snapbytes != (s->d_snap ? (int64_t)s->p.snap_count * s->N * 16 : 0))
     return fail(s, LBM_EINVAL, "checkpoint layout does not match this object");

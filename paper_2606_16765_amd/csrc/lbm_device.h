@@ -14,36 +14,59 @@ struct f16s { uint16_t bits; };
 struct bf16s { uint16_t bits; };
 
 template <typename S> struct Storage;
+// load/store take the value streamed once per step; the _nt forms add the
+// non-temporal hint (the populations are not reused within a step).
+#ifndef MLBM_NT
+#define MLBM_NT 0
+#endif
 template <> struct Storage<double> {
   using T = double;
   static __device__ __forceinline__ double load(const double* p) { return *p; }
   static __device__ __forceinline__ void store(double* p, double v) { *p = v; }
+  static __device__ __forceinline__ double load_nt(const double* p) { return MLBM_NT ? __builtin_nontemporal_load(p) : *p; }
+  static __device__ __forceinline__ void store_nt(double* p, double v) {
+    if (MLBM_NT) __builtin_nontemporal_store(v, p); else *p = v;
+  }
 };
 template <> struct Storage<float> {
   using T = float;
   static __device__ __forceinline__ float load(const float* p) { return *p; }
   static __device__ __forceinline__ void store(float* p, float v) { *p = v; }
+  static __device__ __forceinline__ float load_nt(const float* p) { return MLBM_NT ? __builtin_nontemporal_load(p) : *p; }
+  static __device__ __forceinline__ void store_nt(float* p, float v) {
+    if (MLBM_NT) __builtin_nontemporal_store(v, p); else *p = v;
+  }
 };
+__device__ __forceinline__ float f16_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
+// v_cvt_f16_f32 rounds to nearest even in the default mode
+__device__ __forceinline__ uint16_t f32_to_f16(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+__device__ __forceinline__ uint16_t f32_to_bf16(float v) {
+  uint32_t b = __float_as_uint(v);
+  // round to nearest, ties to even; quiet NaN stays NaN
+  uint32_t r = ((b & 0x7fffffffu) > 0x7f800000u) ? (0x7fc00000u) : (b + 0x7fffu + ((b >> 16) & 1u));
+  return (uint16_t)(r >> 16);
+}
 template <> struct Storage<f16s> {
   using T = float;
-  static __device__ __forceinline__ float load(const f16s* p) {
-    return (float)__builtin_bit_cast(_Float16, *(const uint16_t*)p);
+  static __device__ __forceinline__ float load(const f16s* p) { return f16_to_f32(*(const uint16_t*)p); }
+  static __device__ __forceinline__ void store(f16s* p, float v) { *(uint16_t*)p = f32_to_f16(v); }
+  static __device__ __forceinline__ float load_nt(const f16s* p) {
+    return f16_to_f32(__builtin_nontemporal_load((const uint16_t*)p));
   }
-  static __device__ __forceinline__ void store(f16s* p, float v) {
-    // v_cvt_f16_f32 rounds to nearest even in the default mode
-    *(uint16_t*)p = __builtin_bit_cast(uint16_t, (_Float16)v);
+  static __device__ __forceinline__ void store_nt(f16s* p, float v) {
+    __builtin_nontemporal_store(f32_to_f16(v), (uint16_t*)p);
   }
 };
 template <> struct Storage<bf16s> {
   using T = float;
-  static __device__ __forceinline__ float load(const bf16s* p) {
-    return __uint_as_float(((uint32_t) * (const uint16_t*)p) << 16);
+  static __device__ __forceinline__ float load(const bf16s* p) { return bf16_to_f32(*(const uint16_t*)p); }
+  static __device__ __forceinline__ void store(bf16s* p, float v) { *(uint16_t*)p = f32_to_bf16(v); }
+  static __device__ __forceinline__ float load_nt(const bf16s* p) {
+    return bf16_to_f32(__builtin_nontemporal_load((const uint16_t*)p));
   }
-  static __device__ __forceinline__ void store(bf16s* p, float v) {
-    uint32_t b = __float_as_uint(v);
-    // round to nearest, ties to even; quiet NaN stays NaN
-    uint32_t r = ((b & 0x7fffffffu) > 0x7f800000u) ? (0x7fc00000u) : (b + 0x7fffu + ((b >> 16) & 1u));
-    *(uint16_t*)p = (uint16_t)(r >> 16);
+  static __device__ __forceinline__ void store_nt(bf16s* p, float v) {
+    __builtin_nontemporal_store(f32_to_bf16(v), (uint16_t*)p);
   }
 };
 
@@ -71,6 +94,10 @@ constexpr uint32_t M_ZP = mask_of(2, 1), M_ZN = mask_of(2, -1);
 
 __device__ __forceinline__ uint32_t reverse27(uint32_t m) { return __builtin_bitreverse32(m) >> 5; }
 
+template <typename T> __device__ __forceinline__ T fast_rcp(T x);
+template <> __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double fast_rcp<double>(double x) { return 1.0 / x; }
+
 // ------------------------------------------------- central-moment transform
 // Shifted form: the line holds g = f - K*(1/6, 2/3, 1/6) for a line rest
 // factor K; the transform returns (k0 - K, k1, k2 - K/3), i.e. the central
@@ -96,12 +123,40 @@ __device__ __forceinline__ void inv_line(T& m, T& z, T& p, T a, T K) {
   m = T(0.5) * (m2 - m1);
 }
 
+// Macroscopic quantities and the forward transform in one pass: the z-line
+// sums of the first pass give rho - 1 and the momentum, the velocity then
+// completes the three passes.  hf is half the body force.
 template <typename T>
-__device__ __forceinline__ void forward_transform(T* g, T ux, T uy, T uz) {
+__device__ __forceinline__ void macro_and_forward(T* g, const T* hf, T& drho, T& rho, T& irho, T& ux, T& uy,
+                                                  T& uz) {
+  T sz[9], dz[9];
 #pragma unroll
-  for (int yx = 0; yx < 9; ++yx) {  // z lines, fixed (cx, cy)
+  for (int yx = 0; yx < 9; ++yx) {
+    const T m = g[yx], z = g[9 + yx], p = g[18 + yx];
+    sz[yx] = p + m;
+    dz[yx] = p - m;
+    g[yx] = sz[yx] + z;  // k0 of the z line (shifted)
+  }
+  // density and momentum from the line sums: x and y velocities are those of
+  // the line, z momentum is the sum of the line differences
+  const T c_m = g[0] + g[3] + g[6], c_0 = g[1] + g[4] + g[7], c_p = g[2] + g[5] + g[8];
+  const T r_m = g[0] + g[1] + g[2], r_p = g[6] + g[7] + g[8];
+  const T d = c_m + c_0 + c_p;
+  const T jx = c_p - c_m, jy = r_p - r_m;
+  const T jz = ((dz[0] + dz[1]) + (dz[2] + dz[3])) + ((dz[4] + dz[5]) + (dz[6] + dz[7])) + dz[8];
+  drho = d;
+  rho = T(1) + d;
+  irho = fast_rcp(rho);
+  ux = (jx + hf[0]) * irho;
+  uy = (jy + hf[1]) * irho;
+  uz = (jz + hf[2]) * irho;
+#pragma unroll
+  for (int yx = 0; yx < 9; ++yx) {  // finish the z lines, fixed (cx, cy)
     const int x = yx % 3, y = yx / 3;
-    fwd_line(g[3 * y + x], g[9 + 3 * y + x], g[18 + 3 * y + x], uz, T(w1d(x - 1) * w1d(y - 1)));
+    const T K = T(w1d(x - 1) * w1d(y - 1));
+    const T kt = g[yx] + K;
+    g[9 + yx] = dz[yx] - uz * kt;
+    g[18 + yx] = sz[yx] + uz * (uz * kt - T(2) * dz[yx]);
   }
 #pragma unroll
   for (int zx = 0; zx < 9; ++zx) {  // y lines, fixed (cx, z order)
@@ -114,6 +169,7 @@ __device__ __forceinline__ void forward_transform(T* g, T ux, T uy, T uz) {
     fwd_line(g[9 * c + 3 * b], g[9 * c + 3 * b + 1], g[9 * c + 3 * b + 2], ux, T(rest1d(b) * rest1d(c)));
   }
 }
+
 template <typename T>
 __device__ __forceinline__ void inverse_transform(T* g, T ux, T uy, T uz) {
 #pragma unroll
@@ -136,13 +192,20 @@ __device__ __forceinline__ void inverse_transform(T* g, T ux, T uy, T uz) {
 // moment slot of orders (a, b, c) in x, y, z
 __host__ __device__ constexpr int MI(int a, int b, int c) { return 9 * c + 3 * b + a; }
 
-struct CollideParams {
-  double omega1, omega2;
-  double galilean;            // 1, 0 (or -1)
-  double lambda;
-  double k17[5];              // w3, w4, w5, A, B
-  double force[3];
+// Collision constants, precomputed on the host in the compute type.
+template <typename T>
+struct Coef {
+  T w1, w2;        // shear and bulk rates
+  T omw1, omw2;    // 1 - omega
+  T c1, c2;        // Galilean correction factors G * 3 (1 - omega/2)
+  T lam;           // third-order limiter
+  T l3, l4, l5;    // (1 - w3) lam, (1 - w4) lam, (1 - w5) lam
+  T a4;            // -(2/3) (1/w1 - 1/2) A
+  T b4;            // (1/w1 - 1/2) B w1
+  T hf[3];         // half body force
+  T u6;            // 6 u_in (moving-wall inlet)
 };
+
 
 // Cumulant collision of one cell in the transformed, shifted representation.
 // On entry g holds the shifted central moments of orders <= 3 (higher
@@ -150,62 +213,58 @@ struct CollideParams {
 // set, not relaxed from its value); on exit g holds the post-collision
 // shifted central moments of all orders.
 template <typename T, int MODE>
-__device__ __forceinline__ void collide_moments(T* g, T drho, T rho, T irho, T ux, T uy, T uz,
-                                                const CollideParams& cp) {
-  const T w1 = T(cp.omega1), w2 = T(cp.omega2), G = T(cp.galilean);
+__device__ __forceinline__ void collide_moments(T* g, T drho, T rho, T irho, T ux, T uy, T uz, const Coef<T>& k) {
   const T third = T(1.0 / 3.0);
   // normalised second-order deviations from the rest state 1/3
-  const T d200 = (g[MI(2, 0, 0)] - drho * third) * irho;
-  const T d020 = (g[MI(0, 2, 0)] - drho * third) * irho;
-  const T d002 = (g[MI(0, 0, 2)] - drho * third) * irho;
+  const T d3 = drho * third;
+  const T d200 = (g[MI(2, 0, 0)] - d3) * irho;
+  const T d020 = (g[MI(0, 2, 0)] - d3) * irho;
+  const T d002 = (g[MI(0, 0, 2)] - d3) * irho;
   const T k110 = g[MI(1, 1, 0)] * irho, k101 = g[MI(1, 0, 1)] * irho, k011 = g[MI(0, 1, 1)] * irho;
 
   // velocity-gradient estimates from the second-order non-equilibrium
-  const T Dxu = T(-0.5) * w1 * (T(2) * d200 - d020 - d002) - T(0.5) * w2 * (d200 + d020 + d002);
-  const T Dyv = Dxu + T(1.5) * w1 * (d200 - d020);
-  const T Dzw = Dxu + T(1.5) * w1 * (d200 - d002);
-  const T ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
   const T m1 = d200 - d020, m2 = d200 - d002, tr = d200 + d020 + d002;
-  const T c1 = G * T(3) * (T(1) - T(0.5) * w1), c2 = G * T(3) * (T(1) - T(0.5) * w2);
-  const T m1s = (T(1) - w1) * m1 - c1 * (ux2 * Dxu - uy2 * Dyv);
-  const T m2s = (T(1) - w1) * m2 - c1 * (ux2 * Dxu - uz2 * Dzw);
-  const T trs = (T(1) - w2) * tr - c2 * (ux2 * Dxu + uy2 * Dyv + uz2 * Dzw);
+  const T Dxu = T(-0.5) * k.w1 * (m1 + m2) - T(0.5) * k.w2 * tr;
+  const T Dyv = Dxu + T(1.5) * k.w1 * m1;
+  const T Dzw = Dxu + T(1.5) * k.w1 * m2;
+  const T xD = ux * ux * Dxu, yD = uy * uy * Dyv, zD = uz * uz * Dzw;
+  const T m1s = k.omw1 * m1 - k.c1 * (xD - yD);
+  const T m2s = k.omw1 * m2 - k.c1 * (xD - zD);
+  const T trs = k.omw2 * tr - k.c2 * (xD + yD + zD);
   const T a = (m1s + m2s + trs) * third;            // post d200
   const T b = (trs - T(2) * m1s + m2s) * third;     // post d020
   const T c = (trs + m1s - T(2) * m2s) * third;     // post d002
-  const T s110 = (T(1) - w1) * k110, s101 = (T(1) - w1) * k101, s011 = (T(1) - w1) * k011;
+  const T s110 = k.omw1 * k110, s101 = k.omw1 * k101, s011 = k.omw1 * k011;
 
   // third order (cumulants equal moments) and fourth-order cumulants
   T C210 = 0, C012 = 0, C201 = 0, C021 = 0, C120 = 0, C102 = 0, C111 = 0;
   T C220 = 0, C202 = 0, C022 = 0, C211 = 0, C121 = 0, C112 = 0;
   if (MODE == 1) {
-    const T w3 = T(cp.k17[0]), w4 = T(cp.k17[1]), w5 = T(cp.k17[2]), A = T(cp.k17[3]), B = T(cp.k17[4]);
-    const T lam = T(cp.lambda);
-    // relaxed value (1 - omega_lambda) c with omega_lambda = omega + (1-omega)|c|/(lambda+|c|)
-    auto relax = [&](T wr, T v) { return (T(1) - wr) * lam / (lam + fabs(v)) * v; };
+    // relaxed value (1 - omega_lambda) v with omega_lambda the limited rate
+    // omega + (1 - omega) |v| / (lambda + |v|)
+    auto relax = [&](T lw, T v) { return lw * fast_rcp(k.lam + fabs(v)) * v; };
     {
       const T p = (g[MI(1, 2, 0)] + g[MI(1, 0, 2)]) * irho, d = (g[MI(1, 2, 0)] - g[MI(1, 0, 2)]) * irho;
-      const T ps = relax(w3, p), ds = relax(w4, d);
+      const T ps = relax(k.l3, p), ds = relax(k.l4, d);
       C120 = T(0.5) * (ps + ds); C102 = T(0.5) * (ps - ds);
     }
     {
       const T p = (g[MI(2, 1, 0)] + g[MI(0, 1, 2)]) * irho, d = (g[MI(2, 1, 0)] - g[MI(0, 1, 2)]) * irho;
-      const T ps = relax(w3, p), ds = relax(w4, d);
+      const T ps = relax(k.l3, p), ds = relax(k.l4, d);
       C210 = T(0.5) * (ps + ds); C012 = T(0.5) * (ps - ds);
     }
     {
       const T p = (g[MI(2, 0, 1)] + g[MI(0, 2, 1)]) * irho, d = (g[MI(2, 0, 1)] - g[MI(0, 2, 1)]) * irho;
-      const T ps = relax(w3, p), ds = relax(w4, d);
+      const T ps = relax(k.l3, p), ds = relax(k.l4, d);
       C201 = T(0.5) * (ps + ds); C021 = T(0.5) * (ps - ds);
     }
-    C111 = relax(w5, g[MI(1, 1, 1)] * irho);
-    const T t = T(1) / w1 - T(0.5);
-    C220 = T(-2.0 / 3.0) * t * A * (Dxu + Dyv);
-    C202 = T(-2.0 / 3.0) * t * A * (Dxu + Dzw);
-    C022 = T(-2.0 / 3.0) * t * A * (Dyv + Dzw);
-    C211 = t * B * w1 * k011;   // -(1/3) t B (-3 w1 c011)
-    C121 = t * B * w1 * k101;
-    C112 = t * B * w1 * k110;
+    C111 = relax(k.l5, g[MI(1, 1, 1)] * irho);
+    C220 = k.a4 * (Dxu + Dyv);
+    C202 = k.a4 * (Dxu + Dzw);
+    C022 = k.a4 * (Dyv + Dzw);
+    C211 = k.b4 * k011;   // -(1/3) t B (-3 w1 c011)
+    C121 = k.b4 * k101;
+    C112 = k.b4 * k110;
   }
   // back to normalised central moments (partition sums over post values)
   const T A2 = third + a, B2 = third + b, C2 = third + c;
@@ -232,9 +291,9 @@ __device__ __forceinline__ void collide_moments(T* g, T drho, T rho, T irho, T u
   g[MI(1, 0, 0)] = -g[MI(1, 0, 0)];
   g[MI(0, 1, 0)] = -g[MI(0, 1, 0)];
   g[MI(0, 0, 1)] = -g[MI(0, 0, 1)];
-  g[MI(2, 0, 0)] = rho * a + drho * third;
-  g[MI(0, 2, 0)] = rho * b + drho * third;
-  g[MI(0, 0, 2)] = rho * c + drho * third;
+  g[MI(2, 0, 0)] = rho * a + d3;
+  g[MI(0, 2, 0)] = rho * b + d3;
+  g[MI(0, 0, 2)] = rho * c + d3;
   g[MI(1, 1, 0)] = rho * s110;
   g[MI(1, 0, 1)] = rho * s101;
   g[MI(0, 1, 1)] = rho * s011;
@@ -243,9 +302,10 @@ __device__ __forceinline__ void collide_moments(T* g, T drho, T rho, T irho, T u
   g[MI(1, 2, 0)] = rho * C120; g[MI(1, 0, 2)] = rho * C102;
   g[MI(1, 1, 1)] = rho * C111;
   g[MI(2, 1, 1)] = rho * k211; g[MI(1, 2, 1)] = rho * k121; g[MI(1, 1, 2)] = rho * k112;
-  g[MI(2, 2, 0)] = rho * d220 + drho * T(1.0 / 9.0);
-  g[MI(2, 0, 2)] = rho * d202 + drho * T(1.0 / 9.0);
-  g[MI(0, 2, 2)] = rho * d022 + drho * T(1.0 / 9.0);
+  const T d9 = drho * T(1.0 / 9.0);
+  g[MI(2, 2, 0)] = rho * d220 + d9;
+  g[MI(2, 0, 2)] = rho * d202 + d9;
+  g[MI(0, 2, 2)] = rho * d022 + d9;
   g[MI(2, 2, 1)] = rho * k221; g[MI(2, 1, 2)] = rho * k212; g[MI(1, 2, 2)] = rho * k122;
   g[MI(2, 2, 2)] = rho * d222 + drho * T(1.0 / 27.0);
 }

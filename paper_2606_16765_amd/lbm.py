@@ -42,7 +42,7 @@ class Lbm:
     def __init__(self, shape, storage="f32", periodic=(0, 0, 0), u_in=0.05, nu=None, re=None, l_ref=None,
                  omega2=1.0, mode="auto", galilean=1, lam=0.01, obstacle_bc=0, body_force=(0.0, 0.0, 0.0),
                  avg_start=0, snap_every=0, snap_count=20, snap_start=0, force_every=1, xcd_remap=1, solid=None,
-                 links=None, u0=None, stream=None):
+                 links=None, u0=None, perturb=None, stream=None):
         L = load()
         nx, ny, nz = (int(v) for v in shape)
         self.shape = (nx, ny, nz)
@@ -63,6 +63,9 @@ class Lbm:
         p.avg_start = -1 if avg_start is None else int(avg_start)
         p.snap_every, p.snap_count, p.snap_start = int(snap_every), int(snap_count), int(snap_start)
         p.force_every, p.xcd_remap = int(force_every), int(xcd_remap)
+        if perturb is not None:
+            # (seed, amplitude): the library draws the initial velocity itself
+            p.perturb_seed, p.perturb_amp = int(perturb[0]), float(perturb[1])
         self.params = p
         self.storage = storage
         keep = []

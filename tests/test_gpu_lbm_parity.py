@@ -235,3 +235,15 @@ def test_moments_match_populations():
     m = g.moments().reshape(4, -1)
     assert np.abs(m[:3] - u).max() < 1e-7
     assert np.abs(m[3] - d / 3).max() < 1e-7
+
+
+def test_device_perturbation_matches_host_generator():
+    """The library's on-device SplitMix64 perturbation equals the host
+    input generator's, so both initial states are identical."""
+    P = _gpu()
+    shape = (64, 8, 8)
+    geo = sphere_channel(shape, center=(20.0, 3.5, 3.5), radius=2.0)
+    u0 = perturbation(shape, 77, 5e-4, geo.solid)
+    a = P.Lbm(shape, storage="f64", nu=0.02, solid=geo.solid, u0=u0)
+    b = P.Lbm(shape, storage="f64", nu=0.02, solid=geo.solid, perturb=(77, 5e-4))
+    assert np.array_equal(a.populations(), b.populations())
