@@ -447,9 +447,11 @@ int orc_run(const orc_params* p, const uint8_t* solid, const double* q, double* 
       orc_collide(p, fin, fo, NULL);
       for (int i = 0; i < 27; ++i) post[i * N + n] = fo[i];
     }
-    /* pull streaming with boundary substitutions */
-    double F[3] = {0.0, 0.0, 0.0};
-#pragma omp parallel for schedule(static) reduction(+ : F[:3])
+    /* pull streaming with boundary substitutions; force partials per z
+       plane, summed in plane order afterwards (thread-count independent) */
+    double* Fz = (double*)calloc((size_t)nz * 3, sizeof(double));
+    if (!Fz) { bad = 2; break; }
+#pragma omp parallel for schedule(static)
     for (int z = 0; z < nz; ++z)
       for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
@@ -495,13 +497,19 @@ int orc_run(const orc_params* p, const uint8_t* solid, const double* q, double* 
               if (classify(p, solid, x, y, z, CX[jd], CY[jd], CZ[jd], &nb) != NB_SOLID) continue;
               const double fin = fbar[(26 - jd) * N + n] + WT[jd];
               const double fo = post[jd * N + n] + WT[jd];
-              F[0] += CX[jd] * (fin + fo);
-              F[1] += CY[jd] * (fin + fo);
-              F[2] += CZ[jd] * (fin + fo);
+              Fz[3 * z + 0] += CX[jd] * (fin + fo);
+              Fz[3 * z + 1] += CY[jd] * (fin + fo);
+              Fz[3 * z + 2] += CZ[jd] * (fin + fo);
             }
           }
         }
-    if (forces) { forces[3 * s + 0] = F[0]; forces[3 * s + 1] = F[1]; forces[3 * s + 2] = F[2]; }
+    if (forces) {
+      double F[3] = {0.0, 0.0, 0.0};
+      for (int z = 0; z < nz; ++z)
+        for (int k = 0; k < 3; ++k) F[k] += Fz[3 * z + k];
+      forces[3 * s + 0] = F[0]; forces[3 * s + 1] = F[1]; forces[3 * s + 2] = F[2];
+    }
+    free(Fz);
     memcpy(fbar, next, sizeof(double) * 27 * N);
     double chk = 0.0;
     for (int64_t n = 0; n < N; n += 97) chk += fbar[n];

@@ -333,8 +333,7 @@ def test_interpolated_bounce_back_half_equals_halfway():
         r = lbm.Run(p, solid=g.solid, links=links, u0=u0).step(10)
         runs.append(r)
     assert np.array_equal(runs[0].fbar, runs[1].fbar)
-    # force sums are reduced across threads in a run-dependent order
-    assert np.allclose(np.array(runs[0].forces), np.array(runs[1].forces), rtol=1e-12, atol=1e-18)
+    assert np.array_equal(np.array(runs[0].forces), np.array(runs[1].forces))
 
 
 def test_interpolated_bounce_back_stable_where_obstacle_meets_wall():
