@@ -1,0 +1,271 @@
+"""FP64 numpy oracle of the 3D Fourier neural operator surrogate.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Architecture (paper Sec. 4 and App. A.2: FNO with 32 channels, 4 layers, a
+feed-forward lifting; predicts mean flow fields from geometry and Re):
+  v0 = P x + p                                  lifting cin -> width
+  for l in layers:
+      V = T(v)        truncated 3D real DFT: kx, ky in {0..m-1, -m..-1},
+                      kz in {0..m-1} (corner modes of the half spectrum)
+      Y[b,o,k] = sum_c V[b,c,k] W_l[c,o,k]     per-mode complex mixing
+      s = R(Y)        truncated inverse (the c2r convention of irfftn: the
+                      kz = 0 term enters with its real part, kz >= 1 doubled,
+                      normalised by 1/(X Y Z))
+      h = s + Wp_l v + bp_l
+      v = GELU(h) except after the last layer (GELU with erf)
+  y = Q2 GELU(Q1 v + q1) + q2                   projection width -> hidden -> cout
+Loss: mean squared error over the cells of a mask (App. A.2, inner region),
+all samples and output channels.  Optimiser: Adam (beta 0.9, 0.999,
+eps 1e-8).  The paper's SIREN projection is replaced by a GELU MLP.
+
+Parameter vector layout (shared with the GPU library's C ABI):
+  lift W [width][cin], lift b [width];
+  per layer: spectral W [2mx][2my][mz][width][width][2] (re, im; first
+  index j -> kx = j for j < mx else j - 2mx, likewise ky), pointwise W
+  [width][width] (out, in), bias [width];
+  proj W1 [hidden][width], b1 [hidden], W2 [cout][hidden], b2 [cout].
+"""
+from dataclasses import dataclass
+import math
+
+import numpy as np
+from scipy.special import erf
+
+
+@dataclass(frozen=True)
+class Shape:
+    nx: int = 128
+    ny: int = 64
+    nz: int = 64
+    cin: int = 4
+    cout: int = 4
+    width: int = 32
+    layers: int = 4
+    mx: int = 16
+    my: int = 16
+    mz: int = 16
+    hidden: int = 128
+
+
+def param_count(s: Shape) -> int:
+    w = s.width
+    n = w * s.cin + w
+    n += s.layers * ((2 * s.mx) * (2 * s.my) * s.mz * w * w * 2 + w * w + w)
+    n += s.hidden * w + s.hidden + s.cout * s.hidden + s.cout
+    return n
+
+
+def unpack(theta, s: Shape):
+    theta = np.asarray(theta, dtype=np.float64)
+    w = s.width
+    o = 0
+
+    def take(*shape):
+        nonlocal o
+        k = int(np.prod(shape))
+        a = theta[o:o + k].reshape(shape)
+        o += k
+        return a
+
+    p = {"P": take(w, s.cin), "p": take(w)}
+    p["layers"] = []
+    for _ in range(s.layers):
+        ws = take(2 * s.mx, 2 * s.my, s.mz, w, w, 2)
+        # complex weights as [c_in][c_out][kx][ky][kz]
+        W = (ws[..., 0] + 1j * ws[..., 1]).transpose(3, 4, 0, 1, 2)
+        p["layers"].append({"W": W, "Wp": take(w, w), "bp": take(w)})
+    p["Q1"] = take(s.hidden, w)
+    p["q1"] = take(s.hidden)
+    p["Q2"] = take(s.cout, s.hidden)
+    p["q2"] = take(s.cout)
+    assert o == theta.size
+    return p
+
+
+def pack(p, s: Shape):
+    parts = [p["P"].ravel(), p["p"].ravel()]
+    for L in p["layers"]:
+        W = L["W"].transpose(2, 3, 4, 0, 1)
+        ws = np.stack([W.real, W.imag], -1)
+        parts += [ws.ravel(), L["Wp"].ravel(), L["bp"].ravel()]
+    parts += [p["Q1"].ravel(), p["q1"].ravel(), p["Q2"].ravel(), p["q2"].ravel()]
+    return np.concatenate(parts)
+
+
+def mode_indices(m):
+    """Retained wavenumbers of a full axis: 0..m-1, -m..-1."""
+    return np.concatenate([np.arange(m), np.arange(-m, 0)])
+
+
+def dft_matrices(s: Shape):
+    """Forward truncated DFT matrices: F[k, n] = exp(-2 pi i k n / N)."""
+    kx, ky, kz = mode_indices(s.mx), mode_indices(s.my), np.arange(s.mz)
+    Fx = np.exp(-2j * np.pi * np.outer(kx, np.arange(s.nx)) / s.nx)
+    Fy = np.exp(-2j * np.pi * np.outer(ky, np.arange(s.ny)) / s.ny)
+    Fz = np.exp(-2j * np.pi * np.outer(kz, np.arange(s.nz)) / s.nz)
+    return Fx, Fy, Fz
+
+
+def forward_dft(v, mats):
+    """V[..., kx, ky, kz] = sum_{x,y,z} v[..., x, y, z] exp(-2 pi i k.n / N),
+    the separable sum taken one axis at a time."""
+    Fx, Fy, Fz = mats
+    t = np.tensordot(v, Fz, axes=([-1], [1]))                        # [..., x, y, kz]
+    t = np.moveaxis(np.tensordot(t, Fy, axes=([-2], [1])), -1, -2)   # [..., x, ky, kz]
+    t = np.moveaxis(np.tensordot(t, Fx, axes=([-3], [1])), -1, -3)   # [..., kx, ky, kz]
+    return t
+
+
+def inverse_dft(Y, mats, s: Shape):
+    """s[..., x, y, z] = (1/(XYZ)) sum_k c_kz Re(Y[..., k] exp(+2 pi i k.n/N)),
+    c_0 = 1, c_kz = 2 for kz >= 1."""
+    Fx, Fy, Fz = mats
+    ckz = np.where(np.arange(s.mz) == 0, 1.0, 2.0)
+    t = Y * ckz
+    t = np.tensordot(t, np.conj(Fz), axes=([-1], [0]))                       # [..., kx, ky, z]
+    t = np.moveaxis(np.tensordot(t, np.conj(Fy), axes=([-2], [0])), -1, -2)  # [..., kx, y, z]
+    t = np.moveaxis(np.tensordot(t, np.conj(Fx), axes=([-3], [0])), -1, -3)  # [..., x, y, z]
+    return t.real / (s.nx * s.ny * s.nz)
+
+
+def adjoint_forward_dft(G, mats):
+    """Adjoint of forward_dft as a real-linear map (complex gradient G on
+    the modes -> real gradient on the grid): Re(sum_k G[k] exp(+i k.n))."""
+    Fx, Fy, Fz = mats
+    t = np.tensordot(G, np.conj(Fz), axes=([-1], [0]))
+    t = np.moveaxis(np.tensordot(t, np.conj(Fy), axes=([-2], [0])), -1, -2)
+    t = np.moveaxis(np.tensordot(t, np.conj(Fx), axes=([-3], [0])), -1, -3)
+    return t.real
+
+
+def adjoint_inverse_dft(g, mats, s: Shape):
+    """Adjoint of inverse_dft: (c_kz/(XYZ)) times the forward DFT of g."""
+    ckz = np.where(np.arange(s.mz) == 0, 1.0, 2.0)
+    return forward_dft(g, mats) * ckz / (s.nx * s.ny * s.nz)
+
+
+def gelu(x):
+    return 0.5 * x * (1.0 + erf(x / math.sqrt(2.0)))
+
+
+def gelu_grad(x):
+    return 0.5 * (1.0 + erf(x / math.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
+
+
+def pointwise(W, v, b=None):
+    """(W v)[b, o, ...] = sum_c W[o, c] v[b, c, ...] (+ bias)."""
+    out = np.tensordot(W, v, axes=([1], [1]))  # [o, b, ...]
+    out = np.moveaxis(out, 0, 1)
+    if b is not None:
+        out = out + b.reshape((1, -1) + (1,) * (v.ndim - 2))
+    return out
+
+
+def forward(theta, x, s: Shape, mats=None):
+    """x [B][cin][X][Y][Z] -> y [B][cout][X][Y][Z] and the saved activations."""
+    p = unpack(theta, s)
+    mats = mats or dft_matrices(s)
+    cache = {"x": x}
+    v = pointwise(p["P"], x, p["p"])
+    cache["v"] = []
+    for li, L in enumerate(p["layers"]):
+        cache["v"].append(v)
+        V = forward_dft(v, mats)
+        Y = np.einsum("bck...,cok...->bok...", V, L["W"])
+        h = inverse_dft(Y, mats, s) + pointwise(L["Wp"], v, L["bp"])
+        cache.setdefault("V", []).append(V)
+        cache.setdefault("h", []).append(h)
+        v = gelu(h) if li < s.layers - 1 else h
+    cache["vL"] = v
+    h1 = pointwise(p["Q1"], v, p["q1"])
+    cache["h1"] = h1
+    y = pointwise(p["Q2"], gelu(h1), p["q2"])
+    return y, cache
+
+
+def masked_mse(y, t, mask):
+    """Mean of (y - t)^2 over mask cells, all samples and channels; returns
+    the loss and dL/dy."""
+    m = np.asarray(mask, dtype=np.float64)[None, None]
+    cnt = y.shape[0] * y.shape[1] * m.sum()
+    d = (y - t) * m
+    return float((d * d).sum() / cnt), 2.0 * d / cnt
+
+
+def backward(theta, cache, gy, s: Shape, mats=None):
+    """Gradient of the loss with respect to the parameter vector, given
+    dL/dy, by the chain rule through the saved activations."""
+    p = unpack(theta, s)
+    mats = mats or dft_matrices(s)
+    g = {"layers": [None] * s.layers}
+    # projection
+    h1 = cache["h1"]
+    a = gelu(h1)
+    red = tuple(i for i in range(gy.ndim) if i != 1)
+    g["Q2"] = np.tensordot(gy, a, axes=(red, red))
+    g["q2"] = gy.sum(axis=red)
+    ga = pointwise(p["Q2"].T, gy)
+    gh1 = ga * gelu_grad(h1)
+    vL = cache["vL"]
+    g["Q1"] = np.tensordot(gh1, vL, axes=(red, red))
+    g["q1"] = gh1.sum(axis=red)
+    gv = pointwise(p["Q1"].T, gh1)
+    # Fourier layers in reverse
+    for li in range(s.layers - 1, -1, -1):
+        L = p["layers"][li]
+        h = cache["h"][li]
+        gh = gv * gelu_grad(h) if li < s.layers - 1 else gv
+        v = cache["v"][li]
+        gL = {}
+        gL["Wp"] = np.tensordot(gh, v, axes=(red, red))
+        gL["bp"] = gh.sum(axis=red)
+        gvp = pointwise(L["Wp"].T, gh)
+        gY = adjoint_inverse_dft(gh, mats, s)                 # complex gradient on the modes
+        V = cache["V"][li]
+        gL["W"] = np.einsum("bck...,bok...->cok...", np.conj(V), gY)
+        gV = np.einsum("bok...,cok...->bck...", gY, np.conj(L["W"]))
+        gv = gvp + adjoint_forward_dft(gV, mats)
+        g["layers"][li] = gL
+    x = cache["x"]
+    g["P"] = np.tensordot(gv, x, axes=(red, red))
+    g["p"] = gv.sum(axis=red)
+    return pack(g, s)
+
+
+def adam(theta, grad, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step (step number t >= 1); returns new theta, m, v."""
+    m = b1 * m + (1 - b1) * grad
+    v = b2 * v + (1 - b2) * grad * grad
+    mh = m / (1 - b1 ** t)
+    vh = v / (1 - b2 ** t)
+    return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def init_params(s: Shape, seed=0):
+    """Seeded initial parameters (uniform fan-in scaling; spectral weights
+    uniform with scale 1/width^2)."""
+    rng = np.random.default_rng(seed)
+    w = s.width
+    p = {"P": rng.uniform(-1, 1, (w, s.cin)) / math.sqrt(s.cin), "p": np.zeros(w), "layers": []}
+    for _ in range(s.layers):
+        W = (rng.uniform(0, 1, (w, w, 2 * s.mx, 2 * s.my, s.mz)) + 1j * rng.uniform(0, 1, (w, w, 2 * s.mx, 2 * s.my, s.mz)))
+        p["layers"].append({"W": W / (w * w), "Wp": rng.uniform(-1, 1, (w, w)) / math.sqrt(w), "bp": np.zeros(w)})
+    p["Q1"] = rng.uniform(-1, 1, (s.hidden, w)) / math.sqrt(w)
+    p["q1"] = np.zeros(s.hidden)
+    p["Q2"] = rng.uniform(-1, 1, (s.cout, s.hidden)) / math.sqrt(s.hidden)
+    p["q2"] = np.zeros(s.cout)
+    return pack(p, s)
+
+
+def inner_box_mask(s: Shape):
+    """Loss region of App. A.2 (inner box of the 2x1x1 domain): x in
+    [0.1, 0.9) of X (i.e. [0.2, 1.8) of 2L), y and z in [0.25, 0.75)."""
+    m = np.zeros((s.nx, s.ny, s.nz), np.uint8)
+    m[int(0.1 * s.nx):int(0.9 * s.nx), int(0.25 * s.ny):int(0.75 * s.ny), int(0.25 * s.nz):int(0.75 * s.nz)] = 1
+    return m
+
+
+__all__ = ["Shape", "param_count", "unpack", "pack", "dft_matrices", "forward_dft", "inverse_dft", "forward",
+           "backward", "masked_mse", "adam", "init_params", "gelu", "gelu_grad", "inner_box_mask", "mode_indices",
+           "adjoint_forward_dft", "adjoint_inverse_dft"]
