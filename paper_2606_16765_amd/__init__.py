@@ -7,3 +7,6 @@ there is no CPU fallback.
 from .lbm import Lbm, nu_from_re, bytes_per_cell_update, STORAGE  # noqa: F401
 
 __all__ = ["Lbm", "nu_from_re", "bytes_per_cell_update", "STORAGE"]
+from .fno import Fno, FnoError  # noqa: F401,E402
+
+__all__ += ["Fno", "FnoError"]

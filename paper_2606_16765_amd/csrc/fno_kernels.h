@@ -1,0 +1,371 @@
+// gfx950 kernels of the 3D Fourier neural operator (paper Sec. 4, App. A.2):
+// one generic BF16-MFMA contraction used for every truncated-DFT stage and
+// every pointwise channel map, the per-mode complex channel mixing and its
+// adjoints, a Gram kernel for pointwise weight gradients, and elementwise,
+// reduction and Adam kernels.  All contractions take BF16 operands and
+// accumulate in FP32 (v_mfma_f32_16x16x32_bf16).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mfno {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float v) {
+  uint32_t b = __float_as_uint(v);
+  uint32_t r = ((b & 0x7fffffffu) > 0x7f800000u) ? 0x7fc00000u : (b + 0x7fffu + ((b >> 16) & 1u));
+  return (uint16_t)(r >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+template <typename T> __device__ __forceinline__ float to_f(T v);
+template <> __device__ __forceinline__ float to_f<float>(float v) { return v; }
+template <> __device__ __forceinline__ float to_f<uint16_t>(uint16_t v) { return bf2f(v); }
+template <typename T> __device__ __forceinline__ T from_f(float v);
+template <> __device__ __forceinline__ float from_f<float>(float v) { return v; }
+template <> __device__ __forceinline__ uint16_t from_f<uint16_t>(float v) { return f2bf(v); }
+template <typename T> __device__ __forceinline__ uint16_t to_bf(T v);
+template <> __device__ __forceinline__ uint16_t to_bf<float>(float v) { return f2bf(v); }
+template <> __device__ __forceinline__ uint16_t to_bf<uint16_t>(uint16_t v) { return v; }
+
+__device__ __forceinline__ f32x4 mfma16(const bf16x8& a, const bf16x8& b, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// --------------------------------------------------------------- contract
+// out(o, n, i) = alpha * sum_k in(o, k, i) * G[k][n] (+ out if accumulate)
+//                (+ bias[n])
+// with columns j = o * I + i (I a power of two), index maps
+//   in  address = (j >> lgI) * in_so + (j & (I-1)) * in_si
+//                 + (k >> lgkd) * in_sk1 + (k & (kd-1)) * in_sk2
+//   out address = (j >> lgI) * out_so + (j & (I-1)) * out_si
+//                 + (n >> lgnd) * out_sn1 + (n & (nd-1)) * out_sn2
+// and G given transposed, gt[n][k] (BF16, row length kp, zero padded to
+// kp >= K rounded up to 32 and to a multiple of 64 rows).
+struct ContractArgs {
+  const void* in;
+  void* out;
+  const uint16_t* gt;
+  const float* bias;
+  int64_t cols;
+  int32_t lgI;
+  int64_t in_so, in_si, in_sk1, in_sk2;
+  int32_t lgkd;
+  int64_t out_so, out_si, out_sn1, out_sn2;
+  int32_t lgnd;
+  int32_t K, N, kp;
+  float alpha;
+  int32_t accumulate;
+  int32_t kcontig;  // 1: k runs of 32 are contiguous in memory (load along k)
+};
+
+constexpr int CT_N = 64;   // rows n per block (4 waves x 16)
+constexpr int CT_J = 64;   // columns per block
+constexpr int CT_K = 32;   // k per step (one MFMA)
+constexpr int LDS_KP = 40; // padded k stride of the LDS tile
+
+template <typename InT, typename OutT>
+__global__ __launch_bounds__(256) void contract_kernel(ContractArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t tile[CT_J * LDS_KP];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t j0 = (int64_t)blockIdx.x * CT_J;
+  const int n0 = blockIdx.y * CT_N;
+  const InT* in = (const InT*)a.in;
+  const int64_t Imask = ((int64_t)1 << a.lgI) - 1;
+  const int kdmask = (1 << a.lgkd) - 1;
+  auto colbase = [&](int64_t j) { return (j >> a.lgI) * a.in_so + (j & Imask) * a.in_si; };
+  auto kaddr = [&](int k) { return (int64_t)(k >> a.lgkd) * a.in_sk1 + (int64_t)(k & kdmask) * a.in_sk2; };
+
+  // per-thread load coordinates (one element per instruction, 8 per step)
+  int lk[8], lj[8];
+  int64_t cb[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    if (a.kcontig) { lk[q] = t & 31; lj[q] = (t >> 5) + 8 * q; }
+    else { lj[q] = t & 63; lk[q] = (t >> 6) * 8 + q; }
+    const int64_t j = j0 + lj[q];
+    cb[q] = j < a.cols ? colbase(j) : -1;
+  }
+
+  f32x4 acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int arow = n0 + wave * 16 + (lane & 15);
+  const int akk = 8 * (lane >> 4);
+
+  for (int k0 = 0; k0 < a.K; k0 += CT_K) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = k0 + lk[q];
+      uint16_t v = 0;
+      if (cb[q] >= 0 && k < a.K) v = to_bf(in[cb[q] + kaddr(k)]);
+      tile[lj[q] * LDS_KP + lk[q]] = v;
+    }
+    __syncthreads();
+    // A: rows of G^T (zero padded beyond N and K)
+    const bf16x8 av = *(const bf16x8*)(a.gt + (int64_t)arow * a.kp + k0 + akk);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const bf16x8 bv = *(const bf16x8*)(tile + (c * 16 + (lane & 15)) * LDS_KP + akk);
+      acc[c] = mfma16(av, bv, acc[c]);
+    }
+    __syncthreads();
+  }
+  OutT* out = (OutT*)a.out;
+  const int64_t Om = ((int64_t)1 << a.lgI) - 1;
+  const int ndm = (1 << a.lgnd) - 1;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int64_t j = j0 + c * 16 + (lane & 15);
+    if (j >= a.cols) continue;
+    const int64_t ob = (j >> a.lgI) * a.out_so + (j & Om) * a.out_si;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int n = n0 + wave * 16 + 4 * (lane >> 4) + r;
+      if (n >= a.N) continue;
+      const int64_t addr = ob + (int64_t)(n >> a.lgnd) * a.out_sn1 + (int64_t)(n & ndm) * a.out_sn2;
+      float v = a.alpha * acc[c][r];
+      if (a.bias) v += a.bias[n];
+      if (a.accumulate) v += to_f(out[addr]);
+      out[addr] = from_f<OutT>(v);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ mixing
+// Per retained mode m, batch rows b (up to 16 per pass), complex channels:
+//   Y[m][b][o] = sum_c V[m][b][c] W[m][c][o]                      (MODE 0)
+//   gV[m][b][c] = sum_o gY[m][b][o] conj(W[m][c][o])              (MODE 1)
+// complex values stored as (re, im) pairs; W in BF16 [m][c][o][2].
+// As a real contraction over (c, part) -> (o, part) with the real
+// embedding [[Wr, Wi], [-Wi, Wr]] (MODE 0) or its transpose (MODE 1).
+template <typename InT, typename OutT, int MODE>
+__global__ __launch_bounds__(64) void mix_kernel(const InT* __restrict__ in, const uint16_t* __restrict__ w,
+                                                 OutT* __restrict__ out, int B, int C) {
+  const int m = blockIdx.x, lane = threadIdx.x;
+  const int64_t blk = (int64_t)B * C * 2;  // per-mode block of in / out
+  const uint16_t* wm = w + (int64_t)m * C * C * 2;
+  const int K = 2 * C;  // (c, part) = 2c + part
+  for (int b0 = 0; b0 < B; b0 += 16) {
+    const int brow = b0 + (lane & 15);
+    for (int nt = 0; nt < K / 16; ++nt) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      const int ncol = nt * 16 + (lane & 15);  // output (o, part') = 2o + p'
+      const int o = ncol >> 1, po = ncol & 1;
+      for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8 av, bv;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int kk = k0 + 8 * (lane >> 4) + q;  // input (c, part) = 2c + p
+          av[q] = brow < B ? __builtin_bit_cast(__bf16, to_bf(in[(int64_t)m * blk + (int64_t)brow * K + kk]))
+                           : (__bf16)0.0f;
+          const int c = kk >> 1, pi = kk & 1;
+          float wr, wi;
+          if (MODE == 0) {  // element ((c,pi), (o,po)) of [[Wr, Wi], [-Wi, Wr]]
+            wr = bf2f(wm[((int64_t)c * C + o) * 2]);
+            wi = bf2f(wm[((int64_t)c * C + o) * 2 + 1]);
+          } else {          // transpose: element ((o',pi), (c',po)) = emb((c',po), (o',pi))
+            wr = bf2f(wm[((int64_t)o * C + c) * 2]);
+            wi = bf2f(wm[((int64_t)o * C + c) * 2 + 1]);
+          }
+          float e;
+          if (MODE == 0) e = (pi == po) ? wr : (pi == 0 ? wi : -wi);
+          else e = (pi == po) ? wr : (pi == 0 ? -wi : wi);
+          bv[q] = (__bf16)e;
+        }
+        acc = mfma16(av, bv, acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int b = b0 + 4 * (lane >> 4) + r;
+        if (b < B) out[(int64_t)m * blk + (int64_t)b * K + ncol] = from_f<OutT>(acc[r]);
+      }
+    }
+  }
+}
+
+// Spectral weight gradient, per mode: gW[m][c][o] += sum_b conj(V[b][c]) gY[b][o]
+// as R[(c,p)][(o,p')] = sum_b V[b][(c,p)] gY[b][(o,p')] (K = batch, zero
+// padded to 32), then gWr = R00 + R11, gWi = R01 - R10.
+template <typename InT>
+__global__ __launch_bounds__(64) void mix_grad_kernel(const InT* __restrict__ v, const InT* __restrict__ gy,
+                                                      float* __restrict__ gw, int B, int C) {
+  const int m = blockIdx.x, lane = threadIdx.x;
+  const int64_t blk = (int64_t)B * C * 2;
+  const int K2 = 2 * C;
+  float* g = gw + (int64_t)m * C * C * 2;
+  for (int rt = 0; rt < K2 / 16; ++rt) {
+    for (int ct = 0; ct < K2 / 16; ++ct) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      for (int b0 = 0; b0 < B; b0 += 32) {
+        bf16x8 av, bv;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int b = b0 + 8 * (lane >> 4) + q;
+          const int row = rt * 16 + (lane & 15), col = ct * 16 + (lane & 15);
+          av[q] = b < B ? __builtin_bit_cast(__bf16, to_bf(v[(int64_t)m * blk + (int64_t)b * K2 + row])) : (__bf16)0.0f;
+          bv[q] = b < B ? __builtin_bit_cast(__bf16, to_bf(gy[(int64_t)m * blk + (int64_t)b * K2 + col])) : (__bf16)0.0f;
+        }
+        acc = mfma16(av, bv, acc);
+      }
+      // lane holds R[row = rt*16 + 4*(lane>>4) + r][col = ct*16 + (lane&15)]
+      const int col = ct * 16 + (lane & 15);
+      const float nb0 = __shfl_xor(acc[0], 1), nb1 = __shfl_xor(acc[1], 1);
+      const float nb2 = __shfl_xor(acc[2], 1), nb3 = __shfl_xor(acc[3], 1);
+      if ((col & 1) == 0) {
+        const int o = col >> 1;
+        // rows r = 0,1 are (c0, re), (c0, im); rows 2,3 are (c0+1, re), (c0+1, im)
+        const int c0 = (rt * 16 + 4 * (lane >> 4)) >> 1;
+        // own: R[(c,0)][(o,0)] = acc[0], R[(c,1)][(o,0)] = acc[1]; neighbour (o,1): nb0, nb1
+        g[((int64_t)c0 * C + o) * 2] += acc[0] + nb1;
+        g[((int64_t)c0 * C + o) * 2 + 1] += nb0 - acc[1];
+        g[((int64_t)(c0 + 1) * C + o) * 2] += acc[2] + nb3;
+        g[((int64_t)(c0 + 1) * C + o) * 2 + 1] += nb2 - acc[3];
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------------------- Gram
+// part[chunk][a][c] = sum_{t in chunk} X[a][t] Y[c][t], rows of X and Y with
+// stride rs (per batch sample) and sample stride bs; t = (b, p), chunks of
+// 2048 points within one sample.  One wave per 16 x 16 output tile.
+template <typename XT, typename YT>
+__global__ __launch_bounds__(64) void gram_kernel(const XT* __restrict__ X, const YT* __restrict__ Y, float* part,
+                                                  int A, int Cc, int64_t P, int64_t xbs, int64_t ybs, int chunk) {
+  const int lane = threadIdx.x;
+  const int64_t ch = blockIdx.x;
+  const int64_t per_b = P / chunk;
+  const int64_t b = ch / per_b, p0 = (ch % per_b) * chunk;
+  const int at = blockIdx.y, ct = blockIdx.z;
+  const int row = at * 16 + (lane & 15), col = ct * 16 + (lane & 15);
+  const XT* xr = X + b * xbs + (int64_t)row * P + p0;
+  const YT* yr = Y + b * ybs + (int64_t)col * P + p0;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < chunk; k0 += 32) {
+    bf16x8 av, bv;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = k0 + 8 * (lane >> 4) + q;
+      av[q] = row < A ? __builtin_bit_cast(__bf16, to_bf(xr[k])) : (__bf16)0.0f;
+      bv[q] = col < Cc ? __builtin_bit_cast(__bf16, to_bf(yr[k])) : (__bf16)0.0f;
+    }
+    acc = mfma16(av, bv, acc);
+  }
+  float* o = part + ch * (int64_t)A * Cc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int ar = at * 16 + 4 * (lane >> 4) + r;
+    if (ar < A && col < Cc) o[(int64_t)ar * Cc + col] = acc[r];
+  }
+}
+
+// out[e] (+)= sum_s part[s][e], fixed order
+__global__ __launch_bounds__(256) void reduce_parts_kernel(const float* part, int64_t nparts, int64_t E, float* out,
+                                                           int accumulate) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= E) return;
+  float s = 0.f;
+  for (int64_t k = 0; k < nparts; ++k) s += part[k * E + e];
+  out[e] = accumulate ? out[e] + s : s;
+}
+
+// per-block partial sums over (b, p) of X[b][a][p]: part[blk][a]
+__global__ __launch_bounds__(256) void colsum_kernel(const float* X, int A, int64_t P, int B, int64_t chunk,
+                                                     float* part) {
+  __shared__ float red[256];
+  const int a = blockIdx.y;
+  const int64_t per_b = P / chunk;
+  const int64_t b = blockIdx.x / per_b, p0 = (blockIdx.x % per_b) * chunk;
+  const float* x = X + (b * A + a) * P + p0;
+  float s = 0.f;
+  for (int64_t p = threadIdx.x; p < chunk; p += 256) s += x[p];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.x * A + a] = red[0];
+}
+
+// ------------------------------------------------------------- elementwise
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+// v = bf16(act(h)), act = GELU or identity
+__global__ __launch_bounds__(256) void act_kernel(const float* h, uint16_t* v, int64_t n, int use_gelu) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float x = h[i];
+  v[i] = f2bf(use_gelu ? gelu(x) : x);
+}
+
+// g *= GELU'(h)
+__global__ __launch_bounds__(256) void gelu_bwd_kernel(float* g, const float* h, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  g[i] *= gelu_grad(h[i]);
+}
+
+// masked MSE: per-block partial of sum mask (y - t)^2, and gy = 2 mask (y - t) / cnt
+__global__ __launch_bounds__(256) void mse_kernel(const float* y, const float* t, const uint8_t* mask, int64_t P,
+                                                  int64_t n, float inv_cnt, float* gy, double* part) {
+  __shared__ double red[256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double s = 0.0;
+  if (i < n) {
+    const float m = mask[i % P] ? 1.f : 0.f;
+    const float d = (y[i] - t[i]) * m;
+    s = (double)d * (double)d;
+    if (gy) gy[i] = 2.f * d * inv_cnt;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(float* theta, const float* g, float* m, float* v, int64_t n,
+                                                   float lr, float b1, float b2, float c1, float c2, float eps) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  theta[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+// BF16 copy of a parameter block
+__global__ __launch_bounds__(256) void to_bf16_kernel(const float* src, uint16_t* dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = f2bf(src[i]);
+}
+
+// padded transposed BF16 operand gt[n][k] from W[rows][cols]: transpose = 0
+// gives gt[n][k] = W[n][k] (n < rows, k < cols), transpose = 1 gives
+// gt[n][k] = W[k][n]; zero elsewhere (npad x kp)
+__global__ __launch_bounds__(256) void make_gt_kernel(const float* W, int rows, int cols, int transpose, uint16_t* gt,
+                                                      int npad, int kp) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)npad * kp) return;
+  const int n = (int)(e / kp), k = (int)(e % kp);
+  float v = 0.f;
+  if (!transpose) {
+    if (n < rows && k < cols) v = W[(int64_t)n * cols + k];
+  } else {
+    if (k < rows && n < cols) v = W[(int64_t)k * cols + n];
+  }
+  gt[e] = f2bf(v);
+}
+
+}  // namespace mfno

@@ -1,0 +1,137 @@
+"""Python binding of the Fourier-neural-operator part of the C ABI (argument
+marshalling only; every contraction, activation, reduction and update runs
+in the HIP library).  Device tensors are torch CUDA tensors: inputs BF16
+[B][cin][nx][ny][nz], targets and outputs FP32, the loss mask uint8
+[nx][ny][nz].
+"""
+import ctypes
+import time
+
+import numpy as np
+
+from ._lib import FnoParams, load
+
+
+class FnoError(RuntimeError):
+    pass
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Fno:
+    """3D FNO: lifting, Fourier layers with truncated corner modes, GELU MLP
+    projection; trained with masked MSE and Adam."""
+
+    def __init__(self, nx=128, ny=64, nz=64, cin=4, cout=4, width=32, layers=4, mx=16, my=16, mz=16, hidden=128,
+                 max_batch=16, seed=0):
+        L = load()
+        p = FnoParams()
+        p.nx, p.ny, p.nz, p.cin, p.cout = nx, ny, nz, cin, cout
+        p.width, p.layers, p.mx, p.my, p.mz = width, layers, mx, my, mz
+        p.proj_hidden, p.max_batch = hidden, max_batch
+        self.p = p
+        self.shape = (nx, ny, nz)
+        self._L = L
+        self._h = None
+        h = ctypes.c_void_p()
+        rc = L.fno_create(ctypes.byref(p), ctypes.c_uint64(seed), _stream(), ctypes.byref(h))
+        self._check(rc, "fno_create", None)
+        self._h = h
+        self.nparam = int(L.fno_param_count(ctypes.byref(p)))
+
+    def _check(self, rc, what, h="self"):
+        if rc != 0:
+            msg = self._L.fno_last_error(self._h if h == "self" else None)
+            raise FnoError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+
+    def close(self):
+        if self._h is not None:
+            self._L.fno_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        a = np.empty(self.nparam, np.float32)
+        self._check(self._L.fno_get_params(self._h, ctypes.c_void_p(a.ctypes.data), self.nparam), "fno_get_params")
+        return a
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        assert a.size == self.nparam
+        self._check(self._L.fno_set_params(self._h, ctypes.c_void_p(a.ctypes.data), self.nparam), "fno_set_params")
+
+    def forward(self, x, y=None):
+        import torch
+        assert x.dtype == torch.bfloat16 and x.is_cuda and x.is_contiguous()
+        B = x.shape[0]
+        if y is None:
+            y = torch.empty((B, self.p.cout) + self.shape, dtype=torch.float32, device=x.device)
+        self._check(self._L.fno_forward(self._h, ctypes.c_void_p(x.data_ptr()), B, ctypes.c_void_p(y.data_ptr())),
+                    "fno_forward")
+        return y
+
+    def loss_grad(self, x, target, mask, grads=True):
+        B = x.shape[0]
+        loss = ctypes.c_float()
+        g = np.empty(self.nparam, np.float32) if grads else None
+        self._check(self._L.fno_loss_grad(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(target.data_ptr()),
+                                          ctypes.c_void_p(mask.data_ptr()), B, ctypes.byref(loss),
+                                          None if g is None else ctypes.c_void_p(g.ctypes.data)), "fno_loss_grad")
+        return loss.value, g
+
+    def adam_step(self, lr):
+        self._check(self._L.fno_adam_step(self._h, ctypes.c_float(lr)), "fno_adam_step")
+
+    def train_step(self, x, target, mask, lr):
+        loss = ctypes.c_float()
+        self._check(self._L.fno_train_step(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(target.data_ptr()),
+                                           ctypes.c_void_p(mask.data_ptr()), x.shape[0], ctypes.c_float(lr),
+                                           ctypes.byref(loss)), "fno_train_step")
+        return loss.value
+
+
+def bench_inference(batch=16, reps=10):
+    """Forward time per batch at the full surrogate shape (128x64x64, width
+    32, 4 layers, 32x32x16 retained modes, hidden 128), random input."""
+    import torch
+    net = Fno(max_batch=batch)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn((batch, 4, 128, 64, 64), device="cuda", generator=g).to(torch.bfloat16)
+    y = torch.empty((batch, 4, 128, 64, 64), device="cuda")
+    net.forward(x, y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        net.forward(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    net.close()
+    return {"batch": batch, "ms_per_batch": round(ms, 3), "samples_per_s": round(batch / ms * 1e3, 1)}
+
+
+def smoke_check():
+    """One small forward pass on cuda:0 against the FP64 oracle."""
+    import torch
+    from oracle import fno as ofno
+    s = ofno.Shape(nx=32, ny=16, nz=16, cin=4, cout=4, width=16, layers=2, mx=4, my=4, mz=4, hidden=16)
+    net = Fno(nx=32, ny=16, nz=16, width=16, layers=2, mx=4, my=4, mz=4, hidden=16, max_batch=2, seed=1)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn((2, 4, 32, 16, 16), device="cuda", generator=g).to(torch.bfloat16)
+    y = net.forward(x)
+    th = net.get_params().astype(np.float64)
+    yo, _ = ofno.forward(th, x.float().cpu().numpy().astype(np.float64), s)
+    err = float(np.linalg.norm(y.cpu().numpy() - yo) / np.linalg.norm(yo))
+    print(f"smoke fno: forward 32x16x16 width 16, rel L2 vs oracle {err:.3e}", flush=True)
+    net.close()
+    assert err < 3e-2
+    return err

@@ -1,0 +1,122 @@
+"""GPU Fourier neural operator (BF16 MFMA, FP32 accumulation) against the
+FP64 oracle on the same parameters and inputs.
+
+Tolerance (relative L2): BF16 operands carry a relative rounding error of at
+most 2^-9; with FP32 accumulation each contraction adds about that much in
+relative L2, and a forward pass chains ~9 contractions per Fourier layer
+plus lifting and projection.  Adding in quadrature over ~20 stages gives
+~1e-2; the bounds below are 3e-2 (forward) and 5e-2 (gradients, about
+twice as many stages).
+"""
+import numpy as np
+import pytest
+
+from oracle import fno as ofno
+
+pytestmark = pytest.mark.gpu
+
+SMALL = dict(nx=32, ny=16, nz=16, cin=4, cout=4, width=16, layers=2, mx=4, my=4, mz=4, hidden=16)
+
+
+def _shape(d):
+    return ofno.Shape(nx=d["nx"], ny=d["ny"], nz=d["nz"], cin=d["cin"], cout=d["cout"], width=d["width"],
+                      layers=d["layers"], mx=d["mx"], my=d["my"], mz=d["mz"], hidden=d["hidden"])
+
+
+def _setup(cfg, B, seed=1):
+    import torch
+    from paper_2606_16765_amd import Fno
+    net = Fno(max_batch=B, seed=seed, **cfg)
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    x = torch.randn((B, cfg["cin"], cfg["nx"], cfg["ny"], cfg["nz"]), device="cuda", generator=g).to(torch.bfloat16)
+    t = torch.randn((B, cfg["cout"], cfg["nx"], cfg["ny"], cfg["nz"]), device="cuda", generator=g) * 0.1
+    return net, x, t
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def test_forward_matches_oracle_small():
+    net, x, _ = _setup(SMALL, 2)
+    y = net.forward(x).cpu().numpy()
+    th = net.get_params().astype(np.float64)
+    yo, _ = ofno.forward(th, x.float().cpu().numpy().astype(np.float64), _shape(SMALL))
+    err = rel_l2(y, yo)
+    print("forward rel L2", err)
+    assert err < 3e-2
+
+
+def test_gradients_match_oracle_small():
+    import torch
+    s = _shape(SMALL)
+    net, x, t = _setup(SMALL, 2)
+    mask = torch.from_numpy(ofno.inner_box_mask(s)).cuda()
+    loss, g = net.loss_grad(x, t, mask)
+    th = net.get_params().astype(np.float64)
+    xo = x.float().cpu().numpy().astype(np.float64)
+    yo, cache = ofno.forward(th, xo, s)
+    lo, gy = ofno.masked_mse(yo, t.cpu().numpy().astype(np.float64), ofno.inner_box_mask(s))
+    go = ofno.backward(th, cache, gy, s)
+    assert abs(loss - lo) / lo < 3e-2
+    # per parameter group
+    gu, gou = ofno.unpack(g.astype(np.float64), s), ofno.unpack(go, s)
+    groups = [("P", gu["P"], gou["P"]), ("p", gu["p"], gou["p"]), ("Q1", gu["Q1"], gou["Q1"]),
+              ("q1", gu["q1"], gou["q1"]), ("Q2", gu["Q2"], gou["Q2"]), ("q2", gu["q2"], gou["q2"])]
+    for l in range(s.layers):
+        for k in ("W", "Wp", "bp"):
+            groups.append((f"{k}{l}", gu["layers"][l][k], gou["layers"][l][k]))
+    worst = max((rel_l2(a, b), name) for name, a, b in groups)
+    print("gradient worst group", worst)
+    assert worst[0] < 5e-2, worst
+
+
+def test_forward_full_size_matches_oracle():
+    full = dict(nx=128, ny=64, nz=64, cin=4, cout=4, width=32, layers=4, mx=16, my=16, mz=16, hidden=128)
+    net, x, _ = _setup(full, 1, seed=3)
+    y = net.forward(x).cpu().numpy()
+    th = net.get_params().astype(np.float64)
+    yo, _ = ofno.forward(th, x.float().cpu().numpy().astype(np.float64), _shape(full))
+    err = rel_l2(y, yo)
+    print("full-size forward rel L2", err)
+    assert err < 3e-2
+
+
+def test_adam_trajectory_matches_oracle():
+    """Five loss/grad/Adam steps on the GPU against the same five steps of
+    the FP64 oracle started from the same parameters: the loss sequences
+    agree to the forward tolerance."""
+    import torch
+    s = _shape(SMALL)
+    net, x, t = _setup(SMALL, 2, seed=7)
+    mnp = ofno.inner_box_mask(s)
+    mask = torch.from_numpy(mnp).cuda()
+    th = net.get_params().astype(np.float64)
+    xo = x.float().cpu().numpy().astype(np.float64)
+    to = t.cpu().numpy().astype(np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    lr = 1e-3
+    for k in range(1, 6):
+        lg = net.train_step(x, t, mask, lr)
+        yo, cache = ofno.forward(th, xo, s)
+        lo, gy = ofno.masked_mse(yo, to, mnp)
+        g = ofno.backward(th, cache, gy, s)
+        th, m, v = ofno.adam(th, g, m, v, k, lr)
+        print("step", k, lg, lo)
+        assert abs(lg - lo) / lo < 3e-2
+
+
+def test_training_fits_teacher_network():
+    """A target made by another network of the same architecture is exactly
+    representable; 60 Adam steps must cut the masked loss at least 4x."""
+    import torch
+    from paper_2606_16765_amd import Fno
+    s = _shape(SMALL)
+    net, x, _ = _setup(SMALL, 2, seed=5)
+    teacher = Fno(max_batch=2, seed=11, **SMALL)
+    t = teacher.forward(x)
+    mask = torch.from_numpy(ofno.inner_box_mask(s)).cuda()
+    losses = [net.train_step(x, t, mask, 1e-2) for _ in range(60)]
+    print("losses", losses[0], losses[-1])
+    assert losses[-1] < 0.25 * losses[0]
