@@ -123,6 +123,18 @@ int lbm_step(lbm_sim* s, int64_t nsteps);
  * receives the number of sampled steps.  Synchronises.                       */
 int lbm_mean_fields(lbm_sim* s, double* out, int out_on_device, int64_t* nsamples);
 
+/* Mean fields pooled for the surrogate (paper Sec. 2: fields stored at a
+ * reduced resolution; App. A.2: 128x64x64 training fields, augmented by 90
+ * degree turns about the x axis).  d_out is device float [4][X][Y][Z]
+ * (u, v, w, p; Z fastest) with X = nx/factor, Y = ny/factor, Z = nz/factor:
+ * each value is the mean over a factor^3 block of the values lbm_mean_fields
+ * returns (solid cells count as 0).  quarter_turns in 0..3 turns the pooled
+ * field about +x: the value at (x, y, z) is R^q u(R^-q (x, y, z)) with R
+ * taking +y to +z and +z to -y (requires ny == nz).  The caller owns d_out.
+ * Errors: LBM_EINVAL (factor does not divide the grid, turns out of range),
+ * LBM_ESTATE (averaging off).  Asynchronous on the object's stream.          */
+int lbm_mean_fields_pooled(lbm_sim* s, int32_t factor, int32_t quarter_turns, float* d_out);
+
 /* Snapshots (paper Sec. 2: 20 snapshots 25 steps apart).  out is
  * [k][4][N] float (u, v, w, p), oldest first, k = min(taken, snap_count)
  * written to *k; steps[j] (host int64, may be NULL) receives the step index
@@ -182,12 +194,12 @@ const char* lbm_last_error(const lbm_sim* s); /* s may be NULL: global error */
 typedef struct fno_net fno_net;
 
 typedef struct {
-  int32_t nx, ny, nz;       /* grid; multiples of 16, nz >= 2*mz              */
+  int32_t nx, ny, nz;       /* grid; powers of two, nx*ny*nz % 8192 == 0      */
   int32_t cin, cout;        /* input / output channels (4, 4)                 */
-  int32_t width;            /* channels of the Fourier layers (32)            */
+  int32_t width;            /* channels of the Fourier layers (32), % 16 == 0 */
   int32_t layers;           /* Fourier layers (4)                             */
-  int32_t mx, my, mz;       /* retained modes per corner / half-spectrum (16)  */
-  int32_t proj_hidden;      /* projection hidden width (128)                  */
+  int32_t mx, my, mz;       /* retained modes (16): powers of two, 2m <= n    */
+  int32_t proj_hidden;      /* projection hidden width (128), % 16 == 0       */
   int32_t max_batch;        /* largest batch the workspaces are sized for     */
 } fno_params;
 
@@ -226,6 +238,18 @@ int fno_adam_step(fno_net* n, float lr);
 /* fno_loss_grad followed by fno_adam_step.                                   */
 int fno_train_step(fno_net* n, const uint16_t* x, const float* target, const uint8_t* mask, int32_t B, float lr,
                    float* loss);
+
+/* Per-field min-max scaling of the surrogate's data (App. A.2: min-max
+ * scaling applied to each field).  x is device float [S][C][P], C <= 16.
+ * fno_field_minmax writes the minimum and maximum of each channel over all
+ * samples and points to host lo[C], hi[C] and synchronises hip_stream.
+ * fno_field_scale maps x in place to (x - lo[c]) / (hi[c] - lo[c]) (a
+ * channel with hi == lo maps to 0), or with inverse != 0 back to
+ * x (hi[c] - lo[c]) + lo[c]; lo, hi are host arrays; asynchronous.
+ * Errors: LBM_EINVAL (null pointer, sizes), LBM_ENOMEM, LBM_EDEVICE.        */
+int fno_field_minmax(const float* x, int64_t S, int32_t C, int64_t P, void* hip_stream, float* lo, float* hi);
+int fno_field_scale(float* x, int64_t S, int32_t C, int64_t P, const float* lo, const float* hi, int32_t inverse,
+                    void* hip_stream);
 
 void fno_destroy(fno_net* n);
 const char* fno_last_error(const fno_net* n);

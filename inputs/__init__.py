@@ -7,4 +7,5 @@ product tests and the oracle read its arrays; neither side's arithmetic lives
 here.
 """
 from .rng import splitmix64, uniform_pm1, perturbation  # noqa: F401
-from .geometry import Geometry, sphere_channel, spanwise_cylinder, random_obstacle, from_sdf  # noqa: F401
+from .geometry import Geometry, sphere_channel, spanwise_cylinder, random_obstacle, obstacle_sdf, from_sdf  # noqa: F401
+from .features import coarse_inputs, to_bf16_bits  # noqa: F401

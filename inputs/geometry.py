@@ -269,16 +269,38 @@ def spanwise_cylinder(shape=(1024, 512, 512), center=(307.2, 255.5), diameter=64
                     params=dict(center=center, diameter=diameter))
 
 
-def random_obstacle(shape, seed, scale=None):
-    """Seeded union of 1-3 primitives at (0.3 nx, (ny-1)/2, (nz-1)/2); sizes
-    refer to a 256x128x128 channel and scale with nx/256 unless given."""
+def obstacle_sdf(shape, seed, scale=None, turns=0):
+    """Description and signed distance function of the seeded random object
+    placed at (0.3 nx, (ny-1)/2, (nz-1)/2), turned by `turns` quarter turns
+    about the channel axis (+y towards +z; needs ny == nz when turns != 0)."""
     nx, ny, nz = shape
     if scale is None:
         scale = nx / 256.0
     obj = random_object(seed, scale)
     center = np.array([0.3 * nx, (ny - 1) / 2.0, (nz - 1) / 2.0])
-    sdf = object_sdf(obj, center)
+    base = object_sdf(obj, center)
+    q = int(turns) % 4
+    if q == 0:
+        return obj, base, center, scale
+    if ny != nz:
+        raise ValueError("turns about x need ny == nz")
+    cy, cz = center[1], center[2]
+
+    def sdf(p):
+        p = np.asarray(p, dtype=np.float64)
+        y, z = p[..., 1] - cy, p[..., 2] - cz
+        for _ in range(q):  # pull back: (y, z) -> (z, -y)
+            y, z = z, -y
+        return base(np.stack([p[..., 0], y + cy, z + cz], -1))
+
+    return obj, sdf, center, scale
+
+
+def random_obstacle(shape, seed, scale=None, turns=0):
+    """Seeded union of 1-3 primitives at (0.3 nx, (ny-1)/2, (nz-1)/2); sizes
+    refer to a 256x128x128 channel and scale with nx/256 unless given."""
+    obj, sdf, center, scale = obstacle_sdf(shape, seed, scale, turns)
     ext = 24.0 * scale * 1.5 + 4.0 * scale * 1.8 + 3
     bb = tuple((center[d] - ext, center[d] + ext + 1) for d in range(3))
-    g = from_sdf(shape, sdf, name=f"random{seed}", params=obj, bbox=bb)
+    g = from_sdf(shape, sdf, name=f"random{seed}" + (f"t{turns}" if turns else ""), params=obj, bbox=bb)
     return g

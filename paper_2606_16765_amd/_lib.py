@@ -39,6 +39,7 @@ def _sig(L):
     L.lbm_create.argtypes = [P(LbmParams), vp, i64, vp, vp, vp, vp, vp, P(vp)]
     L.lbm_step.argtypes = [vp, i64]
     L.lbm_mean_fields.argtypes = [vp, vp, ctypes.c_int, P(i64)]
+    L.lbm_mean_fields_pooled.argtypes = [vp, i32, i32, vp]
     L.lbm_snapshots.argtypes = [vp, vp, ctypes.c_int, P(i32), vp]
     L.lbm_forces.argtypes = [vp, vp, i64, P(i64), vp]
     L.lbm_moments.argtypes = [vp, vp, ctypes.c_int]
@@ -67,6 +68,8 @@ def _sig(L):
         L.fno_destroy.argtypes = [vp]
         L.fno_destroy.restype = None
         L.fno_last_error.argtypes = [vp]
+        L.fno_field_minmax.argtypes = [vp, i64, i32, i64, vp, vp, vp]
+        L.fno_field_scale.argtypes = [vp, i64, i32, i64, vp, vp, i32, vp]
         L.fno_last_error.restype = ctypes.c_char_p
 
 

@@ -631,4 +631,57 @@ extern "C" void fno_destroy(fno_net* n) {
   delete n;
 }
 
+extern "C" int fno_field_minmax(const float* x, int64_t S, int32_t C, int64_t P, void* hip_stream, float* lo,
+                                float* hi) {
+  if (!x || !lo || !hi) return ffail(nullptr, LBM_EINVAL, "null argument");
+  if (S <= 0 || C <= 0 || C > MM_MAXC || P <= 0) return ffail(nullptr, LBM_EINVAL, "bad sizes");
+  const hipStream_t st = (hipStream_t)hip_stream;
+  const int64_t nchunk = (P + MM_CHUNK - 1) / MM_CHUNK, nblk = S * nchunk;
+  if (nblk > 0x7fffffff) return ffail(nullptr, LBM_EINVAL, "too many samples");
+  float* part = nullptr;
+  hipError_t e = hipMalloc((void**)&part, (size_t)nblk * C * 2 * 4);
+  if (e != hipSuccess) return ffail(nullptr, LBM_ENOMEM, hipGetErrorString(e));
+  hipLaunchKernelGGL(minmax_kernel, dim3((unsigned)nblk, (unsigned)C), dim3(256), 0, st, x, (int)C, P, nchunk, part,
+                     nblk);
+  std::vector<float> h((size_t)nblk * C * 2);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), part, h.size() * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(part);
+  if (e != hipSuccess) return ffail(nullptr, LBM_EDEVICE, hipGetErrorString(e));
+  for (int c = 0; c < C; ++c) {
+    float a = INFINITY, b = -INFINITY;
+    for (int64_t k = 0; k < nblk; ++k) {
+      a = std::min(a, h[((size_t)c * nblk + k) * 2]);
+      b = std::max(b, h[((size_t)c * nblk + k) * 2 + 1]);
+    }
+    lo[c] = a;
+    hi[c] = b;
+  }
+  return LBM_OK;
+}
+
+extern "C" int fno_field_scale(float* x, int64_t S, int32_t C, int64_t P, const float* lo, const float* hi,
+                               int32_t inverse, void* hip_stream) {
+  if (!x || !lo || !hi) return ffail(nullptr, LBM_EINVAL, "null argument");
+  if (S <= 0 || C <= 0 || C > MM_MAXC || P <= 0) return ffail(nullptr, LBM_EINVAL, "bad sizes");
+  ScaleArgs a{};
+  for (int c = 0; c < C; ++c) {
+    const float r = hi[c] - lo[c];
+    if (inverse) {
+      a.mul[c] = r;
+      a.off[c] = lo[c];
+    } else {
+      a.mul[c] = r > 0.f ? 1.f / r : 0.f;
+      a.off[c] = -lo[c];
+    }
+  }
+  const int64_t n = S * C * P;
+  hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)hip_stream, x,
+                     (int)C, P, n, a, inverse ? 1 : 0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return ffail(nullptr, LBM_EDEVICE, hipGetErrorString(e));
+  return LBM_OK;
+}
+
 extern "C" const char* fno_last_error(const fno_net* n) { return n ? n->err.c_str() : g_fno_err.c_str(); }

@@ -368,4 +368,52 @@ __global__ __launch_bounds__(256) void make_gt_kernel(const float* W, int rows, 
   gt[e] = f2bf(v);
 }
 
+// ------------------------------------------------------- min-max scaling
+constexpr int MM_CHUNK = 4096;
+constexpr int MM_MAXC = 16;
+
+// per (sample, chunk, channel) minimum and maximum of x [S][C][P]:
+// part[(c * S * nchunk + blockIdx.x) * 2 + {0, 1}]
+__global__ __launch_bounds__(256) void minmax_kernel(const float* x, int C, int64_t P, int64_t nchunk, float* part,
+                                                     int64_t nblk) {
+  __shared__ float rmin[256], rmax[256];
+  const int c = blockIdx.y;
+  const int64_t s = blockIdx.x / nchunk, p0 = (blockIdx.x % nchunk) * MM_CHUNK;
+  const int64_t p1 = p0 + MM_CHUNK < P ? p0 + MM_CHUNK : P;
+  const float* r = x + (s * C + c) * P;
+  float lo = INFINITY, hi = -INFINITY;
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) {
+    const float v = r[p];
+    lo = fminf(lo, v);
+    hi = fmaxf(hi, v);
+  }
+  rmin[threadIdx.x] = lo;
+  rmax[threadIdx.x] = hi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      rmin[threadIdx.x] = fminf(rmin[threadIdx.x], rmin[threadIdx.x + w]);
+      rmax[threadIdx.x] = fmaxf(rmax[threadIdx.x], rmax[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[((int64_t)c * nblk + blockIdx.x) * 2] = rmin[0];
+    part[((int64_t)c * nblk + blockIdx.x) * 2 + 1] = rmax[0];
+  }
+}
+
+struct ScaleArgs {
+  float off[MM_MAXC];
+  float mul[MM_MAXC];
+};
+
+// x [S][C][P] in place: x = (x + off[c]) * mul[c] (forward) or x * mul[c] + off[c]
+__global__ __launch_bounds__(256) void scale_kernel(float* x, int C, int64_t P, int64_t n, ScaleArgs a, int inverse) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int c = (int)((i / P) % C);
+  x[i] = inverse ? x[i] * a.mul[c] + a.off[c] : (x[i] + a.off[c]) * a.mul[c];
+}
+
 }  // namespace mfno

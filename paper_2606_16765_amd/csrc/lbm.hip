@@ -567,6 +567,47 @@ __global__ __launch_bounds__(256) void mean_kernel(const double* acc, int64_t N,
   for (int k = 0; k < 4; ++k) out[k * N + n] = sol ? 0.0 : acc[k * N + n] * inv;
 }
 
+// Block means of the running sums over f x f x f cells, written in the
+// surrogate's [channel][X][Y][Z] layout (Z fastest), solid cells counting as
+// zero; optionally turned by q quarter turns about +x.  The turned field at
+// (x, y', z') is R^q applied to the field at R^-q (x, y', z'), where R takes
+// +y to +z and +z to -y; on indices (Y == Z) R^-1 maps (y', z') to
+// (z', Y - 1 - y') and R maps the vector (u, v, w) to (u, -w, v).
+__global__ __launch_bounds__(256) void pool_kernel(const double* acc, int64_t N, double inv, const uint8_t* flag,
+                                                   int nx, int ny, int f, int X, int Y, int Z, int turns,
+                                                   float* out) {
+  const int64_t P = (int64_t)X * Y * Z;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= P) return;
+  const int zo = (int)(e % Z), yo = (int)((e / Z) % Y), xo = (int)(e / ((int64_t)Y * Z));
+  int ys = yo, zs = zo;
+  for (int t = 0; t < turns; ++t) {
+    const int yn = zs, zn = Y - 1 - ys;
+    ys = yn;
+    zs = zn;
+  }
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int dz = 0; dz < f; ++dz)
+    for (int dy = 0; dy < f; ++dy)
+      for (int dx = 0; dx < f; ++dx) {
+        const int64_t n = ((int64_t)(zs * f + dz) * ny + (ys * f + dy)) * nx + (xo * f + dx);
+        if (flag[n] == 2) continue;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[k] += acc[k * N + n];
+      }
+  const double sc = inv / (double)(f * f * f);
+  double u = s[0] * sc, v = s[1] * sc, w = s[2] * sc;
+  for (int t = 0; t < turns; ++t) {
+    const double vn = -w, wn = v;
+    v = vn;
+    w = wn;
+  }
+  out[e] = (float)u;
+  out[P + e] = (float)v;
+  out[2 * P + e] = (float)w;
+  out[3 * P + e] = (float)(s[3] * sc);
+}
+
 // Boundary tables: mark flag-1 cells and their rows.
 __global__ __launch_bounds__(256) void scatter_rows_kernel(const int64_t* cells, int64_t nb, uint8_t* flag,
                                                            int32_t* brow) {
@@ -1086,6 +1127,25 @@ extern "C" int lbm_mean_fields(lbm_sim* s, double* out, int out_on_device, int64
   if (tmp) (void)hipFree(tmp);
   if (e != hipSuccess) return fail(s, LBM_EDEVICE, hipGetErrorString(e));
   if (nsamples) *nsamples = s->nsamples;
+  return LBM_OK;
+}
+
+extern "C" int lbm_mean_fields_pooled(lbm_sim* s, int32_t factor, int32_t quarter_turns, float* d_out) {
+  if (!s || !d_out) return fail(s, LBM_EINVAL, "null argument");
+  if (s->sticky) return s->sticky;
+  if (!s->d_acc) return fail(s, LBM_ESTATE, "averaging is off (avg_start < 0)");
+  const int nx = s->p.nx, ny = s->p.ny, nz = s->p.nz;
+  if (factor < 1 || nx % factor || ny % factor || nz % factor)
+    return fail(s, LBM_EINVAL, "pooling factor must divide nx, ny and nz");
+  if (quarter_turns < 0 || quarter_turns > 3) return fail(s, LBM_EINVAL, "quarter_turns must be 0..3");
+  if (quarter_turns && ny != nz) return fail(s, LBM_EINVAL, "turns about x need ny == nz");
+  const int X = nx / factor, Y = ny / factor, Z = nz / factor;
+  const int64_t P = (int64_t)X * Y * Z;
+  const double inv = s->nsamples > 0 ? 1.0 / (double)s->nsamples : 0.0;
+  hipLaunchKernelGGL(pool_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s->stream, s->d_acc, s->N, inv,
+                     s->d_flag, nx, ny, (int)factor, X, Y, Z, (int)quarter_turns, d_out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(s, LBM_EDEVICE, hipGetErrorString(e));
   return LBM_OK;
 }
 

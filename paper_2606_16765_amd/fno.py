@@ -5,7 +5,6 @@ in the HIP library).  Device tensors are torch CUDA tensors: inputs BF16
 [nx][ny][nz].
 """
 import ctypes
-import time
 
 import numpy as np
 
@@ -96,6 +95,41 @@ class Fno:
                                            ctypes.c_void_p(mask.data_ptr()), x.shape[0], ctypes.c_float(lr),
                                            ctypes.byref(loss)), "fno_train_step")
         return loss.value
+
+
+def _fields_check(x):
+    import torch
+    assert x.dtype == torch.float32 and x.is_cuda and x.is_contiguous() and x.dim() >= 3
+    S, C = x.shape[0], x.shape[1]
+    return S, C, x[0, 0].numel()
+
+
+def field_minmax(x):
+    """Per-channel (min, max) over samples and points of device float
+    x [S][C][...]; returns two numpy arrays."""
+    L = load()
+    S, C, P = _fields_check(x)
+    lo = np.empty(C, np.float32)
+    hi = np.empty(C, np.float32)
+    rc = L.fno_field_minmax(ctypes.c_void_p(x.data_ptr()), S, C, P, _stream(), ctypes.c_void_p(lo.ctypes.data),
+                            ctypes.c_void_p(hi.ctypes.data))
+    if rc:
+        raise FnoError(f"fno_field_minmax failed ({rc}): {L.fno_last_error(None).decode()}")
+    return lo, hi
+
+
+def field_scale(x, lo, hi, inverse=False):
+    """In place: per-channel (x - lo) / (hi - lo), or its inverse."""
+    L = load()
+    S, C, P = _fields_check(x)
+    lo = np.ascontiguousarray(lo, np.float32)
+    hi = np.ascontiguousarray(hi, np.float32)
+    assert lo.size == C and hi.size == C
+    rc = L.fno_field_scale(ctypes.c_void_p(x.data_ptr()), S, C, P, ctypes.c_void_p(lo.ctypes.data),
+                           ctypes.c_void_p(hi.ctypes.data), 1 if inverse else 0, _stream())
+    if rc:
+        raise FnoError(f"fno_field_scale failed ({rc}): {L.fno_last_error(None).decode()}")
+    return x
 
 
 def bench_inference(batch=16, reps=10):

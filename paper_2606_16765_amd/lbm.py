@@ -142,6 +142,19 @@ class Lbm:
         self._chk(self._L.lbm_mean_fields(self._h, _ptr(a), 0, ctypes.byref(n)), "lbm_mean_fields")
         return a, n.value
 
+    def mean_fields_pooled(self, factor=2, quarter_turns=0, out=None):
+        """Means pooled over factor^3 blocks, device float [4][X][Y][Z]
+        (Z fastest), optionally turned about +x; asynchronous."""
+        import torch
+        nx, ny, nz = self.shape
+        if out is None:
+            out = torch.empty((4, nx // factor, ny // factor, nz // factor), dtype=torch.float32, device="cuda")
+        assert out.dtype == torch.float32 and out.is_cuda and out.is_contiguous()
+        assert out.numel() == 4 * (nx // factor) * (ny // factor) * (nz // factor)
+        self._chk(self._L.lbm_mean_fields_pooled(self._h, factor, quarter_turns, ctypes.c_void_p(out.data_ptr())),
+                  "lbm_mean_fields_pooled")
+        return out
+
     def snapshots(self):
         k = ctypes.c_int32()
         self._chk(self._L.lbm_snapshots(self._h, None, 0, ctypes.byref(k), None), "lbm_snapshots")

@@ -1,0 +1,63 @@
+"""GPU data curation and the surrogate pipeline against the oracle:
+pooled and turned mean fields, per-field min-max scaling, and one small
+end-to-end run (LBM runs -> dataset -> training -> held-out metrics)."""
+import numpy as np
+import pytest
+
+from inputs import sphere_channel
+from oracle import dataset as ods
+from oracle import lbm as olbm
+
+pytestmark = pytest.mark.gpu
+
+
+def test_pooled_turned_means_match_oracle():
+    import torch
+    from paper_2606_16765_amd import Lbm
+    geo = sphere_channel((64, 32, 32), (16.0, 15.5, 15.5), 4.0)
+    nu = 0.05 * 8 / 1000.0
+    p = olbm.make_params(geo.shape, nu=nu, u_in=0.05, mode=0, avg_start=0)
+    r = olbm.Run(p, solid=geo.solid)
+    r.step(40)
+    ref = ods.pool_mean(r.mean_fields(), 2)
+    sim = Lbm(geo.shape, storage="f64", u_in=0.05, nu=nu, mode="plain", solid=geo.solid, avg_start=0)
+    sim.step(40)
+    scale = np.abs(ref).max()
+    for q in range(4):
+        out = sim.mean_fields_pooled(2, q).cpu().numpy()
+        exp = ods.quarter_turn(ref, q)
+        err = np.abs(out - exp).max() / scale
+        print("turns", q, "max rel err", err)
+        assert err < 2e-7  # FP32 output of FP64 fields that agree to 1e-11
+    sim.close()
+
+
+def test_minmax_and_scale_match_oracle():
+    import torch
+    from paper_2606_16765_amd import fno as pfno
+    g = torch.Generator(device="cuda").manual_seed(3)
+    x = torch.randn((5, 3, 40, 37), device="cuda", generator=g) * torch.tensor([1.0, 20.0, 0.01], device="cuda")[None, :, None, None]
+    xh = x.cpu().numpy().astype(np.float64)
+    lo, hi = pfno.field_minmax(x)
+    elo, ehi = ods.minmax(xh)
+    assert np.array_equal(lo.astype(np.float64), elo) and np.array_equal(hi.astype(np.float64), ehi)
+    pfno.field_scale(x, lo, hi)
+    y = x.cpu().numpy()
+    ey = ods.scale(xh, lo, hi)
+    assert np.abs(y - ey).max() < 1e-6
+    pfno.field_scale(x, lo, hi, inverse=True)
+    assert np.abs(x.cpu().numpy() - xh).max() < 1e-5 * np.abs(xh).max()
+
+
+def test_small_pipeline_end_to_end():
+    from paper_2606_16765_amd import surrogate
+    cfg = surrogate.Config(shape=(64, 32, 32), sims=6, held_out=2, steps=200, epochs=3, batch=4, width=16,
+                           modes=(4, 4, 4), hidden=16, curve_sims=1, curve_steps=(50, 100), lr=3e-3)
+    res = surrogate.run(cfg)
+    print({k: res[k] for k in ("gain", "time_to_field")})
+    assert res["config"]["n_train"] == 16 and res["config"]["n_held_out"] == 8
+    for k in ("rel_l2_inner", "rel_l2_whole", "mse_inner"):
+        assert np.isfinite(res["fno"]["held_out"][k]) and np.isfinite(res["mean_field_baseline"]["held_out"][k])
+    assert len(res["fno"]["loss_history"]) == 3
+    assert res["time_to_field"]["lbm_ms_per_field"] > 0 and res["time_to_field"]["fno_ms_per_field"] > 0
+    assert len(res["time_to_field"]["lbm_curve"]) == 2

@@ -58,3 +58,30 @@ def test_spanwise_cylinder_links():
     x, y = cell % 128, (cell // 128) % 64
     px, py = x + q * c[dr, 0], y + q * c[dr, 1]
     assert np.abs(np.hypot(px - 38.4, py - 31.5) - 8.0).max() < 1e-9
+
+
+def test_turned_obstacle_is_the_turned_mask():
+    from oracle import dataset as ods
+    shape = (64, 32, 32)
+    for seed in (3, 8):
+        g0 = random_obstacle(shape, seed)
+        for q in (1, 2, 3):
+            gq = random_obstacle(shape, seed, turns=q)
+            assert np.array_equal(gq.solid, ods.turn_mask(g0.solid, q))
+
+
+def test_coarse_inputs_channels():
+    from inputs import coarse_inputs, to_bf16_bits
+    shape = (128, 64, 64)
+    x, obj = coarse_inputs(shape, 5)
+    assert x.shape == (4, 64, 32, 32) and x.dtype == np.float32
+    assert -1.0 <= x[0].min() and x[0].max() <= 1.0
+    assert np.array_equal(x[1] > 0, x[0] <= 0)
+    assert x[1].sum() > 0
+    assert np.all(x[2] == np.float32(obj["re"] / 1e4)) and np.all(x[3] == np.float32(obj["aoa"] / 15.0))
+    # the obstacle sits near x = 0.3 nx
+    xs = np.nonzero(x[1])[0]
+    assert abs(xs.mean() * 2 + 0.5 - 0.3 * 128) < 6
+    # bf16 rounding: exact for representable values, ties to even
+    v = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -2.5], np.float32)
+    assert list(to_bf16_bits(v)) == [0x3F80, 0x3F80, 0x3F82, 0xC020]
