@@ -59,6 +59,25 @@ def read_traffic(workload):
         return None
 
 
+def read_surrogate_result():
+    """Summary of the last full surrogate pipeline run (dataset of LBM runs,
+    training, held-out errors, time-to-field), committed under profiles/ by
+    the run that produced it; None when absent."""
+    path = os.path.join(ROOT, "profiles", "fno_surrogate_c4.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        r = json.load(fh)
+    keep = {k: r[k] for k in ("config", "gain", "time_to_field") if k in r}
+    if "fno" in r:
+        keep["fno_held_out"] = r["fno"].get("held_out")
+        keep["fno_train_samples_per_s"] = r["fno"].get("train_samples_per_s")
+    if "mean_field_baseline" in r:
+        keep["mean_field_held_out"] = r["mean_field_baseline"].get("held_out")
+    keep["source"] = "profiles/fno_surrogate_c4.json (python -m paper_2606_16765_amd.surrogate)"
+    return keep
+
+
 WORKLOADS = {
     # name: (shape, storage, description)
     "c2": ((1024, 512, 512), "f32", "cylinder D=64, Re_D=3900, K17, FP32, 1024x512x512"),
@@ -183,7 +202,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fno", action="store_true")
+    ap.add_argument("--no-precision", action="store_true", help="skip the FP32/FP16/BF16 storage study")
     ap.add_argument("--copy-calib", action="store_true", help="only run a plain device copy of known size")
+    ap.add_argument("--fno-only", action="store_true", help="only time the FNO forward at batch 16")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the x-slab "
@@ -214,6 +235,11 @@ def main():
         dt = (time.perf_counter() - t) / 10
         print(json.dumps({"copy_bytes_read": 4 * 2 ** 30, "copy_bytes_written": 4 * 2 ** 30,
                           "copy_GBps": 2 * 4 * 2 ** 30 / dt / 1e9}), flush=True)
+        return
+
+    if args.fno_only:
+        from paper_2606_16765_amd import fno as pfno
+        print(json.dumps({"fno": pfno.bench_inference(batch=16)}), flush=True)
         return
 
     res = run_lbm(args.workload, args.steps, args.warmup)
@@ -251,6 +277,17 @@ def main():
             log(f"fno: {line['fno']}")
         except (ImportError, AttributeError) as e:
             log(f"fno leg skipped: {e}")
+    if not args.no_fno:
+        sur = read_surrogate_result()
+        if sur is not None:
+            line.setdefault("fno", {})["surrogate_run"] = sur
+    if not args.no_precision:
+        from paper_2606_16765_amd import precision
+        log("precision study ...")
+        line["precision"] = {
+            "error_vs_f64": precision.error_table(log=log),
+            "throughput": precision.throughput(log=log),
+        }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(args.workload)

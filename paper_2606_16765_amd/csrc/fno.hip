@@ -71,6 +71,10 @@ struct fno_net {
   // pointwise operands (forward and transposed)
   GtMat Glift, Gq1, Gq1t, Gq2, Gq2t;
   std::vector<GtMat> Gwp, Gwpt;
+  // fused projection operands (inference): padded BF16 Q1 [Hp][Wp], Q2 [16][Hp], FP32 q1 [Hp]
+  GtMat Pq1, Pq2;
+  float* pq1b = nullptr;
+  bool fused_proj = false;
   // activations and work buffers
   std::vector<uint16_t*> v;  // L + 1, BF16
   std::vector<float*> h;     // L, FP32 pre-activations
@@ -173,7 +177,17 @@ struct CSpec {
   bool accumulate;
   const float* bias;
   bool kcontig;
+  bool store_out = true;
+  uint16_t* act = nullptr;
+  bool act_gelu = false;
 };
+
+template <typename InT, typename OutT>
+static void launch_contract(const ContractArgs& a, int lm, dim3 grid, hipStream_t st) {
+  if (lm == LOAD_KRUN) hipLaunchKernelGGL((contract_kernel<InT, OutT, LOAD_KRUN>), grid, dim3(256), 0, st, a);
+  else if (lm == LOAD_JRUN) hipLaunchKernelGGL((contract_kernel<InT, OutT, LOAD_JRUN>), grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((contract_kernel<InT, OutT, LOAD_SCALAR>), grid, dim3(256), 0, st, a);
+}
 
 static int contract(fno_net* n, const CSpec& c) {
   ContractArgs a{};
@@ -181,28 +195,44 @@ static int contract(fno_net* n, const CSpec& c) {
   a.out = c.out;
   a.gt = c.g->d;
   a.bias = c.bias;
+  a.act = c.act;
   a.cols = c.cols;
   a.lgI = ilog2(c.I);
   a.in_so = c.in_so; a.in_si = c.in_si; a.in_sk1 = c.in_sk1; a.in_sk2 = c.in_sk2;
   a.lgkd = ilog2(c.kd);
   a.out_so = c.out_so; a.out_si = c.out_si; a.out_sn1 = c.out_sn1; a.out_sn2 = c.out_sn2;
   a.lgnd = ilog2(c.nd);
-  a.K = c.g->K; a.N = c.g->N; a.kp = c.g->kp;
+  a.K = c.g->K; a.N = c.g->N; a.kp = c.g->kp; a.np = c.g->np;
   a.alpha = c.alpha;
   a.accumulate = c.accumulate ? 1 : 0;
-  a.kcontig = c.kcontig ? 1 : 0;
+  a.store_out = c.store_out ? 1 : 0;
+  a.act_gelu = c.act_gelu ? 1 : 0;
   if (a.lgI < 0 || a.lgkd < 0 || a.lgnd < 0) return ffail(n, LBM_EINVAL, "contraction index maps need powers of two");
-  const dim3 grid((unsigned)((c.cols + CT_J - 1) / CT_J), (unsigned)(c.g->np / CT_N));
-  if (c.in_bf16 && c.out_bf16) hipLaunchKernelGGL((contract_kernel<uint16_t, uint16_t>), grid, dim3(256), 0, n->st, a);
-  else if (c.in_bf16) hipLaunchKernelGGL((contract_kernel<uint16_t, float>), grid, dim3(256), 0, n->st, a);
-  else if (c.out_bf16) hipLaunchKernelGGL((contract_kernel<float, uint16_t>), grid, dim3(256), 0, n->st, a);
-  else hipLaunchKernelGGL((contract_kernel<float, float>), grid, dim3(256), 0, n->st, a);
+  if ((a.accumulate || a.store_out) && !a.out) return ffail(n, LBM_EINVAL, "contraction output missing");
+  // vector load modes need 8-element alignment of every address they form
+  const size_t esz = c.in_bf16 ? 2 : 4;
+  const bool base_ok = ((uintptr_t)c.in % (8 * esz)) == 0 && c.in_so % 8 == 0;
+  int lm = LOAD_SCALAR;
+  if (c.kcontig && c.kd == 1 && c.in_sk1 == 1 && a.K % 8 == 0 && base_ok && (c.I == 1 || c.in_si % 8 == 0))
+    lm = LOAD_KRUN;
+  else if (!c.kcontig && c.in_si == 1 && c.I % 8 == 0 && c.cols % 8 == 0 && base_ok && c.in_sk1 % 8 == 0 &&
+           (c.kd == 1 || c.in_sk2 % 8 == 0))
+    lm = LOAD_JRUN;
+  const int nblocks = c.g->np / CT_N;
+  const dim3 grid((unsigned)((c.cols + CT_J - 1) / CT_J), (unsigned)(a.K <= CT_K ? 1 : nblocks));
+  if (c.in_bf16 && c.out_bf16) launch_contract<uint16_t, uint16_t>(a, lm, grid, n->st);
+  else if (c.in_bf16) launch_contract<uint16_t, float>(a, lm, grid, n->st);
+  else if (c.out_bf16) launch_contract<float, uint16_t>(a, lm, grid, n->st);
+  else launch_contract<float, float>(a, lm, grid, n->st);
   return LBM_OK;
 }
 
 // pointwise channel map on [B][Cin][P] -> [B][Cout][P]
+// epilogue: out is written when store_out, act (BF16, same layout) receives
+// GELU(value) or the value when act is not null
 static int pointwise(fno_net* n, int B, const void* in, bool in_bf16, int cin, void* out, bool out_bf16, int cout,
-                     const GtMat* g, const float* bias, bool accumulate) {
+                     const GtMat* g, const float* bias, bool accumulate, bool store_out = true,
+                     uint16_t* act = nullptr, bool act_gelu = false) {
   (void)cout;
   CSpec c{};
   c.in = in; c.in_bf16 = in_bf16; c.out = out; c.out_bf16 = out_bf16; c.g = g;
@@ -210,7 +240,29 @@ static int pointwise(fno_net* n, int B, const void* in, bool in_bf16, int cin, v
   c.in_so = (int64_t)cin * n->P; c.in_si = 1; c.in_sk1 = n->P; c.in_sk2 = 0; c.kd = 1;
   c.out_so = (int64_t)g->N * n->P; c.out_si = 1; c.out_sn1 = n->P; c.out_sn2 = 0; c.nd = 1;
   c.alpha = 1.f; c.accumulate = accumulate; c.bias = bias; c.kcontig = false;
+  c.store_out = store_out; c.act = act; c.act_gelu = act_gelu;
   return contract(n, c);
+}
+
+template <int NT, int KS>
+static void launch_proj(fno_net* n, int B, const uint16_t* v, float* y) {
+  const unsigned blocks = (unsigned)((int64_t)B * n->P / 256);
+  hipLaunchKernelGGL((proj_kernel<NT, KS>), dim3(blocks), dim3(256), 0, n->st, v, n->W, n->P, n->Pq1.d, n->pq1b,
+                     n->Pq2.d, n->theta + n->off_q2, n->p.cout, y);
+}
+
+static void fused_projection(fno_net* n, int B, const uint16_t* v, float* y) {
+  const int NT = n->Pq1.np / 16, KS = n->Pq1.kp / 32;
+  switch (NT * 4 + KS) {
+    case 2 * 4 + 1: launch_proj<2, 1>(n, B, v, y); break;
+    case 2 * 4 + 2: launch_proj<2, 2>(n, B, v, y); break;
+    case 4 * 4 + 1: launch_proj<4, 1>(n, B, v, y); break;
+    case 4 * 4 + 2: launch_proj<4, 2>(n, B, v, y); break;
+    case 6 * 4 + 1: launch_proj<6, 1>(n, B, v, y); break;
+    case 6 * 4 + 2: launch_proj<6, 2>(n, B, v, y); break;
+    case 8 * 4 + 1: launch_proj<8, 1>(n, B, v, y); break;
+    default: launch_proj<8, 2>(n, B, v, y); break;
+  }
 }
 
 // truncated forward 3D DFT: v [B][W][P] (BF16 or FP32) -> modes [m][B][W][2]
@@ -312,6 +364,12 @@ static int refresh(fno_net* n) {
   mk(n->Gq1t, n->off_Q1, n->H, n->W, 1);
   mk(n->Gq2, n->off_Q2, n->p.cout, n->H, 0);
   mk(n->Gq2t, n->off_Q2, n->p.cout, n->H, 1);
+  if (n->fused_proj) {
+    mk(n->Pq1, n->off_Q1, n->H, n->W, 0);
+    mk(n->Pq2, n->off_Q2, n->p.cout, n->H, 0);
+    hipError_t ce = hipMemcpyAsync(n->pq1b, n->theta + n->off_q1, (size_t)n->H * 4, hipMemcpyDeviceToDevice, n->st);
+    if (ce != hipSuccess) return ffail(n, LBM_EDEVICE, hipGetErrorString(ce));
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return ffail(n, LBM_EDEVICE, hipGetErrorString(e));
   return LBM_OK;
@@ -419,6 +477,21 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
   if (alloc_gt(n, n->Gq1, n->W, n->H) != hipSuccess || alloc_gt(n, n->Gq1t, n->H, n->W) != hipSuccess ||
       alloc_gt(n, n->Gq2, n->H, p.cout) != hipSuccess || alloc_gt(n, n->Gq2t, p.cout, n->H) != hipSuccess)
     return bail(LBM_ENOMEM, "operand allocation");
+  {
+    // fused projection: hidden padded to a multiple of 32 (at most 128),
+    // width to a multiple of 32 (at most 64), at most 16 outputs
+    const int Hp = (int)round_up(n->H, 32), Wp = (int)round_up(n->W, 32);
+    n->fused_proj = Hp <= 128 && Wp <= 64 && p.cout <= 16 && P % 256 == 0;
+    if (n->fused_proj) {
+      n->Pq1.K = n->W; n->Pq1.N = n->H; n->Pq1.kp = Wp; n->Pq1.np = Hp;
+      n->Pq2.K = n->H; n->Pq2.N = p.cout; n->Pq2.kp = Hp; n->Pq2.np = 16;
+      if (falloc(n, (void**)&n->Pq1.d, (size_t)Hp * Wp * 2) != hipSuccess ||
+          falloc(n, (void**)&n->Pq2.d, (size_t)16 * Hp * 2) != hipSuccess ||
+          falloc(n, (void**)&n->pq1b, (size_t)Hp * 4) != hipSuccess ||
+          hipMemset(n->pq1b, 0, (size_t)Hp * 4) != hipSuccess)
+        return bail(LBM_ENOMEM, "operand allocation");
+    }
+  }
   // DFT operands
   {
     const int X = n->X, Y = n->Y, Z = n->Z, MZ = n->MZ;
@@ -499,33 +572,35 @@ extern "C" int fno_get_params(fno_net* n, float* host, int64_t count) {
   return LBM_OK;
 }
 
-static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout) {
-  const int64_t W = n->W, P = n->P;
+// training keeps what the backward pass reads: FP32 pre-activations of
+// every Fourier layer and of the projection's hidden layer, and its BF16
+// activations; inference keeps only the BF16 activations of the layers.
+static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout, bool training) {
+  const int64_t W = n->W;
   int rc;
-  dim3 g;
-  // lift: h0 = P x + p (kept in h[0]'s buffer only transiently) -> v0
-  if ((rc = pointwise(n, B, x, true, n->p.cin, n->h[0], false, (int)W, &n->Glift, n->theta + n->off_p, false)))
+  // lift: v0 = P x + p (no activation; the pre-activation is not kept)
+  if ((rc = pointwise(n, B, x, true, n->p.cin, nullptr, false, (int)W, &n->Glift, n->theta + n->off_p, false, false,
+                      n->v[0], false)))
     return rc;
-  elementwise_grid((int64_t)B * W * P, g);
-  hipLaunchKernelGGL(act_kernel, g, dim3(256), 0, n->st, n->h[0], n->v[0], (int64_t)B * W * P, 0);
   for (int l = 0; l < n->L; ++l) {
     if ((rc = forward_dft(n, B, n->v[l], true, n->F1, n->Vh[l]))) return rc;
     hipLaunchKernelGGL((mix_kernel<float, float, 0>), dim3((unsigned)n->M), dim3(64), 0, n->st, n->Vh[l],
                        n->wspec + n->off_W[l], n->Yh, B, (int)W);
     if ((rc = inverse_dft(n, B, n->Yh, n->I1, n->h[l], false))) return rc;
+    // h = R(W T v) + Wp v + bp; v' = GELU(h) (identity after the last layer)
     if ((rc = pointwise(n, B, n->v[l], true, (int)W, n->h[l], false, (int)W, &n->Gwp[l], n->theta + n->off_bp[l],
-                        true)))
+                        true, training, n->v[l + 1], l < n->L - 1)))
       return rc;
-    hipLaunchKernelGGL(act_kernel, g, dim3(256), 0, n->st, n->h[l], n->v[l + 1], (int64_t)B * W * P,
-                       l < n->L - 1 ? 1 : 0);
   }
-  if ((rc = pointwise(n, B, n->v[n->L], true, (int)W, n->h1, false, n->H, &n->Gq1, n->theta + n->off_q1, false)))
-    return rc;
-  dim3 g1;
-  elementwise_grid((int64_t)B * n->H * P, g1);
-  hipLaunchKernelGGL(act_kernel, g1, dim3(256), 0, n->st, n->h1, n->a, (int64_t)B * n->H * P, 1);
-  if ((rc = pointwise(n, B, n->a, true, n->H, yout, false, n->p.cout, &n->Gq2, n->theta + n->off_q2, false)))
-    return rc;
+  if (!training && n->fused_proj) {
+    fused_projection(n, B, n->v[n->L], yout);
+  } else {
+    if ((rc = pointwise(n, B, n->v[n->L], true, (int)W, n->h1, false, n->H, &n->Gq1, n->theta + n->off_q1, false,
+                        true, n->a, true)))
+      return rc;
+    if ((rc = pointwise(n, B, n->a, true, n->H, yout, false, n->p.cout, &n->Gq2, n->theta + n->off_q2, false)))
+      return rc;
+  }
   n->lastB = B;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return ffail(n, LBM_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
@@ -535,14 +610,14 @@ static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout) {
 extern "C" int fno_forward(fno_net* n, const uint16_t* x, int32_t B, float* y) {
   if (!n || !x || !y) return ffail(n, LBM_EINVAL, "null argument");
   if (B <= 0 || B > n->p.max_batch) return ffail(n, LBM_EINVAL, "batch out of range");
-  return forward_impl(n, x, B, y);
+  return forward_impl(n, x, B, y, false);
 }
 
 extern "C" int fno_loss_grad(fno_net* n, const uint16_t* x, const float* target, const uint8_t* mask, int32_t B,
                              float* loss, float* host_grads) {
   if (!n || !x || !target || !mask) return ffail(n, LBM_EINVAL, "null argument");
   if (B <= 0 || B > n->p.max_batch) return ffail(n, LBM_EINVAL, "batch out of range");
-  int rc = forward_impl(n, x, B, n->y);
+  int rc = forward_impl(n, x, B, n->y, true);
   if (rc) return rc;
   const int64_t W = n->W, P = n->P, cout = n->p.cout;
   // mask cell count (host copy of the mask is not needed: count on device via

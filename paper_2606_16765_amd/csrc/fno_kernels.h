@@ -43,93 +43,246 @@ __device__ __forceinline__ f32x4 mfma16(const bf16x8& a, const bf16x8& b, const 
 //   out address = (j >> lgI) * out_so + (j & (I-1)) * out_si
 //                 + (n >> lgnd) * out_sn1 + (n & (nd-1)) * out_sn2
 // and G given transposed, gt[n][k] (BF16, row length kp, zero padded to
-// kp >= K rounded up to 32 and to a multiple of 64 rows).
+// kp >= K rounded up to 32 and to np, a multiple of 64 rows).
+// Epilogue: the value is stored to out when store_out is set, and its
+// activation (GELU or identity) is stored as BF16 to act at the same
+// address when act is not null.
 struct ContractArgs {
   const void* in;
   void* out;
   const uint16_t* gt;
   const float* bias;
+  uint16_t* act;
   int64_t cols;
   int32_t lgI;
   int64_t in_so, in_si, in_sk1, in_sk2;
   int32_t lgkd;
   int64_t out_so, out_si, out_sn1, out_sn2;
   int32_t lgnd;
-  int32_t K, N, kp;
+  int32_t K, N, kp, np;
   float alpha;
   int32_t accumulate;
-  int32_t kcontig;  // 1: k runs of 32 are contiguous in memory (load along k)
+  int32_t store_out;
+  int32_t act_gelu;
 };
 
-constexpr int CT_N = 64;   // rows n per block (4 waves x 16)
+constexpr int CT_N = 64;   // rows n per block pass (4 waves x 16)
 constexpr int CT_J = 64;   // columns per block
 constexpr int CT_K = 32;   // k per step (one MFMA)
 constexpr int LDS_KP = 40; // padded k stride of the LDS tile
 
-template <typename InT, typename OutT>
+// Load modes of the 64-column x 32-k input tile (LDS layout [column][k]):
+//  LOAD_SCALAR  any index map, one element per load;
+//  LOAD_KRUN    k contiguous (lgkd = 0, in_sk1 = 1), K % 8 == 0, column
+//               bases 8-element aligned: 8 consecutive k per load;
+//  LOAD_JRUN    columns contiguous (in_si = 1) in runs of 8 (I % 8 == 0,
+//               cols % 8 == 0), k offsets 8-element aligned: 8 consecutive
+//               columns per load, transposed into LDS.
+enum { LOAD_SCALAR = 0, LOAD_KRUN = 1, LOAD_JRUN = 2 };
+
+template <typename T> struct Vec8;
+template <> struct Vec8<uint16_t> {
+  static __device__ __forceinline__ void load(const uint16_t* p, uint16_t (&o)[8]) {
+    const uint4 v = *(const uint4*)p;
+    o[0] = v.x & 0xffff; o[1] = v.x >> 16; o[2] = v.y & 0xffff; o[3] = v.y >> 16;
+    o[4] = v.z & 0xffff; o[5] = v.z >> 16; o[6] = v.w & 0xffff; o[7] = v.w >> 16;
+  }
+};
+template <> struct Vec8<float> {
+  static __device__ __forceinline__ void load(const float* p, uint16_t (&o)[8]) {
+    const float4 a = *(const float4*)p, b = *(const float4*)(p + 4);
+    o[0] = f2bf(a.x); o[1] = f2bf(a.y); o[2] = f2bf(a.z); o[3] = f2bf(a.w);
+    o[4] = f2bf(b.x); o[5] = f2bf(b.y); o[6] = f2bf(b.z); o[7] = f2bf(b.w);
+  }
+};
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+template <typename InT, typename OutT, int LM>
 __global__ __launch_bounds__(256) void contract_kernel(ContractArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t tile[CT_J * LDS_KP];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t j0 = (int64_t)blockIdx.x * CT_J;
-  const int n0 = blockIdx.y * CT_N;
   const InT* in = (const InT*)a.in;
   const int64_t Imask = ((int64_t)1 << a.lgI) - 1;
   const int kdmask = (1 << a.lgkd) - 1;
   auto colbase = [&](int64_t j) { return (j >> a.lgI) * a.in_so + (j & Imask) * a.in_si; };
   auto kaddr = [&](int k) { return (int64_t)(k >> a.lgkd) * a.in_sk1 + (int64_t)(k & kdmask) * a.in_sk2; };
 
-  // per-thread load coordinates (one element per instruction, 8 per step)
+  // per-thread tile coordinates
   int lk[8], lj[8];
   int64_t cb[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    if (a.kcontig) { lk[q] = t & 31; lj[q] = (t >> 5) + 8 * q; }
-    else { lj[q] = t & 63; lk[q] = (t >> 6) * 8 + q; }
-    const int64_t j = j0 + lj[q];
-    cb[q] = j < a.cols ? colbase(j) : -1;
-  }
-
-  f32x4 acc[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int arow = n0 + wave * 16 + (lane & 15);
-  const int akk = 8 * (lane >> 4);
-
-  for (int k0 = 0; k0 < a.K; k0 += CT_K) {
+  if (LM == LOAD_SCALAR) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int k = k0 + lk[q];
-      uint16_t v = 0;
-      if (cb[q] >= 0 && k < a.K) v = to_bf(in[cb[q] + kaddr(k)]);
-      tile[lj[q] * LDS_KP + lk[q]] = v;
+      lj[q] = t & 63;
+      lk[q] = (t >> 6) * 8 + q;
+      const int64_t j = j0 + lj[q];
+      cb[q] = j < a.cols ? colbase(j) : -1;
     }
-    __syncthreads();
-    // A: rows of G^T (zero padded beyond N and K)
-    const bf16x8 av = *(const bf16x8*)(a.gt + (int64_t)arow * a.kp + k0 + akk);
+  } else if (LM == LOAD_KRUN) {
+    lj[0] = t >> 2;
+    lk[0] = (t & 3) * 8;
+    cb[0] = j0 + lj[0] < a.cols ? colbase(j0 + lj[0]) : -1;
+  } else {
+    lk[0] = t >> 3;
+    lj[0] = (t & 7) * 8;
+    cb[0] = j0 + lj[0] < a.cols ? colbase(j0 + lj[0]) : -1;
+  }
+  auto load_tile = [&](int k0) {
+    if (LM == LOAD_SCALAR) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const bf16x8 bv = *(const bf16x8*)(tile + (c * 16 + (lane & 15)) * LDS_KP + akk);
-      acc[c] = mfma16(av, bv, acc[c]);
+      for (int q = 0; q < 8; ++q) {
+        const int k = k0 + lk[q];
+        uint16_t v = 0;
+        if (cb[q] >= 0 && k < a.K) v = to_bf(in[cb[q] + kaddr(k)]);
+        tile[lj[q] * LDS_KP + lk[q]] = v;
+      }
+    } else if (LM == LOAD_KRUN) {
+      uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      const int k = k0 + lk[0];
+      if (cb[0] >= 0 && k < a.K) Vec8<InT>::load(in + cb[0] + k, v);
+      uint4 w;
+      w.x = v[0] | ((uint32_t)v[1] << 16); w.y = v[2] | ((uint32_t)v[3] << 16);
+      w.z = v[4] | ((uint32_t)v[5] << 16); w.w = v[6] | ((uint32_t)v[7] << 16);
+      *(uint4*)(tile + lj[0] * LDS_KP + lk[0]) = w;
+    } else {
+      uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      const int k = k0 + lk[0];
+      if (cb[0] >= 0 && k < a.K) Vec8<InT>::load(in + cb[0] + kaddr(k), v);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) tile[(lj[0] + q) * LDS_KP + lk[0]] = v[q];
     }
+  };
+
+  const bool single_k = a.K <= CT_K;
+  if (single_k) {
+    load_tile(0);
     __syncthreads();
   }
+  const int akk = 8 * (lane >> 4);
   OutT* out = (OutT*)a.out;
-  const int64_t Om = ((int64_t)1 << a.lgI) - 1;
   const int ndm = (1 << a.lgnd) - 1;
+  const int nblocks = a.np / CT_N;
+  for (int nb = blockIdx.y; nb < nblocks; nb += gridDim.y) {
+    const int n0 = nb * CT_N;
+    f32x4 acc[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int64_t j = j0 + c * 16 + (lane & 15);
-    if (j >= a.cols) continue;
-    const int64_t ob = (j >> a.lgI) * a.out_so + (j & Om) * a.out_si;
+    for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int arow = n0 + wave * 16 + (lane & 15);
+    for (int k0 = 0; k0 < a.K; k0 += CT_K) {
+      if (!single_k) {
+        load_tile(k0);
+        __syncthreads();
+      }
+      // A: rows of G^T (zero padded beyond N and K)
+      const bf16x8 av = *(const bf16x8*)(a.gt + (int64_t)arow * a.kp + k0 + akk);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const bf16x8 bv = *(const bf16x8*)(tile + (c * 16 + (lane & 15)) * LDS_KP + akk);
+        acc[c] = mfma16(av, bv, acc[c]);
+      }
+      if (!single_k) __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int64_t j = j0 + c * 16 + (lane & 15);
+      if (j >= a.cols) continue;
+      const int64_t ob = (j >> a.lgI) * a.out_so + (j & Imask) * a.out_si;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = n0 + wave * 16 + 4 * (lane >> 4) + r;
+        if (n >= a.N) continue;
+        const int64_t addr = ob + (int64_t)(n >> a.lgnd) * a.out_sn1 + (int64_t)(n & ndm) * a.out_sn2;
+        float v = a.alpha * acc[c][r];
+        if (a.bias) v += a.bias[n];
+        if (a.accumulate) v += to_f(out[addr]);
+        if (a.store_out) out[addr] = from_f<OutT>(v);
+        if (a.act) a.act[addr] = f2bf(a.act_gelu ? gelu(v) : v);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- projection
+// Fused projection (inference): for every point of v [B][W][P] (BF16)
+//   y[b][o][p] = q2[o] + sum_h Q2[o][h] bf16(GELU(q1[h] + sum_c Q1[h][c] v[b][c][p]))
+// BF16 operands, FP32 accumulation; the GELU output is rounded to BF16 as
+// the unfused path stores it.  Q1p [16 NT][32 KS] and Q2p [16][16 NT] are
+// BF16 and zero padded, q1p [16 NT] FP32 zero padded (NT even).  A block
+// covers 256 consecutive points of one sample (P % 256 == 0); each wave 64
+// points as four 16-point MFMA column tiles.  The hidden accumulators feed
+// the second contraction directly: for its k-step s, lane group g supplies
+// k slots 8g..8g+7 holding hidden rows 32s + 4g + {0..3} (tile 2s) and
+// 32s + 16 + 4g + {0..3} (tile 2s+1), and the Q2 operand is gathered with
+// the same assignment, so the sum runs over every hidden row once.
+template <int NT, int KS>
+__global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ v, int W, int64_t P,
+                                                   const uint16_t* __restrict__ Q1p, const float* __restrict__ q1p,
+                                                   const uint16_t* __restrict__ Q2p, const float* __restrict__ q2,
+                                                   int cout, float* __restrict__ y) {
+  constexpr int WP = 32 * KS, VS = WP + 8, HP = 16 * NT;
+  __shared__ __attribute__((aligned(16))) uint16_t vt[256 * VS];
+  __shared__ __attribute__((aligned(16))) uint16_t q1s[HP * WP];
+  __shared__ __attribute__((aligned(16))) uint16_t q2s[16 * HP];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4;
+  const int64_t j0 = (int64_t)blockIdx.x * 256;
+  const int64_t b = j0 / P, p0 = j0 % P;
+  // operands into LDS
+  for (int e = t * 8; e < HP * WP; e += 256 * 8) *(uint4*)(q1s + e) = *(const uint4*)(Q1p + e);
+  for (int e = t * 8; e < 16 * HP; e += 256 * 8) *(uint4*)(q2s + e) = *(const uint4*)(Q2p + e);
+  // v tile, transposed to [point][channel]
+  for (int idx = t; idx < WP * 32; idx += 256) {
+    const int c = idx >> 5, g8 = (idx & 31) * 8;
+    uint16_t val[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (c < W) Vec8<uint16_t>::load(v + (b * W + c) * P + p0 + g8, val);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) vt[(g8 + i) * VS + c] = val[i];
+  }
+  __syncthreads();
+  // second-stage A operand (Q2 rows o = lane % 16), gathered once
+  bf16x8 a2[NT / 2];
+#pragma unroll
+  for (int s = 0; s < NT / 2; ++s)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int h = 32 * s + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
+      a2[s][j] = __builtin_bit_cast(__bf16, q2s[(lane & 15) * HP + h]);
+    }
+  for (int ct = 0; ct < 4; ++ct) {
+    const int pt = wave * 64 + ct * 16 + (lane & 15);
+    f32x4 acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const bf16x8 bv = *(const bf16x8*)(vt + pt * VS + ks * 32 + 8 * g);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const bf16x8 av = *(const bf16x8*)(q1s + (nt * 16 + (lane & 15)) * WP + ks * 32 + 8 * g);
+        acc[nt] = mfma16(av, bv, acc[nt]);
+      }
+    }
+    f32x4 out = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < NT / 2; ++s) {
+      bf16x8 bv;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int nt = 2 * s + (j >> 2), r = j & 3;
+        const float h = acc[nt][r] + q1p[nt * 16 + 4 * g + r];
+        bv[j] = __builtin_bit_cast(__bf16, f2bf(gelu(h)));
+      }
+      out = mfma16(a2[s], bv, out);
+    }
+    const int64_t p = p0 + wave * 64 + ct * 16 + (lane & 15);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int n = n0 + wave * 16 + 4 * (lane >> 4) + r;
-      if (n >= a.N) continue;
-      const int64_t addr = ob + (int64_t)(n >> a.lgnd) * a.out_sn1 + (int64_t)(n & ndm) * a.out_sn2;
-      float v = a.alpha * acc[c][r];
-      if (a.bias) v += a.bias[n];
-      if (a.accumulate) v += to_f(out[addr]);
-      out[addr] = from_f<OutT>(v);
+      const int o = 4 * g + r;
+      if (o < cout) y[(b * cout + o) * P + p] = out[r] + q2[o];
     }
   }
 }
@@ -292,19 +445,6 @@ __global__ __launch_bounds__(256) void colsum_kernel(const float* X, int A, int6
 }
 
 // ------------------------------------------------------------- elementwise
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_grad(float x) {
-  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
-}
-
-// v = bf16(act(h)), act = GELU or identity
-__global__ __launch_bounds__(256) void act_kernel(const float* h, uint16_t* v, int64_t n, int use_gelu) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const float x = h[i];
-  v[i] = f2bf(use_gelu ? gelu(x) : x);
-}
-
 // g *= GELU'(h)
 __global__ __launch_bounds__(256) void gelu_bwd_kernel(float* g, const float* h, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;

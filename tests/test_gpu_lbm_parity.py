@@ -90,6 +90,23 @@ def test_obstacle_channel_f64(mode, obstacle_bc):
     assert np.abs(fg - fo).max() < 1e-11 * np.abs(fo).max()
 
 
+def test_precision_study_reference_f64_at_128x64x64():
+    """The FP64 storage path that serves as the reference of the FP32/FP16/
+    BF16 error study agrees with the oracle at the study's size: the seeded
+    random obstacle at 128x64x64, interpolated bounce-back, K17 (Re 10000 on
+    the channel height), 60 steps."""
+    from inputs import random_obstacle
+    shape = (128, 64, 64)
+    geo = random_obstacle(shape, 0)
+    u0 = perturbation(shape, 0, 5e-4, geo.solid)
+    nu = 0.05 * 64 / 10000.0
+    g, o = pair(shape, 60, solid=geo.solid, links=geo.links, u0=u0, nu=nu, mode="k17", obstacle_bc=1)
+    err = f64_err(g.populations(), o.fbar)
+    assert err < 1e-11, err
+    m, n = g.mean_fields()
+    assert rel_max(m, o.mean_fields()) < 1e-11
+
+
 def test_poiseuille_body_force_f64():
     shape = (64, 16, 1)
     g, o = pair(shape, 300, periodic=(1, 0, 1), nu=0.1, u_in=0.0, body_force=(1e-6, 0, 0))
