@@ -182,11 +182,18 @@ struct CSpec {
   bool act_gelu = false;
 };
 
+template <typename InT, typename OutT, int LM>
+static void launch_contract_ep(const ContractArgs& a, int ep, dim3 grid, hipStream_t st) {
+  if (ep == EP_NFAST) hipLaunchKernelGGL((contract_kernel<InT, OutT, LM, EP_NFAST>), grid, dim3(256), 0, st, a);
+  else if (ep == EP_JFAST) hipLaunchKernelGGL((contract_kernel<InT, OutT, LM, EP_JFAST>), grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((contract_kernel<InT, OutT, LM, EP_DIRECT>), grid, dim3(256), 0, st, a);
+}
+
 template <typename InT, typename OutT>
-static void launch_contract(const ContractArgs& a, int lm, dim3 grid, hipStream_t st) {
-  if (lm == LOAD_KRUN) hipLaunchKernelGGL((contract_kernel<InT, OutT, LOAD_KRUN>), grid, dim3(256), 0, st, a);
-  else if (lm == LOAD_JRUN) hipLaunchKernelGGL((contract_kernel<InT, OutT, LOAD_JRUN>), grid, dim3(256), 0, st, a);
-  else hipLaunchKernelGGL((contract_kernel<InT, OutT, LOAD_SCALAR>), grid, dim3(256), 0, st, a);
+static void launch_contract(const ContractArgs& a, int lm, int ep, dim3 grid, hipStream_t st) {
+  if (lm == LOAD_KRUN) launch_contract_ep<InT, OutT, LOAD_KRUN>(a, ep, grid, st);
+  else if (lm == LOAD_JRUN) launch_contract_ep<InT, OutT, LOAD_JRUN>(a, ep, grid, st);
+  else launch_contract_ep<InT, OutT, LOAD_SCALAR>(a, ep, grid, st);
 }
 
 static int contract(fno_net* n, const CSpec& c) {
@@ -218,12 +225,17 @@ static int contract(fno_net* n, const CSpec& c) {
   else if (!c.kcontig && c.in_si == 1 && c.I % 8 == 0 && c.cols % 8 == 0 && base_ok && c.in_sk1 % 8 == 0 &&
            (c.kd == 1 || c.in_sk2 % 8 == 0))
     lm = LOAD_JRUN;
+  // outputs contiguous along n or along (runs of at least 16) columns: store
+  // through the LDS-staged epilogue in that order
+  int ep = EP_DIRECT;
+  if (c.nd == 1 && c.out_sn1 == 1) ep = EP_NFAST;
+  else if (c.out_si == 1 && c.I >= 16) ep = EP_JFAST;
   const int nblocks = c.g->np / CT_N;
-  const dim3 grid((unsigned)((c.cols + CT_J - 1) / CT_J), (unsigned)(a.K <= CT_K ? 1 : nblocks));
-  if (c.in_bf16 && c.out_bf16) launch_contract<uint16_t, uint16_t>(a, lm, grid, n->st);
-  else if (c.in_bf16) launch_contract<uint16_t, float>(a, lm, grid, n->st);
-  else if (c.out_bf16) launch_contract<float, uint16_t>(a, lm, grid, n->st);
-  else launch_contract<float, float>(a, lm, grid, n->st);
+  const dim3 grid((unsigned)((c.cols + CT_J - 1) / CT_J), (unsigned)(a.K <= CT_KT ? 1 : nblocks));
+  if (c.in_bf16 && c.out_bf16) launch_contract<uint16_t, uint16_t>(a, lm, ep, grid, n->st);
+  else if (c.in_bf16) launch_contract<uint16_t, float>(a, lm, ep, grid, n->st);
+  else if (c.out_bf16) launch_contract<float, uint16_t>(a, lm, ep, grid, n->st);
+  else launch_contract<float, float>(a, lm, ep, grid, n->st);
   return LBM_OK;
 }
 
@@ -241,6 +253,21 @@ static int pointwise(fno_net* n, int B, const void* in, bool in_bf16, int cin, v
   c.out_so = (int64_t)g->N * n->P; c.out_si = 1; c.out_sn1 = n->P; c.out_sn2 = 0; c.nd = 1;
   c.alpha = 1.f; c.accumulate = accumulate; c.bias = bias; c.kcontig = false;
   c.store_out = store_out; c.act = act; c.act_gelu = act_gelu;
+  // the dedicated channel-map kernel needs 256-point blocks within a sample
+  // and 8-element aligned rows
+  const size_t esz = in_bf16 ? 2 : 4;
+  if (!out_bf16 && n->P % PW_J == 0 && ((uintptr_t)in % (8 * esz)) == 0 && ((uintptr_t)out % 16) == 0 &&
+      ((uintptr_t)act % 16) == 0) {
+    if ((accumulate || store_out) && !out) return ffail(n, LBM_EINVAL, "channel map output missing");
+    PwArgs a{};
+    a.in = in; a.out = (float*)out; a.gt = g->d; a.bias = bias; a.act = act; a.P = n->P;
+    a.K = g->K; a.N = g->N; a.kp = g->kp; a.alpha = 1.f;
+    a.accumulate = accumulate ? 1 : 0; a.store_out = store_out ? 1 : 0; a.act_gelu = act_gelu ? 1 : 0;
+    const dim3 grid((unsigned)((int64_t)B * n->P / PW_J));
+    if (in_bf16) hipLaunchKernelGGL(pw_kernel<uint16_t>, grid, dim3(256), 0, n->st, a);
+    else hipLaunchKernelGGL(pw_kernel<float>, grid, dim3(256), 0, n->st, a);
+    return LBM_OK;
+  }
   return contract(n, c);
 }
 

@@ -101,9 +101,20 @@ __device__ __forceinline__ float gelu_grad(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
 }
 
-template <typename InT, typename OutT, int LM>
+// Epilogue modes: EP_DIRECT stores from the MFMA layout (each lane owns 16
+// outputs); EP_NFAST and EP_JFAST stage the 64 x 64 result tile in LDS and
+// store it with consecutive threads on consecutive n (outputs contiguous
+// along n) or on consecutive columns (outputs contiguous along columns).
+enum { EP_DIRECT = 0, EP_NFAST = 1, EP_JFAST = 2 };
+
+constexpr int CT_KT = 64;            // k held in LDS per pass (two MFMA steps)
+constexpr int CT_TS = CT_KT + 8;     // padded LDS row of the input tile
+constexpr int CT_DS = CT_J + 1;      // padded LDS row of the result tile
+
+template <typename InT, typename OutT, int LM, int EP>
 __global__ __launch_bounds__(256) void contract_kernel(ContractArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t tile[CT_J * LDS_KP];
+  __shared__ __attribute__((aligned(16))) uint16_t tile[CT_J * CT_TS];
+  __shared__ float dst[EP == EP_DIRECT ? 1 : CT_N * CT_DS];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t j0 = (int64_t)blockIdx.x * CT_J;
   const InT* in = (const InT*)a.in;
@@ -112,7 +123,7 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs a) {
   auto colbase = [&](int64_t j) { return (j >> a.lgI) * a.in_so + (j & Imask) * a.in_si; };
   auto kaddr = [&](int k) { return (int64_t)(k >> a.lgkd) * a.in_sk1 + (int64_t)(k & kdmask) * a.in_sk2; };
 
-  // per-thread tile coordinates
+  // per-thread tile coordinates (one 32-k half of the tile per load pass)
   int lk[8], lj[8];
   int64_t cb[8];
   if (LM == LOAD_SCALAR) {
@@ -132,14 +143,15 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs a) {
     lj[0] = (t & 7) * 8;
     cb[0] = j0 + lj[0] < a.cols ? colbase(j0 + lj[0]) : -1;
   }
-  auto load_tile = [&](int k0) {
+  // load k in [k0, k0 + 32) into tile columns [h * 32, h * 32 + 32)
+  auto load_half = [&](int k0, int h) {
     if (LM == LOAD_SCALAR) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int k = k0 + lk[q];
         uint16_t v = 0;
         if (cb[q] >= 0 && k < a.K) v = to_bf(in[cb[q] + kaddr(k)]);
-        tile[lj[q] * LDS_KP + lk[q]] = v;
+        tile[lj[q] * CT_TS + h * 32 + lk[q]] = v;
       }
     } else if (LM == LOAD_KRUN) {
       uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -148,19 +160,21 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs a) {
       uint4 w;
       w.x = v[0] | ((uint32_t)v[1] << 16); w.y = v[2] | ((uint32_t)v[3] << 16);
       w.z = v[4] | ((uint32_t)v[5] << 16); w.w = v[6] | ((uint32_t)v[7] << 16);
-      *(uint4*)(tile + lj[0] * LDS_KP + lk[0]) = w;
+      *(uint4*)(tile + lj[0] * CT_TS + h * 32 + lk[0]) = w;
     } else {
       uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       const int k = k0 + lk[0];
       if (cb[0] >= 0 && k < a.K) Vec8<InT>::load(in + cb[0] + kaddr(k), v);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) tile[(lj[0] + q) * LDS_KP + lk[0]] = v[q];
+      for (int q = 0; q < 8; ++q) tile[(lj[0] + q) * CT_TS + h * 32 + lk[0]] = v[q];
     }
   };
 
-  const bool single_k = a.K <= CT_K;
-  if (single_k) {
-    load_tile(0);
+  // K <= 64: the whole input tile stays in LDS for every n-block
+  const bool resident = a.K <= CT_KT;
+  if (resident) {
+    load_half(0, 0);
+    if (a.K > CT_K) load_half(CT_K, 1);
     __syncthreads();
   }
   const int akk = 8 * (lane >> 4);
@@ -173,37 +187,171 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs a) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int arow = n0 + wave * 16 + (lane & 15);
-    for (int k0 = 0; k0 < a.K; k0 += CT_K) {
-      if (!single_k) {
-        load_tile(k0);
+    for (int k0 = 0; k0 < a.K; k0 += CT_KT) {
+      if (!resident) {
+        load_half(k0, 0);
+        if (k0 + CT_K < a.K) load_half(k0 + CT_K, 1);
         __syncthreads();
       }
-      // A: rows of G^T (zero padded beyond N and K)
-      const bf16x8 av = *(const bf16x8*)(a.gt + (int64_t)arow * a.kp + k0 + akk);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (k0 + h * CT_K >= a.K) break;
+        // A: rows of G^T (zero padded beyond N and K)
+        const bf16x8 av = *(const bf16x8*)(a.gt + (int64_t)arow * a.kp + k0 + h * CT_K + akk);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const bf16x8 bv = *(const bf16x8*)(tile + (c * 16 + (lane & 15)) * CT_TS + h * 32 + akk);
+          acc[c] = mfma16(av, bv, acc[c]);
+        }
+      }
+      if (!resident) __syncthreads();
+    }
+    auto finish = [&](int n, int64_t j, float v) {
+      const int64_t addr = (j >> a.lgI) * a.out_so + (j & Imask) * a.out_si + (int64_t)(n >> a.lgnd) * a.out_sn1 +
+                           (int64_t)(n & ndm) * a.out_sn2;
+      if (a.bias) v += a.bias[n];
+      if (a.accumulate) v += to_f(out[addr]);
+      if (a.store_out) out[addr] = from_f<OutT>(v);
+      if (a.act) a.act[addr] = f2bf(a.act_gelu ? gelu(v) : v);
+    };
+    if (EP == EP_DIRECT) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const bf16x8 bv = *(const bf16x8*)(tile + (c * 16 + (lane & 15)) * LDS_KP + akk);
-        acc[c] = mfma16(av, bv, acc[c]);
+        const int64_t j = j0 + c * 16 + (lane & 15);
+        if (j >= a.cols) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int n = n0 + wave * 16 + 4 * (lane >> 4) + r;
+          if (n < a.N) finish(n, j, a.alpha * acc[c][r]);
+        }
       }
-      if (!single_k) __syncthreads();
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          dst[(wave * 16 + 4 * (lane >> 4) + r) * CT_DS + c * 16 + (lane & 15)] = a.alpha * acc[c][r];
+      __syncthreads();
+#pragma unroll 4
+      for (int e = t; e < CT_N * CT_J; e += 256) {
+        const int nl = EP == EP_NFAST ? (e & 63) : (e >> 6);
+        const int jl = EP == EP_NFAST ? (e >> 6) : (e & 63);
+        const int n = n0 + nl;
+        const int64_t j = j0 + jl;
+        if (n < a.N && j < a.cols) finish(n, j, dst[nl * CT_DS + jl]);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------- channel maps
+// Pointwise channel map over points p of [B][K][P] activations:
+//   out[b][n][p] = alpha * sum_k G[k][n] in[b][k][p] (+ bias[n]) (+ out)
+// with the same epilogue as contract_kernel (store_out, BF16 activation).
+// A block covers 256 consecutive points of one sample (P % 256 == 0) so
+// that every row it touches is a 512 B (BF16) or 1 KB (FP32) run; rows n
+// are done 32 at a time, k 32 at a time.
+struct PwArgs {
+  const void* in;
+  float* out;
+  const uint16_t* gt;  // [np][kp] BF16, G transposed, zero padded
+  const float* bias;
+  uint16_t* act;
+  int64_t P;
+  int32_t K, N, kp;
+  float alpha;
+  int32_t accumulate, store_out, act_gelu;
+};
+
+constexpr int PW_J = 256;        // points per block
+constexpr int PW_TS = 40;        // padded LDS row (32 k)
+constexpr int PW_DS = PW_J + 4;  // padded LDS row of the result tile
+
+template <typename InT>
+__global__ __launch_bounds__(256) void pw_kernel(PwArgs a) {
+  // one LDS buffer: the input tile during the products, then the result
+  // tile for the epilogue (33 KB: four blocks per CU)
+  __shared__ __attribute__((aligned(16))) float lds[32 * PW_DS];
+  uint16_t* tile = (uint16_t*)lds;
+  float* dst = lds;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4;
+  const int64_t j0 = (int64_t)blockIdx.x * PW_J;
+  const int64_t b = j0 / a.P, p0 = j0 % a.P;
+  const InT* in = (const InT*)a.in + b * a.K * a.P + p0;
+  const int nkt = (a.K + 31) / 32;
+  // 256 points x 32 k: thread loads 8 consecutive points of one k, 4 times
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = q * 256 + t;
+      const int kl = idx >> 5, pl = (idx & 31) * 8;
+      uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (k0 + kl < a.K) Vec8<InT>::load(in + (int64_t)(k0 + kl) * a.P + pl, v);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) tile[(pl + i) * PW_TS + kl] = v[i];
+    }
+  };
+  float* out = a.out ? a.out + b * a.N * a.P + p0 : nullptr;
+  uint16_t* act = a.act ? a.act + b * a.N * a.P + p0 : nullptr;
+  for (int n0 = 0; n0 < a.N; n0 += 32) {
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[h][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kt = 0; kt < nkt; ++kt) {
+      load(kt * 32);
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bf16x8 av = *(const bf16x8*)(a.gt + (int64_t)(n0 + h * 16 + (lane & 15)) * a.kp + kt * 32 + 8 * g);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const bf16x8 bv = *(const bf16x8*)(tile + (wave * 64 + c * 16 + (lane & 15)) * PW_TS + 8 * g);
+          acc[h][c] = mfma16(av, bv, acc[h][c]);
+        }
+      }
+      __syncthreads();
     }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int64_t j = j0 + c * 16 + (lane & 15);
-      if (j >= a.cols) continue;
-      const int64_t ob = (j >> a.lgI) * a.out_so + (j & Imask) * a.out_si;
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int n = n0 + wave * 16 + 4 * (lane >> 4) + r;
-        if (n >= a.N) continue;
-        const int64_t addr = ob + (int64_t)(n >> a.lgnd) * a.out_sn1 + (int64_t)(n & ndm) * a.out_sn2;
-        float v = a.alpha * acc[c][r];
-        if (a.bias) v += a.bias[n];
-        if (a.accumulate) v += to_f(out[addr]);
-        if (a.store_out) out[addr] = from_f<OutT>(v);
-        if (a.act) a.act[addr] = f2bf(a.act_gelu ? gelu(v) : v);
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          dst[(h * 16 + 4 * g + r) * PW_DS + wave * 64 + c * 16 + (lane & 15)] = a.alpha * acc[h][c][r];
+    __syncthreads();
+    // 32 rows x 64 float4: a wave stores one contiguous row per step
+#pragma unroll 2
+    for (int e = t; e < 32 * 64; e += 256) {
+      const int nl = e >> 6, p4 = (e & 63) * 4;
+      const int n = n0 + nl;
+      if (n >= a.N) continue;
+      float4 v = *(const float4*)(dst + nl * PW_DS + p4);
+      const int64_t off = (int64_t)n * a.P + p4;
+      if (a.bias) {
+        const float bb = a.bias[n];
+        v.x += bb; v.y += bb; v.z += bb; v.w += bb;
+      }
+      if (a.accumulate) {
+        const float4 o = *(const float4*)(out + off);
+        v.x += o.x; v.y += o.y; v.z += o.z; v.w += o.w;
+      }
+      if (a.store_out) *(float4*)(out + off) = v;
+      if (act) {
+        uint2 w;
+        if (a.act_gelu) {
+          w.x = f2bf(gelu(v.x)) | ((uint32_t)f2bf(gelu(v.y)) << 16);
+          w.y = f2bf(gelu(v.z)) | ((uint32_t)f2bf(gelu(v.w)) << 16);
+        } else {
+          w.x = f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
+          w.y = f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16);
+        }
+        *(uint2*)(act + off) = w;
       }
     }
+    __syncthreads();
   }
 }
 
