@@ -57,6 +57,7 @@ struct StepArgs {
   int32_t tiles_x, tiles_y; // tile grid
   int32_t ntiles;
   int32_t remap;            // XCD-contiguous tile order
+  int32_t obox[6];          // tile box (x0, x1, y0, y1, z0, z1) around the obstacle
   uint64_t perturb_seed;    // device-generated initial perturbation
   double perturb_amp;
 };
@@ -342,6 +343,9 @@ __device__ __forceinline__ void cell_update(const StepArgs& a, const Coef<typena
 #ifndef MLBM_WAVES
 #define MLBM_WAVES 4
 #endif
+#ifndef MLBM_EDGE_PATH
+#define MLBM_EDGE_PATH 1
+#endif
 template <typename S, bool ODD, int MODE>
 __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(MLBM_WAVES, 8))) void lbm_step_kernel(
     StepArgs a, Coef<typename Storage<S>::T> k) {
@@ -353,10 +357,21 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(MLBM_W
   const int z = rest / a.tiles_y;
   const int x = txi * TX + tx, y = tyi * TY + ty;
   const int64_t n = ((int64_t)z * a.ny + y) * a.nx + x;
-  const uint8_t fl = a.flag[n];
 
   double fx = 0.0, fy = 0.0, fz = 0.0;
-  if (fl != 2) {
+  // Tiles away from the walls, periodic faces and the obstacle's box hold
+  // only fluid cells: they skip the cell flags, so their population loads
+  // do not wait for a flag load.
+  const bool plain_tile = z > 0 && z < a.nz - 1 && tyi > 0 && tyi < a.tiles_y - 1 &&
+                          !(a.per[0] && (txi == 0 || txi == a.tiles_x - 1)) &&
+                          !(txi >= a.obox[0] && txi <= a.obox[1] && tyi >= a.obox[2] && tyi <= a.obox[3] &&
+                            z >= a.obox[4] && z <= a.obox[5]);
+  if (plain_tile) {
+    if (!a.per[0] && (txi == 0 || txi == a.tiles_x - 1))
+      cell_update<S, ODD, MODE, MLBM_EDGE_PATH>(a, k, x, y, z, n, 0, fx, fy, fz);
+    else
+      cell_update<S, ODD, MODE, 0>(a, k, x, y, z, n, 0, fx, fy, fz);
+  } else if (const uint8_t fl = a.flag[n]; fl != 2) {
     // periodic axes wrap at their faces and walls bounce back: both take
     // the general path; the inlet and outlet columns take the edge path
     const bool xin = a.per[0] ? (x > 0 && x < a.nx - 1) : true;
@@ -869,10 +884,14 @@ extern "C" int lbm_create(const lbm_params* pin, const uint8_t* solid, int64_t n
   // ---- obstacle tables from the solid mask (authoritative) ----
   std::vector<uint64_t> pairs;  // (cell << 5) | j : cell + c_j is obstacle
   double fc[3] = {0, 0, 0};
+  int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {-1, -1, -1};  // solid-cell box
   if (solid) {
     for (int64_t n = 0; n < N; ++n) {
       if (!solid[n]) continue;
       const int x = (int)(n % p.nx), y = (int)((n / p.nx) % p.ny), z = (int)(n / ((int64_t)p.nx * p.ny));
+      lo[0] = std::min(lo[0], x); hi[0] = std::max(hi[0], x);
+      lo[1] = std::min(lo[1], y); hi[1] = std::max(hi[1], y);
+      lo[2] = std::min(lo[2], z); hi[2] = std::max(hi[2], z);
       if (!p.periodic[0] && (x < 3 || x > p.nx - 4)) {
         fail(nullptr, LBM_EINVAL, "obstacle must keep 3 cells clear of inlet and outlet");
         return bail(LBM_EINVAL);
@@ -1020,6 +1039,25 @@ extern "C" int lbm_create(const lbm_params* pin, const uint8_t* solid, int64_t n
   a.tiles_y = tiles_y;
   a.ntiles = (int32_t)ntiles;
   a.remap = p.xcd_remap ? 1 : 0;
+  // tile box around the obstacle: solid cells dilated by two cells (their
+  // fluid neighbours and the cells behind them); on a periodic axis a box
+  // that reaches a face covers the whole axis
+  if (hi[0] < 0) {
+    a.obox[0] = 1; a.obox[1] = 0; a.obox[2] = 1; a.obox[3] = 0; a.obox[4] = 1; a.obox[5] = 0;
+  } else {
+    const int ext[3] = {p.nx, p.ny, p.nz}, tsz[3] = {TX, TY, 1};
+    for (int d = 0; d < 3; ++d) {
+      int b0 = lo[d] - 2, b1 = hi[d] + 2;
+      if (p.periodic[d] && (b0 < 0 || b1 > ext[d] - 1)) {
+        b0 = 0;
+        b1 = ext[d] - 1;
+      }
+      b0 = std::max(b0, 0);
+      b1 = std::min(b1, ext[d] - 1);
+      a.obox[2 * d] = b0 / tsz[d];
+      a.obox[2 * d + 1] = b1 / tsz[d];
+    }
+  }
   a.perturb_seed = p.perturb_seed;
   a.perturb_amp = p.perturb_amp;
 
