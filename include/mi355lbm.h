@@ -62,7 +62,7 @@ enum { LBM_MODE_AUTO = -1, LBM_MODE_PLAIN = 0, LBM_MODE_K17 = 1 };
 typedef struct lbm_sim lbm_sim;
 
 typedef struct {
-  int32_t nx, ny, nz;      /* cells; nx % 64 == 0, ny % 4 == 0, nz >= 1          */
+  int32_t nx, ny, nz;      /* cells; nx % 64 == 0, ny % 2 == 0, nz >= 1          */
   int32_t storage;         /* LBM_F64 .. LBM_BF16S                                */
   int32_t periodic[3];     /* 1: periodic axis.  0: x has the inlet (x = -1/2)
                               and the outlet (x = nx - 1/2); y, z have no-slip

@@ -25,7 +25,7 @@ using namespace mlbm;
 namespace {
 
 constexpr int TX = 64;   // cells along x per wave
-constexpr int TY = 4;    // waves (rows along y) per block
+constexpr int TY = 2;    // waves (rows along y) per block
 constexpr int NTHREADS = TX * TY;
 
 // Population layout, planes of slots: for each padded z plane, the 27 slots
@@ -36,7 +36,7 @@ constexpr int NTHREADS = TX * TY;
 // row are the inlet and outlet ghosts; guard rows and planes keep every
 // neighbour address of a domain cell inside the array, so loads may be
 // issued before a boundary substitution replaces them.  Everything a tile
-// (64 x 4 cells of one z plane) touches lies within three consecutive
+// (64 x 2 cells of one z plane) touches lies within three consecutive
 // padded planes: one uniform base address plus 32-bit lane offsets.
 struct StepArgs {
   void* A;                  // populations
@@ -341,7 +341,7 @@ __device__ __forceinline__ void cell_update(const StepArgs& a, const Coef<typena
 }
 
 #ifndef MLBM_WAVES
-#define MLBM_WAVES 4
+#define MLBM_WAVES 3
 #endif
 #ifndef MLBM_EDGE_PATH
 #define MLBM_EDGE_PATH 1
@@ -847,7 +847,7 @@ extern "C" int lbm_create(const lbm_params* pin, const uint8_t* solid, int64_t n
   *out = nullptr;
   const lbm_params& p = *pin;
   if (p.nx <= 0 || p.ny <= 0 || p.nz <= 0 || p.nx % TX || p.ny % TY)
-    return fail(nullptr, LBM_EINVAL, "grid must have nx % 64 == 0 and ny % 4 == 0");
+    return fail(nullptr, LBM_EINVAL, "grid must have nx % 64 == 0 and ny % 2 == 0");
   if (storage_size(p.storage) == 0) return fail(nullptr, LBM_EINVAL, "unknown storage type");
   if (!(p.nu > 0.0) || !std::isfinite(p.nu)) return fail(nullptr, LBM_EINVAL, "viscosity must be positive");
   if (!(p.omega2 > 0.0 && p.omega2 < 2.0)) return fail(nullptr, LBM_EINVAL, "omega2 must be in (0, 2)");

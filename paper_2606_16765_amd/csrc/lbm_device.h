@@ -14,27 +14,32 @@ struct f16s { uint16_t bits; };
 struct bf16s { uint16_t bits; };
 
 template <typename S> struct Storage;
-// load/store take the value streamed once per step; the _nt forms add the
-// non-temporal hint (the populations are not reused within a step).
-#ifndef MLBM_NT
-#define MLBM_NT 0
+// load/store take the value streamed once per step; the _nt forms may add
+// the non-temporal hint (the populations are not reused within a step).
+// Measured on MI355X: for 32- and 64-bit storage the hint pays on stores
+// and not on loads; 16-bit storage uses it on both.
+#ifndef MLBM_NT_LOAD
+#define MLBM_NT_LOAD 0
+#endif
+#ifndef MLBM_NT_STORE
+#define MLBM_NT_STORE 1
 #endif
 template <> struct Storage<double> {
   using T = double;
   static __device__ __forceinline__ double load(const double* p) { return *p; }
   static __device__ __forceinline__ void store(double* p, double v) { *p = v; }
-  static __device__ __forceinline__ double load_nt(const double* p) { return MLBM_NT ? __builtin_nontemporal_load(p) : *p; }
+  static __device__ __forceinline__ double load_nt(const double* p) { return MLBM_NT_LOAD ? __builtin_nontemporal_load(p) : *p; }
   static __device__ __forceinline__ void store_nt(double* p, double v) {
-    if (MLBM_NT) __builtin_nontemporal_store(v, p); else *p = v;
+    if (MLBM_NT_STORE) __builtin_nontemporal_store(v, p); else *p = v;
   }
 };
 template <> struct Storage<float> {
   using T = float;
   static __device__ __forceinline__ float load(const float* p) { return *p; }
   static __device__ __forceinline__ void store(float* p, float v) { *p = v; }
-  static __device__ __forceinline__ float load_nt(const float* p) { return MLBM_NT ? __builtin_nontemporal_load(p) : *p; }
+  static __device__ __forceinline__ float load_nt(const float* p) { return MLBM_NT_LOAD ? __builtin_nontemporal_load(p) : *p; }
   static __device__ __forceinline__ void store_nt(float* p, float v) {
-    if (MLBM_NT) __builtin_nontemporal_store(v, p); else *p = v;
+    if (MLBM_NT_STORE) __builtin_nontemporal_store(v, p); else *p = v;
   }
 };
 __device__ __forceinline__ float f16_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
