@@ -142,6 +142,9 @@ def run_lbm(name, steps, warmup):
     elapsed = time.perf_counter() - t
     kern_ms, launches = sim.profile_read()
     sim.profile(False)
+    # same memory traffic without the collision: the attainable rate of this
+    # access pattern on this device
+    probe_ms = sim.bandwidth_probe(20)
     mass = sim.mass()
     forces, fsteps = sim.forces()
     sim.close()
@@ -153,7 +156,11 @@ def run_lbm(name, steps, warmup):
     achieved = bytes_per_launch / avg_kernel_s / 1e9
     log(f"timed {steps} steps in {elapsed:.3f} s: {mlups:.1f} MLUPS; kernel avg {avg_kernel_s * 1e3:.3f} ms "
         f"-> {achieved:.0f} GB/s")
+    esize = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[storage]
+    probe_gbs = N * 2 * 27 * esize / (probe_ms / 1e3) / 1e9
+    log(f"same-pattern probe (no collision): {probe_ms:.3f} ms per pass -> {probe_gbs:.0f} GB/s")
     out = dict(mlups=mlups, elapsed=elapsed, N=N, n_solid=n_solid, desc=desc, storage=storage,
+               probe_ms=probe_ms, probe_gbs=probe_gbs,
                kernel_ms=avg_kernel_s * 1e3, bytes_per_launch=bytes_per_launch, achieved=achieved,
                bytes_per_cell=bpc, mass=mass, launches=launches)
     if len(forces):
@@ -263,7 +270,11 @@ def main():
                      "frac": round(res["achieved"] / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "lbm_step_kernel (stream-collide, both AA parities)",
                      "bytes_per_launch": res["bytes_per_launch"], "bytes_per_cell_update": res["bytes_per_cell"],
-                     "kernel_ms": round(res["kernel_ms"], 4)},
+                     "kernel_ms": round(res["kernel_ms"], 4),
+                     "same_pattern_probe_gbs": round(res["probe_gbs"], 1),
+                     "frac_of_probe": round(res["achieved"] / res["probe_gbs"], 4),
+                     "probe_note": "lbm_bandwidth_probe: the even step's loads and stores of every cell with the "
+                                   "collision left out, same kernel layout and tile order"},
     }
     if "cd" in res:
         line["physics"] = {"cd_mean_second_half": round(res["cd"], 4), "cl_rms_second_half": round(res["cl_rms"], 4),

@@ -181,6 +181,17 @@ int lbm_info(const lbm_sim* s, int64_t* steps, double* omega1, int32_t* mode);
 int lbm_profile(lbm_sim* s, int enable);
 int lbm_profile_read(lbm_sim* s, double* total_ms, int64_t* launches);
 
+/* Bandwidth probe (measurement support for the roofline of lbm_step, not
+ * a step of the method): `passes` launches of a kernel that moves exactly
+ * the even step's memory traffic, every cell's 27 slots loaded and stored
+ * to the opposite slots with the step kernel's addressing, tile order and
+ * cache hints, with no collision.  2 * 27 * sizeof(storage) bytes per cell
+ * per pass.  passes must be even: the swap is its own inverse, so the state
+ * is unchanged afterwards.  *ms_per_pass receives the event-timed average.
+ * Synchronises.  Errors: LBM_EINVAL (null pointer, odd or non-positive
+ * passes), LBM_EDEVICE.                                                      */
+int lbm_bandwidth_probe(lbm_sim* s, int32_t passes, double* ms_per_pass);
+
 void lbm_destroy(lbm_sim* s);
 const char* lbm_last_error(const lbm_sim* s); /* s may be NULL: global error */
 

@@ -413,6 +413,30 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(MLBM_W
   }
 }
 
+// Bandwidth probe: the even step's memory traffic with the collision left
+// out.  Every cell of every tile loads its 27 slots and stores them to the
+// opposite slots through the same addressing, hints and tile order as the
+// stream-and-collide kernel; the swap is an involution, so an even number
+// of passes leaves the array as it was.
+template <typename S>
+__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(MLBM_WAVES, 8))) void swap_probe_kernel(
+    StepArgs a) {
+  using T = typename Storage<S>::T;
+  const int tile = logical_tile(blockIdx.x, a.ntiles, a.remap);
+  const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
+  const int txi = tile % a.tiles_x;
+  const int rest = tile / a.tiles_x;
+  const int tyi = rest % a.tiles_y;
+  const int z = rest / a.tiles_y;
+  const int x = txi * TX + tx, y = tyi * TY + ty;
+  const char* zb = (const char*)a.A + (size_t)z * (size_t)a.zstride * sizeof(S);
+  const uint32_t p0 = (uint32_t)(((y + 1) * a.pitch + x) * (int)sizeof(S));
+  T g[27];
+  load_fast<S, false>(a, zb, p0, g);
+#pragma unroll
+  for (int j = 0; j < 27; ++j) Storage<S>::store_nt((S*)(zb + fast_off<S>(a, p0, 26 - j, 0, 0, 0)), g[j]);
+}
+
 // Sum of the force partials in a fixed order, plus the constant weight part.
 __global__ __launch_bounds__(256) void force_reduce_kernel(const double* fpart, int nslots, double c0, double c1,
                                                            double c2, double* out) {
@@ -1402,6 +1426,35 @@ extern "C" int lbm_profile_read(lbm_sim* s, double* total_ms, int64_t* launches)
   if (launches) *launches = s->prof_launches;
   s->prof_ms = 0;
   s->prof_launches = 0;
+  return LBM_OK;
+}
+
+extern "C" int lbm_bandwidth_probe(lbm_sim* s, int32_t passes, double* ms_per_pass) {
+  if (!s || !ms_per_pass) return fail(s, LBM_EINVAL, "null argument");
+  if (s->sticky) return s->sticky;
+  if (passes <= 0 || passes % 2) return fail(s, LBM_EINVAL, "passes must be positive and even");
+  const StepArgs& a = s->args;
+  hipEvent_t e0, e1;
+  HIPCHK(s, hipEventCreate(&e0));
+  HIPCHK(s, hipEventCreate(&e1));
+  HIPCHK(s, hipEventRecord(e0, s->stream));
+  for (int i = 0; i < passes; ++i) {
+    switch (s->p.storage) {
+      case LBM_F64: hipLaunchKernelGGL(swap_probe_kernel<double>, dim3(a.ntiles), dim3(NTHREADS), 0, s->stream, a); break;
+      case LBM_F32: hipLaunchKernelGGL(swap_probe_kernel<float>, dim3(a.ntiles), dim3(NTHREADS), 0, s->stream, a); break;
+      case LBM_F16S: hipLaunchKernelGGL(swap_probe_kernel<f16s>, dim3(a.ntiles), dim3(NTHREADS), 0, s->stream, a); break;
+      default: hipLaunchKernelGGL(swap_probe_kernel<bf16s>, dim3(a.ntiles), dim3(NTHREADS), 0, s->stream, a); break;
+    }
+  }
+  HIPCHK(s, hipEventRecord(e1, s->stream));
+  HIPCHK(s, hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(s, hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(s, LBM_EDEVICE, hipGetErrorString(e));
+  *ms_per_pass = (double)ms / passes;
   return LBM_OK;
 }
 

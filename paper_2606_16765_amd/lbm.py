@@ -155,6 +155,14 @@ class Lbm:
                   "lbm_mean_fields_pooled")
         return out
 
+    def bandwidth_probe(self, passes=20):
+        """Average ms of one pass that moves the even step's traffic (27
+        slots loaded and stored per cell) without the collision; passes must
+        be even and leave the state unchanged."""
+        ms = ctypes.c_double()
+        self._chk(self._L.lbm_bandwidth_probe(self._h, int(passes), ctypes.byref(ms)), "lbm_bandwidth_probe")
+        return ms.value
+
     def snapshots(self):
         k = ctypes.c_int32()
         self._chk(self._L.lbm_snapshots(self._h, None, 0, ctypes.byref(k), None), "lbm_snapshots")

@@ -44,6 +44,18 @@ def test_invalid_parameters_rejected_without_device_work():
     p.storage = 7
     assert L.lbm_create(ctypes.byref(p), None, 0, None, None, None, None, None, ctypes.byref(h)) == 1
     assert L.lbm_step(None, 1) == 1
+    ms = ctypes.c_double()
+    assert L.lbm_bandwidth_probe(None, 2, ctypes.byref(ms)) == 1
+    assert L.lbm_mean_fields_pooled(None, 2, 0, None) == 1
+    lo = (ctypes.c_float * 4)()
+    assert L.fno_field_minmax(None, 1, 1, 1, None, lo, lo) == 1
+    assert L.fno_field_scale(None, 1, 1, 1, lo, lo, 0, None) == 1
+    fp = __import__("paper_2606_16765_amd._lib", fromlist=["FnoParams"]).FnoParams()
+    fp.nx, fp.ny, fp.nz, fp.cin, fp.cout, fp.width, fp.layers = 48, 16, 16, 4, 4, 16, 1
+    fp.mx = fp.my = fp.mz = 4
+    fp.proj_hidden, fp.max_batch = 16, 1
+    assert L.fno_create(ctypes.byref(fp), 0, None, ctypes.byref(h)) == 1  # 48 is not a power of two
+    assert b"powers of two" in L.fno_last_error(None)
 
 
 def test_binding_raises_on_error():

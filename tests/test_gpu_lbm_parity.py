@@ -107,6 +107,24 @@ def test_precision_study_reference_f64_at_128x64x64():
     assert rel_max(m, o.mean_fields()) < 1e-11
 
 
+def test_bandwidth_probe_leaves_state_unchanged():
+    """The probe swaps every cell's opposite slots; an even number of passes
+    must restore the populations bitwise, at any AA parity."""
+    shape = (64, 8, 8)
+    geo = sphere_channel(shape, center=(20.3, 3.6, 3.4), radius=2.3)
+    P = _gpu()
+    g = P.Lbm(shape, storage="f32", nu=0.02, solid=geo.solid, perturb=(4, 5e-4))
+    for steps in (3, 4):
+        g.step(steps)
+        before = g.populations()
+        ms = g.bandwidth_probe(4)
+        assert ms > 0
+        assert np.array_equal(g.populations(), before)
+    with pytest.raises(Exception):
+        g.bandwidth_probe(3)
+    g.close()
+
+
 def test_poiseuille_body_force_f64():
     shape = (64, 16, 1)
     g, o = pair(shape, 300, periodic=(1, 0, 1), nu=0.1, u_in=0.0, body_force=(1e-6, 0, 0))
