@@ -75,6 +75,8 @@ struct fno_net {
   GtMat Pq1, Pq2;
   float* pq1b = nullptr;
   bool fused_proj = false;
+  // c2r along z, channel map, bias and activation in one kernel
+  bool fused_layer_end = false;
   // activations and work buffers
   std::vector<uint16_t*> v;  // L + 1, BF16
   std::vector<float*> h;     // L, FP32 pre-activations
@@ -321,6 +323,8 @@ static int forward_dft(fno_net* n, int B, const void* v, bool v_bf16, const GtMa
 
 // truncated inverse 3D DFT: modes [m][B][W][2] -> out [B][W][P] (FP32),
 // with the z operand Gz (c2r with 1/N and c_kz, or its unscaled adjoint)
+// out may be null with Gz unused: then only the x and y stages run, leaving
+// the y-stage output in R2 for layer_end_kernel.
 static int inverse_dft(fno_net* n, int B, const float* modes, const GtMat& Gz, float* out, bool accumulate) {
   const int64_t W = n->W, X = n->X, Y = n->Y, Z = n->Z, MY = n->MY, MZ = n->MZ;
   int rc;
@@ -337,6 +341,7 @@ static int inverse_dft(fno_net* n, int B, const float* modes, const GtMat& Gz, f
   c.cols = (int64_t)B * W * X * MZ; c.I = MZ; c.in_so = 2 * MY * MZ; c.in_si = 1; c.in_sk1 = MZ; c.in_sk2 = MY * MZ;
   c.kd = 2; c.out_so = Y * 2 * MZ; c.out_si = 1; c.out_sn1 = MZ; c.nd = 1; c.alpha = 1.f;
   if ((rc = contract(n, c))) return rc;
+  if (!out) return LBM_OK;
   // z (c2r): rows (b,w,x,y), k = (part, kz) contiguous
   c = CSpec{};
   c.in = n->R2; c.out = out; c.g = &Gz;
@@ -509,6 +514,7 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
     // width to a multiple of 32 (at most 64), at most 16 outputs
     const int Hp = (int)round_up(n->H, 32), Wp = (int)round_up(n->W, 32);
     n->fused_proj = Hp <= 128 && Wp <= 64 && p.cout <= 16 && P % 256 == 0;
+    n->fused_layer_end = n->W <= 32 && p.nz >= 16 && p.nz <= 256 && 2 * p.mz <= 32 && P % 256 == 0;
     if (n->fused_proj) {
       n->Pq1.K = n->W; n->Pq1.N = n->H; n->Pq1.kp = Wp; n->Pq1.np = Hp;
       n->Pq2.K = n->H; n->Pq2.N = p.cout; n->Pq2.kp = Hp; n->Pq2.np = 16;
@@ -613,11 +619,22 @@ static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout, bool 
     if ((rc = forward_dft(n, B, n->v[l], true, n->F1, n->Vh[l]))) return rc;
     hipLaunchKernelGGL((mix_kernel<float, float, 0>), dim3((unsigned)n->M), dim3(64), 0, n->st, n->Vh[l],
                        n->wspec + n->off_W[l], n->Yh, B, (int)W);
-    if ((rc = inverse_dft(n, B, n->Yh, n->I1, n->h[l], false))) return rc;
     // h = R(W T v) + Wp v + bp; v' = GELU(h) (identity after the last layer)
-    if ((rc = pointwise(n, B, n->v[l], true, (int)W, n->h[l], false, (int)W, &n->Gwp[l], n->theta + n->off_bp[l],
-                        true, training, n->v[l + 1], l < n->L - 1)))
-      return rc;
+    if (n->fused_layer_end) {
+      if ((rc = inverse_dft(n, B, n->Yh, n->I1, nullptr, false))) return rc;
+      LayerEndArgs e{};
+      e.v = n->v[l]; e.r2 = n->R2; e.gwp = n->Gwp[l].d; e.gi1 = n->I1.d; e.gi1_kp = n->I1.kp;
+      e.bias = n->theta + n->off_bp[l]; e.h = training ? n->h[l] : nullptr; e.act = n->v[l + 1];
+      e.P = n->P; e.W = (int)W; e.Z = n->Z; e.K2 = 2 * n->MZ; e.act_gelu = l < n->L - 1 ? 1 : 0;
+      const dim3 grid((unsigned)((int64_t)B * n->P / PW_J));
+      if (W <= 16) hipLaunchKernelGGL(layer_end_kernel<1>, grid, dim3(256), 0, n->st, e);
+      else hipLaunchKernelGGL(layer_end_kernel<2>, grid, dim3(256), 0, n->st, e);
+    } else {
+      if ((rc = inverse_dft(n, B, n->Yh, n->I1, n->h[l], false))) return rc;
+      if ((rc = pointwise(n, B, n->v[l], true, (int)W, n->h[l], false, (int)W, &n->Gwp[l], n->theta + n->off_bp[l],
+                          true, training, n->v[l + 1], l < n->L - 1)))
+        return rc;
+    }
   }
   if (!training && n->fused_proj) {
     fused_projection(n, B, n->v[n->L], yout);

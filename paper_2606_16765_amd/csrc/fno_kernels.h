@@ -96,7 +96,20 @@ template <> struct Vec8<float> {
   }
 };
 
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// erf by Abramowitz & Stegun, Handbook of Mathematical Functions, formula
+// 7.1.26: erf(x) = 1 - (a1 t + ... + a5 t^5) exp(-x^2), t = 1 / (1 + p x)
+// for x >= 0 (odd extension), absolute error <= 1.5e-7.  Used for the
+// forward activations, whose outputs are rounded to BF16 (relative 2^-9).
+__device__ __forceinline__ float erf_as(float x) {
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * ax);
+  const float poly =
+      t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+  const float e = __builtin_amdgcn_exp2f(-ax * ax * 1.4426950408889634f);
+  const float r = 1.0f - poly * e;
+  return x < 0.f ? -r : r;
+}
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
 }
@@ -352,6 +365,129 @@ __global__ __launch_bounds__(256) void pw_kernel(PwArgs a) {
       }
     }
     __syncthreads();
+  }
+}
+
+// ------------------------------------------------- fused layer completion
+// The end of a Fourier layer in one pass over 256 points of one sample:
+//   h[b][w][p] = sum_c Wp[w][c] v[b][c][p]                  (channel map)
+//              + sum_k R2[b][w][x][y][k] I1[k][z]          (c2r along z)
+//              + bp[w]
+// with p = (x, y, z), z fastest, k = (part, kz) the 2 mz contiguous values
+// of the y stage's output.  Both products share one set of MFMA
+// accumulators: in a 16 x 16 tile the rows are channels w and the columns
+// 16 consecutive z of one (x, y) row, so the channel map reads v through
+// LDS and the c2r reads the R2 row of (w, x, y) as its A operand directly.
+// Epilogue as pw_kernel: h stored when store_h (training), its activation
+// (GELU or identity) stored as BF16.
+struct LayerEndArgs {
+  const uint16_t* v;    // [B][W][P] BF16 layer input
+  const float* r2;      // [B W X Y][2 mz] y-stage output
+  const uint16_t* gwp;  // [64][32] BF16 Wp (rows w_out, k = w_in), zero padded
+  const uint16_t* gi1;  // [Z padded to 64][32] BF16 c2r operand (rows z, k), zero padded
+  int32_t gi1_kp;
+  const float* bias;    // [W]
+  float* h;             // [B][W][P] or null
+  uint16_t* act;        // [B][W][P]
+  int64_t P;
+  int32_t W, Z, K2;     // width, nz, 2 mz
+  int32_t act_gelu;
+};
+
+template <int NT>  // NT = ceil(W / 16), W <= 32
+__global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
+  __shared__ __attribute__((aligned(16))) float lds[32 * PW_DS];
+  uint16_t* tile = (uint16_t*)lds;
+  float* dst = lds;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4;
+  const int64_t j0 = (int64_t)blockIdx.x * PW_J;
+  const int64_t b = j0 / a.P, p0 = j0 % a.P;
+  // v tile [256 points][32 channels], zero beyond W
+  {
+    const uint16_t* in = a.v + b * a.W * a.P + p0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = q * 256 + t;
+      const int kl = idx >> 5, pl = (idx & 31) * 8;
+      uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (kl < a.W) Vec8<uint16_t>::load(in + (int64_t)kl * a.P + pl, v);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) tile[(pl + i) * PW_TS + kl] = v[i];
+    }
+  }
+  __syncthreads();
+  f32x4 acc[NT][4];
+#pragma unroll
+  for (int h = 0; h < NT; ++h)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[h][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // channel map
+#pragma unroll
+  for (int h = 0; h < NT; ++h) {
+    const bf16x8 av = *(const bf16x8*)(a.gwp + (h * 16 + (lane & 15)) * 32 + 8 * g);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const bf16x8 bv = *(const bf16x8*)(tile + (wave * 64 + c * 16 + (lane & 15)) * PW_TS + 8 * g);
+      acc[h][c] = mfma16(av, bv, acc[h][c]);
+    }
+  }
+  // c2r along z: column tile c covers points pp .. pp + 15 of one (x, y) row;
+  // its own accumulators, added to the channel map's in the epilogue
+  f32x4 acc2[NT][4];
+#pragma unroll
+  for (int h = 0; h < NT; ++h)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc2[h][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int64_t pp = p0 + wave * 64 + c * 16;
+    const int64_t xy = pp / a.Z;            // (x, y) row index within the sample
+    const int zb = (int)(pp % a.Z);         // first z of the tile
+    const bf16x8 bv = *(const bf16x8*)(a.gi1 + (int64_t)(zb + (lane & 15)) * a.gi1_kp + 8 * g);
+#pragma unroll
+    for (int h = 0; h < NT; ++h) {
+      // every lane loads (from row 0 where its row or k range does not
+      // exist) and selects: no divergent branch feeds the MFMA operand
+      const int w = h * 16 + (lane & 15);
+      const bool ok = w < a.W && 8 * g < a.K2;
+      const float* r = a.r2 + (ok ? ((b * a.W + w) * (a.P / a.Z) + xy) * a.K2 + 8 * g : 0);
+      const float4 lo = *(const float4*)r, hi = *(const float4*)(r + 4);
+      const float e[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+      bf16x8 av;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) av[j] = __builtin_bit_cast(__bf16, ok ? f2bf(e[j]) : (uint16_t)0);
+      acc2[h][c] = mfma16(av, bv, acc2[h][c]);
+    }
+  }
+  __syncthreads();  // the v tile is dead: its LDS becomes the result tile
+#pragma unroll
+  for (int h = 0; h < NT; ++h)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        dst[(h * 16 + 4 * g + r) * PW_DS + wave * 64 + c * 16 + (lane & 15)] = acc[h][c][r] + acc2[h][c][r];
+  __syncthreads();
+  float* hout = a.h ? a.h + b * a.W * a.P + p0 : nullptr;
+  uint16_t* act = a.act + b * a.W * a.P + p0;
+#pragma unroll 2
+  for (int e = t; e < 32 * 64; e += 256) {
+    const int n = e >> 6, p4 = (e & 63) * 4;
+    if (n >= a.W) continue;
+    float4 v = *(const float4*)(dst + n * PW_DS + p4);
+    const float bb = a.bias[n];
+    v.x += bb; v.y += bb; v.z += bb; v.w += bb;
+    const int64_t off = (int64_t)n * a.P + p4;
+    if (hout) *(float4*)(hout + off) = v;
+    uint2 w;
+    if (a.act_gelu) {
+      w.x = f2bf(gelu(v.x)) | ((uint32_t)f2bf(gelu(v.y)) << 16);
+      w.y = f2bf(gelu(v.z)) | ((uint32_t)f2bf(gelu(v.w)) << 16);
+    } else {
+      w.x = f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
+      w.y = f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16);
+    }
+    *(uint2*)(act + off) = w;
   }
 }
 
