@@ -78,6 +78,32 @@ def read_surrogate_result():
     return keep
 
 
+def read_validation_result():
+    """Sphere drag against the paper's Table 1 and the cylinder's Strouhal
+    number from the committed validation runs (profiles/validation_*.json);
+    None when absent."""
+    out = {}
+    for name in ("validation_sphere_periodic", "validation_sphere_walls"):
+        path = os.path.join(ROOT, "profiles", name + ".json")
+        if not os.path.exists(path):
+            continue
+        with open(path) as fh:
+            r = json.load(fh)
+        key = "sphere_periodic" if "periodic" in name else "sphere"
+        rows = []
+        for blk in r.get(key, []):
+            for row in blk["rows"]:
+                rows.append({"L": blk["resolution"], "re_s": row["re_s"], "cd": round(row["cd"], 4),
+                             "cd_paper": row["cd_paper"]})
+        out[key] = rows
+        if "cylinder" in r:
+            out["cylinder_strouhal"] = round(r["cylinder"]["strouhal"], 4)
+    if not out:
+        return None
+    out["source"] = "profiles/validation_*.json (python -m paper_2606_16765_amd.validation)"
+    return out
+
+
 WORKLOADS = {
     # name: (shape, storage, description)
     "c2": ((1024, 512, 512), "f32", "cylinder D=64, Re_D=3900, K17, FP32, 1024x512x512"),
@@ -292,6 +318,9 @@ def main():
         sur = read_surrogate_result()
         if sur is not None:
             line.setdefault("fno", {})["surrogate_run"] = sur
+    val = read_validation_result()
+    if val is not None:
+        line["validation"] = val
     if not args.no_precision:
         from paper_2606_16765_amd import precision
         log("precision study ...")
