@@ -272,7 +272,7 @@ def main():
 
     if args.fno_only:
         from paper_2606_16765_amd import fno as pfno
-        print(json.dumps({"fno": pfno.bench_inference(batch=16)}), flush=True)
+        print(json.dumps({"fno": dict(pfno.bench_inference(batch=16), train=pfno.bench_train(batch=16))}), flush=True)
         return
 
     res = run_lbm(args.workload, args.steps, args.warmup)
@@ -311,6 +311,7 @@ def main():
         try:
             from paper_2606_16765_amd import fno as pfno
             line["fno"] = pfno.bench_inference(batch=16)
+            line["fno"]["train"] = pfno.bench_train(batch=16)
             log(f"fno: {line['fno']}")
         except (ImportError, AttributeError) as e:
             log(f"fno leg skipped: {e}")

@@ -87,6 +87,8 @@ struct fno_net {
   float *Vg = nullptr;  // mode gradient
   float* part = nullptr;
   int64_t part_elems = 0;
+  float* part2 = nullptr;  // second-stage partials of the Gram reductions
+  int64_t part2_elems = 0;
   double* lpart = nullptr;
   int64_t lpart_n = 0;
   int lastB = 0;
@@ -362,8 +364,42 @@ static int colsum(fno_net* n, const float* Xd, int A, int B, float* out, bool ac
 
 // out[a][c] (+)= sum_{b,p} X[b][a][p] Y[b][c][p]
 template <typename XT, typename YT>
+static bool launch_gram2(fno_net* n, const XT* Xd, int A, const YT* Yd, int Cc, int64_t nch) {
+  const int at = (A + 15) / 16, ct = (Cc + 15) / 16;
+  const dim3 grid((unsigned)(nch / 4)), blk(256);
+#define MFNO_GRAM2(I, J)                                                                                   \
+  if (at <= I && ct <= J) {                                                                                \
+    hipLaunchKernelGGL((gram2_kernel<XT, YT, I, J>), grid, blk, 0, n->st, Xd, Yd, n->part, A, Cc, n->P);  \
+    return true;                                                                                           \
+  }
+  MFNO_GRAM2(1, 1)
+  MFNO_GRAM2(1, 2)
+  MFNO_GRAM2(2, 1)
+  MFNO_GRAM2(2, 2)
+  MFNO_GRAM2(1, 8)
+  MFNO_GRAM2(8, 1)
+  MFNO_GRAM2(8, 2)
+  MFNO_GRAM2(2, 8)
+#undef MFNO_GRAM2
+  return false;
+}
+
+template <typename XT, typename YT>
 static int gram(fno_net* n, const XT* Xd, int A, const YT* Yd, int Cc, int B, float* out, bool accumulate) {
   const int chunk = 2048;
+  static_assert(GR_CHUNK == 2048, "gram chunking");
+  {
+    const int64_t nch = (int64_t)B * n->P / GR_CHUNK;
+    const int64_t E = (int64_t)A * Cc;
+    constexpr int S = 64;
+    if (nch % 4 == 0 && nch * E <= n->part_elems && S * E <= n->part2_elems && launch_gram2(n, Xd, A, Yd, Cc, nch)) {
+      hipLaunchKernelGGL(reduce_slices_kernel, dim3((unsigned)((E + 255) / 256), S), dim3(256), 0, n->st, n->part,
+                         nch, E, S, n->part2);
+      hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, n->st, n->part2,
+                         (int64_t)S, E, out, accumulate ? 1 : 0);
+      return LBM_OK;
+    }
+  }
   const int64_t nch = (int64_t)B * n->P / chunk;
   if (nch * A * Cc > n->part_elems) return ffail(n, LBM_EINVAL, "gram partial buffer too small");
   hipLaunchKernelGGL((gram_kernel<XT, YT>), dim3((unsigned)nch, (unsigned)((A + 15) / 16), (unsigned)((Cc + 15) / 16)),
@@ -496,7 +532,10 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
   n->part_elems = std::max<int64_t>(n->part_elems, (int64_t)B * P / 2048 * n->H * W);
   n->part_elems = std::max<int64_t>(n->part_elems, (int64_t)B * P / 2048 * p.cout * n->H);
   n->lpart_n = ((int64_t)B * p.cout * P + 255) / 256;
-  ok = ok && A((void**)&n->part, (size_t)n->part_elems * 4) && A((void**)&n->lpart, (size_t)n->lpart_n * 8);
+  n->part2_elems = 64 * std::max<int64_t>(std::max<int64_t>((int64_t)n->H * W, (int64_t)p.cout * n->H),
+                                           std::max<int64_t>(W * W, W * (int64_t)p.cin));
+  ok = ok && A((void**)&n->part, (size_t)n->part_elems * 4) && A((void**)&n->lpart, (size_t)n->lpart_n * 8) &&
+       A((void**)&n->part2, (size_t)n->part2_elems * 4);
   if (!ok) return bail(LBM_ENOMEM, "device allocation failed");
   // pointwise operands
   hipError_t e = hipSuccess;

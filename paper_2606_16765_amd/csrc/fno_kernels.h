@@ -699,6 +699,85 @@ __global__ __launch_bounds__(64) void gram_kernel(const XT* __restrict__ X, cons
   }
 }
 
+// Gram over points with K split across waves:
+//   part[w][a][c] = sum over the GR_CHUNK points t of chunk w of X[b][a][t] Y[b][c][t]
+// One wave per chunk (all chunks within one sample); the wave keeps every
+// 16 x 16 tile of the A x C result in MFMA accumulators and loads both
+// operands straight from memory in fragment layout (8 consecutive points per
+// lane, contiguous along the rows).  Rows beyond A or C read row 0 and are
+// zeroed by a select, so no branch feeds an MFMA operand.
+constexpr int GR_CHUNK = 2048;
+template <typename XT, typename YT, int AT, int CT>
+__global__ __launch_bounds__(256) void gram2_kernel(const XT* __restrict__ X, const YT* __restrict__ Y, float* part,
+                                                    int A, int Cc, int64_t P) {
+  const int lane = threadIdx.x & 63, g = lane >> 4;
+  const int64_t wg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t per_b = P / GR_CHUNK;
+  const int64_t b = wg / per_b, p0 = (wg % per_b) * GR_CHUNK + 8 * g;
+  const XT* xr[AT];
+  const YT* yr[CT];
+  bool xok[AT], yok[CT];
+#pragma unroll
+  for (int i = 0; i < AT; ++i) {
+    const int row = i * 16 + (lane & 15);
+    xok[i] = row < A;
+    xr[i] = X + (b * A + (xok[i] ? row : 0)) * P + p0;
+  }
+#pragma unroll
+  for (int i = 0; i < CT; ++i) {
+    const int row = i * 16 + (lane & 15);
+    yok[i] = row < Cc;
+    yr[i] = Y + (b * Cc + (yok[i] ? row : 0)) * P + p0;
+  }
+  f32x4 acc[AT][CT];
+#pragma unroll
+  for (int i = 0; i < AT; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < GR_CHUNK; k0 += 32) {
+    bf16x8 xa[AT], yb[CT];
+#pragma unroll
+    for (int i = 0; i < AT; ++i) {
+      uint16_t v[8];
+      Vec8<XT>::load(xr[i] + k0, v);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) xa[i][q] = __builtin_bit_cast(__bf16, xok[i] ? v[q] : (uint16_t)0);
+    }
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+      uint16_t v[8];
+      Vec8<YT>::load(yr[j] + k0, v);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) yb[j][q] = __builtin_bit_cast(__bf16, yok[j] ? v[q] : (uint16_t)0);
+    }
+#pragma unroll
+    for (int i = 0; i < AT; ++i)
+#pragma unroll
+      for (int j = 0; j < CT; ++j) acc[i][j] = mfma16(xa[i], yb[j], acc[i][j]);
+  }
+  float* o = part + wg * (int64_t)A * Cc;
+#pragma unroll
+  for (int i = 0; i < AT; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = i * 16 + 4 * g + r, c = j * 16 + (lane & 15);
+        if (a < A && c < Cc) o[(int64_t)a * Cc + c] = acc[i][j][r];
+      }
+}
+
+// part2[s][e] = sum over parts k = s, s + S, s + 2S, ... of part[k][e]
+__global__ __launch_bounds__(256) void reduce_slices_kernel(const float* part, int64_t nparts, int64_t E, int S,
+                                                            float* part2) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int s = blockIdx.y;
+  if (e >= E) return;
+  float acc = 0.f;
+  for (int64_t k = s; k < nparts; k += S) acc += part[k * E + e];
+  part2[(int64_t)s * E + e] = acc;
+}
+
 // out[e] (+)= sum_s part[s][e], fixed order
 __global__ __launch_bounds__(256) void reduce_parts_kernel(const float* part, int64_t nparts, int64_t E, float* out,
                                                            int accumulate) {

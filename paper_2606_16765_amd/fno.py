@@ -5,6 +5,7 @@ in the HIP library).  Device tensors are torch CUDA tensors: inputs BF16
 [nx][ny][nz].
 """
 import ctypes
+import time
 
 import numpy as np
 
@@ -151,6 +152,28 @@ def bench_inference(batch=16, reps=10):
     ms = e0.elapsed_time(e1) / reps
     net.close()
     return {"batch": batch, "ms_per_batch": round(ms, 3), "samples_per_s": round(batch / ms * 1e3, 1)}
+
+
+def bench_train(batch=16, reps=5):
+    """One training step (masked-MSE forward, backward, Adam) per batch at the
+    full surrogate shape, random input and target; the paper reports its
+    training rate in samples per second."""
+    import torch
+    net = Fno(max_batch=batch)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn((batch, 4, 128, 64, 64), device="cuda", generator=g).to(torch.bfloat16)
+    t = torch.rand((batch, 4, 128, 64, 64), device="cuda", generator=g)
+    m = torch.zeros((128, 64, 64), dtype=torch.uint8, device="cuda")
+    m[12:115, 16:48, 16:48] = 1
+    net.train_step(x, t, m, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.train_step(x, t, m, 1e-4)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    net.close()
+    return {"batch": batch, "ms_per_step": round(ms, 3), "train_samples_per_s": round(batch / ms * 1e3, 1)}
 
 
 def smoke_check():
