@@ -241,7 +241,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the x-slab "
-              "decomposition across GPUs is described in DESIGN.md, not built)", file=sys.stderr)
+              "decomposition across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch

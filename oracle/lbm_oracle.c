@@ -20,8 +20,9 @@
  *   Sec. 2    mean velocity and pressure, snapshots every 25 steps, forces
  *             on the object.
  * The paper prints none of the operator's formulas (it cites the cumulant
- * papers of Geier et al.); the readings taken here are listed in the design
- * notes and restated at each function.
+ * papers of Geier et al.); the readings taken here are restated at each
+ * function.  Parity unpinned: the fourth-order-mode rates w3, w4, w5, A and
+ * B against their source (see orc_k17_coefficients).
  */
 #include <math.h>
 #include <stdint.h>
@@ -212,7 +213,10 @@ void orc_moments_from_cumulants(const double* C, double* k) {
 /* ------------------------------------------------------------------------ */
 /* Rates of the fourth-order parametrised operator (Geier et al. 2017, cited
  * in Sec. 3.2; the paper does not print them).  Closed forms in omega1 with
- * omega2 entering as the bulk rate.                                          */
+ * omega2 entering as the bulk rate, written as recalled from that source,
+ * which is not at hand: parity unpinned against it.  The pins that do hold
+ * them: the limits at omega1 = 1, the reduction to the plain operator with
+ * neutral coefficients, and the faster diffusion-error convergence.       */
 void orc_k17_coefficients(double w1, double w2, double* out /* w3,w4,w5,A,B */) {
   out[0] = 8.0 * (w1 - 2.0) * (w2 * (3.0 * w1 - 1.0) - 5.0 * w1)
          / (8.0 * (5.0 - 2.0 * w1) * w1 + w2 * (8.0 + w1 * (9.0 * w1 - 26.0)));
