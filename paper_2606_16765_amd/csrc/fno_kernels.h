@@ -96,20 +96,7 @@ template <> struct Vec8<float> {
   }
 };
 
-// erf by Abramowitz & Stegun, Handbook of Mathematical Functions, formula
-// 7.1.26: erf(x) = 1 - (a1 t + ... + a5 t^5) exp(-x^2), t = 1 / (1 + p x)
-// for x >= 0 (odd extension), absolute error <= 1.5e-7.  Used for the
-// forward activations, whose outputs are rounded to BF16 (relative 2^-9).
-__device__ __forceinline__ float erf_as(float x) {
-  const float ax = fabsf(x);
-  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * ax);
-  const float poly =
-      t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
-  const float e = __builtin_amdgcn_exp2f(-ax * ax * 1.4426950408889634f);
-  const float r = 1.0f - poly * e;
-  return x < 0.f ? -r : r;
-}
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
 }
@@ -281,6 +268,15 @@ constexpr int PW_J = 256;        // points per block
 constexpr int PW_TS = 40;        // padded LDS row (32 k)
 constexpr int PW_DS = PW_J + 4;  // padded LDS row of the result tile
 
+// LDS placement of a 256-point x (32 or 64)-channel BF16 tile, [point][k]:
+// the threads of one store instruction hold points 8 apart (one 16-byte
+// load covers 8 consecutive points), so point p goes to row
+// (p % 8) * 32 + p / 8, making those rows consecutive, and its 8-element
+// channel groups are XOR-swizzled by p % 4 so the 16-byte fragment reads of
+// 16 consecutive points spread over the banks.
+__device__ __forceinline__ int tile_row(int p) { return (p & 7) * 32 + (p >> 3); }
+__device__ __forceinline__ int tile_col(int k, int p) { return ((((k >> 3) ^ (p & 3))) << 3) | (k & 7); }
+
 template <typename InT>
 __global__ __launch_bounds__(256) void pw_kernel(PwArgs a) {
   // one LDS buffer: the input tile during the products, then the result
@@ -302,7 +298,7 @@ __global__ __launch_bounds__(256) void pw_kernel(PwArgs a) {
       uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       if (k0 + kl < a.K) Vec8<InT>::load(in + (int64_t)(k0 + kl) * a.P + pl, v);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) tile[(pl + i) * PW_TS + kl] = v[i];
+      for (int i = 0; i < 8; ++i) tile[tile_row(pl + i) * PW_TS + tile_col(kl, pl + i)] = v[i];
     }
   };
   float* out = a.out ? a.out + b * a.N * a.P + p0 : nullptr;
@@ -321,7 +317,8 @@ __global__ __launch_bounds__(256) void pw_kernel(PwArgs a) {
         const bf16x8 av = *(const bf16x8*)(a.gt + (int64_t)(n0 + h * 16 + (lane & 15)) * a.kp + kt * 32 + 8 * g);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const bf16x8 bv = *(const bf16x8*)(tile + (wave * 64 + c * 16 + (lane & 15)) * PW_TS + 8 * g);
+          const int pt = wave * 64 + c * 16 + (lane & 15);
+          const bf16x8 bv = *(const bf16x8*)(tile + tile_row(pt) * PW_TS + tile_col(8 * g, pt));
           acc[h][c] = mfma16(av, bv, acc[h][c]);
         }
       }
@@ -412,7 +409,7 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
       uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       if (kl < a.W) Vec8<uint16_t>::load(in + (int64_t)kl * a.P + pl, v);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) tile[(pl + i) * PW_TS + kl] = v[i];
+      for (int i = 0; i < 8; ++i) tile[tile_row(pl + i) * PW_TS + tile_col(kl, pl + i)] = v[i];
     }
   }
   __syncthreads();
@@ -427,7 +424,8 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
     const bf16x8 av = *(const bf16x8*)(a.gwp + (h * 16 + (lane & 15)) * 32 + 8 * g);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const bf16x8 bv = *(const bf16x8*)(tile + (wave * 64 + c * 16 + (lane & 15)) * PW_TS + 8 * g);
+      const int pt = wave * 64 + c * 16 + (lane & 15);
+      const bf16x8 bv = *(const bf16x8*)(tile + tile_row(pt) * PW_TS + tile_col(8 * g, pt));
       acc[h][c] = mfma16(av, bv, acc[h][c]);
     }
   }
@@ -524,7 +522,7 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
     uint16_t val[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (c < W) Vec8<uint16_t>::load(v + (b * W + c) * P + p0 + g8, val);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) vt[(g8 + i) * VS + c] = val[i];
+    for (int i = 0; i < 8; ++i) vt[tile_row(g8 + i) * VS + tile_col(c, g8 + i)] = val[i];
   }
   __syncthreads();
   // second-stage A operand (Q2 rows o = lane % 16), gathered once
@@ -543,7 +541,7 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
     for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const bf16x8 bv = *(const bf16x8*)(vt + pt * VS + ks * 32 + 8 * g);
+      const bf16x8 bv = *(const bf16x8*)(vt + tile_row(pt) * VS + tile_col(ks * 32 + 8 * g, pt));
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         const bf16x8 av = *(const bf16x8*)(q1s + (nt * 16 + (lane & 15)) * WP + ks * 32 + 8 * g);
