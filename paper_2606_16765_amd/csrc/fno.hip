@@ -89,6 +89,8 @@ struct fno_net {
   int64_t part_elems = 0;
   float* part2 = nullptr;  // second-stage partials of the Gram reductions
   int64_t part2_elems = 0;
+  float* partc = nullptr;  // per-chunk row sums (bias gradients)
+  int64_t partc_elems = 0;
   double* lpart = nullptr;
   int64_t lpart_n = 0;
   int lastB = 0;
@@ -184,6 +186,7 @@ struct CSpec {
   bool store_out = true;
   uint16_t* act = nullptr;
   bool act_gelu = false;
+  const float* gmul = nullptr;
 };
 
 template <typename InT, typename OutT, int LM>
@@ -218,6 +221,7 @@ static int contract(fno_net* n, const CSpec& c) {
   a.accumulate = c.accumulate ? 1 : 0;
   a.store_out = c.store_out ? 1 : 0;
   a.act_gelu = c.act_gelu ? 1 : 0;
+  a.gmul = c.gmul;
   if (a.lgI < 0 || a.lgkd < 0 || a.lgnd < 0) return ffail(n, LBM_EINVAL, "contraction index maps need powers of two");
   if ((a.accumulate || a.store_out) && !a.out) return ffail(n, LBM_EINVAL, "contraction output missing");
   // vector load modes need 8-element alignment of every address they form
@@ -248,7 +252,7 @@ static int contract(fno_net* n, const CSpec& c) {
 // GELU(value) or the value when act is not null
 static int pointwise(fno_net* n, int B, const void* in, bool in_bf16, int cin, void* out, bool out_bf16, int cout,
                      const GtMat* g, const float* bias, bool accumulate, bool store_out = true,
-                     uint16_t* act = nullptr, bool act_gelu = false) {
+                     uint16_t* act = nullptr, bool act_gelu = false, const float* gmul = nullptr) {
   (void)cout;
   CSpec c{};
   c.in = in; c.in_bf16 = in_bf16; c.out = out; c.out_bf16 = out_bf16; c.g = g;
@@ -256,7 +260,7 @@ static int pointwise(fno_net* n, int B, const void* in, bool in_bf16, int cin, v
   c.in_so = (int64_t)cin * n->P; c.in_si = 1; c.in_sk1 = n->P; c.in_sk2 = 0; c.kd = 1;
   c.out_so = (int64_t)g->N * n->P; c.out_si = 1; c.out_sn1 = n->P; c.out_sn2 = 0; c.nd = 1;
   c.alpha = 1.f; c.accumulate = accumulate; c.bias = bias; c.kcontig = false;
-  c.store_out = store_out; c.act = act; c.act_gelu = act_gelu;
+  c.store_out = store_out; c.act = act; c.act_gelu = act_gelu; c.gmul = gmul;
   // the dedicated channel-map kernel needs 256-point blocks within a sample
   // and 8-element aligned rows
   const size_t esz = in_bf16 ? 2 : 4;
@@ -267,6 +271,7 @@ static int pointwise(fno_net* n, int B, const void* in, bool in_bf16, int cin, v
     a.in = in; a.out = (float*)out; a.gt = g->d; a.bias = bias; a.act = act; a.P = n->P;
     a.K = g->K; a.N = g->N; a.kp = g->kp; a.alpha = 1.f;
     a.accumulate = accumulate ? 1 : 0; a.store_out = store_out ? 1 : 0; a.act_gelu = act_gelu ? 1 : 0;
+    a.gmul = gmul;
     const dim3 grid((unsigned)((int64_t)B * n->P / PW_J));
     if (in_bf16) hipLaunchKernelGGL(pw_kernel<uint16_t>, grid, dim3(256), 0, n->st, a);
     else hipLaunchKernelGGL(pw_kernel<float>, grid, dim3(256), 0, n->st, a);
@@ -327,7 +332,8 @@ static int forward_dft(fno_net* n, int B, const void* v, bool v_bf16, const GtMa
 // with the z operand Gz (c2r with 1/N and c_kz, or its unscaled adjoint)
 // out may be null with Gz unused: then only the x and y stages run, leaving
 // the y-stage output in R2 for layer_end_kernel.
-static int inverse_dft(fno_net* n, int B, const float* modes, const GtMat& Gz, float* out, bool accumulate) {
+static int inverse_dft(fno_net* n, int B, const float* modes, const GtMat& Gz, float* out, bool accumulate,
+                       const float* gmul = nullptr) {
   const int64_t W = n->W, X = n->X, Y = n->Y, Z = n->Z, MY = n->MY, MZ = n->MZ;
   int rc;
   CSpec c{};
@@ -349,6 +355,7 @@ static int inverse_dft(fno_net* n, int B, const float* modes, const GtMat& Gz, f
   c.in = n->R2; c.out = out; c.g = &Gz;
   c.cols = (int64_t)B * W * X * Y; c.I = 1; c.in_so = 2 * MZ; c.in_sk1 = 1; c.kd = 1;
   c.out_so = Z; c.out_sn1 = 1; c.nd = 1; c.alpha = 1.f; c.accumulate = accumulate; c.kcontig = true;
+  c.gmul = gmul;
   return contract(n, c);
 }
 
@@ -364,12 +371,13 @@ static int colsum(fno_net* n, const float* Xd, int A, int B, float* out, bool ac
 
 // out[a][c] (+)= sum_{b,p} X[b][a][p] Y[b][c][p]
 template <typename XT, typename YT>
-static bool launch_gram2(fno_net* n, const XT* Xd, int A, const YT* Yd, int Cc, int64_t nch) {
+static bool launch_gram2(fno_net* n, const XT* Xd, int A, const YT* Yd, int Cc, int64_t nch, float* partc) {
   const int at = (A + 15) / 16, ct = (Cc + 15) / 16;
   const dim3 grid((unsigned)(nch / 4)), blk(256);
 #define MFNO_GRAM2(I, J)                                                                                   \
   if (at <= I && ct <= J) {                                                                                \
-    hipLaunchKernelGGL((gram2_kernel<XT, YT, I, J>), grid, blk, 0, n->st, Xd, Yd, n->part, A, Cc, n->P);  \
+    hipLaunchKernelGGL((gram2_kernel<XT, YT, I, J>), grid, blk, 0, n->st, Xd, Yd, n->part, A, Cc, n->P,   \
+                       partc);                                                                             \
     return true;                                                                                           \
   }
   MFNO_GRAM2(1, 1)
@@ -384,21 +392,36 @@ static bool launch_gram2(fno_net* n, const XT* Xd, int A, const YT* Yd, int Cc, 
   return false;
 }
 
+// out[a][c] (+)= sum_{b,p} X[b][a][p] Y[b][c][p]; with bout (FP32 X), also
+// bout[a] = sum_{b,p} X[b][a][p] (the bias gradient of the same map)
 template <typename XT, typename YT>
-static int gram(fno_net* n, const XT* Xd, int A, const YT* Yd, int Cc, int B, float* out, bool accumulate) {
+static int gram(fno_net* n, const XT* Xd, int A, const YT* Yd, int Cc, int B, float* out, bool accumulate,
+                float* bout = nullptr) {
   const int chunk = 2048;
   static_assert(GR_CHUNK == 2048, "gram chunking");
   {
     const int64_t nch = (int64_t)B * n->P / GR_CHUNK;
     const int64_t E = (int64_t)A * Cc;
     constexpr int S = 64;
-    if (nch % 4 == 0 && nch * E <= n->part_elems && S * E <= n->part2_elems && launch_gram2(n, Xd, A, Yd, Cc, nch)) {
+    const bool with_c = bout && std::is_same<XT, float>::value && nch * A <= n->partc_elems && S * A <= n->part2_elems;
+    if (nch % 4 == 0 && nch * E <= n->part_elems && S * E <= n->part2_elems && (with_c || !bout) &&
+        launch_gram2(n, Xd, A, Yd, Cc, nch, with_c ? n->partc : nullptr)) {
       hipLaunchKernelGGL(reduce_slices_kernel, dim3((unsigned)((E + 255) / 256), S), dim3(256), 0, n->st, n->part,
                          nch, E, S, n->part2);
       hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, n->st, n->part2,
                          (int64_t)S, E, out, accumulate ? 1 : 0);
+      if (with_c) {
+        hipLaunchKernelGGL(reduce_slices_kernel, dim3((unsigned)((A + 255) / 256), S), dim3(256), 0, n->st, n->partc,
+                           nch, (int64_t)A, S, n->part2);
+        hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((A + 255) / 256)), dim3(256), 0, n->st, n->part2,
+                           (int64_t)S, (int64_t)A, bout, 0);
+      }
       return LBM_OK;
     }
+  }
+  if (bout) {
+    if constexpr (std::is_same<XT, float>::value) colsum(n, Xd, A, B, bout, false);
+    else return ffail(n, LBM_EINVAL, "bias gradient needs FP32 rows");
   }
   const int64_t nch = (int64_t)B * n->P / chunk;
   if (nch * A * Cc > n->part_elems) return ffail(n, LBM_EINVAL, "gram partial buffer too small");
@@ -534,8 +557,9 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
   n->lpart_n = ((int64_t)B * p.cout * P + 255) / 256;
   n->part2_elems = 64 * std::max<int64_t>(std::max<int64_t>((int64_t)n->H * W, (int64_t)p.cout * n->H),
                                            std::max<int64_t>(W * W, W * (int64_t)p.cin));
+  n->partc_elems = (int64_t)B * P / 2048 * std::max<int64_t>(std::max<int64_t>(n->H, W), p.cout);
   ok = ok && A((void**)&n->part, (size_t)n->part_elems * 4) && A((void**)&n->lpart, (size_t)n->lpart_n * 8) &&
-       A((void**)&n->part2, (size_t)n->part2_elems * 4);
+       A((void**)&n->part2, (size_t)n->part2_elems * 4) && A((void**)&n->partc, (size_t)n->partc_elems * 4);
   if (!ok) return bail(LBM_ENOMEM, "device allocation failed");
   // pointwise operands
   hipError_t e = hipSuccess;
@@ -716,23 +740,21 @@ extern "C" int fno_loss_grad(fno_net* n, const uint16_t* x, const float* target,
   hipLaunchKernelGGL(mse_kernel, dim3((unsigned)nblk), dim3(256), 0, n->st, n->y, target, mask, P, ny,
                      (float)(1.0 / ((double)B * cout * cnt)), n->gy, n->lpart);
   FCHK(n, hipMemsetAsync(n->grad, 0, n->nparam * 4, n->st));
-  dim3 g;
   // projection
-  colsum(n, n->gy, (int)cout, B, n->grad + n->off_q2, false);
-  if ((rc = gram(n, n->gy, (int)cout, n->a, n->H, B, n->grad + n->off_Q2, false))) return rc;
-  if ((rc = pointwise(n, B, n->gy, false, (int)cout, n->ga, false, n->H, &n->Gq2t, nullptr, false))) return rc;
-  elementwise_grid((int64_t)B * n->H * P, g);
-  hipLaunchKernelGGL(gelu_bwd_kernel, g, dim3(256), 0, n->st, n->ga, n->h1, (int64_t)B * n->H * P);
-  colsum(n, n->ga, n->H, B, n->grad + n->off_q1, false);
-  if ((rc = gram(n, n->ga, n->H, n->v[n->L], (int)W, B, n->grad + n->off_Q1, false))) return rc;
+  if ((rc = gram(n, n->gy, (int)cout, n->a, n->H, B, n->grad + n->off_Q2, false, n->grad + n->off_q2))) return rc;
+  // dL/dh1 = GELU'(h1) * Q2^T gy, the derivative applied in the epilogue
+  if ((rc = pointwise(n, B, n->gy, false, (int)cout, n->ga, false, n->H, &n->Gq2t, nullptr, false, true, nullptr,
+                      false, n->h1)))
+    return rc;
+  if ((rc = gram(n, n->ga, n->H, n->v[n->L], (int)W, B, n->grad + n->off_Q1, false, n->grad + n->off_q1)))
+    return rc;
   if ((rc = pointwise(n, B, n->ga, false, n->H, n->gv, false, (int)W, &n->Gq1t, nullptr, false))) return rc;
   // Fourier layers in reverse
-  elementwise_grid((int64_t)B * W * P, g);
+  // at layer l, gv holds dL/dh[l]: the last layer has no activation, and the
+  // GELU' of the layers below is applied where their gradient is completed
   for (int l = n->L - 1; l >= 0; --l) {
-    if (l < n->L - 1)
-      hipLaunchKernelGGL(gelu_bwd_kernel, g, dim3(256), 0, n->st, n->gv, n->h[l], (int64_t)B * W * P);
-    colsum(n, n->gv, (int)W, B, n->grad + n->off_bp[l], false);
-    if ((rc = gram(n, n->gv, (int)W, n->v[l], (int)W, B, n->grad + n->off_Wp[l], false))) return rc;
+    if ((rc = gram(n, n->gv, (int)W, n->v[l], (int)W, B, n->grad + n->off_Wp[l], false, n->grad + n->off_bp[l])))
+      return rc;
     // gradient on the modes: (c_kz/N) T(gh)
     if ((rc = forward_dft(n, B, n->gv, false, n->F1a, n->Yh))) return rc;
     hipLaunchKernelGGL((mix_grad_kernel<float>), dim3((unsigned)n->M), dim3(64), 0, n->st, n->Vh[l], n->Yh,
@@ -740,11 +762,11 @@ extern "C" int fno_loss_grad(fno_net* n, const uint16_t* x, const float* target,
     hipLaunchKernelGGL((mix_kernel<float, float, 1>), dim3((unsigned)n->M), dim3(64), 0, n->st, n->Yh,
                        n->wspec + n->off_W[l], n->Vg, B, (int)W);
     if ((rc = pointwise(n, B, n->gv, false, (int)W, n->gvn, false, (int)W, &n->Gwpt[l], nullptr, false))) return rc;
-    if ((rc = inverse_dft(n, B, n->Vg, n->I1a, n->gvn, true))) return rc;
+    // gvn = dL/dv[l]; for l >= 1 it becomes dL/dh[l - 1] = GELU'(h[l - 1]) dL/dv[l]
+    if ((rc = inverse_dft(n, B, n->Vg, n->I1a, n->gvn, true, l >= 1 ? n->h[l - 1] : nullptr))) return rc;
     std::swap(n->gv, n->gvn);
   }
-  colsum(n, n->gv, (int)W, B, n->grad + n->off_p, false);
-  if ((rc = gram(n, n->gv, (int)W, x, n->p.cin, B, n->grad + n->off_P, false))) return rc;
+  if ((rc = gram(n, n->gv, (int)W, x, n->p.cin, B, n->grad + n->off_P, false, n->grad + n->off_p))) return rc;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return ffail(n, LBM_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   if (loss) {

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace mfno {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -64,6 +66,7 @@ struct ContractArgs {
   int32_t accumulate;
   int32_t store_out;
   int32_t act_gelu;
+  const float* gmul;  // when set: the value is multiplied by GELU'(gmul[addr]) before it is stored
 };
 
 constexpr int CT_N = 64;   // rows n per block pass (4 waves x 16)
@@ -211,6 +214,7 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs a) {
                            (int64_t)(n & ndm) * a.out_sn2;
       if (a.bias) v += a.bias[n];
       if (a.accumulate) v += to_f(out[addr]);
+      if (a.gmul) v *= gelu_grad(a.gmul[addr]);
       if (a.store_out) out[addr] = from_f<OutT>(v);
       if (a.act) a.act[addr] = f2bf(a.act_gelu ? gelu(v) : v);
     };
@@ -262,6 +266,7 @@ struct PwArgs {
   int32_t K, N, kp;
   float alpha;
   int32_t accumulate, store_out, act_gelu;
+  const float* gmul;  // when set: multiplied by GELU'(gmul) (same layout as out) before the store
 };
 
 constexpr int PW_J = 256;        // points per block
@@ -347,6 +352,10 @@ __global__ __launch_bounds__(256) void pw_kernel(PwArgs a) {
       if (a.accumulate) {
         const float4 o = *(const float4*)(out + off);
         v.x += o.x; v.y += o.y; v.z += o.z; v.w += o.w;
+      }
+      if (a.gmul) {
+        const float4 hh = *(const float4*)(a.gmul + b * a.N * a.P + p0 + off);
+        v.x *= gelu_grad(hh.x); v.y *= gelu_grad(hh.y); v.z *= gelu_grad(hh.z); v.w *= gelu_grad(hh.w);
       }
       if (a.store_out) *(float4*)(out + off) = v;
       if (act) {
@@ -705,9 +714,11 @@ __global__ __launch_bounds__(64) void gram_kernel(const XT* __restrict__ X, cons
 // lane, contiguous along the rows).  Rows beyond A or C read row 0 and are
 // zeroed by a select, so no branch feeds an MFMA operand.
 constexpr int GR_CHUNK = 2048;
+// With partc set (FP32 X only), the wave also sums every X row over its
+// chunk in FP32 (the bias gradient), partc[w][a].
 template <typename XT, typename YT, int AT, int CT>
 __global__ __launch_bounds__(256) void gram2_kernel(const XT* __restrict__ X, const YT* __restrict__ Y, float* part,
-                                                    int A, int Cc, int64_t P) {
+                                                    int A, int Cc, int64_t P, float* partc) {
   const int lane = threadIdx.x & 63, g = lane >> 4;
   const int64_t wg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t per_b = P / GR_CHUNK;
@@ -728,16 +739,26 @@ __global__ __launch_bounds__(256) void gram2_kernel(const XT* __restrict__ X, co
     yr[i] = Y + (b * Cc + (yok[i] ? row : 0)) * P + p0;
   }
   f32x4 acc[AT][CT];
+  float rs[AT];
 #pragma unroll
-  for (int i = 0; i < AT; ++i)
+  for (int i = 0; i < AT; ++i) {
+    rs[i] = 0.f;
 #pragma unroll
     for (int j = 0; j < CT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
   for (int k0 = 0; k0 < GR_CHUNK; k0 += 32) {
     bf16x8 xa[AT], yb[CT];
 #pragma unroll
     for (int i = 0; i < AT; ++i) {
       uint16_t v[8];
-      Vec8<XT>::load(xr[i] + k0, v);
+      if constexpr (std::is_same<XT, float>::value) {
+        const float4 lo = *(const float4*)(xr[i] + k0), hi = *(const float4*)(xr[i] + k0 + 4);
+        rs[i] += ((lo.x + lo.y) + (lo.z + lo.w)) + ((hi.x + hi.y) + (hi.z + hi.w));
+        v[0] = f2bf(lo.x); v[1] = f2bf(lo.y); v[2] = f2bf(lo.z); v[3] = f2bf(lo.w);
+        v[4] = f2bf(hi.x); v[5] = f2bf(hi.y); v[6] = f2bf(hi.z); v[7] = f2bf(hi.w);
+      } else {
+        Vec8<XT>::load(xr[i] + k0, v);
+      }
 #pragma unroll
       for (int q = 0; q < 8; ++q) xa[i][q] = __builtin_bit_cast(__bf16, xok[i] ? v[q] : (uint16_t)0);
     }
@@ -763,6 +784,17 @@ __global__ __launch_bounds__(256) void gram2_kernel(const XT* __restrict__ X, co
         const int a = i * 16 + 4 * g + r, c = j * 16 + (lane & 15);
         if (a < A && c < Cc) o[(int64_t)a * Cc + c] = acc[i][j][r];
       }
+  if (partc) {
+    // lanes l, l + 16, l + 32, l + 48 hold quarter sums of the same row
+#pragma unroll
+    for (int i = 0; i < AT; ++i) {
+      float v = rs[i];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      const int row = i * 16 + (lane & 15);
+      if (g == 0 && row < A) partc[wg * (int64_t)A + row] = v;
+    }
+  }
 }
 
 // part2[s][e] = sum over parts k = s, s + S, s + 2S, ... of part[k][e]
@@ -806,13 +838,6 @@ __global__ __launch_bounds__(256) void colsum_kernel(const float* X, int A, int6
 }
 
 // ------------------------------------------------------------- elementwise
-// g *= GELU'(h)
-__global__ __launch_bounds__(256) void gelu_bwd_kernel(float* g, const float* h, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  g[i] *= gelu_grad(h[i]);
-}
-
 // masked MSE: per-block partial of sum mask (y - t)^2, and gy = 2 mask (y - t) / cnt
 __global__ __launch_bounds__(256) void mse_kernel(const float* y, const float* t, const uint8_t* mask, int64_t P,
                                                   int64_t n, float inv_cnt, float* gy, double* part) {
