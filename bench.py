@@ -8,10 +8,13 @@ recorded in FP64 every step, averaging off.  A step is one fused
 stream-and-collide launch plus the force reduction.
 
 Prints one JSON line: MLUPS (million lattice-cell updates per second) for
-the whole job, the roofline of the stream-collide kernel (algorithmic bytes
-per launch over its event-timed duration, against 8 TB/s), the CPU oracle
-timed on a bounded sample of the same workload, and, when the surrogate is
-built, the Fourier neural operator's inference time per batch of 16.
+the whole job; the roofline of the stream-collide kernel (algorithmic bytes
+per launch over its event-timed duration, against 8 TB/s, next to a
+same-pattern probe and a plain copy); the 256x128x128 dataset configuration
+with the running mean on; the Fourier neural operator's forward time per
+batch of 16 with its MFMA and HBM rates, and its training step; the storage
+precision study; and the CPU oracle timed on a bounded sample of the same
+workload.
 """
 import argparse
 import hashlib
@@ -25,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # dense
 
 
 def log(msg):
@@ -132,7 +136,7 @@ def make_workload(name):
     return geo, nu, storage, kw, desc, char_len, area
 
 
-def run_lbm(name, steps, warmup):
+def run_lbm(name, steps, warmup, probe=True):
     import numpy as np
     import torch
     import paper_2606_16765_amd as P
@@ -170,7 +174,7 @@ def run_lbm(name, steps, warmup):
     sim.profile(False)
     # same memory traffic without the collision: the attainable rate of this
     # access pattern on this device
-    probe_ms = sim.bandwidth_probe(20)
+    probe_ms = sim.bandwidth_probe(20) if probe else float("nan")
     mass = sim.mass()
     forces, fsteps = sim.forces()
     sim.close()
@@ -184,7 +188,8 @@ def run_lbm(name, steps, warmup):
         f"-> {achieved:.0f} GB/s")
     esize = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[storage]
     probe_gbs = N * 2 * 27 * esize / (probe_ms / 1e3) / 1e9
-    log(f"same-pattern probe (no collision): {probe_ms:.3f} ms per pass -> {probe_gbs:.0f} GB/s")
+    if probe:
+        log(f"same-pattern probe (no collision): {probe_ms:.3f} ms per pass -> {probe_gbs:.0f} GB/s")
     out = dict(mlups=mlups, elapsed=elapsed, N=N, n_solid=n_solid, desc=desc, storage=storage,
                probe_ms=probe_ms, probe_gbs=probe_gbs,
                kernel_ms=avg_kernel_s * 1e3, bytes_per_launch=bytes_per_launch, achieved=achieved,
@@ -195,6 +200,56 @@ def run_lbm(name, steps, warmup):
         out["cd"] = float(2.0 * half[:, 0].mean() / (u * u * area))
         out["cl_rms"] = float(2.0 * np.sqrt((half[:, 1] ** 2).mean()) / (u * u * area))
     return out
+
+
+def copy_rate(reps=10):
+    """Rate of a plain 4 GiB device-to-device copy (torch's copy kernel), the
+    bandwidth a streaming library kernel gets on this device."""
+    import torch
+    a = torch.empty(2 ** 30, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * 4 * 2 ** 30 / dt / 1e9
+
+
+def fno_leg():
+    """FNO forward and training step at batch 16 on the full surrogate shape,
+    with the forward pass's MFMA and HBM rates."""
+    from paper_2606_16765_amd import fno as pfno
+    out = pfno.bench_inference(batch=16, reps=20)
+    out["train"] = pfno.bench_train(batch=16)
+    cost = pfno.forward_cost(batch=16)
+    s = out["ms_per_batch"] / 1e3
+    out["roofline"] = {
+        "flops_per_batch": cost["flops"], "tflops": round(cost["flops"] / s / 1e12, 2),
+        "mfma_bf16_peak_tflops": MFMA_BF16_PEAK_TFLOPS,
+        "frac_mfma": round(cost["flops"] / s / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4),
+        "min_bytes_per_batch": cost["min_bytes"], "gbs_at_min_bytes": round(cost["min_bytes"] / s / 1e9, 1),
+        "frac_hbm_at_min_bytes": round(cost["min_bytes"] / s / 1e9 / HBM_PEAK_GBS, 4),
+        "note": "flops: the real contractions as executed; min_bytes: BF16 activations read and written once per "
+                "layer, input, output and spectral weights once",
+    }
+    return out
+
+
+def c1_leg(steps=2000, warmup=50):
+    """The dataset configuration (256x128x128, FP32, random obstacle seed 0,
+    Re_c 5500) with the FP64 running mean and snapshots on, as every dataset
+    run executes it: MLUPS and the step kernel's rate at 281 B per cell."""
+    r = run_lbm("c1", steps, warmup, probe=False)
+    return {"workload": r["desc"], "steps": steps, "mlups": round(r["mlups"], 1),
+            "kernel_ms": round(r["kernel_ms"], 4), "bytes_per_cell_update": r["bytes_per_cell"],
+            "achieved_gbs": round(r["achieved"], 1), "frac": round(r["achieved"] / HBM_PEAK_GBS, 4)}
 
 
 def cpu_baseline(name, budget_s=15.0):
@@ -235,9 +290,10 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fno", action="store_true")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 256x128x128 run with the running mean on")
     ap.add_argument("--no-precision", action="store_true", help="skip the FP32/FP16/BF16 storage study")
     ap.add_argument("--copy-calib", action="store_true", help="only run a plain device copy of known size")
-    ap.add_argument("--fno-only", action="store_true", help="only time the FNO forward at batch 16")
+    ap.add_argument("--fno-only", action="store_true", help="only time the FNO forward and training step at batch 16")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the x-slab "
@@ -255,24 +311,12 @@ def main():
 
     if args.copy_calib:
         # plain copy kernel of known size, for scaling the HBM counters
-        a = torch.empty(2 ** 30, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(10):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t) / 10
         print(json.dumps({"copy_bytes_read": 4 * 2 ** 30, "copy_bytes_written": 4 * 2 ** 30,
-                          "copy_GBps": 2 * 4 * 2 ** 30 / dt / 1e9}), flush=True)
+                          "copy_GBps": copy_rate()}), flush=True)
         return
 
     if args.fno_only:
-        from paper_2606_16765_amd import fno as pfno
-        print(json.dumps({"fno": dict(pfno.bench_inference(batch=16), train=pfno.bench_train(batch=16))}), flush=True)
+        print(json.dumps({"fno": fno_leg()}), flush=True)
         return
 
     res = run_lbm(args.workload, args.steps, args.warmup)
@@ -302,19 +346,21 @@ def main():
                      "probe_note": "lbm_bandwidth_probe: the even step's loads and stores of every cell with the "
                                    "collision left out, same kernel layout and tile order"},
     }
+    cgbs = copy_rate()
+    line["roofline"]["plain_copy_gbs"] = round(cgbs, 1)
+    line["roofline"]["frac_of_copy"] = round(res["achieved"] / cgbs, 4)
+    log(f"plain 4 GiB copy: {cgbs:.0f} GB/s")
     if "cd" in res:
         line["physics"] = {"cd_mean_second_half": round(res["cd"], 4), "cl_rms_second_half": round(res["cl_rms"], 4),
                            "strouhal": None,
                            "strouhal_note": "one shedding period is about 6000 steps at this size; not "
                                             "resolvable within the timed steps"}
+    if not args.no_c1:
+        line["c1_running_mean"] = c1_leg()
+        log(f"c1 with running mean: {line['c1_running_mean']}")
     if not args.no_fno:
-        try:
-            from paper_2606_16765_amd import fno as pfno
-            line["fno"] = pfno.bench_inference(batch=16)
-            line["fno"]["train"] = pfno.bench_train(batch=16)
-            log(f"fno: {line['fno']}")
-        except (ImportError, AttributeError) as e:
-            log(f"fno leg skipped: {e}")
+        line["fno"] = fno_leg()
+        log(f"fno: {line['fno']}")
     if not args.no_fno:
         sur = read_surrogate_result()
         if sur is not None:

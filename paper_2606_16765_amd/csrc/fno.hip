@@ -11,6 +11,9 @@
 //   modes            [m = (kx, ky, kz)][B][W][part]
 //   inverse x    R3  [B W][x][part][ky][kz]
 //   inverse y    R2  [B W X][y][part][kz]
+// A1, A2, R3 and R2 are BF16: each is read only as an MFMA operand, which is
+// rounded to BF16 (RNE) in any case, so storing it rounded changes no result
+// and halves the traffic of the intermediate stages.
 // Real embedding of a complex factor F = c - i s (forward) or c + i s
 // (inverse) for input part pi, output part po:
 //   forward  (0,0) c  (1,0) s   (0,1) -s  (1,1) c
@@ -81,7 +84,8 @@ struct fno_net {
   std::vector<uint16_t*> v;  // L + 1, BF16
   std::vector<float*> h;     // L, FP32 pre-activations
   std::vector<float*> Vh;    // L, FP32 modes
-  float *A1 = nullptr, *A2 = nullptr, *Yh = nullptr, *R3 = nullptr, *R2 = nullptr;
+  uint16_t *A1 = nullptr, *A2 = nullptr, *R3 = nullptr, *R2 = nullptr;  // BF16 DFT intermediates
+  float* Yh = nullptr;
   float *h1 = nullptr, *y = nullptr, *gy = nullptr, *ga = nullptr, *gv = nullptr, *gvn = nullptr;
   uint16_t* a = nullptr;
   float *Vg = nullptr;  // mode gradient
@@ -308,19 +312,19 @@ static int forward_dft(fno_net* n, int B, const void* v, bool v_bf16, const GtMa
   CSpec c{};
   // z: rows (b,w,x,y), k = z contiguous -> A1[row][part][kz]
   c = CSpec{};
-  c.in = v; c.in_bf16 = v_bf16; c.out = n->A1; c.g = &Gz;
+  c.in = v; c.in_bf16 = v_bf16; c.out = n->A1; c.out_bf16 = true; c.g = &Gz;
   c.cols = (int64_t)B * W * X * Y; c.I = 1; c.in_so = Z; c.in_sk1 = 1; c.kd = 1;
   c.out_so = 2 * MZ; c.out_sn1 = 1; c.nd = 1; c.alpha = 1.f; c.kcontig = true;
   if ((rc = contract(n, c))) return rc;
   // y: cols (b,w,x) x kz, k = (y, part) at stride MZ -> A2[bwx][part][ky][kz]
   c = CSpec{};
-  c.in = n->A1; c.out = n->A2; c.g = &n->F2;
+  c.in = n->A1; c.in_bf16 = true; c.out = n->A2; c.out_bf16 = true; c.g = &n->F2;
   c.cols = (int64_t)B * W * X * MZ; c.I = MZ; c.in_so = Y * 2 * MZ; c.in_si = 1; c.in_sk1 = MZ; c.kd = 1;
   c.out_so = 2 * MY * MZ; c.out_si = 1; c.out_sn1 = MZ; c.out_sn2 = MY * MZ; c.nd = 2; c.alpha = 1.f;
   if ((rc = contract(n, c))) return rc;
   // x: cols (b,w) x (ky,kz), k = (x, part) at stride MY*MZ -> modes
   c = CSpec{};
-  c.in = n->A2; c.out = modes; c.g = &n->F3;
+  c.in = n->A2; c.in_bf16 = true; c.out = modes; c.g = &n->F3;
   c.cols = (int64_t)B * W * MY * MZ; c.I = MY * MZ; c.in_so = X * 2 * MY * MZ; c.in_si = 1; c.in_sk1 = MY * MZ;
   c.kd = 1;
   c.out_so = 2; c.out_si = (int64_t)B * W * 2; c.out_sn1 = MY * MZ * (int64_t)B * W * 2; c.out_sn2 = 1; c.nd = 2;
@@ -338,21 +342,21 @@ static int inverse_dft(fno_net* n, int B, const float* modes, const GtMat& Gz, f
   int rc;
   CSpec c{};
   // x: cols (b,w) x (ky,kz); k = (kx, part): kx at stride MY*MZ*B*W*2, part at 1
-  c.in = modes; c.out = n->R3; c.g = &n->I3;
+  c.in = modes; c.out = n->R3; c.out_bf16 = true; c.g = &n->I3;
   c.cols = (int64_t)B * W * MY * MZ; c.I = MY * MZ; c.in_so = 2; c.in_si = (int64_t)B * W * 2;
   c.in_sk1 = MY * MZ * (int64_t)B * W * 2; c.in_sk2 = 1; c.kd = 2;
   c.out_so = X * 2 * MY * MZ; c.out_si = 1; c.out_sn1 = MY * MZ; c.nd = 1; c.alpha = 1.f;
   if ((rc = contract(n, c))) return rc;
   // y: cols (b,w,x) x kz; k = (ky, part): ky at MZ, part at MY*MZ
   c = CSpec{};
-  c.in = n->R3; c.out = n->R2; c.g = &n->I2;
+  c.in = n->R3; c.in_bf16 = true; c.out = n->R2; c.out_bf16 = true; c.g = &n->I2;
   c.cols = (int64_t)B * W * X * MZ; c.I = MZ; c.in_so = 2 * MY * MZ; c.in_si = 1; c.in_sk1 = MZ; c.in_sk2 = MY * MZ;
   c.kd = 2; c.out_so = Y * 2 * MZ; c.out_si = 1; c.out_sn1 = MZ; c.nd = 1; c.alpha = 1.f;
   if ((rc = contract(n, c))) return rc;
   if (!out) return LBM_OK;
   // z (c2r): rows (b,w,x,y), k = (part, kz) contiguous
   c = CSpec{};
-  c.in = n->R2; c.out = out; c.g = &Gz;
+  c.in = n->R2; c.in_bf16 = true; c.out = out; c.g = &Gz;
   c.cols = (int64_t)B * W * X * Y; c.I = 1; c.in_so = 2 * MZ; c.in_sk1 = 1; c.kd = 1;
   c.out_so = Z; c.out_sn1 = 1; c.nd = 1; c.alpha = 1.f; c.accumulate = accumulate; c.kcontig = true;
   c.gmul = gmul;
@@ -541,11 +545,11 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
   for (int l = 0; ok && l < n->L; ++l)
     ok = A((void**)&n->h[l], (size_t)B * W * P * 4) && A((void**)&n->Vh[l], (size_t)n->M * B * W * 2 * 4);
   const int64_t rows = (int64_t)B * W * n->X * n->Y;
-  ok = ok && A((void**)&n->A1, (size_t)rows * 2 * n->MZ * 4) &&
-       A((void**)&n->A2, (size_t)B * W * n->X * 2 * n->MY * n->MZ * 4) &&
+  ok = ok && A((void**)&n->A1, (size_t)rows * 2 * n->MZ * 2) &&
+       A((void**)&n->A2, (size_t)B * W * n->X * 2 * n->MY * n->MZ * 2) &&
        A((void**)&n->Yh, (size_t)n->M * B * W * 2 * 4) && A((void**)&n->Vg, (size_t)n->M * B * W * 2 * 4) &&
-       A((void**)&n->R3, (size_t)B * W * n->X * 2 * n->MY * n->MZ * 4) &&
-       A((void**)&n->R2, (size_t)rows * 2 * n->MZ * 4) && A((void**)&n->h1, (size_t)B * n->H * P * 4) &&
+       A((void**)&n->R3, (size_t)B * W * n->X * 2 * n->MY * n->MZ * 2) &&
+       A((void**)&n->R2, (size_t)rows * 2 * n->MZ * 2) && A((void**)&n->h1, (size_t)B * n->H * P * 4) &&
        A((void**)&n->a, (size_t)B * n->H * P * 2) && A((void**)&n->y, (size_t)B * p.cout * P * 4) &&
        A((void**)&n->gy, (size_t)B * p.cout * P * 4) && A((void**)&n->ga, (size_t)B * n->H * P * 4) &&
        A((void**)&n->gv, (size_t)B * W * P * 4) && A((void**)&n->gvn, (size_t)B * W * P * 4);

@@ -15,10 +15,14 @@ namespace mfno {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t f2bf(float v) {
-  uint32_t b = __float_as_uint(v);
-  uint32_t r = ((b & 0x7fffffffu) > 0x7f800000u) ? 0x7fc00000u : (b + 0x7fffu + ((b >> 16) & 1u));
-  return (uint16_t)(r >> 16);
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// FP32 -> BF16 with round to nearest even, in hardware (v_cvt_pk_bf16_f32);
+// f2bf2 packs two values, the first in the low half.
+__device__ __forceinline__ uint16_t f2bf(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
+__device__ __forceinline__ uint32_t f2bf2(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
@@ -94,8 +98,9 @@ template <> struct Vec8<uint16_t> {
 template <> struct Vec8<float> {
   static __device__ __forceinline__ void load(const float* p, uint16_t (&o)[8]) {
     const float4 a = *(const float4*)p, b = *(const float4*)(p + 4);
-    o[0] = f2bf(a.x); o[1] = f2bf(a.y); o[2] = f2bf(a.z); o[3] = f2bf(a.w);
-    o[4] = f2bf(b.x); o[5] = f2bf(b.y); o[6] = f2bf(b.z); o[7] = f2bf(b.w);
+    const uint32_t w[4] = {f2bf2(a.x, a.y), f2bf2(a.z, a.w), f2bf2(b.x, b.y), f2bf2(b.z, b.w)};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) o[i] = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
   }
 };
 
@@ -361,11 +366,11 @@ __global__ __launch_bounds__(256) void pw_kernel(PwArgs a) {
       if (act) {
         uint2 w;
         if (a.act_gelu) {
-          w.x = f2bf(gelu(v.x)) | ((uint32_t)f2bf(gelu(v.y)) << 16);
-          w.y = f2bf(gelu(v.z)) | ((uint32_t)f2bf(gelu(v.w)) << 16);
+          w.x = f2bf2(gelu(v.x), gelu(v.y));
+          w.y = f2bf2(gelu(v.z), gelu(v.w));
         } else {
-          w.x = f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
-          w.y = f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16);
+          w.x = f2bf2(v.x, v.y);
+          w.y = f2bf2(v.z, v.w);
         }
         *(uint2*)(act + off) = w;
       }
@@ -388,7 +393,7 @@ __global__ __launch_bounds__(256) void pw_kernel(PwArgs a) {
 // (GELU or identity) stored as BF16.
 struct LayerEndArgs {
   const uint16_t* v;    // [B][W][P] BF16 layer input
-  const float* r2;      // [B W X Y][2 mz] y-stage output
+  const uint16_t* r2;   // [B W X Y][2 mz] y-stage output (BF16)
   const uint16_t* gwp;  // [64][32] BF16 Wp (rows w_out, k = w_in), zero padded
   const uint16_t* gi1;  // [Z padded to 64][32] BF16 c2r operand (rows z, k), zero padded
   int32_t gi1_kp;
@@ -408,18 +413,40 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4;
   const int64_t j0 = (int64_t)blockIdx.x * PW_J;
   const int64_t b = j0 / a.P, p0 = j0 % a.P;
-  // v tile [256 points][32 channels], zero beyond W
-  {
-    const uint16_t* in = a.v + b * a.W * a.P + p0;
+  // Every global load of the block is issued before the first wait: the v
+  // tile (bound for LDS) and this lane's c2r operands from the y-stage
+  // output, so that both streams are in flight together.
+  const uint16_t* in = a.v + b * a.W * a.P + p0;
+  uint4 vq[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = q * 256 + t;
-      const int kl = idx >> 5, pl = (idx & 31) * 8;
-      uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (kl < a.W) Vec8<uint16_t>::load(in + (int64_t)kl * a.P + pl, v);
+  for (int q = 0; q < 4; ++q) {
+    const int idx = q * 256 + t;
+    const int kl = idx >> 5, pl = (idx & 31) * 8;
+    vq[q] = kl < a.W ? *(const uint4*)(in + (int64_t)kl * a.P + pl) : uint4{0u, 0u, 0u, 0u};
+  }
+  // c2r operand of column tile c (points pp .. pp + 15 of one (x, y) row) and
+  // row tile h: every lane loads (from row 0 where its row or k range does
+  // not exist) and selects at use, so no divergent branch feeds the MFMA
+  uint4 rq[4][NT];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) tile[tile_row(pl + i) * PW_TS + tile_col(kl, pl + i)] = v[i];
+  for (int c = 0; c < 4; ++c) {
+    const int64_t xy = (p0 + wave * 64 + c * 16) / a.Z;  // (x, y) row index within the sample
+#pragma unroll
+    for (int h = 0; h < NT; ++h) {
+      const int w = h * 16 + (lane & 15);
+      const bool ok = w < a.W && 8 * g < a.K2;
+      rq[c][h] = *(const uint4*)(a.r2 + (ok ? ((b * a.W + w) * (a.P / a.Z) + xy) * a.K2 + 8 * g : 0));
     }
+  }
+  // v tile [256 points][32 channels] in LDS, zero beyond W
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = q * 256 + t;
+    const int kl = idx >> 5, pl = (idx & 31) * 8;
+    const uint32_t u[4] = {vq[q].x, vq[q].y, vq[q].z, vq[q].w};
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      tile[tile_row(pl + i) * PW_TS + tile_col(kl, pl + i)] = (uint16_t)(u[i >> 1] >> (16 * (i & 1)));
   }
   __syncthreads();
   f32x4 acc[NT][4];
@@ -438,8 +465,8 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
       acc[h][c] = mfma16(av, bv, acc[h][c]);
     }
   }
-  // c2r along z: column tile c covers points pp .. pp + 15 of one (x, y) row;
-  // its own accumulators, added to the channel map's in the epilogue
+  // c2r along z, with its own accumulators, added to the channel map's in
+  // the epilogue
   f32x4 acc2[NT][4];
 #pragma unroll
   for (int h = 0; h < NT; ++h)
@@ -447,22 +474,17 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
     for (int c = 0; c < 4; ++c) acc2[h][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const int64_t pp = p0 + wave * 64 + c * 16;
-    const int64_t xy = pp / a.Z;            // (x, y) row index within the sample
-    const int zb = (int)(pp % a.Z);         // first z of the tile
+    const int zb = (int)((p0 + wave * 64 + c * 16) % a.Z);  // first z of the tile
     const bf16x8 bv = *(const bf16x8*)(a.gi1 + (int64_t)(zb + (lane & 15)) * a.gi1_kp + 8 * g);
 #pragma unroll
     for (int h = 0; h < NT; ++h) {
-      // every lane loads (from row 0 where its row or k range does not
-      // exist) and selects: no divergent branch feeds the MFMA operand
       const int w = h * 16 + (lane & 15);
       const bool ok = w < a.W && 8 * g < a.K2;
-      const float* r = a.r2 + (ok ? ((b * a.W + w) * (a.P / a.Z) + xy) * a.K2 + 8 * g : 0);
-      const float4 lo = *(const float4*)r, hi = *(const float4*)(r + 4);
-      const float e[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+      const uint32_t e[4] = {ok ? rq[c][h].x : 0u, ok ? rq[c][h].y : 0u, ok ? rq[c][h].z : 0u,
+                             ok ? rq[c][h].w : 0u};
       bf16x8 av;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) av[j] = __builtin_bit_cast(__bf16, ok ? f2bf(e[j]) : (uint16_t)0);
+      for (int j = 0; j < 8; ++j) av[j] = __builtin_bit_cast(__bf16, (uint16_t)(e[j >> 1] >> (16 * (j & 1))));
       acc2[h][c] = mfma16(av, bv, acc2[h][c]);
     }
   }
@@ -488,11 +510,11 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
     if (hout) *(float4*)(hout + off) = v;
     uint2 w;
     if (a.act_gelu) {
-      w.x = f2bf(gelu(v.x)) | ((uint32_t)f2bf(gelu(v.y)) << 16);
-      w.y = f2bf(gelu(v.z)) | ((uint32_t)f2bf(gelu(v.w)) << 16);
+      w.x = f2bf2(gelu(v.x), gelu(v.y));
+      w.y = f2bf2(gelu(v.z), gelu(v.w));
     } else {
-      w.x = f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
-      w.y = f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16);
+      w.x = f2bf2(v.x, v.y);
+      w.y = f2bf2(v.z, v.w);
     }
     *(uint2*)(act + off) = w;
   }

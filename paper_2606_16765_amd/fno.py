@@ -133,6 +133,38 @@ def field_scale(x, lo, hi, inverse=False):
     return x
 
 
+def forward_cost(batch=16, nx=128, ny=64, nz=64, cin=4, cout=4, width=32, layers=4, mx=16, my=16, mz=16,
+                 hidden=128):
+    """Work of one forward pass, for the roofline of the surrogate.
+
+    flops: the real contractions as the kernels execute them (complex values
+    as re/im pairs): per Fourier layer the z, y and x stages of the truncated
+    forward DFT, the per-mode complex channel mixing, the inverse x and y
+    stages, the c2r stage along z and the pointwise channel map; plus the
+    lift and the two-stage projection.  Zero padding of the MFMA tiles is not
+    counted.
+    min_bytes: the least HBM traffic of any implementation that keeps each
+    layer's intermediates on chip: every activation read and written once in
+    BF16, the network input (BF16) and output (FP32), and the BF16 spectral
+    weights once per pass."""
+    P = nx * ny * nz
+    MX, MY, MZ = 2 * mx, 2 * my, mz
+    M = MX * MY * MZ
+    W = width
+    per_layer = 2 * (W * nx * ny * nz * 2 * MZ            # z stage (r2c)
+                     + W * nx * MZ * 2 * ny * 2 * MY      # y stage
+                     + W * MY * MZ * 2 * nx * 2 * MX      # x stage
+                     + M * W * W * 4                      # complex mixing
+                     + W * MY * MZ * 2 * MX * 2 * nx      # inverse x
+                     + W * nx * MZ * 2 * MY * 2 * ny      # inverse y
+                     + W * nx * ny * 2 * MZ * nz          # c2r along z
+                     + P * W * W)                         # channel map
+    flops = batch * (layers * per_layer + 2 * P * cin * W + 2 * P * (W * hidden + hidden * cout))
+    act = W * P * 2
+    min_bytes = batch * (cin * P * 2 + act + layers * 2 * act + act + cout * P * 4) + layers * W * W * M * 2 * 2
+    return {"flops": int(flops), "min_bytes": int(min_bytes)}
+
+
 def bench_inference(batch=16, reps=10):
     """Forward time per batch at the full surrogate shape (128x64x64, width
     32, 4 layers, 32x32x16 retained modes, hidden 128), random input."""
