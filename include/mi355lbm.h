@@ -207,9 +207,11 @@ typedef struct fno_net fno_net;
 typedef struct {
   int32_t nx, ny, nz;       /* grid; powers of two, nx*ny*nz % 8192 == 0      */
   int32_t cin, cout;        /* input / output channels (4, 4)                 */
-  int32_t width;            /* channels of the Fourier layers (32), % 16 == 0 */
+  int32_t width;            /* channels of the Fourier layers (32), % 16 == 0,
+                               at most 64                                     */
   int32_t layers;           /* Fourier layers (4)                             */
-  int32_t mx, my, mz;       /* retained modes (16): powers of two, 2m <= n    */
+  int32_t mx, my, mz;       /* retained modes (16): powers of two, 2m <= n;
+                               2*my*mz >= 32 (>= 16 when width > 32)          */
   int32_t proj_hidden;      /* projection hidden width (128), % 16 == 0       */
   int32_t max_batch;        /* largest batch the workspaces are sized for     */
 } fno_params;

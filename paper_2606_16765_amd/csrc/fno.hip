@@ -8,12 +8,12 @@
 //   activations      [B][W][X][Y][Z]
 //   z stage out  A1  [B W X Y][part][kz]
 //   y stage out  A2  [B W X][part][ky][kz]
-//   modes            [m = (kx, ky, kz)][B][W][part]
+//   modes            [B][W][kx][part][ky][kz] (mode-minor; m = (kx, ky, kz))
 //   inverse x    R3  [B W][x][part][ky][kz]
 //   inverse y    R2  [B W X][y][part][kz]
-// A1, A2, R3 and R2 are BF16: each is read only as an MFMA operand, which is
-// rounded to BF16 (RNE) in any case, so storing it rounded changes no result
-// and halves the traffic of the intermediate stages.
+// A1, A2, the modes, R3 and R2 are BF16: each is read only as an MFMA
+// operand, which is rounded to BF16 (RNE) in any case, so storing it rounded
+// changes no result and halves the traffic of the intermediate stages.
 // Real embedding of a complex factor F = c - i s (forward) or c + i s
 // (inverse) for input part pi, output part po:
 //   forward  (0,0) c  (1,0) s   (0,1) -s  (1,1) c
@@ -83,12 +83,12 @@ struct fno_net {
   // activations and work buffers
   std::vector<uint16_t*> v;  // L + 1, BF16
   std::vector<float*> h;     // L, FP32 pre-activations
-  std::vector<float*> Vh;    // L, FP32 modes
+  std::vector<uint16_t*> Vh;  // L, BF16 modes (mode-minor)
   uint16_t *A1 = nullptr, *A2 = nullptr, *R3 = nullptr, *R2 = nullptr;  // BF16 DFT intermediates
-  float* Yh = nullptr;
+  uint16_t* Yh = nullptr;  // BF16 modes (mode-minor)
   float *h1 = nullptr, *y = nullptr, *gy = nullptr, *ga = nullptr, *gv = nullptr, *gvn = nullptr;
   uint16_t* a = nullptr;
-  float *Vg = nullptr;  // mode gradient
+  uint16_t* Vg = nullptr;  // mode gradient, BF16 mode-minor
   float* part = nullptr;
   int64_t part_elems = 0;
   float* part2 = nullptr;  // second-stage partials of the Gram reductions
@@ -306,7 +306,7 @@ static void fused_projection(fno_net* n, int B, const uint16_t* v, float* y) {
 }
 
 // truncated forward 3D DFT: v [B][W][P] (BF16 or FP32) -> modes [m][B][W][2]
-static int forward_dft(fno_net* n, int B, const void* v, bool v_bf16, const GtMat& Gz, float* modes) {
+static int forward_dft(fno_net* n, int B, const void* v, bool v_bf16, const GtMat& Gz, uint16_t* modes) {
   const int64_t W = n->W, X = n->X, Y = n->Y, Z = n->Z, MY = n->MY, MZ = n->MZ;
   int rc;
   CSpec c{};
@@ -323,11 +323,12 @@ static int forward_dft(fno_net* n, int B, const void* v, bool v_bf16, const GtMa
   c.out_so = 2 * MY * MZ; c.out_si = 1; c.out_sn1 = MZ; c.out_sn2 = MY * MZ; c.nd = 2; c.alpha = 1.f;
   if ((rc = contract(n, c))) return rc;
   // x: cols (b,w) x (ky,kz), k = (x, part) at stride MY*MZ -> modes
+  // [bw][kx][part][ky][kz], n = (kx, part) at stride MY*MZ
   c = CSpec{};
-  c.in = n->A2; c.in_bf16 = true; c.out = modes; c.g = &n->F3;
+  c.in = n->A2; c.in_bf16 = true; c.out = modes; c.out_bf16 = true; c.g = &n->F3;
   c.cols = (int64_t)B * W * MY * MZ; c.I = MY * MZ; c.in_so = X * 2 * MY * MZ; c.in_si = 1; c.in_sk1 = MY * MZ;
   c.kd = 1;
-  c.out_so = 2; c.out_si = (int64_t)B * W * 2; c.out_sn1 = MY * MZ * (int64_t)B * W * 2; c.out_sn2 = 1; c.nd = 2;
+  c.out_so = (int64_t)n->MX * 2 * MY * MZ; c.out_si = 1; c.out_sn1 = MY * MZ; c.nd = 1;
   c.alpha = 1.f;
   return contract(n, c);
 }
@@ -336,15 +337,15 @@ static int forward_dft(fno_net* n, int B, const void* v, bool v_bf16, const GtMa
 // with the z operand Gz (c2r with 1/N and c_kz, or its unscaled adjoint)
 // out may be null with Gz unused: then only the x and y stages run, leaving
 // the y-stage output in R2 for layer_end_kernel.
-static int inverse_dft(fno_net* n, int B, const float* modes, const GtMat& Gz, float* out, bool accumulate,
+static int inverse_dft(fno_net* n, int B, const uint16_t* modes, const GtMat& Gz, float* out, bool accumulate,
                        const float* gmul = nullptr) {
   const int64_t W = n->W, X = n->X, Y = n->Y, Z = n->Z, MY = n->MY, MZ = n->MZ;
   int rc;
   CSpec c{};
-  // x: cols (b,w) x (ky,kz); k = (kx, part): kx at stride MY*MZ*B*W*2, part at 1
-  c.in = modes; c.out = n->R3; c.out_bf16 = true; c.g = &n->I3;
-  c.cols = (int64_t)B * W * MY * MZ; c.I = MY * MZ; c.in_so = 2; c.in_si = (int64_t)B * W * 2;
-  c.in_sk1 = MY * MZ * (int64_t)B * W * 2; c.in_sk2 = 1; c.kd = 2;
+  // x: cols (b,w) x (ky,kz); k = (kx, part) at stride MY*MZ (mode-minor)
+  c.in = modes; c.in_bf16 = true; c.out = n->R3; c.out_bf16 = true; c.g = &n->I3;
+  c.cols = (int64_t)B * W * MY * MZ; c.I = MY * MZ; c.in_so = (int64_t)n->MX * 2 * MY * MZ; c.in_si = 1;
+  c.in_sk1 = MY * MZ; c.kd = 1;
   c.out_so = X * 2 * MY * MZ; c.out_si = 1; c.out_sn1 = MY * MZ; c.nd = 1; c.alpha = 1.f;
   if ((rc = contract(n, c))) return rc;
   // y: cols (b,w,x) x kz; k = (ky, part): ky at MZ, part at MY*MZ
@@ -504,6 +505,9 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
     return ffail(nullptr, LBM_EINVAL, "modes must be powers of two with 2m <= n (and mz <= nz/2)");
   const int64_t P = (int64_t)p.nx * p.ny * p.nz;
   if (P % 8192) return ffail(nullptr, LBM_EINVAL, "grid must hold a multiple of 8192 cells");
+  if (p.width > 64) return ffail(nullptr, LBM_EINVAL, "width must be at most 64");
+  if (2 * p.my * p.mz < (p.width <= 32 ? MixCfg<32>::MQ : MixCfg<64>::MQ))
+    return ffail(nullptr, LBM_EINVAL, "2 my mz must be at least 32 (16 for width above 32)");
   fno_net* n = new (std::nothrow) fno_net();
   if (!n) return ffail(nullptr, LBM_ENOMEM, "host allocation failed");
   n->p = p;
@@ -543,11 +547,11 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
   n->Vh.assign(n->L, nullptr);
   for (int l = 0; ok && l <= n->L; ++l) ok = A((void**)&n->v[l], (size_t)B * W * P * 2);
   for (int l = 0; ok && l < n->L; ++l)
-    ok = A((void**)&n->h[l], (size_t)B * W * P * 4) && A((void**)&n->Vh[l], (size_t)n->M * B * W * 2 * 4);
+    ok = A((void**)&n->h[l], (size_t)B * W * P * 4) && A((void**)&n->Vh[l], (size_t)n->M * B * W * 2 * 2);
   const int64_t rows = (int64_t)B * W * n->X * n->Y;
   ok = ok && A((void**)&n->A1, (size_t)rows * 2 * n->MZ * 2) &&
        A((void**)&n->A2, (size_t)B * W * n->X * 2 * n->MY * n->MZ * 2) &&
-       A((void**)&n->Yh, (size_t)n->M * B * W * 2 * 4) && A((void**)&n->Vg, (size_t)n->M * B * W * 2 * 4) &&
+       A((void**)&n->Yh, (size_t)n->M * B * W * 2 * 2) && A((void**)&n->Vg, (size_t)n->M * B * W * 2 * 2) &&
        A((void**)&n->R3, (size_t)B * W * n->X * 2 * n->MY * n->MZ * 2) &&
        A((void**)&n->R2, (size_t)rows * 2 * n->MZ * 2) && A((void**)&n->h1, (size_t)B * n->H * P * 4) &&
        A((void**)&n->a, (size_t)B * n->H * P * 2) && A((void**)&n->y, (size_t)B * p.cout * P * 4) &&
@@ -675,6 +679,31 @@ extern "C" int fno_get_params(fno_net* n, float* host, int64_t count) {
 // training keeps what the backward pass reads: FP32 pre-activations of
 // every Fourier layer and of the projection's hidden layer, and its BF16
 // activations; inference keeps only the BF16 activations of the layers.
+// per-mode complex channel mixing on mode-minor BF16 modes (MODE 0: by W,
+// MODE 1: by the conjugate transpose of W)
+template <int CM>
+static void launch_mix(fno_net* n, int mode, int B, const uint16_t* in, const uint16_t* w, uint16_t* out) {
+  const int64_t Q = n->MY * n->MZ;
+  const dim3 grid((unsigned)(n->MX * (Q / MixCfg<CM>::MQ))), blk(MIX_THREADS);
+  if (mode == 0) hipLaunchKernelGGL((mix_kernel<CM, 0>), grid, blk, 0, n->st, in, w, out, B, (int)n->W, n->MX, Q);
+  else hipLaunchKernelGGL((mix_kernel<CM, 1>), grid, blk, 0, n->st, in, w, out, B, (int)n->W, n->MX, Q);
+}
+static void mix(fno_net* n, int mode, int B, const uint16_t* in, const uint16_t* w, uint16_t* out) {
+  if (n->W <= 32) launch_mix<32>(n, mode, B, in, w, out);
+  else launch_mix<64>(n, mode, B, in, w, out);
+}
+// spectral weight gradient (overwrites gw)
+static void mix_grad(fno_net* n, int B, const uint16_t* v, const uint16_t* gy, float* gw) {
+  const int64_t Q = n->MY * n->MZ;
+  const dim3 blk(MIX_THREADS);
+  if (n->W <= 32)
+    hipLaunchKernelGGL((mix_grad_kernel<32>), dim3((unsigned)(n->MX * (Q / MixCfg<32>::MQ))), blk, 0, n->st, v, gy,
+                       gw, B, (int)n->W, n->MX, Q, 0);
+  else
+    hipLaunchKernelGGL((mix_grad_kernel<64>), dim3((unsigned)(n->MX * (Q / MixCfg<64>::MQ))), blk, 0, n->st, v, gy,
+                       gw, B, (int)n->W, n->MX, Q, 0);
+}
+
 static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout, bool training) {
   const int64_t W = n->W;
   int rc;
@@ -684,8 +713,7 @@ static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout, bool 
     return rc;
   for (int l = 0; l < n->L; ++l) {
     if ((rc = forward_dft(n, B, n->v[l], true, n->F1, n->Vh[l]))) return rc;
-    hipLaunchKernelGGL((mix_kernel<float, float, 0>), dim3((unsigned)n->M), dim3(64), 0, n->st, n->Vh[l],
-                       n->wspec + n->off_W[l], n->Yh, B, (int)W);
+    mix(n, 0, B, n->Vh[l], n->wspec + n->off_W[l], n->Yh);
     // h = R(W T v) + Wp v + bp; v' = GELU(h) (identity after the last layer)
     if (n->fused_layer_end) {
       if ((rc = inverse_dft(n, B, n->Yh, n->I1, nullptr, false))) return rc;
@@ -761,10 +789,8 @@ extern "C" int fno_loss_grad(fno_net* n, const uint16_t* x, const float* target,
       return rc;
     // gradient on the modes: (c_kz/N) T(gh)
     if ((rc = forward_dft(n, B, n->gv, false, n->F1a, n->Yh))) return rc;
-    hipLaunchKernelGGL((mix_grad_kernel<float>), dim3((unsigned)n->M), dim3(64), 0, n->st, n->Vh[l], n->Yh,
-                       n->grad + n->off_W[l], B, (int)W);
-    hipLaunchKernelGGL((mix_kernel<float, float, 1>), dim3((unsigned)n->M), dim3(64), 0, n->st, n->Yh,
-                       n->wspec + n->off_W[l], n->Vg, B, (int)W);
+    mix_grad(n, B, n->Vh[l], n->Yh, n->grad + n->off_W[l]);
+    mix(n, 1, B, n->Yh, n->wspec + n->off_W[l], n->Vg);
     if ((rc = pointwise(n, B, n->gv, false, (int)W, n->gvn, false, (int)W, &n->Gwpt[l], nullptr, false))) return rc;
     // gvn = dL/dv[l]; for l >= 1 it becomes dL/dh[l - 1] = GELU'(h[l - 1]) dL/dv[l]
     if ((rc = inverse_dft(n, B, n->Vg, n->I1a, n->gvn, true, l >= 1 ? n->h[l - 1] : nullptr))) return rc;

@@ -601,96 +601,198 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
 }
 
 // ------------------------------------------------------------------ mixing
-// Per retained mode m, batch rows b (up to 16 per pass), complex channels:
-//   Y[m][b][o] = sum_c V[m][b][c] W[m][c][o]                      (MODE 0)
-//   gV[m][b][c] = sum_o gY[m][b][o] conj(W[m][c][o])              (MODE 1)
-// complex values stored as (re, im) pairs; W in BF16 [m][c][o][2].
-// As a real contraction over (c, part) -> (o, part) with the real
-// embedding [[Wr, Wi], [-Wi, Wr]] (MODE 0) or its transpose (MODE 1).
-template <typename InT, typename OutT, int MODE>
-__global__ __launch_bounds__(64) void mix_kernel(const InT* __restrict__ in, const uint16_t* __restrict__ w,
-                                                 OutT* __restrict__ out, int B, int C) {
-  const int m = blockIdx.x, lane = threadIdx.x;
-  const int64_t blk = (int64_t)B * C * 2;  // per-mode block of in / out
-  const uint16_t* wm = w + (int64_t)m * C * C * 2;
-  const int K = 2 * C;  // (c, part) = 2c + part
-  for (int b0 = 0; b0 < B; b0 += 16) {
-    const int brow = b0 + (lane & 15);
-    for (int nt = 0; nt < K / 16; ++nt) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      const int ncol = nt * 16 + (lane & 15);  // output (o, part') = 2o + p'
-      const int o = ncol >> 1, po = ncol & 1;
-      for (int k0 = 0; k0 < K; k0 += 32) {
-        bf16x8 av, bv;
+// Retained modes are stored mode-minor in BF16, [B][C][MX][2][Q] with
+// Q = MY * MZ and mode m = kx * Q + q (q = ky * MZ + kz), the layout of the
+// DFT intermediates: the x-stage DFT and its inverse then read and write
+// whole q-runs.  A mixing block takes one kx and MQ consecutive q (MQ modes)
+// for up to 16 batch rows per pass.  It stages the [MQ][rows] slab in LDS
+// from 16-byte loads of 2 MQ-byte q-runs, runs each mode's product on MFMA
+// (one mode per wave at a time), and writes the result slab back the same
+// way.  The capacity class CM bounds the channel count C (C <= CM,
+// C % 16 == 0); MQ = 32 for CM = 32 and 16 for CM = 64.
+constexpr int MIX_B = 16;          // batch rows per pass
+constexpr int MIX_THREADS = 512;   // 8 waves
+template <int CM> struct MixCfg {
+  static constexpr int MQ = CM <= 32 ? 32 : 16;
+  static constexpr int PITCH = MIX_B * 2 * CM + 8;  // slab row of one mode (BF16), 16-byte multiple
+};
+
+// slab[ql][ri] = src(b0 + b, k, q0 + ql) for b < nb (0 beyond), k = 2c + part,
+// ri = b * 2C + k, or k * 16 + b when KB is set
+template <int CM, bool KB>
+__device__ __forceinline__ void mix_slab_load(const uint16_t* __restrict__ src, uint16_t* slab, int pitch, int b0,
+                                              int nb, int C, int MX, int64_t Q, int kx, int64_t q0) {
+  constexpr int MQ = MixCfg<CM>::MQ, HQ = MQ / 8;
+  const int K = 2 * C;
+  for (int idx = threadIdx.x; idx < MIX_B * K * HQ; idx += MIX_THREADS) {
+    const int h = idx % HQ, r = idx / HQ;
+    const int b = r / K, k = r - b * K;
+    uint4 v = {0u, 0u, 0u, 0u};
+    if (b < nb)
+      v = *(const uint4*)(src + ((((int64_t)(b0 + b) * C + (k >> 1)) * MX + kx) * 2 + (k & 1)) * Q + q0 + 8 * h);
+    const int ri = KB ? k * MIX_B + b : r;
+    const uint32_t u[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int kk = k0 + 8 * (lane >> 4) + q;  // input (c, part) = 2c + p
-          av[q] = brow < B ? __builtin_bit_cast(__bf16, to_bf(in[(int64_t)m * blk + (int64_t)brow * K + kk]))
-                           : (__bf16)0.0f;
-          const int c = kk >> 1, pi = kk & 1;
-          float wr, wi;
-          if (MODE == 0) {  // element ((c,pi), (o,po)) of [[Wr, Wi], [-Wi, Wr]]
-            wr = bf2f(wm[((int64_t)c * C + o) * 2]);
-            wi = bf2f(wm[((int64_t)c * C + o) * 2 + 1]);
-          } else {          // transpose: element ((o',pi), (c',po)) = emb((c',po), (o',pi))
-            wr = bf2f(wm[((int64_t)o * C + c) * 2]);
-            wi = bf2f(wm[((int64_t)o * C + c) * 2 + 1]);
-          }
-          float e;
-          if (MODE == 0) e = (pi == po) ? wr : (pi == 0 ? wi : -wi);
-          else e = (pi == po) ? wr : (pi == 0 ? -wi : wi);
-          bv[q] = (__bf16)e;
-        }
-        acc = mfma16(av, bv, acc);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int b = b0 + 4 * (lane >> 4) + r;
-        if (b < B) out[(int64_t)m * blk + (int64_t)b * K + ncol] = from_f<OutT>(acc[r]);
-      }
-    }
+    for (int i = 0; i < 8; ++i) slab[(8 * h + i) * pitch + ri] = (uint16_t)(u[i >> 1] >> (16 * (i & 1)));
   }
 }
 
-// Spectral weight gradient, per mode: gW[m][c][o] += sum_b conj(V[b][c]) gY[b][o]
-// as R[(c,p)][(o,p')] = sum_b V[b][(c,p)] gY[b][(o,p')] (K = batch, zero
-// padded to 32), then gWr = R00 + R11, gWi = R01 - R10.
-template <typename InT>
-__global__ __launch_bounds__(64) void mix_grad_kernel(const InT* __restrict__ v, const InT* __restrict__ gy,
-                                                      float* __restrict__ gw, int B, int C) {
-  const int m = blockIdx.x, lane = threadIdx.x;
-  const int64_t blk = (int64_t)B * C * 2;
-  const int K2 = 2 * C;
-  float* g = gw + (int64_t)m * C * C * 2;
-  for (int rt = 0; rt < K2 / 16; ++rt) {
-    for (int ct = 0; ct < K2 / 16; ++ct) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      for (int b0 = 0; b0 < B; b0 += 32) {
-        bf16x8 av, bv;
+// Per mode m, batch rows b, complex channels:
+//   Y[b][o] = sum_c V[b][c] W[m][c][o]                      (MODE 0)
+//   gV[b][c] = sum_o gY[b][o] conj(W[m][c][o])              (MODE 1)
+// W in BF16 [m][c][o][2] (re, im).  As a real contraction over
+// k = (c, part) -> n = (o, part') with the embedding [[Wr, Wi], [-Wi, Wr]]
+// (MODE 0) or its transpose (MODE 1).  in and out are mode-minor BF16.
+// Grid: MX * Q / MQ blocks of MIX_THREADS.
+template <int CM, int MODE>
+__global__ __launch_bounds__(MIX_THREADS) void mix_kernel(const uint16_t* __restrict__ in,
+                                                          const uint16_t* __restrict__ w,
+                                                          uint16_t* __restrict__ out, int B, int C, int MX,
+                                                          int64_t Q) {
+  constexpr int MQ = MixCfg<CM>::MQ, HQ = MQ / 8, PITCH = MixCfg<CM>::PITCH;
+  __shared__ __attribute__((aligned(16))) uint16_t slab[MQ * PITCH];
+  const int nqb = (int)(Q / MQ);
+  const int kx = blockIdx.x / nqb;
+  const int64_t q0 = (int64_t)(blockIdx.x % nqb) * MQ;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
+  const int K = 2 * C;  // also N
+  for (int b0 = 0; b0 < B; b0 += MIX_B) {
+    const int nb = min(MIX_B, B - b0);
+    mix_slab_load<CM, false>(in, slab, PITCH, b0, nb, C, MX, Q, kx, q0);
+    __syncthreads();
+    for (int ql = wave; ql < MQ; ql += MIX_THREADS / 64) {
+      const uint16_t* wm = w + ((int64_t)kx * Q + q0 + ql) * C * C * 2;
+      uint16_t* row = slab + ql * PITCH;
+      f32x4 acc[CM / 8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int b = b0 + 8 * (lane >> 4) + q;
-          const int row = rt * 16 + (lane & 15), col = ct * 16 + (lane & 15);
-          av[q] = b < B ? __builtin_bit_cast(__bf16, to_bf(v[(int64_t)m * blk + (int64_t)b * K2 + row])) : (__bf16)0.0f;
-          bv[q] = b < B ? __builtin_bit_cast(__bf16, to_bf(gy[(int64_t)m * blk + (int64_t)b * K2 + col])) : (__bf16)0.0f;
+      for (int nt = 0; nt < CM / 8; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int ks = 0; ks < K / 32; ++ks) {
+        // A: row b = l16, k = 32 ks + 8 g + j
+        const bf16x8 av = *(const bf16x8*)(row + l16 * K + ks * 32 + 8 * g);
+#pragma unroll
+        for (int nt = 0; nt < CM / 8; ++nt) {
+          if (nt * 16 >= K) break;
+          const int n = nt * 16 + l16, o = n >> 1, po = n & 1;
+          // B: col n, k = 32 ks + 8 g + j = (c, pi) with c = 16 ks + 4 g + j / 2, pi = j % 2
+          uint16_t e[8];
+          if (MODE == 0) {
+            // element ((c, pi), (o, po)): po = 0 -> (Wr, -Wi), po = 1 -> (Wi, Wr)
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+              const uint32_t wv = *(const uint32_t*)(wm + ((int64_t)(ks * 16 + 4 * g + cc) * C + o) * 2);
+              const uint16_t wr = (uint16_t)(wv & 0xffffu), wi = (uint16_t)(wv >> 16);
+              e[2 * cc] = po ? wi : wr;
+              e[2 * cc + 1] = po ? wr : (uint16_t)(wi ^ 0x8000u);
+            }
+          } else {
+            // k = (o', pi), n = (c', po): W[c'][o'] for four consecutive o';
+            // element: po = 0 -> (Wr, Wi), po = 1 -> (-Wi, Wr)
+            const uint4 wv = *(const uint4*)(wm + ((int64_t)o * C + ks * 16 + 4 * g) * 2);
+            const uint32_t u[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+              const uint16_t wr = (uint16_t)(u[cc] & 0xffffu), wi = (uint16_t)(u[cc] >> 16);
+              e[2 * cc] = po ? (uint16_t)(wi ^ 0x8000u) : wr;
+              e[2 * cc + 1] = po ? wr : wi;
+            }
+          }
+          bf16x8 bv;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) bv[j] = __builtin_bit_cast(__bf16, e[j]);
+          acc[nt] = mfma16(av, bv, acc[nt]);
         }
-        acc = mfma16(av, bv, acc);
       }
-      // lane holds R[row = rt*16 + 4*(lane>>4) + r][col = ct*16 + (lane&15)]
-      const int col = ct * 16 + (lane & 15);
-      const float nb0 = __shfl_xor(acc[0], 1), nb1 = __shfl_xor(acc[1], 1);
-      const float nb2 = __shfl_xor(acc[2], 1), nb3 = __shfl_xor(acc[3], 1);
-      if ((col & 1) == 0) {
-        const int o = col >> 1;
-        // rows r = 0,1 are (c0, re), (c0, im); rows 2,3 are (c0+1, re), (c0+1, im)
-        const int c0 = (rt * 16 + 4 * (lane >> 4)) >> 1;
-        // own: R[(c,0)][(o,0)] = acc[0], R[(c,1)][(o,0)] = acc[1]; neighbour (o,1): nb0, nb1
-        g[((int64_t)c0 * C + o) * 2] += acc[0] + nb1;
-        g[((int64_t)c0 * C + o) * 2 + 1] += nb0 - acc[1];
-        g[((int64_t)(c0 + 1) * C + o) * 2] += acc[2] + nb3;
-        g[((int64_t)(c0 + 1) * C + o) * 2 + 1] += nb2 - acc[3];
+      // D: col n = 16 nt + l16, row b = 4 g + r; the mode's own slab row is
+      // overwritten only by this wave, after its last read of it
+#pragma unroll
+      for (int nt = 0; nt < CM / 8; ++nt) {
+        if (nt * 16 >= K) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) row[(4 * g + r) * K + nt * 16 + l16] = f2bf(acc[nt][r]);
       }
     }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < MIX_B * K * HQ; idx += MIX_THREADS) {
+      const int h = idx % HQ, r = idx / HQ;
+      const int b = r / K, k = r - b * K;
+      if (b >= nb) continue;
+      uint32_t u[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        u[i] = (uint32_t)slab[(8 * h + 2 * i) * PITCH + r] | ((uint32_t)slab[(8 * h + 2 * i + 1) * PITCH + r] << 16);
+      *(uint4*)(out + ((((int64_t)(b0 + b) * C + (k >> 1)) * MX + kx) * 2 + (k & 1)) * Q + q0 + 8 * h) =
+          uint4{u[0], u[1], u[2], u[3]};
+    }
+    __syncthreads();
+  }
+}
+
+// Spectral weight gradient, per mode: gW[m][c][o] (+)= sum_b conj(V[b][c]) gY[b][o]
+// as R[(c,p)][(o,p')] = sum_b V[b][(c,p)] gY[b][(o,p')] (K = batch rows,
+// 16 per pass, zero padded to 32), then gWr = R00 + R11, gWi = R01 - R10.
+// V and gY are mode-minor BF16; gw is FP32 [m][c][o][2], overwritten unless
+// accumulate is set (later passes over the batch always add).
+template <int CM>
+__global__ __launch_bounds__(MIX_THREADS) void mix_grad_kernel(const uint16_t* __restrict__ v,
+                                                               const uint16_t* __restrict__ gy,
+                                                               float* __restrict__ gw, int B, int C, int MX,
+                                                               int64_t Q, int accumulate) {
+  constexpr int MQ = MixCfg<CM>::MQ, PITCH = MixCfg<CM>::PITCH;
+  __shared__ __attribute__((aligned(16))) uint16_t sv[MQ * PITCH];
+  __shared__ __attribute__((aligned(16))) uint16_t sy[MQ * PITCH];
+  const int nqb = (int)(Q / MQ);
+  const int kx = blockIdx.x / nqb;
+  const int64_t q0 = (int64_t)(blockIdx.x % nqb) * MQ;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
+  const int K2 = 2 * C;
+  constexpr int NT = CM / 8;
+  for (int b0 = 0; b0 < B; b0 += MIX_B) {
+    const int nb = min(MIX_B, B - b0);
+    mix_slab_load<CM, true>(v, sv, PITCH, b0, nb, C, MX, Q, kx, q0);
+    mix_slab_load<CM, true>(gy, sy, PITCH, b0, nb, C, MX, Q, kx, q0);
+    __syncthreads();
+    for (int ql = wave; ql < MQ; ql += MIX_THREADS / 64) {
+      // A: row (c, p) = 16 rt + l16, k = b = 8 g + j (g < 2; zero beyond 16)
+      bf16x8 av[NT], bv[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        av[t] = bf16x8{};
+        bv[t] = bf16x8{};
+        if (t * 16 < K2 && g < 2) {
+          av[t] = *(const bf16x8*)(sv + ql * PITCH + (t * 16 + l16) * MIX_B + 8 * g);
+          bv[t] = *(const bf16x8*)(sy + ql * PITCH + (t * 16 + l16) * MIX_B + 8 * g);
+        }
+      }
+      float* gm = gw + ((int64_t)kx * Q + q0 + ql) * C * C * 2;
+      const bool add = accumulate || b0 > 0;
+#pragma unroll
+      for (int rt = 0; rt < NT; ++rt) {
+        if (rt * 16 >= K2) break;
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
+          if (ct * 16 >= K2) break;
+          const f32x4 acc = mfma16(av[rt], bv[ct], f32x4{0.f, 0.f, 0.f, 0.f});
+          // lane holds R[row = 16 rt + 4 g + r][col = 16 ct + l16]
+          const float nb0 = __shfl_xor(acc[0], 1), nb1 = __shfl_xor(acc[1], 1);
+          const float nb2 = __shfl_xor(acc[2], 1), nb3 = __shfl_xor(acc[3], 1);
+          if ((l16 & 1) == 0) {
+            const int o = (ct * 16 + l16) >> 1;
+            const int c0 = (rt * 16 + 4 * g) >> 1;
+            // rows r = 0, 1: (c0, re), (c0, im); rows 2, 3: (c0 + 1, re), (c0 + 1, im)
+            float2* d0 = (float2*)(gm + ((int64_t)c0 * C + o) * 2);
+            float2* d1 = (float2*)(gm + ((int64_t)(c0 + 1) * C + o) * 2);
+            float2 x0 = {acc[0] + nb1, nb0 - acc[1]}, x1 = {acc[2] + nb3, nb2 - acc[3]};
+            if (add) {
+              const float2 p0 = *d0, p1 = *d1;
+              x0.x += p0.x; x0.y += p0.y; x1.x += p1.x; x1.y += p1.y;
+            }
+            *d0 = x0;
+            *d1 = x1;
+          }
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 

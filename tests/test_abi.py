@@ -56,6 +56,13 @@ def test_invalid_parameters_rejected_without_device_work():
     fp.proj_hidden, fp.max_batch = 16, 1
     assert L.fno_create(ctypes.byref(fp), 0, None, ctypes.byref(h)) == 1  # 48 is not a power of two
     assert b"powers of two" in L.fno_last_error(None)
+    fp.nx = 64
+    fp.width = 80
+    assert L.fno_create(ctypes.byref(fp), 0, None, ctypes.byref(h)) == 1  # wider than the mixing kernels
+    assert b"at most 64" in L.fno_last_error(None)
+    fp.width, fp.my, fp.mz = 16, 2, 4
+    assert L.fno_create(ctypes.byref(fp), 0, None, ctypes.byref(h)) == 1  # 2 my mz = 16 < 32
+    assert b"2 my mz" in L.fno_last_error(None)
 
 
 def test_binding_raises_on_error():
