@@ -306,16 +306,20 @@ static void fused_projection(fno_net* n, int B, const uint16_t* v, float* y) {
 }
 
 // truncated forward 3D DFT: v [B][W][P] (BF16 or FP32) -> modes [m][B][W][2]
-static int forward_dft(fno_net* n, int B, const void* v, bool v_bf16, const GtMat& Gz, uint16_t* modes) {
+// (z_done: A1 already holds the z stage, written by the previous layer end)
+static int forward_dft(fno_net* n, int B, const void* v, bool v_bf16, const GtMat& Gz, uint16_t* modes,
+                       bool z_done = false) {
   const int64_t W = n->W, X = n->X, Y = n->Y, Z = n->Z, MY = n->MY, MZ = n->MZ;
   int rc;
   CSpec c{};
   // z: rows (b,w,x,y), k = z contiguous -> A1[row][part][kz]
-  c = CSpec{};
-  c.in = v; c.in_bf16 = v_bf16; c.out = n->A1; c.out_bf16 = true; c.g = &Gz;
-  c.cols = (int64_t)B * W * X * Y; c.I = 1; c.in_so = Z; c.in_sk1 = 1; c.kd = 1;
-  c.out_so = 2 * MZ; c.out_sn1 = 1; c.nd = 1; c.alpha = 1.f; c.kcontig = true;
-  if ((rc = contract(n, c))) return rc;
+  if (!z_done) {
+    c = CSpec{};
+    c.in = v; c.in_bf16 = v_bf16; c.out = n->A1; c.out_bf16 = true; c.g = &Gz;
+    c.cols = (int64_t)B * W * X * Y; c.I = 1; c.in_so = Z; c.in_sk1 = 1; c.kd = 1;
+    c.out_so = 2 * MZ; c.out_sn1 = 1; c.nd = 1; c.alpha = 1.f; c.kcontig = true;
+    if ((rc = contract(n, c))) return rc;
+  }
   // y: cols (b,w,x) x kz, k = (y, part) at stride MZ -> A2[bwx][part][ky][kz]
   c = CSpec{};
   c.in = n->A1; c.in_bf16 = true; c.out = n->A2; c.out_bf16 = true; c.g = &n->F2;
@@ -441,10 +445,12 @@ static int gram(fno_net* n, const XT* Xd, int A, const YT* Yd, int Cc, int B, fl
 static void elementwise_grid(int64_t cnt, dim3& g) { g = dim3((unsigned)((cnt + 255) / 256)); }
 
 // Refresh the BF16 operands from the FP32 master parameters.
-static int refresh(fno_net* n) {
+// operands derived from the FP32 parameters (bf16_done: the BF16 working
+// copy is already current, written by the optimizer step)
+static int refresh(fno_net* n, bool bf16_done = false) {
   dim3 g;
   elementwise_grid(n->nparam, g);
-  hipLaunchKernelGGL(to_bf16_kernel, g, dim3(256), 0, n->st, n->theta, n->wspec, n->nparam);
+  if (!bf16_done) hipLaunchKernelGGL(to_bf16_kernel, g, dim3(256), 0, n->st, n->theta, n->wspec, n->nparam);
   auto mk = [&](GtMat& m, int64_t off, int rows, int cols, int tr) {
     const int64_t cnt = (int64_t)m.np * m.kp;
     dim3 gg;
@@ -711,8 +717,12 @@ static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout, bool 
   if ((rc = pointwise(n, B, x, true, n->p.cin, nullptr, false, (int)W, &n->Glift, n->theta + n->off_p, false, false,
                       n->v[0], false)))
     return rc;
+  // the layer end can run the next layer's z stage at the production shape
+  const bool fuse_z = n->fused_layer_end && n->Z == 64 && W == 32 && 2 * n->MZ == 32 && n->F1.kp >= 64;
+  bool z_done = false;
   for (int l = 0; l < n->L; ++l) {
-    if ((rc = forward_dft(n, B, n->v[l], true, n->F1, n->Vh[l]))) return rc;
+    if ((rc = forward_dft(n, B, n->v[l], true, n->F1, n->Vh[l], z_done))) return rc;
+    z_done = false;
     mix(n, 0, B, n->Vh[l], n->wspec + n->off_W[l], n->Yh);
     // h = R(W T v) + Wp v + bp; v' = GELU(h) (identity after the last layer)
     if (n->fused_layer_end) {
@@ -721,6 +731,10 @@ static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout, bool 
       e.v = n->v[l]; e.r2 = n->R2; e.gwp = n->Gwp[l].d; e.gi1 = n->I1.d; e.gi1_kp = n->I1.kp;
       e.bias = n->theta + n->off_bp[l]; e.h = training ? n->h[l] : nullptr; e.act = n->v[l + 1];
       e.P = n->P; e.W = (int)W; e.Z = n->Z; e.K2 = 2 * n->MZ; e.act_gelu = l < n->L - 1 ? 1 : 0;
+      if (fuse_z && l < n->L - 1) {
+        e.gz = n->F1.d; e.gz_kp = n->F1.kp; e.a1 = n->A1;
+        z_done = true;
+      }
       const dim3 grid((unsigned)((int64_t)B * n->P / PW_J));
       if (W <= 16) hipLaunchKernelGGL(layer_end_kernel<1>, grid, dim3(256), 0, n->st, e);
       else hipLaunchKernelGGL(layer_end_kernel<2>, grid, dim3(256), 0, n->st, e);
@@ -823,8 +837,8 @@ extern "C" int fno_adam_step(fno_net* n, float lr) {
   dim3 g;
   elementwise_grid(n->nparam, g);
   hipLaunchKernelGGL(adam_kernel, g, dim3(256), 0, n->st, n->theta, n->grad, n->am, n->av, n->nparam, lr, (float)b1,
-                     (float)b2, c1, c2, 1e-8f);
-  return refresh(n);
+                     (float)b2, c1, c2, 1e-8f, n->wspec);
+  return refresh(n, true);
 }
 
 extern "C" int fno_train_step(fno_net* n, const uint16_t* x, const float* target, const uint8_t* mask, int32_t B,

@@ -385,12 +385,17 @@ __global__ __launch_bounds__(256) void pw_kernel(PwArgs a) {
 //              + sum_k R2[b][w][x][y][k] I1[k][z]          (c2r along z)
 //              + bp[w]
 // with p = (x, y, z), z fastest, k = (part, kz) the 2 mz contiguous values
-// of the y stage's output.  Both products share one set of MFMA
-// accumulators: in a 16 x 16 tile the rows are channels w and the columns
-// 16 consecutive z of one (x, y) row, so the channel map reads v through
-// LDS and the c2r reads the R2 row of (w, x, y) as its A operand directly.
-// Epilogue as pw_kernel: h stored when store_h (training), its activation
-// (GELU or identity) stored as BF16.
+// of the y stage's output.  In a 16 x 16 MFMA tile the rows are channels w
+// and the columns 16 consecutive z of one (x, y) row, so the channel map
+// reads v through LDS and the c2r reads the R2 row of (w, x, y) as its A
+// operand directly; each product has its own accumulators, added in the
+// epilogue, which stages the sum through LDS: h stored when requested
+// (training), its activation (GELU or identity) stored as BF16.
+// When a1 is set (Z = 64, W = 32, 2 mz = 32) the block also runs the next
+// layer's truncated z-DFT on the activation tile it holds:
+//   A1[b][w][x][y][k] = sum_z act[b][w][x][y][z] Fz[k][z]
+// with the same operand roles and accumulation order as the stand-alone
+// contraction, so the next layer skips its z stage.
 struct LayerEndArgs {
   const uint16_t* v;    // [B][W][P] BF16 layer input
   const uint16_t* r2;   // [B W X Y][2 mz] y-stage output (BF16)
@@ -403,13 +408,20 @@ struct LayerEndArgs {
   int64_t P;
   int32_t W, Z, K2;     // width, nz, 2 mz
   int32_t act_gelu;
+  const uint16_t* gz;   // next layer's z-DFT operand [2 mz padded][kp] BF16 (rows k, columns z)
+  int32_t gz_kp;
+  uint16_t* a1;         // next layer's z-stage output [B W X Y][2 mz] BF16, or null
 };
 
 template <int NT>  // NT = ceil(W / 16), W <= 32
 __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
-  __shared__ __attribute__((aligned(16))) float lds[32 * PW_DS];
+  // the v tile [256 points][PW_TS], then the FP32 result tile [32][PW_DS];
+  // after it the BF16 activation tile [32][PW_J + 8] for the fused z-DFT
+  constexpr int AP = PW_J + 8;
+  __shared__ __attribute__((aligned(16))) float lds[32 * PW_DS + 32 * AP / 2];
   uint16_t* tile = (uint16_t*)lds;
   float* dst = lds;
+  uint16_t* at = (uint16_t*)(lds + 32 * PW_DS);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4;
   const int64_t j0 = (int64_t)blockIdx.x * PW_J;
   const int64_t b = j0 / a.P, p0 = j0 % a.P;
@@ -489,13 +501,14 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
     }
   }
   __syncthreads();  // the v tile is dead: its LDS becomes the result tile
+  const int l16 = lane & 15;
 #pragma unroll
   for (int h = 0; h < NT; ++h)
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        dst[(h * 16 + 4 * g + r) * PW_DS + wave * 64 + c * 16 + (lane & 15)] = acc[h][c][r] + acc2[h][c][r];
+        dst[(h * 16 + 4 * g + r) * PW_DS + wave * 64 + c * 16 + l16] = acc[h][c][r] + acc2[h][c][r];
   __syncthreads();
   float* hout = a.h ? a.h + b * a.W * a.P + p0 : nullptr;
   uint16_t* act = a.act + b * a.W * a.P + p0;
@@ -517,6 +530,40 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
       w.y = f2bf2(v.z, v.w);
     }
     *(uint2*)(act + off) = w;
+    if (a.a1) *(uint2*)(at + n * AP + p4) = w;
+  }
+  if (a.a1) {
+    __syncthreads();
+    // columns (w, row) = 16 ct + l16 with w = col / 4 and row = col % 4 the
+    // (x, y) row within the block; rows of the result k = 16 rt + 4 g + r
+    f32x4 za[2][2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) za[rt][cc] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      bf16x8 ga[2];
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) ga[rt] = *(const bf16x8*)(a.gz + (rt * 16 + l16) * a.gz_kp + ks * 32 + 8 * g);
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) {
+        const int col = (2 * wave + cc) * 16 + l16;
+        const bf16x8 bv = *(const bf16x8*)(at + (col >> 2) * AP + (col & 3) * 64 + ks * 32 + 8 * g);
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) za[rt][cc] = mfma16(ga[rt], bv, za[rt][cc]);
+      }
+    }
+    const int64_t xy0 = p0 / 64, XY = a.P / 64;
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+      const int col = (2 * wave + cc) * 16 + l16;
+      uint16_t* d1 = a.a1 + ((b * a.W + (col >> 2)) * XY + xy0 + (col & 3)) * 32;
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+        *(uint2*)(d1 + rt * 16 + 4 * g) = uint2{f2bf2(za[rt][cc][0], za[rt][cc][1]),
+                                                f2bf2(za[rt][cc][2], za[rt][cc][3])};
+    }
   }
 }
 
@@ -983,8 +1030,10 @@ __global__ __launch_bounds__(256) void mse_kernel(const float* y, const float* t
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// (also refreshes the BF16 working copy wbf of the updated parameters)
 __global__ __launch_bounds__(256) void adam_kernel(float* theta, const float* g, float* m, float* v, int64_t n,
-                                                   float lr, float b1, float b2, float c1, float c2, float eps) {
+                                                   float lr, float b1, float b2, float c1, float c2, float eps,
+                                                   uint16_t* wbf) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
@@ -992,7 +1041,9 @@ __global__ __launch_bounds__(256) void adam_kernel(float* theta, const float* g,
   const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
   m[i] = mi;
   v[i] = vi;
-  theta[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+  const float th = theta[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+  theta[i] = th;
+  wbf[i] = f2bf(th);
 }
 
 // BF16 copy of a parameter block
