@@ -736,8 +736,8 @@ static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout, bool 
         z_done = true;
       }
       const dim3 grid((unsigned)((int64_t)B * n->P / PW_J));
-      if (W <= 16) hipLaunchKernelGGL(layer_end_kernel<1>, grid, dim3(256), 0, n->st, e);
-      else hipLaunchKernelGGL(layer_end_kernel<2>, grid, dim3(256), 0, n->st, e);
+      if (W <= 16) hipLaunchKernelGGL((layer_end_kernel<1, uint16_t>), grid, dim3(256), 0, n->st, e);
+      else hipLaunchKernelGGL((layer_end_kernel<2, uint16_t>), grid, dim3(256), 0, n->st, e);
     } else {
       if ((rc = inverse_dft(n, B, n->Yh, n->I1, n->h[l], false))) return rc;
       if ((rc = pointwise(n, B, n->v[l], true, (int)W, n->h[l], false, (int)W, &n->Gwp[l], n->theta + n->off_bp[l],
@@ -805,9 +805,23 @@ extern "C" int fno_loss_grad(fno_net* n, const uint16_t* x, const float* target,
     if ((rc = forward_dft(n, B, n->gv, false, n->F1a, n->Yh))) return rc;
     mix_grad(n, B, n->Vh[l], n->Yh, n->grad + n->off_W[l]);
     mix(n, 1, B, n->Yh, n->wspec + n->off_W[l], n->Vg);
-    if ((rc = pointwise(n, B, n->gv, false, (int)W, n->gvn, false, (int)W, &n->Gwpt[l], nullptr, false))) return rc;
-    // gvn = dL/dv[l]; for l >= 1 it becomes dL/dh[l - 1] = GELU'(h[l - 1]) dL/dv[l]
-    if ((rc = inverse_dft(n, B, n->Vg, n->I1a, n->gvn, true, l >= 1 ? n->h[l - 1] : nullptr))) return rc;
+    // gvn = dL/dv[l] = Wp^T gv + (adjoint of the truncated DFT path); for
+    // l >= 1 it becomes dL/dh[l - 1] = GELU'(h[l - 1]) dL/dv[l]
+    const float* gmul = l >= 1 ? n->h[l - 1] : nullptr;
+    if (n->fused_layer_end) {
+      if ((rc = inverse_dft(n, B, n->Vg, n->I1a, nullptr, false))) return rc;
+      LayerEndArgs e{};
+      e.v = n->gv; e.r2 = n->R2; e.gwp = n->Gwpt[l].d; e.gi1 = n->I1a.d; e.gi1_kp = n->I1a.kp;
+      e.bias = nullptr; e.h = n->gvn; e.act = nullptr; e.gmul = gmul;
+      e.P = n->P; e.W = (int)W; e.Z = n->Z; e.K2 = 2 * n->MZ; e.act_gelu = 0;
+      const dim3 grid((unsigned)((int64_t)B * n->P / PW_J));
+      if (W <= 16) hipLaunchKernelGGL((layer_end_kernel<1, float>), grid, dim3(256), 0, n->st, e);
+      else hipLaunchKernelGGL((layer_end_kernel<2, float>), grid, dim3(256), 0, n->st, e);
+    } else {
+      if ((rc = pointwise(n, B, n->gv, false, (int)W, n->gvn, false, (int)W, &n->Gwpt[l], nullptr, false)))
+        return rc;
+      if ((rc = inverse_dft(n, B, n->Vg, n->I1a, n->gvn, true, gmul))) return rc;
+    }
     std::swap(n->gv, n->gvn);
   }
   if ((rc = gram(n, n->gv, (int)W, x, n->p.cin, B, n->grad + n->off_P, false, n->grad + n->off_p))) return rc;

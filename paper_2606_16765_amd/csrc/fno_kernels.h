@@ -396,15 +396,20 @@ __global__ __launch_bounds__(256) void pw_kernel(PwArgs a) {
 //   A1[b][w][x][y][k] = sum_z act[b][w][x][y][z] Fz[k][z]
 // with the same operand roles and accumulation order as the stand-alone
 // contraction, so the next layer skips its z stage.
+// The backward pass uses the same kernel on FP32 input (InT = float) with
+// the transposed channel map, the adjoint c2r operand, no bias, gmul set
+// (the result times GELU'(gmul), the pre-activation of the layer below)
+// and only the FP32 output h.
 struct LayerEndArgs {
-  const uint16_t* v;    // [B][W][P] BF16 layer input
+  const void* v;        // [B][W][P] layer input, BF16 or FP32 (InT)
   const uint16_t* r2;   // [B W X Y][2 mz] y-stage output (BF16)
   const uint16_t* gwp;  // [64][32] BF16 Wp (rows w_out, k = w_in), zero padded
   const uint16_t* gi1;  // [Z padded to 64][32] BF16 c2r operand (rows z, k), zero padded
   int32_t gi1_kp;
   const float* bias;    // [W]
   float* h;             // [B][W][P] or null
-  uint16_t* act;        // [B][W][P]
+  uint16_t* act;        // [B][W][P] or null
+  const float* gmul;    // [B][W][P] or null
   int64_t P;
   int32_t W, Z, K2;     // width, nz, 2 mz
   int32_t act_gelu;
@@ -413,7 +418,15 @@ struct LayerEndArgs {
   uint16_t* a1;         // next layer's z-stage output [B W X Y][2 mz] BF16, or null
 };
 
-template <int NT>  // NT = ceil(W / 16), W <= 32
+// eight consecutive values as packed BF16 (RNE)
+template <typename T> __device__ __forceinline__ uint4 load8_bf(const T* p);
+template <> __device__ __forceinline__ uint4 load8_bf<uint16_t>(const uint16_t* p) { return *(const uint4*)p; }
+template <> __device__ __forceinline__ uint4 load8_bf<float>(const float* p) {
+  const float4 x = *(const float4*)p, y = *(const float4*)(p + 4);
+  return uint4{f2bf2(x.x, x.y), f2bf2(x.z, x.w), f2bf2(y.x, y.y), f2bf2(y.z, y.w)};
+}
+
+template <int NT, typename InT>  // NT = ceil(W / 16), W <= 32
 __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
   // the v tile [256 points][PW_TS], then the FP32 result tile [32][PW_DS];
   // after it the BF16 activation tile [32][PW_J + 8] for the fused z-DFT
@@ -428,13 +441,13 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
   // Every global load of the block is issued before the first wait: the v
   // tile (bound for LDS) and this lane's c2r operands from the y-stage
   // output, so that both streams are in flight together.
-  const uint16_t* in = a.v + b * a.W * a.P + p0;
+  const InT* in = (const InT*)a.v + b * a.W * a.P + p0;
   uint4 vq[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int idx = q * 256 + t;
     const int kl = idx >> 5, pl = (idx & 31) * 8;
-    vq[q] = kl < a.W ? *(const uint4*)(in + (int64_t)kl * a.P + pl) : uint4{0u, 0u, 0u, 0u};
+    vq[q] = kl < a.W ? load8_bf<InT>(in + (int64_t)kl * a.P + pl) : uint4{0u, 0u, 0u, 0u};
   }
   // c2r operand of column tile c (points pp .. pp + 15 of one (x, y) row) and
   // row tile h: every lane loads (from row 0 where its row or k range does
@@ -511,16 +524,24 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
         dst[(h * 16 + 4 * g + r) * PW_DS + wave * 64 + c * 16 + l16] = acc[h][c][r] + acc2[h][c][r];
   __syncthreads();
   float* hout = a.h ? a.h + b * a.W * a.P + p0 : nullptr;
-  uint16_t* act = a.act + b * a.W * a.P + p0;
+  uint16_t* act = a.act ? a.act + b * a.W * a.P + p0 : nullptr;
+  const float* gm = a.gmul ? a.gmul + b * a.W * a.P + p0 : nullptr;
 #pragma unroll 2
   for (int e = t; e < 32 * 64; e += 256) {
     const int n = e >> 6, p4 = (e & 63) * 4;
     if (n >= a.W) continue;
     float4 v = *(const float4*)(dst + n * PW_DS + p4);
-    const float bb = a.bias[n];
-    v.x += bb; v.y += bb; v.z += bb; v.w += bb;
     const int64_t off = (int64_t)n * a.P + p4;
+    if (a.bias) {
+      const float bb = a.bias[n];
+      v.x += bb; v.y += bb; v.z += bb; v.w += bb;
+    }
+    if (gm) {
+      const float4 hh = *(const float4*)(gm + off);
+      v.x *= gelu_grad(hh.x); v.y *= gelu_grad(hh.y); v.z *= gelu_grad(hh.z); v.w *= gelu_grad(hh.w);
+    }
     if (hout) *(float4*)(hout + off) = v;
+    if (!act) continue;
     uint2 w;
     if (a.act_gelu) {
       w.x = f2bf2(gelu(v.x), gelu(v.y));
