@@ -14,12 +14,13 @@ import numpy as np
 from .geometry import obstacle_sdf
 
 
-def coarse_inputs(shape, seed, factor=2, turns=0):
+def coarse_inputs(shape, seed, factor=2, turns=0, re=None, aoa=None):
     """float32 [4][X][Y][Z] for the seeded random obstacle in a channel of
-    the given fine shape, and the object description."""
+    the given fine shape, and the object description (re and aoa override
+    the seeded values)."""
     nx, ny, nz = shape
     X, Y, Z = nx // factor, ny // factor, nz // factor
-    obj, sdf, _, _ = obstacle_sdf(shape, seed, turns=turns)
+    obj, sdf, _, _ = obstacle_sdf(shape, seed, turns=turns, re=re, aoa=aoa)
     off = (factor - 1) / 2.0
     x, y, z = np.meshgrid(np.arange(X) * factor + off, np.arange(Y) * factor + off, np.arange(Z) * factor + off,
                           indexing="ij")

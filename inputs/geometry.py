@@ -269,14 +269,20 @@ def spanwise_cylinder(shape=(1024, 512, 512), center=(307.2, 255.5), diameter=64
                     params=dict(center=center, diameter=diameter))
 
 
-def obstacle_sdf(shape, seed, scale=None, turns=0):
+def obstacle_sdf(shape, seed, scale=None, turns=0, re=None, aoa=None):
     """Description and signed distance function of the seeded random object
     placed at (0.3 nx, (ny-1)/2, (nz-1)/2), turned by `turns` quarter turns
-    about the channel axis (+y towards +z; needs ny == nz when turns != 0)."""
+    about the channel axis (+y towards +z; needs ny == nz when turns != 0).
+    re and aoa, when given, replace the seeded Reynolds number and angle of
+    attack (degrees)."""
     nx, ny, nz = shape
     if scale is None:
         scale = nx / 256.0
     obj = random_object(seed, scale)
+    if re is not None:
+        obj["re"] = float(re)
+    if aoa is not None:
+        obj["aoa"] = float(aoa)
     center = np.array([0.3 * nx, (ny - 1) / 2.0, (nz - 1) / 2.0])
     base = object_sdf(obj, center)
     q = int(turns) % 4
@@ -296,10 +302,11 @@ def obstacle_sdf(shape, seed, scale=None, turns=0):
     return obj, sdf, center, scale
 
 
-def random_obstacle(shape, seed, scale=None, turns=0):
+def random_obstacle(shape, seed, scale=None, turns=0, re=None, aoa=None):
     """Seeded union of 1-3 primitives at (0.3 nx, (ny-1)/2, (nz-1)/2); sizes
-    refer to a 256x128x128 channel and scale with nx/256 unless given."""
-    obj, sdf, center, scale = obstacle_sdf(shape, seed, scale, turns)
+    refer to a 256x128x128 channel and scale with nx/256 unless given; re and
+    aoa override the seeded values."""
+    obj, sdf, center, scale = obstacle_sdf(shape, seed, scale, turns, re, aoa)
     ext = 24.0 * scale * 1.5 + 4.0 * scale * 1.8 + 3
     bb = tuple((center[d] - ext, center[d] + ext + 1) for d in range(3))
     g = from_sdf(shape, sdf, name=f"random{seed}" + (f"t{turns}" if turns else ""), params=obj, bbox=bb)

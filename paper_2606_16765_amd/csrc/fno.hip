@@ -285,23 +285,48 @@ static int pointwise(fno_net* n, int B, const void* in, bool in_bf16, int cin, v
 }
 
 template <int NT, int KS>
-static void launch_proj(fno_net* n, int B, const uint16_t* v, float* y) {
+static void launch_proj(fno_net* n, int B, const uint16_t* v, float* y, uint16_t* aout) {
   const unsigned blocks = (unsigned)((int64_t)B * n->P / 256);
-  hipLaunchKernelGGL((proj_kernel<NT, KS>), dim3(blocks), dim3(256), 0, n->st, v, n->W, n->P, n->Pq1.d, n->pq1b,
-                     n->Pq2.d, n->theta + n->off_q2, n->p.cout, y);
+  if (aout)
+    hipLaunchKernelGGL((proj_kernel<NT, KS, true>), dim3(blocks), dim3(256), 0, n->st, v, n->W, n->P, n->Pq1.d,
+                       n->pq1b, n->Pq2.d, n->theta + n->off_q2, n->p.cout, y, n->H, aout);
+  else
+    hipLaunchKernelGGL((proj_kernel<NT, KS>), dim3(blocks), dim3(256), 0, n->st, v, n->W, n->P, n->Pq1.d, n->pq1b,
+                       n->Pq2.d, n->theta + n->off_q2, n->p.cout, y, 0, nullptr);
+}
+template <int NT, int KS>
+static void launch_proj_bwd(fno_net* n, int B, const uint16_t* v, const float* gy, uint16_t* ga, float* gv) {
+  const unsigned blocks = (unsigned)((int64_t)B * n->P / 256);
+  hipLaunchKernelGGL((proj_bwd_kernel<NT, KS>), dim3(blocks), dim3(256), 0, n->st, v, n->W, n->P, n->Pq1.d, n->pq1b,
+                     n->Gq2t.d, n->Gq2t.kp, gy, n->p.cout, n->H, ga, gv);
 }
 
-static void fused_projection(fno_net* n, int B, const uint16_t* v, float* y) {
+// fused projection; aout (training) also receives the BF16 hidden activation
+static void fused_projection(fno_net* n, int B, const uint16_t* v, float* y, uint16_t* aout = nullptr) {
   const int NT = n->Pq1.np / 16, KS = n->Pq1.kp / 32;
   switch (NT * 4 + KS) {
-    case 2 * 4 + 1: launch_proj<2, 1>(n, B, v, y); break;
-    case 2 * 4 + 2: launch_proj<2, 2>(n, B, v, y); break;
-    case 4 * 4 + 1: launch_proj<4, 1>(n, B, v, y); break;
-    case 4 * 4 + 2: launch_proj<4, 2>(n, B, v, y); break;
-    case 6 * 4 + 1: launch_proj<6, 1>(n, B, v, y); break;
-    case 6 * 4 + 2: launch_proj<6, 2>(n, B, v, y); break;
-    case 8 * 4 + 1: launch_proj<8, 1>(n, B, v, y); break;
-    default: launch_proj<8, 2>(n, B, v, y); break;
+    case 2 * 4 + 1: launch_proj<2, 1>(n, B, v, y, aout); break;
+    case 2 * 4 + 2: launch_proj<2, 2>(n, B, v, y, aout); break;
+    case 4 * 4 + 1: launch_proj<4, 1>(n, B, v, y, aout); break;
+    case 4 * 4 + 2: launch_proj<4, 2>(n, B, v, y, aout); break;
+    case 6 * 4 + 1: launch_proj<6, 1>(n, B, v, y, aout); break;
+    case 6 * 4 + 2: launch_proj<6, 2>(n, B, v, y, aout); break;
+    case 8 * 4 + 1: launch_proj<8, 1>(n, B, v, y, aout); break;
+    default: launch_proj<8, 2>(n, B, v, y, aout); break;
+  }
+}
+// fused projection backward: ga (BF16) = GELU'(h1) Q2^T gy, gv = Q1^T ga
+static void fused_projection_bwd(fno_net* n, int B, const uint16_t* v, const float* gy, uint16_t* ga, float* gv) {
+  const int NT = n->Pq1.np / 16, KS = n->Pq1.kp / 32;
+  switch (NT * 4 + KS) {
+    case 2 * 4 + 1: launch_proj_bwd<2, 1>(n, B, v, gy, ga, gv); break;
+    case 2 * 4 + 2: launch_proj_bwd<2, 2>(n, B, v, gy, ga, gv); break;
+    case 4 * 4 + 1: launch_proj_bwd<4, 1>(n, B, v, gy, ga, gv); break;
+    case 4 * 4 + 2: launch_proj_bwd<4, 2>(n, B, v, gy, ga, gv); break;
+    case 6 * 4 + 1: launch_proj_bwd<6, 1>(n, B, v, gy, ga, gv); break;
+    case 6 * 4 + 2: launch_proj_bwd<6, 2>(n, B, v, gy, ga, gv); break;
+    case 8 * 4 + 1: launch_proj_bwd<8, 1>(n, B, v, gy, ga, gv); break;
+    default: launch_proj_bwd<8, 2>(n, B, v, gy, ga, gv); break;
   }
 }
 
@@ -412,7 +437,7 @@ static int gram(fno_net* n, const XT* Xd, int A, const YT* Yd, int Cc, int B, fl
     const int64_t nch = (int64_t)B * n->P / GR_CHUNK;
     const int64_t E = (int64_t)A * Cc;
     constexpr int S = 64;
-    const bool with_c = bout && std::is_same<XT, float>::value && nch * A <= n->partc_elems && S * A <= n->part2_elems;
+    const bool with_c = bout && nch * A <= n->partc_elems && S * A <= n->part2_elems;
     if (nch % 4 == 0 && nch * E <= n->part_elems && S * E <= n->part2_elems && (with_c || !bout) &&
         launch_gram2(n, Xd, A, Yd, Cc, nch, with_c ? n->partc : nullptr)) {
       hipLaunchKernelGGL(reduce_slices_kernel, dim3((unsigned)((E + 255) / 256), S), dim3(256), 0, n->st, n->part,
@@ -544,6 +569,12 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
   };
   const int B = p.max_batch;
   const int64_t W = n->W;
+  // fused projection: hidden padded to a multiple of 32 (at most 128),
+  // width to a multiple of 32 (at most 64), at most 16 outputs
+  const int Hp = (int)round_up(n->H, 32), Wp = (int)round_up(n->W, 32);
+  n->fused_proj = Hp <= 128 && Wp <= 64 && p.cout <= 16 && P % 256 == 0;
+  // the FP32 hidden pre-activation and its gradient exist only without it
+  const size_t hid32 = n->fused_proj ? 0 : (size_t)B * n->H * P * 4;
   auto A = [&](void** ptr, size_t bytes) { return falloc(n, ptr, bytes) == hipSuccess; };
   bool ok = A((void**)&n->theta, n->nparam * 4) && A((void**)&n->grad, n->nparam * 4) &&
             A((void**)&n->am, n->nparam * 4) && A((void**)&n->av, n->nparam * 4) &&
@@ -559,9 +590,9 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
        A((void**)&n->A2, (size_t)B * W * n->X * 2 * n->MY * n->MZ * 2) &&
        A((void**)&n->Yh, (size_t)n->M * B * W * 2 * 2) && A((void**)&n->Vg, (size_t)n->M * B * W * 2 * 2) &&
        A((void**)&n->R3, (size_t)B * W * n->X * 2 * n->MY * n->MZ * 2) &&
-       A((void**)&n->R2, (size_t)rows * 2 * n->MZ * 2) && A((void**)&n->h1, (size_t)B * n->H * P * 4) &&
+       A((void**)&n->R2, (size_t)rows * 2 * n->MZ * 2) && (hid32 == 0 || A((void**)&n->h1, hid32)) &&
        A((void**)&n->a, (size_t)B * n->H * P * 2) && A((void**)&n->y, (size_t)B * p.cout * P * 4) &&
-       A((void**)&n->gy, (size_t)B * p.cout * P * 4) && A((void**)&n->ga, (size_t)B * n->H * P * 4) &&
+       A((void**)&n->gy, (size_t)B * p.cout * P * 4) && (hid32 == 0 || A((void**)&n->ga, hid32)) &&
        A((void**)&n->gv, (size_t)B * W * P * 4) && A((void**)&n->gvn, (size_t)B * W * P * 4);
   n->part_elems = std::max<int64_t>((int64_t)B * P / 2048 * std::max<int64_t>(n->H, W) * std::max<int64_t>(W, p.cout) +
                                         (int64_t)B * P / 2048 * n->H * std::max<int64_t>(n->H, W),
@@ -587,10 +618,6 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
       alloc_gt(n, n->Gq2, n->H, p.cout) != hipSuccess || alloc_gt(n, n->Gq2t, p.cout, n->H) != hipSuccess)
     return bail(LBM_ENOMEM, "operand allocation");
   {
-    // fused projection: hidden padded to a multiple of 32 (at most 128),
-    // width to a multiple of 32 (at most 64), at most 16 outputs
-    const int Hp = (int)round_up(n->H, 32), Wp = (int)round_up(n->W, 32);
-    n->fused_proj = Hp <= 128 && Wp <= 64 && p.cout <= 16 && P % 256 == 0;
     n->fused_layer_end = n->W <= 32 && p.nz >= 16 && p.nz <= 256 && 2 * p.mz <= 32 && P % 256 == 0;
     if (n->fused_proj) {
       n->Pq1.K = n->W; n->Pq1.N = n->H; n->Pq1.kp = Wp; n->Pq1.np = Hp;
@@ -713,13 +740,23 @@ static void mix_grad(fno_net* n, int B, const uint16_t* v, const uint16_t* gy, f
 static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout, bool training) {
   const int64_t W = n->W;
   int rc;
-  // lift: v0 = P x + p (no activation; the pre-activation is not kept)
-  if ((rc = pointwise(n, B, x, true, n->p.cin, nullptr, false, (int)W, &n->Glift, n->theta + n->off_p, false, false,
-                      n->v[0], false)))
-    return rc;
   // the layer end can run the next layer's z stage at the production shape
   const bool fuse_z = n->fused_layer_end && n->Z == 64 && W == 32 && 2 * n->MZ == 32 && n->F1.kp >= 64;
   bool z_done = false;
+  // lift: v0 = P x + p (no activation; the pre-activation is not kept)
+  if (fuse_z && n->p.cin <= 32 && n->Glift.kp == 32) {
+    LayerEndArgs e{};
+    e.v = x; e.r2 = nullptr; e.gwp = n->Glift.d; e.gi1 = nullptr; e.gi1_kp = 0;
+    e.bias = n->theta + n->off_p; e.h = nullptr; e.act = n->v[0];
+    e.P = n->P; e.W = (int)W; e.Win = n->p.cin; e.Z = n->Z; e.K2 = 2 * n->MZ; e.act_gelu = 0;
+    e.gz = n->F1.d; e.gz_kp = n->F1.kp; e.a1 = n->A1;
+    hipLaunchKernelGGL((layer_end_kernel<2, uint16_t, false>), dim3((unsigned)((int64_t)B * n->P / PW_J)), dim3(256),
+                       0, n->st, e);
+    z_done = true;
+  } else if ((rc = pointwise(n, B, x, true, n->p.cin, nullptr, false, (int)W, &n->Glift, n->theta + n->off_p, false,
+                             false, n->v[0], false))) {
+    return rc;
+  }
   for (int l = 0; l < n->L; ++l) {
     if ((rc = forward_dft(n, B, n->v[l], true, n->F1, n->Vh[l], z_done))) return rc;
     z_done = false;
@@ -730,7 +767,7 @@ static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout, bool 
       LayerEndArgs e{};
       e.v = n->v[l]; e.r2 = n->R2; e.gwp = n->Gwp[l].d; e.gi1 = n->I1.d; e.gi1_kp = n->I1.kp;
       e.bias = n->theta + n->off_bp[l]; e.h = training ? n->h[l] : nullptr; e.act = n->v[l + 1];
-      e.P = n->P; e.W = (int)W; e.Z = n->Z; e.K2 = 2 * n->MZ; e.act_gelu = l < n->L - 1 ? 1 : 0;
+      e.P = n->P; e.W = (int)W; e.Win = (int)W; e.Z = n->Z; e.K2 = 2 * n->MZ; e.act_gelu = l < n->L - 1 ? 1 : 0;
       if (fuse_z && l < n->L - 1) {
         e.gz = n->F1.d; e.gz_kp = n->F1.kp; e.a1 = n->A1;
         z_done = true;
@@ -745,8 +782,10 @@ static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout, bool 
         return rc;
     }
   }
-  if (!training && n->fused_proj) {
-    fused_projection(n, B, n->v[n->L], yout);
+  if (n->fused_proj) {
+    // training keeps the BF16 hidden activation for the gradient of Q2; the
+    // pre-activation is recomputed in the backward pass
+    fused_projection(n, B, n->v[n->L], yout, training ? n->a : nullptr);
   } else {
     if ((rc = pointwise(n, B, n->v[n->L], true, (int)W, n->h1, false, n->H, &n->Gq1, n->theta + n->off_q1, false,
                         true, n->a, true)))
@@ -788,13 +827,22 @@ extern "C" int fno_loss_grad(fno_net* n, const uint16_t* x, const float* target,
   FCHK(n, hipMemsetAsync(n->grad, 0, n->nparam * 4, n->st));
   // projection
   if ((rc = gram(n, n->gy, (int)cout, n->a, n->H, B, n->grad + n->off_Q2, false, n->grad + n->off_q2))) return rc;
-  // dL/dh1 = GELU'(h1) * Q2^T gy, the derivative applied in the epilogue
-  if ((rc = pointwise(n, B, n->gy, false, (int)cout, n->ga, false, n->H, &n->Gq2t, nullptr, false, true, nullptr,
-                      false, n->h1)))
-    return rc;
-  if ((rc = gram(n, n->ga, n->H, n->v[n->L], (int)W, B, n->grad + n->off_Q1, false, n->grad + n->off_q1)))
-    return rc;
-  if ((rc = pointwise(n, B, n->ga, false, n->H, n->gv, false, (int)W, &n->Gq1t, nullptr, false))) return rc;
+  if (n->fused_proj) {
+    // dL/dh1 = GELU'(h1) * Q2^T gy in BF16 (the hidden activation's buffer,
+    // already consumed) and dL/dv = Q1^T dL/dh1, in one pass
+    fused_projection_bwd(n, B, n->v[n->L], n->gy, n->a, n->gv);
+    if ((rc = gram(n, (const uint16_t*)n->a, n->H, n->v[n->L], (int)W, B, n->grad + n->off_Q1, false,
+                   n->grad + n->off_q1)))
+      return rc;
+  } else {
+    // dL/dh1 = GELU'(h1) * Q2^T gy, the derivative applied in the epilogue
+    if ((rc = pointwise(n, B, n->gy, false, (int)cout, n->ga, false, n->H, &n->Gq2t, nullptr, false, true, nullptr,
+                        false, n->h1)))
+      return rc;
+    if ((rc = gram(n, n->ga, n->H, n->v[n->L], (int)W, B, n->grad + n->off_Q1, false, n->grad + n->off_q1)))
+      return rc;
+    if ((rc = pointwise(n, B, n->ga, false, n->H, n->gv, false, (int)W, &n->Gq1t, nullptr, false))) return rc;
+  }
   // Fourier layers in reverse
   // at layer l, gv holds dL/dh[l]: the last layer has no activation, and the
   // GELU' of the layers below is applied where their gradient is completed
@@ -813,7 +861,7 @@ extern "C" int fno_loss_grad(fno_net* n, const uint16_t* x, const float* target,
       LayerEndArgs e{};
       e.v = n->gv; e.r2 = n->R2; e.gwp = n->Gwpt[l].d; e.gi1 = n->I1a.d; e.gi1_kp = n->I1a.kp;
       e.bias = nullptr; e.h = n->gvn; e.act = nullptr; e.gmul = gmul;
-      e.P = n->P; e.W = (int)W; e.Z = n->Z; e.K2 = 2 * n->MZ; e.act_gelu = 0;
+      e.P = n->P; e.W = (int)W; e.Win = (int)W; e.Z = n->Z; e.K2 = 2 * n->MZ; e.act_gelu = 0;
       const dim3 grid((unsigned)((int64_t)B * n->P / PW_J));
       if (W <= 16) hipLaunchKernelGGL((layer_end_kernel<1, float>), grid, dim3(256), 0, n->st, e);
       else hipLaunchKernelGGL((layer_end_kernel<2, float>), grid, dim3(256), 0, n->st, e);

@@ -399,7 +399,9 @@ __global__ __launch_bounds__(256) void pw_kernel(PwArgs a) {
 // The backward pass uses the same kernel on FP32 input (InT = float) with
 // the transposed channel map, the adjoint c2r operand, no bias, gmul set
 // (the result times GELU'(gmul), the pre-activation of the layer below)
-// and only the FP32 output h.
+// and only the FP32 output h.  The lift uses it with cin input channels,
+// the lift weights as the channel map and no c2r term (r2 null), so that
+// layer 0's z stage is fused as well.
 struct LayerEndArgs {
   const void* v;        // [B][W][P] layer input, BF16 or FP32 (InT)
   const uint16_t* r2;   // [B W X Y][2 mz] y-stage output (BF16)
@@ -412,6 +414,7 @@ struct LayerEndArgs {
   const float* gmul;    // [B][W][P] or null
   int64_t P;
   int32_t W, Z, K2;     // width, nz, 2 mz
+  int32_t Win;          // input channels of the channel map (<= 32; W except for the lift)
   int32_t act_gelu;
   const uint16_t* gz;   // next layer's z-DFT operand [2 mz padded][kp] BF16 (rows k, columns z)
   int32_t gz_kp;
@@ -426,7 +429,7 @@ template <> __device__ __forceinline__ uint4 load8_bf<float>(const float* p) {
   return uint4{f2bf2(x.x, x.y), f2bf2(x.z, x.w), f2bf2(y.x, y.y), f2bf2(y.z, y.w)};
 }
 
-template <int NT, typename InT>  // NT = ceil(W / 16), W <= 32
+template <int NT, typename InT, bool C2R = true>  // NT = ceil(W / 16), W <= 32; C2R: r2 term present
 __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
   // the v tile [256 points][PW_TS], then the FP32 result tile [32][PW_DS];
   // after it the BF16 activation tile [32][PW_J + 8] for the fused z-DFT
@@ -441,26 +444,28 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
   // Every global load of the block is issued before the first wait: the v
   // tile (bound for LDS) and this lane's c2r operands from the y-stage
   // output, so that both streams are in flight together.
-  const InT* in = (const InT*)a.v + b * a.W * a.P + p0;
+  const InT* in = (const InT*)a.v + b * a.Win * a.P + p0;
   uint4 vq[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int idx = q * 256 + t;
     const int kl = idx >> 5, pl = (idx & 31) * 8;
-    vq[q] = kl < a.W ? load8_bf<InT>(in + (int64_t)kl * a.P + pl) : uint4{0u, 0u, 0u, 0u};
+    vq[q] = kl < a.Win ? load8_bf<InT>(in + (int64_t)kl * a.P + pl) : uint4{0u, 0u, 0u, 0u};
   }
   // c2r operand of column tile c (points pp .. pp + 15 of one (x, y) row) and
   // row tile h: every lane loads (from row 0 where its row or k range does
   // not exist) and selects at use, so no divergent branch feeds the MFMA
   uint4 rq[4][NT];
+  if (C2R) {
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int64_t xy = (p0 + wave * 64 + c * 16) / a.Z;  // (x, y) row index within the sample
+    for (int c = 0; c < 4; ++c) {
+      const int64_t xy = (p0 + wave * 64 + c * 16) / a.Z;  // (x, y) row index within the sample
 #pragma unroll
-    for (int h = 0; h < NT; ++h) {
-      const int w = h * 16 + (lane & 15);
-      const bool ok = w < a.W && 8 * g < a.K2;
-      rq[c][h] = *(const uint4*)(a.r2 + (ok ? ((b * a.W + w) * (a.P / a.Z) + xy) * a.K2 + 8 * g : 0));
+      for (int h = 0; h < NT; ++h) {
+        const int w = h * 16 + (lane & 15);
+        const bool ok = w < a.W && 8 * g < a.K2;
+        rq[c][h] = *(const uint4*)(a.r2 + (ok ? ((b * a.W + w) * (a.P / a.Z) + xy) * a.K2 + 8 * g : 0));
+      }
     }
   }
   // v tile [256 points][32 channels] in LDS, zero beyond W
@@ -498,7 +503,7 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc2[h][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < 4 * C2R; ++c) {
     const int zb = (int)((p0 + wave * 64 + c * 16) % a.Z);  // first z of the tile
     const bf16x8 bv = *(const bf16x8*)(a.gi1 + (int64_t)(zb + (lane & 15)) * a.gi1_kp + 8 * g);
 #pragma unroll
@@ -600,15 +605,20 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
 // k slots 8g..8g+7 holding hidden rows 32s + 4g + {0..3} (tile 2s) and
 // 32s + 16 + 4g + {0..3} (tile 2s+1), and the Q2 operand is gathered with
 // the same assignment, so the sum runs over every hidden row once.
-template <int NT, int KS>
+// With STORE_A (training) the BF16 hidden activation is also stored to
+// aout [B][H][P], for the gradient of Q2.
+template <int NT, int KS, bool STORE_A = false>
 __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ v, int W, int64_t P,
                                                    const uint16_t* __restrict__ Q1p, const float* __restrict__ q1p,
                                                    const uint16_t* __restrict__ Q2p, const float* __restrict__ q2,
-                                                   int cout, float* __restrict__ y) {
+                                                   int cout, float* __restrict__ y, int H = 0,
+                                                   uint16_t* __restrict__ aout = nullptr) {
   constexpr int WP = 32 * KS, VS = WP + 8, HP = 16 * NT;
   __shared__ __attribute__((aligned(16))) uint16_t vt[256 * VS];
   __shared__ __attribute__((aligned(16))) uint16_t q1s[HP * WP];
   __shared__ __attribute__((aligned(16))) uint16_t q2s[16 * HP];
+  // per wave: the BF16 hidden tile [HP][16 points] of one column tile
+  __shared__ __attribute__((aligned(16))) uint16_t hs[STORE_A ? 4 * HP * 16 : 8];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4;
   const int64_t j0 = (int64_t)blockIdx.x * 256;
   const int64_t b = j0 / P, p0 = j0 % P;
@@ -647,6 +657,7 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
         acc[nt] = mfma16(av, bv, acc[nt]);
       }
     }
+    const int64_t p = p0 + wave * 64 + ct * 16 + (lane & 15);
     f32x4 out = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < NT / 2; ++s) {
@@ -655,15 +666,137 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
       for (int j = 0; j < 8; ++j) {
         const int nt = 2 * s + (j >> 2), r = j & 3;
         const float h = acc[nt][r] + q1p[nt * 16 + 4 * g + r];
-        bv[j] = __builtin_bit_cast(__bf16, f2bf(gelu(h)));
+        const uint16_t hb = f2bf(gelu(h));
+        bv[j] = __builtin_bit_cast(__bf16, hb);
+        if (STORE_A) hs[wave * HP * 16 + (nt * 16 + 4 * g + r) * 16 + (lane & 15)] = hb;
       }
       out = mfma16(a2[s], bv, out);
     }
-    const int64_t p = p0 + wave * 64 + ct * 16 + (lane & 15);
+    if (STORE_A) {
+      __syncthreads();  // the wave's hidden tile is complete
+      // rows h of 16 points, two 16-byte halves each
+      for (int e = lane; e < HP * 2; e += 64) {
+        const int hr = e >> 1, half = e & 1;
+        if (hr < H)
+          *(uint4*)(aout + (b * H + hr) * P + p0 + wave * 64 + ct * 16 + 8 * half) =
+              *(const uint4*)(hs + wave * HP * 16 + hr * 16 + 8 * half);
+      }
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int o = 4 * g + r;
       if (o < cout) y[(b * cout + o) * P + p] = out[r] + q2[o];
+    }
+  }
+}
+
+// Fused projection backward (training), per point of v [B][W][P]:
+//   h1 = q1 + Q1 v                        (recomputed, as in the forward)
+//   ga = GELU'(h1) * (Q2^T gy)            stored BF16 to ga [B][H][P]
+//   gv = Q1^T ga                          stored FP32 to gv [B][W][P]
+// with gy [B][cout][P] the gradient at the output.  h1 comes from the same
+// MFMA products and the same bias add as the forward's, so it is not kept
+// between the passes.  Q2t [16 NT][kp2] is Q2 transposed (rows h, k = o),
+// BF16, zero padded; the Q1^T operand is gathered from Q1p with the hidden
+// rows permuted as the forward's second stage, so that ga feeds it straight
+// from the accumulator registers.  Block and wave layout as proj_kernel.
+template <int NT, int KS>
+__global__ __launch_bounds__(256) void proj_bwd_kernel(const uint16_t* __restrict__ v, int W, int64_t P,
+                                                       const uint16_t* __restrict__ Q1p, const float* __restrict__ q1p,
+                                                       const uint16_t* __restrict__ Q2t, int kp2,
+                                                       const float* __restrict__ gy, int cout, int H,
+                                                       uint16_t* __restrict__ ga, float* __restrict__ gv) {
+  constexpr int WP = 32 * KS, VS = WP + 8, HP = 16 * NT;
+  __shared__ __attribute__((aligned(16))) uint16_t vt[256 * VS];
+  __shared__ __attribute__((aligned(16))) uint16_t q1s[HP * WP];
+  // the Q1^T operand per (step s, column tile, lane), and per wave the BF16
+  // gradient tile [HP][16 points] of one column tile
+  __shared__ __attribute__((aligned(16))) bf16x8 q1t[(NT / 2) * (2 * KS) * 64];
+  __shared__ __attribute__((aligned(16))) uint16_t hs[4 * HP * 16];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4, l16 = lane & 15;
+  const int64_t j0 = (int64_t)blockIdx.x * 256;
+  const int64_t b = j0 / P, p0 = j0 % P;
+  for (int e = t * 8; e < HP * WP; e += 256 * 8) *(uint4*)(q1s + e) = *(const uint4*)(Q1p + e);
+  for (int idx = t; idx < WP * 32; idx += 256) {
+    const int c = idx >> 5, g8 = (idx & 31) * 8;
+    uint16_t val[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (c < W) Vec8<uint16_t>::load(v + (b * W + c) * P + p0 + g8, val);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) vt[tile_row(g8 + i) * VS + tile_col(c, g8 + i)] = val[i];
+  }
+  __syncthreads();
+  // A operand of Q1^T: rows c = 16 ct2 + l16, k slots of step s holding the
+  // hidden rows 32 s + 4 g + {0..3} and 32 s + 16 + 4 g + {0..3}
+  for (int e = t; e < (NT / 2) * (2 * KS) * 64; e += 256) {
+    const int ln = e & 63, ct2 = (e >> 6) % (2 * KS), s = (e >> 6) / (2 * KS);
+    const int gg = ln >> 4, cc = ct2 * 16 + (ln & 15);
+    bf16x8 o;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int h = 32 * s + (j < 4 ? 4 * gg + j : 16 + 4 * gg + (j - 4));
+      o[j] = __builtin_bit_cast(__bf16, q1s[h * WP + cc]);
+    }
+    q1t[e] = o;
+  }
+  __syncthreads();
+  uint16_t* hw = hs + wave * HP * 16;
+#pragma unroll 1
+  for (int ct = 0; ct < 4; ++ct) {
+    const int pt = wave * 64 + ct * 16 + l16;
+    const int64_t p = p0 + pt;
+    bf16x8 vb[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) vb[ks] = *(const bf16x8*)(vt + tile_row(pt) * VS + tile_col(ks * 32 + 8 * g, pt));
+    // gy operand: column = this point, k = o (zero beyond cout)
+    bf16x8 gb;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int o = 8 * g + j;
+      gb[j] = __builtin_bit_cast(__bf16, o < cout ? f2bf(gy[(b * cout + o) * P + p]) : (uint16_t)0);
+    }
+    f32x4 go[2 * KS];
+#pragma unroll
+    for (int ct2 = 0; ct2 < 2 * KS; ++ct2) go[ct2] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // one k step of Q1^T at a time: hidden tiles 2 s and 2 s + 1
+#pragma unroll 1
+    for (int s = 0; s < NT / 2; ++s) {
+      uint32_t u[4];  // packed BF16 gradient, (tile, r = 0, 1) and (tile, r = 2, 3)
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const int nt = 2 * s + hh, hr = nt * 16 + 4 * g;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+          acc = mfma16(*(const bf16x8*)(q1s + (nt * 16 + l16) * WP + ks * 32 + 8 * g), vb[ks], acc);
+        const f32x4 tq = mfma16(*(const bf16x8*)(Q2t + (nt * 16 + l16) * kp2 + 8 * g), gb, f32x4{0.f, 0.f, 0.f, 0.f});
+        float d[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) d[r] = tq[r] * gelu_grad(acc[r] + q1p[hr + r]);
+        u[2 * hh] = f2bf2(d[0], d[1]);
+        u[2 * hh + 1] = f2bf2(d[2], d[3]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) hw[(hr + r) * 16 + l16] = (uint16_t)(u[2 * hh + (r >> 1)] >> (16 * (r & 1)));
+      }
+      bf16x8 bv;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) bv[j] = __builtin_bit_cast(__bf16, (uint16_t)(u[j >> 1] >> (16 * (j & 1))));
+#pragma unroll
+      for (int ct2 = 0; ct2 < 2 * KS; ++ct2) go[ct2] = mfma16(q1t[(s * 2 * KS + ct2) * 64 + lane], bv, go[ct2]);
+    }
+#pragma unroll
+    for (int ct2 = 0; ct2 < 2 * KS; ++ct2)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = ct2 * 16 + 4 * g + r;
+        if (c < W) gv[(b * W + c) * P + p] = go[ct2][r];
+      }
+    __syncthreads();  // the wave's gradient tile is complete
+    // rows h of 16 points, two 16-byte halves each
+    for (int e = lane; e < HP * 2; e += 64) {
+      const int hr = e >> 1, half = e & 1;
+      if (hr < H)
+        *(uint4*)(ga + (b * H + hr) * P + p0 + wave * 64 + ct * 16 + 8 * half) =
+            *(const uint4*)(hw + hr * 16 + 8 * half);
     }
   }
 }
@@ -906,8 +1039,8 @@ __global__ __launch_bounds__(64) void gram_kernel(const XT* __restrict__ X, cons
 // lane, contiguous along the rows).  Rows beyond A or C read row 0 and are
 // zeroed by a select, so no branch feeds an MFMA operand.
 constexpr int GR_CHUNK = 2048;
-// With partc set (FP32 X only), the wave also sums every X row over its
-// chunk in FP32 (the bias gradient), partc[w][a].
+// With partc set, the wave also sums every X row over its chunk in FP32
+// (the bias gradient), partc[w][a]; BF16 rows are summed as stored.
 template <typename XT, typename YT, int AT, int CT>
 __global__ __launch_bounds__(256) void gram2_kernel(const XT* __restrict__ X, const YT* __restrict__ Y, float* part,
                                                     int A, int Cc, int64_t P, float* partc) {
@@ -950,6 +1083,8 @@ __global__ __launch_bounds__(256) void gram2_kernel(const XT* __restrict__ X, co
         v[4] = f2bf(hi.x); v[5] = f2bf(hi.y); v[6] = f2bf(hi.z); v[7] = f2bf(hi.w);
       } else {
         Vec8<XT>::load(xr[i] + k0, v);
+        rs[i] += ((bf2f(v[0]) + bf2f(v[1])) + (bf2f(v[2]) + bf2f(v[3]))) +
+                 ((bf2f(v[4]) + bf2f(v[5])) + (bf2f(v[6]) + bf2f(v[7])));
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) xa[i][q] = __builtin_bit_cast(__bf16, xok[i] ? v[q] : (uint16_t)0);

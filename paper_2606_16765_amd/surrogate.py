@@ -220,6 +220,41 @@ def predict(cfg, net, xs, idx, lo, hi):
     return np.concatenate(out), times
 
 
+class FieldModel:
+    """Mean fields of a seeded obstacle at a given Reynolds number and angle
+    of attack.  Inside the parameter range the network was trained on
+    (Re_c in [1000, 10000], |AoA| <= 15 degrees by default) the trained FNO
+    answers; outside it the LBM runs the case (the fallback of the gain
+    test).  Fields are physical-unit numpy [4][X][Y][Z] (u, v, w, p) on the
+    coarse grid."""
+
+    def __init__(self, cfg, net, lo, hi, re_range=(1000.0, 10000.0), aoa_max=15.0):
+        self.cfg, self.net, self.lo, self.hi = cfg, net, lo, hi
+        self.re_range, self.aoa_max = (float(re_range[0]), float(re_range[1])), float(aoa_max)
+
+    def in_range(self, re, aoa):
+        return self.re_range[0] <= float(re) <= self.re_range[1] and abs(float(aoa)) <= self.aoa_max
+
+    def mean_field(self, seed, re=None, aoa=None):
+        """(fields, source) with source "fno" or "lbm"; re and aoa default to
+        the seeded values."""
+        import torch
+        from inputs import coarse_inputs, random_obstacle, to_bf16_bits
+        from .fno import field_scale
+        cfg = self.cfg
+        feats, obj = coarse_inputs(cfg.shape, seed, cfg.factor, re=re, aoa=aoa)
+        if self.in_range(obj["re"], obj["aoa"]):
+            x = torch.from_numpy(to_bf16_bits(feats).view(np.int16)).to("cuda").view(torch.bfloat16)
+            y = self.net.forward(x.unsqueeze(0).contiguous())
+            field_scale(y, self.lo, self.hi, inverse=True)
+            return y[0].cpu().numpy(), "fno"
+        geo = random_obstacle(cfg.shape, seed, re=obj["re"], aoa=obj["aoa"])
+        sim, out, (_, e1), _ = run_lbm(cfg, seed, cfg.steps, turns=1, geo=geo)
+        e1.synchronize()
+        sim.close()
+        return out[0].cpu().numpy(), "lbm"
+
+
 def _dump(path, obj):
     if path:
         with open(path, "w") as fh:

@@ -61,3 +61,35 @@ def test_small_pipeline_end_to_end():
     assert len(res["fno"]["loss_history"]) == 3
     assert res["time_to_field"]["lbm_ms_per_field"] > 0 and res["time_to_field"]["fno_ms_per_field"] > 0
     assert len(res["time_to_field"]["lbm_curve"]) == 2
+
+
+def test_field_model_routes_out_of_range_inputs_to_the_lbm():
+    """Inside the trained parameter range the model answers with the network
+    (its unscaled output on the same input channels); outside it, in Re or
+    in angle of attack, with the LBM run of the same case."""
+    import torch
+    from inputs import coarse_inputs, random_obstacle, to_bf16_bits
+    from paper_2606_16765_amd import Fno, surrogate
+    from paper_2606_16765_amd.fno import field_scale
+    cfg = surrogate.Config(shape=(64, 32, 32), steps=100, width=16, modes=(4, 4, 4), hidden=16)
+    net = Fno(nx=32, ny=16, nz=16, width=16, layers=2, mx=4, my=4, mz=4, hidden=16, max_batch=1, seed=3)
+    lo = np.array([-0.01, -0.01, -0.01, -1e-3], np.float32)
+    hi = np.array([0.08, 0.01, 0.01, 1e-3], np.float32)
+    fm = surrogate.FieldModel(cfg, net, lo, hi)
+    f, src = fm.mean_field(5, re=4000.0, aoa=5.0)
+    assert src == "fno"
+    feats, _ = coarse_inputs(cfg.shape, 5, cfg.factor, re=4000.0, aoa=5.0)
+    x = torch.from_numpy(to_bf16_bits(feats).view(np.int16)).cuda().view(torch.bfloat16).unsqueeze(0).contiguous()
+    y = net.forward(x)
+    field_scale(y, lo, hi, inverse=True)
+    assert np.array_equal(f, y[0].cpu().numpy())
+    for re, aoa in ((20000.0, 0.0), (4000.0, 30.0)):
+        f, src = fm.mean_field(5, re=re, aoa=aoa)
+        assert src == "lbm", (re, aoa)
+        geo = random_obstacle(cfg.shape, 5, re=re, aoa=aoa)
+        sim, out, (_, e1), _ = surrogate.run_lbm(cfg, 5, cfg.steps, turns=1, geo=geo)
+        e1.synchronize()
+        sim.close()
+        assert np.isfinite(f).all()
+        assert np.array_equal(f, out[0].cpu().numpy())
+    net.close()

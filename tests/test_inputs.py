@@ -85,3 +85,19 @@ def test_coarse_inputs_channels():
     # bf16 rounding: exact for representable values, ties to even
     v = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -2.5], np.float32)
     assert list(to_bf16_bits(v)) == [0x3F80, 0x3F80, 0x3F82, 0xC020]
+
+
+def test_reynolds_and_angle_overrides():
+    """re and aoa replace the seeded values in the description, the input
+    channels and the geometry (the angle turns the obstacle)."""
+    from inputs import coarse_inputs, random_obstacle
+    shape = (64, 32, 32)
+    base, obj = coarse_inputs(shape, 7)
+    feats, obj2 = coarse_inputs(shape, 7, re=2500.0, aoa=-12.0)
+    assert obj2["re"] == 2500.0 and obj2["aoa"] == -12.0
+    assert np.all(feats[2] == np.float32(0.25)) and np.all(feats[3] == np.float32(-0.8))
+    same, _ = coarse_inputs(shape, 7, re=obj["re"], aoa=obj["aoa"])
+    assert np.array_equal(same, base)
+    g0 = random_obstacle(shape, 7)
+    g1 = random_obstacle(shape, 7, aoa=obj["aoa"] + 10.0)
+    assert g1.params["aoa"] == obj["aoa"] + 10.0 and not np.array_equal(g0.solid, g1.solid)
