@@ -240,7 +240,9 @@ int fno_forward(fno_net* n, const uint16_t* x, int32_t B, float* y);
  * (device uint8 [nx][ny][nz], shared by all samples and channels); target
  * device FP32 [B][cout][nx][ny][nz].  Gradients land in the FP32 gradient
  * buffer; host_grads (may be NULL) receives a copy; *loss (host, may be
- * NULL) the loss.  Synchronises when either host output is requested.        */
+ * NULL) the loss.  Asynchronous unless a host output is requested, then it
+ * synchronises.  An empty mask gives zero gradients, and LBM_EINVAL when the
+ * loss is requested.                                                         */
 int fno_loss_grad(fno_net* n, const uint16_t* x, const float* target, const uint8_t* mask, int32_t B,
                   float* loss, float* host_grads);
 

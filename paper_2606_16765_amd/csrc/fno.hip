@@ -97,6 +97,9 @@ struct fno_net {
   int64_t partc_elems = 0;
   double* lpart = nullptr;
   int64_t lpart_n = 0;
+  // device scalars of the loss: [0] mask count (int64), [1] loss (FP64),
+  // [2] gradient scale (FP32)
+  double* lscal = nullptr;
   int lastB = 0;
   std::vector<void*> allocs;
 };
@@ -604,6 +607,7 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
                                            std::max<int64_t>(W * W, W * (int64_t)p.cin));
   n->partc_elems = (int64_t)B * P / 2048 * std::max<int64_t>(std::max<int64_t>(n->H, W), p.cout);
   ok = ok && A((void**)&n->part, (size_t)n->part_elems * 4) && A((void**)&n->lpart, (size_t)n->lpart_n * 8) &&
+       A((void**)&n->lscal, 32) &&
        A((void**)&n->part2, (size_t)n->part2_elems * 4) && A((void**)&n->partc, (size_t)n->partc_elems * 4);
   if (!ok) return bail(LBM_ENOMEM, "device allocation failed");
   // pointwise operands
@@ -812,18 +816,17 @@ extern "C" int fno_loss_grad(fno_net* n, const uint16_t* x, const float* target,
   int rc = forward_impl(n, x, B, n->y, true);
   if (rc) return rc;
   const int64_t W = n->W, P = n->P, cout = n->p.cout;
-  // mask cell count (host copy of the mask is not needed: count on device via
-  // the loss kernel with unit target difference would be indirect; read it)
-  std::vector<uint8_t> hm((size_t)P);
-  FCHK(n, hipMemcpyAsync(hm.data(), mask, P, hipMemcpyDeviceToHost, n->st));
-  FCHK(n, hipStreamSynchronize(n->st));
-  int64_t cnt = 0;
-  for (uint8_t m : hm) cnt += m ? 1 : 0;
-  if (cnt == 0) return ffail(n, LBM_EINVAL, "empty loss mask");
+  // mask cell count and gradient scale on the device: nothing waits for the
+  // host unless the loss or the gradients are requested
+  long long* dcnt = (long long*)n->lscal;
+  double* dloss = n->lscal + 1;
+  float* dscale = (float*)(n->lscal + 2);
+  const double bc = (double)B * cout;
+  hipLaunchKernelGGL(mask_count_kernel, dim3(1), dim3(1024), 0, n->st, mask, P, bc, dcnt, dscale);
   const int64_t ny = (int64_t)B * cout * P;
   const int64_t nblk = (ny + 255) / 256;
   hipLaunchKernelGGL(mse_kernel, dim3((unsigned)nblk), dim3(256), 0, n->st, n->y, target, mask, P, ny,
-                     (float)(1.0 / ((double)B * cout * cnt)), n->gy, n->lpart);
+                     (const float*)dscale, n->gy, n->lpart);
   FCHK(n, hipMemsetAsync(n->grad, 0, n->nparam * 4, n->st));
   // projection
   if ((rc = gram(n, n->gy, (int)cout, n->a, n->H, B, n->grad + n->off_Q2, false, n->grad + n->off_q2))) return rc;
@@ -876,12 +879,15 @@ extern "C" int fno_loss_grad(fno_net* n, const uint16_t* x, const float* target,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return ffail(n, LBM_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   if (loss) {
-    std::vector<double> lp((size_t)nblk);
-    FCHK(n, hipMemcpyAsync(lp.data(), n->lpart, nblk * 8, hipMemcpyDeviceToHost, n->st));
+    hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(1024), 0, n->st, n->lpart, nblk, (const long long*)dcnt,
+                       bc, dloss);
+    double hl[2];
+    FCHK(n, hipMemcpyAsync(hl, n->lscal, 16, hipMemcpyDeviceToHost, n->st));
     FCHK(n, hipStreamSynchronize(n->st));
-    double s = 0.0;
-    for (double v : lp) s += v;
-    *loss = (float)(s / ((double)B * cout * cnt));
+    long long hc;
+    std::memcpy(&hc, &hl[0], 8);
+    if (hc == 0) return ffail(n, LBM_EINVAL, "empty loss mask");
+    *loss = (float)hl[1];
   }
   if (host_grads) {
     FCHK(n, hipMemcpyAsync(host_grads, n->grad, n->nparam * 4, hipMemcpyDeviceToHost, n->st));

@@ -758,7 +758,7 @@ __global__ __launch_bounds__(256) void proj_bwd_kernel(const uint16_t* __restric
 #pragma unroll
     for (int ct2 = 0; ct2 < 2 * KS; ++ct2) go[ct2] = f32x4{0.f, 0.f, 0.f, 0.f};
     // one k step of Q1^T at a time: hidden tiles 2 s and 2 s + 1
-#pragma unroll 1
+#pragma unroll
     for (int s = 0; s < NT / 2; ++s) {
       uint32_t u[4];  // packed BF16 gradient, (tile, r = 0, 1) and (tile, r = 2, 3)
 #pragma unroll
@@ -1166,8 +1166,50 @@ __global__ __launch_bounds__(256) void colsum_kernel(const float* X, int A, int6
 
 // ------------------------------------------------------------- elementwise
 // masked MSE: per-block partial of sum mask (y - t)^2, and gy = 2 mask (y - t) / cnt
+// Number of cells with mask != 0 (one block; P % 16 == 0), and the gradient
+// scale 1 / (bc * count) rounded once from FP64 (0 for an empty mask).
+__global__ __launch_bounds__(1024) void mask_count_kernel(const uint8_t* mask, int64_t P, double bc,
+                                                          long long* cnt, float* scale) {
+  __shared__ long long red[1024];
+  const int t = threadIdx.x;
+  long long c = 0;
+  for (int64_t i = (int64_t)t * 16; i < P; i += 1024 * 16) {
+    const uint4 q = *(const uint4*)(mask + i);
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) c += ((w[k >> 2] >> (8 * (k & 3))) & 0xffu) ? 1 : 0;
+  }
+  red[t] = c;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  if (t == 0) {
+    *cnt = red[0];
+    *scale = red[0] ? (float)(1.0 / (bc * (double)red[0])) : 0.f;
+  }
+}
+
+// loss = (sum of the block partials, fixed order) / (bc * count)
+__global__ __launch_bounds__(1024) void loss_reduce_kernel(const double* part, int64_t nparts, const long long* cnt,
+                                                           double bc, double* loss) {
+  __shared__ double red[1024];
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (int64_t i = t; i < nparts; i += 1024) s += part[i];
+  red[t] = s;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  if (t == 0) *loss = red[0] / (bc * (double)*cnt);
+}
+
 __global__ __launch_bounds__(256) void mse_kernel(const float* y, const float* t, const uint8_t* mask, int64_t P,
-                                                  int64_t n, float inv_cnt, float* gy, double* part) {
+                                                  int64_t n, const float* inv_cnt_d, float* gy, double* part) {
+  const float inv_cnt = *inv_cnt_d;
   __shared__ double red[256];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double s = 0.0;

@@ -90,12 +90,14 @@ class Fno:
     def adam_step(self, lr):
         self._check(self._L.fno_adam_step(self._h, ctypes.c_float(lr)), "fno_adam_step")
 
-    def train_step(self, x, target, mask, lr):
+    def train_step(self, x, target, mask, lr, want_loss=True):
+        """One Adam step; returns the loss, or None without want_loss (then
+        nothing waits for the device)."""
         loss = ctypes.c_float()
         self._check(self._L.fno_train_step(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(target.data_ptr()),
                                            ctypes.c_void_p(mask.data_ptr()), x.shape[0], ctypes.c_float(lr),
-                                           ctypes.byref(loss)), "fno_train_step")
-        return loss.value
+                                           ctypes.byref(loss) if want_loss else None), "fno_train_step")
+        return loss.value if want_loss else None
 
 
 def _fields_check(x):
@@ -201,7 +203,7 @@ def bench_train(batch=16, reps=5):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        net.train_step(x, t, m, 1e-4)
+        net.train_step(x, t, m, 1e-4, want_loss=False)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / reps * 1e3
     net.close()

@@ -176,15 +176,18 @@ def train(cfg, net, xs, ys, n_train, mask_d):
     e0.record()
     step = 0
     for ep in range(cfg.epochs):
-        perm = rng.permutation(n_train)
+        perm = torch.from_numpy(rng.permutation(n_train)).to("cuda")
         losses = []
         for b in range(steps_per_epoch):
             idx = perm[b * cfg.batch:(b + 1) * cfg.batch]
-            for j, i in enumerate(idx):
-                xb[j].copy_(xs[int(i)])
-                yb[j].copy_(ys[int(i)])
+            torch.index_select(xs, 0, idx, out=xb)
+            torch.index_select(ys, 0, idx, out=yb)
             lr = cfg.lr * 0.5 * (1.0 + math.cos(math.pi * step / total))
-            losses.append(net.train_step(xb, yb, mask_d, lr))
+            # the loss is read back (a device wait) on every 8th step only
+            want = b % 8 == 7 or b == steps_per_epoch - 1
+            loss = net.train_step(xb, yb, mask_d, lr, want_loss=want)
+            if want:
+                losses.append(loss)
             step += 1
         hist.append(float(np.mean(losses)))
         log(f"epoch {ep + 1}/{cfg.epochs}: loss {hist[-1]:.3e}")

@@ -120,3 +120,19 @@ def test_training_fits_teacher_network():
     losses = [net.train_step(x, t, mask, 1e-2) for _ in range(60)]
     print("losses", losses[0], losses[-1])
     assert losses[-1] < 0.25 * losses[0]
+
+
+def test_empty_mask_is_an_error_when_the_loss_is_read():
+    """An empty loss mask gives zero gradients (so a first Adam step leaves the
+    parameters unchanged) and LBM_EINVAL when the loss is requested."""
+    import torch
+    from paper_2606_16765_amd import FnoError
+    net, x, t = _setup(SMALL, 1)
+    mask = torch.zeros((SMALL["nx"], SMALL["ny"], SMALL["nz"]), dtype=torch.uint8, device="cuda")
+    with pytest.raises(FnoError, match="empty loss mask"):
+        net.loss_grad(x, t, mask, grads=False)
+    before = net.get_params()
+    assert net.train_step(x, t, mask, 1e-2, want_loss=False) is None
+    torch.cuda.synchronize()
+    assert np.array_equal(net.get_params(), before)
+    net.close()
