@@ -155,6 +155,13 @@ int lbm_moments(lbm_sim* s, float* out, int out_on_device);
  * (solid cells 0), whatever the AA parity.  Host pointer.  Synchronises.     */
 int lbm_get_populations(lbm_sim* s, double* fbar);
 
+/* The same for the cells of one box [x0, x0 + bx) x [y0, y0 + by) x
+ * [z0, z0 + bz): host double fbar [27][bz][by][bx].  LBM_EINVAL for a box
+ * not inside the grid.  Synchronises.  For checking sampled cells of grids
+ * whose full state does not fit the host.                                   */
+int lbm_get_populations_box(lbm_sim* s, int32_t x0, int32_t y0, int32_t z0, int32_t bx, int32_t by, int32_t bz,
+                            double* fbar);
+
 /* Replace the state with natural-layout fbar [27][N] (host double, rounded
  * to the storage type); resets the AA parity, keeps step count and
  * accumulators.                                                              */

@@ -45,6 +45,7 @@ def _sig(L):
     L.lbm_moments.argtypes = [vp, vp, ctypes.c_int]
     L.lbm_get_populations.argtypes = [vp, vp]
     L.lbm_set_populations.argtypes = [vp, vp]
+    L.lbm_get_populations_box.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp]
     L.lbm_mass.argtypes = [vp, P(dbl)]
     L.lbm_export_state.argtypes = [vp, vp, ctypes.c_size_t, P(ctypes.c_size_t)]
     L.lbm_import_state.argtypes = [vp, vp, ctypes.c_size_t]

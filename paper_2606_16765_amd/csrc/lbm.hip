@@ -578,6 +578,30 @@ __global__ __launch_bounds__(NTHREADS) void export_kernel(StepArgs a, Coef<typen
   }
 }
 
+// Natural-layout export of a box of cells [x0, x0 + bx) x [y0, y0 + by) x
+// [z0, z0 + bz): pops [27][bz][by][bx], the same values export_kernel
+// writes for those cells.
+template <typename S, bool ODD>
+__global__ __launch_bounds__(256) void export_box_kernel(StepArgs a, Coef<typename Storage<S>::T> k, int x0, int y0,
+                                                         int z0, int bx, int by, int bz, double* pops) {
+  using T = typename Storage<S>::T;
+  const int64_t nb = (int64_t)bx * by * bz;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nb) return;
+  const int x = x0 + (int)(i % bx), y = y0 + (int)((i / bx) % by), z = z0 + (int)(i / ((int64_t)bx * by));
+  const int64_t n = ((int64_t)z * a.ny + y) * a.nx + x;
+  const uint8_t fl = a.flag[n];
+  if (fl == 2) {
+    for (int q = 0; q < 27; ++q) pops[(int64_t)q * nb + i] = 0.0;
+    return;
+  }
+  CellCtx c;
+  make_ctx(a, x, y, z, fl, c);
+  T g[27];
+  load_general<S, ODD>(a, k, c, g);
+  for (int q = 0; q < 27; ++q) pops[(int64_t)q * nb + i] = (double)g[q];
+}
+
 // Natural-layout import (even parity): double fbar [27][N] -> storage.
 template <typename S>
 __global__ __launch_bounds__(256) void import_kernel(StepArgs a, const double* pops) {
@@ -828,6 +852,19 @@ static void launch_export(int storage, const StepArgs& a, const Coefs& c, bool o
     case LBM_F16S: launch_export_s<f16s>(a, c, odd, pops, mom, mp, st); break;
     case LBM_BF16S: launch_export_s<bf16s>(a, c, odd, pops, mom, mp, st); break;
   }
+}
+
+template <typename S>
+static void launch_export_box_s(const StepArgs& a, const Coefs& c, bool odd, const int* box, double* pops,
+                                hipStream_t st) {
+  const int64_t nb = (int64_t)box[3] * box[4] * box[5];
+  const dim3 g((unsigned)((nb + 255) / 256));
+  if (odd)
+    hipLaunchKernelGGL((export_box_kernel<S, true>), g, dim3(256), 0, st, a, coef_for<S>(c), box[0], box[1], box[2],
+                       box[3], box[4], box[5], pops);
+  else
+    hipLaunchKernelGGL((export_box_kernel<S, false>), g, dim3(256), 0, st, a, coef_for<S>(c), box[0], box[1], box[2],
+                       box[3], box[4], box[5], pops);
 }
 
 static void launch_init(int storage, const StepArgs& a, const double* u0, hipStream_t st) {
@@ -1268,6 +1305,31 @@ extern "C" int lbm_get_populations(lbm_sim* s, double* fbar) {
   HIPCHK(s, hipMalloc(&tmp, (size_t)s->N * 27 * 8));
   launch_export(s->p.storage, s->args, s->coefs, s->parity != 0, tmp, nullptr, nullptr, s->stream);
   hipError_t e = hipMemcpyAsync(fbar, tmp, (size_t)s->N * 27 * 8, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(s, LBM_EDEVICE, hipGetErrorString(e));
+  return LBM_OK;
+}
+
+extern "C" int lbm_get_populations_box(lbm_sim* s, int32_t x0, int32_t y0, int32_t z0, int32_t bx, int32_t by,
+                                       int32_t bz, double* fbar) {
+  if (!s || !fbar) return fail(s, LBM_EINVAL, "null argument");
+  if (s->sticky) return s->sticky;
+  if (bx <= 0 || by <= 0 || bz <= 0 || x0 < 0 || y0 < 0 || z0 < 0 || x0 > s->p.nx - bx || y0 > s->p.ny - by ||
+      z0 > s->p.nz - bz)
+    return fail(s, LBM_EINVAL, "box outside the grid");
+  const int64_t nb = (int64_t)bx * by * bz;
+  double* tmp = nullptr;
+  HIPCHK(s, hipMalloc(&tmp, (size_t)nb * 27 * 8));
+  const int box[6] = {x0, y0, z0, bx, by, bz};
+  switch (s->p.storage) {
+    case LBM_F64: launch_export_box_s<double>(s->args, s->coefs, s->parity != 0, box, tmp, s->stream); break;
+    case LBM_F32: launch_export_box_s<float>(s->args, s->coefs, s->parity != 0, box, tmp, s->stream); break;
+    case LBM_F16S: launch_export_box_s<f16s>(s->args, s->coefs, s->parity != 0, box, tmp, s->stream); break;
+    case LBM_BF16S: launch_export_box_s<bf16s>(s->args, s->coefs, s->parity != 0, box, tmp, s->stream); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(fbar, tmp, (size_t)nb * 27 * 8, hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   (void)hipFree(tmp);
   if (e != hipSuccess) return fail(s, LBM_EDEVICE, hipGetErrorString(e));

@@ -194,6 +194,15 @@ class Lbm:
         self._chk(self._L.lbm_get_populations(self._h, _ptr(a)), "lbm_get_populations")
         return a
 
+    def populations_box(self, origin, size):
+        """Pre-collision populations of the cells of one box, natural layout,
+        double [27][bz][by][bx]; origin (x0, y0, z0), size (bx, by, bz)."""
+        (x0, y0, z0), (bx, by, bz) = origin, size
+        a = np.empty((27, bz, by, bx))
+        self._chk(self._L.lbm_get_populations_box(self._h, x0, y0, z0, bx, by, bz, _ptr(a)),
+                  "lbm_get_populations_box")
+        return a
+
     def set_populations(self, fbar):
         a = np.ascontiguousarray(fbar, dtype=np.float64)
         assert a.size == 27 * self.N

@@ -46,6 +46,7 @@ def test_invalid_parameters_rejected_without_device_work():
     assert L.lbm_step(None, 1) == 1
     ms = ctypes.c_double()
     assert L.lbm_bandwidth_probe(None, 2, ctypes.byref(ms)) == 1
+    assert L.lbm_get_populations_box(None, 0, 0, 0, 1, 1, 1, None) == 1
     assert L.lbm_mean_fields_pooled(None, 2, 0, None) == 1
     lo = (ctypes.c_float * 4)()
     assert L.fno_field_minmax(None, 1, 1, 1, None, lo, lo) == 1

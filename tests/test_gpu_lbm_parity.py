@@ -282,3 +282,84 @@ def test_device_perturbation_matches_host_generator():
     a = P.Lbm(shape, storage="f64", nu=0.02, solid=geo.solid, u0=u0)
     b = P.Lbm(shape, storage="f64", nu=0.02, solid=geo.solid, perturb=(77, 5e-4))
     assert np.array_equal(a.populations(), b.populations())
+
+
+# ---------------------------------------------------------- full size (C2)
+def test_full_size_c2_step_on_sampled_boxes():
+    """The benchmark configuration itself: 1024 x 512 x 512, FP32 storage,
+    spanwise cylinder D = 64 at (307.2, 255.5), Re_D 3900 (K17), interpolated
+    bounce-back, forces every step.  After 40 steps, boxes of cells are cut
+    out of the GPU state (natural layout) and stepped once by the FP64 oracle
+    as stand-alone domains; the GPU's next step must agree on every cell
+    whose neighbourhood lies in the box or beyond a real domain boundary.
+    Two consecutive steps cover both AA parities.  The boxes hold the
+    cylinder surface (interpolated links, general path), open interior
+    (flag-free tiles), the inlet with two walls and the outlet with the two
+    other walls.  Bound: 1e-5 of the largest |fbar| in the box (FP32 storage
+    and arithmetic against FP64 from the same FP32 inputs)."""
+    P = _gpu()
+    from inputs import spanwise_cylinder
+    shape = (1024, 512, 512)
+    geo = spanwise_cylinder(shape, center=(307.2, 255.5), diameter=64.0)
+    nu = P.nu_from_re(0.05, 64.0, 3900.0)
+    sim = P.Lbm(shape, storage="f32", u_in=0.05, nu=nu, mode="auto", solid=geo.solid, links=geo.links,
+                obstacle_bc=1, perturb=(0, 0.01 * 0.05), avg_start=None, force_every=1)
+    assert sim.info()["mode"] == 1
+    sim.step(40)
+    boxes = [((260, 236, 100), (96, 40, 12)),   # cylinder front and flank
+             ((600, 300, 200), (64, 16, 16)),   # open interior
+             ((0, 0, 0), (32, 16, 16)),          # inlet corner with walls y = 0, z = 0
+             ((992, 496, 496), (32, 16, 16))]    # outlet corner with walls y = ny - 1, z = nz - 1
+    cell, d, q = geo.links
+    lx_all = cell % shape[0]
+    ly_all = (cell // shape[0]) % shape[1]
+    lz_all = cell // (shape[0] * shape[1])
+    worst = 0.0
+    for step in range(2):
+        pres = [sim.populations_box(o, s) for o, s in boxes]
+        sim.step(1)
+        for (o, s), pre in zip(boxes, pres):
+            post = sim.populations_box(o, s)
+            (x0, y0, z0), (bx, by, bz) = o, s
+            solid = np.ascontiguousarray(geo.solid.reshape(shape[2], shape[1], shape[0])[z0:z0 + bz, y0:y0 + by,
+                                                                                         x0:x0 + bx])
+            inb = ((lx_all >= x0) & (lx_all < x0 + bx) & (ly_all >= y0) & (ly_all < y0 + by) & (lz_all >= z0) &
+                   (lz_all < z0 + bz))
+            lc = ((lz_all[inb] - z0) * by + (ly_all[inb] - y0)) * bx + (lx_all[inb] - x0)
+            p = olbm.make_params(s, nu=nu, u_in=0.05, mode=1, obstacle_bc=1)
+            o_run = olbm.Run(p, solid=solid, links=(lc, d[inb], q[inb]), fbar=pre)
+            o_run.step(1, forces=False)
+            ref = o_run.fbar.reshape(27, bz, by, bx)
+            sl = []
+            for org, size, n in zip((z0, y0, x0), (bz, by, bx), (shape[2], shape[1], shape[0])):
+                lo = 0 if org == 0 else 1
+                hi = size if org + size == n else size - 1
+                sl.append(slice(lo, hi))
+            a, r = post[:, sl[0], sl[1], sl[2]], ref[:, sl[0], sl[1], sl[2]]
+            err = float(np.abs(a - r).max() / np.abs(r).max())
+            nlink = int(inb.sum())
+            print(f"step {41 + step} box {o} {s}: {nlink} links, max rel err {err:.2e}")
+            assert np.abs(r).max() > 0
+            assert err < 1e-5, (o, s, step, err)
+            worst = max(worst, err)
+    print("worst", worst)
+    sim.close()
+
+
+def test_populations_box_matches_full_export():
+    """The box export returns the full export's values for its cells, at
+    both AA parities, and rejects boxes that leave the grid."""
+    P = _gpu()
+    shape = (64, 32, 32)
+    geo = sphere_channel(shape, (20.0, 15.5, 15.5), 5.0)
+    g = P.Lbm(shape, storage="f32", nu=0.01, u_in=0.05, mode="k17", solid=geo.solid, links=geo.links,
+              obstacle_bc=1, perturb=(3, 5e-4))
+    for n in (7, 1):
+        g.step(n)
+        full = g.populations()
+        b = g.populations_box((5, 9, 2), (40, 13, 21))
+        assert np.array_equal(b, full[:, 2:23, 9:22, 5:45])
+    from paper_2606_16765_amd._lib import HipError
+    with pytest.raises(HipError, match="box outside"):
+        g.populations_box((30, 0, 0), (40, 8, 8))
+    g.close()
