@@ -252,7 +252,7 @@ def c1_leg(steps=2000, warmup=50):
             "achieved_gbs": round(r["achieved"], 1), "frac": round(r["achieved"] / HBM_PEAK_GBS, 4)}
 
 
-def cpu_baseline(name, budget_s=15.0):
+def cpu_baseline(name, budget_s=15.0, one_core=False):
     """The FP64 oracle, as it stands, on a bounded sample of the workload:
     the same configuration at 128 x 64 x 64 (geometry scaled by 1/8), timed
     on this host's cores."""
@@ -277,9 +277,26 @@ def cpu_baseline(name, budget_s=15.0):
     r.step(n)
     dt = time.perf_counter() - t
     N = shape[0] * shape[1] * shape[2]
-    return dict(value=N * n / dt / 1e6, unit="MLUPS", cores=olbm.threads(), kind="oracle",
-                sample=f"{name} configuration at 128x64x64 (geometry scaled 1/8), FP64 oracle, {n} steps, "
-                       f"{dt:.1f} s")
+    out = dict(value=N * n / dt / 1e6, unit="MLUPS", cores=olbm.threads(), kind="oracle",
+               sample=f"{name} configuration at 128x64x64 (geometry scaled 1/8), FP64 oracle, {n} steps, "
+                      f"{dt:.1f} s")
+    if not one_core:
+        out["single_core"] = cpu_baseline_one_core(name)
+    return out
+
+
+def cpu_baseline_one_core(name, budget_s=6.0):
+    """The same oracle sample on one core: a child process with
+    OMP_NUM_THREADS=1 (the oracle library fixes its thread count when it
+    loads), so that nothing in it touches the GPU."""
+    import subprocess
+    code = ("import json, sys; sys.path.insert(0, %r); import bench; "
+            "print(json.dumps(bench.cpu_baseline(%r, %r, one_core=True)))" % (ROOT, name, budget_s))
+    env = dict(os.environ, OMP_NUM_THREADS="1", HIP_VISIBLE_DEVICES="")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=300)
+    if r.returncode != 0:
+        return {"error": r.stderr[-300:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def main():
