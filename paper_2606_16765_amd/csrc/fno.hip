@@ -396,11 +396,12 @@ static int inverse_dft(fno_net* n, int B, const uint16_t* modes, const GtMat& Gz
   return contract(n, c);
 }
 
-static int colsum(fno_net* n, const float* Xd, int A, int B, float* out, bool accumulate) {
+template <typename XT>
+static int colsum(fno_net* n, const XT* Xd, int A, int B, float* out, bool accumulate) {
   const int64_t chunk = 8192;
   const int64_t nb = (int64_t)B * n->P / chunk;
-  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)nb, (unsigned)A), dim3(256), 0, n->st, Xd, A, n->P, B, chunk,
-                     n->part);
+  hipLaunchKernelGGL((colsum_kernel<XT>), dim3((unsigned)nb, (unsigned)A), dim3(256), 0, n->st, Xd, A, n->P, B,
+                     chunk, n->part);
   hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((A + 255) / 256)), dim3(256), 0, n->st, n->part, nb,
                      (int64_t)A, out, accumulate ? 1 : 0);
   return LBM_OK;
@@ -425,11 +426,13 @@ static bool launch_gram2(fno_net* n, const XT* Xd, int A, const YT* Yd, int Cc, 
   MFNO_GRAM2(8, 1)
   MFNO_GRAM2(8, 2)
   MFNO_GRAM2(2, 8)
+  MFNO_GRAM2(4, 4)
+  MFNO_GRAM2(8, 4)
 #undef MFNO_GRAM2
   return false;
 }
 
-// out[a][c] (+)= sum_{b,p} X[b][a][p] Y[b][c][p]; with bout (FP32 X), also
+// out[a][c] (+)= sum_{b,p} X[b][a][p] Y[b][c][p]; with bout, also
 // bout[a] = sum_{b,p} X[b][a][p] (the bias gradient of the same map)
 template <typename XT, typename YT>
 static int gram(fno_net* n, const XT* Xd, int A, const YT* Yd, int Cc, int B, float* out, bool accumulate,
@@ -456,10 +459,7 @@ static int gram(fno_net* n, const XT* Xd, int A, const YT* Yd, int Cc, int B, fl
       return LBM_OK;
     }
   }
-  if (bout) {
-    if constexpr (std::is_same<XT, float>::value) colsum(n, Xd, A, B, bout, false);
-    else return ffail(n, LBM_EINVAL, "bias gradient needs FP32 rows");
-  }
+  if (bout) colsum(n, Xd, A, B, bout, false);
   const int64_t nch = (int64_t)B * n->P / chunk;
   if (nch * A * Cc > n->part_elems) return ffail(n, LBM_EINVAL, "gram partial buffer too small");
   hipLaunchKernelGGL((gram_kernel<XT, YT>), dim3((unsigned)nch, (unsigned)((A + 15) / 16), (unsigned)((Cc + 15) / 16)),

@@ -1146,15 +1146,16 @@ __global__ __launch_bounds__(256) void reduce_parts_kernel(const float* part, in
 }
 
 // per-block partial sums over (b, p) of X[b][a][p]: part[blk][a]
-__global__ __launch_bounds__(256) void colsum_kernel(const float* X, int A, int64_t P, int B, int64_t chunk,
+template <typename XT>  // FP32 rows, or BF16 rows summed as stored
+__global__ __launch_bounds__(256) void colsum_kernel(const XT* X, int A, int64_t P, int B, int64_t chunk,
                                                      float* part) {
   __shared__ float red[256];
   const int a = blockIdx.y;
   const int64_t per_b = P / chunk;
   const int64_t b = blockIdx.x / per_b, p0 = (blockIdx.x % per_b) * chunk;
-  const float* x = X + (b * A + a) * P + p0;
+  const XT* x = X + (b * A + a) * P + p0;
   float s = 0.f;
-  for (int64_t p = threadIdx.x; p < chunk; p += 256) s += x[p];
+  for (int64_t p = threadIdx.x; p < chunk; p += 256) s += to_f(x[p]);
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {

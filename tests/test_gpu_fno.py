@@ -47,10 +47,27 @@ def test_forward_matches_oracle_small():
     assert err < 3e-2
 
 
-def test_gradients_match_oracle_small():
+# wider networks take the other code paths: 64-channel-class mixing kernels,
+# the unfused layer end (width > 32) and the two-k-step projection (width 64)
+WIDE = [dict(SMALL, width=48, layers=1, hidden=32), dict(SMALL, width=64, layers=2, hidden=48)]
+
+
+@pytest.mark.parametrize("cfg", WIDE, ids=["w48", "w64"])
+def test_forward_wide_matches_oracle(cfg):
+    net, x, _ = _setup(cfg, 2)
+    y = net.forward(x).cpu().numpy()
+    th = net.get_params().astype(np.float64)
+    yo, _ = ofno.forward(th, x.float().cpu().numpy().astype(np.float64), _shape(cfg))
+    err = rel_l2(y, yo)
+    print("forward rel L2", cfg["width"], err)
+    assert err < 3e-2
+
+
+@pytest.mark.parametrize("cfg", [SMALL] + WIDE, ids=["w16", "w48", "w64"])
+def test_gradients_match_oracle_small(cfg):
     import torch
-    s = _shape(SMALL)
-    net, x, t = _setup(SMALL, 2)
+    s = _shape(cfg)
+    net, x, t = _setup(cfg, 2)
     mask = torch.from_numpy(ofno.inner_box_mask(s)).cuda()
     loss, g = net.loss_grad(x, t, mask)
     th = net.get_params().astype(np.float64)
