@@ -75,6 +75,23 @@ def test_walled_channel_f64_populations(steps):
 
 
 @pytest.mark.parametrize("mode", ["plain", "k17"])
+def test_periodic_sides_obstacle_channel_f64(mode):
+    """Inlet and outlet in x with periodic y and z, the lateral setting of
+    the sphere-drag validation runs, with interpolated bounce-back."""
+    shape = (64, 16, 16)
+    geo = sphere_channel(shape, center=(20.3, 7.6, 7.4), radius=3.3)
+    u0 = perturbation(shape, 6, 5e-4, geo.solid)
+    nu = 0.05 * 16 / 5000 if mode == "k17" else 0.01
+    g, o = pair(shape, 33, solid=geo.solid, links=geo.links, u0=u0, nu=nu, mode=mode, obstacle_bc=1,
+                periodic=(0, 1, 1))
+    err = f64_err(g.populations(), o.fbar)
+    assert err < 1e-11, err
+    fg, _ = g.forces()
+    fo = np.array(o.forces)
+    assert np.abs(fg - fo).max() < 1e-11 * np.abs(fo).max()
+
+
+@pytest.mark.parametrize("mode", ["plain", "k17"])
 @pytest.mark.parametrize("obstacle_bc", [0, 1])
 def test_obstacle_channel_f64(mode, obstacle_bc):
     shape = (64, 16, 16)
