@@ -444,7 +444,9 @@ static int gram(fno_net* n, const XT* Xd, int A, const YT* Yd, int Cc, int B, fl
     const int64_t E = (int64_t)A * Cc;
     constexpr int S = 64;
     const bool with_c = bout && nch * A <= n->partc_elems && S * A <= n->part2_elems;
-    if (nch % 4 == 0 && nch * E <= n->part_elems && S * E <= n->part2_elems && (with_c || !bout) &&
+    // (16-byte operand loads: misaligned rows take the scalar fallback)
+    const bool aligned = ((uintptr_t)Xd % 16) == 0 && ((uintptr_t)Yd % 16) == 0;
+    if (aligned && nch % 4 == 0 && nch * E <= n->part_elems && S * E <= n->part2_elems && (with_c || !bout) &&
         launch_gram2(n, Xd, A, Yd, Cc, nch, with_c ? n->partc : nullptr)) {
       hipLaunchKernelGGL(reduce_slices_kernel, dim3((unsigned)((E + 255) / 256), S), dim3(256), 0, n->st, n->part,
                          nch, E, S, n->part2);
@@ -748,7 +750,8 @@ static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout, bool 
   const bool fuse_z = n->fused_layer_end && n->Z == 64 && W == 32 && 2 * n->MZ == 32 && n->F1.kp >= 64;
   bool z_done = false;
   // lift: v0 = P x + p (no activation; the pre-activation is not kept)
-  if (fuse_z && n->p.cin <= 32 && n->Glift.kp == 32) {
+  // (16-byte vector loads of x: a misaligned input takes the separate lift)
+  if (fuse_z && n->p.cin <= 32 && n->Glift.kp == 32 && ((uintptr_t)x % 16) == 0) {
     LayerEndArgs e{};
     e.v = x; e.r2 = nullptr; e.gwp = n->Glift.d; e.gi1 = nullptr; e.gi1_kp = 0;
     e.bias = n->theta + n->off_p; e.h = nullptr; e.act = n->v[0];

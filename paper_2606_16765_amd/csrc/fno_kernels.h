@@ -1167,18 +1167,23 @@ __global__ __launch_bounds__(256) void colsum_kernel(const XT* X, int A, int64_t
 
 // ------------------------------------------------------------- elementwise
 // masked MSE: per-block partial of sum mask (y - t)^2, and gy = 2 mask (y - t) / cnt
-// Number of cells with mask != 0 (one block; P % 16 == 0), and the gradient
-// scale 1 / (bc * count) rounded once from FP64 (0 for an empty mask).
+// Number of cells with mask != 0 (one block), and the gradient scale
+// 1 / (bc * count) rounded once from FP64 (0 for an empty mask).  16-byte
+// loads when the mask is 16-byte aligned and P % 16 == 0, bytes otherwise.
 __global__ __launch_bounds__(1024) void mask_count_kernel(const uint8_t* mask, int64_t P, double bc,
                                                           long long* cnt, float* scale) {
   __shared__ long long red[1024];
   const int t = threadIdx.x;
   long long c = 0;
-  for (int64_t i = (int64_t)t * 16; i < P; i += 1024 * 16) {
-    const uint4 q = *(const uint4*)(mask + i);
-    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+  if (((uintptr_t)mask & 15) == 0 && P % 16 == 0) {
+    for (int64_t i = (int64_t)t * 16; i < P; i += 1024 * 16) {
+      const uint4 q = *(const uint4*)(mask + i);
+      const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-    for (int k = 0; k < 16; ++k) c += ((w[k >> 2] >> (8 * (k & 3))) & 0xffu) ? 1 : 0;
+      for (int k = 0; k < 16; ++k) c += ((w[k >> 2] >> (8 * (k & 3))) & 0xffu) ? 1 : 0;
+    }
+  } else {
+    for (int64_t i = t; i < P; i += 1024) c += mask[i] ? 1 : 0;
   }
   red[t] = c;
   __syncthreads();
