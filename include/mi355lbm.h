@@ -207,7 +207,8 @@ const char* lbm_last_error(const lbm_sim* s); /* s may be NULL: global error */
  * `layers` Fourier layers (truncated 3D real DFT keeping kx, ky in
  * {0..m-1, -m..-1} and kz in {0..m-1}, per-mode complex channel mixing,
  * truncated inverse DFT, plus a pointwise linear map and bias, GELU after
- * all but the last), projection width -> proj_hidden (GELU) -> cout.
+ * all but the last), projection width -> proj_hidden (GELU, or the sine of
+ * a SIREN) -> cout.
  * Contractions run as BF16 MFMA with FP32 accumulation.                      */
 typedef struct fno_net fno_net;
 
@@ -221,6 +222,11 @@ typedef struct {
                                2*my*mz >= 32 (>= 16 when width > 32)          */
   int32_t proj_hidden;      /* projection hidden width (128), % 16 == 0       */
   int32_t max_batch;        /* largest batch the workspaces are sized for     */
+  int32_t proj_act;         /* projection hidden activation: 0 GELU (erf),
+                               1 sine (SIREN, App. A.2): sin(proj_w0 (W1 v + b1))
+                               with Sitzmann's initialisation; the sine needs
+                               proj_hidden <= 128, width <= 64, cout <= 16   */
+  float proj_w0;            /* SIREN frequency (30); ignored for GELU         */
 } fno_params;
 
 /* Parameter vector layout (FP32, fno_param_count entries), in this order:

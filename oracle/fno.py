@@ -14,10 +14,13 @@ feed-forward lifting; predicts mean flow fields from geometry and Re):
                       normalised by 1/(X Y Z))
       h = s + Wp_l v + bp_l
       v = GELU(h) except after the last layer (GELU with erf)
-  y = Q2 GELU(Q1 v + q1) + q2                   projection width -> hidden -> cout
+  y = Q2 act(Q1 v + q1) + q2                    projection width -> hidden -> cout
+                      act = GELU, or for the SIREN projection of App. A.2
+                      act(h) = sin(w0 h) (w0 = 30)
 Loss: mean squared error over the cells of a mask (App. A.2, inner region),
 all samples and output channels.  Optimiser: Adam (beta 0.9, 0.999,
-eps 1e-8).  The paper's SIREN projection is replaced by a GELU MLP.
+eps 1e-8).  The projection is a GELU MLP by default; proj = "siren" gives
+the paper's SIREN (sine activation with frequency w0).
 
 Parameter vector layout (shared with the GPU library's C ABI):
   lift W [width][cin], lift b [width];
@@ -46,6 +49,8 @@ class Shape:
     my: int = 16
     mz: int = 16
     hidden: int = 128
+    proj: str = "gelu"
+    w0: float = 30.0
 
 
 def param_count(s: Shape) -> int:
@@ -153,6 +158,15 @@ def gelu_grad(x):
     return 0.5 * (1.0 + erf(x / math.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
 
 
+def proj_act(h, s: Shape):
+    """Hidden activation of the projection: GELU, or sin(w0 h) (SIREN)."""
+    return np.sin(s.w0 * h) if s.proj == "siren" else gelu(h)
+
+
+def proj_act_grad(h, s: Shape):
+    return s.w0 * np.cos(s.w0 * h) if s.proj == "siren" else gelu_grad(h)
+
+
 def pointwise(W, v, b=None):
     """(W v)[b, o, ...] = sum_c W[o, c] v[b, c, ...] (+ bias)."""
     out = np.tensordot(W, v, axes=([1], [1]))  # [o, b, ...]
@@ -180,7 +194,7 @@ def forward(theta, x, s: Shape, mats=None):
     cache["vL"] = v
     h1 = pointwise(p["Q1"], v, p["q1"])
     cache["h1"] = h1
-    y = pointwise(p["Q2"], gelu(h1), p["q2"])
+    y = pointwise(p["Q2"], proj_act(h1, s), p["q2"])
     return y, cache
 
 
@@ -201,12 +215,12 @@ def backward(theta, cache, gy, s: Shape, mats=None):
     g = {"layers": [None] * s.layers}
     # projection
     h1 = cache["h1"]
-    a = gelu(h1)
+    a = proj_act(h1, s)
     red = tuple(i for i in range(gy.ndim) if i != 1)
     g["Q2"] = np.tensordot(gy, a, axes=(red, red))
     g["q2"] = gy.sum(axis=red)
     ga = pointwise(p["Q2"].T, gy)
-    gh1 = ga * gelu_grad(h1)
+    gh1 = ga * proj_act_grad(h1, s)
     vL = cache["vL"]
     g["Q1"] = np.tensordot(gh1, vL, axes=(red, red))
     g["q1"] = gh1.sum(axis=red)
@@ -251,9 +265,13 @@ def init_params(s: Shape, seed=0):
     for _ in range(s.layers):
         W = (rng.uniform(0, 1, (w, w, 2 * s.mx, 2 * s.my, s.mz)) + 1j * rng.uniform(0, 1, (w, w, 2 * s.mx, 2 * s.my, s.mz)))
         p["layers"].append({"W": W / (w * w), "Wp": rng.uniform(-1, 1, (w, w)) / math.sqrt(w), "bp": np.zeros(w)})
-    p["Q1"] = rng.uniform(-1, 1, (s.hidden, w)) / math.sqrt(w)
+    if s.proj == "siren":  # Sitzmann et al.: first layer U(+-1/n), later U(+-sqrt(6/n)/w0)
+        p["Q1"] = rng.uniform(-1, 1, (s.hidden, w)) / w
+        p["Q2"] = rng.uniform(-1, 1, (s.cout, s.hidden)) * math.sqrt(6.0 / s.hidden) / s.w0
+    else:
+        p["Q1"] = rng.uniform(-1, 1, (s.hidden, w)) / math.sqrt(w)
+        p["Q2"] = rng.uniform(-1, 1, (s.cout, s.hidden)) / math.sqrt(s.hidden)
     p["q1"] = np.zeros(s.hidden)
-    p["Q2"] = rng.uniform(-1, 1, (s.cout, s.hidden)) / math.sqrt(s.hidden)
     p["q2"] = np.zeros(s.cout)
     return pack(p, s)
 
@@ -267,5 +285,6 @@ def inner_box_mask(s: Shape):
 
 
 __all__ = ["Shape", "param_count", "unpack", "pack", "dft_matrices", "forward_dft", "inverse_dft", "forward",
-           "backward", "masked_mse", "adam", "init_params", "gelu", "gelu_grad", "inner_box_mask", "mode_indices",
+           "backward", "masked_mse", "adam", "init_params", "gelu", "gelu_grad", "proj_act", "proj_act_grad",
+           "inner_box_mask", "mode_indices",
            "adjoint_forward_dft", "adjoint_inverse_dft"]

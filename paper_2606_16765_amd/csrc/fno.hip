@@ -287,21 +287,31 @@ static int pointwise(fno_net* n, int B, const void* in, bool in_bf16, int cin, v
   return contract(n, c);
 }
 
+template <int NT, int KS, int ACT>
+static void launch_proj_act(fno_net* n, int B, const uint16_t* v, float* y, uint16_t* aout) {
+  const unsigned blocks = (unsigned)((int64_t)B * n->P / 256);
+  const float w0 = n->p.proj_w0;
+  if (aout)
+    hipLaunchKernelGGL((proj_kernel<NT, KS, true, ACT>), dim3(blocks), dim3(256), 0, n->st, v, n->W, n->P, n->Pq1.d,
+                       n->pq1b, n->Pq2.d, n->theta + n->off_q2, n->p.cout, y, n->H, aout, w0);
+  else
+    hipLaunchKernelGGL((proj_kernel<NT, KS, false, ACT>), dim3(blocks), dim3(256), 0, n->st, v, n->W, n->P,
+                       n->Pq1.d, n->pq1b, n->Pq2.d, n->theta + n->off_q2, n->p.cout, y, 0, nullptr, w0);
+}
 template <int NT, int KS>
 static void launch_proj(fno_net* n, int B, const uint16_t* v, float* y, uint16_t* aout) {
-  const unsigned blocks = (unsigned)((int64_t)B * n->P / 256);
-  if (aout)
-    hipLaunchKernelGGL((proj_kernel<NT, KS, true>), dim3(blocks), dim3(256), 0, n->st, v, n->W, n->P, n->Pq1.d,
-                       n->pq1b, n->Pq2.d, n->theta + n->off_q2, n->p.cout, y, n->H, aout);
-  else
-    hipLaunchKernelGGL((proj_kernel<NT, KS>), dim3(blocks), dim3(256), 0, n->st, v, n->W, n->P, n->Pq1.d, n->pq1b,
-                       n->Pq2.d, n->theta + n->off_q2, n->p.cout, y, 0, nullptr);
+  if (n->p.proj_act == 1) launch_proj_act<NT, KS, 1>(n, B, v, y, aout);
+  else launch_proj_act<NT, KS, 0>(n, B, v, y, aout);
 }
 template <int NT, int KS>
 static void launch_proj_bwd(fno_net* n, int B, const uint16_t* v, const float* gy, uint16_t* ga, float* gv) {
   const unsigned blocks = (unsigned)((int64_t)B * n->P / 256);
-  hipLaunchKernelGGL((proj_bwd_kernel<NT, KS>), dim3(blocks), dim3(256), 0, n->st, v, n->W, n->P, n->Pq1.d, n->pq1b,
-                     n->Gq2t.d, n->Gq2t.kp, gy, n->p.cout, n->H, ga, gv);
+  if (n->p.proj_act == 1)
+    hipLaunchKernelGGL((proj_bwd_kernel<NT, KS, 1>), dim3(blocks), dim3(256), 0, n->st, v, n->W, n->P, n->Pq1.d,
+                       n->pq1b, n->Gq2t.d, n->Gq2t.kp, gy, n->p.cout, n->H, ga, gv, n->p.proj_w0);
+  else
+    hipLaunchKernelGGL((proj_bwd_kernel<NT, KS, 0>), dim3(blocks), dim3(256), 0, n->st, v, n->W, n->P, n->Pq1.d,
+                       n->pq1b, n->Gq2t.d, n->Gq2t.kp, gy, n->p.cout, n->H, ga, gv, 0.f);
 }
 
 // fused projection; aout (training) also receives the BF16 hidden activation
@@ -542,6 +552,10 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
   const int64_t P = (int64_t)p.nx * p.ny * p.nz;
   if (P % 8192) return ffail(nullptr, LBM_EINVAL, "grid must hold a multiple of 8192 cells");
   if (p.width > 64) return ffail(nullptr, LBM_EINVAL, "width must be at most 64");
+  if (p.proj_act != 0 && p.proj_act != 1) return ffail(nullptr, LBM_EINVAL, "proj_act must be 0 (GELU) or 1 (sine)");
+  if (p.proj_act == 1 && (!(p.proj_w0 > 0.f) || !std::isfinite(p.proj_w0) || round_up(p.proj_hidden, 32) > 128 ||
+                          p.width > 64 || p.cout > 16 || P % 256))
+    return ffail(nullptr, LBM_EINVAL, "the sine projection needs proj_w0 > 0, proj_hidden <= 128 and cout <= 16");
   if (2 * p.my * p.mz < (p.width <= 32 ? MixCfg<32>::MQ : MixCfg<64>::MQ))
     return ffail(nullptr, LBM_EINVAL, "2 my mz must be at least 32 (16 for width above 32)");
   fno_net* n = new (std::nothrow) fno_net();
@@ -683,9 +697,13 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
       for (int64_t i = 0; i < n->M * W * W * 2; ++i) th[n->off_W[l] + i] = (float)(uni(0, 1) / (double)(W * W));
       for (int64_t i = 0; i < W * W; ++i) th[n->off_Wp[l] + i] = (float)uni(-1, 1) / std::sqrt((float)W);
     }
-    for (int64_t i = 0; i < (int64_t)n->H * W; ++i) th[n->off_Q1 + i] = (float)uni(-1, 1) / std::sqrt((float)W);
+    // SIREN (Sitzmann et al.): first layer U(+-1/n), later layers U(+-sqrt(6/n)/w0)
+    const bool siren = p.proj_act == 1;
+    for (int64_t i = 0; i < (int64_t)n->H * W; ++i)
+      th[n->off_Q1 + i] = (float)uni(-1, 1) / (siren ? (float)W : std::sqrt((float)W));
     for (int64_t i = 0; i < (int64_t)p.cout * n->H; ++i)
-      th[n->off_Q2 + i] = (float)uni(-1, 1) / std::sqrt((float)n->H);
+      th[n->off_Q2 + i] = siren ? (float)(uni(-1, 1) * std::sqrt(6.0 / n->H) / p.proj_w0)
+                                : (float)uni(-1, 1) / std::sqrt((float)n->H);
     e = hipMemcpy(n->theta, th.data(), th.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(n->am, 0, n->nparam * 4);
     if (e == hipSuccess) e = hipMemset(n->av, 0, n->nparam * 4);

@@ -606,13 +606,22 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
 // 32s + 16 + 4g + {0..3} (tile 2s+1), and the Q2 operand is gathered with
 // the same assignment, so the sum runs over every hidden row once.
 // With STORE_A (training) the BF16 hidden activation is also stored to
-// aout [B][H][P], for the gradient of Q2.
-template <int NT, int KS, bool STORE_A = false>
+// aout [B][H][P], for the gradient of Q2.  ACT selects the hidden
+// activation: 0 GELU, 1 the SIREN sine sin(w0 h).
+template <int ACT>
+__device__ __forceinline__ float proj_act(float h, float w0) {
+  return ACT == 1 ? sinf(w0 * h) : gelu(h);
+}
+template <int ACT>
+__device__ __forceinline__ float proj_act_grad(float h, float w0) {
+  return ACT == 1 ? w0 * cosf(w0 * h) : gelu_grad(h);
+}
+template <int NT, int KS, bool STORE_A = false, int ACT = 0>
 __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ v, int W, int64_t P,
                                                    const uint16_t* __restrict__ Q1p, const float* __restrict__ q1p,
                                                    const uint16_t* __restrict__ Q2p, const float* __restrict__ q2,
                                                    int cout, float* __restrict__ y, int H = 0,
-                                                   uint16_t* __restrict__ aout = nullptr) {
+                                                   uint16_t* __restrict__ aout = nullptr, float w0 = 0.f) {
   constexpr int WP = 32 * KS, VS = WP + 8, HP = 16 * NT;
   __shared__ __attribute__((aligned(16))) uint16_t vt[256 * VS];
   __shared__ __attribute__((aligned(16))) uint16_t q1s[HP * WP];
@@ -666,7 +675,7 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
       for (int j = 0; j < 8; ++j) {
         const int nt = 2 * s + (j >> 2), r = j & 3;
         const float h = acc[nt][r] + q1p[nt * 16 + 4 * g + r];
-        const uint16_t hb = f2bf(gelu(h));
+        const uint16_t hb = f2bf(proj_act<ACT>(h, w0));
         bv[j] = __builtin_bit_cast(__bf16, hb);
         if (STORE_A) hs[wave * HP * 16 + (nt * 16 + 4 * g + r) * 16 + (lane & 15)] = hb;
       }
@@ -700,12 +709,13 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
 // BF16, zero padded; the Q1^T operand is gathered from Q1p with the hidden
 // rows permuted as the forward's second stage, so that ga feeds it straight
 // from the accumulator registers.  Block and wave layout as proj_kernel.
-template <int NT, int KS>
+template <int NT, int KS, int ACT = 0>
 __global__ __launch_bounds__(256) void proj_bwd_kernel(const uint16_t* __restrict__ v, int W, int64_t P,
                                                        const uint16_t* __restrict__ Q1p, const float* __restrict__ q1p,
                                                        const uint16_t* __restrict__ Q2t, int kp2,
                                                        const float* __restrict__ gy, int cout, int H,
-                                                       uint16_t* __restrict__ ga, float* __restrict__ gv) {
+                                                       uint16_t* __restrict__ ga, float* __restrict__ gv,
+                                                       float w0 = 0.f) {
   constexpr int WP = 32 * KS, VS = WP + 8, HP = 16 * NT;
   __shared__ __attribute__((aligned(16))) uint16_t vt[256 * VS];
   __shared__ __attribute__((aligned(16))) uint16_t q1s[HP * WP];
@@ -771,7 +781,7 @@ __global__ __launch_bounds__(256) void proj_bwd_kernel(const uint16_t* __restric
         const f32x4 tq = mfma16(*(const bf16x8*)(Q2t + (nt * 16 + l16) * kp2 + 8 * g), gb, f32x4{0.f, 0.f, 0.f, 0.f});
         float d[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) d[r] = tq[r] * gelu_grad(acc[r] + q1p[hr + r]);
+        for (int r = 0; r < 4; ++r) d[r] = tq[r] * proj_act_grad<ACT>(acc[r] + q1p[hr + r], w0);
         u[2 * hh] = f2bf2(d[0], d[1]);
         u[2 * hh + 1] = f2bf2(d[2], d[3]);
 #pragma unroll

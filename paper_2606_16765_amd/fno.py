@@ -26,12 +26,14 @@ class Fno:
     projection; trained with masked MSE and Adam."""
 
     def __init__(self, nx=128, ny=64, nz=64, cin=4, cout=4, width=32, layers=4, mx=16, my=16, mz=16, hidden=128,
-                 max_batch=16, seed=0):
+                 max_batch=16, seed=0, proj="gelu", w0=30.0):
         L = load()
         p = FnoParams()
         p.nx, p.ny, p.nz, p.cin, p.cout = nx, ny, nz, cin, cout
         p.width, p.layers, p.mx, p.my, p.mz = width, layers, mx, my, mz
         p.proj_hidden, p.max_batch = hidden, max_batch
+        p.proj_act = {"gelu": 0, "siren": 1}[proj]
+        p.proj_w0 = w0
         self.p = p
         self.shape = (nx, ny, nz)
         self._L = L

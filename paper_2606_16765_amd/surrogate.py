@@ -46,6 +46,9 @@ class Config:
     layers: int = 4
     modes: tuple = (16, 16, 16)
     hidden: int = 128
+    proj: str = "gelu"          # projection hidden activation: "gelu" or "siren" (sine, w0)
+    w0: float = 30.0
+    also_proj: tuple = ()       # further projections trained and evaluated on the same data
     seed: int = 0
     curve_sims: int = 4
     curve_steps: tuple = (1000, 2000, 5000, 10000)
@@ -294,7 +297,7 @@ def run(cfg, out_path=None):
     mask_d = torch.from_numpy(mask).cuda()
     mx, my, mz = cfg.modes
     net = Fno(nx=X, ny=Y, nz=Z, width=cfg.width, layers=cfg.layers, mx=mx, my=my, mz=mz, hidden=cfg.hidden,
-              max_batch=cfg.batch, seed=cfg.seed)
+              max_batch=cfg.batch, seed=cfg.seed, proj=cfg.proj, w0=cfg.w0)
     tinfo = train(cfg, net, xtr, ytr, len(tr) - len(tr) % cfg.batch if len(tr) >= cfg.batch else len(tr), mask_d)
     log(f"trained: {tinfo['train_s']:.1f} s, {tinfo['train_samples_per_s']:.1f} samples/s")
     _dump(out_path, dict(partial="trained", sims=recs, train=tinfo))
@@ -315,6 +318,17 @@ def run(cfg, out_path=None):
     fwd_ms = sum(t for t, _ in times) / sum(b for _, b in times)
     full = [t / b for t, b in times if b == cfg.batch]
     log(f"held-out rel L2 inner: FNO {res_fno['rel_l2_inner']:.4f} vs mean field {res_mean['rel_l2_inner']:.4f}")
+    variants = {}
+    for proj in cfg.also_proj:
+        # the same data, scaling, seed and schedule with another projection
+        vnet = Fno(nx=X, ny=Y, nz=Z, width=cfg.width, layers=cfg.layers, mx=mx, my=my, mz=mz, hidden=cfg.hidden,
+                   max_batch=cfg.batch, seed=cfg.seed, proj=proj, w0=cfg.w0)
+        vinfo = train(cfg, vnet, xtr, ytr, len(tr) - len(tr) % cfg.batch if len(tr) >= cfg.batch else len(tr), mask_d)
+        vpred, _ = predict(cfg, vnet, xs, te, lo, hi)
+        vnet.close()
+        variants[proj] = dict(held_out=metrics(vpred, true, mask), held_out_scaled=metrics(sc(vpred), sc(true), mask),
+                              train_samples_per_s=vinfo["train_samples_per_s"], loss_history=vinfo["loss_history"])
+        log(f"projection {proj}: held-out rel L2 inner {variants[proj]['held_out']['rel_l2_inner']:.4f}")
     # gain test (ii) and time-to-field: shorter LBM runs of held-out obstacles
     curve = []
     held_seeds = [r["seed"] for r in recs[n_train_sims:] if r["stable"]][:cfg.curve_sims]
@@ -344,6 +358,7 @@ def run(cfg, out_path=None):
         fno=dict(held_out=res_fno, held_out_scaled=res_fno_scaled, forward_ms_per_sample=fwd_ms,
                  forward_ms_per_batch=float(np.mean(full)) * cfg.batch if full else None, **tinfo),
         mean_field_baseline=dict(held_out=res_mean, held_out_scaled=res_mean_scaled),
+        projection_variants=variants,
         gain=dict(rel_l2_inner_ratio_mean_over_fno=res_mean["rel_l2_inner"] / res_fno["rel_l2_inner"],
                   rel_l2_whole_ratio_mean_over_fno=res_mean["rel_l2_whole"] / res_fno["rel_l2_whole"]),
         time_to_field=dict(
@@ -373,6 +388,10 @@ def main(argv=None):
     ap.add_argument("--modes", type=int, nargs=3, default=[16, 16, 16])
     ap.add_argument("--hidden", type=int, default=128)
     ap.add_argument("--layers", type=int, default=4)
+    ap.add_argument("--proj", choices=["gelu", "siren"], default="gelu")
+    ap.add_argument("--w0", type=float, default=30.0)
+    ap.add_argument("--also-proj", choices=["gelu", "siren"], nargs="*", default=[],
+                    help="also train and evaluate networks with these projections on the same data")
     ap.add_argument("--curve-sims", type=int, default=4)
     ap.add_argument("--curve-steps", type=int, nargs="*", default=[1000, 2000, 5000, 10000])
     ap.add_argument("--log-every", type=int, default=1)
@@ -380,6 +399,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     cfg = Config(shape=tuple(a.shape), sims=a.sims, held_out=a.held_out, steps=a.steps, epochs=a.epochs,
                  batch=a.batch, lr=a.lr, width=a.width, modes=tuple(a.modes), hidden=a.hidden, layers=a.layers,
+                 proj=a.proj, w0=a.w0, also_proj=tuple(a.also_proj),
                  curve_sims=a.curve_sims, curve_steps=tuple(a.curve_steps), log_every=a.log_every)
     if a.out:
         os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)

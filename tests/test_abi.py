@@ -64,6 +64,13 @@ def test_invalid_parameters_rejected_without_device_work():
     fp.width, fp.my, fp.mz = 16, 2, 4
     assert L.fno_create(ctypes.byref(fp), 0, None, ctypes.byref(h)) == 1  # 2 my mz = 16 < 32
     assert b"2 my mz" in L.fno_last_error(None)
+    fp.my = 4
+    fp.proj_act = 2
+    assert L.fno_create(ctypes.byref(fp), 0, None, ctypes.byref(h)) == 1
+    assert b"proj_act" in L.fno_last_error(None)
+    fp.proj_act, fp.proj_w0 = 1, 0.0
+    assert L.fno_create(ctypes.byref(fp), 0, None, ctypes.byref(h)) == 1  # sine needs w0 > 0
+    assert b"sine projection" in L.fno_last_error(None)
 
 
 def test_binding_raises_on_error():

@@ -20,7 +20,8 @@ SMALL = dict(nx=32, ny=16, nz=16, cin=4, cout=4, width=16, layers=2, mx=4, my=4,
 
 def _shape(d):
     return ofno.Shape(nx=d["nx"], ny=d["ny"], nz=d["nz"], cin=d["cin"], cout=d["cout"], width=d["width"],
-                      layers=d["layers"], mx=d["mx"], my=d["my"], mz=d["mz"], hidden=d["hidden"])
+                      layers=d["layers"], mx=d["mx"], my=d["my"], mz=d["mz"], hidden=d["hidden"],
+                      proj=d.get("proj", "gelu"), w0=d.get("w0", 30.0))
 
 
 def _setup(cfg, B, seed=1):
@@ -50,9 +51,11 @@ def test_forward_matches_oracle_small():
 # wider networks take the other code paths: 64-channel-class mixing kernels,
 # the unfused layer end (width > 32) and the two-k-step projection (width 64)
 WIDE = [dict(SMALL, width=48, layers=1, hidden=32), dict(SMALL, width=64, layers=2, hidden=48)]
+# the paper's SIREN projection (sine hidden activation, w0 = 30)
+SIREN = dict(SMALL, proj="siren", w0=30.0)
 
 
-@pytest.mark.parametrize("cfg", WIDE, ids=["w48", "w64"])
+@pytest.mark.parametrize("cfg", WIDE + [SIREN], ids=["w48", "w64", "siren"])
 def test_forward_wide_matches_oracle(cfg):
     net, x, _ = _setup(cfg, 2)
     y = net.forward(x).cpu().numpy()
@@ -63,7 +66,7 @@ def test_forward_wide_matches_oracle(cfg):
     assert err < 3e-2
 
 
-@pytest.mark.parametrize("cfg", [SMALL] + WIDE, ids=["w16", "w48", "w64"])
+@pytest.mark.parametrize("cfg", [SMALL] + WIDE + [SIREN], ids=["w16", "w48", "w64", "siren"])
 def test_gradients_match_oracle_small(cfg):
     import torch
     s = _shape(cfg)

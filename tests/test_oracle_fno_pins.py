@@ -9,6 +9,8 @@ from oracle import fno
 
 RNG = np.random.default_rng(42)
 SMALL = fno.Shape(nx=8, ny=8, nz=8, cin=2, cout=2, width=3, layers=2, mx=2, my=2, mz=2, hidden=5)
+SMALL_SIREN = fno.Shape(nx=8, ny=8, nz=8, cin=2, cout=2, width=3, layers=2, mx=2, my=2, mz=2, hidden=5,
+                        proj="siren", w0=30.0)
 
 
 def corner(Vfull, s):
@@ -86,6 +88,25 @@ def test_gelu_and_derivative():
     assert np.abs(fno.gelu(x) - x * phi).max() < 1e-14
 
 
+def test_siren_activation_and_derivative():
+    s = SMALL_SIREN
+    x = np.linspace(-0.3, 0.3, 101)
+    assert np.array_equal(fno.proj_act(x, s), np.sin(30.0 * x))
+    h = 1e-7
+    fd = (fno.proj_act(x + h, s) - fno.proj_act(x - h, s)) / (2 * h)
+    assert np.abs(fd - fno.proj_act_grad(x, s)).max() < 1e-5 * 30.0
+    # the default projection is GELU
+    assert np.array_equal(fno.proj_act(x, SMALL), fno.gelu(x))
+
+
+def test_siren_initialisation_scales():
+    s = fno.Shape(width=32, hidden=128, proj="siren")
+    p = fno.unpack(fno.init_params(s, 0), s)
+    assert np.abs(p["Q1"]).max() <= 1.0 / 32 and np.abs(p["Q1"]).max() > 0.9 / 32
+    bound = math.sqrt(6.0 / 128) / 30.0
+    assert np.abs(p["Q2"]).max() <= bound and np.abs(p["Q2"]).max() > 0.9 * bound
+
+
 def test_parameter_pack_round_trip_and_count():
     th = fno.init_params(SMALL, 3)
     assert th.size == fno.param_count(SMALL)
@@ -100,8 +121,8 @@ def _loss(th, x, t, mask, s):
     return fno.masked_mse(y, t, mask)[0]
 
 
-def test_backward_matches_finite_differences():
-    s = SMALL
+@pytest.mark.parametrize("s", [SMALL, SMALL_SIREN], ids=["gelu", "siren"])
+def test_backward_matches_finite_differences(s):
     th = fno.init_params(s, 1)
     x = RNG.standard_normal((2, s.cin, s.nx, s.ny, s.nz))
     t = RNG.standard_normal((2, s.cout, s.nx, s.ny, s.nz))
@@ -111,7 +132,9 @@ def test_backward_matches_finite_differences():
     _, gy = fno.masked_mse(y, t, mask)
     g = fno.backward(th, c, gy, s)
     # every parameter group is sampled: lift, spectral, pointwise, projection
-    idx = np.unique(np.concatenate([np.arange(0, 6), RNG.choice(th.size, 40, replace=False), np.arange(th.size - 8, th.size)]))
+    nproj = s.hidden * s.width + s.hidden + s.cout * s.hidden + s.cout
+    idx = np.unique(np.concatenate([np.arange(0, 6), RNG.choice(th.size, 40, replace=False),
+                                    np.arange(th.size - nproj, th.size)]))
     # central differences: truncation O(h^2), rounding O(eps L / h); the
     # bound leaves room for both and still fails on any wrong term (O(1))
     h = 1e-5
