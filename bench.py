@@ -228,6 +228,7 @@ def fno_leg():
     from paper_2606_16765_amd import fno as pfno
     out = pfno.bench_inference(batch=16, reps=20)
     out["train"] = pfno.bench_train(batch=16)
+    out["siren_projection"] = pfno.bench_inference(batch=16, reps=20, proj="siren")
     cost = pfno.forward_cost(batch=16)
     s = out["ms_per_batch"] / 1e3
     out["roofline"] = {

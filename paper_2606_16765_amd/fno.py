@@ -169,11 +169,11 @@ def forward_cost(batch=16, nx=128, ny=64, nz=64, cin=4, cout=4, width=32, layers
     return {"flops": int(flops), "min_bytes": int(min_bytes)}
 
 
-def bench_inference(batch=16, reps=10):
+def bench_inference(batch=16, reps=10, proj="gelu"):
     """Forward time per batch at the full surrogate shape (128x64x64, width
     32, 4 layers, 32x32x16 retained modes, hidden 128), random input."""
     import torch
-    net = Fno(max_batch=batch)
+    net = Fno(max_batch=batch, proj=proj)
     g = torch.Generator(device="cuda").manual_seed(0)
     x = torch.randn((batch, 4, 128, 64, 64), device="cuda", generator=g).to(torch.bfloat16)
     y = torch.empty((batch, 4, 128, 64, 64), device="cuda")
