@@ -26,6 +26,22 @@ import numpy as np
 
 from .lbm import Lbm, nu_from_re
 
+
+def _run_steps(sim, steps, log, label, parts=10):
+    """Step in chunks, waiting for each, with a progress line per chunk
+    (long runs at large L print something every minute or so)."""
+    import torch
+    chunk = max(1, -(-steps // parts))
+    done = 0
+    t0 = time.time()
+    while done < steps:
+        k = min(chunk, steps - done)
+        sim.step(k)
+        torch.cuda.synchronize()
+        done += k
+        if done < steps:
+            log(f"{label}: {done}/{steps} steps ({time.time() - t0:.0f} s)")
+
 # paper Table 1 (drag coefficient of the sphere at channel resolution L)
 TABLE1 = {
     100: {128: 1.122, 256: 1.108, 384: 1.106, 512: 1.106, "ref": 1.08},
@@ -107,7 +123,7 @@ def sphere_drag(res=128, re_s=(100, 500, 1000, 2000), ftt=6.0, u_in=0.05, storag
                   solid=geo.solid, links=geo.links, obstacle_bc=1, avg_start=None, force_every=1,
                   perturb=(0, 0.01 * u_in))
         mode = sim.info()["mode"]
-        sim.step(steps)
+        _run_steps(sim, steps, log, f"sphere L={L} Re_s {re}")
         F, _ = sim.forces()
         mass = sim.mass()
         sim.close()
