@@ -78,6 +78,8 @@ def read_surrogate_result():
         keep["fno_train_samples_per_s"] = r["fno"].get("train_samples_per_s")
     if "mean_field_baseline" in r:
         keep["mean_field_held_out"] = r["mean_field_baseline"].get("held_out")
+    for proj, v in r.get("projection_variants", {}).items():
+        keep[f"fno_{proj}_projection_held_out"] = v.get("held_out")
     keep["source"] = "profiles/fno_surrogate_c4.json (python -m paper_2606_16765_amd.surrogate)"
     return keep
 
