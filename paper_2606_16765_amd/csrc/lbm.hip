@@ -81,7 +81,6 @@ __device__ __forceinline__ int64_t cell_index(const StepArgs& a, int x, int y, i
   return (int64_t)(z + 1) * a.zstride + (int64_t)(y + 1) * a.pitch + x;
 }
 
-// element access through a uniform slot base and a 32-bit element offset
 // general element access: population slot of the cell whose slot-0 index is idx
 template <typename S>
 __device__ __forceinline__ typename Storage<S>::T ld(const StepArgs& a, int slot, int64_t idx) {
@@ -101,26 +100,29 @@ struct CellCtx {
   uint32_t inlet;   // bit i: that source is the inlet
   uint32_t om;      // bit j: cell + c_j is obstacle
   int32_t row;      // boundary row or -1
-  int32_t off[3][3];// source offset per axis for c = -1, 0, +1 (source = cell - c)
+  int32_t off[2][3];// x and y source offset for c = -1, 0, +1 (source = cell - c)
+  int64_t offz[3];  // z source offset: a periodic wrap spans nz - 1 padded
+                    // planes, more elements than int32 holds on large grids
 };
 
-__device__ __forceinline__ int src_off(int i, const CellCtx& c) {
-  return c.off[0][cx(i) + 1] + c.off[1][cy(i) + 1] + c.off[2][cz(i) + 1];
+__device__ __forceinline__ int64_t src_off(int i, const CellCtx& c) {
+  return (int64_t)(c.off[0][cx(i) + 1] + c.off[1][cy(i) + 1]) + c.offz[cz(i) + 1];
 }
 
 __device__ __forceinline__ void make_ctx(const StepArgs& a, int x, int y, int z, uint8_t fl, CellCtx& c) {
   c.x = x; c.y = y; c.z = z;
   c.n = ((int64_t)z * a.ny + y) * a.nx + x;
   c.pc = cell_index(a, x, y, z);
-  const int rowp = a.pitch, plane = a.zstride;
+  const int rowp = a.pitch;
+  const int64_t plane = a.zstride;
   // x: source of c=+1 is x-1, of c=-1 is x+1 (x+1 = nx is the outlet ghost)
-  c.off[0][1] = 0; c.off[1][1] = 0; c.off[2][1] = 0;
+  c.off[0][1] = 0; c.off[1][1] = 0; c.offz[1] = 0;
   c.off[0][2] = (a.per[0] && x == 0) ? (a.nx - 1) : -1;
   c.off[0][0] = (a.per[0] && x == a.nx - 1) ? -(a.nx - 1) : 1;
   c.off[1][2] = (a.per[1] && y == 0) ? (a.ny - 1) * rowp : -rowp;
   c.off[1][0] = (a.per[1] && y == a.ny - 1) ? -(a.ny - 1) * rowp : rowp;
-  c.off[2][2] = (a.per[2] && z == 0) ? (a.nz - 1) * plane : -plane;
-  c.off[2][0] = (a.per[2] && z == a.nz - 1) ? -(a.nz - 1) * plane : plane;
+  c.offz[2] = (a.per[2] && z == 0) ? (a.nz - 1) * plane : -plane;
+  c.offz[0] = (a.per[2] && z == a.nz - 1) ? -(a.nz - 1) * plane : plane;
   uint32_t wall = 0;
   if (!a.per[1]) {
     if (y == 0) wall |= M_YP;

@@ -91,6 +91,34 @@ def test_periodic_sides_obstacle_channel_f64(mode):
     assert np.abs(fg - fo).max() < 1e-11 * np.abs(fo).max()
 
 
+def test_periodic_z_wrap_beyond_int32_elements():
+    """Periodic z on a grid whose wrap offset, nz - 1 padded planes, exceeds
+    2^31 elements (64 x 4 x 103584, FP64 storage, inlet and outlet in x,
+    periodic y and z).  The initial velocity repeats every 16 planes, so the
+    state stays 16-periodic in z and every 16-plane box must equal the
+    oracle on a 16-plane periodic domain, the boxes at both periodic faces
+    included; their cells pull across the wrap on odd steps."""
+    P = _gpu()
+    nx, ny, per = 64, 4, 16
+    plane = 27 * (nx + 64) * (ny + 2)
+    nz = per * ((1 << 31) // (plane * per) + 2)
+    assert (nz - 1) * plane >= (1 << 31)
+    small = (nx, ny, per)
+    u0s = perturbation(small, 21, 5e-3)
+    nu, steps = 0.01, 11
+    g = P.Lbm((nx, ny, nz), storage="f64", periodic=(0, 1, 1), u_in=0.05, nu=nu, mode="k17",
+              u0=np.tile(u0s, (1, nz // per, 1, 1)))
+    g.step(steps)
+    p = olbm.make_params(small, periodic=(0, 1, 1), nu=nu, u_in=0.05, mode=1)
+    o = olbm.Run(p, u0=u0s)
+    o.step(steps)
+    for z0 in (0, (nz // 2 // per) * per, nz - per):
+        err = f64_err(g.populations_box((0, 0, z0), small), o.fbar)
+        print("z0", z0, "err", err)
+        assert err < 1e-11, (z0, err)
+    g.close()
+
+
 @pytest.mark.parametrize("mode", ["plain", "k17"])
 @pytest.mark.parametrize("obstacle_bc", [0, 1])
 def test_obstacle_channel_f64(mode, obstacle_bc):
