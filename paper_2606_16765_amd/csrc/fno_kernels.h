@@ -608,13 +608,23 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
 // With STORE_A (training) the BF16 hidden activation is also stored to
 // aout [B][H][P], for the gradient of Q2.  ACT selects the hidden
 // activation: 0 GELU, 1 the SIREN sine sin(w0 h).
+// The sine runs on the hardware sine and cosine (argument in revolutions,
+// valid within +-256 revolutions) with the library functions beyond that.
+__device__ __forceinline__ float sin_w(float x) {
+  const float r = x * 0.15915494309189535f;
+  return fabsf(r) < 256.f ? __builtin_amdgcn_sinf(r) : sinf(x);
+}
+__device__ __forceinline__ float cos_w(float x) {
+  const float r = x * 0.15915494309189535f;
+  return fabsf(r) < 256.f ? __builtin_amdgcn_cosf(r) : cosf(x);
+}
 template <int ACT>
 __device__ __forceinline__ float proj_act(float h, float w0) {
-  return ACT == 1 ? sinf(w0 * h) : gelu(h);
+  return ACT == 1 ? sin_w(w0 * h) : gelu(h);
 }
 template <int ACT>
 __device__ __forceinline__ float proj_act_grad(float h, float w0) {
-  return ACT == 1 ? w0 * cosf(w0 * h) : gelu_grad(h);
+  return ACT == 1 ? w0 * cos_w(w0 * h) : gelu_grad(h);
 }
 template <int NT, int KS, bool STORE_A = false, int ACT = 0>
 __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ v, int W, int64_t P,
