@@ -17,6 +17,12 @@ feed-forward lifting; predicts mean flow fields from geometry and Re):
   y = Q2 act(Q1 v + q1) + q2                    projection width -> hidden -> cout
                       act = GELU, or for the SIREN projection of App. A.2
                       act(h) = sin(w0 h) (w0 = 30)
+Hybrid F/FNO (arch = "hybrid", App. A.2: the factorized FNO's layer
+structure with the unfactorized 3D spectral convolution of the FNO): each
+layer is a residual block around a pointwise feed-forward network,
+      s = R(W_l . T(v))                         the same spectral convolution
+      v = v + W2_l GELU(W1_l s + b1_l) + b2_l   width -> ff_hidden -> width
+with no bypass channel map and no activation on the residual stream.
 Loss: mean squared error over the cells of a mask (App. A.2, inner region),
 all samples and output channels.  Optimiser: Adam (beta 0.9, 0.999,
 eps 1e-8).  The projection is a GELU MLP by default; proj = "siren" gives
@@ -25,8 +31,10 @@ the paper's SIREN (sine activation with frequency w0).
 Parameter vector layout (shared with the GPU library's C ABI):
   lift W [width][cin], lift b [width];
   per layer: spectral W [2mx][2my][mz][width][width][2] (re, im; first
-  index j -> kx = j for j < mx else j - 2mx, likewise ky), pointwise W
-  [width][width] (out, in), bias [width];
+  index j -> kx = j for j < mx else j - 2mx, likewise ky), then for the
+  FNO the pointwise W [width][width] (out, in) and bias [width], for the
+  hybrid W1 [ff_hidden][width], b1 [ff_hidden], W2 [width][ff_hidden],
+  b2 [width];
   proj W1 [hidden][width], b1 [hidden], W2 [cout][hidden], b2 [cout].
 """
 from dataclasses import dataclass
@@ -51,12 +59,18 @@ class Shape:
     hidden: int = 128
     proj: str = "gelu"
     w0: float = 30.0
+    arch: str = "fno"
+    ff_hidden: int = 128
 
 
 def param_count(s: Shape) -> int:
     w = s.width
     n = w * s.cin + w
-    n += s.layers * ((2 * s.mx) * (2 * s.my) * s.mz * w * w * 2 + w * w + w)
+    spec = (2 * s.mx) * (2 * s.my) * s.mz * w * w * 2
+    if s.arch == "hybrid":
+        n += s.layers * (spec + 2 * s.ff_hidden * w + s.ff_hidden + w)
+    else:
+        n += s.layers * (spec + w * w + w)
     n += s.hidden * w + s.hidden + s.cout * s.hidden + s.cout
     return n
 
@@ -79,7 +93,11 @@ def unpack(theta, s: Shape):
         ws = take(2 * s.mx, 2 * s.my, s.mz, w, w, 2)
         # complex weights as [c_in][c_out][kx][ky][kz]
         W = (ws[..., 0] + 1j * ws[..., 1]).transpose(3, 4, 0, 1, 2)
-        p["layers"].append({"W": W, "Wp": take(w, w), "bp": take(w)})
+        if s.arch == "hybrid":
+            H = s.ff_hidden
+            p["layers"].append({"W": W, "W1": take(H, w), "b1": take(H), "W2": take(w, H), "b2": take(w)})
+        else:
+            p["layers"].append({"W": W, "Wp": take(w, w), "bp": take(w)})
     p["Q1"] = take(s.hidden, w)
     p["q1"] = take(s.hidden)
     p["Q2"] = take(s.cout, s.hidden)
@@ -93,7 +111,10 @@ def pack(p, s: Shape):
     for L in p["layers"]:
         W = L["W"].transpose(2, 3, 4, 0, 1)
         ws = np.stack([W.real, W.imag], -1)
-        parts += [ws.ravel(), L["Wp"].ravel(), L["bp"].ravel()]
+        if s.arch == "hybrid":
+            parts += [ws.ravel(), L["W1"].ravel(), L["b1"].ravel(), L["W2"].ravel(), L["b2"].ravel()]
+        else:
+            parts += [ws.ravel(), L["Wp"].ravel(), L["bp"].ravel()]
     parts += [p["Q1"].ravel(), p["q1"].ravel(), p["Q2"].ravel(), p["q2"].ravel()]
     return np.concatenate(parts)
 
@@ -187,8 +208,15 @@ def forward(theta, x, s: Shape, mats=None):
         cache["v"].append(v)
         V = forward_dft(v, mats)
         Y = np.einsum("bck...,cok...->bok...", V, L["W"])
-        h = inverse_dft(Y, mats, s) + pointwise(L["Wp"], v, L["bp"])
         cache.setdefault("V", []).append(V)
+        if s.arch == "hybrid":
+            sc = inverse_dft(Y, mats, s)
+            z = pointwise(L["W1"], sc, L["b1"])
+            cache.setdefault("s", []).append(sc)
+            cache.setdefault("z", []).append(z)
+            v = v + pointwise(L["W2"], gelu(z), L["b2"])
+            continue
+        h = inverse_dft(Y, mats, s) + pointwise(L["Wp"], v, L["bp"])
         cache.setdefault("h", []).append(h)
         v = gelu(h) if li < s.layers - 1 else h
     cache["vL"] = v
@@ -228,6 +256,21 @@ def backward(theta, cache, gy, s: Shape, mats=None):
     # Fourier layers in reverse
     for li in range(s.layers - 1, -1, -1):
         L = p["layers"][li]
+        if s.arch == "hybrid":
+            # v' = v + W2 GELU(z) + b2, z = W1 s + b1, s = R(W . T(v))
+            z, sc = cache["z"][li], cache["s"][li]
+            gL = {"W2": np.tensordot(gv, gelu(z), axes=(red, red)), "b2": gv.sum(axis=red)}
+            gz = pointwise(L["W2"].T, gv) * gelu_grad(z)
+            gL["W1"] = np.tensordot(gz, sc, axes=(red, red))
+            gL["b1"] = gz.sum(axis=red)
+            gs = pointwise(L["W1"].T, gz)
+            gY = adjoint_inverse_dft(gs, mats, s)
+            V = cache["V"][li]
+            gL["W"] = np.einsum("bck...,bok...->cok...", np.conj(V), gY)
+            gV = np.einsum("bok...,cok...->bck...", gY, np.conj(L["W"]))
+            gv = gv + adjoint_forward_dft(gV, mats)
+            g["layers"][li] = gL
+            continue
         h = cache["h"][li]
         gh = gv * gelu_grad(h) if li < s.layers - 1 else gv
         v = cache["v"][li]
@@ -264,7 +307,13 @@ def init_params(s: Shape, seed=0):
     p = {"P": rng.uniform(-1, 1, (w, s.cin)) / math.sqrt(s.cin), "p": np.zeros(w), "layers": []}
     for _ in range(s.layers):
         W = (rng.uniform(0, 1, (w, w, 2 * s.mx, 2 * s.my, s.mz)) + 1j * rng.uniform(0, 1, (w, w, 2 * s.mx, 2 * s.my, s.mz)))
-        p["layers"].append({"W": W / (w * w), "Wp": rng.uniform(-1, 1, (w, w)) / math.sqrt(w), "bp": np.zeros(w)})
+        if s.arch == "hybrid":
+            H = s.ff_hidden
+            p["layers"].append({"W": W / (w * w), "W1": rng.uniform(-1, 1, (H, w)) / math.sqrt(w), "b1": np.zeros(H),
+                                "W2": rng.uniform(-1, 1, (w, H)) / math.sqrt(H), "b2": np.zeros(w)})
+        else:
+            p["layers"].append({"W": W / (w * w), "Wp": rng.uniform(-1, 1, (w, w)) / math.sqrt(w),
+                                "bp": np.zeros(w)})
     if s.proj == "siren":  # Sitzmann et al.: first layer U(+-1/n), later U(+-sqrt(6/n)/w0)
         p["Q1"] = rng.uniform(-1, 1, (s.hidden, w)) / w
         p["Q2"] = rng.uniform(-1, 1, (s.cout, s.hidden)) * math.sqrt(6.0 / s.hidden) / s.w0

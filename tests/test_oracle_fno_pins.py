@@ -11,6 +11,8 @@ RNG = np.random.default_rng(42)
 SMALL = fno.Shape(nx=8, ny=8, nz=8, cin=2, cout=2, width=3, layers=2, mx=2, my=2, mz=2, hidden=5)
 SMALL_SIREN = fno.Shape(nx=8, ny=8, nz=8, cin=2, cout=2, width=3, layers=2, mx=2, my=2, mz=2, hidden=5,
                         proj="siren", w0=30.0)
+SMALL_HYBRID = fno.Shape(nx=8, ny=8, nz=8, cin=2, cout=2, width=3, layers=2, mx=2, my=2, mz=2, hidden=5,
+                         arch="hybrid", ff_hidden=4)
 
 
 def corner(Vfull, s):
@@ -121,7 +123,7 @@ def _loss(th, x, t, mask, s):
     return fno.masked_mse(y, t, mask)[0]
 
 
-@pytest.mark.parametrize("s", [SMALL, SMALL_SIREN], ids=["gelu", "siren"])
+@pytest.mark.parametrize("s", [SMALL, SMALL_SIREN, SMALL_HYBRID], ids=["gelu", "siren", "hybrid"])
 def test_backward_matches_finite_differences(s):
     th = fno.init_params(s, 1)
     x = RNG.standard_normal((2, s.cin, s.nx, s.ny, s.nz))
@@ -133,8 +135,16 @@ def test_backward_matches_finite_differences(s):
     g = fno.backward(th, c, gy, s)
     # every parameter group is sampled: lift, spectral, pointwise, projection
     nproj = s.hidden * s.width + s.hidden + s.cout * s.hidden + s.cout
-    idx = np.unique(np.concatenate([np.arange(0, 6), RNG.choice(th.size, 40, replace=False),
-                                    np.arange(th.size - nproj, th.size)]))
+    parts = [np.arange(0, 6), RNG.choice(th.size, 40, replace=False), np.arange(th.size - nproj, th.size)]
+    if s.arch == "hybrid":
+        # every feed-forward parameter of every layer (W1, b1, W2, b2 follow
+        # the layer's spectral weights)
+        nlift, nspec = s.width * s.cin + s.width, 4 * s.mx * s.my * s.mz * s.width * s.width * 2
+        nff = 2 * s.ff_hidden * s.width + s.ff_hidden + s.width
+        for l in range(s.layers):
+            o = nlift + l * (nspec + nff) + nspec
+            parts.append(np.arange(o, o + nff))
+    idx = np.unique(np.concatenate(parts))
     # central differences: truncation O(h^2), rounding O(eps L / h); the
     # bound leaves room for both and still fails on any wrong term (O(1))
     h = 1e-5
@@ -145,6 +155,62 @@ def test_backward_matches_finite_differences(s):
         fd = (_loss(th + e, x, t, mask, s) - _loss(th - e, x, t, mask, s)) / (2 * h)
         err.append(abs(g[i] - fd) / (abs(fd) + 1e-3 * np.abs(g).max()))
     assert max(err) < 5e-5, max(err)
+
+
+def _ffn(v, L):
+    """The hybrid's residual block without its spectral part, written out
+    per point: v + W2 GELU(W1 v + b1) + b2."""
+    z = np.einsum("hc,bc...->bh...", L["W1"], v) + L["b1"].reshape(1, -1, 1, 1, 1)
+    return v + np.einsum("ch,bh...->bc...", L["W2"], fno.gelu(z)) + L["b2"].reshape(1, -1, 1, 1, 1)
+
+
+def test_hybrid_with_identity_spectral_weights_is_a_pointwise_residual_block():
+    """Identity mixing on a lifted input made of retained modes reproduces
+    the field (s = v), so one hybrid layer equals the pointwise residual
+    feed-forward block, followed by the projection."""
+    s = fno.Shape(nx=16, ny=8, nz=8, cin=2, cout=2, width=3, layers=1, mx=3, my=2, mz=3, hidden=5,
+                  arch="hybrid", ff_hidden=6)
+    p = fno.unpack(fno.init_params(s, 4), s)
+    p["p"] = RNG.standard_normal(s.width)
+    L = p["layers"][0]
+    L["W"] = np.broadcast_to(np.eye(s.width)[:, :, None, None, None], L["W"].shape).astype(complex)
+    L["b1"], L["b2"] = RNG.standard_normal(s.ff_hidden), RNG.standard_normal(s.width)
+    x, y, z = np.meshgrid(np.arange(s.nx), np.arange(s.ny), np.arange(s.nz), indexing="ij")
+    xin = np.stack([np.cos(2 * np.pi * (2 * x / s.nx + y / s.ny + 2 * z / s.nz)),
+                    np.sin(2 * np.pi * (x / s.nx - z / s.nz))])[None]
+    out, _ = fno.forward(fno.pack(p, s), xin, s)
+    v0 = np.einsum("wc,bc...->bw...", p["P"], xin) + p["p"].reshape(1, -1, 1, 1, 1)
+    v1 = _ffn(v0, L)
+    h1 = np.einsum("hw,bw...->bh...", p["Q1"], v1) + p["q1"].reshape(1, -1, 1, 1, 1)
+    ref = np.einsum("oh,bh...->bo...", p["Q2"], fno.gelu(h1)) + p["q2"].reshape(1, -1, 1, 1, 1)
+    assert np.abs(out - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+def test_hybrid_with_zero_output_weights_adds_its_biases():
+    """With W2 = 0 every hybrid layer adds b2 whatever its spectral weights:
+    v_L = P x + p + sum_l b2_l."""
+    s = SMALL_HYBRID
+    p = fno.unpack(fno.init_params(s, 2), s)
+    shift = np.zeros(s.width)
+    for L in p["layers"]:
+        L["W2"] = np.zeros_like(L["W2"])
+        L["b2"] = RNG.standard_normal(s.width)
+        shift += L["b2"]
+    x = RNG.standard_normal((2, s.cin, s.nx, s.ny, s.nz))
+    out, c = fno.forward(fno.pack(p, s), x, s)
+    v = np.einsum("wc,bc...->bw...", p["P"], x) + (p["p"] + shift).reshape(1, -1, 1, 1, 1)
+    assert np.abs(c["vL"] - v).max() < 1e-12
+    h1 = np.einsum("hw,bw...->bh...", p["Q1"], v) + p["q1"].reshape(1, -1, 1, 1, 1)
+    ref = np.einsum("oh,bh...->bo...", p["Q2"], fno.gelu(h1)) + p["q2"].reshape(1, -1, 1, 1, 1)
+    assert np.abs(out - ref).max() < 1e-12
+
+
+def test_hybrid_parameter_count():
+    s = fno.Shape(arch="hybrid", ff_hidden=128)
+    th = fno.init_params(fno.Shape(nx=8, ny=8, nz=8, mx=2, my=2, mz=2, arch="hybrid", ff_hidden=8), 0)
+    assert th.size == fno.param_count(fno.Shape(nx=8, ny=8, nz=8, mx=2, my=2, mz=2, arch="hybrid", ff_hidden=8))
+    # width 32, 4 layers, 32x32x16 modes, feed-forward 32 -> 128 -> 32
+    assert fno.param_count(s) - 134217728 == 4 * (2 * 128 * 32 + 128 + 32) + 32 * 4 + 32 + 128 * 32 + 128 + 4 * 128 + 4
 
 
 def test_masked_mse_only_counts_mask_cells():
