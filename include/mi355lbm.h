@@ -209,6 +209,10 @@ const char* lbm_last_error(const lbm_sim* s); /* s may be NULL: global error */
  * truncated inverse DFT, plus a pointwise linear map and bias, GELU after
  * all but the last), projection width -> proj_hidden (GELU, or the sine of
  * a SIREN) -> cout.
+ * arch = 1 gives the hybrid F/FNO of App. A.2 instead: every layer is the
+ * residual block v + W2 GELU(W1 s + b1) + b2 around the same spectral
+ * convolution s of v (width -> ff_hidden -> width), with no pointwise map
+ * beside it and no activation on the residual stream.
  * Contractions run as BF16 MFMA with FP32 accumulation.                      */
 typedef struct fno_net fno_net;
 
@@ -227,13 +231,20 @@ typedef struct {
                                with Sitzmann's initialisation; the sine needs
                                proj_hidden <= 128, width <= 64, cout <= 16   */
   float proj_w0;            /* SIREN frequency (30); ignored for GELU         */
+  int32_t arch;             /* 0 FNO, 1 hybrid F/FNO; the hybrid needs
+                               width <= 32, nz in [16, 256], 2*mz <= 32 and
+                               ff_hidden <= 128                               */
+  int32_t ff_hidden;        /* hybrid feed-forward width (128), % 16 == 0;
+                               ignored for the FNO                            */
 } fno_params;
 
 /* Parameter vector layout (FP32, fno_param_count entries), in this order:
  * lift W [width][cin], lift b [width]; per layer l: spectral weights
- * [2*mx][2*my][mz][width_in][width_out][2] (re, im), pointwise W
- * [width][width] (out, in), bias [width]; proj W1 [proj_hidden][width],
- * b1 [proj_hidden], W2 [cout][proj_hidden], b2 [cout].                      */
+ * [2*mx][2*my][mz][width_in][width_out][2] (re, im), then for the FNO the
+ * pointwise W [width][width] (out, in) and bias [width], for the hybrid
+ * W1 [ff_hidden][width], b1 [ff_hidden], W2 [width][ff_hidden], b2 [width];
+ * proj W1 [proj_hidden][width], b1 [proj_hidden], W2 [cout][proj_hidden],
+ * b2 [cout].                                                                 */
 int64_t fno_param_count(const fno_params* p);
 
 /* Create with parameters initialised from seed (uniform fan-in scaling);

@@ -30,7 +30,8 @@ class LbmParams(ctypes.Structure):
 class FnoParams(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
                 ("nx", "ny", "nz", "cin", "cout", "width", "layers", "mx", "my", "mz", "proj_hidden", "max_batch",
-                 "proj_act")] + [("proj_w0", ctypes.c_float)]
+                 "proj_act")] + [("proj_w0", ctypes.c_float), ("arch", ctypes.c_int32),
+                                 ("ff_hidden", ctypes.c_int32)]
 
 
 def _sig(L):

@@ -66,6 +66,10 @@ struct fno_net {
   // parameter offsets
   int64_t off_P = 0, off_p = 0, off_Q1 = 0, off_q1 = 0, off_Q2 = 0, off_q2 = 0;
   std::vector<int64_t> off_W, off_Wp, off_bp;
+  // hybrid F/FNO: feed-forward width and per-layer W1, b1, W2, b2 offsets
+  bool hybrid = false;
+  int Hf = 0;
+  std::vector<int64_t> off_W1, off_b1, off_W2, off_b2;
   float *theta = nullptr, *grad = nullptr, *am = nullptr, *av = nullptr;
   int adam_t = 0;
   uint16_t* wspec = nullptr;  // BF16 copy of all parameters (spectral blocks used)
@@ -78,12 +82,21 @@ struct fno_net {
   GtMat Pq1, Pq2;
   float* pq1b = nullptr;
   bool fused_proj = false;
+  // hybrid feed-forward operands per layer (the fused projection's layout):
+  // W1 [Hfp][32], W2 [32][Hfp], W2^T [Hfp][32] BF16, b1 [Hfp] FP32, zero padded
+  std::vector<GtMat> Pf1, Pf2, Gf2t;
+  std::vector<float*> fb1;
   // c2r along z, channel map, bias and activation in one kernel
   bool fused_layer_end = false;
   // activations and work buffers
   std::vector<uint16_t*> v;  // L + 1, BF16
   std::vector<float*> h;     // L, FP32 pre-activations
   std::vector<uint16_t*> Vh;  // L, BF16 modes (mode-minor)
+  // hybrid: spectral convolution s and feed-forward hidden activation per
+  // layer (BF16), the hidden gradient and the gradient of s
+  std::vector<uint16_t*> S, Aff;
+  uint16_t* ffa = nullptr;
+  float* gs = nullptr;
   uint16_t *A1 = nullptr, *A2 = nullptr, *R3 = nullptr, *R2 = nullptr;  // BF16 DFT intermediates
   uint16_t* Yh = nullptr;  // BF16 modes (mode-minor)
   float *h1 = nullptr, *y = nullptr, *gy = nullptr, *ga = nullptr, *gv = nullptr, *gvn = nullptr;
@@ -343,6 +356,46 @@ static void fused_projection_bwd(fno_net* n, int B, const uint16_t* v, const flo
   }
 }
 
+// Hybrid F/FNO feed-forward block of layer l, forward:
+//   vout = resid + W2 GELU(W1 s + b1) + b2 (BF16), aout (training) the BF16
+//   hidden activation
+template <int NT>
+static void launch_ffn_t(fno_net* n, int l, int B, const uint16_t* s, const uint16_t* resid, uint16_t* vout,
+                         uint16_t* aout) {
+  const unsigned blocks = (unsigned)((int64_t)B * n->P / 256);
+  const float* b2 = n->theta + n->off_b2[l];
+  if (aout)
+    hipLaunchKernelGGL((proj_kernel<NT, 1, true, 0, true>), dim3(blocks), dim3(256), 0, n->st, s, n->W, n->P,
+                       n->Pf1[l].d, n->fb1[l], n->Pf2[l].d, b2, n->W, nullptr, n->Hf, aout, 0.f, resid, vout);
+  else
+    hipLaunchKernelGGL((proj_kernel<NT, 1, false, 0, true>), dim3(blocks), dim3(256), 0, n->st, s, n->W, n->P,
+                       n->Pf1[l].d, n->fb1[l], n->Pf2[l].d, b2, n->W, nullptr, 0, nullptr, 0.f, resid, vout);
+}
+static void launch_ffn(fno_net* n, int l, int B, const uint16_t* s, const uint16_t* resid, uint16_t* vout,
+                       uint16_t* aout) {
+  switch (n->Pf1[l].np / 16) {
+    case 2: launch_ffn_t<2>(n, l, B, s, resid, vout, aout); break;
+    case 4: launch_ffn_t<4>(n, l, B, s, resid, vout, aout); break;
+    case 6: launch_ffn_t<6>(n, l, B, s, resid, vout, aout); break;
+    default: launch_ffn_t<8>(n, l, B, s, resid, vout, aout); break;
+  }
+}
+// backward: ga (BF16) = GELU'(W1 s + b1) W2^T gv, gsv (FP32) = W1^T ga
+template <int NT>
+static void launch_ffn_bwd_t(fno_net* n, int l, int B, const uint16_t* s, const float* gv, uint16_t* ga, float* gsv) {
+  const unsigned blocks = (unsigned)((int64_t)B * n->P / 256);
+  hipLaunchKernelGGL((proj_bwd_kernel<NT, 1, 0>), dim3(blocks), dim3(256), 0, n->st, s, n->W, n->P, n->Pf1[l].d,
+                     n->fb1[l], n->Gf2t[l].d, n->Gf2t[l].kp, gv, n->W, n->Hf, ga, gsv, 0.f);
+}
+static void launch_ffn_bwd(fno_net* n, int l, int B, const uint16_t* s, const float* gv, uint16_t* ga, float* gsv) {
+  switch (n->Pf1[l].np / 16) {
+    case 2: launch_ffn_bwd_t<2>(n, l, B, s, gv, ga, gsv); break;
+    case 4: launch_ffn_bwd_t<4>(n, l, B, s, gv, ga, gsv); break;
+    case 6: launch_ffn_bwd_t<6>(n, l, B, s, gv, ga, gsv); break;
+    default: launch_ffn_bwd_t<8>(n, l, B, s, gv, ga, gsv); break;
+  }
+}
+
 // truncated forward 3D DFT: v [B][W][P] (BF16 or FP32) -> modes [m][B][W][2]
 // (z_done: A1 already holds the z stage, written by the previous layer end)
 static int forward_dft(fno_net* n, int B, const void* v, bool v_bf16, const GtMat& Gz, uint16_t* modes,
@@ -499,6 +552,15 @@ static int refresh(fno_net* n, bool bf16_done = false) {
   };
   mk(n->Glift, n->off_P, n->W, n->p.cin, 0);
   for (int l = 0; l < n->L; ++l) {
+    if (n->hybrid) {
+      mk(n->Pf1[l], n->off_W1[l], n->Hf, n->W, 0);
+      mk(n->Pf2[l], n->off_W2[l], n->W, n->Hf, 0);
+      mk(n->Gf2t[l], n->off_W2[l], n->W, n->Hf, 1);
+      hipError_t ce = hipMemcpyAsync(n->fb1[l], n->theta + n->off_b1[l], (size_t)n->Hf * 4, hipMemcpyDeviceToDevice,
+                                     n->st);
+      if (ce != hipSuccess) return ffail(n, LBM_EDEVICE, hipGetErrorString(ce));
+      continue;
+    }
     mk(n->Gwp[l], n->off_Wp[l], n->W, n->W, 0);
     mk(n->Gwpt[l], n->off_Wp[l], n->W, n->W, 1);
   }
@@ -527,9 +589,10 @@ static hipError_t alloc_gt(fno_net* n, GtMat& m, int K, int N) {
 
 extern "C" int64_t fno_param_count(const fno_params* p) {
   if (!p) return -1;
-  const int64_t w = p->width, M = (int64_t)(2 * p->mx) * (2 * p->my) * p->mz;
-  return w * p->cin + w + (int64_t)p->layers * (M * w * w * 2 + w * w + w) + (int64_t)p->proj_hidden * w +
-         p->proj_hidden + (int64_t)p->cout * p->proj_hidden + p->cout;
+  const int64_t w = p->width, M = (int64_t)(2 * p->mx) * (2 * p->my) * p->mz, hf = p->ff_hidden;
+  const int64_t layer = M * w * w * 2 + (p->arch == 1 ? 2 * hf * w + hf + w : w * w + w);
+  return w * p->cin + w + (int64_t)p->layers * layer + (int64_t)p->proj_hidden * w + p->proj_hidden +
+         (int64_t)p->cout * p->proj_hidden + p->cout;
 }
 
 static void free_net(fno_net* n) {
@@ -558,11 +621,19 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
     return ffail(nullptr, LBM_EINVAL, "the sine projection needs proj_w0 > 0, proj_hidden <= 128 and cout <= 16");
   if (2 * p.my * p.mz < (p.width <= 32 ? MixCfg<32>::MQ : MixCfg<64>::MQ))
     return ffail(nullptr, LBM_EINVAL, "2 my mz must be at least 32 (16 for width above 32)");
+  if (p.arch != 0 && p.arch != 1) return ffail(nullptr, LBM_EINVAL, "arch must be 0 (FNO) or 1 (hybrid F/FNO)");
+  if (p.arch == 1 && (p.width > 32 || p.nz < 16 || p.nz > 256 || 2 * p.mz > 32 || P % 256 || p.ff_hidden <= 0 ||
+                      p.ff_hidden % 16 || round_up(p.ff_hidden, 32) > 128))
+    return ffail(nullptr, LBM_EINVAL,
+                 "the hybrid F/FNO needs width <= 32, nz in [16, 256], 2 mz <= 32 and ff_hidden a multiple of 16 "
+                 "up to 128");
   fno_net* n = new (std::nothrow) fno_net();
   if (!n) return ffail(nullptr, LBM_ENOMEM, "host allocation failed");
   n->p = p;
   n->st = (hipStream_t)hip_stream;
   n->W = p.width; n->X = p.nx; n->Y = p.ny; n->Z = p.nz;
+  n->hybrid = p.arch == 1;
+  n->Hf = n->hybrid ? p.ff_hidden : 0;
   n->MX = 2 * p.mx; n->MY = 2 * p.my; n->MZ = p.mz; n->L = p.layers; n->H = p.proj_hidden;
   n->P = P;
   n->M = (int64_t)n->MX * n->MY * n->MZ;
@@ -573,8 +644,15 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
   n->off_p = o; o += n->W;
   for (int l = 0; l < n->L; ++l) {
     n->off_W.push_back(o); o += n->M * n->W * n->W * 2;
-    n->off_Wp.push_back(o); o += (int64_t)n->W * n->W;
-    n->off_bp.push_back(o); o += n->W;
+    if (n->hybrid) {
+      n->off_W1.push_back(o); o += (int64_t)n->Hf * n->W;
+      n->off_b1.push_back(o); o += n->Hf;
+      n->off_W2.push_back(o); o += (int64_t)n->W * n->Hf;
+      n->off_b2.push_back(o); o += n->W;
+    } else {
+      n->off_Wp.push_back(o); o += (int64_t)n->W * n->W;
+      n->off_bp.push_back(o); o += n->W;
+    }
   }
   n->off_Q1 = o; o += (int64_t)n->H * n->W;
   n->off_q1 = o; o += n->H;
@@ -603,7 +681,15 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
   n->Vh.assign(n->L, nullptr);
   for (int l = 0; ok && l <= n->L; ++l) ok = A((void**)&n->v[l], (size_t)B * W * P * 2);
   for (int l = 0; ok && l < n->L; ++l)
-    ok = A((void**)&n->h[l], (size_t)B * W * P * 4) && A((void**)&n->Vh[l], (size_t)n->M * B * W * 2 * 2);
+    ok = (n->hybrid || A((void**)&n->h[l], (size_t)B * W * P * 4)) &&
+         A((void**)&n->Vh[l], (size_t)n->M * B * W * 2 * 2);
+  if (n->hybrid) {
+    n->S.assign(n->L, nullptr);
+    n->Aff.assign(n->L, nullptr);
+    for (int l = 0; ok && l < n->L; ++l)
+      ok = A((void**)&n->S[l], (size_t)B * W * P * 2) && A((void**)&n->Aff[l], (size_t)B * n->Hf * P * 2);
+    ok = ok && A((void**)&n->ffa, (size_t)B * n->Hf * P * 2) && A((void**)&n->gs, (size_t)B * W * P * 4);
+  }
   const int64_t rows = (int64_t)B * W * n->X * n->Y;
   ok = ok && A((void**)&n->A1, (size_t)rows * 2 * n->MZ * 2) &&
        A((void**)&n->A2, (size_t)B * W * n->X * 2 * n->MY * n->MZ * 2) &&
@@ -613,15 +699,18 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
        A((void**)&n->a, (size_t)B * n->H * P * 2) && A((void**)&n->y, (size_t)B * p.cout * P * 4) &&
        A((void**)&n->gy, (size_t)B * p.cout * P * 4) && (hid32 == 0 || A((void**)&n->ga, hid32)) &&
        A((void**)&n->gv, (size_t)B * W * P * 4) && A((void**)&n->gvn, (size_t)B * W * P * 4);
-  n->part_elems = std::max<int64_t>((int64_t)B * P / 2048 * std::max<int64_t>(n->H, W) * std::max<int64_t>(W, p.cout) +
-                                        (int64_t)B * P / 2048 * n->H * std::max<int64_t>(n->H, W),
-                                    (int64_t)B * P / 8192 * std::max<int64_t>(n->H, W));
-  n->part_elems = std::max<int64_t>(n->part_elems, (int64_t)B * P / 2048 * n->H * W);
+  // Gram partials: the widest hidden layer is the projection's or the
+  // hybrid feed-forward's
+  const int64_t Hm = std::max<int64_t>(n->H, n->Hf);
+  n->part_elems = std::max<int64_t>((int64_t)B * P / 2048 * std::max<int64_t>(Hm, W) * std::max<int64_t>(W, p.cout) +
+                                        (int64_t)B * P / 2048 * Hm * std::max<int64_t>(Hm, W),
+                                    (int64_t)B * P / 8192 * std::max<int64_t>(Hm, W));
+  n->part_elems = std::max<int64_t>(n->part_elems, (int64_t)B * P / 2048 * Hm * W);
   n->part_elems = std::max<int64_t>(n->part_elems, (int64_t)B * P / 2048 * p.cout * n->H);
   n->lpart_n = ((int64_t)B * p.cout * P + 255) / 256;
-  n->part2_elems = 64 * std::max<int64_t>(std::max<int64_t>((int64_t)n->H * W, (int64_t)p.cout * n->H),
+  n->part2_elems = 64 * std::max<int64_t>(std::max<int64_t>(Hm * W, (int64_t)p.cout * n->H),
                                            std::max<int64_t>(W * W, W * (int64_t)p.cin));
-  n->partc_elems = (int64_t)B * P / 2048 * std::max<int64_t>(std::max<int64_t>(n->H, W), p.cout);
+  n->partc_elems = (int64_t)B * P / 2048 * std::max<int64_t>(std::max<int64_t>(Hm, W), p.cout);
   ok = ok && A((void**)&n->part, (size_t)n->part_elems * 4) && A((void**)&n->lpart, (size_t)n->lpart_n * 8) &&
        A((void**)&n->lscal, 32) &&
        A((void**)&n->part2, (size_t)n->part2_elems * 4) && A((void**)&n->partc, (size_t)n->partc_elems * 4);
@@ -631,9 +720,28 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
   n->Gwp.resize(n->L);
   n->Gwpt.resize(n->L);
   if ((e = alloc_gt(n, n->Glift, p.cin, n->W)) != hipSuccess) return bail(LBM_ENOMEM, "operand allocation");
-  for (int l = 0; l < n->L; ++l)
+  for (int l = 0; l < n->L && !n->hybrid; ++l)
     if (alloc_gt(n, n->Gwp[l], n->W, n->W) != hipSuccess || alloc_gt(n, n->Gwpt[l], n->W, n->W) != hipSuccess)
       return bail(LBM_ENOMEM, "operand allocation");
+  if (n->hybrid) {
+    const int Hfp = (int)round_up(n->Hf, 32);
+    n->Pf1.resize(n->L);
+    n->Pf2.resize(n->L);
+    n->Gf2t.resize(n->L);
+    n->fb1.assign(n->L, nullptr);
+    for (int l = 0; l < n->L; ++l) {
+      GtMat& f1 = n->Pf1[l];
+      GtMat& f2 = n->Pf2[l];
+      f1.K = n->W; f1.N = n->Hf; f1.kp = 32; f1.np = Hfp;
+      f2.K = n->Hf; f2.N = n->W; f2.kp = Hfp; f2.np = 32;
+      if (falloc(n, (void**)&f1.d, (size_t)Hfp * 32 * 2) != hipSuccess ||
+          falloc(n, (void**)&f2.d, (size_t)32 * Hfp * 2) != hipSuccess ||
+          alloc_gt(n, n->Gf2t[l], n->W, n->Hf) != hipSuccess ||
+          falloc(n, (void**)&n->fb1[l], (size_t)Hfp * 4) != hipSuccess ||
+          hipMemset(n->fb1[l], 0, (size_t)Hfp * 4) != hipSuccess)
+        return bail(LBM_ENOMEM, "operand allocation");
+    }
+  }
   if (alloc_gt(n, n->Gq1, n->W, n->H) != hipSuccess || alloc_gt(n, n->Gq1t, n->H, n->W) != hipSuccess ||
       alloc_gt(n, n->Gq2, n->H, p.cout) != hipSuccess || alloc_gt(n, n->Gq2t, p.cout, n->H) != hipSuccess)
     return bail(LBM_ENOMEM, "operand allocation");
@@ -695,7 +803,13 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
     for (int64_t i = 0; i < (int64_t)W * p.cin; ++i) th[n->off_P + i] = (float)uni(-1, 1) / std::sqrt((float)p.cin);
     for (int l = 0; l < n->L; ++l) {
       for (int64_t i = 0; i < n->M * W * W * 2; ++i) th[n->off_W[l] + i] = (float)(uni(0, 1) / (double)(W * W));
-      for (int64_t i = 0; i < W * W; ++i) th[n->off_Wp[l] + i] = (float)uni(-1, 1) / std::sqrt((float)W);
+      if (n->hybrid) {
+        for (int64_t i = 0; i < (int64_t)n->Hf * W; ++i) th[n->off_W1[l] + i] = (float)uni(-1, 1) / std::sqrt((float)W);
+        for (int64_t i = 0; i < (int64_t)W * n->Hf; ++i)
+          th[n->off_W2[l] + i] = (float)uni(-1, 1) / std::sqrt((float)n->Hf);
+      } else {
+        for (int64_t i = 0; i < W * W; ++i) th[n->off_Wp[l] + i] = (float)uni(-1, 1) / std::sqrt((float)W);
+      }
     }
     // SIREN (Sitzmann et al.): first layer U(+-1/n), later layers U(+-sqrt(6/n)/w0)
     const bool siren = p.proj_act == 1;
@@ -786,6 +900,21 @@ static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout, bool 
     if ((rc = forward_dft(n, B, n->v[l], true, n->F1, n->Vh[l], z_done))) return rc;
     z_done = false;
     mix(n, 0, B, n->Vh[l], n->wspec + n->off_W[l], n->Yh);
+    if (n->hybrid) {
+      // s = R(W T v) alone (no channel map, bias or activation), then
+      // v' = v + W2 GELU(W1 s + b1) + b2; the next z stage runs on its own
+      if ((rc = inverse_dft(n, B, n->Yh, n->I1, nullptr, false))) return rc;
+      uint16_t* sl = n->S[training ? l : 0];
+      LayerEndArgs e{};
+      e.v = n->v[l]; e.r2 = n->R2; e.gwp = nullptr; e.gi1 = n->I1.d; e.gi1_kp = n->I1.kp;
+      e.bias = nullptr; e.h = nullptr; e.act = sl;
+      e.P = n->P; e.W = (int)W; e.Win = 0; e.Z = n->Z; e.K2 = 2 * n->MZ; e.act_gelu = 0;
+      const dim3 grid((unsigned)((int64_t)B * n->P / PW_J));
+      if (W <= 16) hipLaunchKernelGGL((layer_end_kernel<1, uint16_t>), grid, dim3(256), 0, n->st, e);
+      else hipLaunchKernelGGL((layer_end_kernel<2, uint16_t>), grid, dim3(256), 0, n->st, e);
+      launch_ffn(n, l, B, sl, n->v[l], n->v[l + 1], training ? n->Aff[l] : nullptr);
+      continue;
+    }
     // h = R(W T v) + Wp v + bp; v' = GELU(h) (identity after the last layer)
     if (n->fused_layer_end) {
       if ((rc = inverse_dft(n, B, n->Yh, n->I1, nullptr, false))) return rc;
@@ -870,7 +999,31 @@ extern "C" int fno_loss_grad(fno_net* n, const uint16_t* x, const float* target,
   // Fourier layers in reverse
   // at layer l, gv holds dL/dh[l]: the last layer has no activation, and the
   // GELU' of the layers below is applied where their gradient is completed
-  for (int l = n->L - 1; l >= 0; --l) {
+  // (hybrid: gv holds dL/dv[l + 1], the gradient of the residual stream)
+  for (int l = n->L - 1; l >= 0 && n->hybrid; --l) {
+    // feed-forward block: dL/dz = GELU'(z) W2^T gv (BF16), dL/ds = W1^T dL/dz
+    launch_ffn_bwd(n, l, B, n->S[l], n->gv, n->ffa, n->gs);
+    if ((rc = gram(n, n->gv, (int)W, n->Aff[l], n->Hf, B, n->grad + n->off_W2[l], false, n->grad + n->off_b2[l])))
+      return rc;
+    if ((rc = gram(n, (const uint16_t*)n->ffa, n->Hf, n->S[l], (int)W, B, n->grad + n->off_W1[l], false,
+                   n->grad + n->off_b1[l])))
+      return rc;
+    // spectral convolution: mode gradient, weight gradient, adjoint path
+    if ((rc = forward_dft(n, B, n->gs, false, n->F1a, n->Yh))) return rc;
+    mix_grad(n, B, n->Vh[l], n->Yh, n->grad + n->off_W[l]);
+    mix(n, 1, B, n->Yh, n->wspec + n->off_W[l], n->Vg);
+    if ((rc = inverse_dft(n, B, n->Vg, n->I1a, nullptr, false))) return rc;
+    // dL/dv[l] = dL/dv[l + 1] (residual) + adjoint c2r of the y-stage output
+    LayerEndArgs e{};
+    e.v = n->gv; e.r2 = n->R2; e.gwp = nullptr; e.gi1 = n->I1a.d; e.gi1_kp = n->I1a.kp;
+    e.bias = nullptr; e.h = n->gvn; e.act = nullptr; e.gmul = nullptr; e.resid = n->gv;
+    e.P = n->P; e.W = (int)W; e.Win = 0; e.Z = n->Z; e.K2 = 2 * n->MZ; e.act_gelu = 0;
+    const dim3 grid((unsigned)((int64_t)B * n->P / PW_J));
+    if (W <= 16) hipLaunchKernelGGL((layer_end_kernel<1, float>), grid, dim3(256), 0, n->st, e);
+    else hipLaunchKernelGGL((layer_end_kernel<2, float>), grid, dim3(256), 0, n->st, e);
+    std::swap(n->gv, n->gvn);
+  }
+  for (int l = n->L - 1; l >= 0 && !n->hybrid; --l) {
     if ((rc = gram(n, n->gv, (int)W, n->v[l], (int)W, B, n->grad + n->off_Wp[l], false, n->grad + n->off_bp[l])))
       return rc;
     // gradient on the modes: (c_kz/N) T(gh)

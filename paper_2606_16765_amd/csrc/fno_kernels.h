@@ -402,6 +402,9 @@ __global__ __launch_bounds__(256) void pw_kernel(PwArgs a) {
 // and only the FP32 output h.  The lift uses it with cin input channels,
 // the lift weights as the channel map and no c2r term (r2 null), so that
 // layer 0's z stage is fused as well.
+// The hybrid F/FNO layer has no channel map (Win = 0 skips it): forward,
+// the kernel yields the spectral convolution s alone; backward, it adds the
+// FP32 residual gradient resid to the adjoint c2r term.
 struct LayerEndArgs {
   const void* v;        // [B][W][P] layer input, BF16 or FP32 (InT)
   const uint16_t* r2;   // [B W X Y][2 mz] y-stage output (BF16)
@@ -419,6 +422,7 @@ struct LayerEndArgs {
   const uint16_t* gz;   // next layer's z-DFT operand [2 mz padded][kp] BF16 (rows k, columns z)
   int32_t gz_kp;
   uint16_t* a1;         // next layer's z-stage output [B W X Y][2 mz] BF16, or null
+  const float* resid;   // [B][W][P] FP32 added before gmul, or null
 };
 
 // eight consecutive values as packed BF16 (RNE)
@@ -484,15 +488,17 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
   for (int h = 0; h < NT; ++h)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[h][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // channel map
+  // channel map (uniform branch: absent in the hybrid layer)
+  if (a.Win > 0) {
 #pragma unroll
-  for (int h = 0; h < NT; ++h) {
-    const bf16x8 av = *(const bf16x8*)(a.gwp + (h * 16 + (lane & 15)) * 32 + 8 * g);
+    for (int h = 0; h < NT; ++h) {
+      const bf16x8 av = *(const bf16x8*)(a.gwp + (h * 16 + (lane & 15)) * 32 + 8 * g);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int pt = wave * 64 + c * 16 + (lane & 15);
-      const bf16x8 bv = *(const bf16x8*)(tile + tile_row(pt) * PW_TS + tile_col(8 * g, pt));
-      acc[h][c] = mfma16(av, bv, acc[h][c]);
+      for (int c = 0; c < 4; ++c) {
+        const int pt = wave * 64 + c * 16 + (lane & 15);
+        const bf16x8 bv = *(const bf16x8*)(tile + tile_row(pt) * PW_TS + tile_col(8 * g, pt));
+        acc[h][c] = mfma16(av, bv, acc[h][c]);
+      }
     }
   }
   // c2r along z, with its own accumulators, added to the channel map's in
@@ -540,6 +546,10 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
     if (a.bias) {
       const float bb = a.bias[n];
       v.x += bb; v.y += bb; v.z += bb; v.w += bb;
+    }
+    if (a.resid) {
+      const float4 rr = *(const float4*)(a.resid + b * a.W * a.P + p0 + off);
+      v.x += rr.x; v.y += rr.y; v.z += rr.z; v.w += rr.w;
     }
     if (gm) {
       const float4 hh = *(const float4*)(gm + off);
@@ -608,6 +618,10 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
 // With STORE_A (training) the BF16 hidden activation is also stored to
 // aout [B][H][P], for the gradient of Q2.  ACT selects the hidden
 // activation: 0 GELU, 1 the SIREN sine sin(w0 h).
+// RES selects the residual feed-forward form of the hybrid F/FNO layer:
+//   vout[b][o][p] = bf16(resid[b][o][p] + q2[o] + sum_h Q2[o][h] act(...))
+// with cout = W <= 32 outputs (two 16-row output tiles, Q2p [32][16 NT]),
+// resid and vout BF16 [B][W][P].
 // The sine runs on the hardware sine and cosine (argument in revolutions,
 // valid within +-256 revolutions) with the library functions beyond that.
 __device__ __forceinline__ float sin_w(float x) {
@@ -626,16 +640,18 @@ template <int ACT>
 __device__ __forceinline__ float proj_act_grad(float h, float w0) {
   return ACT == 1 ? w0 * cos_w(w0 * h) : gelu_grad(h);
 }
-template <int NT, int KS, bool STORE_A = false, int ACT = 0>
+template <int NT, int KS, bool STORE_A = false, int ACT = 0, bool RES = false>
 __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ v, int W, int64_t P,
                                                    const uint16_t* __restrict__ Q1p, const float* __restrict__ q1p,
                                                    const uint16_t* __restrict__ Q2p, const float* __restrict__ q2,
                                                    int cout, float* __restrict__ y, int H = 0,
-                                                   uint16_t* __restrict__ aout = nullptr, float w0 = 0.f) {
-  constexpr int WP = 32 * KS, VS = WP + 8, HP = 16 * NT;
+                                                   uint16_t* __restrict__ aout = nullptr, float w0 = 0.f,
+                                                   const uint16_t* __restrict__ resid = nullptr,
+                                                   uint16_t* __restrict__ vout = nullptr) {
+  constexpr int WP = 32 * KS, VS = WP + 8, HP = 16 * NT, OT = RES ? 2 : 1;
   __shared__ __attribute__((aligned(16))) uint16_t vt[256 * VS];
   __shared__ __attribute__((aligned(16))) uint16_t q1s[HP * WP];
-  __shared__ __attribute__((aligned(16))) uint16_t q2s[16 * HP];
+  __shared__ __attribute__((aligned(16))) uint16_t q2s[16 * OT * HP];
   // per wave: the BF16 hidden tile [HP][16 points] of one column tile
   __shared__ __attribute__((aligned(16))) uint16_t hs[STORE_A ? 4 * HP * 16 : 8];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4;
@@ -643,7 +659,7 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
   const int64_t b = j0 / P, p0 = j0 % P;
   // operands into LDS
   for (int e = t * 8; e < HP * WP; e += 256 * 8) *(uint4*)(q1s + e) = *(const uint4*)(Q1p + e);
-  for (int e = t * 8; e < 16 * HP; e += 256 * 8) *(uint4*)(q2s + e) = *(const uint4*)(Q2p + e);
+  for (int e = t * 8; e < 16 * OT * HP; e += 256 * 8) *(uint4*)(q2s + e) = *(const uint4*)(Q2p + e);
   // v tile, transposed to [point][channel]
   for (int idx = t; idx < WP * 32; idx += 256) {
     const int c = idx >> 5, g8 = (idx & 31) * 8;
@@ -653,15 +669,17 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
     for (int i = 0; i < 8; ++i) vt[tile_row(g8 + i) * VS + tile_col(c, g8 + i)] = val[i];
   }
   __syncthreads();
-  // second-stage A operand (Q2 rows o = lane % 16), gathered once
-  bf16x8 a2[NT / 2];
+  // second-stage A operand (Q2 rows o = 16 ot + lane % 16), gathered once
+  bf16x8 a2[OT][NT / 2];
 #pragma unroll
-  for (int s = 0; s < NT / 2; ++s)
+  for (int ot = 0; ot < OT; ++ot)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int h = 32 * s + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
-      a2[s][j] = __builtin_bit_cast(__bf16, q2s[(lane & 15) * HP + h]);
-    }
+    for (int s = 0; s < NT / 2; ++s)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int h = 32 * s + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
+        a2[ot][s][j] = __builtin_bit_cast(__bf16, q2s[(ot * 16 + (lane & 15)) * HP + h]);
+      }
   for (int ct = 0; ct < 4; ++ct) {
     const int pt = wave * 64 + ct * 16 + (lane & 15);
     f32x4 acc[NT];
@@ -677,7 +695,9 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
       }
     }
     const int64_t p = p0 + wave * 64 + ct * 16 + (lane & 15);
-    f32x4 out = {0.f, 0.f, 0.f, 0.f};
+    f32x4 out[OT];
+#pragma unroll
+    for (int ot = 0; ot < OT; ++ot) out[ot] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < NT / 2; ++s) {
       bf16x8 bv;
@@ -689,7 +709,8 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
         bv[j] = __builtin_bit_cast(__bf16, hb);
         if (STORE_A) hs[wave * HP * 16 + (nt * 16 + 4 * g + r) * 16 + (lane & 15)] = hb;
       }
-      out = mfma16(a2[s], bv, out);
+#pragma unroll
+      for (int ot = 0; ot < OT; ++ot) out[ot] = mfma16(a2[ot][s], bv, out[ot]);
     }
     if (STORE_A) {
       __syncthreads();  // the wave's hidden tile is complete
@@ -701,10 +722,23 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
               *(const uint4*)(hs + wave * HP * 16 + hr * 16 + 8 * half);
       }
     }
+    if (RES) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int o = 4 * g + r;
-      if (o < cout) y[(b * cout + o) * P + p] = out[r] + q2[o];
+      for (int ot = 0; ot < OT; ++ot)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int o = ot * 16 + 4 * g + r;
+          if (o < cout) {
+            const int64_t off = (b * cout + o) * P + p;
+            vout[off] = f2bf(out[ot][r] + q2[o] + bf2f(resid[off]));
+          }
+        }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = 4 * g + r;
+        if (o < cout) y[(b * cout + o) * P + p] = out[0][r] + q2[o];
+      }
     }
   }
 }

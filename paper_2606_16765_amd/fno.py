@@ -23,10 +23,12 @@ def _stream():
 
 class Fno:
     """3D FNO: lifting, Fourier layers with truncated corner modes, GELU MLP
-    projection; trained with masked MSE and Adam."""
+    projection; trained with masked MSE and Adam.  arch="hybrid" gives the
+    hybrid F/FNO: residual layers v + W2 GELU(W1 s + b1) + b2 around the same
+    spectral convolution s (feed-forward width ff_hidden)."""
 
     def __init__(self, nx=128, ny=64, nz=64, cin=4, cout=4, width=32, layers=4, mx=16, my=16, mz=16, hidden=128,
-                 max_batch=16, seed=0, proj="gelu", w0=30.0):
+                 max_batch=16, seed=0, proj="gelu", w0=30.0, arch="fno", ff_hidden=128):
         L = load()
         p = FnoParams()
         p.nx, p.ny, p.nz, p.cin, p.cout = nx, ny, nz, cin, cout
@@ -34,6 +36,8 @@ class Fno:
         p.proj_hidden, p.max_batch = hidden, max_batch
         p.proj_act = {"gelu": 0, "siren": 1}[proj]
         p.proj_w0 = w0
+        p.arch = {"fno": 0, "hybrid": 1}[arch]
+        p.ff_hidden = ff_hidden
         self.p = p
         self.shape = (nx, ny, nz)
         self._L = L
@@ -169,11 +173,11 @@ def forward_cost(batch=16, nx=128, ny=64, nz=64, cin=4, cout=4, width=32, layers
     return {"flops": int(flops), "min_bytes": int(min_bytes)}
 
 
-def bench_inference(batch=16, reps=10, proj="gelu"):
+def bench_inference(batch=16, reps=10, proj="gelu", arch="fno"):
     """Forward time per batch at the full surrogate shape (128x64x64, width
     32, 4 layers, 32x32x16 retained modes, hidden 128), random input."""
     import torch
-    net = Fno(max_batch=batch, proj=proj)
+    net = Fno(max_batch=batch, proj=proj, arch=arch)
     g = torch.Generator(device="cuda").manual_seed(0)
     x = torch.randn((batch, 4, 128, 64, 64), device="cuda", generator=g).to(torch.bfloat16)
     y = torch.empty((batch, 4, 128, 64, 64), device="cuda")
@@ -190,12 +194,12 @@ def bench_inference(batch=16, reps=10, proj="gelu"):
     return {"batch": batch, "ms_per_batch": round(ms, 3), "samples_per_s": round(batch / ms * 1e3, 1)}
 
 
-def bench_train(batch=16, reps=5):
+def bench_train(batch=16, reps=5, arch="fno"):
     """One training step (masked-MSE forward, backward, Adam) per batch at the
     full surrogate shape, random input and target; the paper reports its
     training rate in samples per second."""
     import torch
-    net = Fno(max_batch=batch)
+    net = Fno(max_batch=batch, arch=arch)
     g = torch.Generator(device="cuda").manual_seed(0)
     x = torch.randn((batch, 4, 128, 64, 64), device="cuda", generator=g).to(torch.bfloat16)
     t = torch.rand((batch, 4, 128, 64, 64), device="cuda", generator=g)

@@ -71,6 +71,30 @@ def test_invalid_parameters_rejected_without_device_work():
     fp.proj_act, fp.proj_w0 = 1, 0.0
     assert L.fno_create(ctypes.byref(fp), 0, None, ctypes.byref(h)) == 1  # sine needs w0 > 0
     assert b"sine projection" in L.fno_last_error(None)
+    fp.proj_act, fp.proj_w0 = 0, 30.0
+    fp.arch = 2
+    assert L.fno_create(ctypes.byref(fp), 0, None, ctypes.byref(h)) == 1
+    assert b"arch must be" in L.fno_last_error(None)
+    fp.arch, fp.ff_hidden, fp.width = 1, 32, 48
+    assert L.fno_create(ctypes.byref(fp), 0, None, ctypes.byref(h)) == 1  # hybrid width above 32
+    assert b"hybrid" in L.fno_last_error(None)
+    fp.width, fp.ff_hidden = 16, 160
+    assert L.fno_create(ctypes.byref(fp), 0, None, ctypes.byref(h)) == 1  # feed-forward wider than 128
+    assert b"hybrid" in L.fno_last_error(None)
+
+
+def test_hybrid_parameter_count_matches_the_oracle_layout():
+    """fno_param_count (host only) for both architectures against the
+    oracle's parameter layout."""
+    from oracle import fno as ofno
+    from paper_2606_16765_amd._lib import FnoParams, load
+    L = load()
+    for arch, code in (("fno", 0), ("hybrid", 1)):
+        fp = FnoParams()
+        fp.nx, fp.ny, fp.nz, fp.cin, fp.cout, fp.width, fp.layers = 128, 64, 64, 4, 4, 32, 4
+        fp.mx, fp.my, fp.mz, fp.proj_hidden, fp.max_batch = 16, 16, 16, 128, 1
+        fp.arch, fp.ff_hidden = code, 96
+        assert L.fno_param_count(ctypes.byref(fp)) == ofno.param_count(ofno.Shape(arch=arch, ff_hidden=96))
 
 
 def test_binding_raises_on_error():

@@ -21,7 +21,8 @@ SMALL = dict(nx=32, ny=16, nz=16, cin=4, cout=4, width=16, layers=2, mx=4, my=4,
 def _shape(d):
     return ofno.Shape(nx=d["nx"], ny=d["ny"], nz=d["nz"], cin=d["cin"], cout=d["cout"], width=d["width"],
                       layers=d["layers"], mx=d["mx"], my=d["my"], mz=d["mz"], hidden=d["hidden"],
-                      proj=d.get("proj", "gelu"), w0=d.get("w0", 30.0))
+                      proj=d.get("proj", "gelu"), w0=d.get("w0", 30.0), arch=d.get("arch", "fno"),
+                      ff_hidden=d.get("ff_hidden", 128))
 
 
 def _setup(cfg, B, seed=1):
@@ -53,9 +54,12 @@ def test_forward_matches_oracle_small():
 WIDE = [dict(SMALL, width=48, layers=1, hidden=32), dict(SMALL, width=64, layers=2, hidden=48)]
 # the paper's SIREN projection (sine hidden activation, w0 = 30)
 SIREN = dict(SMALL, proj="siren", w0=30.0)
+# the hybrid F/FNO: residual feed-forward layers (two hidden widths, the
+# second the production instance of the feed-forward kernels)
+HYBRID = [dict(SMALL, arch="hybrid", ff_hidden=32), dict(SMALL, width=32, hidden=32, arch="hybrid", ff_hidden=128)]
 
 
-@pytest.mark.parametrize("cfg", WIDE + [SIREN], ids=["w48", "w64", "siren"])
+@pytest.mark.parametrize("cfg", WIDE + [SIREN] + HYBRID, ids=["w48", "w64", "siren", "hybrid16", "hybrid32"])
 def test_forward_wide_matches_oracle(cfg):
     net, x, _ = _setup(cfg, 2)
     y = net.forward(x).cpu().numpy()
@@ -66,7 +70,8 @@ def test_forward_wide_matches_oracle(cfg):
     assert err < 3e-2
 
 
-@pytest.mark.parametrize("cfg", [SMALL] + WIDE + [SIREN], ids=["w16", "w48", "w64", "siren"])
+@pytest.mark.parametrize("cfg", [SMALL] + WIDE + [SIREN] + HYBRID,
+                         ids=["w16", "w48", "w64", "siren", "hybrid16", "hybrid32"])
 def test_gradients_match_oracle_small(cfg):
     import torch
     s = _shape(cfg)
@@ -84,15 +89,16 @@ def test_gradients_match_oracle_small(cfg):
     groups = [("P", gu["P"], gou["P"]), ("p", gu["p"], gou["p"]), ("Q1", gu["Q1"], gou["Q1"]),
               ("q1", gu["q1"], gou["q1"]), ("Q2", gu["Q2"], gou["Q2"]), ("q2", gu["q2"], gou["q2"])]
     for l in range(s.layers):
-        for k in ("W", "Wp", "bp"):
+        for k in (("W", "W1", "b1", "W2", "b2") if s.arch == "hybrid" else ("W", "Wp", "bp")):
             groups.append((f"{k}{l}", gu["layers"][l][k], gou["layers"][l][k]))
     worst = max((rel_l2(a, b), name) for name, a, b in groups)
     print("gradient worst group", worst)
     assert worst[0] < 5e-2, worst
 
 
-def test_forward_full_size_matches_oracle():
-    full = dict(nx=128, ny=64, nz=64, cin=4, cout=4, width=32, layers=4, mx=16, my=16, mz=16, hidden=128)
+@pytest.mark.parametrize("arch", ["fno", "hybrid"])
+def test_forward_full_size_matches_oracle(arch):
+    full = dict(nx=128, ny=64, nz=64, cin=4, cout=4, width=32, layers=4, mx=16, my=16, mz=16, hidden=128, arch=arch)
     net, x, _ = _setup(full, 1, seed=3)
     y = net.forward(x).cpu().numpy()
     th = net.get_params().astype(np.float64)
