@@ -231,6 +231,9 @@ def fno_leg():
     out = pfno.bench_inference(batch=16, reps=20)
     out["train"] = pfno.bench_train(batch=16)
     out["siren_projection"] = pfno.bench_inference(batch=16, reps=20, proj="siren")
+    # the hybrid F/FNO (residual feed-forward layers, width 32 -> 128 -> 32)
+    out["hybrid"] = pfno.bench_inference(batch=16, reps=20, arch="hybrid")
+    out["hybrid"]["train"] = pfno.bench_train(batch=16, arch="hybrid")
     cost = pfno.forward_cost(batch=16)
     s = out["ms_per_batch"] / 1e3
     out["roofline"] = {

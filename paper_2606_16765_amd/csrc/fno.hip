@@ -384,7 +384,7 @@ static void launch_ffn(fno_net* n, int l, int B, const uint16_t* s, const uint16
 template <int NT>
 static void launch_ffn_bwd_t(fno_net* n, int l, int B, const uint16_t* s, const float* gv, uint16_t* ga, float* gsv) {
   const unsigned blocks = (unsigned)((int64_t)B * n->P / 256);
-  hipLaunchKernelGGL((proj_bwd_kernel<NT, 1, 0>), dim3(blocks), dim3(256), 0, n->st, s, n->W, n->P, n->Pf1[l].d,
+  hipLaunchKernelGGL((proj_bwd_kernel<NT, 1, 0, true>), dim3(blocks), dim3(256), 0, n->st, s, n->W, n->P, n->Pf1[l].d,
                      n->fb1[l], n->Gf2t[l].d, n->Gf2t[l].kp, gv, n->W, n->Hf, ga, gsv, 0.f);
 }
 static void launch_ffn_bwd(fno_net* n, int l, int B, const uint16_t* s, const float* gv, uint16_t* ga, float* gsv) {

@@ -654,9 +654,23 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
   __shared__ __attribute__((aligned(16))) uint16_t q2s[16 * OT * HP];
   // per wave: the BF16 hidden tile [HP][16 points] of one column tile
   __shared__ __attribute__((aligned(16))) uint16_t hs[STORE_A ? 4 * HP * 16 : 8];
+  // RES: per wave the FP32 output tile [32][16 points] (row pitch 17), two
+  // buffers alternating between column tiles
+  __shared__ __attribute__((aligned(16))) float stg[RES ? 2 * 4 * 32 * 17 : 1];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4;
   const int64_t j0 = (int64_t)blockIdx.x * 256;
   const int64_t b = j0 / P, p0 = j0 % P;
+  // RES: in the epilogue lane (c, half) = (lane / 2, lane % 2) completes 8
+  // consecutive points of channel c; its residual values for every column
+  // tile are loaded here, before anything waits, 16 bytes per tile
+  const int rc = lane >> 1, rh = lane & 1;
+  uint4 rres[RES ? 4 : 1];
+  if (RES) {
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+      rres[ct] = rc < cout ? *(const uint4*)(resid + (b * cout + rc) * P + p0 + wave * 64 + ct * 16 + 8 * rh)
+                           : uint4{0u, 0u, 0u, 0u};
+  }
   // operands into LDS
   for (int e = t * 8; e < HP * WP; e += 256 * 8) *(uint4*)(q1s + e) = *(const uint4*)(Q1p + e);
   for (int e = t * 8; e < 16 * OT * HP; e += 256 * 8) *(uint4*)(q2s + e) = *(const uint4*)(Q2p + e);
@@ -680,6 +694,8 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
         const int h = 32 * s + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
         a2[ot][s][j] = __builtin_bit_cast(__bf16, q2s[(ot * 16 + (lane & 15)) * HP + h]);
       }
+  // (unrolled in the residual form, whose prefetched values are indexed by ct)
+#pragma unroll(RES ? 4 : 1)
   for (int ct = 0; ct < 4; ++ct) {
     const int pt = wave * 64 + ct * 16 + (lane & 15);
     f32x4 acc[NT];
@@ -723,16 +739,26 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
       }
     }
     if (RES) {
+      float* sw = stg + ((ct & 1) * 4 + wave) * 32 * 17;
 #pragma unroll
       for (int ot = 0; ot < OT; ++ot)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int o = ot * 16 + 4 * g + r;
-          if (o < cout) {
-            const int64_t off = (b * cout + o) * P + p;
-            vout[off] = f2bf(out[ot][r] + q2[o] + bf2f(resid[off]));
-          }
+          sw[o * 17 + (lane & 15)] = out[ot][r] + (o < cout ? q2[o] : 0.f);
         }
+      __syncthreads();  // the wave's output tile is complete (the other buffer is free again)
+      if (rc < cout) {
+        const uint32_t u[4] = {rres[ct].x, rres[ct].y, rres[ct].z, rres[ct].w};
+        uint32_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float lo = sw[rc * 17 + 8 * rh + 2 * i] + __uint_as_float(u[i] << 16);
+          const float hi = sw[rc * 17 + 8 * rh + 2 * i + 1] + __uint_as_float(u[i] & 0xffff0000u);
+          w[i] = f2bf2(lo, hi);
+        }
+        *(uint4*)(vout + (b * cout + rc) * P + p0 + wave * 64 + ct * 16 + 8 * rh) = uint4{w[0], w[1], w[2], w[3]};
+      }
     } else {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -753,7 +779,9 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
 // BF16, zero padded; the Q1^T operand is gathered from Q1p with the hidden
 // rows permuted as the forward's second stage, so that ga feeds it straight
 // from the accumulator registers.  Block and wave layout as proj_kernel.
-template <int NT, int KS, int ACT = 0>
+// PF (the hybrid's feed-forward, cout = 32) loads the next column tile's gy
+// while the current one computes.
+template <int NT, int KS, int ACT = 0, bool PF = false>
 __global__ __launch_bounds__(256) void proj_bwd_kernel(const uint16_t* __restrict__ v, int W, int64_t P,
                                                        const uint16_t* __restrict__ Q1p, const float* __restrict__ q1p,
                                                        const uint16_t* __restrict__ Q2t, int kp2,
@@ -794,6 +822,14 @@ __global__ __launch_bounds__(256) void proj_bwd_kernel(const uint16_t* __restric
   }
   __syncthreads();
   uint16_t* hw = hs + wave * HP * 16;
+  float gnx[PF ? 8 : 1];
+  if (PF) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int o = 8 * g + j;
+      gnx[j] = o < cout ? gy[(b * cout + o) * P + p0 + wave * 64 + l16] : 0.f;
+    }
+  }
 #pragma unroll 1
   for (int ct = 0; ct < 4; ++ct) {
     const int pt = wave * 64 + ct * 16 + l16;
@@ -803,10 +839,25 @@ __global__ __launch_bounds__(256) void proj_bwd_kernel(const uint16_t* __restric
     for (int ks = 0; ks < KS; ++ks) vb[ks] = *(const bf16x8*)(vt + tile_row(pt) * VS + tile_col(ks * 32 + 8 * g, pt));
     // gy operand: column = this point, k = o (zero beyond cout)
     bf16x8 gb;
+    if (PF) {
+      float gc[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int o = 8 * g + j;
-      gb[j] = __builtin_bit_cast(__bf16, o < cout ? f2bf(gy[(b * cout + o) * P + p]) : (uint16_t)0);
+      for (int j = 0; j < 8; ++j) gc[j] = gnx[j];
+      if (ct < 3) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int o = 8 * g + j;
+          gnx[j] = o < cout ? gy[(b * cout + o) * P + p + 16] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) gb[j] = __builtin_bit_cast(__bf16, f2bf(gc[j]));
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int o = 8 * g + j;
+        gb[j] = __builtin_bit_cast(__bf16, o < cout ? f2bf(gy[(b * cout + o) * P + p]) : (uint16_t)0);
+      }
     }
     f32x4 go[2 * KS];
 #pragma unroll

@@ -49,6 +49,9 @@ class Config:
     proj: str = "gelu"          # projection hidden activation: "gelu" or "siren" (sine, w0)
     w0: float = 30.0
     also_proj: tuple = ()       # further projections trained and evaluated on the same data
+    arch: str = "fno"           # "fno" or "hybrid" (hybrid F/FNO: residual feed-forward layers)
+    ff_hidden: int = 128        # hybrid feed-forward width
+    also_arch: tuple = ()       # further architectures trained and evaluated on the same data
     seed: int = 0
     curve_sims: int = 4
     curve_steps: tuple = (1000, 2000, 5000, 10000)
@@ -297,7 +300,7 @@ def run(cfg, out_path=None):
     mask_d = torch.from_numpy(mask).cuda()
     mx, my, mz = cfg.modes
     net = Fno(nx=X, ny=Y, nz=Z, width=cfg.width, layers=cfg.layers, mx=mx, my=my, mz=mz, hidden=cfg.hidden,
-              max_batch=cfg.batch, seed=cfg.seed, proj=cfg.proj, w0=cfg.w0)
+              max_batch=cfg.batch, seed=cfg.seed, proj=cfg.proj, w0=cfg.w0, arch=cfg.arch, ff_hidden=cfg.ff_hidden)
     tinfo = train(cfg, net, xtr, ytr, len(tr) - len(tr) % cfg.batch if len(tr) >= cfg.batch else len(tr), mask_d)
     log(f"trained: {tinfo['train_s']:.1f} s, {tinfo['train_samples_per_s']:.1f} samples/s")
     _dump(out_path, dict(partial="trained", sims=recs, train=tinfo))
@@ -318,17 +321,23 @@ def run(cfg, out_path=None):
     fwd_ms = sum(t for t, _ in times) / sum(b for _, b in times)
     full = [t / b for t, b in times if b == cfg.batch]
     log(f"held-out rel L2 inner: FNO {res_fno['rel_l2_inner']:.4f} vs mean field {res_mean['rel_l2_inner']:.4f}")
-    variants = {}
-    for proj in cfg.also_proj:
+    variants, arch_variants = {}, {}
+    specs = [("proj", v, dict(proj=v, arch=cfg.arch)) for v in cfg.also_proj]
+    specs += [("arch", v, dict(proj=cfg.proj, arch=v)) for v in cfg.also_arch]
+    for kind, name, kw in specs:
         # the same data, scaling, seed and schedule with another projection
+        # or architecture
         vnet = Fno(nx=X, ny=Y, nz=Z, width=cfg.width, layers=cfg.layers, mx=mx, my=my, mz=mz, hidden=cfg.hidden,
-                   max_batch=cfg.batch, seed=cfg.seed, proj=proj, w0=cfg.w0)
+                   max_batch=cfg.batch, seed=cfg.seed, w0=cfg.w0, ff_hidden=cfg.ff_hidden, **kw)
         vinfo = train(cfg, vnet, xtr, ytr, len(tr) - len(tr) % cfg.batch if len(tr) >= cfg.batch else len(tr), mask_d)
-        vpred, _ = predict(cfg, vnet, xs, te, lo, hi)
+        vpred, vtimes = predict(cfg, vnet, xs, te, lo, hi)
         vnet.close()
-        variants[proj] = dict(held_out=metrics(vpred, true, mask), held_out_scaled=metrics(sc(vpred), sc(true), mask),
-                              train_samples_per_s=vinfo["train_samples_per_s"], loss_history=vinfo["loss_history"])
-        log(f"projection {proj}: held-out rel L2 inner {variants[proj]['held_out']['rel_l2_inner']:.4f}")
+        row = dict(held_out=metrics(vpred, true, mask), held_out_scaled=metrics(sc(vpred), sc(true), mask),
+                   train_samples_per_s=vinfo["train_samples_per_s"], loss_history=vinfo["loss_history"],
+                   forward_ms_per_sample=sum(t for t, _ in vtimes) / sum(b for _, b in vtimes))
+        (variants if kind == "proj" else arch_variants)[name] = row
+        log(f"{'projection' if kind == 'proj' else 'architecture'} {name}: held-out rel L2 inner "
+            f"{row['held_out']['rel_l2_inner']:.4f}, {row['train_samples_per_s']:.1f} training samples/s")
     # gain test (ii) and time-to-field: shorter LBM runs of held-out obstacles
     curve = []
     held_seeds = [r["seed"] for r in recs[n_train_sims:] if r["stable"]][:cfg.curve_sims]
@@ -359,6 +368,7 @@ def run(cfg, out_path=None):
                  forward_ms_per_batch=float(np.mean(full)) * cfg.batch if full else None, **tinfo),
         mean_field_baseline=dict(held_out=res_mean, held_out_scaled=res_mean_scaled),
         projection_variants=variants,
+        architecture_variants=arch_variants,
         gain=dict(rel_l2_inner_ratio_mean_over_fno=res_mean["rel_l2_inner"] / res_fno["rel_l2_inner"],
                   rel_l2_whole_ratio_mean_over_fno=res_mean["rel_l2_whole"] / res_fno["rel_l2_whole"]),
         time_to_field=dict(
@@ -392,6 +402,10 @@ def main(argv=None):
     ap.add_argument("--w0", type=float, default=30.0)
     ap.add_argument("--also-proj", choices=["gelu", "siren"], nargs="*", default=[],
                     help="also train and evaluate networks with these projections on the same data")
+    ap.add_argument("--arch", choices=["fno", "hybrid"], default="fno")
+    ap.add_argument("--ff-hidden", type=int, default=128)
+    ap.add_argument("--also-arch", choices=["fno", "hybrid"], nargs="*", default=[],
+                    help="also train and evaluate these architectures on the same data")
     ap.add_argument("--curve-sims", type=int, default=4)
     ap.add_argument("--curve-steps", type=int, nargs="*", default=[1000, 2000, 5000, 10000])
     ap.add_argument("--log-every", type=int, default=1)
@@ -399,7 +413,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     cfg = Config(shape=tuple(a.shape), sims=a.sims, held_out=a.held_out, steps=a.steps, epochs=a.epochs,
                  batch=a.batch, lr=a.lr, width=a.width, modes=tuple(a.modes), hidden=a.hidden, layers=a.layers,
-                 proj=a.proj, w0=a.w0, also_proj=tuple(a.also_proj),
+                 proj=a.proj, w0=a.w0, also_proj=tuple(a.also_proj), arch=a.arch, ff_hidden=a.ff_hidden,
+                 also_arch=tuple(a.also_arch),
                  curve_sims=a.curve_sims, curve_steps=tuple(a.curve_steps), log_every=a.log_every)
     if a.out:
         os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)

@@ -53,10 +53,13 @@ def test_small_pipeline_end_to_end():
     from paper_2606_16765_amd import surrogate
     cfg = surrogate.Config(shape=(64, 32, 32), sims=6, held_out=2, steps=200, epochs=3, batch=4, width=16,
                            modes=(4, 4, 4), hidden=16, curve_sims=1, curve_steps=(50, 100), lr=3e-3,
-                           also_proj=("siren",))
+                           also_proj=("siren",), also_arch=("hybrid",), ff_hidden=32)
     res = surrogate.run(cfg)
     v = res["projection_variants"]["siren"]
     assert np.isfinite(v["held_out"]["rel_l2_inner"]) and len(v["loss_history"]) == 3
+    h = res["architecture_variants"]["hybrid"]
+    assert np.isfinite(h["held_out"]["rel_l2_inner"]) and len(h["loss_history"]) == 3
+    assert h["forward_ms_per_sample"] > 0
     print({k: res[k] for k in ("gain", "time_to_field")})
     assert res["config"]["n_train"] == 16 and res["config"]["n_held_out"] == 8
     for k in ("rel_l2_inner", "rel_l2_whole", "mse_inner"):
