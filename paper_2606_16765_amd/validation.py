@@ -157,7 +157,7 @@ def cylinder_strouhal(scale=0.5, steps=40000, re_d=3900.0, u_in=0.05, storage="f
     t0 = time.time()
     sim = Lbm(shape, storage=storage, u_in=u_in, nu=nu_from_re(u_in, D, re_d), mode="auto", solid=geo.solid,
               links=geo.links, obstacle_bc=1, avg_start=None, force_every=1, perturb=(0, 0.01 * u_in))
-    sim.step(steps)
+    _run_steps(sim, steps, log, f"cylinder {shape}")
     F, _ = sim.forces()
     sim.close()
     half = F[len(F) // 2:]
