@@ -80,6 +80,9 @@ def read_surrogate_result():
         keep["mean_field_held_out"] = r["mean_field_baseline"].get("held_out")
     for proj, v in r.get("projection_variants", {}).items():
         keep[f"fno_{proj}_projection_held_out"] = v.get("held_out")
+    for arch, v in r.get("architecture_variants", {}).items():
+        keep[f"{arch}_held_out"] = v.get("held_out")
+        keep[f"{arch}_train_samples_per_s"] = v.get("train_samples_per_s")
     keep["source"] = "profiles/fno_surrogate_c4.json (python -m paper_2606_16765_amd.surrogate)"
     return keep
 
@@ -89,7 +92,7 @@ def read_validation_result():
     number from the committed validation runs (profiles/validation_*.json);
     None when absent."""
     out = {}
-    for name in ("validation_sphere_periodic", "validation_sphere_walls"):
+    for name in ("validation_sphere_periodic", "validation_sphere_walls", "validation_sphere_periodic_l384"):
         path = os.path.join(ROOT, "profiles", name + ".json")
         if not os.path.exists(path):
             continue
@@ -101,7 +104,7 @@ def read_validation_result():
             for row in blk["rows"]:
                 rows.append({"L": blk["resolution"], "re_s": row["re_s"], "cd": round(row["cd"], 4),
                              "cd_paper": row["cd_paper"]})
-        out[key] = rows
+        out.setdefault(key, []).extend(rows)
         if "cylinder" in r:
             out["cylinder_strouhal"] = round(r["cylinder"]["strouhal"], 4)
     if not out:
