@@ -92,7 +92,8 @@ def read_validation_result():
     number from the committed validation runs (profiles/validation_*.json);
     None when absent."""
     out = {}
-    for name in ("validation_sphere_periodic", "validation_sphere_walls", "validation_sphere_periodic_l384"):
+    for name in ("validation_sphere_periodic", "validation_sphere_walls", "validation_sphere_periodic_l384",
+                 "validation_c2_cylinder"):
         path = os.path.join(ROOT, "profiles", name + ".json")
         if not os.path.exists(path):
             continue
@@ -106,7 +107,9 @@ def read_validation_result():
                              "cd_paper": row["cd_paper"]})
         out.setdefault(key, []).extend(rows)
         if "cylinder" in r:
-            out["cylinder_strouhal"] = round(r["cylinder"]["strouhal"], 4)
+            cy = r["cylinder"]
+            out.setdefault("cylinder", []).append({"shape": cy["shape"], "steps": cy["steps"],
+                                                   "strouhal": round(cy["strouhal"], 4), "cd": round(cy["cd"], 4)})
     if not out:
         return None
     out["source"] = "profiles/validation_*.json (python -m paper_2606_16765_amd.validation)"
@@ -380,7 +383,8 @@ def main():
         line["physics"] = {"cd_mean_second_half": round(res["cd"], 4), "cl_rms_second_half": round(res["cl_rms"], 4),
                            "strouhal": None,
                            "strouhal_note": "one shedding period is about 6000 steps at this size; not "
-                                            "resolvable within the timed steps"}
+                                            "resolvable within the timed steps (the 66,000-step run of this "
+                                            "workload is under validation.cylinder)"}
     if not args.no_c1:
         line["c1_running_mean"] = c1_leg()
         log(f"c1 with running mean: {line['c1_running_mean']}")
