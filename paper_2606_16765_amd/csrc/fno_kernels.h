@@ -104,6 +104,17 @@ template <> struct Vec8<float> {
   }
 };
 
+// Makes this wave's earlier LDS stores visible to its later LDS loads from
+// other lanes of the same wave.  A wave's LDS operations complete in issue
+// order, so no block barrier is needed for a tile that only this wave
+// writes and reads; the wavefront-scope fences keep the compiler from
+// moving LDS accesses across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
@@ -729,7 +740,7 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
       for (int ot = 0; ot < OT; ++ot) out[ot] = mfma16(a2[ot][s], bv, out[ot]);
     }
     if (STORE_A) {
-      __syncthreads();  // the wave's hidden tile is complete
+      wave_lds_sync();  // the wave's hidden tile is complete
       // rows h of 16 points, two 16-byte halves each
       for (int e = lane; e < HP * 2; e += 64) {
         const int hr = e >> 1, half = e & 1;
@@ -747,7 +758,7 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
           const int o = ot * 16 + 4 * g + r;
           sw[o * 17 + (lane & 15)] = out[ot][r] + (o < cout ? q2[o] : 0.f);
         }
-      __syncthreads();  // the wave's output tile is complete (the other buffer is free again)
+      wave_lds_sync();  // the wave's output tile is complete
       if (rc < cout) {
         const uint32_t u[4] = {rres[ct].x, rres[ct].y, rres[ct].z, rres[ct].w};
         uint32_t w[4];
@@ -895,7 +906,7 @@ __global__ __launch_bounds__(256) void proj_bwd_kernel(const uint16_t* __restric
         const int c = ct2 * 16 + 4 * g + r;
         if (c < W) gv[(b * W + c) * P + p] = go[ct2][r];
       }
-    __syncthreads();  // the wave's gradient tile is complete
+    wave_lds_sync();  // the wave's gradient tile is complete
     // rows h of 16 points, two 16-byte halves each
     for (int e = lane; e < HP * 2; e += 64) {
       const int hr = e >> 1, half = e & 1;
