@@ -660,14 +660,22 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
                                                    const uint16_t* __restrict__ resid = nullptr,
                                                    uint16_t* __restrict__ vout = nullptr) {
   constexpr int WP = 32 * KS, VS = WP + 8, HP = 16 * NT, OT = RES ? 2 : 1;
+  // Q2 rows padded by 8: the gather of the second-stage operand reads one
+  // column of 16 rows at a time, which with unpadded rows of 64 words would
+  // all fall in one LDS bank
+  constexpr int Q2S = HP + 8;
+  // RES: per wave the FP32 output tile [32][16 points] (row pitch 20, so the
+  // four lane groups of a store hit disjoint banks); it reuses the Q2 rows,
+  // which are dead once the operand is gathered
+  constexpr int SP = 20;
+  constexpr int Q2_BYTES = 16 * OT * Q2S * 2, STG_BYTES = RES ? 4 * 32 * SP * 4 : 0;
   __shared__ __attribute__((aligned(16))) uint16_t vt[256 * VS];
   __shared__ __attribute__((aligned(16))) uint16_t q1s[HP * WP];
-  __shared__ __attribute__((aligned(16))) uint16_t q2s[16 * OT * HP];
+  __shared__ __attribute__((aligned(16))) unsigned char q2buf[Q2_BYTES > STG_BYTES ? Q2_BYTES : STG_BYTES];
+  uint16_t* q2s = (uint16_t*)q2buf;
+  float* stg = (float*)q2buf;
   // per wave: the BF16 hidden tile [HP][16 points] of one column tile
   __shared__ __attribute__((aligned(16))) uint16_t hs[STORE_A ? 4 * HP * 16 : 8];
-  // RES: per wave the FP32 output tile [32][16 points] (row pitch 17), two
-  // buffers alternating between column tiles
-  __shared__ __attribute__((aligned(16))) float stg[RES ? 2 * 4 * 32 * 17 : 1];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4;
   const int64_t j0 = (int64_t)blockIdx.x * 256;
   const int64_t b = j0 / P, p0 = j0 % P;
@@ -684,7 +692,7 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
   }
   // operands into LDS
   for (int e = t * 8; e < HP * WP; e += 256 * 8) *(uint4*)(q1s + e) = *(const uint4*)(Q1p + e);
-  for (int e = t * 8; e < 16 * OT * HP; e += 256 * 8) *(uint4*)(q2s + e) = *(const uint4*)(Q2p + e);
+  for (int e = t * 8; e < 16 * OT * HP; e += 256 * 8) *(uint4*)(q2s + (e / HP) * Q2S + e % HP) = *(const uint4*)(Q2p + e);
   // v tile, transposed to [point][channel]
   for (int idx = t; idx < WP * 32; idx += 256) {
     const int c = idx >> 5, g8 = (idx & 31) * 8;
@@ -703,8 +711,9 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int h = 32 * s + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
-        a2[ot][s][j] = __builtin_bit_cast(__bf16, q2s[(ot * 16 + (lane & 15)) * HP + h]);
+        a2[ot][s][j] = __builtin_bit_cast(__bf16, q2s[(ot * 16 + (lane & 15)) * Q2S + h]);
       }
+  if (RES) __syncthreads();  // every wave has its operand: the Q2 rows become the output tiles
   // (unrolled in the residual form, whose prefetched values are indexed by ct)
 #pragma unroll(RES ? 4 : 1)
   for (int ct = 0; ct < 4; ++ct) {
@@ -750,22 +759,24 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
       }
     }
     if (RES) {
-      float* sw = stg + ((ct & 1) * 4 + wave) * 32 * 17;
+      float* sw = stg + wave * 32 * SP;
 #pragma unroll
       for (int ot = 0; ot < OT; ++ot)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int o = ot * 16 + 4 * g + r;
-          sw[o * 17 + (lane & 15)] = out[ot][r] + (o < cout ? q2[o] : 0.f);
+          sw[o * SP + (lane & 15)] = out[ot][r] + (o < cout ? q2[o] : 0.f);
         }
       wave_lds_sync();  // the wave's output tile is complete
       if (rc < cout) {
         const uint32_t u[4] = {rres[ct].x, rres[ct].y, rres[ct].z, rres[ct].w};
+        const float4 f0 = *(const float4*)(sw + rc * SP + 8 * rh), f1 = *(const float4*)(sw + rc * SP + 8 * rh + 4);
+        const float f[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
         uint32_t w[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const float lo = sw[rc * 17 + 8 * rh + 2 * i] + __uint_as_float(u[i] << 16);
-          const float hi = sw[rc * 17 + 8 * rh + 2 * i + 1] + __uint_as_float(u[i] & 0xffff0000u);
+          const float lo = f[2 * i] + __uint_as_float(u[i] << 16);
+          const float hi = f[2 * i + 1] + __uint_as_float(u[i] & 0xffff0000u);
           w[i] = f2bf2(lo, hi);
         }
         *(uint4*)(vout + (b * cout + rc) * P + p0 + wave * 64 + ct * 16 + 8 * rh) = uint4{w[0], w[1], w[2], w[3]};
