@@ -254,6 +254,25 @@ def fno_leg():
     return out
 
 
+def fno_cpu_baseline():
+    """The FP64 numpy oracle of the FNO, as it stands: one forward pass at
+    batch 1 on the full surrogate shape, on this host's cores (threaded
+    BLAS)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import fno as ofno
+    s = ofno.Shape()
+    th = ofno.init_params(s, 0)
+    x = np.random.default_rng(0).standard_normal((1, s.cin, s.nx, s.ny, s.nz))
+    mats = ofno.dft_matrices(s)
+    t = time.perf_counter()
+    ofno.forward(th, x, s, mats)
+    dt = time.perf_counter() - t
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return dict(value=1.0 / dt, unit="samples/s", cores=threads, kind="oracle",
+                sample=f"one FP64 forward pass at batch 1, 128x64x64, width 32, 4 layers, 32x32x16 modes: {dt:.1f} s")
+
+
 def c1_leg(steps=2000, warmup=50):
     """The dataset configuration (256x128x128, FP32, random obstacle seed 0,
     Re_c 5500) with the FP64 running mean and snapshots on, as every dataset
@@ -409,6 +428,9 @@ def main():
         log("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(args.workload)
         log(f"cpu baseline: {line['cpu_baseline']}")
+        if "fno" in line:
+            line["fno"]["cpu_oracle"] = fno_cpu_baseline()
+            log(f"fno oracle: {line['fno']['cpu_oracle']}")
     print(json.dumps(line), flush=True)
 
 
