@@ -814,16 +814,24 @@ template <> const Coef<float>& coef_for<f16s>(const Coefs& c) { return c.f; }
 template <> const Coef<float>& coef_for<bf16s>(const Coefs& c) { return c.f; }
 
 // Occupancy cap of the odd-parity FP32 step.  Its registers allow 5 waves
-// per SIMD, but at 1024x512x512 it runs 0.7% faster at 3: more waves in
-// flight only add cache contention to this streaming kernel (the even
-// kernel sits at 4 by its registers, and capping it lower does not help).
-// The cap is dynamic LDS that the kernel does not touch: 21 KB on top of
-// its 3 KB of static LDS leaves room for 6 blocks of 2 waves per CU.
-constexpr size_t ODD_F32_CAP_LDS = 21504;
+// per SIMD.  Measured (kernel time over both parities):
+//   256x128x128 (32K tiles): uncapped best (0.315 ms; 0.320 at 3 waves);
+//   512x256x256 (262K tiles): 4 waves best (1.698 ms; 1.712 uncapped);
+//   1024x512x512 (2.1M tiles): 3 waves best (12.97 ms; 13.09 uncapped).
+// The larger the grid, the more the extra waves in flight only add cache
+// contention.  (The even kernel sits at 4 waves by its registers; capping it
+// lower does not help.)  The cap is dynamic LDS that the kernel does not
+// touch: with its 3 KB of static LDS, 17 KB allows 8 blocks of 2 waves per
+// CU (4 waves per SIMD), 21 KB allows 6 (3 waves per SIMD).
+static size_t odd_f32_cap_lds(int64_t ntiles) {
+  if (ntiles < (int64_t(1) << 16)) return 0;
+  if (ntiles < (int64_t(1) << 20)) return 17408;
+  return 21504;
+}
 
 template <typename S, bool ODD, int MODE>
 static void launch_step(const StepArgs& a, const Coefs& c, hipStream_t st) {
-  const size_t lds = (ODD && std::is_same<S, float>::value) ? ODD_F32_CAP_LDS : 0;
+  const size_t lds = (ODD && std::is_same<S, float>::value) ? odd_f32_cap_lds(a.ntiles) : 0;
   hipLaunchKernelGGL((lbm_step_kernel<S, ODD, MODE>), dim3(a.ntiles), dim3(NTHREADS), lds, st, a, coef_for<S>(c));
 }
 
