@@ -56,10 +56,14 @@ WIDE = [dict(SMALL, width=48, layers=1, hidden=32), dict(SMALL, width=64, layers
 SIREN = dict(SMALL, proj="siren", w0=30.0)
 # the hybrid F/FNO: residual feed-forward layers (two hidden widths, the
 # second the production instance of the feed-forward kernels)
-HYBRID = [dict(SMALL, arch="hybrid", ff_hidden=32), dict(SMALL, width=32, hidden=32, arch="hybrid", ff_hidden=128)]
+# (feed-forward 48 pads to 64 hidden rows: the four-tile kernel instances
+# with zero rows)
+HYBRID = [dict(SMALL, arch="hybrid", ff_hidden=32), dict(SMALL, width=32, hidden=32, arch="hybrid", ff_hidden=128),
+          dict(SMALL, arch="hybrid", ff_hidden=48)]
 
 
-@pytest.mark.parametrize("cfg", WIDE + [SIREN] + HYBRID, ids=["w48", "w64", "siren", "hybrid16", "hybrid32"])
+@pytest.mark.parametrize("cfg", WIDE + [SIREN] + HYBRID,
+                         ids=["w48", "w64", "siren", "hybrid16", "hybrid32", "hybrid16ff48"])
 def test_forward_wide_matches_oracle(cfg):
     net, x, _ = _setup(cfg, 2)
     y = net.forward(x).cpu().numpy()
@@ -71,7 +75,7 @@ def test_forward_wide_matches_oracle(cfg):
 
 
 @pytest.mark.parametrize("cfg", [SMALL] + WIDE + [SIREN] + HYBRID,
-                         ids=["w16", "w48", "w64", "siren", "hybrid16", "hybrid32"])
+                         ids=["w16", "w48", "w64", "siren", "hybrid16", "hybrid32", "hybrid16ff48"])
 def test_gradients_match_oracle_small(cfg):
     import torch
     s = _shape(cfg)
