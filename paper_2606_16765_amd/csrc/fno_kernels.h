@@ -446,13 +446,15 @@ template <> __device__ __forceinline__ uint4 load8_bf<float>(const float* p) {
 
 template <int NT, typename InT, bool C2R = true>  // NT = ceil(W / 16), W <= 32; C2R: r2 term present
 __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
-  // the v tile [256 points][PW_TS], then the FP32 result tile [32][PW_DS];
-  // after it the BF16 activation tile [32][PW_J + 8] for the fused z-DFT
+  // one LDS region holds in turn the v tile [256 points][PW_TS], the FP32
+  // result tile [32][PW_DS] and the BF16 activation tile [32][PW_J + 8] of
+  // the fused z-DFT (33 KB, so 4 blocks fit a CU)
   constexpr int AP = PW_J + 8;
-  __shared__ __attribute__((aligned(16))) float lds[32 * PW_DS + 32 * AP / 2];
+  static_assert(32 * AP * 2 <= 32 * PW_DS * 4 && 256 * PW_TS * 2 <= 32 * PW_DS * 4, "LDS reuse");
+  __shared__ __attribute__((aligned(16))) float lds[32 * PW_DS];
   uint16_t* tile = (uint16_t*)lds;
   float* dst = lds;
-  uint16_t* at = (uint16_t*)(lds + 32 * PW_DS);
+  uint16_t* at = (uint16_t*)lds;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4;
   const int64_t j0 = (int64_t)blockIdx.x * PW_J;
   const int64_t b = j0 / a.P, p0 = j0 % a.P;
@@ -548,9 +550,14 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
   float* hout = a.h ? a.h + b * a.W * a.P + p0 : nullptr;
   uint16_t* act = a.act ? a.act + b * a.W * a.P + p0 : nullptr;
   const float* gm = a.gmul ? a.gmul + b * a.W * a.P + p0 : nullptr;
-#pragma unroll 2
-  for (int e = t; e < 32 * 64; e += 256) {
+  // this thread's BF16 activations, kept for the z-DFT tile, which is
+  // written over the result tile once every thread has read its values
+  uint2 wz[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int e = t + 256 * q;
     const int n = e >> 6, p4 = (e & 63) * 4;
+    wz[q] = uint2{0u, 0u};
     if (n >= a.W) continue;
     float4 v = *(const float4*)(dst + n * PW_DS + p4);
     const int64_t off = (int64_t)n * a.P + p4;
@@ -577,9 +584,16 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
       w.y = f2bf2(v.z, v.w);
     }
     *(uint2*)(act + off) = w;
-    if (a.a1) *(uint2*)(at + n * AP + p4) = w;
+    wz[q] = w;
   }
   if (a.a1) {
+    __syncthreads();  // the result tile is read: its region becomes the activation tile
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + 256 * q;
+      const int n = e >> 6, p4 = (e & 63) * 4;
+      if (n < a.W) *(uint2*)(at + n * AP + p4) = wz[q];
+    }
     __syncthreads();
     // columns (w, row) = 16 ct + l16 with w = col / 4 and row = col % 4 the
     // (x, y) row within the block; rows of the result k = 16 rt + 4 g + r
