@@ -45,7 +45,7 @@ enum {
   LBM_EINVAL = 1,    /* bad argument (shape, pointer, parameter range)          */
   LBM_ENOMEM = 2,    /* device or host allocation failed                         */
   LBM_EDEVICE = 3,   /* HIP runtime error; sticky                                */
-  LBM_EUNSTABLE = 4, /* non-finite mass found by the periodic check; sticky      */
+  LBM_EUNSTABLE = 4, /* non-finite mass found by lbm_mass; sticky               */
   LBM_ESTATE = 5     /* call not valid in the object's state                     */
 };
 
