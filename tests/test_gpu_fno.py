@@ -112,13 +112,14 @@ def test_forward_full_size_matches_oracle(arch):
     assert err < 3e-2
 
 
-def test_adam_trajectory_matches_oracle():
+@pytest.mark.parametrize("cfg", [SMALL, HYBRID[0]], ids=["fno", "hybrid"])
+def test_adam_trajectory_matches_oracle(cfg):
     """Five loss/grad/Adam steps on the GPU against the same five steps of
     the FP64 oracle started from the same parameters: the loss sequences
     agree to the forward tolerance."""
     import torch
-    s = _shape(SMALL)
-    net, x, t = _setup(SMALL, 2, seed=7)
+    s = _shape(cfg)
+    net, x, t = _setup(cfg, 2, seed=7)
     mnp = ofno.inner_box_mask(s)
     mask = torch.from_numpy(mnp).cuda()
     th = net.get_params().astype(np.float64)
@@ -137,14 +138,15 @@ def test_adam_trajectory_matches_oracle():
         assert abs(lg - lo) / lo < 3e-2
 
 
-def test_training_fits_teacher_network():
+@pytest.mark.parametrize("cfg", [SMALL, HYBRID[0]], ids=["fno", "hybrid"])
+def test_training_fits_teacher_network(cfg):
     """A target made by another network of the same architecture is exactly
     representable; 60 Adam steps must cut the masked loss at least 4x."""
     import torch
     from paper_2606_16765_amd import Fno
-    s = _shape(SMALL)
-    net, x, _ = _setup(SMALL, 2, seed=5)
-    teacher = Fno(max_batch=2, seed=11, **SMALL)
+    s = _shape(cfg)
+    net, x, _ = _setup(cfg, 2, seed=5)
+    teacher = Fno(max_batch=2, seed=11, **cfg)
     t = teacher.forward(x)
     mask = torch.from_numpy(ofno.inner_box_mask(s)).cuda()
     losses = [net.train_step(x, t, mask, 1e-2) for _ in range(60)]
