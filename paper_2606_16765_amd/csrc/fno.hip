@@ -82,6 +82,9 @@ struct fno_net {
   GtMat Pq1, Pq2;
   float* pq1b = nullptr;
   bool fused_proj = false;
+  // the projection backward also forms the Q2 gradient (cout <= 8), so the
+  // forward pass of a training step stores no hidden activation
+  bool q2_in_bwd = false;
   // hybrid feed-forward operands per layer (the fused projection's layout):
   // W1 [Hfp][32], W2 [32][Hfp], W2^T [Hfp][32] BF16, b1 [Hfp] FP32, zero padded
   std::vector<GtMat> Pf1, Pf2, Gf2t;
@@ -316,15 +319,22 @@ static void launch_proj(fno_net* n, int B, const uint16_t* v, float* y, uint16_t
   if (n->p.proj_act == 1) launch_proj_act<NT, KS, 1>(n, B, v, y, aout);
   else launch_proj_act<NT, KS, 0>(n, B, v, y, aout);
 }
-template <int NT, int KS>
-static void launch_proj_bwd(fno_net* n, int B, const uint16_t* v, const float* gy, uint16_t* ga, float* gv) {
+template <int NT, int KS, bool GQ2>
+static void launch_proj_bwd_q(fno_net* n, int B, const uint16_t* v, const float* gy, uint16_t* ga, float* gv,
+                              float* q2part) {
   const unsigned blocks = (unsigned)((int64_t)B * n->P / 256);
   if (n->p.proj_act == 1)
-    hipLaunchKernelGGL((proj_bwd_kernel<NT, KS, 1>), dim3(blocks), dim3(256), 0, n->st, v, n->W, n->P, n->Pq1.d,
-                       n->pq1b, n->Gq2t.d, n->Gq2t.kp, gy, n->p.cout, n->H, ga, gv, n->p.proj_w0);
+    hipLaunchKernelGGL((proj_bwd_kernel<NT, KS, 1, false, GQ2>), dim3(blocks), dim3(256), 0, n->st, v, n->W, n->P,
+                       n->Pq1.d, n->pq1b, n->Gq2t.d, n->Gq2t.kp, gy, n->p.cout, n->H, ga, gv, n->p.proj_w0, q2part);
   else
-    hipLaunchKernelGGL((proj_bwd_kernel<NT, KS, 0>), dim3(blocks), dim3(256), 0, n->st, v, n->W, n->P, n->Pq1.d,
-                       n->pq1b, n->Gq2t.d, n->Gq2t.kp, gy, n->p.cout, n->H, ga, gv, 0.f);
+    hipLaunchKernelGGL((proj_bwd_kernel<NT, KS, 0, false, GQ2>), dim3(blocks), dim3(256), 0, n->st, v, n->W, n->P,
+                       n->Pq1.d, n->pq1b, n->Gq2t.d, n->Gq2t.kp, gy, n->p.cout, n->H, ga, gv, 0.f, q2part);
+}
+template <int NT, int KS>
+static void launch_proj_bwd(fno_net* n, int B, const uint16_t* v, const float* gy, uint16_t* ga, float* gv,
+                            float* q2part) {
+  if (q2part) launch_proj_bwd_q<NT, KS, true>(n, B, v, gy, ga, gv, q2part);
+  else launch_proj_bwd_q<NT, KS, false>(n, B, v, gy, ga, gv, nullptr);
 }
 
 // fused projection; aout (training) also receives the BF16 hidden activation
@@ -342,17 +352,18 @@ static void fused_projection(fno_net* n, int B, const uint16_t* v, float* y, uin
   }
 }
 // fused projection backward: ga (BF16) = GELU'(h1) Q2^T gy, gv = Q1^T ga
-static void fused_projection_bwd(fno_net* n, int B, const uint16_t* v, const float* gy, uint16_t* ga, float* gv) {
+static void fused_projection_bwd(fno_net* n, int B, const uint16_t* v, const float* gy, uint16_t* ga, float* gv,
+                                 float* q2part = nullptr) {
   const int NT = n->Pq1.np / 16, KS = n->Pq1.kp / 32;
   switch (NT * 4 + KS) {
-    case 2 * 4 + 1: launch_proj_bwd<2, 1>(n, B, v, gy, ga, gv); break;
-    case 2 * 4 + 2: launch_proj_bwd<2, 2>(n, B, v, gy, ga, gv); break;
-    case 4 * 4 + 1: launch_proj_bwd<4, 1>(n, B, v, gy, ga, gv); break;
-    case 4 * 4 + 2: launch_proj_bwd<4, 2>(n, B, v, gy, ga, gv); break;
-    case 6 * 4 + 1: launch_proj_bwd<6, 1>(n, B, v, gy, ga, gv); break;
-    case 6 * 4 + 2: launch_proj_bwd<6, 2>(n, B, v, gy, ga, gv); break;
-    case 8 * 4 + 1: launch_proj_bwd<8, 1>(n, B, v, gy, ga, gv); break;
-    default: launch_proj_bwd<8, 2>(n, B, v, gy, ga, gv); break;
+    case 2 * 4 + 1: launch_proj_bwd<2, 1>(n, B, v, gy, ga, gv, q2part); break;
+    case 2 * 4 + 2: launch_proj_bwd<2, 2>(n, B, v, gy, ga, gv, q2part); break;
+    case 4 * 4 + 1: launch_proj_bwd<4, 1>(n, B, v, gy, ga, gv, q2part); break;
+    case 4 * 4 + 2: launch_proj_bwd<4, 2>(n, B, v, gy, ga, gv, q2part); break;
+    case 6 * 4 + 1: launch_proj_bwd<6, 1>(n, B, v, gy, ga, gv, q2part); break;
+    case 6 * 4 + 2: launch_proj_bwd<6, 2>(n, B, v, gy, ga, gv, q2part); break;
+    case 8 * 4 + 1: launch_proj_bwd<8, 1>(n, B, v, gy, ga, gv, q2part); break;
+    default: launch_proj_bwd<8, 2>(n, B, v, gy, ga, gv, q2part); break;
   }
 }
 
@@ -711,6 +722,9 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
   n->part2_elems = 64 * std::max<int64_t>(std::max<int64_t>(Hm * W, (int64_t)p.cout * n->H),
                                            std::max<int64_t>(W * W, W * (int64_t)p.cin));
   n->partc_elems = (int64_t)B * P / 2048 * std::max<int64_t>(std::max<int64_t>(Hm, W), p.cout);
+  // per-block Q2 partials of the projection backward (cout x H per 256 points)
+  n->q2_in_bwd = n->fused_proj && p.cout <= 8 && (int64_t)B * P / 256 * p.cout * n->H <= n->part_elems &&
+                 64 * (int64_t)p.cout * n->H <= n->part2_elems;
   ok = ok && A((void**)&n->part, (size_t)n->part_elems * 4) && A((void**)&n->lpart, (size_t)n->lpart_n * 8) &&
        A((void**)&n->lscal, 32) &&
        A((void**)&n->part2, (size_t)n->part2_elems * 4) && A((void**)&n->partc, (size_t)n->partc_elems * 4);
@@ -939,7 +953,7 @@ static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout, bool 
   if (n->fused_proj) {
     // training keeps the BF16 hidden activation for the gradient of Q2; the
     // pre-activation is recomputed in the backward pass
-    fused_projection(n, B, n->v[n->L], yout, training ? n->a : nullptr);
+    fused_projection(n, B, n->v[n->L], yout, training && !n->q2_in_bwd ? n->a : nullptr);
   } else {
     if ((rc = pointwise(n, B, n->v[n->L], true, (int)W, n->h1, false, n->H, &n->Gq1, n->theta + n->off_q1, false,
                         true, n->a, true)))
@@ -979,8 +993,23 @@ extern "C" int fno_loss_grad(fno_net* n, const uint16_t* x, const float* target,
                      (const float*)dscale, n->gy, n->lpart);
   FCHK(n, hipMemsetAsync(n->grad, 0, n->nparam * 4, n->st));
   // projection
-  if ((rc = gram(n, n->gy, (int)cout, n->a, n->H, B, n->grad + n->off_Q2, false, n->grad + n->off_q2))) return rc;
-  if (n->fused_proj) {
+  if (n->q2_in_bwd) {
+    // one pass: dL/dh1 (BF16, into the hidden buffer), dL/dv, and per-block
+    // sums of the Q2 gradient, reduced here in a fixed order; q2 from gy
+    fused_projection_bwd(n, B, n->v[n->L], n->gy, n->a, n->gv, n->part);
+    const int64_t nblk = (int64_t)B * P / 256, E2 = cout * n->H;
+    constexpr int S = 64;
+    hipLaunchKernelGGL(reduce_slices_kernel, dim3((unsigned)((E2 + 255) / 256), S), dim3(256), 0, n->st, n->part, nblk,
+                       E2, S, n->part2);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((E2 + 255) / 256)), dim3(256), 0, n->st, n->part2,
+                       (int64_t)S, E2, n->grad + n->off_Q2, 0);
+    if ((rc = colsum(n, n->gy, (int)cout, B, n->grad + n->off_q2, false))) return rc;
+    if ((rc = gram(n, (const uint16_t*)n->a, n->H, n->v[n->L], (int)W, B, n->grad + n->off_Q1, false,
+                   n->grad + n->off_q1)))
+      return rc;
+  } else if ((rc = gram(n, n->gy, (int)cout, n->a, n->H, B, n->grad + n->off_Q2, false, n->grad + n->off_q2))) {
+    return rc;
+  } else if (n->fused_proj) {
     // dL/dh1 = GELU'(h1) * Q2^T gy in BF16 (the hidden activation's buffer,
     // already consumed) and dL/dv = Q1^T dL/dh1, in one pass
     fused_projection_bwd(n, B, n->v[n->L], n->gy, n->a, n->gv);

@@ -665,6 +665,18 @@ template <int ACT>
 __device__ __forceinline__ float proj_act_grad(float h, float w0) {
   return ACT == 1 ? w0 * cos_w(w0 * h) : gelu_grad(h);
 }
+// the activation and its derivative together (one erf for GELU)
+template <int ACT>
+__device__ __forceinline__ void proj_act_both(float h, float w0, float& a, float& da) {
+  if (ACT == 1) {
+    a = sin_w(w0 * h);
+    da = w0 * cos_w(w0 * h);
+  } else {
+    const float e = erff(h * 0.70710678118654752f);
+    a = 0.5f * h * (1.0f + e);
+    da = 0.5f * (1.0f + e) + h * expf(-0.5f * h * h) * 0.39894228040143268f;
+  }
+}
 template <int NT, int KS, bool STORE_A = false, int ACT = 0, bool RES = false>
 __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ v, int W, int64_t P,
                                                    const uint16_t* __restrict__ Q1p, const float* __restrict__ q1p,
@@ -817,13 +829,21 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
 // from the accumulator registers.  Block and wave layout as proj_kernel.
 // PF (the hybrid's feed-forward, cout = 32) loads the next column tile's gy
 // while the current one computes.
-template <int NT, int KS, int ACT = 0, bool PF = false>
+// GQ2 (cout <= 8) also forms the Q2 gradient, so that the forward pass need
+// not store the hidden activation: each column tile's BF16 activation
+//   a = bf16(act(h1))                     (the forward's value, recomputed)
+// goes through the wave's tile, and sum_p gy[o][p] a[h][p] over its 16
+// points is formed on MFMA (points as k; the upper 16 k are zero) and
+// added, per lane in column-tile order, into the wave's LDS sums of rows
+// o < 8.  The block's four waves are summed in a fixed order into
+// q2part[block][o][h] (cout x H), reduced over blocks on the host side.
+template <int NT, int KS, int ACT = 0, bool PF = false, bool GQ2 = false>
 __global__ __launch_bounds__(256) void proj_bwd_kernel(const uint16_t* __restrict__ v, int W, int64_t P,
                                                        const uint16_t* __restrict__ Q1p, const float* __restrict__ q1p,
                                                        const uint16_t* __restrict__ Q2t, int kp2,
                                                        const float* __restrict__ gy, int cout, int H,
                                                        uint16_t* __restrict__ ga, float* __restrict__ gv,
-                                                       float w0 = 0.f) {
+                                                       float w0 = 0.f, float* __restrict__ q2part = nullptr) {
   constexpr int WP = 32 * KS, VS = WP + 8, HP = 16 * NT;
   __shared__ __attribute__((aligned(16))) uint16_t vt[256 * VS];
   __shared__ __attribute__((aligned(16))) uint16_t q1s[HP * WP];
@@ -831,6 +851,8 @@ __global__ __launch_bounds__(256) void proj_bwd_kernel(const uint16_t* __restric
   // gradient tile [HP][16 points] of one column tile
   __shared__ __attribute__((aligned(16))) bf16x8 q1t[(NT / 2) * (2 * KS) * 64];
   __shared__ __attribute__((aligned(16))) uint16_t hs[4 * HP * 16];
+  // GQ2: per wave the Q2 gradient sums [8 rows o][HP]
+  __shared__ __attribute__((aligned(16))) float qacc[GQ2 ? 4 * 8 * HP : 1];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4, l16 = lane & 15;
   const int64_t j0 = (int64_t)blockIdx.x * 256;
   const int64_t b = j0 / P, p0 = j0 % P;
@@ -858,6 +880,13 @@ __global__ __launch_bounds__(256) void proj_bwd_kernel(const uint16_t* __restric
   }
   __syncthreads();
   uint16_t* hw = hs + wave * HP * 16;
+  if (GQ2 && g < 2) {
+    // lanes of groups 0 and 1 own rows o = 4 g + r, columns 16 nt + l16
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) qacc[(wave * 8 + 4 * g + r) * HP + nt * 16 + l16] = 0.f;
+  }
   float gnx[PF ? 8 : 1];
   if (PF) {
 #pragma unroll
@@ -898,6 +927,7 @@ __global__ __launch_bounds__(256) void proj_bwd_kernel(const uint16_t* __restric
     f32x4 go[2 * KS];
 #pragma unroll
     for (int ct2 = 0; ct2 < 2 * KS; ++ct2) go[ct2] = f32x4{0.f, 0.f, 0.f, 0.f};
+    uint32_t apk[GQ2 ? NT : 1][2];  // GQ2: packed BF16 activation, (r = 0, 1) and (r = 2, 3)
     // one k step of Q1^T at a time: hidden tiles 2 s and 2 s + 1
 #pragma unroll
     for (int s = 0; s < NT / 2; ++s) {
@@ -911,8 +941,20 @@ __global__ __launch_bounds__(256) void proj_bwd_kernel(const uint16_t* __restric
           acc = mfma16(*(const bf16x8*)(q1s + (nt * 16 + l16) * WP + ks * 32 + 8 * g), vb[ks], acc);
         const f32x4 tq = mfma16(*(const bf16x8*)(Q2t + (nt * 16 + l16) * kp2 + 8 * g), gb, f32x4{0.f, 0.f, 0.f, 0.f});
         float d[4];
+        if (GQ2) {
+          float av[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) d[r] = tq[r] * proj_act_grad<ACT>(acc[r] + q1p[hr + r], w0);
+          for (int r = 0; r < 4; ++r) {
+            float da;
+            proj_act_both<ACT>(acc[r] + q1p[hr + r], w0, av[r], da);
+            d[r] = tq[r] * da;
+          }
+          apk[GQ2 ? nt : 0][0] = f2bf2(av[0], av[1]);
+          apk[GQ2 ? nt : 0][1] = f2bf2(av[2], av[3]);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) d[r] = tq[r] * proj_act_grad<ACT>(acc[r] + q1p[hr + r], w0);
+        }
         u[2 * hh] = f2bf2(d[0], d[1]);
         u[2 * hh + 1] = f2bf2(d[2], d[3]);
 #pragma unroll
@@ -938,6 +980,47 @@ __global__ __launch_bounds__(256) void proj_bwd_kernel(const uint16_t* __restric
       if (hr < H)
         *(uint4*)(ga + (b * H + hr) * P + p0 + wave * 64 + ct * 16 + 8 * half) =
             *(const uint4*)(hw + hr * 16 + 8 * half);
+    }
+    if (GQ2) {
+      // the activation tile replaces the gradient tile just stored
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          hw[(nt * 16 + 4 * g + r) * 16 + l16] = (uint16_t)(apk[GQ2 ? nt : 0][r >> 1] >> (16 * (r & 1)));
+      wave_lds_sync();
+      // A: rows o = l16 (zero from cout on), k = the tile's points 8 g + j
+      // for g < 2; B: columns h, the same points, from the tile
+      bf16x8 ya;
+      const bool live = g < 2 && l16 < cout;
+      const float* gr = gy + (b * cout + (live ? l16 : 0)) * P + p0 + wave * 64 + ct * 16 + 8 * (g & 1);
+      const float4 y0 = *(const float4*)gr, y1 = *(const float4*)(gr + 4);
+      const float yv[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
+#pragma unroll
+      for (int j = 0; j < 8; ++j) ya[j] = __builtin_bit_cast(__bf16, live ? f2bf(yv[j]) : (uint16_t)0);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        bf16x8 ab = *(const bf16x8*)(hw + (nt * 16 + l16) * 16 + 8 * (g & 1));
+        if (g >= 2) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) ab[j] = __builtin_bit_cast(__bf16, (uint16_t)0);
+        }
+        const f32x4 pq = mfma16(ya, ab, f32x4{0.f, 0.f, 0.f, 0.f});
+        if (g < 2) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) qacc[(wave * 8 + 4 * g + r) * HP + nt * 16 + l16] += pq[r];
+        }
+      }
+    }
+  }
+  if (GQ2) {
+    // the four waves' sums, added in wave order
+    __syncthreads();
+    for (int e = t; e < cout * H; e += 256) {
+      const int o = e / H, h = e % H;
+      const float sum = ((qacc[(0 * 8 + o) * HP + h] + qacc[(1 * 8 + o) * HP + h]) + qacc[(2 * 8 + o) * HP + h]) +
+                        qacc[(3 * 8 + o) * HP + h];
+      q2part[(int64_t)blockIdx.x * cout * H + e] = sum;
     }
   }
 }
