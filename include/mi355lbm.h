@@ -45,7 +45,9 @@ enum {
   LBM_EINVAL = 1,    /* bad argument (shape, pointer, parameter range)          */
   LBM_ENOMEM = 2,    /* device or host allocation failed                         */
   LBM_EDEVICE = 3,   /* HIP runtime error; sticky                                */
-  LBM_EUNSTABLE = 4, /* non-finite mass found by lbm_mass; sticky               */
+  LBM_EUNSTABLE = 4, /* run diverged: a check step (lbm_params.check_every) found
+                        a cell with non-finite or out-of-range density or speed,
+                        or lbm_mass found a non-finite mass; sticky              */
   LBM_ESTATE = 5     /* call not valid in the object's state                     */
 };
 
@@ -68,7 +70,8 @@ typedef struct {
                               and the outlet (x = nx - 1/2); y, z have no-slip
                               walls at -1/2 and n - 1/2                           */
   double u_in;             /* inlet velocity along +x, lattice units              */
-  double nu;               /* lattice viscosity; omega1 = 1/(3 nu + 1/2)          */
+  double nu;               /* lattice viscosity; omega1 = 1/(3 nu + 1/2); ignored
+                              when re > 0                                         */
   double omega2;           /* bulk relaxation rate (1.0)                          */
   int32_t mode;            /* LBM_MODE_*                                          */
   int32_t galilean;        /* 1: Galilean correction of the 2nd-order rates       */
@@ -88,11 +91,28 @@ typedef struct {
                               (output k = mix(seed + (k+1) * 0x9E3779B97F4A7C15),
                               top 53 bits), generated on the device            */
   double perturb_amp;
+  double re;               /* > 0: Reynolds number on l_ref (paper Sec. 3.1, Re
+                              set through the viscosity): nu = u_in l_ref / re;
+                              needs u_in > 0.  0: take nu as given               */
+  double l_ref;            /* reference length in cells for re; <= 0: ny, the
+                              channel height                                      */
+  int32_t check_every;     /* > 0: every check_every-th step (steps k, 2k, ...)
+                              flags, on the device, any fluid cell whose
+                              pre-collision density leaves (0, 2) or whose speed
+                              reaches the lattice sound speed 1/sqrt(3), NaN and
+                              infinity included; the flag travels to the host
+                              asynchronously and the next call on the object
+                              returns the sticky LBM_EUNSTABLE.  0: off         */
+  int32_t reserved;        /* 0                                                   */
+  int64_t force_capacity;  /* > 0: the force series is a ring holding the last
+                              force_capacity samples (required with a caller
+                              workspace); 0: it grows without bound              */
 } lbm_params;
 
 /* Fill *p with defaults (F32, channel, omega2 = 1, Galilean on, lambda 0.01,
  * halfway bounce-back, averaging from step 0, no snapshots, forces every
- * step, XCD remap on) for an nx x ny x nz grid.                               */
+ * step, XCD remap on, no stability check, growing force series, nu for
+ * Re 5000 on the channel height, re = 0) for an nx x ny x nz grid.          */
 int lbm_default_params(lbm_params* p, int32_t nx, int32_t ny, int32_t nz);
 
 /* Create a solver (paper Sec. 3.1: obstacle in a channel, inlet velocity u_in,
@@ -108,13 +128,50 @@ int lbm_default_params(lbm_params* p, int32_t nx, int32_t ny, int32_t nz);
  *             state is the equilibrium at rho = 1 and u0.
  *  hip_stream hipStream_t cast to void* (NULL: null stream).
  * On success *out owns device memory of about 27*N*sizeof(storage) bytes
- * plus 32 B per cell when averaging is on.                                   */
+ * plus 32 B per cell when averaging is on.
+ * Errors: LBM_EINVAL for a grid the kernels do not tile, a non-positive
+ * viscosity, omega2 outside (0, 2), an obstacle within 3 cells of inlet or
+ * outlet, links out of range, and the fourth-order mode where its rates are
+ * undefined (|omega1 - omega2| < 1e-3, where A and B have a pole, or
+ * omega3..5 outside (0, 2)); LBM_ENOMEM; LBM_EDEVICE.                       */
 int lbm_create(const lbm_params* p, const uint8_t* solid, int64_t nlinks, const int64_t* link_cell,
                const uint8_t* link_dir, const double* link_q, const double* u0, void* hip_stream, lbm_sim** out);
 
+/* Device bytes that lbm_create_in needs as a caller workspace for these
+ * parameters and this solid mask (host uint8 [N] or NULL): populations in
+ * the padded layout, cell flags, boundary tables, force partials, FP64
+ * accumulators when averaging, the snapshot ring, the force ring
+ * (force_capacity samples) and a stability flag.  Host work only; no device
+ * call.  Errors: LBM_EINVAL, as lbm_create would return it.                  */
+int lbm_workspace_size(const lbm_params* p, const uint8_t* solid, size_t* bytes);
+
+/* lbm_create with an optional caller workspace: d_workspace NULL behaves as
+ * lbm_create; otherwise it is device memory of at least
+ * lbm_workspace_size() bytes, 256-byte aligned, on the current device, that
+ * the caller owns and keeps alive until lbm_destroy, which does not free it.
+ * All state the step touches then lives in it; with forces on, the force
+ * series must be a ring (force_capacity > 0).  Creation still allocates and
+ * frees small temporaries (link cells, u0) and readouts into host pointers
+ * stage through temporaries; lbm_step allocates nothing.
+ * Errors: LBM_EINVAL (workspace too small or misaligned, force_capacity 0
+ * with forces on, and everything lbm_create rejects), LBM_ENOMEM,
+ * LBM_EDEVICE.                                                              */
+int lbm_create_in(const lbm_params* p, const uint8_t* solid, int64_t nlinks, const int64_t* link_cell,
+                  const uint8_t* link_dir, const double* link_q, const double* u0, void* d_workspace,
+                  size_t workspace_bytes, void* hip_stream, lbm_sim** out);
+
 /* Advance nsteps steps (asynchronous on the object's stream).  One step is
- * one fused stream-and-collide launch (in-place AA pattern; the parity is
- * tracked internally) plus a force reduction when a force sample is due.    */
+ * one time step of the method of paper Sec. 3.1-3.2: streaming of the 27
+ * populations with the channel's boundary rules (velocity inlet, zero-
+ * gradient outlet, no-slip walls, bounce-back at the obstacle) and the
+ * cumulant collision; plus the data capture of Sec. 2 (running means,
+ * snapshots, force on the object) when due.  It is one fused
+ * stream-and-collide launch (in-place AA pattern; the parity is tracked
+ * internally), a force reduction when a force sample is due, and a 4-byte
+ * copy of the stability flag after a check step.  nsteps = 0 only reports
+ * the object's state (LBM_EUNSTABLE once a finished check step has flagged).
+ * Errors: LBM_EINVAL (negative count), the sticky LBM_EUNSTABLE and
+ * LBM_EDEVICE, LBM_ENOMEM (growing force series).                            */
 int lbm_step(lbm_sim* s, int64_t nsteps);
 
 /* Mean fields (paper Sec. 2: mean velocity and pressure).  out is [4][N]
@@ -142,8 +199,9 @@ int lbm_mean_fields_pooled(lbm_sim* s, int32_t factor, int32_t quarter_turns, fl
 int lbm_snapshots(lbm_sim* s, float* out, int out_on_device, int32_t* k, int64_t* steps);
 
 /* Force on the obstacle (paper Sec. 2: forces in x and y; all three given).
- * Host double [n][3], the recorded samples in step order; the step index of
- * sample j is returned in steps[j] when steps is not NULL.  Force of step n:
+ * Host double [n][3], the retained samples in step order (all of them, or
+ * the last force_capacity of a ring); *n receives their number; the step
+ * index of sample j is returned in steps[j] when steps is not NULL.  Force of step n:
  * sum over fluid->obstacle links (x, j) of c_j (f_jbar(x) entering step n
  * + f*_j(x) leaving it).  Synchronises.                                      */
 int lbm_forces(lbm_sim* s, double* fxyz, int64_t cap, int64_t* n, int64_t* steps);

@@ -215,8 +215,9 @@ void orc_moments_from_cumulants(const double* C, double* k) {
  * in Sec. 3.2; the paper does not print them).  Closed forms in omega1 with
  * omega2 entering as the bulk rate, written as recalled from that source,
  * which is not at hand: parity unpinned against it.  The pins that do hold
- * them: the limits at omega1 = 1, the reduction to the plain operator with
- * neutral coefficients, and the faster diffusion-error convergence.       */
+ * them: omega3..5 vanish as omega1 -> 2 (their factor omega1 - 2), the
+ * reduction to the plain operator with neutral coefficients, and the faster
+ * diffusion-error convergence.  A and B have a pole at omega1 = omega2.    */
 void orc_k17_coefficients(double w1, double w2, double* out /* w3,w4,w5,A,B */) {
   out[0] = 8.0 * (w1 - 2.0) * (w2 * (3.0 * w1 - 1.0) - 5.0 * w1)
          / (8.0 * (5.0 - 2.0 * w1) * w1 + w2 * (8.0 + w1 * (9.0 * w1 - 26.0)));

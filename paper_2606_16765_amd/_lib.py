@@ -24,6 +24,9 @@ class LbmParams(ctypes.Structure):
         ("snap_start", ctypes.c_int64),
         ("force_every", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
         ("perturb_seed", ctypes.c_uint64), ("perturb_amp", ctypes.c_double),
+        ("re", ctypes.c_double), ("l_ref", ctypes.c_double),
+        ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("force_capacity", ctypes.c_int64),
     ]
 
 
@@ -39,6 +42,8 @@ def _sig(L):
     P = ctypes.POINTER
     L.lbm_default_params.argtypes = [P(LbmParams), i32, i32, i32]
     L.lbm_create.argtypes = [P(LbmParams), vp, i64, vp, vp, vp, vp, vp, P(vp)]
+    L.lbm_workspace_size.argtypes = [P(LbmParams), vp, P(ctypes.c_size_t)]
+    L.lbm_create_in.argtypes = [P(LbmParams), vp, i64, vp, vp, vp, vp, vp, ctypes.c_size_t, vp, P(vp)]
     L.lbm_step.argtypes = [vp, i64]
     L.lbm_mean_fields.argtypes = [vp, vp, ctypes.c_int, P(i64)]
     L.lbm_mean_fields_pooled.argtypes = [vp, i32, i32, vp]

@@ -61,6 +61,7 @@ struct StepArgs {
   int32_t obox[6];          // tile box (x0, x1, y0, y1, z0, z1) around the obstacle
   uint64_t perturb_seed;    // device-generated initial perturbation
   double perturb_amp;
+  int32_t* chk;             // stability flag, set on a check step (null: no check)
 };
 
 struct Coefs {
@@ -262,6 +263,13 @@ __device__ __forceinline__ void cell_update(const StepArgs& a, const Coef<typena
     a.acc[N + n] += (double)uy;
     a.acc[2 * N + n] += (double)uz;
     a.acc[3 * N + n] += (double)drho * (1.0 / 3.0);
+  }
+  if (a.chk) {
+    // a cell whose density left (0, 2) or whose speed reached the lattice
+    // sound speed (or any non-finite value: every comparison fails) marks
+    // the run as unstable
+    const T usq = ux * ux + uy * uy + uz * uz;
+    if (!(usq < T(1.0 / 3.0) && drho > T(-1) && drho < T(1))) *a.chk = 1;
   }
   if (a.snap) {
     const int64_t N = (int64_t)a.nx * a.ny * a.nz;
@@ -698,6 +706,8 @@ struct lbm_sim {
   StepArgs args{};
   Coefs coefs{};
   int64_t pop_elems = 0;
+  char* block = nullptr;     // device memory of the solver (see Layout)
+  bool owns_block = false;   // false: the caller's workspace
   void* A = nullptr;
   uint8_t* d_flag = nullptr;
   int32_t* d_brow = nullptr;
@@ -709,6 +719,7 @@ struct lbm_sim {
   double* d_fpart = nullptr;
   double fconst[3] = {0, 0, 0};
   double* d_forces = nullptr;
+  bool force_ring = false;   // true: the last force_cap samples, in the block
   int64_t force_cap = 0, nforces = 0;
   std::vector<int64_t> force_steps;
   double* d_acc = nullptr;
@@ -716,6 +727,8 @@ struct lbm_sim {
   float* d_snap = nullptr;
   int64_t snap_taken = 0;
   std::vector<int64_t> snap_steps;
+  int32_t* d_chk = nullptr;  // stability flag written by check steps
+  int32_t* h_chk = nullptr;  // its pinned host copy, refreshed after each check step
   int64_t steps = 0;
   int parity = 0;   // AA parity of the stored layout: 0 natural, 1 swapped
   int sticky = 0;
@@ -910,10 +923,12 @@ static void launch_import(int storage, const StepArgs& a, const double* pops, hi
 }
 
 static void free_all(lbm_sim* s) {
-  void* ptrs[] = {s->A, s->d_flag, s->d_brow, s->d_bmask, s->d_bq, s->d_bslot, s->d_fpart, s->d_forces, s->d_acc,
-                  s->d_snap};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+  if (s->block && s->owns_block) (void)hipFree(s->block);
+  s->block = nullptr;
+  if (s->d_forces && !s->force_ring) (void)hipFree(s->d_forces);
+  s->d_forces = nullptr;
+  if (s->h_chk) (void)hipHostFree(s->h_chk);
+  s->h_chk = nullptr;
   for (auto& e : s->events) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
@@ -921,62 +936,83 @@ static void free_all(lbm_sim* s) {
   s->events.clear();
 }
 
-extern "C" int lbm_create(const lbm_params* pin, const uint8_t* solid, int64_t nlinks, const int64_t* link_cell,
-                          const uint8_t* link_dir, const double* link_q, const double* u0, void* hip_stream,
-                          lbm_sim** out) {
-  if (!pin || !out) return fail(nullptr, LBM_EINVAL, "null argument");
-  *out = nullptr;
-  const lbm_params& p = *pin;
+// Parameters resolved from lbm_params: viscosity (from re and l_ref when
+// re > 0, paper Sec. 3.1: Re set through the lattice viscosity), omega1,
+// collision mode (paper Sec. 3.2: the fourth-order mode off below Re_c 3000)
+// and the fourth-order rates.  Rejects what the step cannot run.
+struct Resolved {
+  double nu = 0, omega1 = 0;
+  int mode = 0;
+  double k17[5] = {0, 0, 0, 0, 0};
+  int64_t N = 0, pitch = 0, slotp = 0, zstride = 0, pop_elems = 0, ntiles = 0;
+};
+
+static int resolve(const lbm_params& p, Resolved& r) {
   if (p.nx <= 0 || p.ny <= 0 || p.nz <= 0 || p.nx % TX || p.ny % TY)
     return fail(nullptr, LBM_EINVAL, "grid must have nx % 64 == 0 and ny % 2 == 0");
   if (storage_size(p.storage) == 0) return fail(nullptr, LBM_EINVAL, "unknown storage type");
-  if (!(p.nu > 0.0) || !std::isfinite(p.nu)) return fail(nullptr, LBM_EINVAL, "viscosity must be positive");
+  if (p.re > 0.0) {
+    if (!(p.u_in > 0.0) || !std::isfinite(p.re)) return fail(nullptr, LBM_EINVAL, "re needs u_in > 0");
+    r.nu = p.u_in * (p.l_ref > 0.0 ? p.l_ref : (double)p.ny) / p.re;
+  } else {
+    r.nu = p.nu;
+  }
+  if (!(r.nu > 0.0) || !std::isfinite(r.nu)) return fail(nullptr, LBM_EINVAL, "viscosity must be positive");
   if (!(p.omega2 > 0.0 && p.omega2 < 2.0)) return fail(nullptr, LBM_EINVAL, "omega2 must be in (0, 2)");
-  if (p.snap_every < 0 || p.snap_count < 0 || p.force_every < 0) return fail(nullptr, LBM_EINVAL, "negative period");
+  if (p.snap_every < 0 || p.snap_count < 0 || p.force_every < 0 || p.check_every < 0 || p.force_capacity < 0)
+    return fail(nullptr, LBM_EINVAL, "negative period or capacity");
   if (p.snap_every > 0 && p.snap_count <= 0) return fail(nullptr, LBM_EINVAL, "snap_count must be positive");
-  if (nlinks < 0 || (nlinks > 0 && (!link_cell || !link_dir || !link_q)))
-    return fail(nullptr, LBM_EINVAL, "bad link arrays");
-  const int64_t N = (int64_t)p.nx * p.ny * p.nz;
-  const int64_t pitch = (int64_t)p.nx + 64;
-  const int64_t slotp = pitch * (p.ny + 2);
-  const int64_t zstride = 27 * slotp;
-  const int64_t pop_elems = zstride * (p.nz + 2);
-  if (3 * zstride * (int64_t)storage_size(p.storage) >= (int64_t(1) << 31) || N >= (int64_t(1) << 31))
+  r.omega1 = 1.0 / (3.0 * r.nu + 0.5);
+  const double re_c = p.u_in * p.ny / r.nu;
+  r.mode = p.mode == LBM_MODE_AUTO ? (re_c >= 3000.0 ? 1 : 0) : (p.mode ? 1 : 0);
+  k17_rates(r.omega1, p.omega2, r.k17);
+  if (r.mode == 1) {
+    // A and B carry 1/(omega1 - omega2), and the rates have poles of their
+    // own; the third-order rates must be relaxation rates in (0, 2)
+    bool ok = std::fabs(r.omega1 - p.omega2) >= 1e-3;
+    for (int i = 0; i < 3; ++i) ok = ok && r.k17[i] > 0.0 && r.k17[i] < 2.0;
+    ok = ok && std::isfinite(r.k17[3]) && std::isfinite(r.k17[4]);
+    if (!ok)
+      return fail(nullptr, LBM_EINVAL,
+                  "fourth-order mode undefined at this omega1: needs |omega1 - omega2| >= 1e-3 and rates "
+                  "omega3..5 in (0, 2)");
+  }
+  r.N = (int64_t)p.nx * p.ny * p.nz;
+  r.pitch = (int64_t)p.nx + 64;
+  r.slotp = r.pitch * (p.ny + 2);
+  r.zstride = 27 * r.slotp;
+  r.pop_elems = r.zstride * (p.nz + 2);
+  if (3 * r.zstride * (int64_t)storage_size(p.storage) >= (int64_t(1) << 31) || r.N >= (int64_t(1) << 31))
     return fail(nullptr, LBM_EINVAL, "grid too large (three padded planes must stay below 2 GiB)");
-  const int64_t ntiles = (int64_t)(p.nx / TX) * (p.ny / TY) * p.nz;
-  if (ntiles >= (int64_t(1) << 31)) return fail(nullptr, LBM_EINVAL, "too many tiles");
+  r.ntiles = (int64_t)(p.nx / TX) * (p.ny / TY) * p.nz;
+  if (r.ntiles >= (int64_t(1) << 31)) return fail(nullptr, LBM_EINVAL, "too many tiles");
+  return LBM_OK;
+}
 
-  lbm_sim* s = new (std::nothrow) lbm_sim();
-  if (!s) return fail(nullptr, LBM_ENOMEM, "host allocation failed");
-  s->p = p;
-  s->N = N;
-  s->esize = storage_size(p.storage);
-  s->stream = (hipStream_t)hip_stream;
-  s->omega1 = 1.0 / (3.0 * p.nu + 0.5);
-  const double re_c = p.u_in * p.ny / p.nu;
-  s->mode = p.mode == LBM_MODE_AUTO ? (re_c >= 3000.0 ? 1 : 0) : (p.mode ? 1 : 0);
-  (void)hipGetDevice(&s->device);
-  auto bail = [&](int code) {
-    free_all(s);
-    delete s;
-    return code;
-  };
-
-  // ---- obstacle tables from the solid mask (authoritative) ----
-  std::vector<uint64_t> pairs;  // (cell << 5) | j : cell + c_j is obstacle
+// Obstacle tables from the solid mask (host, once): boundary cells (fluid
+// cells with a link into the obstacle) in ascending order with their link
+// masks, the constant weight part of the momentum exchange, the solid-cell
+// box and the force slot of every tile holding a boundary cell.
+struct Tables {
+  std::vector<int64_t> rcell;
+  std::vector<uint32_t> rmask;
   double fc[3] = {0, 0, 0};
-  int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {-1, -1, -1};  // solid-cell box
+  int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {-1, -1, -1};
+  std::vector<int32_t> bslot;
+  int32_t nslots = 0;
+};
+
+static int build_tables(const lbm_params& p, const Resolved& r, const uint8_t* solid, Tables& t) {
+  std::vector<uint64_t> pairs;  // (cell << 5) | j : cell + c_j is obstacle
   if (solid) {
-    for (int64_t n = 0; n < N; ++n) {
+    for (int64_t n = 0; n < r.N; ++n) {
       if (!solid[n]) continue;
       const int x = (int)(n % p.nx), y = (int)((n / p.nx) % p.ny), z = (int)(n / ((int64_t)p.nx * p.ny));
-      lo[0] = std::min(lo[0], x); hi[0] = std::max(hi[0], x);
-      lo[1] = std::min(lo[1], y); hi[1] = std::max(hi[1], y);
-      lo[2] = std::min(lo[2], z); hi[2] = std::max(hi[2], z);
-      if (!p.periodic[0] && (x < 3 || x > p.nx - 4)) {
-        fail(nullptr, LBM_EINVAL, "obstacle must keep 3 cells clear of inlet and outlet");
-        return bail(LBM_EINVAL);
-      }
+      t.lo[0] = std::min(t.lo[0], x); t.hi[0] = std::max(t.hi[0], x);
+      t.lo[1] = std::min(t.lo[1], y); t.hi[1] = std::max(t.hi[1], y);
+      t.lo[2] = std::min(t.lo[2], z); t.hi[2] = std::max(t.hi[2], z);
+      if (!p.periodic[0] && (x < 3 || x > p.nx - 4))
+        return fail(nullptr, LBM_EINVAL, "obstacle must keep 3 cells clear of inlet and outlet");
       for (int j = 0; j < 27; ++j) {
         if (j == 13) continue;
         int fx = x - cx(j), fy = y - cy(j), fz = z - cz(j);
@@ -990,21 +1026,113 @@ extern "C" int lbm_create(const lbm_params* pin, const uint8_t* solid, int64_t n
     }
   }
   std::sort(pairs.begin(), pairs.end());
-  std::vector<int64_t> rcell;
-  std::vector<uint32_t> rmask;
   for (uint64_t pr : pairs) {
     const int64_t cell = (int64_t)(pr >> 5);
     const int j = (int)(pr & 31);
-    if (rcell.empty() || rcell.back() != cell) {
-      rcell.push_back(cell);
-      rmask.push_back(0);
+    if (t.rcell.empty() || t.rcell.back() != cell) {
+      t.rcell.push_back(cell);
+      t.rmask.push_back(0);
     }
-    rmask.back() |= 1u << j;
-    fc[0] += 2.0 * wgt(j) * cx(j);
-    fc[1] += 2.0 * wgt(j) * cy(j);
-    fc[2] += 2.0 * wgt(j) * cz(j);
+    t.rmask.back() |= 1u << j;
+    t.fc[0] += 2.0 * wgt(j) * cx(j);
+    t.fc[1] += 2.0 * wgt(j) * cy(j);
+    t.fc[2] += 2.0 * wgt(j) * cz(j);
   }
-  s->nb = (int64_t)rcell.size();
+  const int tiles_x = p.nx / TX, tiles_y = p.ny / TY;
+  if (p.force_every > 0 && !t.rcell.empty()) {
+    t.bslot.assign((size_t)r.ntiles, -1);
+    for (int64_t cell : t.rcell) {
+      const int x = (int)(cell % p.nx), y = (int)((cell / p.nx) % p.ny), z = (int)(cell / ((int64_t)p.nx * p.ny));
+      const int64_t tt = ((int64_t)z * tiles_y + y / TY) * tiles_x + x / TX;
+      if (t.bslot[(size_t)tt] < 0) t.bslot[(size_t)tt] = t.nslots++;
+    }
+  }
+  return LBM_OK;
+}
+
+// Device memory of one solver: one block carved into 256-byte aligned
+// regions (populations, cell flags, boundary rows, link masks, wall
+// distances, force slots and partials, FP64 accumulators, snapshot ring,
+// force ring, stability flag).
+struct Layout {
+  size_t A = 0, flag = 0, brow = 0, bmask = 0, bq = 0, bslot = 0, fpart = 0, acc = 0, snap = 0, forces = 0, chk = 0;
+  size_t total = 0;
+};
+
+static Layout make_layout(const lbm_params& p, const Resolved& r, const Tables& t) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  };
+  const int64_t nb = std::max<int64_t>((int64_t)t.rcell.size(), 1);
+  L.A = take((size_t)r.pop_elems * storage_size(p.storage));
+  L.flag = take((size_t)r.N);
+  L.brow = take((size_t)r.N * 4);
+  L.bmask = take((size_t)nb * 4);
+  L.bq = take((size_t)nb * 27 * 8);
+  L.bslot = take(t.nslots > 0 ? (size_t)r.ntiles * 4 : 0);
+  L.fpart = take((size_t)t.nslots * 24);
+  L.acc = take(p.avg_start >= 0 ? (size_t)r.N * 32 : 0);
+  L.snap = take(p.snap_every > 0 ? (size_t)p.snap_count * r.N * 16 : 0);
+  L.forces = take(p.force_capacity > 0 && t.nslots > 0 ? (size_t)p.force_capacity * 24 : 0);
+  L.chk = take(4);
+  L.total = off;
+  return L;
+}
+
+extern "C" int lbm_workspace_size(const lbm_params* pin, const uint8_t* solid, size_t* bytes) {
+  if (!pin || !bytes) return fail(nullptr, LBM_EINVAL, "null argument");
+  Resolved r;
+  int rc = resolve(*pin, r);
+  if (rc) return rc;
+  Tables t;
+  if ((rc = build_tables(*pin, r, solid, t))) return rc;
+  *bytes = make_layout(*pin, r, t).total;
+  return LBM_OK;
+}
+
+extern "C" int lbm_create_in(const lbm_params* pin, const uint8_t* solid, int64_t nlinks, const int64_t* link_cell,
+                             const uint8_t* link_dir, const double* link_q, const double* u0, void* d_workspace,
+                             size_t workspace_bytes, void* hip_stream, lbm_sim** out) {
+  if (!pin || !out) return fail(nullptr, LBM_EINVAL, "null argument");
+  *out = nullptr;
+  const lbm_params& p = *pin;
+  Resolved r;
+  int rc = resolve(p, r);
+  if (rc) return rc;
+  if (nlinks < 0 || (nlinks > 0 && (!link_cell || !link_dir || !link_q)))
+    return fail(nullptr, LBM_EINVAL, "bad link arrays");
+  if (d_workspace && ((uintptr_t)d_workspace & 255))
+    return fail(nullptr, LBM_EINVAL, "workspace must be 256-byte aligned");
+  Tables t;
+  if ((rc = build_tables(p, r, solid, t))) return rc;
+  if (d_workspace && p.force_every > 0 && !t.rcell.empty() && p.force_capacity <= 0)
+    return fail(nullptr, LBM_EINVAL, "a caller workspace needs force_capacity > 0 (the force series is a ring in it)");
+  const Layout lay = make_layout(p, r, t);
+  if (d_workspace && workspace_bytes < lay.total)
+    return fail(nullptr, LBM_EINVAL, "workspace smaller than lbm_workspace_size");
+  const int64_t N = r.N;
+
+  lbm_sim* s = new (std::nothrow) lbm_sim();
+  if (!s) return fail(nullptr, LBM_ENOMEM, "host allocation failed");
+  s->p = p;
+  s->p.nu = r.nu;
+  s->N = N;
+  s->esize = storage_size(p.storage);
+  s->stream = (hipStream_t)hip_stream;
+  s->omega1 = r.omega1;
+  s->mode = r.mode;
+  (void)hipGetDevice(&s->device);
+  auto bail = [&](int code) {
+    free_all(s);
+    delete s;
+    return code;
+  };
+
+  s->nb = (int64_t)t.rcell.size();
   std::vector<double> rq((size_t)std::max<int64_t>(s->nb, 1) * 27, 0.5);
   for (int64_t k = 0; k < nlinks; ++k) {
     const int64_t cell = link_cell[k];
@@ -1018,32 +1146,45 @@ extern "C" int lbm_create(const lbm_params* pin, const uint8_t* solid, int64_t n
       fail(nullptr, LBM_EINVAL, "wall distance fraction must be in (0, 1]");
       return bail(LBM_EINVAL);
     }
-    auto it = std::lower_bound(rcell.begin(), rcell.end(), cell);
-    if (it != rcell.end() && *it == cell) rq[(size_t)(it - rcell.begin()) * 27 + j] = q;
+    auto it = std::lower_bound(t.rcell.begin(), t.rcell.end(), cell);
+    if (it != t.rcell.end() && *it == cell) rq[(size_t)(it - t.rcell.begin()) * 27 + j] = q;
   }
-  s->fconst[0] = fc[0]; s->fconst[1] = fc[1]; s->fconst[2] = fc[2];
+  for (int d = 0; d < 3; ++d) s->fconst[d] = t.fc[d];
+  s->nslots = t.nslots;
 
-  // force slots: tiles containing boundary rows
-  const int tiles_x = p.nx / TX, tiles_y = p.ny / TY;
-  std::vector<int32_t> bslot;
-  if (p.force_every > 0 && s->nb > 0) {
-    bslot.assign((size_t)ntiles, -1);
-    int32_t ns = 0;
-    for (int64_t cell : rcell) {
-      const int x = (int)(cell % p.nx), y = (int)((cell / p.nx) % p.ny), z = (int)(cell / ((int64_t)p.nx * p.ny));
-      const int64_t t = ((int64_t)z * tiles_y + y / TY) * tiles_x + x / TX;
-      if (bslot[(size_t)t] < 0) bslot[(size_t)t] = ns++;
-    }
-    s->nslots = ns;
-  }
-
-  // ---- device memory ----
+  // ---- device memory: one block, the caller's or the library's ----
   hipError_t e = hipSuccess;
-  const size_t popbytes = (size_t)pop_elems * s->esize;
-  s->pop_elems = pop_elems;
-  if ((e = hipMalloc(&s->A, popbytes)) != hipSuccess) {
-    fail(nullptr, e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "population allocation failed");
-    return bail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE);
+  if (d_workspace) {
+    s->block = (char*)d_workspace;
+    s->owns_block = false;
+  } else {
+    if ((e = hipMalloc((void**)&s->block, lay.total)) != hipSuccess) {
+      fail(nullptr, e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "device allocation failed");
+      return bail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE);
+    }
+    s->owns_block = true;
+  }
+  if ((e = hipHostMalloc((void**)&s->h_chk, sizeof(int32_t), hipHostMallocDefault)) != hipSuccess) {
+    fail(nullptr, LBM_ENOMEM, "pinned host allocation failed");
+    return bail(LBM_ENOMEM);
+  }
+  *s->h_chk = 0;
+  char* B = s->block;
+  s->A = B + lay.A;
+  s->pop_elems = r.pop_elems;
+  s->d_flag = (uint8_t*)(B + lay.flag);
+  s->d_brow = (int32_t*)(B + lay.brow);
+  s->d_bmask = (uint32_t*)(B + lay.bmask);
+  s->d_bq = (double*)(B + lay.bq);
+  s->d_bslot = s->nslots > 0 ? (int32_t*)(B + lay.bslot) : nullptr;
+  s->d_fpart = s->nslots > 0 ? (double*)(B + lay.fpart) : nullptr;
+  s->d_acc = p.avg_start >= 0 ? (double*)(B + lay.acc) : nullptr;
+  s->d_snap = p.snap_every > 0 ? (float*)(B + lay.snap) : nullptr;
+  s->d_chk = (int32_t*)(B + lay.chk);
+  if (p.force_capacity > 0 && s->nslots > 0) {
+    s->force_ring = true;
+    s->d_forces = (double*)(B + lay.forces);
+    s->force_cap = p.force_capacity;
   }
   auto dalloc = [&](void** ptr, size_t bytes) -> bool {
     hipError_t ee = hipMalloc(ptr, bytes);
@@ -1053,13 +1194,10 @@ extern "C" int lbm_create(const lbm_params* pin, const uint8_t* solid, int64_t n
     }
     return true;
   };
-  if (!dalloc((void**)&s->d_flag, (size_t)N) || !dalloc((void**)&s->d_brow, (size_t)N * 4) ||
-      !dalloc((void**)&s->d_bmask, (size_t)std::max<int64_t>(s->nb, 1) * 4) ||
-      !dalloc((void**)&s->d_bq, (size_t)std::max<int64_t>(s->nb, 1) * 27 * 8))
-    return bail(LBM_ENOMEM);
   hipStream_t st = s->stream;
-  (void)hipMemsetAsync(s->A, 0, popbytes, st);
+  (void)hipMemsetAsync(s->A, 0, (size_t)r.pop_elems * s->esize, st);
   (void)hipMemsetAsync(s->d_brow, 0xff, (size_t)N * 4, st);
+  (void)hipMemsetAsync(s->d_chk, 0, sizeof(int32_t), st);
   if (solid) {
     // flags: 2 solid, 0 fluid; the scatter kernel below marks boundary rows 1
     std::vector<uint8_t> fl(solid, solid + N);
@@ -1072,63 +1210,51 @@ extern "C" int lbm_create(const lbm_params* pin, const uint8_t* solid, int64_t n
   if (s->nb > 0) {
     int64_t* d_cells = nullptr;
     if (!dalloc((void**)&d_cells, (size_t)s->nb * 8)) return bail(LBM_ENOMEM);
-    (void)hipMemcpyAsync(d_cells, rcell.data(), (size_t)s->nb * 8, hipMemcpyHostToDevice, st);
-    (void)hipMemcpyAsync(s->d_bmask, rmask.data(), (size_t)s->nb * 4, hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(d_cells, t.rcell.data(), (size_t)s->nb * 8, hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(s->d_bmask, t.rmask.data(), (size_t)s->nb * 4, hipMemcpyHostToDevice, st);
     (void)hipMemcpyAsync(s->d_bq, rq.data(), (size_t)s->nb * 27 * 8, hipMemcpyHostToDevice, st);
     hipLaunchKernelGGL(scatter_rows_kernel, dim3((unsigned)((s->nb + 255) / 256)), dim3(256), 0, st, d_cells, s->nb,
                        s->d_flag, s->d_brow);
     (void)hipStreamSynchronize(st);
     (void)hipFree(d_cells);
   }
-  if (s->nslots > 0) {
-    if (!dalloc((void**)&s->d_bslot, (size_t)ntiles * 4) || !dalloc((void**)&s->d_fpart, (size_t)s->nslots * 24))
-      return bail(LBM_ENOMEM);
-    (void)hipMemcpyAsync(s->d_bslot, bslot.data(), (size_t)ntiles * 4, hipMemcpyHostToDevice, st);
-  }
-  if (p.avg_start >= 0) {
-    if (!dalloc((void**)&s->d_acc, (size_t)N * 32)) return bail(LBM_ENOMEM);
-    (void)hipMemsetAsync(s->d_acc, 0, (size_t)N * 32, st);
-  }
-  if (p.snap_every > 0) {
-    if (!dalloc((void**)&s->d_snap, (size_t)p.snap_count * N * 16)) return bail(LBM_ENOMEM);
-    (void)hipMemsetAsync(s->d_snap, 0, (size_t)p.snap_count * N * 16, st);
-  }
+  if (s->nslots > 0)
+    (void)hipMemcpyAsync(s->d_bslot, t.bslot.data(), (size_t)r.ntiles * 4, hipMemcpyHostToDevice, st);
+  if (s->d_acc) (void)hipMemsetAsync(s->d_acc, 0, (size_t)N * 32, st);
+  if (s->d_snap) (void)hipMemsetAsync(s->d_snap, 0, (size_t)p.snap_count * N * 16, st);
 
   StepArgs& a = s->args;
   a.A = s->A;
   a.nx = p.nx; a.ny = p.ny; a.nz = p.nz;
-  a.pitch = (int32_t)pitch;
-  a.slotp = (int32_t)slotp;
-  a.zstride = (int32_t)zstride;
+  a.pitch = (int32_t)r.pitch;
+  a.slotp = (int32_t)r.slotp;
+  a.zstride = (int32_t)r.zstride;
   for (int d = 0; d < 3; ++d) a.per[d] = p.periodic[d] ? 1 : 0;
   a.flag = s->d_flag;
   a.brow = s->d_brow;
   a.bmask = s->d_bmask;
   a.bq = s->d_bq;
   a.interp = p.obstacle_bc == 1 ? 1 : 0;
-  {
-    double co[5];
-    k17_rates(s->omega1, p.omega2, co);
-    fill_coef(s->coefs.f, s->omega1, p.omega2, p.galilean, p.lambda, co, p.body_force, p.u_in);
-    fill_coef(s->coefs.d, s->omega1, p.omega2, p.galilean, p.lambda, co, p.body_force, p.u_in);
-  }
+  fill_coef(s->coefs.f, s->omega1, p.omega2, p.galilean, p.lambda, r.k17, p.body_force, p.u_in);
+  fill_coef(s->coefs.d, s->omega1, p.omega2, p.galilean, p.lambda, r.k17, p.body_force, p.u_in);
   a.acc = nullptr;
   a.snap = nullptr;
   a.bslot = nullptr;
+  a.chk = nullptr;
   a.fpart = s->d_fpart;
-  a.tiles_x = tiles_x;
-  a.tiles_y = tiles_y;
-  a.ntiles = (int32_t)ntiles;
+  a.tiles_x = p.nx / TX;
+  a.tiles_y = p.ny / TY;
+  a.ntiles = (int32_t)r.ntiles;
   a.remap = p.xcd_remap ? 1 : 0;
   // tile box around the obstacle: solid cells dilated by two cells (their
   // fluid neighbours and the cells behind them); on a periodic axis a box
   // that reaches a face covers the whole axis
-  if (hi[0] < 0) {
+  if (t.hi[0] < 0) {
     a.obox[0] = 1; a.obox[1] = 0; a.obox[2] = 1; a.obox[3] = 0; a.obox[4] = 1; a.obox[5] = 0;
   } else {
     const int ext[3] = {p.nx, p.ny, p.nz}, tsz[3] = {TX, TY, 1};
     for (int d = 0; d < 3; ++d) {
-      int b0 = lo[d] - 2, b1 = hi[d] + 2;
+      int b0 = t.lo[d] - 2, b1 = t.hi[d] + 2;
       if (p.periodic[d] && (b0 < 0 || b1 > ext[d] - 1)) {
         b0 = 0;
         b1 = ext[d] - 1;
@@ -1158,8 +1284,14 @@ extern "C" int lbm_create(const lbm_params* pin, const uint8_t* solid, int64_t n
   return LBM_OK;
 }
 
+extern "C" int lbm_create(const lbm_params* p, const uint8_t* solid, int64_t nlinks, const int64_t* link_cell,
+                          const uint8_t* link_dir, const double* link_q, const double* u0, void* hip_stream,
+                          lbm_sim** out) {
+  return lbm_create_in(p, solid, nlinks, link_cell, link_dir, link_q, u0, nullptr, 0, hip_stream, out);
+}
+
 static int ensure_force_cap(lbm_sim* s, int64_t need) {
-  if (need <= s->force_cap) return LBM_OK;
+  if (s->force_ring || need <= s->force_cap) return LBM_OK;
   int64_t cap = std::max<int64_t>(need, 2 * s->force_cap);
   cap = std::max<int64_t>(cap, 1024);
   double* nb = nullptr;
@@ -1174,9 +1306,23 @@ static int ensure_force_cap(lbm_sim* s, int64_t need) {
   return LBM_OK;
 }
 
+// Stability state: the flag a check step set, as last copied to the host.
+static int unstable(lbm_sim* s) {
+  if (s->h_chk && *(volatile int32_t*)s->h_chk)
+    return fail(s, LBM_EUNSTABLE, "a check step found a cell with non-finite, out-of-range density or velocity");
+  return LBM_OK;
+}
+
+static int guard(lbm_sim* s) {
+  if (s->sticky) return s->sticky;
+  return unstable(s);
+}
+
+// One time step of the method (paper Sec. 3.1-3.2: stream and collide with
+// the channel's boundary rules; Sec. 2: mean fields, snapshots, forces).
 extern "C" int lbm_step(lbm_sim* s, int64_t nsteps) {
   if (!s) return fail(nullptr, LBM_EINVAL, "null object");
-  if (s->sticky) return s->sticky;
+  if (int rc = guard(s)) return rc;
   if (nsteps < 0) return fail(s, LBM_EINVAL, "negative step count");
   const lbm_params& p = s->p;
   if (p.force_every > 0 && s->nslots > 0) {
@@ -1200,6 +1346,8 @@ extern "C" int lbm_step(lbm_sim* s, int64_t nsteps) {
     }
     const bool do_force = p.force_every > 0 && s->nslots > 0 && n % p.force_every == 0;
     if (do_force) a.bslot = s->d_bslot;
+    const bool do_chk = p.check_every > 0 && (n + 1) % p.check_every == 0;
+    if (do_chk) a.chk = s->d_chk;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (s->profiling) {
       HIPCHK(s, hipEventCreate(&e0));
@@ -1211,11 +1359,15 @@ extern "C" int lbm_step(lbm_sim* s, int64_t nsteps) {
       HIPCHK(s, hipEventRecord(e1, s->stream));
       s->events.emplace_back(e0, e1);
     }
+    if (do_chk)
+      HIPCHK(s, hipMemcpyAsync(s->h_chk, s->d_chk, sizeof(int32_t), hipMemcpyDeviceToHost, s->stream));
     if (do_force) {
+      const int64_t slot = s->force_ring ? s->nforces % s->force_cap : s->nforces;
       hipLaunchKernelGGL(force_reduce_kernel, dim3(1), dim3(256), 0, s->stream, s->d_fpart, s->nslots, s->fconst[0],
-                         s->fconst[1], s->fconst[2], s->d_forces + 3 * s->nforces);
+                         s->fconst[1], s->fconst[2], s->d_forces + 3 * slot);
+      if (s->force_ring && (int64_t)s->force_steps.size() == s->force_cap) s->force_steps[(size_t)slot] = n;
+      else s->force_steps.push_back(n);
       s->nforces++;
-      s->force_steps.push_back(n);
     }
     s->steps++;
     s->parity ^= 1;
@@ -1227,7 +1379,7 @@ extern "C" int lbm_step(lbm_sim* s, int64_t nsteps) {
 
 extern "C" int lbm_mean_fields(lbm_sim* s, double* out, int out_on_device, int64_t* nsamples) {
   if (!s || !out) return fail(s, LBM_EINVAL, "null argument");
-  if (s->sticky) return s->sticky;
+  if (int rc = guard(s)) return rc;
   if (!s->d_acc) return fail(s, LBM_ESTATE, "averaging is off (avg_start < 0)");
   const int64_t N = s->N;
   double* dst = out;
@@ -1251,7 +1403,7 @@ extern "C" int lbm_mean_fields(lbm_sim* s, double* out, int out_on_device, int64
 
 extern "C" int lbm_mean_fields_pooled(lbm_sim* s, int32_t factor, int32_t quarter_turns, float* d_out) {
   if (!s || !d_out) return fail(s, LBM_EINVAL, "null argument");
-  if (s->sticky) return s->sticky;
+  if (int rc = guard(s)) return rc;
   if (!s->d_acc) return fail(s, LBM_ESTATE, "averaging is off (avg_start < 0)");
   const int nx = s->p.nx, ny = s->p.ny, nz = s->p.nz;
   if (factor < 1 || nx % factor || ny % factor || nz % factor)
@@ -1270,7 +1422,7 @@ extern "C" int lbm_mean_fields_pooled(lbm_sim* s, int32_t factor, int32_t quarte
 
 extern "C" int lbm_snapshots(lbm_sim* s, float* out, int out_on_device, int32_t* k, int64_t* steps) {
   if (!s || !k) return fail(s, LBM_EINVAL, "null argument");
-  if (s->sticky) return s->sticky;
+  if (int rc = guard(s)) return rc;
   const int64_t taken = s->snap_taken;
   const int64_t cnt = std::min<int64_t>(taken, s->p.snap_count);
   *k = (int32_t)cnt;
@@ -1289,21 +1441,33 @@ extern "C" int lbm_snapshots(lbm_sim* s, float* out, int out_on_device, int32_t*
 
 extern "C" int lbm_forces(lbm_sim* s, double* fxyz, int64_t cap, int64_t* n, int64_t* steps) {
   if (!s || !n) return fail(s, LBM_EINVAL, "null argument");
-  if (s->sticky) return s->sticky;
-  *n = s->nforces;
-  const int64_t m = std::min(cap, s->nforces);
+  if (int rc = guard(s)) return rc;
+  // retained samples: all of them, or the last force_cap of a ring
+  const int64_t kept = s->force_ring ? std::min(s->nforces, s->force_cap) : s->nforces;
+  const int64_t first = s->nforces - kept;  // sample index of the oldest kept
+  *n = kept;
+  const int64_t m = std::min(cap, kept);
   if (fxyz && m > 0) {
-    HIPCHK(s, hipMemcpyAsync(fxyz, s->d_forces, (size_t)m * 24, hipMemcpyDeviceToHost, s->stream));
+    int64_t j = 0;
+    while (j < m) {
+      // contiguous run of ring slots starting at the slot of sample first + j
+      const int64_t slot = s->force_ring ? (first + j) % s->force_cap : first + j;
+      const int64_t run = std::min(m - j, s->force_ring ? s->force_cap - slot : m - j);
+      HIPCHK(s, hipMemcpyAsync(fxyz + 3 * j, s->d_forces + 3 * slot, (size_t)run * 24, hipMemcpyDeviceToHost,
+                               s->stream));
+      j += run;
+    }
     HIPCHK(s, hipStreamSynchronize(s->stream));
   }
   if (steps)
-    for (int64_t j = 0; j < m; ++j) steps[j] = s->force_steps[(size_t)j];
+    for (int64_t j = 0; j < m; ++j)
+      steps[j] = s->force_steps[(size_t)(s->force_ring ? (first + j) % s->force_cap : first + j)];
   return LBM_OK;
 }
 
 extern "C" int lbm_moments(lbm_sim* s, float* out, int out_on_device) {
   if (!s || !out) return fail(s, LBM_EINVAL, "null argument");
-  if (s->sticky) return s->sticky;
+  if (int rc = guard(s)) return rc;
   float* dst = out;
   float* tmp = nullptr;
   if (!out_on_device) {
@@ -1320,7 +1484,7 @@ extern "C" int lbm_moments(lbm_sim* s, float* out, int out_on_device) {
 
 extern "C" int lbm_get_populations(lbm_sim* s, double* fbar) {
   if (!s || !fbar) return fail(s, LBM_EINVAL, "null argument");
-  if (s->sticky) return s->sticky;
+  if (int rc = guard(s)) return rc;
   double* tmp = nullptr;
   HIPCHK(s, hipMalloc(&tmp, (size_t)s->N * 27 * 8));
   launch_export(s->p.storage, s->args, s->coefs, s->parity != 0, tmp, nullptr, nullptr, s->stream);
@@ -1334,7 +1498,7 @@ extern "C" int lbm_get_populations(lbm_sim* s, double* fbar) {
 extern "C" int lbm_get_populations_box(lbm_sim* s, int32_t x0, int32_t y0, int32_t z0, int32_t bx, int32_t by,
                                        int32_t bz, double* fbar) {
   if (!s || !fbar) return fail(s, LBM_EINVAL, "null argument");
-  if (s->sticky) return s->sticky;
+  if (int rc = guard(s)) return rc;
   if (bx <= 0 || by <= 0 || bz <= 0 || x0 < 0 || y0 < 0 || z0 < 0 || x0 > s->p.nx - bx || y0 > s->p.ny - by ||
       z0 > s->p.nz - bz)
     return fail(s, LBM_EINVAL, "box outside the grid");
@@ -1358,7 +1522,7 @@ extern "C" int lbm_get_populations_box(lbm_sim* s, int32_t x0, int32_t y0, int32
 
 extern "C" int lbm_set_populations(lbm_sim* s, const double* fbar) {
   if (!s || !fbar) return fail(s, LBM_EINVAL, "null argument");
-  if (s->sticky) return s->sticky;
+  if (int rc = guard(s)) return rc;
   double* tmp = nullptr;
   HIPCHK(s, hipMalloc(&tmp, (size_t)s->N * 27 * 8));
   hipError_t e = hipMemcpyAsync(tmp, fbar, (size_t)s->N * 27 * 8, hipMemcpyHostToDevice, s->stream);
@@ -1375,7 +1539,7 @@ extern "C" int lbm_set_populations(lbm_sim* s, const double* fbar) {
 
 extern "C" int lbm_mass(lbm_sim* s, double* mass) {
   if (!s || !mass) return fail(s, LBM_EINVAL, "null argument");
-  if (s->sticky) return s->sticky;
+  if (int rc = guard(s)) return rc;
   double* part = nullptr;
   const int nt = s->args.ntiles;
   HIPCHK(s, hipMalloc(&part, (size_t)nt * 8));
@@ -1398,20 +1562,22 @@ struct Blob {
   int32_t nx, ny, nz, storage;
   int64_t steps, nsamples, snap_taken, nforces, parity;
   int64_t popbytes, accbytes, snapbytes;
+  int64_t fstored;  // force slots stored: every sample, or the ring's filled slots in slot order
 };
 
 extern "C" int lbm_export_state(lbm_sim* s, void* blob, size_t cap, size_t* used) {
   if (!s || !used) return fail(s, LBM_EINVAL, "null argument");
-  if (s->sticky) return s->sticky;
+  if (int rc = guard(s)) return rc;
   Blob h{};
-  std::memcpy(h.magic, "MLBMCKP1", 8);
+  std::memcpy(h.magic, "MLBMCKP2", 8);
   h.nx = s->p.nx; h.ny = s->p.ny; h.nz = s->p.nz; h.storage = s->p.storage;
   h.steps = s->steps; h.nsamples = s->nsamples; h.snap_taken = s->snap_taken; h.nforces = s->nforces;
   h.parity = s->parity;
   h.popbytes = (int64_t)(s->pop_elems * (int64_t)s->esize);
   h.accbytes = s->d_acc ? s->N * 32 : 0;
   h.snapbytes = s->d_snap ? (int64_t)s->p.snap_count * s->N * 16 : 0;
-  const size_t need = sizeof(Blob) + h.popbytes + h.accbytes + h.snapbytes + (size_t)h.nforces * 32 +
+  h.fstored = (int64_t)s->force_steps.size();
+  const size_t need = sizeof(Blob) + h.popbytes + h.accbytes + h.snapbytes + (size_t)h.fstored * 32 +
                       s->snap_steps.size() * 8 + 8;
   *used = need;
   if (!blob) return LBM_OK;
@@ -1425,11 +1591,11 @@ extern "C" int lbm_export_state(lbm_sim* s, void* blob, size_t cap, size_t* used
   b += h.accbytes;
   if (h.snapbytes) HIPCHK(s, hipMemcpyAsync(b, s->d_snap, (size_t)h.snapbytes, hipMemcpyDeviceToHost, s->stream));
   b += h.snapbytes;
-  if (h.nforces) HIPCHK(s, hipMemcpyAsync(b, s->d_forces, (size_t)h.nforces * 24, hipMemcpyDeviceToHost, s->stream));
+  if (h.fstored) HIPCHK(s, hipMemcpyAsync(b, s->d_forces, (size_t)h.fstored * 24, hipMemcpyDeviceToHost, s->stream));
   HIPCHK(s, hipStreamSynchronize(s->stream));
-  b += h.nforces * 24;
-  std::memcpy(b, s->force_steps.data(), (size_t)h.nforces * 8);
-  b += h.nforces * 8;
+  b += h.fstored * 24;
+  std::memcpy(b, s->force_steps.data(), (size_t)h.fstored * 8);
+  b += h.fstored * 8;
   int64_t nss = (int64_t)s->snap_steps.size();
   std::memcpy(b, &nss, 8);
   b += 8;
@@ -1439,11 +1605,11 @@ extern "C" int lbm_export_state(lbm_sim* s, void* blob, size_t cap, size_t* used
 
 extern "C" int lbm_import_state(lbm_sim* s, const void* blob, size_t n) {
   if (!s || !blob) return fail(s, LBM_EINVAL, "null argument");
-  if (s->sticky) return s->sticky;
+  if (int rc = guard(s)) return rc;
   if (n < sizeof(Blob)) return fail(s, LBM_EINVAL, "checkpoint too short");
   Blob h;
   std::memcpy(&h, blob, sizeof h);
-  if (std::memcmp(h.magic, "MLBMCKP1", 8) || h.nx != s->p.nx || h.ny != s->p.ny || h.nz != s->p.nz ||
+  if (std::memcmp(h.magic, "MLBMCKP2", 8) || h.nx != s->p.nx || h.ny != s->p.ny || h.nz != s->p.nz ||
       h.storage != s->p.storage)
     return fail(s, LBM_EINVAL, "checkpoint does not match this object");
   const int64_t popbytes = (int64_t)(s->pop_elems * (int64_t)s->esize);
@@ -1451,7 +1617,9 @@ extern "C" int lbm_import_state(lbm_sim* s, const void* blob, size_t n) {
       h.snapbytes != (s->d_snap ? (int64_t)s->p.snap_count * s->N * 16 : 0))
     return fail(s, LBM_EINVAL, "checkpoint layout does not match this object");
   const char* b = (const char*)blob + sizeof h;
-  size_t need = sizeof(Blob) + h.popbytes + h.accbytes + h.snapbytes + (size_t)h.nforces * 32 + 8;
+  if (h.fstored < 0 || (s->force_ring && h.fstored > s->force_cap) || (!s->force_ring && h.fstored != h.nforces))
+    return fail(s, LBM_EINVAL, "checkpoint force series does not match this object");
+  size_t need = sizeof(Blob) + h.popbytes + h.accbytes + h.snapbytes + (size_t)h.fstored * 32 + 8;
   if (n < need) return fail(s, LBM_EINVAL, "checkpoint truncated");
   HIPCHK(s, hipMemcpyAsync(s->A, b, (size_t)h.popbytes, hipMemcpyHostToDevice, s->stream));
   b += h.popbytes;
@@ -1459,14 +1627,14 @@ extern "C" int lbm_import_state(lbm_sim* s, const void* blob, size_t n) {
   b += h.accbytes;
   if (h.snapbytes) HIPCHK(s, hipMemcpyAsync(s->d_snap, b, (size_t)h.snapbytes, hipMemcpyHostToDevice, s->stream));
   b += h.snapbytes;
-  if (h.nforces) {
-    int rc = ensure_force_cap(s, h.nforces + 1);
+  if (h.fstored) {
+    int rc = ensure_force_cap(s, h.fstored + 1);
     if (rc) return rc;
-    HIPCHK(s, hipMemcpyAsync(s->d_forces, b, (size_t)h.nforces * 24, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->d_forces, b, (size_t)h.fstored * 24, hipMemcpyHostToDevice, s->stream));
   }
-  b += h.nforces * 24;
-  s->force_steps.assign((const int64_t*)b, (const int64_t*)b + h.nforces);
-  b += h.nforces * 8;
+  b += h.fstored * 24;
+  s->force_steps.assign((const int64_t*)b, (const int64_t*)b + h.fstored);
+  b += h.fstored * 8;
   int64_t nss;
   std::memcpy(&nss, b, 8);
   b += 8;
@@ -1513,7 +1681,7 @@ extern "C" int lbm_profile_read(lbm_sim* s, double* total_ms, int64_t* launches)
 
 extern "C" int lbm_bandwidth_probe(lbm_sim* s, int32_t passes, double* ms_per_pass) {
   if (!s || !ms_per_pass) return fail(s, LBM_EINVAL, "null argument");
-  if (s->sticky) return s->sticky;
+  if (int rc = guard(s)) return rc;
   if (passes <= 0 || passes % 2) return fail(s, LBM_EINVAL, "passes must be positive and even");
   const StepArgs& a = s->args;
   hipEvent_t e0, e1;

@@ -214,21 +214,3 @@ def bench_train(batch=16, reps=5, arch="fno"):
     ms = (time.perf_counter() - t0) / reps * 1e3
     net.close()
     return {"batch": batch, "ms_per_step": round(ms, 3), "train_samples_per_s": round(batch / ms * 1e3, 1)}
-
-
-def smoke_check():
-    """One small forward pass on cuda:0 against the FP64 oracle."""
-    import torch
-    from oracle import fno as ofno
-    s = ofno.Shape(nx=32, ny=16, nz=16, cin=4, cout=4, width=16, layers=2, mx=4, my=4, mz=4, hidden=16)
-    net = Fno(nx=32, ny=16, nz=16, width=16, layers=2, mx=4, my=4, mz=4, hidden=16, max_batch=2, seed=1)
-    g = torch.Generator(device="cuda").manual_seed(0)
-    x = torch.randn((2, 4, 32, 16, 16), device="cuda", generator=g).to(torch.bfloat16)
-    y = net.forward(x)
-    th = net.get_params().astype(np.float64)
-    yo, _ = ofno.forward(th, x.float().cpu().numpy().astype(np.float64), s)
-    err = float(np.linalg.norm(y.cpu().numpy() - yo) / np.linalg.norm(yo))
-    print(f"smoke fno: forward 32x16x16 width 16, rel L2 vs oracle {err:.3e}", flush=True)
-    net.close()
-    assert err < 3e-2
-    return err

@@ -42,22 +42,32 @@ class Lbm:
     def __init__(self, shape, storage="f32", periodic=(0, 0, 0), u_in=0.05, nu=None, re=None, l_ref=None,
                  omega2=1.0, mode="auto", galilean=1, lam=0.01, obstacle_bc=0, body_force=(0.0, 0.0, 0.0),
                  avg_start=0, snap_every=0, snap_count=20, snap_start=0, force_every=1, xcd_remap=1, solid=None,
-                 links=None, u0=None, perturb=None, stream=None):
+                 links=None, u0=None, perturb=None, stream=None, check_every=0, force_capacity=0,
+                 workspace=None):
+        """shape (nx, ny, nz); give the viscosity nu, or re (and l_ref, in
+        cells, default the channel height ny) for the library to derive it.
+        workspace: a caller-owned CUDA tensor of at least
+        ``Lbm.workspace_size(...)`` bytes that holds all device state (needs
+        force_capacity > 0 when forces are on); kept referenced by the
+        object."""
         L = load()
         nx, ny, nz = (int(v) for v in shape)
         self.shape = (nx, ny, nz)
         self.N = nx * ny * nz
-        if nu is None:
-            if re is None:
-                raise ValueError("give nu or re")
-            nu = nu_from_re(u_in, ny if l_ref is None else l_ref, re)
+        if nu is None and re is None:
+            raise ValueError("give nu or re")
         p = LbmParams()
         L.lbm_default_params(ctypes.byref(p), nx, ny, nz)
         p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
         for d in range(3):
             p.periodic[d] = int(periodic[d])
             p.body_force[d] = float(body_force[d])
-        p.u_in, p.nu, p.omega2 = float(u_in), float(nu), float(omega2)
+        p.u_in, p.omega2 = float(u_in), float(omega2)
+        if re is not None:
+            p.re, p.l_ref = float(re), float(l_ref or 0.0)
+        else:
+            p.nu = float(nu)
+        p.check_every, p.force_capacity = int(check_every), int(force_capacity)
         p.mode = MODES[mode] if isinstance(mode, str) else int(mode)
         p.galilean, p.lam, p.obstacle_bc = int(galilean), float(lam), int(obstacle_bc)
         p.avg_start = -1 if avg_start is None else int(avg_start)
@@ -89,12 +99,52 @@ class Lbm:
         h = ctypes.c_void_p()
         self._L = L
         self._h = None
-        rc = L.lbm_create(ctypes.byref(p), None if sol is None else _ptr(sol), nl,
-                          None if lc is None else _ptr(lc), None if ld is None else _ptr(ld),
-                          None if lq is None else _ptr(lq), None if u is None else _ptr(u), _stream_handle(stream),
-                          ctypes.byref(h))
-        check(rc, None, "lbm_create")
+        self._workspace = workspace
+        ws, wsb = None, 0
+        if workspace is not None:
+            ws = ctypes.c_void_p(workspace.data_ptr())
+            wsb = workspace.numel() * workspace.element_size()
+        rc = L.lbm_create_in(ctypes.byref(p), None if sol is None else _ptr(sol), nl,
+                             None if lc is None else _ptr(lc), None if ld is None else _ptr(ld),
+                             None if lq is None else _ptr(lq), None if u is None else _ptr(u), ws, wsb,
+                             _stream_handle(stream), ctypes.byref(h))
+        check(rc, None, "lbm_create_in" if workspace is not None else "lbm_create")
         self._h = h
+
+    @staticmethod
+    def params_struct(shape, **kw):
+        """The lbm_params the constructor would pass (for workspace sizing)."""
+        L = load()
+        nx, ny, nz = (int(v) for v in shape)
+        p = LbmParams()
+        L.lbm_default_params(ctypes.byref(p), nx, ny, nz)
+        for k, v in kw.items():
+            if k == "storage":
+                v = STORAGE[v] if isinstance(v, str) else int(v)
+            elif k == "mode":
+                v = MODES[v] if isinstance(v, str) else int(v)
+            elif k == "avg_start" and v is None:
+                v = -1
+            if k in ("periodic", "body_force"):
+                for d in range(3):
+                    getattr(p, k)[d] = v[d]
+            else:
+                setattr(p, k, v)
+        return p
+
+    @staticmethod
+    def workspace_size(shape, solid=None, **kw):
+        """Bytes lbm_workspace_size reports for these parameters (keyword
+        names of lbm_params) and solid mask; host work only."""
+        L = load()
+        p = Lbm.params_struct(shape, **kw)
+        sol = None
+        if solid is not None:
+            sol = np.ascontiguousarray(np.asarray(solid).reshape(-1), dtype=np.uint8)
+        n = ctypes.c_size_t()
+        check(L.lbm_workspace_size(ctypes.byref(p), None if sol is None else _ptr(sol), ctypes.byref(n)), None,
+              "lbm_workspace_size")
+        return n.value
 
     # ------------------------------------------------------------------
     def close(self):

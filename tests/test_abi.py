@@ -102,3 +102,97 @@ def test_binding_raises_on_error():
     from paper_2606_16765_amd._lib import HipError
     with pytest.raises(HipError):
         P.Lbm((63, 8, 8), nu=0.01)
+
+
+def _params(shape, **kw):
+    from paper_2606_16765_amd._lib import LbmParams, load
+    L = load()
+    p = LbmParams()
+    L.lbm_default_params(ctypes.byref(p), *shape)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return L, p
+
+
+def test_fourth_order_mode_rejected_where_its_rates_are_undefined():
+    """A and B of the fourth-order mode carry 1/(omega1 - omega2): at
+    nu = 1/6 (omega1 = 1 = omega2) lbm_create answers LBM_EINVAL before any
+    device work, and so it does where a third-order rate leaves (0, 2)
+    (omega1 = 1.5 gives omega4 = 3.2).  Plain mode at the same viscosity is
+    not rejected by this rule (lbm_workspace_size, host only, accepts it)."""
+    h = ctypes.c_void_p()
+    for nu in (1.0 / 6.0, (1 / 1.5 - 0.5) / 3):
+        L, p = _params((64, 8, 8), nu=nu, mode=1)
+        assert L.lbm_create(ctypes.byref(p), None, 0, None, None, None, None, None, ctypes.byref(h)) == 1
+        assert b"fourth-order mode undefined" in L.lbm_last_error(None)
+        n = ctypes.c_size_t()
+        assert L.lbm_workspace_size(ctypes.byref(p), None, ctypes.byref(n)) == 1
+        p.mode = 0
+        assert L.lbm_workspace_size(ctypes.byref(p), None, ctypes.byref(n)) == 0
+    # the production range (omega1 near 2) is accepted
+    L, p = _params((64, 8, 8), nu=0.05 * 8 / 3900, mode=1)
+    n = ctypes.c_size_t()
+    assert L.lbm_workspace_size(ctypes.byref(p), None, ctypes.byref(n)) == 0
+
+
+def test_reynolds_number_maps_to_viscosity_in_the_library():
+    """re > 0 makes the library derive nu = u_in l_ref / re, and that nu
+    decides the automatic switch at Re_c = u_in ny / nu = 3000.  With
+    l_ref = ny and u_in = re / 48 on ny = 8 the derived nu is 1/6, where the
+    fourth-order mode has a pole (omega1 = 1 = omega2): re = 3000 resolves
+    to that mode and is rejected, re = 2990 resolves to the plain mode and
+    is accepted (host-only checks through lbm_workspace_size)."""
+    n = ctypes.c_size_t()
+    for re_, rc in ((3000.0, 1), (2990.0, 0)):
+        L, p = _params((64, 8, 8), re=re_, l_ref=8.0, u_in=re_ / 48.0, nu=0.01)  # nu ignored when re > 0
+        assert L.lbm_workspace_size(ctypes.byref(p), None, ctypes.byref(n)) == rc, re_
+    # l_ref <= 0 means the channel height
+    L, p = _params((64, 8, 8), re=3000.0, l_ref=0.0, u_in=3000.0 / 48.0)
+    assert L.lbm_workspace_size(ctypes.byref(p), None, ctypes.byref(n)) == 1
+    L, p = _params((64, 8, 8), re=1000.0, u_in=0.0)
+    assert L.lbm_workspace_size(ctypes.byref(p), None, ctypes.byref(n)) == 1
+    assert b"re needs u_in" in L.lbm_last_error(None)
+
+
+def test_workspace_size_counts_every_region():
+    """lbm_workspace_size: populations in the padded plane layout
+    (27 slots of (nx + 64) x (ny + 2) per padded plane, nz + 2 planes),
+    flags, rows, tables, accumulators (32 B per cell), snapshot ring
+    (16 B per cell per snapshot), each region rounded up to 256 bytes."""
+    import numpy as np
+    shape = (128, 16, 8)
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    r256 = lambda b: (b + 255) // 256 * 256  # noqa: E731
+    base = lambda es, nb: (r256(27 * (nx + 64) * (ny + 2) * (nz + 2) * es) + r256(N) + r256(4 * N)  # noqa: E731
+                           + r256(4 * max(nb, 1)) + r256(216 * max(nb, 1)) + 256)
+    n = ctypes.c_size_t()
+    L, p = _params(shape, avg_start=-1, force_every=0)
+    assert L.lbm_workspace_size(ctypes.byref(p), None, ctypes.byref(n)) == 0
+    assert n.value == base(4, 0)
+    L, p = _params(shape, storage=0, avg_start=0, snap_every=25, snap_count=3, force_every=0)
+    assert L.lbm_workspace_size(ctypes.byref(p), None, ctypes.byref(n)) == 0
+    assert n.value == base(8, 0) + r256(32 * N) + r256(3 * 16 * N)
+    # one solid cell far from the faces: 26 fluid neighbours, all in one
+    # x tile and 2 y tiles (3 z planes) -> slots in 6 tiles
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    solid[4, 8, 40] = 1
+    L, p = _params(shape, avg_start=-1, force_every=1, force_capacity=10)
+    assert L.lbm_workspace_size(ctypes.byref(p), solid.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)) == 0
+    tiles = (nx // 64) * (ny // 2) * nz
+    assert n.value == base(4, 26) + r256(4 * tiles) + r256(24 * 6) + r256(24 * 10)
+
+
+def test_product_package_does_not_load_the_oracle():
+    """The product package never imports, loads or runs anything under
+    oracle/: only the tests, the smoke check and the benchmark's CPU
+    baseline do."""
+    pkg = os.path.join(ROOT, "paper_2606_16765_amd")
+    bad = []
+    for dp, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dp, f)).read()
+                if re.search(r"^\s*(from\s+oracle\b|import\s+oracle\b)|lbm_oracle|_lbm_oracle", txt, flags=re.M):
+                    bad.append(f)
+    assert not bad, bad

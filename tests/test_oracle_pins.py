@@ -197,13 +197,107 @@ def test_k17_with_neutral_coefficients_is_plain():
 
 
 def test_k17_rates_limits():
-    """Rates vanish as omega1 -> 2 (the factor omega1 - 2), and the limiter
-    makes the effective rate 1 for large third-order cumulants."""
+    """Rates vanish as omega1 -> 2 (the factor omega1 - 2) and are small
+    positive relaxation rates at omega1 = 1.99; the closed forms agree with
+    the brute variant's transcription.  (The limiter is pinned by
+    test_limiter_effective_rate_closed_form.)"""
     co = lbm.k17_coefficients(2.0 - 1e-9)
     assert np.abs(co[:3]).max() < 1e-7
     co99 = lbm.k17_coefficients(1.99)
     assert 0 < co99[0] < 0.1 and 0 < co99[1] < 0.1 and 0 < co99[2] < 0.1
     assert np.allclose(lbm.k17_coefficients(1.9), brute.k17_coefficients(1.9), rtol=1e-14)
+
+
+def _state_from_cumulants(C, rho=1.0, u=(0.0, 0.0, 0.0)):
+    """Shifted populations whose normalised cumulants are C (index 9a+3b+c)
+    at density rho and velocity u."""
+    u = np.asarray(u, float)
+    k = lbm.moments_from_cumulants(C)
+    K = rho * k
+    K[0] = rho
+    K[9] = K[3] = K[1] = 0.0
+    _, w = lbm.lattice()
+    return lbm.populations_from_central(K, u) - w
+
+
+def _post_cumulants(p, fbar, u=(0.0, 0.0, 0.0)):
+    _, w = lbm.lattice()
+    g = lbm.collide(p, fbar) + w
+    rho = g.sum()
+    return lbm.cumulants(lbm.central_moments(g, np.asarray(u, float)) / rho)
+
+
+@pytest.mark.parametrize("which", ["sum", "diff", "c111"])
+def test_limiter_effective_rate_closed_form(which):
+    """Third-order limiter of the fourth-order mode (Sec. 3.2, limiter of
+    the parametrised operator; reading R4).  At rest with second-order
+    cumulants at equilibrium, one third-order combination c is relaxed to
+    (1 - w_eff) c and nothing else changes.  The limiter's defining
+    properties fix w_eff without the formula: w_eff -> w (the unlimited
+    rate) for |c| << lambda, w_eff -> 1 (full relaxation) for |c| >> lambda,
+    w_eff = (w + 1)/2 at |c| = lambda (lambda is the half-way scale), even
+    in c and monotone in |c|.  Given rates w3 = 0.2 (pair sums),
+    w4 = 0.5 (pair differences) and w5 = 0.8 (c111) are distinct, so a rate
+    applied to the wrong combination fails too, and so does a limiter
+    weighted by lambda/(lambda + |c|) or with (1 + w)."""
+    lam = 1e-3
+    rates = {"sum": 0.2, "diff": 0.5, "c111": 0.8}
+    w = rates[which]
+    p = lbm.make_params((1, 1, 1), omega1=1.9, mode=1, lam=lam, k17=(0.2, 0.5, 0.8, 0.0, 0.0))
+
+    def w_eff(c):
+        C = np.zeros(27)
+        C[0] = 1.0
+        C[18] = C[6] = C[2] = 1.0 / 3.0
+        if which == "c111":
+            C[13] = c
+        else:
+            # c120 = IX(1,2,0) = 15, c102 = IX(1,0,2) = 11
+            C[15], C[11] = (c / 2, c / 2) if which == "sum" else (c / 2, -c / 2)
+        Cs = _post_cumulants(p, _state_from_cumulants(C))
+        if which == "c111":
+            out = Cs[13]
+            other = 0.0
+            touched = [13]
+        else:
+            out = Cs[15] + Cs[11] if which == "sum" else Cs[15] - Cs[11]
+            other = Cs[15] - Cs[11] if which == "sum" else Cs[15] + Cs[11]
+            touched = [15, 11]
+        # everything else keeps its equilibrium value (rest, second order 1/3)
+        rest = np.zeros(27)
+        rest[0] = 1.0
+        rest[18] = rest[6] = rest[2] = 1.0 / 3.0
+        mask = np.ones(27, bool)
+        mask[touched] = False
+        assert np.abs(Cs[mask] - rest[mask]).max() < 1e-13 and abs(other) < 1e-13 * max(abs(c), 1.0)
+        return 1.0 - out / c
+
+    small = w_eff(lam * 1e-6)
+    assert abs(small - w) < 1e-5
+    large = w_eff(lam * 1e6)
+    assert abs(large - 1.0) < 1e-5
+    assert abs(w_eff(lam) - 0.5 * (w + 1.0)) < 1e-9
+    assert abs(w_eff(-lam) - w_eff(lam)) < 1e-12
+    grid = [w_eff(lam * t) for t in (0.01, 0.1, 0.5, 1.0, 2.0, 10.0, 100.0)]
+    assert all(b > a for a, b in zip(grid, grid[1:]))
+
+
+def test_collision_relaxes_shear_at_omega1():
+    """Off-diagonal second-order cumulants relax at omega1 (the rate that
+    sets nu = (1/omega1 - 1/2)/3): at rest, c110* = (1 - omega1) c110, and
+    a traceless diagonal deviation relaxes the same way."""
+    for om in (0.8, 1.6, 1.99):
+        p = lbm.make_params((1, 1, 1), omega1=om, mode=0)
+        C = np.zeros(27)
+        C[0] = 1.0
+        C[18] = C[6] = C[2] = 1.0 / 3.0
+        C[12] = 2e-3                               # c110
+        C[18] += 1e-3
+        C[6] -= 1e-3                               # c200 - c020 = 2e-3, trace unchanged
+        Cs = _post_cumulants(p, _state_from_cumulants(C))
+        assert abs(Cs[12] - (1 - om) * 2e-3) < 1e-15
+        assert abs((Cs[18] - Cs[6]) - (1 - om) * 2e-3) < 1e-15
+        assert abs(Cs[18] + Cs[6] + Cs[2] - 1.0) < 1e-15
 
 
 def _tgv_error(N, omega, mode=0, U=(0.0, 0.0), G=1, U0=1e-3, frac=0.5):
@@ -389,6 +483,132 @@ def test_walled_channel_develops_no_slip():
     prof = u[0, :, :, 8]
     assert prof[4, 4] > prof[0, 4] and prof[4, 4] > prof[4, 0]
     assert np.all(np.isfinite(r.fbar))
+
+
+def _fields_of(fbar, force=(0.0, 0.0, 0.0)):
+    """(u, v, w, p) of a pre-collision state by the definitions of the
+    macroscopic quantities: rho = sum f, u = (sum f c + F/2)/rho,
+    p = (rho - 1)/3."""
+    c, _ = lbm.lattice()
+    f = fbar.reshape(27, -1)
+    d = f.sum(0)
+    u = (c.T.astype(np.float64) @ f + 0.5 * np.asarray(force, float)[:, None]) / (1.0 + d)
+    return np.concatenate([u, (d / 3.0)[None]], 0).reshape((4,) + fbar.shape[1:])
+
+
+def test_mean_fields_sample_the_pre_collision_state():
+    """Averaging (Sec. 2; reading R11): the sample of step n is the
+    pre-collision state of step n, p = (rho - 1)/3.  One step from an
+    equilibrium of known rho0, u0 must give means u0 + F/(2 rho0) and
+    (rho0 - 1)/3 exactly: a post-collision sample would carry F/rho0 more
+    velocity (the collision adds the body force F), a post-streaming one
+    the streamed fields, and p = rho - 1 three times the pressure.  Two
+    steps average the initial and the once-stepped state."""
+    shape = (8, 6, 5)
+    rng = np.random.default_rng(11)
+    rho0 = 1.0 + 0.02 * rng.standard_normal((5, 6, 8))
+    u0 = 0.03 * rng.standard_normal((3, 5, 6, 8))
+    F = (2e-4, -1e-4, 3e-4)
+    p = lbm.make_params(shape, periodic=(1, 1, 1), nu=0.02, force=F, avg_start=0)
+    r = lbm.Run(p, rho0=rho0, u0=u0)
+    f0 = r.fbar.copy()
+    r.step(1, forces=False)
+    m = r.mean_fields()
+    expect_u = u0 + np.asarray(F)[:, None, None, None] / (2.0 * rho0)
+    assert np.abs(m[:3] - expect_u).max() < 1e-15
+    assert np.abs(m[3] - (rho0 - 1.0) / 3.0).max() < 1e-15
+    assert np.abs(_fields_of(f0, F) - m).max() < 1e-15
+    f1 = r.fbar.copy()
+    r.step(1, forces=False)
+    m2 = r.mean_fields()
+    assert r.count == 2
+    assert np.abs(m2 - 0.5 * (_fields_of(f0, F) + _fields_of(f1, F))).max() < 1e-15
+    # a window starting at step 1 holds only the second state
+    p1 = lbm.make_params(shape, periodic=(1, 1, 1), nu=0.02, force=F, avg_start=1)
+    r1 = lbm.Run(p1, rho0=rho0, u0=u0).step(2, forces=False)
+    assert r1.count == 1
+    assert np.abs(r1.mean_fields() - _fields_of(f1, F)).max() < 1e-15
+
+
+def test_snapshots_are_taken_at_snap_start_plus_multiples_of_the_period():
+    """Snapshots (Sec. 2, 25 steps apart; reading R12): the FP64 fields of
+    the pre-collision states of steps snap_start + k snap_every, here
+    2, 5, 8 of a 10-step run, equal to the states stepped one by one."""
+    shape = (8, 6, 5)
+    rng = np.random.default_rng(12)
+    u0 = 0.03 * rng.standard_normal((3, 5, 6, 8))
+    p = lbm.make_params(shape, periodic=(1, 1, 1), nu=0.02, avg_start=10 ** 6, snap_every=3, snap_start=2)
+    r = lbm.Run(p, u0=u0).step(10, forces=False, snap_cap=10)
+    assert len(r.snaps) == 3
+    ref = lbm.Run(p, u0=u0)
+    states = []
+    for _ in range(10):
+        states.append(_fields_of(ref.fbar))
+        ref.step(1, forces=False)
+    for k, n in enumerate((2, 5, 8)):
+        assert np.abs(r.snaps[k].reshape(4, 5, 6, 8) - states[n]).max() < 1e-15, n
+
+
+def _one_step_with_post(p, fbar, solid=None):
+    """The oracle's state after one step, and every cell's post-collision
+    populations computed cell by cell with lbm.collide."""
+    r = lbm.Run(p, solid=solid, fbar=fbar).step(1, forces=False)
+    post = np.zeros_like(fbar)
+    nz, ny, nx = fbar.shape[1:]
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                if solid is None or not solid[z, y, x]:
+                    post[:, z, y, x] = lbm.collide(p, fbar[:, z, y, x])
+    return r.fbar, post
+
+
+def test_outlet_inlet_and_walls_at_the_population_level():
+    """Boundary rules of the channel (Sec. 3.1; readings R6-R8), checked on
+    every boundary population after one step of a state that varies along
+    x, y and z (so that copying the wrong column, bouncing the wrong
+    population or dropping the inlet term fails):
+      outlet, zero gradient: a population entering the last column from
+        outside (c_x = -1) equals what the last column itself emits in that
+        direction from the cell behind it, post(nx - 1, y - c_y, z - c_z);
+      inlet at x = -1/2, moving-wall bounce-back with rho_w = 1: a
+        population entering column 0 (c_x = +1) is the cell's own opposite
+        post-collision population plus 6 w_i c_ix u_in;
+      walls at y = -1/2, ny - 1/2 (halfway): the cell's own opposite
+        population, taking precedence over inlet and outlet."""
+    shape = (10, 6, 4)
+    nx, ny, nz = shape
+    rng = np.random.default_rng(13)
+    u0 = np.zeros((3, nz, ny, nx))
+    u0[0] = 0.05 + 0.02 * rng.standard_normal((nz, ny, nx))
+    u0[1:] = 0.02 * rng.standard_normal((2, nz, ny, nx))
+    rho0 = 1.0 + 0.01 * rng.standard_normal((nz, ny, nx))
+    p = lbm.make_params(shape, periodic=(0, 0, 1), nu=0.02, u_in=0.05)
+    f0 = lbm.init(p, rho0=rho0, u0=u0)
+    f1, post = _one_step_with_post(p, f0)
+    c, w = lbm.lattice()
+    checked = {"outlet": 0, "inlet": 0, "wall": 0}
+    for z in range(nz):
+        for y in range(ny):
+            for x in (0, nx - 1):
+                for i in range(27):
+                    cx_, cy_, cz_ = c[i]
+                    sy, sz = y - cy_, (z - cz_) % nz
+                    if sy < 0 or sy >= ny:
+                        expect = post[26 - i, z, y, x]
+                        checked["wall"] += 1
+                    elif x == 0 and cx_ == 1:
+                        expect = post[26 - i, z, y, x] + 6.0 * w[i] * cx_ * 0.05
+                        checked["inlet"] += 1
+                    elif x == nx - 1 and cx_ == -1:
+                        expect = post[i, sz, sy, nx - 1]
+                        checked["outlet"] += 1
+                    else:
+                        continue
+                    assert abs(f1[i, z, y, x] - expect) < 1e-16, (x, y, z, i)
+    assert min(checked.values()) > 50
+    # the outlet copy is not the interior pull: column nx - 2 differs
+    assert np.abs(post[:, :, :, nx - 1] - post[:, :, :, nx - 2]).max() > 1e-4
 
 
 # ------------------------------------------------------------ whole oracle
