@@ -5,8 +5,14 @@ Tolerance (relative L2): BF16 operands carry a relative rounding error of at
 most 2^-9; with FP32 accumulation each contraction adds about that much in
 relative L2, and a forward pass chains ~9 contractions per Fourier layer
 plus lifting and projection.  Adding in quadrature over ~20 stages gives
-~1e-2; the bounds below are 3e-2 (forward) and 5e-2 (gradients, about
-twice as many stages).
+~1e-2.  The bounds are set at about twice the error measured on the GPU
+for each instance (all kernels are deterministic, so the measurement
+repeats bit for bit):
+  forward 1e-2 (measured 3.6e-3 to 4.5e-3), full size 1.4e-2 (6.7e-3);
+  gradients, worst parameter group, 3e-2 on the small instances (worst
+  1.4e-2, the hybrid's q2 at feed-forward 48), 3e-2 on the production
+  instance at 64x32x32 (1.4e-2) and 1.7e-2 at full size (8.4e-3);
+  loss 3e-3 (1e-3); Adam trajectories 7e-3 per step (3.2e-3).
 """
 import numpy as np
 import pytest
@@ -46,7 +52,7 @@ def test_forward_matches_oracle_small():
     yo, _ = ofno.forward(th, x.float().cpu().numpy().astype(np.float64), _shape(SMALL))
     err = rel_l2(y, yo)
     print("forward rel L2", err)
-    assert err < 3e-2
+    assert err < 1e-2
 
 
 # wider networks take the other code paths: 64-channel-class mixing kernels,
@@ -79,7 +85,7 @@ def test_forward_wide_matches_oracle(cfg):
     yo, _ = ofno.forward(th, x.float().cpu().numpy().astype(np.float64), _shape(cfg))
     err = rel_l2(y, yo)
     print("forward rel L2", cfg["width"], err)
-    assert err < 3e-2
+    assert err < 1e-2
 
 
 def _grad_groups(cfg, B, seed=1):
@@ -113,22 +119,22 @@ def _grad_groups(cfg, B, seed=1):
                          ids=["w16", "w48", "w64", "siren", "hybrid16", "hybrid32", "hybrid16ff48"])
 def test_gradients_match_oracle_small(cfg):
     errs = _grad_groups(cfg, 2)
-    assert errs["loss"] < 3e-2
+    assert errs["loss"] < 3e-3
     worst = max((v, k) for k, v in errs.items())
-    assert worst[0] < 5e-2, worst
+    assert worst[0] < 3e-2, worst
 
 
-@pytest.mark.parametrize("cfg,B", [(PROD, 2), (FULL, 1)], ids=["prod64x32x32", "full128x64x64"])
-def test_gradients_match_oracle_production_instance(cfg, B):
+@pytest.mark.parametrize("cfg,B,bound", [(PROD, 2, 3e-2), (FULL, 1, 1.7e-2)], ids=["prod64x32x32", "full128x64x64"])
+def test_gradients_match_oracle_production_instance(cfg, B, bound):
     """Gradient parity of the network the surrogate trains (width 32,
     projection hidden 128, four outputs), every parameter group element by
     element in relative L2, on a cheap grid at batch 2 and once at the full
-    128x64x64 shape.  Bound: 2e-2 per group (twice the largest group error
-    measured at these instances)."""
+    128x64x64 shape.  Bound per group: twice the largest group error
+    measured at each instance (1.4e-2 and 8.4e-3)."""
     errs = _grad_groups(cfg, B, seed=2)
-    assert errs["loss"] < 1e-2
+    assert errs["loss"] < 1e-6
     worst = max((v, k) for k, v in errs.items())
-    assert worst[0] < 2e-2, worst
+    assert worst[0] < bound, worst
 
 
 @pytest.mark.parametrize("arch", ["fno", "hybrid"])
@@ -140,7 +146,7 @@ def test_forward_full_size_matches_oracle(arch):
     yo, _ = ofno.forward(th, x.float().cpu().numpy().astype(np.float64), _shape(full))
     err = rel_l2(y, yo)
     print("full-size forward rel L2", err)
-    assert err < 3e-2
+    assert err < 1.4e-2
 
 
 @pytest.mark.parametrize("cfg", [SMALL, HYBRID[0], PROD], ids=["fno", "hybrid", "prod"])
@@ -166,7 +172,7 @@ def test_adam_trajectory_matches_oracle(cfg):
         g = ofno.backward(th, cache, gy, s)
         th, m, v = ofno.adam(th, g, m, v, k, lr)
         print("step", k, lg, lo)
-        assert abs(lg - lo) / lo < 3e-2
+        assert abs(lg - lo) / lo < 7e-3
 
 
 @pytest.mark.parametrize("cfg", [SMALL, HYBRID[0], PROD], ids=["fno", "hybrid", "prod"])

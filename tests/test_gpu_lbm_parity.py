@@ -231,9 +231,8 @@ def test_c0_f32_mean_fields_within_1e5(c0_oracle):
     per = [rel_l2(m[k], mo[k]) for k in range(4)]
     print("C0 FP32 mean fields: e_vel", vel, "u v w p", per, flush=True)
     assert vel < 1e-5, vel
-    for k in range(3):
+    for k in range(4):
         assert per[k] < 1e-5, (k, per[k])
-    assert per[3] < 1e-4, per[3]
     fg, _ = g.forces()
     fo = np.array(o.forces)
     assert rel_l2(fg[:, 0], fo[:, 0]) < 1e-5
