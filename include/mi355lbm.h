@@ -348,6 +348,19 @@ int fno_field_minmax(const float* x, int64_t S, int32_t C, int64_t P, void* hip_
 int fno_field_scale(float* x, int64_t S, int32_t C, int64_t P, const float* lo, const float* hi, int32_t inverse,
                     void* hip_stream);
 
+/* fno_field_minmax for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result, with the per-block partials in a fixed device array of the
+ * library (4 MiB per GPU, held until the process ends) instead of a
+ * temporary allocation.  It calls no allocating routine.  Limit:
+ * S * ceil(P / 4096) * C <= 524288 (e.g. 512 samples of 4 fields of
+ * 128x64x64), larger inputs return LBM_EINVAL.  Every call on one GPU
+ * shares that GPU's array and overwrites what it reads, so calls that
+ * overlap on one GPU (several host threads or streams) race; serialise
+ * them.  Synchronises hip_stream.  Errors: LBM_EINVAL, LBM_EDEVICE.        */
+int fno_field_minmax_noalloc(const float* x, int64_t S, int32_t C, int64_t P, void* hip_stream, float* lo,
+                             float* hi);
+
 void fno_destroy(fno_net* n);
 const char* fno_last_error(const fno_net* n);
 

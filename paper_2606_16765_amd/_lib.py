@@ -78,6 +78,7 @@ def _sig(L):
         L.fno_destroy.restype = None
         L.fno_last_error.argtypes = [vp]
         L.fno_field_minmax.argtypes = [vp, i64, i32, i64, vp, vp, vp]
+        L.fno_field_minmax_noalloc.argtypes = [vp, i64, i32, i64, vp, vp, vp]
         L.fno_field_scale.argtypes = [vp, i64, i32, i64, vp, vp, i32, vp]
         L.fno_last_error.restype = ctypes.c_char_p
 

@@ -22,6 +22,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1152,6 +1153,91 @@ extern "C" int fno_field_minmax(const float* x, int64_t S, int32_t C, int64_t P,
     }
     lo[c] = a;
     hi[c] = b;
+  }
+  return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free min-max: the per-block partials of minmax_kernel and the
+// final per-channel pair live in a fixed device array instead of a
+// hipMalloc'd buffer.  Each GPU the library runs on holds its own copy until
+// the process ends; the host reaches it only through the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr int64_t MM_SCRATCH_FLOATS = int64_t(1) << 20;  // 4 MiB
+static __device__ __align__(256) float scratch[MM_SCRATCH_FLOATS + 2 * MM_MAXC];
+
+// per channel c: minimum and maximum over the nblk partial pairs of part,
+// written to out[2c], out[2c + 1] (NaN partials are skipped, as on the
+// host path)
+__global__ __launch_bounds__(256) void minmax_reduce_kernel(const float* part, int64_t nblk, float* out) {
+  __shared__ float rmin[256], rmax[256];
+  const int c = blockIdx.x;
+  float lo = INFINITY, hi = -INFINITY;
+  for (int64_t k = threadIdx.x; k < nblk; k += 256) {
+    lo = fminf(lo, part[((int64_t)c * nblk + k) * 2]);
+    hi = fmaxf(hi, part[((int64_t)c * nblk + k) * 2 + 1]);
+  }
+  rmin[threadIdx.x] = lo;
+  rmax[threadIdx.x] = hi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      rmin[threadIdx.x] = fminf(rmin[threadIdx.x], rmin[threadIdx.x + w]);
+      rmax[threadIdx.x] = fmaxf(rmax[threadIdx.x], rmax[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * c] = rmin[0];
+    out[2 * c + 1] = rmax[0];
+  }
+}
+
+static std::mutex g_scratch_mu;
+static std::vector<float*> g_scratch_ptr;  // device address of scratch, per device
+
+// Device address of the scratch array on the current device, looked up
+// once per device.
+static hipError_t scratch_ptr(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+  if (!g_scratch_ptr[(size_t)dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[(size_t)dev] = (float*)p;
+  }
+  *out = g_scratch_ptr[(size_t)dev];
+  return hipSuccess;
+}
+
+extern "C" int fno_field_minmax_noalloc(const float* x, int64_t S, int32_t C, int64_t P, void* hip_stream, float* lo,
+                                        float* hi) {
+  if (!x || !lo || !hi) return ffail(nullptr, LBM_EINVAL, "null argument");
+  if (S <= 0 || C <= 0 || C > MM_MAXC || P <= 0) return ffail(nullptr, LBM_EINVAL, "bad sizes");
+  const int64_t nchunk = (P + MM_CHUNK - 1) / MM_CHUNK, nblk = S * nchunk;
+  if (nblk > 0x7fffffff || nblk * C * 2 > MM_SCRATCH_FLOATS)
+    return ffail(nullptr, LBM_EINVAL,
+                 "input too large for the fixed scratch: S * ceil(P / 4096) * C must be at most 524288");
+  float* part = nullptr;
+  hipError_t e = scratch_ptr(&part);
+  if (e != hipSuccess) return ffail(nullptr, LBM_EDEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+  float* res = part + MM_SCRATCH_FLOATS;
+  const hipStream_t st = (hipStream_t)hip_stream;
+  hipLaunchKernelGGL(minmax_kernel, dim3((unsigned)nblk, (unsigned)C), dim3(256), 0, st, x, (int)C, P, nchunk, part,
+                     nblk);
+  hipLaunchKernelGGL(minmax_reduce_kernel, dim3((unsigned)C), dim3(256), 0, st, part, nblk, res);
+  float h[2 * MM_MAXC];
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(h, res, (size_t)C * 2 * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return ffail(nullptr, LBM_EDEVICE, hipGetErrorString(e));
+  for (int c = 0; c < C; ++c) {
+    lo[c] = h[2 * c];
+    hi[c] = h[2 * c + 1];
   }
   return LBM_OK;
 }
