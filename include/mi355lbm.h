@@ -127,8 +127,8 @@ int lbm_default_params(lbm_params* p, int32_t nx, int32_t ny, int32_t nz);
  *  u0         host double [3][N] initial velocity (NULL: rest); the initial
  *             state is the equilibrium at rho = 1 and u0.
  *  hip_stream hipStream_t cast to void* (NULL: null stream).
- * On success *out owns device memory of about 27*N*sizeof(storage) bytes
- * plus 32 B per cell when averaging is on.
+ * On success *out owns device memory of about 2*27*N*sizeof(storage) bytes
+ * (two population lattices) plus 32 B per cell when averaging is on.
  * Errors: LBM_EINVAL for a grid the kernels do not tile, a non-positive
  * viscosity, omega2 outside (0, 2), an obstacle within 3 cells of inlet or
  * outlet, links out of range, and the fourth-order mode where its rates are
@@ -138,8 +138,8 @@ int lbm_create(const lbm_params* p, const uint8_t* solid, int64_t nlinks, const 
                const uint8_t* link_dir, const double* link_q, const double* u0, void* hip_stream, lbm_sim** out);
 
 /* Device bytes that lbm_create_in needs as a caller workspace for these
- * parameters and this solid mask (host uint8 [N] or NULL): populations in
- * the padded layout, cell flags, boundary tables, force partials, FP64
+ * parameters and this solid mask (host uint8 [N] or NULL): two population
+ * lattices in the padded layout, cell flags, boundary tables, force partials, FP64
  * accumulators when averaging, the snapshot ring, the force ring
  * (force_capacity samples) and a stability flag.  Host work only; no device
  * call.  Errors: LBM_EINVAL, as lbm_create would return it.                  */
@@ -166,8 +166,9 @@ int lbm_create_in(const lbm_params* p, const uint8_t* solid, int64_t nlinks, con
  * gradient outlet, no-slip walls, bounce-back at the obstacle) and the
  * cumulant collision; plus the data capture of Sec. 2 (running means,
  * snapshots, force on the object) when due.  It is one fused
- * stream-and-collide launch (in-place AA pattern; the parity is tracked
- * internally), a force reduction when a force sample is due, and a 4-byte
+ * stream-and-collide launch (two-lattice pull: the step reads the previous
+ * post-collision populations at the upstream cells from one lattice and
+ * writes its own to the other), a force reduction when a force sample is due, and a 4-byte
  * copy of the stability flag after a check step.  nsteps = 0 only reports
  * the object's state (LBM_EUNSTABLE once a finished check step has flagged).
  * Errors: LBM_EINVAL (negative count), the sticky LBM_EUNSTABLE and
@@ -210,7 +211,8 @@ int lbm_forces(lbm_sim* s, double* fxyz, int64_t cap, int64_t* n, int64_t* steps
 int lbm_moments(lbm_sim* s, float* out, int out_on_device);
 
 /* Current pre-collision populations, natural layout, double fbar [27][N]
- * (solid cells 0), whatever the AA parity.  Host pointer.  Synchronises.     */
+ * (solid cells 0): the populations the next step collides, boundary rules
+ * applied.  Host pointer.  Synchronises.                                    */
 int lbm_get_populations(lbm_sim* s, double* fbar);
 
 /* The same for the cells of one box [x0, x0 + bx) x [y0, y0 + by) x
@@ -221,7 +223,7 @@ int lbm_get_populations_box(lbm_sim* s, int32_t x0, int32_t y0, int32_t z0, int3
                             double* fbar);
 
 /* Replace the state with natural-layout fbar [27][N] (host double, rounded
- * to the storage type); resets the AA parity, keeps step count and
+ * to the storage type), read in place by the next step; keeps step count and
  * accumulators.                                                              */
 int lbm_set_populations(lbm_sim* s, const double* fbar);
 
@@ -229,7 +231,7 @@ int lbm_set_populations(lbm_sim* s, const double* fbar);
  * sticky LBM_EUNSTABLE state if it is not finite.  Synchronises.             */
 int lbm_mass(lbm_sim* s, double* mass);
 
-/* Raw checkpoint: populations in storage layout plus step count, parity,
+/* Raw checkpoint: populations in storage layout plus step count, state kind,
  * accumulators and snapshot ring.  lbm_export_state with blob == NULL
  * reports the size in *used.  Restoring into an object created with the
  * same parameters and geometry continues bitwise identically.               */
@@ -248,13 +250,15 @@ int lbm_profile_read(lbm_sim* s, double* total_ms, int64_t* launches);
 
 /* Bandwidth probe (measurement support for the roofline of lbm_step, not
  * a step of the method): `passes` launches of a kernel that moves exactly
- * the even step's memory traffic, every cell's 27 slots loaded and stored
- * to the opposite slots with the step kernel's addressing, tile order and
- * cache hints, with no collision.  2 * 27 * sizeof(storage) bytes per cell
- * per pass.  passes must be even: the swap is its own inverse, so the state
- * is unchanged afterwards.  *ms_per_pass receives the event-timed average.
- * Synchronises.  Errors: LBM_EINVAL (null pointer, odd or non-positive
- * passes), LBM_EDEVICE.                                                      */
+ * the step's memory traffic, every cell's 27 populations loaded from the
+ * upstream cells of the current lattice and stored to the cell in the
+ * other lattice, with the step kernel's addressing, tile order and cache
+ * hints, with no collision.  2 * 27 * sizeof(storage) bytes per cell per
+ * pass.  The current lattice is only read, so the state is unchanged;
+ * passes must be even (kept for callers of earlier versions).
+ * *ms_per_pass receives the event-timed average.  Synchronises.
+ * Errors: LBM_EINVAL (null pointer, odd or non-positive passes),
+ * LBM_EDEVICE.                                                             */
 int lbm_bandwidth_probe(lbm_sim* s, int32_t passes, double* ms_per_pass);
 
 void lbm_destroy(lbm_sim* s);

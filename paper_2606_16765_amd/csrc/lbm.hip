@@ -1,7 +1,7 @@
 // MI355X (gfx950) D3Q27 cumulant lattice Boltzmann solver behind the C ABI
 // of include/mi355lbm.h.
 //
-// One fused kernel per time step: in-place AA-pattern streaming over a
+// One fused kernel per time step: two-lattice pull streaming over a
 // structure-of-arrays population field (x fastest, 64 cells per wave), the
 // central-moment / cumulant transforms and the collision in registers, the
 // boundary substitutions (walls, velocity inlet, zero-gradient outlet via a
@@ -29,22 +29,31 @@ constexpr int TX = 64;   // cells along x per wave
 constexpr int TY = 2;    // waves (rows along y) per block
 constexpr int NTHREADS = TX * TY;
 
-// Population layout, planes of slots: for each padded z plane, the 27 slots
-// of that plane follow each other, each a padded pitch x (ny + 2) sheet,
-// pitch = nx + 64.  Population i of cell (x, y, z) sits at
-//   (z + 1) zstride + i slotp + (y + 1) pitch + x,
-// slotp = pitch (ny + 2), zstride = 27 slotp.  Columns -1 and nx of every
-// row are the inlet and outlet ghosts; guard rows and planes keep every
-// neighbour address of a domain cell inside the array, so loads may be
-// issued before a boundary substitution replaces them.  Everything a tile
-// (64 x 2 cells of one z plane) touches lies within three consecutive
-// padded planes: one uniform base address plus 32-bit lane offsets.
+// Population layout, rows of slots: for each padded z plane and padded row,
+// the 27 slots of that row follow each other, each a run of slotp = nx + 64
+// elements.  Population i of cell (x, y, z) sits at
+//   (z + 1) zstride + (y + 1) rowp + i slotp + x,
+// rowp = 27 slotp, zstride = rowp (ny + 2).  Columns -1 and nx of every row
+// are the inlet and outlet ghosts (column -1 of slot i is the padding of
+// slot i - 1); guard rows and planes keep every neighbour address of a
+// domain cell inside the array, so loads may be issued before a boundary
+// substitution replaces them.  Everything a tile (64 x 2 cells of one z
+// plane) touches lies within three consecutive padded planes: one uniform
+// base address plus 32-bit lane offsets.
+//
+// Streaming is a two-lattice pull: a step reads the post-collision
+// populations of the previous step from array A at the upstream cells
+// x - c_i (the boundary rules substitute at read time) and writes the cell's
+// own post-collision populations to array B, aligned; the arrays swap roles
+// every step.  After creation or an import, A holds the natural
+// pre-collision state instead (the first step reads it in place).
 struct StepArgs {
-  void* A;                  // populations
+  const void* A;            // populations read by the step
+  void* B;                  // populations written by the step
   int32_t nx, ny, nz;
-  int32_t pitch;            // elements per row
-  int32_t slotp;            // elements per slot sheet = pitch * (ny + 2)
-  int32_t zstride;          // elements per padded plane = 27 * slotp
+  int32_t slotp;            // elements per slot run = nx + 64
+  int32_t rowp;             // elements per padded row = 27 slotp
+  int32_t zstride;          // elements per padded plane = rowp (ny + 2)
   int32_t per[3];           // periodic axes
   const uint8_t* flag;      // [N] 0 fluid, 1 fluid next to obstacle, 2 solid
   const int32_t* brow;      // [N] boundary row of flag-1 cells
@@ -80,17 +89,17 @@ __device__ __forceinline__ int logical_tile(int b, int ntiles, int remap) {
 
 // element index of population slot 0 of cell (x, y, z)
 __device__ __forceinline__ int64_t cell_index(const StepArgs& a, int x, int y, int z) {
-  return (int64_t)(z + 1) * a.zstride + (int64_t)(y + 1) * a.pitch + x;
+  return (int64_t)(z + 1) * a.zstride + (int64_t)(y + 1) * a.rowp + x;
 }
 
 // general element access: population slot of the cell whose slot-0 index is idx
 template <typename S>
-__device__ __forceinline__ typename Storage<S>::T ld(const StepArgs& a, int slot, int64_t idx) {
-  return Storage<S>::load((const S*)a.A + idx + (int64_t)slot * a.slotp);
+__device__ __forceinline__ typename Storage<S>::T ld(const void* A, const StepArgs& a, int slot, int64_t idx) {
+  return Storage<S>::load((const S*)A + idx + (int64_t)slot * a.slotp);
 }
 template <typename S>
-__device__ __forceinline__ void st(const StepArgs& a, int slot, int64_t idx, typename Storage<S>::T v) {
-  Storage<S>::store((S*)a.A + idx + (int64_t)slot * a.slotp, v);
+__device__ __forceinline__ void st(void* A, const StepArgs& a, int slot, int64_t idx, typename Storage<S>::T v) {
+  Storage<S>::store((S*)A + idx + (int64_t)slot * a.slotp, v);
 }
 
 // Per-cell boundary context of the general path.
@@ -115,7 +124,7 @@ __device__ __forceinline__ void make_ctx(const StepArgs& a, int x, int y, int z,
   c.x = x; c.y = y; c.z = z;
   c.n = ((int64_t)z * a.ny + y) * a.nx + x;
   c.pc = cell_index(a, x, y, z);
-  const int rowp = a.pitch;
+  const int rowp = a.rowp;
   const int64_t plane = a.zstride;
   // x: source of c=+1 is x-1, of c=-1 is x+1 (x+1 = nx is the outlet ghost)
   c.off[0][1] = 0; c.off[1][1] = 0; c.offz[1] = 0;
@@ -143,52 +152,74 @@ __device__ __forceinline__ void make_ctx(const StepArgs& a, int x, int y, int z,
   c.rmask = wall | c.inlet | reverse27(c.om);
 }
 
-// Pre-collision populations of a fluid cell, general path (any boundary),
-// with the interpolated bounce-back completion of q < 1/2 links.
-template <typename S, bool ODD>
+// Pre-collision populations of a fluid cell, general path: the pull from
+// the upstream cells with the boundary rules applied at read time.
+//  wall (y, z at -1/2 and n - 1/2): halfway bounce-back, the cell's own
+//    opposite population;
+//  inlet (x = -1/2): moving-wall bounce-back with rho_w = 1, the own
+//    opposite population plus 6 w_i (c_i . u_in);
+//  outlet: the source x = nx is the ghost column, which holds the copy of
+//    the post-collision column nx - 1 (zero gradient);
+//  obstacle: halfway bounce-back, or linear interpolation with the wall
+//    distance q of the link: q < 1/2 blends the own opposite population with
+//    the one the fluid node behind the cell sent (halfway where that node is
+//    not fluid); q >= 1/2 blends it with the cell's own population i.
+// natural = true: A holds the pre-collision state itself.
+template <typename S>
 __device__ __forceinline__ void load_general(const StepArgs& a, const Coef<typename Storage<S>::T>& k,
-                                             const CellCtx& c, typename Storage<S>::T* g) {
+                                             const CellCtx& c, bool natural, typename Storage<S>::T* g) {
   using T = typename Storage<S>::T;
+  if (natural) {
+#pragma unroll
+    for (int i = 0; i < 27; ++i) g[i] = ld<S>(a.A, a, i, c.pc);
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
-    T v;
-    if (!ODD) {
-      v = ld<S>(a, i, c.pc);
-    } else {
-      const bool r = (c.rmask >> i) & 1u;
-      v = ld<S>(a, r ? i : 26 - i, r ? c.pc : c.pc + src_off(i, c));
-      if (cx(i) == 1 && ((c.inlet >> i) & 1u)) v += T(wgt(i)) * k.u6;
-    }
+    const bool r = (c.rmask >> i) & 1u;
+    T v = ld<S>(a.A, a, r ? 26 - i : i, r ? c.pc : c.pc + src_off(i, c));
+    if (cx(i) == 1 && ((c.inlet >> i) & 1u)) v += T(wgt(i)) * k.u6;
     g[i] = v;
   }
   if (a.interp && c.om) {
+    // g[26 - i] of a direction whose source is fluid is never modified here
 #pragma unroll
-    for (int j = 0; j < 27; ++j) {
-      if (((c.om >> j) & 1u) && !((c.rmask >> j) & 1u)) {
-        const T q = T(a.bq[(int64_t)c.row * 27 + j]);
-        if (q < T(0.5)) g[26 - j] += (T(1) - T(2) * q) * g[j];
+    for (int i = 0; i < 27; ++i) {
+      if ((c.om >> (26 - i)) & 1u) {
+        const T q = T(a.bq[(int64_t)c.row * 27 + (26 - i)]);
+        if (q < T(0.5)) {
+          if (!((c.rmask >> (26 - i)) & 1u)) g[i] = T(2) * q * g[i] + (T(1) - T(2) * q) * g[26 - i];
+        } else {
+          g[i] = g[i] / (T(2) * q) + (T(2) * q - T(1)) / (T(2) * q) * ld<S>(a.A, a, i, c.pc);
+        }
       }
     }
   }
 }
 
 // Interior fast path: no wall, obstacle or periodic wrap in the wave.  zb
-// is the uniform address of the padded plane below the tile's plane, p0 the
-// lane's byte offset within a slot sheet; the neighbour offsets are
-// compile-time combinations of the row, sheet and plane strides.
+// is the uniform address of the tile's plane, biased back by one padded row
+// and one element, p0 the lane's biased byte offset; the neighbour offsets
+// are compile-time combinations of the slot, row and plane strides and stay
+// non-negative for every domain cell.
+template <typename S>
+__device__ __forceinline__ const char* plane_base(const void* A, const StepArgs& a, int z) {
+  return (const char*)A + ((int64_t)z * a.zstride - (a.rowp + 1)) * (int64_t)sizeof(S);
+}
+template <typename S>
+__device__ __forceinline__ uint32_t lane_off(const StepArgs& a, int x, int y) {
+  return (uint32_t)(((y + 2) * a.rowp + x + 1) * (int)sizeof(S));
+}
 template <typename S>
 __device__ __forceinline__ uint32_t fast_off(const StepArgs& a, uint32_t p0, int slot, int dx, int dy, int dz) {
-  return p0 + (uint32_t)(((1 + dz) * a.zstride + slot * a.slotp + dy * a.pitch + dx) * (int)sizeof(S));
+  return p0 + (uint32_t)(((1 + dz) * a.zstride + dy * a.rowp + slot * a.slotp + dx) * (int)sizeof(S));
 }
 
-template <typename S, bool ODD>
+template <typename S>
 __device__ __forceinline__ void load_fast(const StepArgs& a, const char* zb, uint32_t p0,
                                           typename Storage<S>::T* g) {
 #pragma unroll
-  for (int i = 0; i < 27; ++i) {
-    const uint32_t o = ODD ? fast_off<S>(a, p0, 26 - i, -cx(i), -cy(i), -cz(i)) : fast_off<S>(a, p0, i, 0, 0, 0);
-    g[i] = Storage<S>::load_nt((const S*)(zb + o));
-  }
+  for (int i = 0; i < 27; ++i) g[i] = Storage<S>::load_nt((const S*)(zb + fast_off<S>(a, p0, i, -cx(i), -cy(i), -cz(i))));
 }
 
 template <typename T>
@@ -214,34 +245,35 @@ __device__ __forceinline__ void macroscopic(const T* g, const Coef<T>& k, T& drh
 
 // One cell update.  PATH 0: interior wave (no wall, obstacle, periodic wrap,
 // inlet or outlet column in the wave); PATH 1: interior wave of the first or
-// last x tile, with the inlet and outlet columns handled per lane; PATH 2:
-// general boundary path.
-//  inlet (x = -1/2): moving-wall bounce-back, rho_w = 1: a population leaving
-//    through it returns with 6 w_i (c_i . u_in) added;
-//  outlet: zero gradient, through the ghost column x = nx: after an even step
-//    the ghost holds copies of column nx - 1, after an odd step column nx - 1
-//    receives the populations streamed into column nx - 2 from its ghost.
-template <typename S, bool ODD, int MODE, int PATH>
+// last x tile, with the inlet column handled per lane (the outlet column
+// pulls from the ghost column like any other source); PATH 2: general
+// boundary path.  NAT: the first step after creation or an import, which
+// reads the natural pre-collision state in place (PATH 2 only).  Every path
+// stores the cell's 27 post-collision populations to B at the cell itself;
+// column nx - 1 also fills the outlet ghost column nx with its populations
+// that move in -x (zero-gradient outlet).
+template <typename S, bool NAT, int MODE, int PATH>
 __device__ __forceinline__ void cell_update(const StepArgs& a, const Coef<typename Storage<S>::T>& k, int x, int y,
                                             int z, int64_t n, uint8_t fl, double& fx, double& fy, double& fz) {
   using T = typename Storage<S>::T;
   CellCtx c;
   T g[27];
   T Fx = 0, Fy = 0, Fz = 0;
-  const char* zb = (const char*)a.A + (size_t)z * (size_t)a.zstride * sizeof(S);
-  const uint32_t p0 = (uint32_t)(((y + 1) * a.pitch + x) * (int)sizeof(S));
+  const char* zb = plane_base<S>(a.A, a, z);
+  const uint32_t p0 = lane_off<S>(a, x, y);
   const bool at_inlet = PATH == 1 && !a.per[0] && x == 0;
   const bool outlet = PATH != 0 && !a.per[0] && x == a.nx - 1;
   if (PATH < 2) {
-    load_fast<S, ODD>(a, zb, p0, g);
-    if (ODD && at_inlet) {
+    load_fast<S>(a, zb, p0, g);
+    if (at_inlet) {
 #pragma unroll
       for (int i = 0; i < 27; ++i)
-        if (cx(i) == 1) g[i] = Storage<S>::load((const S*)(zb + fast_off<S>(a, p0, i, 0, 0, 0))) + T(wgt(i)) * k.u6;
+        if (cx(i) == 1)
+          g[i] = Storage<S>::load((const S*)(zb + fast_off<S>(a, p0, 26 - i, 0, 0, 0))) + T(wgt(i)) * k.u6;
     }
   } else {
     make_ctx(a, x, y, z, fl, c);
-    load_general<S, ODD>(a, k, c, g);
+    load_general<S>(a, k, c, NAT, g);
     // incoming half of the momentum exchange on obstacle links
     if (c.om) {
 #pragma unroll
@@ -281,73 +313,23 @@ __device__ __forceinline__ void cell_update(const StepArgs& a, const Coef<typena
   collide_moments<T, MODE>(g, drho, rho, irho, ux, uy, uz, k);
   inverse_transform(g, ux, uy, uz);
 
-  if (PATH == 0) {
+  char* wb = (char*)plane_base<S>(a.B, a, z);
 #pragma unroll
-    for (int j = 0; j < 27; ++j) {
-      const uint32_t o = ODD ? fast_off<S>(a, p0, j, cx(j), cy(j), cz(j)) : fast_off<S>(a, p0, 26 - j, 0, 0, 0);
-      Storage<S>::store_nt((S*)(zb + o), g[j]);
-    }
-  } else if (PATH == 1) {
+  for (int j = 0; j < 27; ++j) {
+    S* p = (S*)(wb + fast_off<S>(a, p0, j, 0, 0, 0));
+    Storage<S>::store_nt(p, g[j]);
+    if (cx(j) == -1 && outlet) Storage<S>::store(p + 1, g[j]);  // ghost column copy
+  }
+  if (PATH == 2 && c.om) {
 #pragma unroll
-    for (int j = 0; j < 27; ++j) {
-      if (!ODD) {
-        S* p = (S*)(zb + fast_off<S>(a, p0, 26 - j, 0, 0, 0));
-        Storage<S>::store_nt(p, g[j]);
-        if (cx(j) == -1 && outlet) Storage<S>::store(p + 1, g[j]);  // ghost column copy
-      } else {
-        if (cx(j) == -1 && at_inlet) {
-          Storage<S>::store((S*)(zb + fast_off<S>(a, p0, 26 - j, 0, 0, 0)), g[j] + T(wgt(j)) * k.u6);
-        } else {
-          S* p = (S*)(zb + fast_off<S>(a, p0, j, cx(j), cy(j), cz(j)));
-          Storage<S>::store_nt(p, g[j]);
-          // zero-gradient outlet: column nx-1 receives the same value
-          if (cx(j) == -1 && outlet) Storage<S>::store(p + 1, g[j]);
-        }
+    for (int j = 0; j < 27; ++j)
+      if ((c.om >> j) & 1u) {
+        const T v = g[j];
+        if (cx(j)) Fx += cx(j) > 0 ? v : -v;
+        if (cy(j)) Fy += cy(j) > 0 ? v : -v;
+        if (cz(j)) Fz += cz(j) > 0 ? v : -v;
       }
-    }
-  } else {
-    if (c.om) {
-#pragma unroll
-      for (int j = 0; j < 27; ++j)
-        if ((c.om >> j) & 1u) {
-          const T v = g[j];
-          if (cx(j)) Fx += cx(j) > 0 ? v : -v;
-          if (cy(j)) Fy += cy(j) > 0 ? v : -v;
-          if (cz(j)) Fz += cz(j) > 0 ? v : -v;
-        }
-      fx = (double)Fx; fy = (double)Fy; fz = (double)Fz;
-    }
-#pragma unroll
-    for (int j = 0; j < 27; ++j) {
-      const int o = 26 - j;
-      T v = g[j];
-      if (a.interp && ((c.om >> j) & 1u)) {
-        // linear interpolated bounce-back: pre-blend of the value that
-        // returns along o (completed on read when q < 1/2)
-        const T q = T(a.bq[(int64_t)c.row * 27 + j]);
-        if (q < T(0.5)) {
-          // no fluid node behind the cell: halfway bounce-back
-          if (!((c.rmask >> j) & 1u)) v = T(2) * q * g[j];
-        } else {
-          v = g[j] / (T(2) * q) + (T(2) * q - T(1)) / (T(2) * q) * g[o];
-        }
-      }
-      if (!ODD) {
-        st<S>(a, o, c.pc, v);
-        if (outlet && cx(j) == -1) st<S>(a, o, c.pc + 1, v);  // ghost column copy
-      } else {
-        const bool r = (c.rmask >> o) & 1u;
-        if (r) {
-          if (cx(j) == -1 && ((c.inlet >> o) & 1u)) v += T(wgt(j)) * k.u6;
-          st<S>(a, o, c.pc, v);
-        } else {
-          const int64_t d = c.pc + src_off(o, c);
-          st<S>(a, j, d, v);
-          // zero-gradient outlet: column nx-1 receives the same value
-          if (outlet && cx(j) == -1) st<S>(a, j, d + 1, v);
-        }
-      }
-    }
+    fx = (double)Fx; fy = (double)Fy; fz = (double)Fz;
   }
 }
 
@@ -357,7 +339,7 @@ __device__ __forceinline__ void cell_update(const StepArgs& a, const Coef<typena
 #ifndef MLBM_EDGE_PATH
 #define MLBM_EDGE_PATH 1
 #endif
-template <typename S, bool ODD, int MODE>
+template <typename S, bool NAT, int MODE>
 __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(MLBM_WAVES, 8))) void lbm_step_kernel(
     StepArgs a, Coef<typename Storage<S>::T> k) {
   const int tile = logical_tile(blockIdx.x, a.ntiles, a.remap);
@@ -370,32 +352,34 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(MLBM_W
   const int64_t n = ((int64_t)z * a.ny + y) * a.nx + x;
 
   double fx = 0.0, fy = 0.0, fz = 0.0;
-  // Tiles away from the walls, periodic faces and the obstacle's box hold
-  // only fluid cells: they skip the cell flags, so their population loads
-  // do not wait for a flag load.
-  const bool plain_tile = z > 0 && z < a.nz - 1 && tyi > 0 && tyi < a.tiles_y - 1 &&
-                          !(a.per[0] && (txi == 0 || txi == a.tiles_x - 1)) &&
-                          !(txi >= a.obox[0] && txi <= a.obox[1] && tyi >= a.obox[2] && tyi <= a.obox[3] &&
-                            z >= a.obox[4] && z <= a.obox[5]);
-  if (plain_tile) {
-    if (!a.per[0] && (txi == 0 || txi == a.tiles_x - 1))
-      cell_update<S, ODD, MODE, MLBM_EDGE_PATH>(a, k, x, y, z, n, 0, fx, fy, fz);
-    else
-      cell_update<S, ODD, MODE, 0>(a, k, x, y, z, n, 0, fx, fy, fz);
-  } else if (const uint8_t fl = a.flag[n]; fl != 2) {
-    // periodic axes wrap at their faces and walls bounce back: both take
-    // the general path; the inlet and outlet columns take the edge path
-    const bool xin = a.per[0] ? (x > 0 && x < a.nx - 1) : true;
-    const bool interior = fl == 0 && xin && y > 0 && y < a.ny - 1 && z > 0 && z < a.nz - 1;
-#ifndef MLBM_EDGE_PATH
-#define MLBM_EDGE_PATH 1
-#endif
-    const bool edge_tile = !a.per[0] && (txi == 0 || txi == a.tiles_x - 1);
-    if (!__any(!interior)) {
-      if (edge_tile) cell_update<S, ODD, MODE, MLBM_EDGE_PATH>(a, k, x, y, z, n, fl, fx, fy, fz);
-      else cell_update<S, ODD, MODE, 0>(a, k, x, y, z, n, fl, fx, fy, fz);
-    } else {
-      cell_update<S, ODD, MODE, 2>(a, k, x, y, z, n, fl, fx, fy, fz);
+  if (NAT) {
+    const uint8_t fl = a.flag[n];
+    if (fl != 2) cell_update<S, true, MODE, 2>(a, k, x, y, z, n, fl, fx, fy, fz);
+  } else {
+    // Tiles away from the walls, periodic faces and the obstacle's box hold
+    // only fluid cells: they skip the cell flags, so their population loads
+    // do not wait for a flag load.
+    const bool plain_tile = z > 0 && z < a.nz - 1 && tyi > 0 && tyi < a.tiles_y - 1 &&
+                            !(a.per[0] && (txi == 0 || txi == a.tiles_x - 1)) &&
+                            !(txi >= a.obox[0] && txi <= a.obox[1] && tyi >= a.obox[2] && tyi <= a.obox[3] &&
+                              z >= a.obox[4] && z <= a.obox[5]);
+    if (plain_tile) {
+      if (!a.per[0] && (txi == 0 || txi == a.tiles_x - 1))
+        cell_update<S, false, MODE, MLBM_EDGE_PATH>(a, k, x, y, z, n, 0, fx, fy, fz);
+      else
+        cell_update<S, false, MODE, 0>(a, k, x, y, z, n, 0, fx, fy, fz);
+    } else if (const uint8_t fl = a.flag[n]; fl != 2) {
+      // periodic axes wrap at their faces and walls bounce back: both take
+      // the general path; the inlet and outlet columns take the edge path
+      const bool xin = a.per[0] ? (x > 0 && x < a.nx - 1) : true;
+      const bool interior = fl == 0 && xin && y > 0 && y < a.ny - 1 && z > 0 && z < a.nz - 1;
+      const bool edge_tile = !a.per[0] && (txi == 0 || txi == a.tiles_x - 1);
+      if (!__any(!interior)) {
+        if (edge_tile) cell_update<S, false, MODE, MLBM_EDGE_PATH>(a, k, x, y, z, n, fl, fx, fy, fz);
+        else cell_update<S, false, MODE, 0>(a, k, x, y, z, n, fl, fx, fy, fz);
+      } else {
+        cell_update<S, false, MODE, 2>(a, k, x, y, z, n, fl, fx, fy, fz);
+      }
     }
   }
 
@@ -424,13 +408,13 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(MLBM_W
   }
 }
 
-// Bandwidth probe: the even step's memory traffic with the collision left
-// out.  Every cell of every tile loads its 27 slots and stores them to the
-// opposite slots through the same addressing, hints and tile order as the
-// stream-and-collide kernel; the swap is an involution, so an even number
-// of passes leaves the array as it was.
+// Bandwidth probe: the pull step's memory traffic with the collision left
+// out.  Every cell of every tile loads its 27 populations from the
+// upstream cells of A and stores them to itself in B, through the same
+// addressing, hints and tile order as the stream-and-collide kernel.  A is
+// only read, so the state is unchanged.
 template <typename S>
-__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(MLBM_WAVES, 8))) void swap_probe_kernel(
+__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(MLBM_WAVES, 8))) void pull_probe_kernel(
     StepArgs a) {
   using T = typename Storage<S>::T;
   const int tile = logical_tile(blockIdx.x, a.ntiles, a.remap);
@@ -440,12 +424,12 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(MLBM_W
   const int tyi = rest % a.tiles_y;
   const int z = rest / a.tiles_y;
   const int x = txi * TX + tx, y = tyi * TY + ty;
-  const char* zb = (const char*)a.A + (size_t)z * (size_t)a.zstride * sizeof(S);
-  const uint32_t p0 = (uint32_t)(((y + 1) * a.pitch + x) * (int)sizeof(S));
+  const uint32_t p0 = lane_off<S>(a, x, y);
   T g[27];
-  load_fast<S, false>(a, zb, p0, g);
+  load_fast<S>(a, plane_base<S>(a.A, a, z), p0, g);
+  char* wb = (char*)plane_base<S>(a.B, a, z);
 #pragma unroll
-  for (int j = 0; j < 27; ++j) Storage<S>::store_nt((S*)(zb + fast_off<S>(a, p0, 26 - j, 0, 0, 0)), g[j]);
+  for (int j = 0; j < 27; ++j) Storage<S>::store_nt((S*)(wb + fast_off<S>(a, p0, j, 0, 0, 0)), g[j]);
 }
 
 // Sum of the force partials in a fixed order, plus the constant weight part.
@@ -471,33 +455,21 @@ __global__ __launch_bounds__(256) void force_reduce_kernel(const double* fpart, 
   }
 }
 
-// Natural-layout state written into storage (even parity).  Slots of
-// interpolated bounce-back links with q < 1/2 hold the pre-blended part
-// f_obar - (1 - 2q) f_j: the read completes them with the incoming f_j.
+// Natural-layout state: the pre-collision populations of a cell written in
+// place into dst (the state the next step reads with NAT).
 template <typename S>
-__device__ __forceinline__ void store_natural(const StepArgs& a, int x, int y, int z, uint8_t fl,
+__device__ __forceinline__ void store_natural(void* dst, const StepArgs& a, int x, int y, int z,
                                               typename Storage<S>::T* g) {
-  using T = typename Storage<S>::T;
-  CellCtx c;
-  make_ctx(a, x, y, z, fl, c);
-  if (a.interp && c.om) {
+  const int64_t pc = cell_index(a, x, y, z);
 #pragma unroll
-    for (int j = 0; j < 27; ++j) {
-      if (((c.om >> j) & 1u) && !((c.rmask >> j) & 1u)) {
-        const T q = T(a.bq[(int64_t)c.row * 27 + j]);
-        if (q < T(0.5)) g[26 - j] -= (T(1) - T(2) * q) * g[j];
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 27; ++i) st<S>(a, i, c.pc, g[i]);
+  for (int i = 0; i < 27; ++i) st<S>(dst, a, i, pc, g[i]);
 }
 
 // Equilibrium initial state at rho = 1: fbar = w (Phi - 1) with Phi the
 // product of per-axis factors 1 + delta (delta(0) = -3a^2/2,
 // delta(+-1) = 3a^2 +- 3a), expanded so that no rest value is subtracted.
 template <typename S>
-__global__ __launch_bounds__(256) void init_kernel(StepArgs a, const double* u0) {
+__global__ __launch_bounds__(256) void init_kernel(StepArgs a, const double* u0, void* dst) {
   using T = typename Storage<S>::T;
   const int64_t N = (int64_t)a.nx * a.ny * a.nz;
   const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -507,7 +479,7 @@ __global__ __launch_bounds__(256) void init_kernel(StepArgs a, const double* u0)
   T g[27];
   if (fl == 2) {
     const int64_t pc = cell_index(a, x, y, z);
-    for (int i = 0; i < 27; ++i) st<S>(a, i, pc, T(0));
+    for (int i = 0; i < 27; ++i) st<S>(dst, a, i, pc, T(0));
     return;
   }
   T u[3] = {0, 0, 0};
@@ -536,13 +508,14 @@ __global__ __launch_bounds__(256) void init_kernel(StepArgs a, const double* u0)
     const T ph = dx + dy + dz + dx * dy + dx * dz + dy * dz + dx * dy * dz;
     g[i] = T(wgt(i)) * ph;
   }
-  store_natural<S>(a, x, y, z, fl, g);
+  store_natural<S>(dst, a, x, y, z, g);
 }
 
-// Natural-layout export of the pre-collision state (any parity): populations
-// as double [27][N], and/or moments (u, v, w, p) as float [4][N], and/or the
-// per-block mass partial.
-template <typename S, bool ODD>
+// Natural-layout export of the pre-collision state (pulled from A, or A
+// itself when it holds the natural state): populations as double [27][N],
+// and/or moments (u, v, w, p) as float [4][N], and/or the per-block mass
+// partial.
+template <typename S, bool NAT>
 __global__ __launch_bounds__(NTHREADS) void export_kernel(StepArgs a, Coef<typename Storage<S>::T> k, double* pops,
                                                           float* mom, double* mass_part) {
   using T = typename Storage<S>::T;
@@ -561,7 +534,7 @@ __global__ __launch_bounds__(NTHREADS) void export_kernel(StepArgs a, Coef<typen
     CellCtx c;
     make_ctx(a, x, y, z, fl, c);
     T g[27];
-    load_general<S, ODD>(a, k, c, g);
+    load_general<S>(a, k, c, NAT, g);
     if (pops)
       for (int i = 0; i < 27; ++i) pops[(int64_t)i * N + n] = (double)g[i];
     T drho, ux, uy, uz;
@@ -592,7 +565,7 @@ __global__ __launch_bounds__(NTHREADS) void export_kernel(StepArgs a, Coef<typen
 // Natural-layout export of a box of cells [x0, x0 + bx) x [y0, y0 + by) x
 // [z0, z0 + bz): pops [27][bz][by][bx], the same values export_kernel
 // writes for those cells.
-template <typename S, bool ODD>
+template <typename S, bool NAT>
 __global__ __launch_bounds__(256) void export_box_kernel(StepArgs a, Coef<typename Storage<S>::T> k, int x0, int y0,
                                                          int z0, int bx, int by, int bz, double* pops) {
   using T = typename Storage<S>::T;
@@ -609,13 +582,13 @@ __global__ __launch_bounds__(256) void export_box_kernel(StepArgs a, Coef<typena
   CellCtx c;
   make_ctx(a, x, y, z, fl, c);
   T g[27];
-  load_general<S, ODD>(a, k, c, g);
+  load_general<S>(a, k, c, NAT, g);
   for (int q = 0; q < 27; ++q) pops[(int64_t)q * nb + i] = (double)g[q];
 }
 
-// Natural-layout import (even parity): double fbar [27][N] -> storage.
+// Natural-layout import: double fbar [27][N] -> the natural state in dst.
 template <typename S>
-__global__ __launch_bounds__(256) void import_kernel(StepArgs a, const double* pops) {
+__global__ __launch_bounds__(256) void import_kernel(StepArgs a, const double* pops, void* dst) {
   using T = typename Storage<S>::T;
   const int64_t N = (int64_t)a.nx * a.ny * a.nz;
   const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -624,12 +597,7 @@ __global__ __launch_bounds__(256) void import_kernel(StepArgs a, const double* p
   const uint8_t fl = a.flag[n];
   T g[27];
   for (int i = 0; i < 27; ++i) g[i] = fl == 2 ? T(0) : T(pops[(int64_t)i * N + n]);
-  if (fl == 2) {
-    const int64_t pc = cell_index(a, x, y, z);
-    for (int i = 0; i < 27; ++i) st<S>(a, i, pc, T(0));
-    return;
-  }
-  store_natural<S>(a, x, y, z, fl, g);
+  store_natural<S>(dst, a, x, y, z, g);
 }
 
 // Mean fields = sums / count, zero in solid cells.
@@ -708,7 +676,9 @@ struct lbm_sim {
   int64_t pop_elems = 0;
   char* block = nullptr;     // device memory of the solver (see Layout)
   bool owns_block = false;   // false: the caller's workspace
-  void* A = nullptr;
+  void* arr[2] = {nullptr, nullptr};  // the two population lattices
+  int cur = 0;               // lattice holding the state
+  bool natural = true;       // true: it holds the natural pre-collision state
   uint8_t* d_flag = nullptr;
   int32_t* d_brow = nullptr;
   uint32_t* d_bmask = nullptr;
@@ -730,7 +700,6 @@ struct lbm_sim {
   int32_t* d_chk = nullptr;  // stability flag written by check steps
   int32_t* h_chk = nullptr;  // its pinned host copy, refreshed after each check step
   int64_t steps = 0;
-  int parity = 0;   // AA parity of the stored layout: 0 natural, 1 swapped
   int sticky = 0;
   std::string err;
   bool profiling = false;
@@ -826,50 +795,45 @@ template <> const Coef<float>& coef_for<float>(const Coefs& c) { return c.f; }
 template <> const Coef<float>& coef_for<f16s>(const Coefs& c) { return c.f; }
 template <> const Coef<float>& coef_for<bf16s>(const Coefs& c) { return c.f; }
 
-// Occupancy cap of the odd-parity FP32 step.  Its registers allow 5 waves
-// per SIMD.  Measured (kernel time over both parities):
-//   256x128x128 (32K tiles): uncapped best (0.315 ms; 0.320 at 3 waves);
-//   512x256x256 (262K tiles): 4 waves best (1.698 ms; 1.712 uncapped);
-//   1024x512x512 (2.1M tiles): 3 waves best (12.97 ms; 13.09 uncapped).
-// The larger the grid, the more the extra waves in flight only add cache
-// contention.  (The even kernel sits at 4 waves by its registers; capping it
-// lower does not help.)  The cap is dynamic LDS that the kernel does not
-// touch: with its 3 KB of static LDS, 17 KB allows 8 blocks of 2 waves per
-// CU (4 waves per SIMD), 21 KB allows 6 (3 waves per SIMD).
-static size_t odd_f32_cap_lds(int64_t ntiles) {
-  if (ntiles < (int64_t(1) << 16)) return 0;
-  if (ntiles < (int64_t(1) << 20)) return 17408;
-  return 21504;
+// Occupancy cap of the FP32 pull step through dynamic LDS the kernel does
+// not use (0: none).  With 3 KB of static LDS, 17 KB allows 8 blocks of two
+// waves per CU (4 waves per SIMD), 21 KB allows 6 (3 waves per SIMD).
+#ifndef MLBM_F32_CAP_LDS
+#define MLBM_F32_CAP_LDS 0
+#endif
+static size_t f32_cap_lds(int64_t ntiles) {
+  (void)ntiles;
+  return MLBM_F32_CAP_LDS;
 }
 
-template <typename S, bool ODD, int MODE>
+template <typename S, bool NAT, int MODE>
 static void launch_step(const StepArgs& a, const Coefs& c, hipStream_t st) {
-  const size_t lds = (ODD && std::is_same<S, float>::value) ? odd_f32_cap_lds(a.ntiles) : 0;
-  hipLaunchKernelGGL((lbm_step_kernel<S, ODD, MODE>), dim3(a.ntiles), dim3(NTHREADS), lds, st, a, coef_for<S>(c));
+  const size_t lds = (!NAT && std::is_same<S, float>::value) ? f32_cap_lds(a.ntiles) : 0;
+  hipLaunchKernelGGL((lbm_step_kernel<S, NAT, MODE>), dim3(a.ntiles), dim3(NTHREADS), lds, st, a, coef_for<S>(c));
 }
 
 template <typename S>
-static void launch_step_s(const StepArgs& a, const Coefs& c, bool odd, int mode, hipStream_t st) {
-  if (odd) {
+static void launch_step_s(const StepArgs& a, const Coefs& c, bool nat, int mode, hipStream_t st) {
+  if (nat) {
     if (mode) launch_step<S, true, 1>(a, c, st); else launch_step<S, true, 0>(a, c, st);
   } else {
     if (mode) launch_step<S, false, 1>(a, c, st); else launch_step<S, false, 0>(a, c, st);
   }
 }
 
-static void launch_step_any(int storage, const StepArgs& a, const Coefs& c, bool odd, int mode, hipStream_t st) {
+static void launch_step_any(int storage, const StepArgs& a, const Coefs& c, bool nat, int mode, hipStream_t st) {
   switch (storage) {
-    case LBM_F64: launch_step_s<double>(a, c, odd, mode, st); break;
-    case LBM_F32: launch_step_s<float>(a, c, odd, mode, st); break;
-    case LBM_F16S: launch_step_s<f16s>(a, c, odd, mode, st); break;
-    case LBM_BF16S: launch_step_s<bf16s>(a, c, odd, mode, st); break;
+    case LBM_F64: launch_step_s<double>(a, c, nat, mode, st); break;
+    case LBM_F32: launch_step_s<float>(a, c, nat, mode, st); break;
+    case LBM_F16S: launch_step_s<f16s>(a, c, nat, mode, st); break;
+    case LBM_BF16S: launch_step_s<bf16s>(a, c, nat, mode, st); break;
   }
 }
 
 template <typename S>
-static void launch_export_s(const StepArgs& a, const Coefs& c, bool odd, double* pops, float* mom, double* mp,
+static void launch_export_s(const StepArgs& a, const Coefs& c, bool nat, double* pops, float* mom, double* mp,
                             hipStream_t st) {
-  if (odd)
+  if (nat)
     hipLaunchKernelGGL((export_kernel<S, true>), dim3(a.ntiles), dim3(NTHREADS), 0, st, a, coef_for<S>(c), pops, mom,
                        mp);
   else
@@ -877,22 +841,22 @@ static void launch_export_s(const StepArgs& a, const Coefs& c, bool odd, double*
                        mom, mp);
 }
 
-static void launch_export(int storage, const StepArgs& a, const Coefs& c, bool odd, double* pops, float* mom,
+static void launch_export(int storage, const StepArgs& a, const Coefs& c, bool nat, double* pops, float* mom,
                           double* mp, hipStream_t st) {
   switch (storage) {
-    case LBM_F64: launch_export_s<double>(a, c, odd, pops, mom, mp, st); break;
-    case LBM_F32: launch_export_s<float>(a, c, odd, pops, mom, mp, st); break;
-    case LBM_F16S: launch_export_s<f16s>(a, c, odd, pops, mom, mp, st); break;
-    case LBM_BF16S: launch_export_s<bf16s>(a, c, odd, pops, mom, mp, st); break;
+    case LBM_F64: launch_export_s<double>(a, c, nat, pops, mom, mp, st); break;
+    case LBM_F32: launch_export_s<float>(a, c, nat, pops, mom, mp, st); break;
+    case LBM_F16S: launch_export_s<f16s>(a, c, nat, pops, mom, mp, st); break;
+    case LBM_BF16S: launch_export_s<bf16s>(a, c, nat, pops, mom, mp, st); break;
   }
 }
 
 template <typename S>
-static void launch_export_box_s(const StepArgs& a, const Coefs& c, bool odd, const int* box, double* pops,
+static void launch_export_box_s(const StepArgs& a, const Coefs& c, bool nat, const int* box, double* pops,
                                 hipStream_t st) {
   const int64_t nb = (int64_t)box[3] * box[4] * box[5];
   const dim3 g((unsigned)((nb + 255) / 256));
-  if (odd)
+  if (nat)
     hipLaunchKernelGGL((export_box_kernel<S, true>), g, dim3(256), 0, st, a, coef_for<S>(c), box[0], box[1], box[2],
                        box[3], box[4], box[5], pops);
   else
@@ -900,25 +864,25 @@ static void launch_export_box_s(const StepArgs& a, const Coefs& c, bool odd, con
                        box[3], box[4], box[5], pops);
 }
 
-static void launch_init(int storage, const StepArgs& a, const double* u0, hipStream_t st) {
+static void launch_init(int storage, const StepArgs& a, const double* u0, void* dst, hipStream_t st) {
   const int64_t N = (int64_t)a.nx * a.ny * a.nz;
   const dim3 g((unsigned)((N + 255) / 256));
   switch (storage) {
-    case LBM_F64: hipLaunchKernelGGL(init_kernel<double>, g, dim3(256), 0, st, a, u0); break;
-    case LBM_F32: hipLaunchKernelGGL(init_kernel<float>, g, dim3(256), 0, st, a, u0); break;
-    case LBM_F16S: hipLaunchKernelGGL(init_kernel<f16s>, g, dim3(256), 0, st, a, u0); break;
-    case LBM_BF16S: hipLaunchKernelGGL(init_kernel<bf16s>, g, dim3(256), 0, st, a, u0); break;
+    case LBM_F64: hipLaunchKernelGGL(init_kernel<double>, g, dim3(256), 0, st, a, u0, dst); break;
+    case LBM_F32: hipLaunchKernelGGL(init_kernel<float>, g, dim3(256), 0, st, a, u0, dst); break;
+    case LBM_F16S: hipLaunchKernelGGL(init_kernel<f16s>, g, dim3(256), 0, st, a, u0, dst); break;
+    case LBM_BF16S: hipLaunchKernelGGL(init_kernel<bf16s>, g, dim3(256), 0, st, a, u0, dst); break;
   }
 }
 
-static void launch_import(int storage, const StepArgs& a, const double* pops, hipStream_t st) {
+static void launch_import(int storage, const StepArgs& a, const double* pops, void* dst, hipStream_t st) {
   const int64_t N = (int64_t)a.nx * a.ny * a.nz;
   const dim3 g((unsigned)((N + 255) / 256));
   switch (storage) {
-    case LBM_F64: hipLaunchKernelGGL(import_kernel<double>, g, dim3(256), 0, st, a, pops); break;
-    case LBM_F32: hipLaunchKernelGGL(import_kernel<float>, g, dim3(256), 0, st, a, pops); break;
-    case LBM_F16S: hipLaunchKernelGGL(import_kernel<f16s>, g, dim3(256), 0, st, a, pops); break;
-    case LBM_BF16S: hipLaunchKernelGGL(import_kernel<bf16s>, g, dim3(256), 0, st, a, pops); break;
+    case LBM_F64: hipLaunchKernelGGL(import_kernel<double>, g, dim3(256), 0, st, a, pops, dst); break;
+    case LBM_F32: hipLaunchKernelGGL(import_kernel<float>, g, dim3(256), 0, st, a, pops, dst); break;
+    case LBM_F16S: hipLaunchKernelGGL(import_kernel<f16s>, g, dim3(256), 0, st, a, pops, dst); break;
+    case LBM_BF16S: hipLaunchKernelGGL(import_kernel<bf16s>, g, dim3(256), 0, st, a, pops, dst); break;
   }
 }
 
@@ -944,7 +908,7 @@ struct Resolved {
   double nu = 0, omega1 = 0;
   int mode = 0;
   double k17[5] = {0, 0, 0, 0, 0};
-  int64_t N = 0, pitch = 0, slotp = 0, zstride = 0, pop_elems = 0, ntiles = 0;
+  int64_t N = 0, slotp = 0, rowp = 0, zstride = 0, pop_elems = 0, ntiles = 0;
 };
 
 static int resolve(const lbm_params& p, Resolved& r) {
@@ -978,9 +942,9 @@ static int resolve(const lbm_params& p, Resolved& r) {
                   "omega3..5 in (0, 2)");
   }
   r.N = (int64_t)p.nx * p.ny * p.nz;
-  r.pitch = (int64_t)p.nx + 64;
-  r.slotp = r.pitch * (p.ny + 2);
-  r.zstride = 27 * r.slotp;
+  r.slotp = (int64_t)p.nx + 64;
+  r.rowp = 27 * r.slotp;
+  r.zstride = r.rowp * (p.ny + 2);
   r.pop_elems = r.zstride * (p.nz + 2);
   if (3 * r.zstride * (int64_t)storage_size(p.storage) >= (int64_t(1) << 31) || r.N >= (int64_t(1) << 31))
     return fail(nullptr, LBM_EINVAL, "grid too large (three padded planes must stay below 2 GiB)");
@@ -1055,7 +1019,7 @@ static int build_tables(const lbm_params& p, const Resolved& r, const uint8_t* s
 // distances, force slots and partials, FP64 accumulators, snapshot ring,
 // force ring, stability flag).
 struct Layout {
-  size_t A = 0, flag = 0, brow = 0, bmask = 0, bq = 0, bslot = 0, fpart = 0, acc = 0, snap = 0, forces = 0, chk = 0;
+  size_t A = 0, A1 = 0, flag = 0, brow = 0, bmask = 0, bq = 0, bslot = 0, fpart = 0, acc = 0, snap = 0, forces = 0, chk = 0;
   size_t total = 0;
 };
 
@@ -1068,7 +1032,13 @@ static Layout make_layout(const lbm_params& p, const Resolved& r, const Tables& 
     return o;
   };
   const int64_t nb = std::max<int64_t>((int64_t)t.rcell.size(), 1);
+  // each lattice has a 256-byte guard in front: the probe's pull of the
+  // corner cell reads one element before element 0 (inlet ghost of slot 0
+  // in the guard row of the guard plane)
+  (void)take(256);
   L.A = take((size_t)r.pop_elems * storage_size(p.storage));
+  (void)take(256);
+  L.A1 = take((size_t)r.pop_elems * storage_size(p.storage));
   L.flag = take((size_t)r.N);
   L.brow = take((size_t)r.N * 4);
   L.bmask = take((size_t)nb * 4);
@@ -1170,7 +1140,10 @@ extern "C" int lbm_create_in(const lbm_params* pin, const uint8_t* solid, int64_
   }
   *s->h_chk = 0;
   char* B = s->block;
-  s->A = B + lay.A;
+  s->arr[0] = B + lay.A;
+  s->arr[1] = B + lay.A1;
+  s->cur = 0;
+  s->natural = true;
   s->pop_elems = r.pop_elems;
   s->d_flag = (uint8_t*)(B + lay.flag);
   s->d_brow = (int32_t*)(B + lay.brow);
@@ -1195,7 +1168,8 @@ extern "C" int lbm_create_in(const lbm_params* pin, const uint8_t* solid, int64_
     return true;
   };
   hipStream_t st = s->stream;
-  (void)hipMemsetAsync(s->A, 0, (size_t)r.pop_elems * s->esize, st);
+  (void)hipMemsetAsync(s->arr[0], 0, (size_t)r.pop_elems * s->esize, st);
+  (void)hipMemsetAsync(s->arr[1], 0, (size_t)r.pop_elems * s->esize, st);
   (void)hipMemsetAsync(s->d_brow, 0xff, (size_t)N * 4, st);
   (void)hipMemsetAsync(s->d_chk, 0, sizeof(int32_t), st);
   if (solid) {
@@ -1224,10 +1198,11 @@ extern "C" int lbm_create_in(const lbm_params* pin, const uint8_t* solid, int64_
   if (s->d_snap) (void)hipMemsetAsync(s->d_snap, 0, (size_t)p.snap_count * N * 16, st);
 
   StepArgs& a = s->args;
-  a.A = s->A;
+  a.A = s->arr[0];
+  a.B = s->arr[1];
   a.nx = p.nx; a.ny = p.ny; a.nz = p.nz;
-  a.pitch = (int32_t)r.pitch;
   a.slotp = (int32_t)r.slotp;
+  a.rowp = (int32_t)r.rowp;
   a.zstride = (int32_t)r.zstride;
   for (int d = 0; d < 3; ++d) a.per[d] = p.periodic[d] ? 1 : 0;
   a.flag = s->d_flag;
@@ -1273,7 +1248,7 @@ extern "C" int lbm_create_in(const lbm_params* pin, const uint8_t* solid, int64_
     if (!dalloc((void**)&d_u0, (size_t)N * 24)) return bail(LBM_ENOMEM);
     (void)hipMemcpyAsync(d_u0, u0, (size_t)N * 24, hipMemcpyHostToDevice, st);
   }
-  launch_init(p.storage, a, d_u0, st);
+  launch_init(p.storage, a, d_u0, s->arr[0], st);
   e = hipStreamSynchronize(st);
   if (d_u0) (void)hipFree(d_u0);
   if (e != hipSuccess || (e = hipGetLastError()) != hipSuccess) {
@@ -1306,6 +1281,15 @@ static int ensure_force_cap(lbm_sim* s, int64_t need) {
   return LBM_OK;
 }
 
+// Kernel arguments reading the current state (A) and writing the other
+// lattice (B).
+static StepArgs state_args(const lbm_sim* s) {
+  StepArgs a = s->args;
+  a.A = s->arr[s->cur];
+  a.B = s->arr[s->cur ^ 1];
+  return a;
+}
+
 // Stability state: the flag a check step set, as last copied to the host.
 static int unstable(lbm_sim* s) {
   if (s->h_chk && *(volatile int32_t*)s->h_chk)
@@ -1332,7 +1316,7 @@ extern "C" int lbm_step(lbm_sim* s, int64_t nsteps) {
   }
   for (int64_t k = 0; k < nsteps; ++k) {
     const int64_t n = s->steps;
-    StepArgs a = s->args;
+    StepArgs a = state_args(s);
     if (s->d_acc && n >= p.avg_start) {
       a.acc = s->d_acc;
       s->nsamples++;
@@ -1354,7 +1338,7 @@ extern "C" int lbm_step(lbm_sim* s, int64_t nsteps) {
       HIPCHK(s, hipEventCreate(&e1));
       HIPCHK(s, hipEventRecord(e0, s->stream));
     }
-    launch_step_any(p.storage, a, s->coefs, s->parity != 0, s->mode, s->stream);
+    launch_step_any(p.storage, a, s->coefs, s->natural, s->mode, s->stream);
     if (s->profiling) {
       HIPCHK(s, hipEventRecord(e1, s->stream));
       s->events.emplace_back(e0, e1);
@@ -1370,7 +1354,8 @@ extern "C" int lbm_step(lbm_sim* s, int64_t nsteps) {
       s->nforces++;
     }
     s->steps++;
-    s->parity ^= 1;
+    s->cur ^= 1;
+    s->natural = false;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(s, LBM_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   }
@@ -1474,7 +1459,7 @@ extern "C" int lbm_moments(lbm_sim* s, float* out, int out_on_device) {
     HIPCHK(s, hipMalloc(&tmp, (size_t)s->N * 16));
     dst = tmp;
   }
-  launch_export(s->p.storage, s->args, s->coefs, s->parity != 0, nullptr, dst, nullptr, s->stream);
+  launch_export(s->p.storage, state_args(s), s->coefs, s->natural, nullptr, dst, nullptr, s->stream);
   if (tmp) HIPCHK(s, hipMemcpyAsync(out, tmp, (size_t)s->N * 16, hipMemcpyDeviceToHost, s->stream));
   hipError_t e = hipStreamSynchronize(s->stream);
   if (tmp) (void)hipFree(tmp);
@@ -1487,7 +1472,7 @@ extern "C" int lbm_get_populations(lbm_sim* s, double* fbar) {
   if (int rc = guard(s)) return rc;
   double* tmp = nullptr;
   HIPCHK(s, hipMalloc(&tmp, (size_t)s->N * 27 * 8));
-  launch_export(s->p.storage, s->args, s->coefs, s->parity != 0, tmp, nullptr, nullptr, s->stream);
+  launch_export(s->p.storage, state_args(s), s->coefs, s->natural, tmp, nullptr, nullptr, s->stream);
   hipError_t e = hipMemcpyAsync(fbar, tmp, (size_t)s->N * 27 * 8, hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   (void)hipFree(tmp);
@@ -1507,10 +1492,10 @@ extern "C" int lbm_get_populations_box(lbm_sim* s, int32_t x0, int32_t y0, int32
   HIPCHK(s, hipMalloc(&tmp, (size_t)nb * 27 * 8));
   const int box[6] = {x0, y0, z0, bx, by, bz};
   switch (s->p.storage) {
-    case LBM_F64: launch_export_box_s<double>(s->args, s->coefs, s->parity != 0, box, tmp, s->stream); break;
-    case LBM_F32: launch_export_box_s<float>(s->args, s->coefs, s->parity != 0, box, tmp, s->stream); break;
-    case LBM_F16S: launch_export_box_s<f16s>(s->args, s->coefs, s->parity != 0, box, tmp, s->stream); break;
-    case LBM_BF16S: launch_export_box_s<bf16s>(s->args, s->coefs, s->parity != 0, box, tmp, s->stream); break;
+    case LBM_F64: launch_export_box_s<double>(state_args(s), s->coefs, s->natural, box, tmp, s->stream); break;
+    case LBM_F32: launch_export_box_s<float>(state_args(s), s->coefs, s->natural, box, tmp, s->stream); break;
+    case LBM_F16S: launch_export_box_s<f16s>(state_args(s), s->coefs, s->natural, box, tmp, s->stream); break;
+    case LBM_BF16S: launch_export_box_s<bf16s>(state_args(s), s->coefs, s->natural, box, tmp, s->stream); break;
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(fbar, tmp, (size_t)nb * 27 * 8, hipMemcpyDeviceToHost, s->stream);
@@ -1527,13 +1512,12 @@ extern "C" int lbm_set_populations(lbm_sim* s, const double* fbar) {
   HIPCHK(s, hipMalloc(&tmp, (size_t)s->N * 27 * 8));
   hipError_t e = hipMemcpyAsync(tmp, fbar, (size_t)s->N * 27 * 8, hipMemcpyHostToDevice, s->stream);
   if (e == hipSuccess) {
-    launch_import(s->p.storage, s->args, tmp, s->stream);
+    launch_import(s->p.storage, s->args, tmp, s->arr[s->cur], s->stream);
     e = hipStreamSynchronize(s->stream);
   }
   (void)hipFree(tmp);
   if (e != hipSuccess) return fail(s, LBM_EDEVICE, hipGetErrorString(e));
-  // the natural layout is the even-parity layout
-  s->parity = 0;
+  s->natural = true;
   return LBM_OK;
 }
 
@@ -1543,7 +1527,7 @@ extern "C" int lbm_mass(lbm_sim* s, double* mass) {
   double* part = nullptr;
   const int nt = s->args.ntiles;
   HIPCHK(s, hipMalloc(&part, (size_t)nt * 8));
-  launch_export(s->p.storage, s->args, s->coefs, s->parity != 0, nullptr, nullptr, part, s->stream);
+  launch_export(s->p.storage, state_args(s), s->coefs, s->natural, nullptr, nullptr, part, s->stream);
   std::vector<double> h((size_t)nt);
   hipError_t e = hipMemcpyAsync(h.data(), part, (size_t)nt * 8, hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -1560,7 +1544,7 @@ extern "C" int lbm_mass(lbm_sim* s, double* mass) {
 struct Blob {
   char magic[8];
   int32_t nx, ny, nz, storage;
-  int64_t steps, nsamples, snap_taken, nforces, parity;
+  int64_t steps, nsamples, snap_taken, nforces, natural;
   int64_t popbytes, accbytes, snapbytes;
   int64_t fstored;  // force slots stored: every sample, or the ring's filled slots in slot order
 };
@@ -1569,10 +1553,10 @@ extern "C" int lbm_export_state(lbm_sim* s, void* blob, size_t cap, size_t* used
   if (!s || !used) return fail(s, LBM_EINVAL, "null argument");
   if (int rc = guard(s)) return rc;
   Blob h{};
-  std::memcpy(h.magic, "MLBMCKP2", 8);
+  std::memcpy(h.magic, "MLBMCKP3", 8);
   h.nx = s->p.nx; h.ny = s->p.ny; h.nz = s->p.nz; h.storage = s->p.storage;
   h.steps = s->steps; h.nsamples = s->nsamples; h.snap_taken = s->snap_taken; h.nforces = s->nforces;
-  h.parity = s->parity;
+  h.natural = s->natural ? 1 : 0;
   h.popbytes = (int64_t)(s->pop_elems * (int64_t)s->esize);
   h.accbytes = s->d_acc ? s->N * 32 : 0;
   h.snapbytes = s->d_snap ? (int64_t)s->p.snap_count * s->N * 16 : 0;
@@ -1585,7 +1569,7 @@ extern "C" int lbm_export_state(lbm_sim* s, void* blob, size_t cap, size_t* used
   char* b = (char*)blob;
   std::memcpy(b, &h, sizeof h);
   b += sizeof h;
-  HIPCHK(s, hipMemcpyAsync(b, s->A, (size_t)h.popbytes, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipMemcpyAsync(b, s->arr[s->cur], (size_t)h.popbytes, hipMemcpyDeviceToHost, s->stream));
   b += h.popbytes;
   if (h.accbytes) HIPCHK(s, hipMemcpyAsync(b, s->d_acc, (size_t)h.accbytes, hipMemcpyDeviceToHost, s->stream));
   b += h.accbytes;
@@ -1609,7 +1593,7 @@ extern "C" int lbm_import_state(lbm_sim* s, const void* blob, size_t n) {
   if (n < sizeof(Blob)) return fail(s, LBM_EINVAL, "checkpoint too short");
   Blob h;
   std::memcpy(&h, blob, sizeof h);
-  if (std::memcmp(h.magic, "MLBMCKP2", 8) || h.nx != s->p.nx || h.ny != s->p.ny || h.nz != s->p.nz ||
+  if (std::memcmp(h.magic, "MLBMCKP3", 8) || h.nx != s->p.nx || h.ny != s->p.ny || h.nz != s->p.nz ||
       h.storage != s->p.storage)
     return fail(s, LBM_EINVAL, "checkpoint does not match this object");
   const int64_t popbytes = (int64_t)(s->pop_elems * (int64_t)s->esize);
@@ -1621,7 +1605,7 @@ extern "C" int lbm_import_state(lbm_sim* s, const void* blob, size_t n) {
     return fail(s, LBM_EINVAL, "checkpoint force series does not match this object");
   size_t need = sizeof(Blob) + h.popbytes + h.accbytes + h.snapbytes + (size_t)h.fstored * 32 + 8;
   if (n < need) return fail(s, LBM_EINVAL, "checkpoint truncated");
-  HIPCHK(s, hipMemcpyAsync(s->A, b, (size_t)h.popbytes, hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipMemcpyAsync(s->arr[0], b, (size_t)h.popbytes, hipMemcpyHostToDevice, s->stream));
   b += h.popbytes;
   if (h.accbytes) HIPCHK(s, hipMemcpyAsync(s->d_acc, b, (size_t)h.accbytes, hipMemcpyHostToDevice, s->stream));
   b += h.accbytes;
@@ -1642,7 +1626,8 @@ extern "C" int lbm_import_state(lbm_sim* s, const void* blob, size_t n) {
   s->snap_steps.assign((const int64_t*)b, (const int64_t*)b + nss);
   HIPCHK(s, hipStreamSynchronize(s->stream));
   s->steps = h.steps; s->nsamples = h.nsamples; s->snap_taken = h.snap_taken; s->nforces = h.nforces;
-  s->parity = (int)h.parity;
+  s->cur = 0;
+  s->natural = h.natural != 0;
   return LBM_OK;
 }
 
@@ -1683,17 +1668,17 @@ extern "C" int lbm_bandwidth_probe(lbm_sim* s, int32_t passes, double* ms_per_pa
   if (!s || !ms_per_pass) return fail(s, LBM_EINVAL, "null argument");
   if (int rc = guard(s)) return rc;
   if (passes <= 0 || passes % 2) return fail(s, LBM_EINVAL, "passes must be positive and even");
-  const StepArgs& a = s->args;
+  const StepArgs a = state_args(s);
   hipEvent_t e0, e1;
   HIPCHK(s, hipEventCreate(&e0));
   HIPCHK(s, hipEventCreate(&e1));
   HIPCHK(s, hipEventRecord(e0, s->stream));
   for (int i = 0; i < passes; ++i) {
     switch (s->p.storage) {
-      case LBM_F64: hipLaunchKernelGGL(swap_probe_kernel<double>, dim3(a.ntiles), dim3(NTHREADS), 0, s->stream, a); break;
-      case LBM_F32: hipLaunchKernelGGL(swap_probe_kernel<float>, dim3(a.ntiles), dim3(NTHREADS), 0, s->stream, a); break;
-      case LBM_F16S: hipLaunchKernelGGL(swap_probe_kernel<f16s>, dim3(a.ntiles), dim3(NTHREADS), 0, s->stream, a); break;
-      default: hipLaunchKernelGGL(swap_probe_kernel<bf16s>, dim3(a.ntiles), dim3(NTHREADS), 0, s->stream, a); break;
+      case LBM_F64: hipLaunchKernelGGL(pull_probe_kernel<double>, dim3(a.ntiles), dim3(NTHREADS), 0, s->stream, a); break;
+      case LBM_F32: hipLaunchKernelGGL(pull_probe_kernel<float>, dim3(a.ntiles), dim3(NTHREADS), 0, s->stream, a); break;
+      case LBM_F16S: hipLaunchKernelGGL(pull_probe_kernel<f16s>, dim3(a.ntiles), dim3(NTHREADS), 0, s->stream, a); break;
+      default: hipLaunchKernelGGL(pull_probe_kernel<bf16s>, dim3(a.ntiles), dim3(NTHREADS), 0, s->stream, a); break;
     }
   }
   HIPCHK(s, hipEventRecord(e1, s->stream));

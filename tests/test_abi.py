@@ -155,16 +155,17 @@ def test_reynolds_number_maps_to_viscosity_in_the_library():
 
 
 def test_workspace_size_counts_every_region():
-    """lbm_workspace_size: populations in the padded plane layout
-    (27 slots of (nx + 64) x (ny + 2) per padded plane, nz + 2 planes),
-    flags, rows, tables, accumulators (32 B per cell), snapshot ring
-    (16 B per cell per snapshot), each region rounded up to 256 bytes."""
+    """lbm_workspace_size: two population lattices in the padded layout
+    (27 slots of nx + 64 per padded row, ny + 2 rows, nz + 2 planes),
+    each behind a 256-byte guard, flags, rows, tables, accumulators (32 B
+    per cell), snapshot ring (16 B per cell per snapshot), each region
+    rounded up to 256 bytes."""
     import numpy as np
     shape = (128, 16, 8)
     nx, ny, nz = shape
     N = nx * ny * nz
     r256 = lambda b: (b + 255) // 256 * 256  # noqa: E731
-    base = lambda es, nb: (r256(27 * (nx + 64) * (ny + 2) * (nz + 2) * es) + r256(N) + r256(4 * N)  # noqa: E731
+    base = lambda es, nb: (2 * (256 + r256(27 * (nx + 64) * (ny + 2) * (nz + 2) * es)) + r256(N) + r256(4 * N)  # noqa: E731
                            + r256(4 * max(nb, 1)) + r256(216 * max(nb, 1)) + 256)
     n = ctypes.c_size_t()
     L, p = _params(shape, avg_start=-1, force_every=0)
