@@ -211,8 +211,16 @@ def run_lbm(name, steps, warmup, probe=True):
 
 
 def copy_rate(reps=10):
-    """Rate of a plain 4 GiB device-to-device copy (torch's copy kernel), the
-    bandwidth a streaming library kernel gets on this device."""
+    """Rate of the library's plain streaming copy of 4 GiB (one 16-byte
+    vector per lane, non-temporal stores), the attainable bandwidth of a
+    streaming kernel on this device."""
+    from paper_2606_16765_amd.lbm import copy_bandwidth
+    return copy_bandwidth(4 * 2 ** 30, reps)
+
+
+def torch_copy_rate(reps=10):
+    """Rate of a plain 4 GiB device-to-device copy with torch's copy kernel,
+    for comparison."""
     import torch
     a = torch.empty(2 ** 30, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
@@ -271,6 +279,18 @@ def fno_cpu_baseline():
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     return dict(value=1.0 / dt, unit="samples/s", cores=threads, kind="oracle",
                 sample=f"one FP64 forward pass at batch 1, 128x64x64, width 32, 4 layers, 32x32x16 modes: {dt:.1f} s")
+
+
+def precision_oracle_means():
+    """The FP64 CPU oracle's mean fields of the precision study's laminar
+    case (Re 1000, 128x64x64, 10,000 steps), written by
+    tests/golden/make_precision_reference.py; {} when absent."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "precision_ref_re1000.npz")
+    if not os.path.exists(path):
+        return {}
+    d = np.load(path)
+    return {float(d["re"]): d["means"]}
 
 
 def c1_leg(steps=2000, warmup=50):
@@ -386,18 +406,22 @@ def main():
                    "u_in": 0.05, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(res["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(res["achieved"] / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "lbm_step_kernel (stream-collide, both AA parities)",
+                     "kernel": "lbm_step_kernel (stream-collide, two-lattice pull)",
                      "bytes_per_launch": res["bytes_per_launch"], "bytes_per_cell_update": res["bytes_per_cell"],
                      "kernel_ms": round(res["kernel_ms"], 4),
                      "same_pattern_probe_gbs": round(res["probe_gbs"], 1),
                      "frac_of_probe": round(res["achieved"] / res["probe_gbs"], 4),
-                     "probe_note": "lbm_bandwidth_probe: the even step's loads and stores of every cell with the "
+                     "probe_note": "lbm_bandwidth_probe: the pull step's loads and stores of every cell with the "
                                    "collision left out, same kernel layout and tile order"},
     }
     cgbs = copy_rate()
     line["roofline"]["plain_copy_gbs"] = round(cgbs, 1)
     line["roofline"]["frac_of_copy"] = round(res["achieved"] / cgbs, 4)
-    log(f"plain 4 GiB copy: {cgbs:.0f} GB/s")
+    line["roofline"]["plain_copy_note"] = ("lbm_copy_bandwidth: 4 GiB read + 4 GiB written, one 16-byte vector per "
+                                           "lane, non-temporal stores")
+    tgbs = torch_copy_rate()
+    line["roofline"]["torch_copy_gbs"] = round(tgbs, 1)
+    log(f"plain 4 GiB copy: {cgbs:.0f} GB/s (library), {tgbs:.0f} GB/s (torch)")
     if "cd" in res:
         line["physics"] = {"cd_mean_second_half": round(res["cd"], 4), "cl_rms_second_half": round(res["cl_rms"], 4),
                            "strouhal": None,
@@ -421,7 +445,7 @@ def main():
         from paper_2606_16765_amd import precision
         log("precision study ...")
         line["precision"] = {
-            "error_vs_f64": precision.error_table(log=log),
+            "error_vs_f64": precision.error_table(log=log, oracle_means=precision_oracle_means()),
             "throughput": precision.throughput(log=log),
         }
     if not args.no_cpu_baseline:

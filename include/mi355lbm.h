@@ -261,6 +261,16 @@ int lbm_profile_read(lbm_sim* s, double* total_ms, int64_t* launches);
  * LBM_EDEVICE.                                                             */
 int lbm_bandwidth_probe(lbm_sim* s, int32_t passes, double* ms_per_pass);
 
+/* Plain-copy bandwidth (measurement support, not a step of the method): a
+ * device-to-device copy of `bytes` (a multiple of 16) between two buffers
+ * the call allocates and frees, one 16-byte vector per lane with
+ * non-temporal stores, run `passes` times after two warm-up passes on
+ * hip_stream; *ms_per_pass receives the event-timed average (read + write =
+ * 2 * bytes per pass).  The attainable-bandwidth reference next to the
+ * roofline of lbm_step.  Synchronises.  Errors: LBM_EINVAL, LBM_ENOMEM,
+ * LBM_EDEVICE.                                                             */
+int lbm_copy_bandwidth(int64_t bytes, int32_t passes, void* hip_stream, double* ms_per_pass);
+
 void lbm_destroy(lbm_sim* s);
 const char* lbm_last_error(const lbm_sim* s); /* s may be NULL: global error */
 

@@ -60,6 +60,7 @@ def _sig(L):
     L.lbm_profile.argtypes = [vp, ctypes.c_int]
     L.lbm_profile_read.argtypes = [vp, P(dbl), P(i64)]
     L.lbm_bandwidth_probe.argtypes = [vp, i32, P(dbl)]
+    L.lbm_copy_bandwidth.argtypes = [i64, i32, vp, P(dbl)]
     L.lbm_destroy.argtypes = [vp]
     L.lbm_destroy.restype = None
     L.lbm_last_error.argtypes = [vp]

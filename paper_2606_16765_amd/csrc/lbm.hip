@@ -432,6 +432,17 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(MLBM_W
   for (int j = 0; j < 27; ++j) Storage<S>::store_nt((S*)(wb + fast_off<S>(a, p0, j, 0, 0, 0)), g[j]);
 }
 
+// Plain streaming copy: one 16-byte vector per lane, non-temporal stores,
+// one pass over the buffer with no loop.  The attainable-bandwidth
+// reference of the roofline (the fastest of the copy forms measured on
+// MI355X: 6.3 TB/s against 4.5-5.4 TB/s for grid-stride loops).
+typedef float float4_v __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void copy_probe_kernel(const float4_v* __restrict__ src, float4_v* __restrict__ dst,
+                                                         int64_t n4) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n4) __builtin_nontemporal_store(src[i], dst + i);
+}
+
 // Sum of the force partials in a fixed order, plus the constant weight part.
 __global__ __launch_bounds__(256) void force_reduce_kernel(const double* fpart, int nslots, double c0, double c1,
                                                            double c2, double* out) {
@@ -796,14 +807,16 @@ template <> const Coef<float>& coef_for<f16s>(const Coefs& c) { return c.f; }
 template <> const Coef<float>& coef_for<bf16s>(const Coefs& c) { return c.f; }
 
 // Occupancy cap of the FP32 pull step through dynamic LDS the kernel does
-// not use (0: none).  With 3 KB of static LDS, 17 KB allows 8 blocks of two
-// waves per CU (4 waves per SIMD), 21 KB allows 6 (3 waves per SIMD).
+// not use.  With its 3 KB of static LDS, 17 KB allows 8 blocks of two waves
+// per CU (4 waves per SIMD).  Kernel time per launch at 1024x512x512, three
+// to four repeats each: 9.78-9.92 ms capped, 10.22-10.41 ms without; at
+// 256x128x128 the cap makes no difference (0.273-0.276 ms), so small grids
+// run without it.
 #ifndef MLBM_F32_CAP_LDS
-#define MLBM_F32_CAP_LDS 0
+#define MLBM_F32_CAP_LDS 17408
 #endif
 static size_t f32_cap_lds(int64_t ntiles) {
-  (void)ntiles;
-  return MLBM_F32_CAP_LDS;
+  return ntiles >= (int64_t(1) << 16) ? (size_t)MLBM_F32_CAP_LDS : 0;
 }
 
 template <typename S, bool NAT, int MODE>
@@ -1689,6 +1702,47 @@ extern "C" int lbm_bandwidth_probe(lbm_sim* s, int32_t passes, double* ms_per_pa
   (void)hipEventDestroy(e1);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(s, LBM_EDEVICE, hipGetErrorString(e));
+  *ms_per_pass = (double)ms / passes;
+  return LBM_OK;
+}
+
+extern "C" int lbm_copy_bandwidth(int64_t bytes, int32_t passes, void* hip_stream, double* ms_per_pass) {
+  if (!ms_per_pass || bytes <= 0 || bytes % 16 || passes <= 0)
+    return fail(nullptr, LBM_EINVAL, "bytes must be a positive multiple of 16, passes positive");
+  const int64_t n4 = bytes / 16;
+  if ((n4 + 255) / 256 > 0x7fffffff) return fail(nullptr, LBM_EINVAL, "copy too large");
+  const hipStream_t st = (hipStream_t)hip_stream;
+  void *a = nullptr, *b = nullptr;
+  hipError_t e = hipMalloc(&a, (size_t)bytes);
+  if (e == hipSuccess) e = hipMalloc(&b, (size_t)bytes);
+  if (e != hipSuccess) {
+    if (a) (void)hipFree(a);
+    return fail(nullptr, e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, hipGetErrorString(e));
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const dim3 grid((unsigned)((n4 + 255) / 256));
+  e = hipMemsetAsync(a, 0, (size_t)bytes, st);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) {
+    for (int w = 0; w < 2; ++w)
+      hipLaunchKernelGGL(copy_probe_kernel, grid, dim3(256), 0, st, (const float4_v*)a, (float4_v*)b, n4);
+    e = hipEventRecord(e0, st);
+  }
+  if (e == hipSuccess) {
+    for (int i = 0; i < passes; ++i)
+      hipLaunchKernelGGL(copy_probe_kernel, grid, dim3(256), 0, st, (const float4_v*)a, (float4_v*)b, n4);
+    e = hipEventRecord(e1, st);
+  }
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(a);
+  (void)hipFree(b);
+  if (e != hipSuccess) return fail(nullptr, LBM_EDEVICE, hipGetErrorString(e));
   *ms_per_pass = (double)ms / passes;
   return LBM_OK;
 }

@@ -283,6 +283,16 @@ class Lbm:
         return ms.value, n.value
 
 
+def copy_bandwidth(nbytes=4 * 2 ** 30, passes=10, stream=None):
+    """GB/s (read + write) of the library's plain streaming copy of nbytes
+    between two device buffers: the attainable-bandwidth reference."""
+    L = load()
+    ms = ctypes.c_double()
+    check(L.lbm_copy_bandwidth(int(nbytes), int(passes), _stream_handle(stream), ctypes.byref(ms)), None,
+          "lbm_copy_bandwidth")
+    return 2.0 * nbytes / (ms.value / 1e3) / 1e9
+
+
 def bytes_per_cell_update(storage, averaging=False):
     """Algorithmic HBM bytes of one cell update: 27 reads and 27 writes of the
     stored population type, one flag byte, and with averaging a read-modify-
