@@ -378,6 +378,78 @@ int fno_field_minmax_noalloc(const float* x, int64_t S, int32_t C, int64_t P, vo
 void fno_destroy(fno_net* n);
 const char* fno_last_error(const fno_net* n);
 
+/* ------------------------------------------------------------------------ */
+/* 3D U-Net surrogate (paper Sec. 4, Table 2; architecture of App. A.2): a
+ * 3D encoder-decoder with skip connections on the same inputs and outputs
+ * as the Fourier operator.  Encoder: four stages of widths widths[0..3],
+ * each two blocks of 3x3x3 convolution (one cell of zero padding, no bias),
+ * batch normalisation and ReLU, then 2x2x2 max pooling.  Bottleneck: two
+ * blocks of `bottleneck` channels.  Decoder: trilinear upsampling by two
+ * (half-pixel centres, clamped at the faces), concatenation with the skip
+ * connection of the same level (upsampled channels first), two blocks.
+ * Head: 1x1x1 convolution with bias to cout channels and a sigmoid.
+ * Batch normalisation uses the batch statistics (biased variance,
+ * eps 1e-5) in training passes, which also move the running statistics
+ * 10% of the way (unbiased variance); evaluation passes use the running
+ * statistics.  Convolutions run as BF16 MFMA with FP32 accumulation;
+ * batch-norm statistics and reductions in FP64.                            */
+typedef struct unet_net unet_net;
+
+typedef struct {
+  int32_t nx, ny, nz;       /* grid; positive multiples of 16                  */
+  int32_t cin, cout;        /* input / output channels, 1..8 (4, 4)            */
+  int32_t widths[4];        /* encoder widths (32, 64, 128, 256); powers of
+                               two in [8, 2048]                               */
+  int32_t bottleneck;       /* bottleneck width (512); power of two <= 2048    */
+  int32_t max_batch;        /* largest batch the workspaces are sized for     */
+} unet_params;
+
+/* Parameter vector layout (FP32, unet_param_count entries): per block in
+ * forward order (enc0a, enc0b, ..., enc3b, bottleneck a, b, dec3a, dec3b, ...,
+ * dec0a, dec0b) the convolution weight [out][in][27] (tap
+ * t = 9 (dx + 1) + 3 (dy + 1) + (dz + 1) reads the input at
+ * (x + dx, y + dy, z + dz)), the batch-norm scale [out] and shift [out];
+ * then the head weight [cout][widths[0]] and bias [cout].  -1 for invalid
+ * parameters.                                                               */
+int64_t unet_param_count(const unet_params* p);
+
+/* Create with seeded parameters (convolutions and head U(+-1/sqrt(fan_in)),
+ * batch-norm scale 1, shift 0; running mean 0, variance 1); allocates the
+ * training workspaces for max_batch.  Errors: LBM_EINVAL, LBM_ENOMEM,
+ * LBM_EDEVICE.                                                             */
+int unet_create(const unet_params* p, uint64_t seed, void* hip_stream, unet_net** out);
+
+/* Copy the FP32 parameter vector in or out (host pointers); synchronises.  */
+int unet_set_params(unet_net* n, const float* host_params, int64_t count);
+int unet_get_params(unet_net* n, float* host_params, int64_t count);
+
+/* Running statistics, host float [2][sum of block widths]: all running
+ * means in block order, then all running variances.  Synchronises.         */
+int unet_bn_stats(unet_net* n, float* host, int64_t count);
+
+/* Forward pass: x device BF16 [B][cin][nx][ny][nz], y device FP32
+ * [B][cout][nx][ny][nz].  training != 0 normalises with the batch
+ * statistics and updates the running ones.  Asynchronous.                  */
+int unet_forward(unet_net* n, const uint16_t* x, int32_t B, int32_t training, float* y);
+
+/* Training-mode forward pass, masked MSE (as fno_loss_grad: mask device
+ * uint8 [nx][ny][nz], target device FP32 [B][cout][nx][ny][nz]) and the
+ * gradient of every parameter; host_grads (may be NULL) receives a copy,
+ * *loss (may be NULL) the loss (LBM_EINVAL for an empty mask when the loss
+ * is requested).  Asynchronous unless a host output is requested.          */
+int unet_loss_grad(unet_net* n, const uint16_t* x, const float* target, const uint8_t* mask, int32_t B, float* loss,
+                   float* host_grads);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the last gradients.   */
+int unet_adam_step(unet_net* n, float lr);
+
+/* unet_loss_grad followed by unet_adam_step.                               */
+int unet_train_step(unet_net* n, const uint16_t* x, const float* target, const uint8_t* mask, int32_t B, float lr,
+                    float* loss);
+
+void unet_destroy(unet_net* n);
+const char* unet_last_error(const unet_net* n);
+
 #ifdef __cplusplus
 }
 #endif

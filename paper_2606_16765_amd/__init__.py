@@ -10,3 +10,6 @@ __all__ = ["Lbm", "nu_from_re", "bytes_per_cell_update", "STORAGE"]
 from .fno import Fno, FnoError  # noqa: F401,E402
 
 __all__ += ["Fno", "FnoError"]
+from .unet import Unet, UnetError  # noqa: F401,E402
+
+__all__ += ["Unet", "UnetError"]

@@ -37,6 +37,11 @@ class FnoParams(ctypes.Structure):
                                  ("ff_hidden", ctypes.c_int32)]
 
 
+class UnetParams(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("nx", "ny", "nz", "cin", "cout")] + \
+               [("widths", ctypes.c_int32 * 4), ("bottleneck", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+
+
 def _sig(L):
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     P = ctypes.POINTER
@@ -82,6 +87,21 @@ def _sig(L):
         L.fno_field_minmax_noalloc.argtypes = [vp, i64, i32, i64, vp, vp, vp]
         L.fno_field_scale.argtypes = [vp, i64, i32, i64, vp, vp, i32, vp]
         L.fno_last_error.restype = ctypes.c_char_p
+    if hasattr(L, "unet_create"):
+        L.unet_param_count.argtypes = [P(UnetParams)]
+        L.unet_param_count.restype = i64
+        L.unet_create.argtypes = [P(UnetParams), ctypes.c_uint64, vp, P(vp)]
+        L.unet_set_params.argtypes = [vp, vp, i64]
+        L.unet_get_params.argtypes = [vp, vp, i64]
+        L.unet_bn_stats.argtypes = [vp, vp, i64]
+        L.unet_forward.argtypes = [vp, vp, i32, i32, vp]
+        L.unet_loss_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp]
+        L.unet_adam_step.argtypes = [vp, ctypes.c_float]
+        L.unet_train_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, vp]
+        L.unet_destroy.argtypes = [vp]
+        L.unet_destroy.restype = None
+        L.unet_last_error.argtypes = [vp]
+        L.unet_last_error.restype = ctypes.c_char_p
 
 
 def load():

@@ -1,0 +1,787 @@
+// gfx950 kernels of the 3D U-Net surrogate (paper Sec. 4, Table 2; the
+// architecture of App. A.2): implicit-GEMM 3x3x3 convolution on BF16 MFMA
+// with FP32 accumulation and fused batch-norm statistics, split-K weight
+// gradients, batch normalisation with ReLU and its adjoint, 2x2x2 max
+// pooling, trilinear upsampling by two and their adjoints, the 1x1x1
+// sigmoid head with the masked MSE, and Adam.
+//
+// Activations are channels-last, [B][X][Y][Z][C] with C fastest, so that the
+// eight consecutive channels an MFMA operand lane needs are one 16-byte load.
+// Every channel count on the device is a multiple of 8 (the 4 input channels
+// are padded to 8 with zeros).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace munet {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// FP32 -> BF16 with round to nearest even (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint16_t f2bf(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
+__device__ __forceinline__ uint32_t f2bf2(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+__device__ __forceinline__ float bflo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bfhi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
+__device__ __forceinline__ f32x4 mfma16(const bf16x8& a, const bf16x8& b, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void unpack8(const uint4& w, float* f) {
+  f[0] = bflo(w.x); f[1] = bfhi(w.x); f[2] = bflo(w.y); f[3] = bfhi(w.y);
+  f[4] = bflo(w.z); f[5] = bfhi(w.z); f[6] = bflo(w.w); f[7] = bfhi(w.w);
+}
+__device__ __forceinline__ uint4 pack8(const float* f) {
+  return uint4{f2bf2(f[0], f[1]), f2bf2(f[2], f[3]), f2bf2(f[4], f[5]), f2bf2(f[6], f[7])};
+}
+
+// ----------------------------------------------------------- convolution
+// out[v][co] = sum over taps t and input channels ci of
+//              wt[co][t * cin + ci] * in(v + offset(t))[ci]
+// (cross-correlation with one cell of zero padding; taps = 27, tap
+// t = 9 (dx + 1) + 3 (dy + 1) + (dz + 1), or taps = 1 for a pointwise map).
+// The input is the channel concatenation of in0 (c0 channels) and in1 (c1
+// channels, may be null with c1 = 0), both channels-last BF16.  wt is BF16
+// [coutp][kp], kp = K = taps * cin rounded up to 32, zero padded.  out is
+// FP32 [V][cout].  With stats set, each block also writes the sum and the
+// sum of squares of its outputs per channel to stats[blockIdx.x][cout][2]
+// (batch-norm statistics, reduced in a fixed order afterwards).
+//
+// Block: four waves, each an MFMA tile of 32 output channels x 64 voxels
+// (2 x 4 tiles of 16 x 16); operands are loaded straight from global memory
+// (the 27 taps re-read each input row through the caches).
+struct ConvArgs {
+  const uint16_t* in0;
+  const uint16_t* in1;
+  int32_t c0, c1;
+  const uint16_t* wt;
+  int32_t kp;
+  float* out;
+  int32_t cout;
+  int32_t taps;
+  int32_t B, X, Y, Z;
+  float* stats;
+};
+
+constexpr int CV_VOX = 256;  // voxels per block (4 waves x 64)
+constexpr int CV_CO = 32;    // output channels per block
+
+__global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t YZ = (int64_t)a.Y * a.Z;
+  const int64_t V = (int64_t)a.B * a.X * YZ;
+  const int cin = a.c0 + a.c1;
+  const int K = a.taps * cin;
+  const int co0 = blockIdx.y * CV_CO;
+  const int64_t vb0 = (int64_t)blockIdx.x * CV_VOX + wave * 64;
+  int vx[4], vy[4], vz[4];
+  int64_t vv[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int64_t v = vb0 + 16 * c + (lane & 15);
+    vv[c] = v < V ? v : -1;
+    const int64_t w = v < V ? v : 0;
+    vz[c] = (int)(w % a.Z);
+    vy[c] = (int)((w / a.Z) % a.Y);
+    vx[c] = (int)((w / YZ) % a.X);
+  }
+  f32x4 acc[2][4];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[m][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int kl = 8 * (lane >> 4);
+  const uint16_t* w0 = a.wt + (int64_t)(co0 + (lane & 15)) * a.kp + kl;
+  const uint16_t* w1 = w0 + (int64_t)16 * a.kp;
+  for (int k0 = 0; k0 < a.kp; k0 += 32) {
+    const int k = k0 + kl;
+    bf16x8 bv[4];
+    if (k < K) {
+      const int t = a.taps == 1 ? 0 : k / cin;
+      const int ci = k - t * cin;
+      const int dx = a.taps == 1 ? 0 : t / 9 - 1, dy = a.taps == 1 ? 0 : (t / 3) % 3 - 1,
+                dz = a.taps == 1 ? 0 : t % 3 - 1;
+      const bool first = ci < a.c0;
+      const uint16_t* src = first ? a.in0 : a.in1;
+      const int cs = first ? a.c0 : a.c1;
+      const int cc = first ? ci : ci - a.c0;
+      const int64_t off = dx * YZ + dy * a.Z + dz;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int nx = vx[c] + dx, ny = vy[c] + dy, nz = vz[c] + dz;
+        const bool ok = vv[c] >= 0 && nx >= 0 && nx < a.X && ny >= 0 && ny < a.Y && nz >= 0 && nz < a.Z;
+        if (ok) {
+          bv[c] = *(const bf16x8*)(src + (vv[c] + off) * cs + cc);
+        } else {
+          bv[c] = bf16x8{};
+        }
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bv[c] = bf16x8{};
+    }
+    const bf16x8 a0 = *(const bf16x8*)(w0 + k0);
+    const bf16x8 a1 = *(const bf16x8*)(w1 + k0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      acc[0][c] = mfma16(a0, bv[c], acc[0][c]);
+      acc[1][c] = mfma16(a1, bv[c], acc[1][c]);
+    }
+  }
+  // lane holds out[voxel vb0 + 16c + (lane & 15)][co0 + 16m + 4 (lane >> 4) + r]
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const int cb = co0 + 16 * m + 4 * (lane >> 4);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (vv[c] < 0) continue;
+      float* o = a.out + vv[c] * a.cout + cb;
+      if (cb + 3 < a.cout) {
+        *(float4*)o = float4{acc[m][c][0], acc[m][c][1], acc[m][c][2], acc[m][c][3]};
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (cb + r < a.cout) o[r] = acc[m][c][r];
+      }
+    }
+  }
+  if (a.stats) {
+    // per channel: sums over this block's voxels (padding voxels hold 0)
+    __shared__ float red[4][CV_CO][2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float s = 0.f, q = 0.f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          s += acc[m][c][r];
+          q += acc[m][c][r] * acc[m][c][r];
+        }
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+          s += __shfl_xor(s, o);
+          q += __shfl_xor(q, o);
+        }
+        if ((lane & 15) == 0) {
+          red[wave][16 * m + 4 * (lane >> 4) + r][0] = s;
+          red[wave][16 * m + 4 * (lane >> 4) + r][1] = q;
+        }
+      }
+    __syncthreads();
+    if (threadIdx.x < 2 * CV_CO) {
+      const int col = threadIdx.x >> 1, h = threadIdx.x & 1;
+      const float v = red[0][col][h] + red[1][col][h] + red[2][col][h] + red[3][col][h];
+      if (co0 + col < a.cout) a.stats[((int64_t)blockIdx.x * a.cout + co0 + col) * 2 + h] = v;
+    }
+  }
+}
+
+// --------------------------------------------------------- weight gradient
+// part[chunk][co][k] = sum over the chunk's voxels v of
+//                      dz[v][co] * in(v + offset(t))[ci],   k = t * cin + ci
+// (the adjoint of conv_kernel with respect to its weights; chunks of the
+// voxel range are reduced afterwards in a fixed order).  Block: a 64 x 64
+// tile of (co, k), the chunk walked 64 voxels at a time; both operands are
+// transposed through LDS so that an MFMA lane reads 8 consecutive voxels.
+struct WgradArgs {
+  const uint16_t* dz;   // [V][cout] BF16
+  int32_t cout;
+  const uint16_t* in0;
+  const uint16_t* in1;
+  int32_t c0, c1;
+  int32_t taps;
+  int32_t B, X, Y, Z;
+  int64_t chunk;        // voxels per chunk, a multiple of 64
+  float* part;          // [nchunk][cout][K]
+};
+
+constexpr int WG_T = 64;      // tile rows (co) and columns (k)
+constexpr int WG_VS = 72;     // LDS row stride in elements (64 voxels + 8)
+
+__global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t sd[WG_T * WG_VS];
+  __shared__ __attribute__((aligned(16))) uint16_t sx[WG_T * WG_VS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
+  const int64_t YZ = (int64_t)a.Y * a.Z;
+  const int64_t V = (int64_t)a.B * a.X * YZ;
+  const int cin = a.c0 + a.c1;
+  const int K = a.taps * cin;
+  const int co0 = blockIdx.x * WG_T, k0 = blockIdx.y * WG_T;
+  const int64_t v0 = (int64_t)blockIdx.z * a.chunk;
+  const int64_t v1 = v0 + a.chunk < V ? v0 + a.chunk : V;
+  f32x4 acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // loader roles: 512 vectors of 8 channels per tile, two per thread
+  for (int64_t vs = v0; vs < v1; vs += 64) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = t + 256 * h;         // 0..511
+      const int vl = e & 63, g = e >> 6; // voxel in the step, 8-column group
+      const int64_t v = vs + vl;
+      // dz tile: channels co0 + 8g .. +8 of voxel v -> sd[co][voxel]
+      uint4 w = uint4{0u, 0u, 0u, 0u};
+      const int cc = co0 + 8 * g;
+      if (v < v1 && cc < a.cout) w = *(const uint4*)(a.dz + v * a.cout + cc);
+      const uint16_t* wv = (const uint16_t*)&w;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sd[(8 * g + j) * WG_VS + vl] = wv[j];
+      // input tile: columns k0 + 8g .. +8 (one tap, 8 channels) of voxel v
+      uint4 x = uint4{0u, 0u, 0u, 0u};
+      const int k = k0 + 8 * g;
+      if (v < v1 && k < K) {
+        const int tp = a.taps == 1 ? 0 : k / cin;
+        const int ci = k - tp * cin;
+        const int dx = a.taps == 1 ? 0 : tp / 9 - 1, dy = a.taps == 1 ? 0 : (tp / 3) % 3 - 1,
+                  dz = a.taps == 1 ? 0 : tp % 3 - 1;
+        const int z = (int)(v % a.Z), y = (int)((v / a.Z) % a.Y), xx = (int)((v / YZ) % a.X);
+        const int nx = xx + dx, ny = y + dy, nz = z + dz;
+        if (nx >= 0 && nx < a.X && ny >= 0 && ny < a.Y && nz >= 0 && nz < a.Z) {
+          const bool first = ci < a.c0;
+          const uint16_t* src = first ? a.in0 : a.in1;
+          const int cs = first ? a.c0 : a.c1;
+          x = *(const uint4*)(src + (v + dx * YZ + dy * a.Z + dz) * cs + (first ? ci : ci - a.c0));
+        }
+      }
+      const uint16_t* xv = (const uint16_t*)&x;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sx[(8 * g + j) * WG_VS + vl] = xv[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const bf16x8 av = *(const bf16x8*)(sd + (16 * wave + (lane & 15)) * WG_VS + 32 * s + 8 * (lane >> 4));
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const bf16x8 bv = *(const bf16x8*)(sx + (16 * c + (lane & 15)) * WG_VS + 32 * s + 8 * (lane >> 4));
+        acc[c] = mfma16(av, bv, acc[c]);
+      }
+    }
+    __syncthreads();
+  }
+  float* part = a.part + (int64_t)blockIdx.z * a.cout * K;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int k = k0 + 16 * c + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int co = co0 + 16 * wave + 4 * (lane >> 4) + r;
+      if (co < a.cout && k < K) part[(int64_t)co * K + k] = acc[c][r];
+    }
+  }
+}
+
+// dW[co][ci][t] (the parameter layout) = sum over chunks of
+// part[.][co][t * cinp + ci] for co < cout, ci < cin (cinp: the device
+// channel count the convolution ran with; coutp: the partials' row count)
+__global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* part, int nchunk, int coutp, int cout, int cin,
+                                                           int cinp, int taps, float* dW) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)cout * cin * taps;
+  if (i >= n) return;
+  const int t = (int)(i % taps);
+  const int ci = (int)((i / taps) % cin);
+  const int co = (int)(i / ((int64_t)taps * cin));
+  const int64_t K = (int64_t)taps * cinp;
+  const int64_t col = (int64_t)co * K + (int64_t)t * cinp + ci;
+  float s = 0.f;
+  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * coutp * K + col];
+  dW[i] = s;
+}
+
+// --------------------------------------------------------- batch norm
+// Per channel c: mean and biased variance of the block's conv outputs over
+// n voxels from the per-block partial sums (FP64 reduction in a fixed
+// order); scale = gamma / sqrt(var + eps), shift = beta - mean * scale;
+// running mean/var move 10% of the way (unbiased variance).  One block per
+// channel.  With train = 0 the scale and shift come from the running
+// statistics instead.
+__global__ __launch_bounds__(256) void bn_finalize_kernel(const float* stats, int64_t nblk, int C, double n,
+                                                          const float* gamma, const float* beta, float* rmean,
+                                                          float* rvar, float* mean_out, float* istd_out,
+                                                          float* scale, float* shift, int train) {
+  const int c = blockIdx.x;
+  __shared__ double rs[256], rq[256];
+  double s = 0.0, q = 0.0;
+  if (train)
+    for (int64_t b = threadIdx.x; b < nblk; b += 256) {
+      s += (double)stats[(b * C + c) * 2];
+      q += (double)stats[(b * C + c) * 2 + 1];
+    }
+  rs[threadIdx.x] = s;
+  rq[threadIdx.x] = q;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      rs[threadIdx.x] += rs[threadIdx.x + w];
+      rq[threadIdx.x] += rq[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double mean, var;
+    if (train) {
+      mean = rs[0] / n;
+      var = rq[0] / n - mean * mean;
+      if (var < 0.0) var = 0.0;
+      rmean[c] = (float)(0.9 * (double)rmean[c] + 0.1 * mean);
+      rvar[c] = (float)(0.9 * (double)rvar[c] + 0.1 * var * n / (n - 1.0));
+    } else {
+      mean = rmean[c];
+      var = rvar[c];
+    }
+    const double is = 1.0 / sqrt(var + 1e-5);
+    mean_out[c] = (float)mean;
+    istd_out[c] = (float)is;
+    scale[c] = (float)(gamma[c] * is);
+    shift[c] = (float)(beta[c] - mean * gamma[c] * is);
+  }
+}
+
+// a[v][c] = BF16(max(z[v][c] * scale[c] + shift[c], 0)), eight channels per thread
+__global__ __launch_bounds__(256) void bn_relu_kernel(const float* z, int64_t V, int C, const float* scale,
+                                                      const float* shift, uint16_t* act) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int g = C / 8;
+  if (e >= V * g) return;
+  const int c0 = (int)(e % g) * 8;
+  const float4 p = *(const float4*)(z + e * 8), q = *(const float4*)(z + e * 8 + 4);
+  const float v[8] = {p.x, p.y, p.z, p.w, q.x, q.y, q.z, q.w};
+  float o[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) o[j] = fmaxf(v[j] * scale[c0 + j] + shift[c0 + j], 0.f);
+  *(uint4*)(act + e * 8) = pack8(o);
+}
+
+// Adjoint of batch norm and ReLU, pass 1: per block and channel, the sums
+// of dy and dy * xhat over the block's voxels, with dy = g where the
+// activation is positive and xhat = (z - mean) * istd.  Block: 256 voxels x
+// all channels, thread (voxel lane, channel group) -> partial[blk][C][2].
+__global__ __launch_bounds__(256) void bn_bwd_reduce_kernel(const float* g, const float* z, int64_t V, int C,
+                                                            const float* scale, const float* shift,
+                                                            const float* mean, const float* istd, float* partial) {
+  extern __shared__ float sm[];  // [threads][8][2]
+  const int groups = C / 8;
+  const int per = 256 / groups;  // voxels handled in parallel (groups divides 256)
+  const int gi = threadIdx.x % groups, vi = threadIdx.x / groups;
+  const int c0 = gi * 8;
+  float s[8], q[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) { s[j] = 0.f; q[j] = 0.f; }
+  const int64_t vb = (int64_t)blockIdx.x * 256;
+  for (int64_t v = vb + vi; v < vb + 256 && v < V; v += per) {
+    const float4 za = *(const float4*)(z + v * C + c0), zb = *(const float4*)(z + v * C + c0 + 4);
+    const float4 ga = *(const float4*)(g + v * C + c0), gb = *(const float4*)(g + v * C + c0 + 4);
+    const float zz[8] = {za.x, za.y, za.z, za.w, zb.x, zb.y, zb.z, zb.w};
+    const float gg[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float y = zz[j] * scale[c0 + j] + shift[c0 + j];
+      const float dy = y > 0.f ? gg[j] : 0.f;
+      s[j] += dy;
+      q[j] += dy * (zz[j] - mean[c0 + j]) * istd[c0 + j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    sm[(threadIdx.x * 8 + j) * 2] = s[j];
+    sm[(threadIdx.x * 8 + j) * 2 + 1] = q[j];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < C * 2; e += 256) {
+    const int c = e >> 1, h = e & 1, gg = c / 8, j = c % 8;
+    float acc = 0.f;
+    for (int p = 0; p < per; ++p) acc += sm[((p * groups + gg) * 8 + j) * 2 + h];
+    partial[((int64_t)blockIdx.x * C + c) * 2 + h] = acc;
+  }
+}
+
+// pass 2 coefficients per channel: dbeta = sum dy, dgamma = sum dy * xhat
+// (FP64 reduction of the partials in a fixed order), written to the
+// gradient vector; k1 = gamma * istd, k2 = dbeta / n, k3 = dgamma / n.
+__global__ __launch_bounds__(256) void bn_bwd_finalize_kernel(const float* partial, int64_t nblk, int C, double n,
+                                                              const float* gamma, const float* istd, float* dgamma,
+                                                              float* dbeta, float* coef) {
+  const int c = blockIdx.x;
+  __shared__ double rs[256], rq[256];
+  double s = 0.0, q = 0.0;
+  for (int64_t b = threadIdx.x; b < nblk; b += 256) {
+    s += (double)partial[(b * C + c) * 2];
+    q += (double)partial[(b * C + c) * 2 + 1];
+  }
+  rs[threadIdx.x] = s;
+  rq[threadIdx.x] = q;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      rs[threadIdx.x] += rs[threadIdx.x + w];
+      rq[threadIdx.x] += rq[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    dbeta[c] = (float)rs[0];
+    dgamma[c] = (float)rq[0];
+    coef[3 * c] = gamma[c] * istd[c];
+    coef[3 * c + 1] = (float)(rs[0] / n);
+    coef[3 * c + 2] = (float)(rq[0] / n);
+  }
+}
+
+// pass 2: dz = k1 (dy - k2 - xhat k3), stored BF16 (the operand of both
+// adjoint convolutions), eight channels per thread
+__global__ __launch_bounds__(256) void bn_bwd_apply_kernel(const float* g, const float* z, int64_t V, int C,
+                                                           const float* scale, const float* shift, const float* mean,
+                                                           const float* istd, const float* coef, uint16_t* dz) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= V * (C / 8)) return;
+  const int c0 = (int)(e % (C / 8)) * 8;
+  const float4 za = *(const float4*)(z + e * 8), zb = *(const float4*)(z + e * 8 + 4);
+  const float4 ga = *(const float4*)(g + e * 8), gb = *(const float4*)(g + e * 8 + 4);
+  const float zz[8] = {za.x, za.y, za.z, za.w, zb.x, zb.y, zb.z, zb.w};
+  const float gg[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+  float o[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int c = c0 + j;
+    const float y = zz[j] * scale[c] + shift[c];
+    const float dy = y > 0.f ? gg[j] : 0.f;
+    const float xh = (zz[j] - mean[c]) * istd[c];
+    o[j] = coef[3 * c] * (dy - coef[3 * c + 1] - xh * coef[3 * c + 2]);
+  }
+  *(uint4*)(dz + e * 8) = pack8(o);
+}
+
+// ------------------------------------------------------ pooling, upsampling
+// 2x2x2 max pooling, channels-last BF16, eight channels per thread
+__global__ __launch_bounds__(256) void maxpool_kernel(const uint16_t* in, int B, int X, int Y, int Z, int C,
+                                                      uint16_t* out) {
+  const int Xo = X / 2, Yo = Y / 2, Zo = Z / 2, g = C / 8;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)B * Xo * Yo * Zo * g;
+  if (e >= n) return;
+  const int c0 = (int)(e % g) * 8;
+  int64_t r = e / g;
+  const int zo = (int)(r % Zo); r /= Zo;
+  const int yo = (int)(r % Yo); r /= Yo;
+  const int xo = (int)(r % Xo);
+  const int b = (int)(r / Xo);
+  float m[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) m[j] = -INFINITY;
+  for (int d = 0; d < 8; ++d) {
+    const int x = 2 * xo + (d >> 2), y = 2 * yo + ((d >> 1) & 1), z = 2 * zo + (d & 1);
+    float f[8];
+    unpack8(*(const uint4*)(in + ((((int64_t)b * X + x) * Y + y) * Z + z) * C + c0), f);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) m[j] = fmaxf(m[j], f[j]);
+  }
+  *(uint4*)(out + e * 8) = pack8(m);
+}
+
+// Adjoint of max pooling plus a second gradient of the pooled tensor's
+// input: gin[v] = (v is the first maximum of its window, scanned x, y, z
+// with z fastest ? gout[window] : 0) + gadd[v], FP32.  gadd has row stride
+// sadd and channel offset oadd (the skip part of a concatenation's
+// gradient), or is null.
+__global__ __launch_bounds__(256) void maxpool_bwd_kernel(const uint16_t* in, const float* gout, int B, int X, int Y,
+                                                          int Z, int C, const float* gadd, int sadd, int oadd,
+                                                          float* gin) {
+  const int Xo = X / 2, Yo = Y / 2, Zo = Z / 2, g = C / 8;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)B * Xo * Yo * Zo * g;
+  if (e >= n) return;
+  const int c0 = (int)(e % g) * 8;
+  int64_t r = e / g;
+  const int zo = (int)(r % Zo); r /= Zo;
+  const int yo = (int)(r % Yo); r /= Yo;
+  const int xo = (int)(r % Xo);
+  const int b = (int)(r / Xo);
+  float m[8];
+  int arg[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) { m[j] = -INFINITY; arg[j] = 0; }
+  int64_t vox[8];
+  for (int d = 0; d < 8; ++d) {
+    const int x = 2 * xo + (d >> 2), y = 2 * yo + ((d >> 1) & 1), z = 2 * zo + (d & 1);
+    vox[d] = (((int64_t)b * X + x) * Y + y) * Z + z;
+    float f[8];
+    unpack8(*(const uint4*)(in + vox[d] * C + c0), f);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (f[j] > m[j]) { m[j] = f[j]; arg[j] = d; }
+  }
+  const float* go = gout + e * 8;
+  for (int d = 0; d < 8; ++d) {
+    float o[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o[j] = arg[j] == d ? go[j] : 0.f;
+    if (gadd) {
+      const float* ga = gadd + vox[d] * sadd + oadd + c0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) o[j] += ga[j];
+    }
+    float* gi = gin + vox[d] * C + c0;
+    *(float4*)gi = float4{o[0], o[1], o[2], o[3]};
+    *(float4*)(gi + 4) = float4{o[4], o[5], o[6], o[7]};
+  }
+}
+
+// one axis of the half-pixel linear upsampling: output index o reads inputs
+// i0 (weight 3/4) and i1 (1/4), clamped at the faces
+__device__ __forceinline__ void up_taps(int o, int n, int& i0, int& i1) {
+  i0 = o >> 1;
+  i1 = (o & 1) ? (i0 + 1 < n ? i0 + 1 : n - 1) : (i0 > 0 ? i0 - 1 : 0);
+}
+
+// trilinear upsampling by 2 (half-pixel centres), channels-last BF16 in
+// [B][X][Y][Z][C] -> out [B][2X][2Y][2Z][C]
+__global__ __launch_bounds__(256) void upsample_kernel(const uint16_t* in, int B, int X, int Y, int Z, int C,
+                                                       uint16_t* out) {
+  const int Xo = 2 * X, Yo = 2 * Y, Zo = 2 * Z, g = C / 8;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)B * Xo * Yo * Zo * g;
+  if (e >= n) return;
+  const int c0 = (int)(e % g) * 8;
+  int64_t r = e / g;
+  const int zo = (int)(r % Zo); r /= Zo;
+  const int yo = (int)(r % Yo); r /= Yo;
+  const int xo = (int)(r % Xo);
+  const int b = (int)(r / Xo);
+  int xi[2], yi[2], zi[2];
+  up_taps(xo, X, xi[0], xi[1]);
+  up_taps(yo, Y, yi[0], yi[1]);
+  up_taps(zo, Z, zi[0], zi[1]);
+  const float w[2] = {0.75f, 0.25f};
+  float o[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) o[j] = 0.f;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        float f[8];
+        unpack8(*(const uint4*)(in + ((((int64_t)b * X + xi[a]) * Y + yi[bb]) * Z + zi[c]) * C + c0), f);
+        const float wt = w[a] * w[bb] * w[c];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) o[j] += wt * f[j];
+      }
+  *(uint4*)(out + e * 8) = pack8(o);
+}
+
+// adjoint weights of one axis: the input index i receives from the outputs
+// 2i, 2i + 1 (3/4 each), 2i - 1 and 2i + 2 (1/4 each, where they exist) and
+// at a face from the clamped output (1/4 more)
+__device__ __forceinline__ int up_adj(int i, int n, int* o, float* w) {
+  int k = 0;
+  o[k] = 2 * i; w[k++] = 0.75f;
+  o[k] = 2 * i + 1; w[k++] = 0.75f;
+  o[k] = i > 0 ? 2 * i - 1 : 0; w[k++] = 0.25f;
+  o[k] = i < n - 1 ? 2 * i + 2 : 2 * n - 1; w[k++] = 0.25f;
+  return k;
+}
+
+// Adjoint of upsample_kernel: gin [B][X][Y][Z][C] (FP32) from gout
+// [B][2X][2Y][2Z][*] read with row stride sout from channel 0 (the upsampled
+// part of a concatenation's gradient)
+__global__ __launch_bounds__(256) void upsample_bwd_kernel(const float* gout, int sout, int B, int X, int Y, int Z,
+                                                           int C, float* gin) {
+  const int g = C / 8;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)B * X * Y * Z * g;
+  if (e >= n) return;
+  const int c0 = (int)(e % g) * 8;
+  int64_t r = e / g;
+  const int z = (int)(r % Z); r /= Z;
+  const int y = (int)(r % Y); r /= Y;
+  const int x = (int)(r % X);
+  const int b = (int)(r / X);
+  int ox[4], oy[4], oz[4];
+  float wx[4], wy[4], wz[4];
+  up_adj(x, X, ox, wx);
+  up_adj(y, Y, oy, wy);
+  up_adj(z, Z, oz, wz);
+  const int Xo = 2 * X, Yo = 2 * Y, Zo = 2 * Z;
+  float o[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) o[j] = 0.f;
+  for (int a = 0; a < 4; ++a)
+    for (int bb = 0; bb < 4; ++bb)
+      for (int c = 0; c < 4; ++c) {
+        const float wt = wx[a] * wy[bb] * wz[c];
+        const float* gp = gout + ((((int64_t)b * Xo + ox[a]) * Yo + oy[bb]) * Zo + oz[c]) * sout + c0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) o[j] += wt * gp[j];
+      }
+  float* gi = gin + e * 8;
+  *(float4*)gi = float4{o[0], o[1], o[2], o[3]};
+  *(float4*)(gi + 4) = float4{o[4], o[5], o[6], o[7]};
+}
+
+// ------------------------------------------------------------------- I/O
+// network input [B][cin][X][Y][Z] BF16 -> channels-last [V][8] BF16, zero
+// padded beyond cin
+__global__ __launch_bounds__(256) void input_kernel(const uint16_t* x, int64_t P, int B, int cin, uint16_t* out) {
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= (int64_t)B * P) return;
+  const int64_t b = v / P, p = v % P;
+  uint16_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int c = 0; c < cin; ++c) w[c] = x[(b * cin + c) * P + p];
+  *(uint4*)(out + v * 8) = uint4{w[0] | ((uint32_t)w[1] << 16), w[2] | ((uint32_t)w[3] << 16),
+                                 w[4] | ((uint32_t)w[5] << 16), w[6] | ((uint32_t)w[7] << 16)};
+}
+
+// head: y[b][o][p] = sigmoid(sum_c W[o][c] a[v][c] + bias[o]), FP32
+// channels-first output, W FP32 [cout][C] (C % 8 == 0, cout <= 8)
+__global__ __launch_bounds__(256) void head_kernel(const uint16_t* act, int64_t P, int B, int C, const float* W,
+                                                   const float* bias, int cout, float* y) {
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= (int64_t)B * P) return;
+  float s[8];
+  for (int o = 0; o < cout; ++o) s[o] = bias[o];
+  for (int c0 = 0; c0 < C; c0 += 8) {
+    float f[8];
+    unpack8(*(const uint4*)(act + v * C + c0), f);
+    for (int o = 0; o < cout; ++o)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s[o] += W[o * C + c0 + j] * f[j];
+  }
+  const int64_t b = v / P, p = v % P;
+  for (int o = 0; o < cout; ++o) y[(b * cout + o) * P + p] = 1.f / (1.f + expf(-s[o]));
+}
+
+// number of nonzero mask cells (one block, fixed order) to out[0], times
+// mul (samples x channels: the loss denominator) to out[2]
+__global__ __launch_bounds__(256) void mask_count_kernel(const uint8_t* mask, int64_t P, double mul, double* out) {
+  __shared__ double r[256];
+  double s = 0.0;
+  for (int64_t p = threadIdx.x; p < P; p += 256) s += mask[p] ? 1.0 : 0.0;
+  r[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) r[threadIdx.x] += r[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = r[0];
+    out[2] = r[0] * mul;
+  }
+}
+
+// Loss and head adjoint: with cnt = B * cout * (mask cells), per voxel
+// dlogit[o] = 2 (y - t) mask / cnt * y (1 - y), stored BF16 in dlog[v][8]
+// (zero beyond cout; the operand of the head's weight gradient);
+// gact[v][c] = sum_o W[o][c] dlogit[o] (FP32); per block partials of the
+// loss numerator and of the bias gradient: part[blk][0], part[blk][1 + o].
+__global__ __launch_bounds__(256) void head_bwd_kernel(const uint16_t* act, const float* y, const float* t,
+                                                       const uint8_t* mask, const double* cnt, int64_t P, int B, int C,
+                                                       const float* W, int cout, float* gact, uint16_t* dlog,
+                                                       float* part) {
+  __shared__ float sm[256][9];
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (int i = 0; i < 9; ++i) sm[threadIdx.x][i] = 0.f;
+  if (v < (int64_t)B * P) {
+    const int64_t b = v / P, p = v % P;
+    const float inv = cnt[0] > 0.0 ? (float)(2.0 / cnt[0]) : 0.f;
+    const bool in = mask[p] != 0;
+    float dl[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float loss = 0.f;
+    for (int o = 0; o < cout; ++o) {
+      const float yy = y[(b * cout + o) * P + p];
+      const float d = in ? yy - t[(b * cout + o) * P + p] : 0.f;
+      loss += d * d;
+      dl[o] = d * inv * yy * (1.f - yy);
+      sm[threadIdx.x][1 + o] = dl[o];
+    }
+    sm[threadIdx.x][0] = loss;
+    *(uint4*)(dlog + v * 8) = pack8(dl);
+    for (int c0 = 0; c0 < C; c0 += 8) {
+      float g[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) g[j] = 0.f;
+      for (int o = 0; o < cout; ++o)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) g[j] += W[o * C + c0 + j] * dl[o];
+      float* gp = gact + v * C + c0;
+      *(float4*)gp = float4{g[0], g[1], g[2], g[3]};
+      *(float4*)(gp + 4) = float4{g[4], g[5], g[6], g[7]};
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 1 + cout) {
+    float s = 0.f;
+    for (int k = 0; k < 256; ++k) s += sm[k][threadIdx.x];
+    part[(int64_t)blockIdx.x * 9 + threadIdx.x] = s;
+  }
+}
+
+// sums of the head partials over blocks in a fixed order: the loss (divided
+// by cnt) and the bias gradient; one block per entry (entry 0 the loss)
+__global__ __launch_bounds__(256) void head_reduce_kernel(const float* part, int64_t nblk, const double* cnt,
+                                                          double* loss, float* dbias) {
+  const int i = blockIdx.x;
+  __shared__ double r[256];
+  double s = 0.0;
+  for (int64_t b = threadIdx.x; b < nblk; b += 256) s += (double)part[b * 9 + i];
+  r[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) r[threadIdx.x] += r[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (i == 0) loss[0] = cnt[0] > 0.0 ? r[0] / cnt[0] : 0.0;
+    else dbias[i - 1] = (float)r[0];
+  }
+}
+
+// ---------------------------------------------------------- parameters
+// forward operand: wt[co][t * cinp + ci] = BF16(W[co][ci][t]) for co < cout,
+// ci < cin, zero elsewhere ([coutp][kp])
+__global__ __launch_bounds__(256) void pack_fwd_kernel(const float* W, int cout, int cin, int cinp, int taps,
+                                                       int coutp, int kp, uint16_t* wt) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)coutp * kp) return;
+  const int co = (int)(e / kp), k = (int)(e % kp);
+  const int t = k / cinp, ci = k % cinp;
+  float v = 0.f;
+  if (co < cout && t < taps && ci < cin) v = W[((int64_t)co * cin + ci) * taps + t];
+  wt[e] = f2bf(v);
+}
+
+// adjoint operand (flipped taps, roles of the channels exchanged):
+// wb[ci][t * cout + co] = BF16(W[co][ci][taps - 1 - t]) for ci < cin; rows
+// up to cinp_out, zero elsewhere ([rows][kp])
+__global__ __launch_bounds__(256) void pack_bwd_kernel(const float* W, int cout, int cin, int taps, int rows, int kp,
+                                                       uint16_t* wb) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)rows * kp) return;
+  const int ci = (int)(e / kp), k = (int)(e % kp);
+  const int t = k / cout, co = k % cout;
+  float v = 0.f;
+  if (ci < cin && t < taps) v = W[((int64_t)co * cin + ci) * taps + (taps - 1 - t)];
+  wb[e] = f2bf(v);
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(float* theta, const float* g, float* m, float* v, int64_t n,
+                                                   float lr, float b1, float b2, float c1, float c2, float eps) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  theta[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+}  // namespace munet

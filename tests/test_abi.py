@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_functions():
     txt = open(os.path.join(ROOT, "include", "mi355lbm.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*((?:lbm|fno)_[a-z_0-9]+)\s*\(", txt, flags=re.M)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*((?:lbm|fno|unet)_[a-z_0-9]+)\s*\(", txt, flags=re.M)
     return sorted(set(names))
 
 
