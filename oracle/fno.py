@@ -23,6 +23,15 @@ layer is a residual block around a pointwise feed-forward network,
       s = R(W_l . T(v))                         the same spectral convolution
       v = v + W2_l GELU(W1_l s + b1_l) + b2_l   width -> ff_hidden -> width
 with no bypass channel map and no activation on the residual stream.
+Factorized FNO (arch = "ffno", Table 2 and App. A.2 after Tran et al.): the
+same residual feed-forward block as the hybrid, with the spectral
+convolution split into one 1D convolution per axis and summed,
+      s = sum_{d in x, y, z} R_d(W_{d,l} . T_d(v))
+      T_d  1D real DFT along axis d, modes k = 0..m_d - 1
+           (V_k = sum_n v_n exp(-2 pi i k n / N_d))
+      W    per-mode complex mixing of the channels, Y_k[o] = sum_c V_k[c] W[k][c][o]
+      R_d  1D c2r inverse along d: (1/N_d) sum_k c_k Re(Y_k exp(+2 pi i k n / N_d)),
+           c_0 = 1, c_k = 2 for k >= 1 (m_d <= N_d / 2, so no Nyquist term)
 Loss: mean squared error over the cells of a mask (App. A.2, inner region),
 all samples and output channels.  Optimiser: Adam (beta 0.9, 0.999,
 eps 1e-8).  The projection is a GELU MLP by default; proj = "siren" gives
@@ -34,7 +43,9 @@ Parameter vector layout (shared with the GPU library's C ABI):
   index j -> kx = j for j < mx else j - 2mx, likewise ky), then for the
   FNO the pointwise W [width][width] (out, in) and bias [width], for the
   hybrid W1 [ff_hidden][width], b1 [ff_hidden], W2 [width][ff_hidden],
-  b2 [width];
+  b2 [width]; for the factorized FNO the spectral block is the three axis
+  weights Wx [mx][width][width][2], Wy [my][...], Wz [mz][...] (mode, in,
+  out, re/im) followed by the hybrid's W1, b1, W2, b2;
   proj W1 [hidden][width], b1 [hidden], W2 [cout][hidden], b2 [cout].
 """
 from dataclasses import dataclass
@@ -63,11 +74,21 @@ class Shape:
     ff_hidden: int = 128
 
 
+AXES = (("x", 2), ("y", 3), ("z", 4))  # factorized FNO: weight name suffix, array axis of [B][C][X][Y][Z]
+
+
+def axis_modes(s: Shape):
+    """Retained modes per axis of the factorized FNO."""
+    return {"x": s.mx, "y": s.my, "z": s.mz}
+
+
 def param_count(s: Shape) -> int:
     w = s.width
     n = w * s.cin + w
     spec = (2 * s.mx) * (2 * s.my) * s.mz * w * w * 2
-    if s.arch == "hybrid":
+    if s.arch == "ffno":
+        spec = (s.mx + s.my + s.mz) * w * w * 2
+    if s.arch in ("hybrid", "ffno"):
         n += s.layers * (spec + 2 * s.ff_hidden * w + s.ff_hidden + w)
     else:
         n += s.layers * (spec + w * w + w)
@@ -90,6 +111,15 @@ def unpack(theta, s: Shape):
     p = {"P": take(w, s.cin), "p": take(w)}
     p["layers"] = []
     for _ in range(s.layers):
+        if s.arch == "ffno":
+            L = {}
+            for a, m in axis_modes(s).items():
+                wa = take(m, w, w, 2)
+                L["W" + a] = wa[..., 0] + 1j * wa[..., 1]          # [k][c_in][c_out]
+            H = s.ff_hidden
+            L.update({"W1": take(H, w), "b1": take(H), "W2": take(w, H), "b2": take(w)})
+            p["layers"].append(L)
+            continue
         ws = take(2 * s.mx, 2 * s.my, s.mz, w, w, 2)
         # complex weights as [c_in][c_out][kx][ky][kz]
         W = (ws[..., 0] + 1j * ws[..., 1]).transpose(3, 4, 0, 1, 2)
@@ -109,6 +139,10 @@ def unpack(theta, s: Shape):
 def pack(p, s: Shape):
     parts = [p["P"].ravel(), p["p"].ravel()]
     for L in p["layers"]:
+        if s.arch == "ffno":
+            parts += [np.stack([L["W" + a].real, L["W" + a].imag], -1).ravel() for a, _ in AXES]
+            parts += [L["W1"].ravel(), L["b1"].ravel(), L["W2"].ravel(), L["b2"].ravel()]
+            continue
         W = L["W"].transpose(2, 3, 4, 0, 1)
         ws = np.stack([W.real, W.imag], -1)
         if s.arch == "hybrid":
@@ -171,6 +205,58 @@ def adjoint_inverse_dft(g, mats, s: Shape):
     return forward_dft(g, mats) * ckz / (s.nx * s.ny * s.nz)
 
 
+def axis_dft(v, axis, m):
+    """V[..., k, ...] = sum_n v[..., n, ...] exp(-2 pi i k n / N), k = 0..m-1,
+    along one axis (the factorized FNO's per-axis transform)."""
+    N = v.shape[axis]
+    F = np.exp(-2j * np.pi * np.outer(np.arange(m), np.arange(N)) / N)
+    return np.moveaxis(np.tensordot(v, F, axes=([axis], [1])), -1, axis)
+
+
+def axis_idft(Y, axis, N):
+    """c2r inverse along one axis: (1/N) sum_k c_k Re(Y_k exp(+2 pi i k n / N)),
+    c_0 = 1, c_k = 2 for k >= 1."""
+    m = Y.shape[axis]
+    ck = np.where(np.arange(m) == 0, 1.0, 2.0)
+    E = np.exp(2j * np.pi * np.outer(np.arange(m), np.arange(N)) / N) * ck[:, None]
+    return np.moveaxis(np.tensordot(Y, E, axes=([axis], [0])), -1, axis).real / N
+
+
+def axis_adjoint_dft(G, axis, N):
+    """Adjoint of axis_dft as a real-linear map: Re(sum_k G_k exp(+i theta))."""
+    m = G.shape[axis]
+    E = np.exp(2j * np.pi * np.outer(np.arange(m), np.arange(N)) / N)
+    return np.moveaxis(np.tensordot(G, E, axes=([axis], [0])), -1, axis).real
+
+
+def axis_adjoint_idft(g, axis, m):
+    """Adjoint of axis_idft: (c_k / N) times the forward transform of g."""
+    N = g.shape[axis]
+    ck = np.where(np.arange(m) == 0, 1.0, 2.0)
+    shape = [1] * g.ndim
+    shape[axis] = m
+    return axis_dft(g, axis, m) * (ck / N).reshape(shape)
+
+
+def axis_mix(V, W, axis):
+    """Y[b, o, .., k, ..] = sum_c V[b, c, .., k, ..] W[k][c][o] (mode along axis)."""
+    Vm = np.moveaxis(V, axis, -1)
+    return np.moveaxis(np.einsum("bcijk,kco->boijk", Vm, W), -1, axis)
+
+
+def ffno_spectral(v, L, s: Shape, cache=None):
+    """s = sum over the three axes of R_d(W_d . T_d(v)); the per-axis modes
+    are kept in cache["Vd"] when a cache list is given."""
+    out = np.zeros_like(v)
+    modes = axis_modes(s)
+    for a, ax in AXES:
+        V = axis_dft(v, ax, modes[a])
+        if cache is not None:
+            cache.append(V)
+        out = out + axis_idft(axis_mix(V, L["W" + a], ax), ax, v.shape[ax])
+    return out
+
+
 def gelu(x):
     return 0.5 * x * (1.0 + erf(x / math.sqrt(2.0)))
 
@@ -206,6 +292,15 @@ def forward(theta, x, s: Shape, mats=None):
     cache["v"] = []
     for li, L in enumerate(p["layers"]):
         cache["v"].append(v)
+        if s.arch == "ffno":
+            Vd = []
+            sc = ffno_spectral(v, L, s, Vd)
+            z = pointwise(L["W1"], sc, L["b1"])
+            cache.setdefault("Vd", []).append(Vd)
+            cache.setdefault("s", []).append(sc)
+            cache.setdefault("z", []).append(z)
+            v = v + pointwise(L["W2"], gelu(z), L["b2"])
+            continue
         V = forward_dft(v, mats)
         Y = np.einsum("bck...,cok...->bok...", V, L["W"])
         cache.setdefault("V", []).append(V)
@@ -256,6 +351,22 @@ def backward(theta, cache, gy, s: Shape, mats=None):
     # Fourier layers in reverse
     for li in range(s.layers - 1, -1, -1):
         L = p["layers"][li]
+        if s.arch == "ffno":
+            z, sc = cache["z"][li], cache["s"][li]
+            gL = {"W2": np.tensordot(gv, gelu(z), axes=(red, red)), "b2": gv.sum(axis=red)}
+            gz = pointwise(L["W2"].T, gv) * gelu_grad(z)
+            gL["W1"] = np.tensordot(gz, sc, axes=(red, red))
+            gL["b1"] = gz.sum(axis=red)
+            gs = pointwise(L["W1"].T, gz)
+            modes = axis_modes(s)
+            for (a, ax), V in zip(AXES, cache["Vd"][li]):
+                gY = axis_adjoint_idft(gs, ax, modes[a])
+                Vm, gYm = np.moveaxis(V, ax, -1), np.moveaxis(gY, ax, -1)
+                gL["W" + a] = np.einsum("bcijk,boijk->kco", np.conj(Vm), gYm)
+                gV = np.moveaxis(np.einsum("boijk,kco->bcijk", gYm, np.conj(L["W" + a])), -1, ax)
+                gv = gv + axis_adjoint_dft(gV, ax, gs.shape[ax])
+            g["layers"][li] = gL
+            continue
         if s.arch == "hybrid":
             # v' = v + W2 GELU(z) + b2, z = W1 s + b1, s = R(W . T(v))
             z, sc = cache["z"][li], cache["s"][li]
@@ -306,6 +417,14 @@ def init_params(s: Shape, seed=0):
     w = s.width
     p = {"P": rng.uniform(-1, 1, (w, s.cin)) / math.sqrt(s.cin), "p": np.zeros(w), "layers": []}
     for _ in range(s.layers):
+        if s.arch == "ffno":
+            H = s.ff_hidden
+            L = {"W" + a: (rng.uniform(0, 1, (m, w, w)) + 1j * rng.uniform(0, 1, (m, w, w))) / (w * w)
+                 for a, m in axis_modes(s).items()}
+            L.update({"W1": rng.uniform(-1, 1, (H, w)) / math.sqrt(w), "b1": np.zeros(H),
+                      "W2": rng.uniform(-1, 1, (w, H)) / math.sqrt(H), "b2": np.zeros(w)})
+            p["layers"].append(L)
+            continue
         W = (rng.uniform(0, 1, (w, w, 2 * s.mx, 2 * s.my, s.mz)) + 1j * rng.uniform(0, 1, (w, w, 2 * s.mx, 2 * s.my, s.mz)))
         if s.arch == "hybrid":
             H = s.ff_hidden
@@ -336,4 +455,5 @@ def inner_box_mask(s: Shape):
 __all__ = ["Shape", "param_count", "unpack", "pack", "dft_matrices", "forward_dft", "inverse_dft", "forward",
            "backward", "masked_mse", "adam", "init_params", "gelu", "gelu_grad", "proj_act", "proj_act_grad",
            "inner_box_mask", "mode_indices",
-           "adjoint_forward_dft", "adjoint_inverse_dft"]
+           "adjoint_forward_dft", "adjoint_inverse_dft", "axis_dft", "axis_idft", "axis_adjoint_dft",
+           "axis_adjoint_idft", "axis_mix", "ffno_spectral", "axis_modes", "AXES"]
