@@ -285,6 +285,11 @@ const char* lbm_last_error(const lbm_sim* s); /* s may be NULL: global error */
  * residual block v + W2 GELU(W1 s + b1) + b2 around the same spectral
  * convolution s of v (width -> ff_hidden -> width), with no pointwise map
  * beside it and no activation on the residual stream.
+ * arch = 2 gives the factorized FNO of Table 2 (per-axis layers after Tran
+ * et al.): the hybrid's residual block with s the sum over the three axes of
+ * 1D spectral convolutions, each a real DFT along the axis truncated to
+ * modes k = 0..m-1 (m = mx, my or mz), per-mode complex channel mixing and
+ * the c2r inverse along the axis (1/n, modes k >= 1 counted twice).
  * Contractions run as BF16 MFMA with FP32 accumulation.                      */
 typedef struct fno_net fno_net;
 
@@ -295,7 +300,8 @@ typedef struct {
                                at most 64                                     */
   int32_t layers;           /* Fourier layers (4)                             */
   int32_t mx, my, mz;       /* retained modes (16): powers of two, 2m <= n;
-                               2*my*mz >= 32 (>= 16 when width > 32)          */
+                               2*my*mz >= 32 (>= 16 when width > 32); the
+                               factorized FNO's modes per axis, 4 to 16     */
   int32_t proj_hidden;      /* projection hidden width (128), % 16 == 0       */
   int32_t max_batch;        /* largest batch the workspaces are sized for     */
   int32_t proj_act;         /* projection hidden activation: 0 GELU (erf),
@@ -303,18 +309,23 @@ typedef struct {
                                with Sitzmann's initialisation; the sine needs
                                proj_hidden <= 128, width <= 64, cout <= 16   */
   float proj_w0;            /* SIREN frequency (30); ignored for GELU         */
-  int32_t arch;             /* 0 FNO, 1 hybrid F/FNO; the hybrid needs
-                               width <= 32, nz in [16, 256], 2*mz <= 32 and
-                               ff_hidden <= 128                               */
-  int32_t ff_hidden;        /* hybrid feed-forward width (128), % 16 == 0;
-                               ignored for the FNO                            */
+  int32_t arch;             /* 0 FNO, 1 hybrid F/FNO, 2 factorized FNO; the
+                               hybrid needs width <= 32, nz in [16, 256],
+                               2*mz <= 32 and ff_hidden <= 128; the
+                               factorized FNO width 16 or 32, nz in
+                               [32, 256] and ff_hidden <= 128               */
+  int32_t ff_hidden;        /* feed-forward width of the hybrid and the
+                               factorized FNO (128), % 16 == 0; ignored for
+                               the FNO                                        */
 } fno_params;
 
 /* Parameter vector layout (FP32, fno_param_count entries), in this order:
  * lift W [width][cin], lift b [width]; per layer l: spectral weights
- * [2*mx][2*my][mz][width_in][width_out][2] (re, im), then for the FNO the
- * pointwise W [width][width] (out, in) and bias [width], for the hybrid
- * W1 [ff_hidden][width], b1 [ff_hidden], W2 [width][ff_hidden], b2 [width];
+ * [2*mx][2*my][mz][width_in][width_out][2] (re, im) (factorized FNO: the
+ * axis weights [mx][width_in][width_out][2], then [my][...], then [mz][...]),
+ * then for the FNO the pointwise W [width][width] (out, in) and bias
+ * [width], for the hybrid and the factorized FNO W1 [ff_hidden][width],
+ * b1 [ff_hidden], W2 [width][ff_hidden], b2 [width];
  * proj W1 [proj_hidden][width], b1 [proj_hidden], W2 [cout][proj_hidden],
  * b2 [cout].                                                                 */
 int64_t fno_param_count(const fno_params* p);

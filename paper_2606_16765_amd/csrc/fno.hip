@@ -18,6 +18,8 @@
 // (inverse) for input part pi, output part po:
 //   forward  (0,0) c  (1,0) s   (0,1) -s  (1,1) c
 //   inverse  (0,0) c  (1,0) -s  (0,1) s   (1,1) c
+// The factorized FNO (arch 2) keeps per-axis modes [B][W][OUT][2][m][IN]
+// instead (ffno_kernels.h), one 1D transform per axis.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -26,6 +28,7 @@
 #include <string>
 #include <vector>
 
+#include "ffno_kernels.h"
 #include "fno_kernels.h"
 #include "mi355lbm.h"
 
@@ -71,6 +74,22 @@ struct fno_net {
   bool hybrid = false;
   int Hf = 0;
   std::vector<int64_t> off_W1, off_b1, off_W2, off_b2;
+  // factorized FNO (arch 2; it shares the hybrid's feed-forward blocks):
+  // per axis d (0 x, 1 y, 2 z) the length N, retained modes m, the extents
+  // OUT and IN of its mode layout, the 1D DFT operands (F forward, I c2r
+  // inverse, Ia and Fa their adjoints), the offset of its weights in a
+  // layer's spectral block and of its modes in Vh[l]; the embedded mixing
+  // weights E and their transposes per (layer, axis)
+  bool ffno = false;
+  struct Axis {
+    int N = 0, m = 0;
+    int64_t OUT = 0, IN = 0, woff = 0, voff = 0;
+    GtMat F, I, Ia, Fa;
+  };
+  Axis ax[3];
+  std::vector<uint16_t*> Emix, ETmix;
+  float* fpart = nullptr;  // Gram partials of the mixing gradient
+  int64_t fpart_elems = 0;
   float *theta = nullptr, *grad = nullptr, *am = nullptr, *av = nullptr;
   int adam_t = 0;
   uint16_t* wspec = nullptr;  // BF16 copy of all parameters (spectral blocks used)
@@ -408,6 +427,100 @@ static void launch_ffn_bwd(fno_net* n, int l, int B, const uint16_t* s, const fl
   }
 }
 
+// ------------------------------------------------ factorized FNO (arch 2)
+// Truncated 1D DFT along axis d as one contraction: grid values [B][W][P]
+// -> modes [B][W][OUT][2][m][IN] (to_modes, with F or Ia), or modes -> grid
+// values (with I or Fa).  The epilogue options are the contraction's.
+static int axis_dft(fno_net* n, int d, int B, const void* in, bool in_bf16, const GtMat& G, void* out, bool out_bf16,
+                    bool to_modes, bool accumulate, bool store_out = true, uint16_t* act = nullptr) {
+  const auto& a = n->ax[d];
+  const int64_t W = n->W, N = a.N, m = a.m, OUT = a.OUT, IN = a.IN;
+  CSpec c{};
+  c.in = in; c.in_bf16 = in_bf16; c.out = out; c.out_bf16 = out_bf16; c.g = &G;
+  c.alpha = 1.f; c.accumulate = accumulate; c.store_out = store_out; c.act = act;
+  c.cols = (int64_t)B * W * OUT * IN; c.I = IN; c.kd = 1; c.nd = 1;
+  if (to_modes) {
+    if (IN == 1) {
+      c.in_so = N; c.in_sk1 = 1; c.kcontig = true;
+      c.out_so = 2 * m; c.out_sn1 = 1;
+    } else {
+      c.in_so = N * IN; c.in_si = 1; c.in_sk1 = IN;
+      c.out_so = 2 * m * IN; c.out_si = 1; c.nd = (int)m; c.out_sn1 = m * IN; c.out_sn2 = IN;
+    }
+  } else {
+    if (IN == 1) {
+      c.in_so = 2 * m; c.in_sk1 = 1; c.kcontig = true;
+      c.out_so = N; c.out_sn1 = 1;
+    } else {
+      c.in_so = 2 * m * IN; c.in_si = 1; c.kd = (int)m; c.in_sk1 = m * IN; c.in_sk2 = IN;
+      c.out_so = N * IN; c.out_si = 1; c.out_sn1 = IN;
+    }
+  }
+  return contract(n, c);
+}
+
+// per-mode channel mixing of axis d's modes by the embedded weights e
+// (E for the forward mixing, ET for its adjoint)
+static void axis_mix(fno_net* n, int d, int B, const uint16_t* in, const uint16_t* e, uint16_t* out) {
+  const auto& a = n->ax[d];
+  AxisMixArgs m{};
+  m.in = in; m.out = out; m.e = e; m.OUT = (int)a.OUT; m.IN = (int)a.IN; m.M = a.m;
+  m.tiles = (int64_t)B * a.OUT * a.IN / AX_TR;
+  const size_t lds = (size_t)a.m * AX_TR * (2 * n->W + 8) * 2;
+  if (n->W == 16) hipLaunchKernelGGL(axis_mix_kernel<16>, dim3((unsigned)m.tiles), dim3(256), lds, n->st, m);
+  else hipLaunchKernelGGL(axis_mix_kernel<32>, dim3((unsigned)m.tiles), dim3(256), lds, n->st, m);
+}
+
+// weight gradient of axis d's mixing from its forward modes v and mode
+// gradient g, stored to grad [m][W][W][2]
+static void axis_mix_grad(fno_net* n, int d, int B, const uint16_t* v, const uint16_t* g, float* grad) {
+  const auto& a = n->ax[d];
+  AxisGradArgs ga{};
+  ga.v = v; ga.g = g; ga.part = n->fpart; ga.OUT = (int)a.OUT; ga.IN = (int)a.IN; ga.M = a.m;
+  ga.steps = (int64_t)B * a.OUT * a.IN / AX_GR;
+  ga.per_chunk = (ga.steps + FFNO_NCHUNK - 1) / FFNO_NCHUNK;
+  const int64_t nchunk = (ga.steps + ga.per_chunk - 1) / ga.per_chunk;
+  const dim3 grid((unsigned)nchunk, (unsigned)(a.m / 4));
+  if (n->W == 16) hipLaunchKernelGGL(axis_mix_grad_kernel<16>, grid, dim3(256), 0, n->st, ga);
+  else hipLaunchKernelGGL(axis_mix_grad_kernel<32>, grid, dim3(256), 0, n->st, ga);
+  const int64_t e = (int64_t)a.m * n->W * n->W;
+  hipLaunchKernelGGL(axis_mix_grad_fold_kernel, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, n->st, n->fpart,
+                     nchunk, a.m, n->W, grad);
+}
+
+// s = sum over the axes of R_d(W_d . T_d(v[l])) into S (BF16), summed in
+// FP32 in the buffer of dL/ds (unused in the forward pass); the modes of
+// each axis are kept in Vh[l] when training
+static int ffno_spectral(fno_net* n, int l, int B, bool training, uint16_t* S) {
+  int rc;
+  float* sacc = n->gs;
+  const int order[3] = {2, 1, 0};
+  for (int i = 0; i < 3; ++i) {
+    const int d = order[i];
+    auto& a = n->ax[d];
+    uint16_t* V = training ? n->Vh[l] + a.voff : n->Vg;
+    if ((rc = axis_dft(n, d, B, n->v[l], true, a.F, V, true, true, false))) return rc;
+    axis_mix(n, d, B, V, n->Emix[3 * l + d], n->Yh);
+    const bool last = i == 2;
+    if ((rc = axis_dft(n, d, B, n->Yh, true, a.I, sacc, false, false, i > 0, !last, last ? S : nullptr))) return rc;
+  }
+  return LBM_OK;
+}
+
+// backward of the spectral convolution of layer l given dL/ds in gs:
+// weight gradients of the three axes, and gv += the adjoint path
+static int ffno_spectral_bwd(fno_net* n, int l, int B) {
+  int rc;
+  for (int d = 0; d < 3; ++d) {
+    auto& a = n->ax[d];
+    if ((rc = axis_dft(n, d, B, n->gs, false, a.Ia, n->Yh, true, true, false))) return rc;
+    axis_mix_grad(n, d, B, n->Vh[l] + a.voff, n->Yh, n->grad + n->off_W[l] + a.woff);
+    axis_mix(n, d, B, n->Yh, n->ETmix[3 * l + d], n->Vg);
+    if ((rc = axis_dft(n, d, B, n->Vg, true, a.Fa, n->gv, false, false, true))) return rc;
+  }
+  return LBM_OK;
+}
+
 // truncated forward 3D DFT: v [B][W][P] (BF16 or FP32) -> modes [m][B][W][2]
 // (z_done: A1 already holds the z stage, written by the previous layer end)
 static int forward_dft(fno_net* n, int B, const void* v, bool v_bf16, const GtMat& Gz, uint16_t* modes,
@@ -564,6 +677,12 @@ static int refresh(fno_net* n, bool bf16_done = false) {
   };
   mk(n->Glift, n->off_P, n->W, n->p.cin, 0);
   for (int l = 0; l < n->L; ++l) {
+    for (int d = 0; n->ffno && d < 3; ++d) {
+      const int64_t cnt = (int64_t)n->ax[d].m * (2 * n->W) * (2 * n->W);
+      hipLaunchKernelGGL(axis_pack_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, n->st,
+                         n->theta + n->off_W[l] + n->ax[d].woff, n->ax[d].m, n->W, n->Emix[3 * l + d],
+                         n->ETmix[3 * l + d]);
+    }
     if (n->hybrid) {
       mk(n->Pf1[l], n->off_W1[l], n->Hf, n->W, 0);
       mk(n->Pf2[l], n->off_W2[l], n->W, n->Hf, 0);
@@ -601,8 +720,9 @@ static hipError_t alloc_gt(fno_net* n, GtMat& m, int K, int N) {
 
 extern "C" int64_t fno_param_count(const fno_params* p) {
   if (!p) return -1;
-  const int64_t w = p->width, M = (int64_t)(2 * p->mx) * (2 * p->my) * p->mz, hf = p->ff_hidden;
-  const int64_t layer = M * w * w * 2 + (p->arch == 1 ? 2 * hf * w + hf + w : w * w + w);
+  const int64_t w = p->width, hf = p->ff_hidden;
+  const int64_t M = p->arch == 2 ? (int64_t)p->mx + p->my + p->mz : (int64_t)(2 * p->mx) * (2 * p->my) * p->mz;
+  const int64_t layer = M * w * w * 2 + (p->arch == 1 || p->arch == 2 ? 2 * hf * w + hf + w : w * w + w);
   return w * p->cin + w + (int64_t)p->layers * layer + (int64_t)p->proj_hidden * w + p->proj_hidden +
          (int64_t)p->cout * p->proj_hidden + p->cout;
 }
@@ -624,6 +744,13 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
   if (p.mx <= 0 || p.my <= 0 || p.mz <= 0 || 2 * p.mx > p.nx || 2 * p.my > p.ny || 2 * p.mz > p.nz ||
       ilog2(p.mx) < 0 || ilog2(p.my) < 0 || ilog2(p.mz) < 0)
     return ffail(nullptr, LBM_EINVAL, "modes must be powers of two with 2m <= n (and mz <= nz/2)");
+  if (p.arch == 2 && (p.width != 16 && p.width != 32))
+    return ffail(nullptr, LBM_EINVAL, "the factorized FNO needs width 16 or 32");
+  if (p.arch == 2 && (p.mx < 4 || p.my < 4 || p.mz < 4 || p.mx > 16 || p.my > 16 || p.mz > 16 || p.nz < 32 ||
+                      p.nz > 256 || p.ff_hidden <= 0 || p.ff_hidden % 16 || round_up(p.ff_hidden, 32) > 128))
+    return ffail(nullptr, LBM_EINVAL,
+                 "the factorized FNO needs 4 to 16 modes per axis, nz in [32, 256] and ff_hidden a multiple of 16 "
+                 "up to 128");
   const int64_t P = (int64_t)p.nx * p.ny * p.nz;
   if (P % 8192) return ffail(nullptr, LBM_EINVAL, "grid must hold a multiple of 8192 cells");
   if (p.width > 64) return ffail(nullptr, LBM_EINVAL, "width must be at most 64");
@@ -631,9 +758,10 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
   if (p.proj_act == 1 && (!(p.proj_w0 > 0.f) || !std::isfinite(p.proj_w0) || round_up(p.proj_hidden, 32) > 128 ||
                           p.width > 64 || p.cout > 16 || P % 256))
     return ffail(nullptr, LBM_EINVAL, "the sine projection needs proj_w0 > 0, proj_hidden <= 128 and cout <= 16");
-  if (2 * p.my * p.mz < (p.width <= 32 ? MixCfg<32>::MQ : MixCfg<64>::MQ))
+  if (p.arch != 2 && 2 * p.my * p.mz < (p.width <= 32 ? MixCfg<32>::MQ : MixCfg<64>::MQ))
     return ffail(nullptr, LBM_EINVAL, "2 my mz must be at least 32 (16 for width above 32)");
-  if (p.arch != 0 && p.arch != 1) return ffail(nullptr, LBM_EINVAL, "arch must be 0 (FNO) or 1 (hybrid F/FNO)");
+  if (p.arch < 0 || p.arch > 2)
+    return ffail(nullptr, LBM_EINVAL, "arch must be 0 (FNO), 1 (hybrid F/FNO) or 2 (factorized FNO)");
   if (p.arch == 1 && (p.width > 32 || p.nz < 16 || p.nz > 256 || 2 * p.mz > 32 || P % 256 || p.ff_hidden <= 0 ||
                       p.ff_hidden % 16 || round_up(p.ff_hidden, 32) > 128))
     return ffail(nullptr, LBM_EINVAL,
@@ -644,11 +772,26 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
   n->p = p;
   n->st = (hipStream_t)hip_stream;
   n->W = p.width; n->X = p.nx; n->Y = p.ny; n->Z = p.nz;
-  n->hybrid = p.arch == 1;
+  n->hybrid = p.arch == 1 || p.arch == 2;
+  n->ffno = p.arch == 2;
   n->Hf = n->hybrid ? p.ff_hidden : 0;
   n->MX = 2 * p.mx; n->MY = 2 * p.my; n->MZ = p.mz; n->L = p.layers; n->H = p.proj_hidden;
   n->P = P;
   n->M = (int64_t)n->MX * n->MY * n->MZ;
+  if (n->ffno) {
+    const int Ns[3] = {p.nx, p.ny, p.nz}, ms[3] = {p.mx, p.my, p.mz};
+    int64_t wo = 0, vo = 0;
+    for (int d = 0; d < 3; ++d) {
+      auto& a = n->ax[d];
+      a.N = Ns[d]; a.m = ms[d];
+      a.OUT = d == 0 ? 1 : (d == 1 ? p.nx : (int64_t)p.nx * p.ny);
+      a.IN = d == 0 ? (int64_t)p.ny * p.nz : (d == 1 ? p.nz : 1);
+      a.woff = wo; wo += (int64_t)a.m * p.width * p.width * 2;
+      a.voff = vo; vo += (int64_t)p.max_batch * p.width * a.OUT * 2 * a.m * a.IN;
+    }
+    n->MX = p.mx; n->MY = p.my; n->MZ = p.mz;
+    n->M = (int64_t)p.mx + p.my + p.mz;
+  }
   n->nparam = fno_param_count(&p);
   // offsets
   int64_t o = 0;
@@ -692,9 +835,19 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
   n->h.assign(n->L, nullptr);
   n->Vh.assign(n->L, nullptr);
   for (int l = 0; ok && l <= n->L; ++l) ok = A((void**)&n->v[l], (size_t)B * W * P * 2);
+  // modes kept for the weight gradient: the FNO's 3D modes, or the three
+  // axes' modes of the factorized FNO
+  int64_t vh_elems = n->M * B * W * 2, ax_max = 0;
+  if (n->ffno) {
+    vh_elems = 0;
+    for (auto& a : n->ax) {
+      const int64_t e = (int64_t)B * W * a.OUT * 2 * a.m * a.IN;
+      vh_elems += e;
+      ax_max = std::max(ax_max, e);
+    }
+  }
   for (int l = 0; ok && l < n->L; ++l)
-    ok = (n->hybrid || A((void**)&n->h[l], (size_t)B * W * P * 4)) &&
-         A((void**)&n->Vh[l], (size_t)n->M * B * W * 2 * 2);
+    ok = (n->hybrid || A((void**)&n->h[l], (size_t)B * W * P * 4)) && A((void**)&n->Vh[l], (size_t)vh_elems * 2);
   if (n->hybrid) {
     n->S.assign(n->L, nullptr);
     n->Aff.assign(n->L, nullptr);
@@ -703,11 +856,13 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
     ok = ok && A((void**)&n->ffa, (size_t)B * n->Hf * P * 2) && A((void**)&n->gs, (size_t)B * W * P * 4);
   }
   const int64_t rows = (int64_t)B * W * n->X * n->Y;
-  ok = ok && A((void**)&n->A1, (size_t)rows * 2 * n->MZ * 2) &&
-       A((void**)&n->A2, (size_t)B * W * n->X * 2 * n->MY * n->MZ * 2) &&
-       A((void**)&n->Yh, (size_t)n->M * B * W * 2 * 2) && A((void**)&n->Vg, (size_t)n->M * B * W * 2 * 2) &&
-       A((void**)&n->R3, (size_t)B * W * n->X * 2 * n->MY * n->MZ * 2) &&
-       A((void**)&n->R2, (size_t)rows * 2 * n->MZ * 2) && (hid32 == 0 || A((void**)&n->h1, hid32)) &&
+  const int64_t mode_elems = n->ffno ? ax_max : n->M * B * W * 2;
+  ok = ok && (n->ffno || (A((void**)&n->A1, (size_t)rows * 2 * n->MZ * 2) &&
+                          A((void**)&n->A2, (size_t)B * W * n->X * 2 * n->MY * n->MZ * 2) &&
+                          A((void**)&n->R3, (size_t)B * W * n->X * 2 * n->MY * n->MZ * 2) &&
+                          A((void**)&n->R2, (size_t)rows * 2 * n->MZ * 2))) &&
+       A((void**)&n->Yh, (size_t)mode_elems * 2) && A((void**)&n->Vg, (size_t)mode_elems * 2) &&
+       (hid32 == 0 || A((void**)&n->h1, hid32)) &&
        A((void**)&n->a, (size_t)B * n->H * P * 2) && A((void**)&n->y, (size_t)B * p.cout * P * 4) &&
        A((void**)&n->gy, (size_t)B * p.cout * P * 4) && (hid32 == 0 || A((void**)&n->ga, hid32)) &&
        A((void**)&n->gv, (size_t)B * W * P * 4) && A((void**)&n->gvn, (size_t)B * W * P * 4);
@@ -726,6 +881,17 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
   // per-block Q2 partials of the projection backward (cout x H per 256 points)
   n->q2_in_bwd = n->fused_proj && p.cout <= 8 && (int64_t)B * P / 256 * p.cout * n->H <= n->part_elems &&
                  64 * (int64_t)p.cout * n->H <= n->part2_elems;
+  if (n->ffno) {
+    n->fpart_elems = (int64_t)FFNO_NCHUNK * 16 * (2 * W) * (2 * W);
+    n->Emix.assign(3 * n->L, nullptr);
+    n->ETmix.assign(3 * n->L, nullptr);
+    ok = ok && A((void**)&n->fpart, (size_t)n->fpart_elems * 4);
+    for (int l = 0; ok && l < n->L; ++l)
+      for (int d = 0; ok && d < 3; ++d) {
+        const size_t eb = (size_t)n->ax[d].m * (2 * W) * (2 * W) * 2;
+        ok = A((void**)&n->Emix[3 * l + d], eb) && A((void**)&n->ETmix[3 * l + d], eb);
+      }
+  }
   ok = ok && A((void**)&n->part, (size_t)n->part_elems * 4) && A((void**)&n->lpart, (size_t)n->lpart_n * 8) &&
        A((void**)&n->lscal, 32) &&
        A((void**)&n->part2, (size_t)n->part2_elems * 4) && A((void**)&n->partc, (size_t)n->partc_elems * 4);
@@ -761,7 +927,7 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
       alloc_gt(n, n->Gq2, n->H, p.cout) != hipSuccess || alloc_gt(n, n->Gq2t, p.cout, n->H) != hipSuccess)
     return bail(LBM_ENOMEM, "operand allocation");
   {
-    n->fused_layer_end = n->W <= 32 && p.nz >= 16 && p.nz <= 256 && 2 * p.mz <= 32 && P % 256 == 0;
+    n->fused_layer_end = !n->ffno && n->W <= 32 && p.nz >= 16 && p.nz <= 256 && 2 * p.mz <= 32 && P % 256 == 0;
     if (n->fused_proj) {
       n->Pq1.K = n->W; n->Pq1.N = n->H; n->Pq1.kp = Wp; n->Pq1.np = Hp;
       n->Pq2.K = n->H; n->Pq2.N = p.cout; n->Pq2.kp = Hp; n->Pq2.np = 16;
@@ -773,7 +939,33 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
     }
   }
   // DFT operands
-  {
+  if (n->ffno) {
+    // per axis, theta = 2 pi k n / N, c_0 = 1, c_k = 2:
+    //   F  [n][(part, k)]  (cos, -sin)            forward r2c
+    //   I  [(part, k)][n]  c_k (cos, -sin) / N    c2r inverse
+    //   Ia [n][(part, k)]  c_k (cos, -sin) / N    adjoint of I
+    //   Fa [(part, k)][n]  (cos, -sin)            adjoint of F
+    for (auto& a : n->ax) {
+      const int N = a.N, m = a.m;
+      std::vector<double> f((size_t)N * 2 * m), in((size_t)2 * m * N), ia((size_t)N * 2 * m), fa((size_t)2 * m * N);
+      for (int x = 0; x < N; ++x)
+        for (int k = 0; k < m; ++k) {
+          const double th = 2.0 * M_PI * (double)k * x / N, c = std::cos(th), sn = std::sin(th);
+          const double sc = (k == 0 ? 1.0 : 2.0) / N;
+          f[(size_t)x * 2 * m + k] = c;
+          f[(size_t)x * 2 * m + m + k] = -sn;
+          ia[(size_t)x * 2 * m + k] = c * sc;
+          ia[(size_t)x * 2 * m + m + k] = -sn * sc;
+          in[(size_t)k * N + x] = c * sc;
+          in[(size_t)(m + k) * N + x] = -sn * sc;
+          fa[(size_t)k * N + x] = c;
+          fa[(size_t)(m + k) * N + x] = -sn;
+        }
+      if (make_gt_host(n, a.F, f, N, 2 * m) || make_gt_host(n, a.I, in, 2 * m, N) ||
+          make_gt_host(n, a.Ia, ia, N, 2 * m) || make_gt_host(n, a.Fa, fa, 2 * m, N))
+        return bail(LBM_EDEVICE, "DFT operand upload failed");
+    }
+  } else {
     const int X = n->X, Y = n->Y, Z = n->Z, MZ = n->MZ;
     std::vector<int> kx, ky;
     for (int j = 0; j < n->MX; ++j) kx.push_back(mode_value(j, p.mx));
@@ -894,7 +1086,7 @@ static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout, bool 
   const int64_t W = n->W;
   int rc;
   // the layer end can run the next layer's z stage at the production shape
-  const bool fuse_z = n->fused_layer_end && n->Z == 64 && W == 32 && 2 * n->MZ == 32 && n->F1.kp >= 64;
+  const bool fuse_z = !n->ffno && n->fused_layer_end && n->Z == 64 && W == 32 && 2 * n->MZ == 32 && n->F1.kp >= 64;
   bool z_done = false;
   // lift: v0 = P x + p (no activation; the pre-activation is not kept)
   // (16-byte vector loads of x: a misaligned input takes the separate lift)
@@ -912,6 +1104,13 @@ static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout, bool 
     return rc;
   }
   for (int l = 0; l < n->L; ++l) {
+    if (n->ffno) {
+      // s = sum_d R_d(W_d T_d v) in BF16, then the residual feed-forward block
+      uint16_t* sl = n->S[training ? l : 0];
+      if ((rc = ffno_spectral(n, l, B, training, sl))) return rc;
+      launch_ffn(n, l, B, sl, n->v[l], n->v[l + 1], training ? n->Aff[l] : nullptr);
+      continue;
+    }
     if ((rc = forward_dft(n, B, n->v[l], true, n->F1, n->Vh[l], z_done))) return rc;
     z_done = false;
     mix(n, 0, B, n->Vh[l], n->wspec + n->off_W[l], n->Yh);
@@ -1038,6 +1237,11 @@ extern "C" int fno_loss_grad(fno_net* n, const uint16_t* x, const float* target,
     if ((rc = gram(n, (const uint16_t*)n->ffa, n->Hf, n->S[l], (int)W, B, n->grad + n->off_W1[l], false,
                    n->grad + n->off_b1[l])))
       return rc;
+    if (n->ffno) {
+      // per-axis spectral convolutions; gv accumulates dL/dv[l] in place
+      if ((rc = ffno_spectral_bwd(n, l, B))) return rc;
+      continue;
+    }
     // spectral convolution: mode gradient, weight gradient, adjoint path
     if ((rc = forward_dft(n, B, n->gs, false, n->F1a, n->Yh))) return rc;
     mix_grad(n, B, n->Vh[l], n->Yh, n->grad + n->off_W[l]);

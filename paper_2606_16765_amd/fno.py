@@ -25,7 +25,9 @@ class Fno:
     """3D FNO: lifting, Fourier layers with truncated corner modes, GELU MLP
     projection; trained with masked MSE and Adam.  arch="hybrid" gives the
     hybrid F/FNO: residual layers v + W2 GELU(W1 s + b1) + b2 around the same
-    spectral convolution s (feed-forward width ff_hidden)."""
+    spectral convolution s (feed-forward width ff_hidden); arch="ffno" the
+    factorized FNO, the same residual layers with s the sum of 1D spectral
+    convolutions along x, y and z (mx, my, mz modes each)."""
 
     def __init__(self, nx=128, ny=64, nz=64, cin=4, cout=4, width=32, layers=4, mx=16, my=16, mz=16, hidden=128,
                  max_batch=16, seed=0, proj="gelu", w0=30.0, arch="fno", ff_hidden=128):
@@ -36,7 +38,7 @@ class Fno:
         p.proj_hidden, p.max_batch = hidden, max_batch
         p.proj_act = {"gelu": 0, "siren": 1}[proj]
         p.proj_w0 = w0
-        p.arch = {"fno": 0, "hybrid": 1}[arch]
+        p.arch = {"fno": 0, "hybrid": 1, "ffno": 2}[arch]
         p.ff_hidden = ff_hidden
         self.p = p
         self.shape = (nx, ny, nz)

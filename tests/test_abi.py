@@ -72,9 +72,20 @@ def test_invalid_parameters_rejected_without_device_work():
     assert L.fno_create(ctypes.byref(fp), 0, None, ctypes.byref(h)) == 1  # sine needs w0 > 0
     assert b"sine projection" in L.fno_last_error(None)
     fp.proj_act, fp.proj_w0 = 0, 30.0
-    fp.arch = 2
+    fp.arch = 3
     assert L.fno_create(ctypes.byref(fp), 0, None, ctypes.byref(h)) == 1
     assert b"arch must be" in L.fno_last_error(None)
+    # factorized FNO: nz 16 (< 32), 2 modes, width 48
+    fp.arch, fp.ff_hidden = 2, 32
+    assert L.fno_create(ctypes.byref(fp), 0, None, ctypes.byref(h)) == 1
+    assert b"factorized FNO needs 4 to 16 modes" in L.fno_last_error(None)
+    fp.nz, fp.mz = 32, 2
+    assert L.fno_create(ctypes.byref(fp), 0, None, ctypes.byref(h)) == 1
+    assert b"factorized FNO needs 4 to 16 modes" in L.fno_last_error(None)
+    fp.mz, fp.width = 4, 48
+    assert L.fno_create(ctypes.byref(fp), 0, None, ctypes.byref(h)) == 1
+    assert b"width 16 or 32" in L.fno_last_error(None)
+    fp.nz = 16
     fp.arch, fp.ff_hidden, fp.width = 1, 32, 48
     assert L.fno_create(ctypes.byref(fp), 0, None, ctypes.byref(h)) == 1  # hybrid width above 32
     assert b"hybrid" in L.fno_last_error(None)
@@ -84,12 +95,12 @@ def test_invalid_parameters_rejected_without_device_work():
 
 
 def test_hybrid_parameter_count_matches_the_oracle_layout():
-    """fno_param_count (host only) for both architectures against the
+    """fno_param_count (host only) for the three architectures against the
     oracle's parameter layout."""
     from oracle import fno as ofno
     from paper_2606_16765_amd._lib import FnoParams, load
     L = load()
-    for arch, code in (("fno", 0), ("hybrid", 1)):
+    for arch, code in (("fno", 0), ("hybrid", 1), ("ffno", 2)):
         fp = FnoParams()
         fp.nx, fp.ny, fp.nz, fp.cin, fp.cout, fp.width, fp.layers = 128, 64, 64, 4, 4, 32, 4
         fp.mx, fp.my, fp.mz, fp.proj_hidden, fp.max_batch = 16, 16, 16, 128, 1
