@@ -64,26 +64,33 @@ def read_traffic(workload):
 
 
 def read_surrogate_result():
-    """Summary of the last full surrogate pipeline run (dataset of LBM runs,
+    """Summary of the full surrogate pipeline runs (dataset of LBM runs,
     training, held-out errors, time-to-field), committed under profiles/ by
-    the run that produced it; None when absent."""
-    path = os.path.join(ROOT, "profiles", "fno_surrogate_c4.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as fh:
-        r = json.load(fh)
-    keep = {k: r[k] for k in ("config", "gain", "time_to_field") if k in r}
-    if "fno" in r:
-        keep["fno_held_out"] = r["fno"].get("held_out")
-        keep["fno_train_samples_per_s"] = r["fno"].get("train_samples_per_s")
-    if "mean_field_baseline" in r:
-        keep["mean_field_held_out"] = r["mean_field_baseline"].get("held_out")
-    for proj, v in r.get("projection_variants", {}).items():
-        keep[f"fno_{proj}_projection_held_out"] = v.get("held_out")
-    for arch, v in r.get("architecture_variants", {}).items():
-        keep[f"{arch}_held_out"] = v.get("held_out")
-        keep[f"{arch}_train_samples_per_s"] = v.get("train_samples_per_s")
-    keep["source"] = "profiles/fno_surrogate_c4.json (python -m paper_2606_16765_amd.surrogate)"
+    the runs that produced them; None when absent.  Both runs use the same
+    seeds, hence the same LBM fields: the first trains the FNO with both
+    projections and the hybrid, the second the FNO and the U-Net."""
+    files = ("fno_surrogate_c4.json", "surrogate_c4_unet.json")
+    keep = None
+    for name in files:
+        path = os.path.join(ROOT, "profiles", name)
+        if not os.path.exists(path):
+            continue
+        with open(path) as fh:
+            r = json.load(fh)
+        if keep is None:
+            keep = {k: r[k] for k in ("config", "gain", "time_to_field") if k in r}
+            if "fno" in r:
+                keep["fno_held_out"] = r["fno"].get("held_out")
+                keep["fno_train_samples_per_s"] = r["fno"].get("train_samples_per_s")
+            if "mean_field_baseline" in r:
+                keep["mean_field_held_out"] = r["mean_field_baseline"].get("held_out")
+            keep["source"] = []
+        for proj, v in r.get("projection_variants", {}).items():
+            keep[f"fno_{proj}_projection_held_out"] = v.get("held_out")
+        for arch, v in r.get("architecture_variants", {}).items():
+            keep[f"{arch}_held_out"] = v.get("held_out")
+            keep[f"{arch}_train_samples_per_s"] = v.get("train_samples_per_s")
+        keep["source"].append(f"profiles/{name} (python -m paper_2606_16765_amd.surrogate)")
     return keep
 
 
@@ -248,6 +255,15 @@ def fno_leg():
     # the hybrid F/FNO (residual feed-forward layers, width 32 -> 128 -> 32)
     out["hybrid"] = pfno.bench_inference(batch=16, reps=20, arch="hybrid")
     out["hybrid"]["train"] = pfno.bench_train(batch=16, arch="hybrid")
+    # the factorized FNO (per-axis spectral convolutions, 16 modes per axis)
+    out["ffno"] = pfno.bench_inference(batch=16, reps=20, arch="ffno")
+    out["ffno"]["train"] = pfno.bench_train(batch=16, arch="ffno")
+    # the 3D U-Net of App. A.2 (implicit-GEMM convolutions on BF16 MFMA)
+    from paper_2606_16765_amd import unet as punet
+    u = punet.bench_inference(batch=16, reps=10)
+    u["frac_mfma"] = round(u["tflops"] / MFMA_BF16_PEAK_TFLOPS, 4)
+    u["train"] = punet.bench_train(batch=16, reps=5)
+    out["unet"] = u
     cost = pfno.forward_cost(batch=16)
     s = out["ms_per_batch"] / 1e3
     out["roofline"] = {

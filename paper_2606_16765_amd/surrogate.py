@@ -50,8 +50,10 @@ class Config:
     w0: float = 30.0
     also_proj: tuple = ()       # further projections trained and evaluated on the same data
     arch: str = "fno"           # "fno" or "hybrid" (hybrid F/FNO: residual feed-forward layers)
+                                # or "ffno" (factorized FNO: per-axis spectral convolutions)
     ff_hidden: int = 128        # hybrid feed-forward width
     also_arch: tuple = ()       # further architectures trained and evaluated on the same data
+                                # ("fno", "hybrid", "ffno", or "unet": the 3D U-Net of App. A.2)
     seed: int = 0
     curve_sims: int = 4
     curve_steps: tuple = (1000, 2000, 5000, 10000)
@@ -327,13 +329,19 @@ def run(cfg, out_path=None):
     for kind, name, kw in specs:
         # the same data, scaling, seed and schedule with another projection
         # or architecture
-        vnet = Fno(nx=X, ny=Y, nz=Z, width=cfg.width, layers=cfg.layers, mx=mx, my=my, mz=mz, hidden=cfg.hidden,
-                   max_batch=cfg.batch, seed=cfg.seed, w0=cfg.w0, ff_hidden=cfg.ff_hidden, **kw)
+        if kw["arch"] == "unet":
+            from .unet import Unet
+            vnet = Unet(nx=X, ny=Y, nz=Z, max_batch=cfg.batch, seed=cfg.seed)
+        else:
+            vnet = Fno(nx=X, ny=Y, nz=Z, width=cfg.width, layers=cfg.layers, mx=mx, my=my, mz=mz,
+                       hidden=cfg.hidden, max_batch=cfg.batch, seed=cfg.seed, w0=cfg.w0, ff_hidden=cfg.ff_hidden,
+                       **kw)
         vinfo = train(cfg, vnet, xtr, ytr, len(tr) - len(tr) % cfg.batch if len(tr) >= cfg.batch else len(tr), mask_d)
         vpred, vtimes = predict(cfg, vnet, xs, te, lo, hi)
         vnet.close()
         row = dict(held_out=metrics(vpred, true, mask), held_out_scaled=metrics(sc(vpred), sc(true), mask),
-                   train_samples_per_s=vinfo["train_samples_per_s"], loss_history=vinfo["loss_history"],
+                   train_samples_per_s=vinfo["train_samples_per_s"], train_s=vinfo["train_s"],
+                   loss_history=vinfo["loss_history"],
                    forward_ms_per_sample=sum(t for t, _ in vtimes) / sum(b for _, b in vtimes))
         (variants if kind == "proj" else arch_variants)[name] = row
         log(f"{'projection' if kind == 'proj' else 'architecture'} {name}: held-out rel L2 inner "
@@ -404,7 +412,7 @@ def main(argv=None):
                     help="also train and evaluate networks with these projections on the same data")
     ap.add_argument("--arch", choices=["fno", "hybrid"], default="fno")
     ap.add_argument("--ff-hidden", type=int, default=128)
-    ap.add_argument("--also-arch", choices=["fno", "hybrid"], nargs="*", default=[],
+    ap.add_argument("--also-arch", choices=["fno", "hybrid", "ffno", "unet"], nargs="*", default=[],
                     help="also train and evaluate these architectures on the same data")
     ap.add_argument("--curve-sims", type=int, default=4)
     ap.add_argument("--curve-steps", type=int, nargs="*", default=[1000, 2000, 5000, 10000])

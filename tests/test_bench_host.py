@@ -23,6 +23,8 @@ def test_surrogate_and_validation_summaries_parse():
     s = bench.read_surrogate_result()
     assert s is not None and 0 < s["fno_held_out"]["rel_l2_inner"] < s["mean_field_held_out"]["rel_l2_inner"]
     assert "hybrid_held_out" in s and "fno_siren_projection_held_out" in s
+    # the U-Net beats the FNO inside the loss box, as in the paper's Table 2
+    assert s["unet_held_out"]["rel_l2_inner"] < s["fno_held_out"]["rel_l2_inner"]
     v = bench.read_validation_result()
     Ls = {(r["L"], r["re_s"]) for r in v["sphere_periodic"]}
     assert {(128, 1000), (256, 1000), (384, 1000)} <= Ls
