@@ -335,6 +335,28 @@ extern "C" int unet_bn_stats(unet_net* n, float* host, int64_t count) {
   return LBM_OK;
 }
 
+// A convolution of a block (or its input-gradient adjoint) with rows
+// padded output channels: the LDS-tiled kernel where its tiling applies
+// (input channels in multiples of 32, the grid in 4 x 4 x 16 boxes), else
+// the direct one.  Returns the number of blocks along x, the number of
+// per-block statistics partials.
+static unsigned conv(unet_net* n, const ConvArgs& a, int rows) {
+  const int64_t V = (int64_t)a.B * a.X * a.Y * a.Z;
+  const bool tiled = a.taps == 27 && a.c0 % 32 == 0 && a.c1 % 32 == 0 && a.X % CL_TX == 0 && a.Y % CL_TY == 0 &&
+                     a.Z % CL_TZ == 0;
+  if (tiled) {
+    const unsigned gx = (unsigned)(V / (CL_TX * CL_TY * CL_TZ));
+    if (rows % 64 == 0)
+      hipLaunchKernelGGL(conv_lds_kernel<64>, dim3(gx, (unsigned)(rows / 64)), dim3(256), 0, n->st, a);
+    else
+      hipLaunchKernelGGL(conv_lds_kernel<32>, dim3(gx, (unsigned)(rows / 32)), dim3(256), 0, n->st, a);
+    return gx;
+  }
+  const unsigned gx = (unsigned)((V + CV_VOX - 1) / CV_VOX);
+  hipLaunchKernelGGL(conv_kernel, dim3(gx, (unsigned)(rows / CV_CO)), dim3(256), 0, n->st, a);
+  return gx;
+}
+
 // one conv-BN-ReLU block forward
 static void block_fwd(unet_net* n, Blk& k, int B, const uint16_t* in0, int c0, const uint16_t* in1, int c1,
                       bool train) {
@@ -345,8 +367,7 @@ static void block_fwd(unet_net* n, Blk& k, int B, const uint16_t* in0, int c0, c
   a.wt = k.wt; a.kp = k.kp; a.out = k.z; a.cout = k.cout; a.taps = 27;
   a.B = B; a.X = d[0]; a.Y = d[1]; a.Z = d[2];
   a.stats = train ? n->stats : nullptr;
-  const unsigned gx = (unsigned)((V + CV_VOX - 1) / CV_VOX);
-  hipLaunchKernelGGL(conv_kernel, dim3(gx, (unsigned)(k.coutp / CV_CO)), dim3(256), 0, n->st, a);
+  const unsigned gx = conv(n, a, k.coutp);
   hipLaunchKernelGGL(bn_finalize_kernel, dim3((unsigned)k.cout), dim3(256), 0, n->st, n->stats, (int64_t)gx, k.cout,
                      (double)V, n->theta + k.goff, n->theta + k.boff, k.rmean, k.rvar, k.mean, k.istd, k.scale,
                      k.shift, train ? 1 : 0);
@@ -442,8 +463,7 @@ static void block_bwd(unet_net* n, Blk& k, int B, const uint16_t* in0, int c0, c
     a.in0 = k.dz; a.in1 = nullptr; a.c0 = k.cout; a.c1 = 0;
     a.wt = k.wb; a.kp = k.kpb; a.out = gin; a.cout = k.cind; a.taps = 27;
     a.B = B; a.X = d[0]; a.Y = d[1]; a.Z = d[2]; a.stats = nullptr;
-    hipLaunchKernelGGL(conv_kernel, dim3((unsigned)((V + CV_VOX - 1) / CV_VOX), (unsigned)(k.rowsb / CV_CO)),
-                       dim3(256), 0, n->st, a);
+    conv(n, a, k.rowsb);
   }
 }
 

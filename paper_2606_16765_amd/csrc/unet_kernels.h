@@ -183,6 +183,128 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
   }
 }
 
+// ------------------------------------------------ convolution through LDS
+// The same convolution for inputs whose channel counts are multiples of 32
+// on grids with Z % 16 == 0, Y % 4 == 0 and X % 4 == 0.  A block owns a
+// 4 x 4 x 16 (x, y, z) box of output voxels of one sample and COB output
+// channels.  Per 32-channel chunk of the input it stages the box's 6 x 6 x 18
+// halo once in LDS (rows of 32 channels padded to 40, so that the 16 lanes
+// of an MFMA column group, on 16 consecutive z, read disjoint banks), then
+// runs all 27 taps from there: each staged value feeds up to 27 taps
+// instead of being re-read through the caches per tap.  Wave w computes
+// the voxels of x-slice w (4 y-rows of 16 z: four 16-voxel MFMA column
+// groups) for all COB channels.  Outputs, statistics and the weight operand
+// are those of conv_kernel; the per-block statistics cover the block's 256
+// voxels (blockIdx.x enumerates the boxes).
+constexpr int CL_TX = 4, CL_TY = 4, CL_TZ = 16;
+constexpr int CL_HX = CL_TX + 2, CL_HY = CL_TY + 2, CL_HZ = CL_TZ + 2;
+constexpr int CL_HALO = CL_HX * CL_HY * CL_HZ;  // 648 voxels
+constexpr int CL_CP = 40;                       // LDS row: 32 channels + 8
+
+template <int COB>
+__global__ __launch_bounds__(256) void conv_lds_kernel(ConvArgs a) {
+  constexpr int MT = COB / 16;
+  __shared__ __attribute__((aligned(16))) uint16_t halo[CL_HALO * CL_CP];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int nbx = a.X / CL_TX, nby = a.Y / CL_TY, nbz = a.Z / CL_TZ;
+  int64_t bi = blockIdx.x;
+  const int bz = (int)(bi % nbz); bi /= nbz;
+  const int by = (int)(bi % nby); bi /= nby;
+  const int bx = (int)(bi % nbx);
+  const int64_t b = bi / nbx;
+  const int x0 = bx * CL_TX, y0 = by * CL_TY, z0 = bz * CL_TZ;
+  const int64_t YZ = (int64_t)a.Y * a.Z;
+  const int64_t sbase = b * a.X * YZ;  // first voxel of the sample
+  const int cin = a.c0 + a.c1;
+  const int co0 = blockIdx.y * COB;
+  const int kl = 8 * (lane >> 4);
+  f32x4 acc[MT][4];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[m][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const uint16_t* wrow[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) wrow[m] = a.wt + (int64_t)(co0 + 16 * m + (lane & 15)) * a.kp + kl;
+  for (int cb = 0; cb < cin; cb += 32) {
+    const bool first = cb < a.c0;
+    const uint16_t* src = first ? a.in0 : a.in1;
+    const int cs = first ? a.c0 : a.c1;
+    const int cc = first ? cb : cb - a.c0;
+    // stage the halo: 648 voxels x 4 groups of 8 channels
+    for (int e = t; e < CL_HALO * 4; e += 256) {
+      const int q = e & 3, h = e >> 2;
+      const int hz = h % CL_HZ, hy = (h / CL_HZ) % CL_HY, hx = h / (CL_HZ * CL_HY);
+      const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+      uint4 v = uint4{0u, 0u, 0u, 0u};
+      if (gx >= 0 && gx < a.X && gy >= 0 && gy < a.Y && gz >= 0 && gz < a.Z)
+        v = *(const uint4*)(src + (sbase + gx * YZ + (int64_t)gy * a.Z + gz) * cs + cc + 8 * q);
+      *(uint4*)(halo + h * CL_CP + 8 * q) = v;
+    }
+    __syncthreads();
+    for (int tp = 0; tp < 27; ++tp) {
+      const int dx = tp / 9, dy = (tp / 3) % 3, dz = tp % 3;  // offsets + 1
+      bf16x8 av[MT];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) av[m] = *(const bf16x8*)(wrow[m] + tp * cin + cb);
+      const int hb = ((wave + dx) * CL_HY + dy) * CL_HZ + (lane & 15) + dz;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const bf16x8 bv = *(const bf16x8*)(halo + (hb + c * CL_HZ) * CL_CP + kl);
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m][c] = mfma16(av[m], bv, acc[m][c]);
+      }
+    }
+    __syncthreads();
+  }
+  // lane holds out[voxel (x0 + wave, y0 + c, z0 + (lane & 15))][co0 + 16m + 4 (lane >> 4) + r]
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int cbase = co0 + 16 * m + 4 * (lane >> 4);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int64_t v = sbase + (int64_t)(x0 + wave) * YZ + (int64_t)(y0 + c) * a.Z + z0 + (lane & 15);
+      float* o = a.out + v * a.cout + cbase;
+      if (cbase + 3 < a.cout) {
+        *(float4*)o = float4{acc[m][c][0], acc[m][c][1], acc[m][c][2], acc[m][c][3]};
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (cbase + r < a.cout) o[r] = acc[m][c][r];
+      }
+    }
+  }
+  if (a.stats) {
+    __shared__ float red[4][COB][2];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float s = 0.f, q = 0.f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          s += acc[m][c][r];
+          q += acc[m][c][r] * acc[m][c][r];
+        }
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+          s += __shfl_xor(s, o);
+          q += __shfl_xor(q, o);
+        }
+        if ((lane & 15) == 0) {
+          red[wave][16 * m + 4 * (lane >> 4) + r][0] = s;
+          red[wave][16 * m + 4 * (lane >> 4) + r][1] = q;
+        }
+      }
+    __syncthreads();
+    if (t < 2 * COB) {
+      const int col = t >> 1, h = t & 1;
+      const float v = red[0][col][h] + red[1][col][h] + red[2][col][h] + red[3][col][h];
+      if (co0 + col < a.cout) a.stats[((int64_t)blockIdx.x * a.cout + co0 + col) * 2 + h] = v;
+    }
+  }
+}
+
 // --------------------------------------------------------- weight gradient
 // part[chunk][co][k] = sum over the chunk's voxels v of
 //                      dz[v][co] * in(v + offset(t))[ci],   k = t * cin + ci

@@ -9,9 +9,12 @@ at the production's 16 modes along z; the full-size instance is the network
 the surrogate trains (128x64x64, width 32, 16 modes per axis, projection
 32 -> 128 -> 4, feed-forward 32 -> 128 -> 32).
 
-Tolerances (relative L2) follow the FNO's: BF16 operands (2^-9 relative
-rounding) in ~12 chained contractions per layer with FP32 accumulation give
-a few 1e-3; each bound is about twice the error measured on the GPU.
+Tolerances (relative L2): BF16 operands (2^-9 relative rounding) in ~12
+chained contractions per layer with FP32 accumulation give a few 1e-3.
+Each bound is about twice the error measured on the GPU (the kernels are
+deterministic): forward 4.3e-3 / 4.8e-3 / 3.8e-3 (w16 / w32 / full),
+worst gradient group 3.9e-3 / 5.7e-3 / 7.5e-3, loss 1e-4 / 7.7e-4 /
+1.3e-3, Adam losses per step 4e-4, teacher fit 430x in 60 steps.
 """
 import numpy as np
 import pytest
@@ -48,7 +51,7 @@ def rel_l2(a, b):
     return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
 
 
-@pytest.mark.parametrize("cfg,B,bound", [(SMALL, 2, 1e-2), (W32, 2, 1e-2), (FULL, 1, 1.4e-2)],
+@pytest.mark.parametrize("cfg,B,bound", [(SMALL, 2, 9e-3), (W32, 2, 1e-2), (FULL, 1, 8e-3)],
                          ids=["w16", "w32", "full"])
 def test_forward_matches_oracle(cfg, B, bound):
     print("case", cfg, flush=True)
@@ -85,7 +88,7 @@ def _grad_groups(cfg, B, seed=1):
     return errs
 
 
-@pytest.mark.parametrize("cfg,B,bound", [(SMALL, 2, 3e-2), (W32, 2, 3e-2), (FULL, 1, 3e-2)],
+@pytest.mark.parametrize("cfg,B,bound", [(SMALL, 2, 8e-3), (W32, 2, 1.2e-2), (FULL, 1, 1.5e-2)],
                          ids=["w16", "w32", "full"])
 def test_gradients_match_oracle(cfg, B, bound):
     """Every parameter group, each axis's spectral weights on their own."""
@@ -118,13 +121,13 @@ def test_adam_trajectory_matches_oracle():
         g = ofno.backward(th, cache, gy, s)
         th, m, v = ofno.adam(th, g, m, v, k, lr)
         print("step", k, lg, lo)
-        assert abs(lg - lo) / lo < 7e-3
+        assert abs(lg - lo) / lo < 1e-3
     net.close()
 
 
 def test_training_fits_teacher_network():
     """A target made by another factorized FNO of the same shape: 60 Adam
-    steps cut the masked loss at least 4x."""
+    steps cut the masked loss at least 100x (measured 430x)."""
     import torch
     from paper_2606_16765_amd import Fno
     cfg = SMALL
@@ -137,4 +140,4 @@ def test_training_fits_teacher_network():
     print("losses", losses[0], losses[-1])
     net.close()
     teacher.close()
-    assert losses[-1] < 0.25 * losses[0]
+    assert losses[-1] < 0.01 * losses[0]
