@@ -172,6 +172,20 @@ static int64_t vox(const unet_net* n, int level, int B) {
 }
 
 // chunking of a weight-gradient reduction over V voxels for a (cout, K) tile grid
+// chunking of the LDS weight-gradient kernel: about 1024 blocks over the
+// (chunk, 32 output channels, 32 input channels) grid
+static int wgrad_lds_chunks(int64_t nbox, int cout, int cind, int64_t& per_chunk) {
+  const int64_t tiles = (int64_t)(cout / 32) * (cind / 32);
+  int64_t nc = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
+  nc = std::min<int64_t>(nc, nbox);
+  per_chunk = (nbox + nc - 1) / nc;
+  return (int)((nbox + per_chunk - 1) / per_chunk);
+}
+
+static bool lds_tiling(int c0, int c1, const int* d) {
+  return c0 % 32 == 0 && c1 % 32 == 0 && d[0] % CL_TX == 0 && d[1] % CL_TY == 0 && d[2] % CL_TZ == 0;
+}
+
 static void wgrad_chunks(int64_t V, int cout, int K, int& nchunk, int64_t& chunk) {
   const int tiles = ((cout + 63) / 64) * ((K + 63) / 64);
   const int64_t steps = (V + 63) / 64;
@@ -248,6 +262,10 @@ extern "C" int unet_create(const unet_params* pin, uint64_t seed, void* hip_stre
     int64_t ch;
     wgrad_chunks(V, k.cout, 27 * k.cind, nc, ch);
     n->part_cap = std::max<int64_t>(n->part_cap, (int64_t)nc * k.cout * 27 * k.cind);
+    if (k.cout % 32 == 0 && lds_tiling(k.cind, 0, n->dims[k.level])) {
+      nc = wgrad_lds_chunks(V / (CL_TX * CL_TY * CL_TZ), k.cout, k.cind, ch);
+      n->part_cap = std::max<int64_t>(n->part_cap, (int64_t)nc * k.cout * 27 * k.cind);
+    }
   }
   const int64_t V0 = vox(n, 0, B);
   {
@@ -433,6 +451,18 @@ static void wgrad(unet_net* n, int level, int B, const uint16_t* dz, int coutp_r
   const int K = taps * cind;
   int nchunk;
   int64_t chunk;
+  if (taps == 27 && coutp_rows % 32 == 0 && lds_tiling(c0, c1, d)) {
+    WgradLdsArgs a{};
+    a.dz = dz; a.cout = coutp_rows; a.in0 = in0; a.in1 = in1; a.c0 = c0; a.c1 = c1;
+    a.B = B; a.X = d[0]; a.Y = d[1]; a.Z = d[2]; a.part = n->part;
+    nchunk = wgrad_lds_chunks(V / (CL_TX * CL_TY * CL_TZ), coutp_rows, cind, a.per_chunk);
+    hipLaunchKernelGGL(wgrad_lds_kernel, dim3((unsigned)nchunk, (unsigned)(coutp_rows / 32), (unsigned)(cind / 32)),
+                       dim3(192), 0, n->st, a);
+    const int64_t ne = (int64_t)cout_param * cin_param * taps;
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(nb256(ne)), dim3(256), 0, n->st, n->part, nchunk, coutp_rows,
+                       cout_param, cin_param, cind, taps, dW);
+    return;
+  }
   wgrad_chunks(V, coutp_rows, K, nchunk, chunk);
   WgradArgs a{};
   a.dz = dz; a.cout = coutp_rows; a.in0 = in0; a.in1 = in1; a.c0 = c0; a.c1 = c1; a.taps = taps;

@@ -400,6 +400,154 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
   }
 }
 
+// Weight gradient through LDS, for the convolutions conv_lds_kernel runs
+// (input channels in multiples of 32, the grid in 4 x 4 x 16 boxes) with
+// cout % 32 == 0.  Grid (nchunk, cout / 32, cin / 32); three waves.  A
+// block owns 32 output channels x 32 input channels x all 27 taps and
+// walks the boxes [blockIdx.x * per_chunk, ...).  Per box it stages the
+// box's dz [32 co][4][4][16 z] and the input halo [32 ci][6][6][24 z]
+// transposed in LDS, z contiguous, so that an MFMA lane's k slots are 8
+// z-consecutive voxels (a 32-voxel k step is two (x, y) rows of 16 z).
+// Wave w owns the (dx, dy) tap pairs w, w + 3, w + 6 and all three dz of
+// each: from one aligned 16-voxel window of the halo row it forms the
+// operands of the three z shifts in registers (the odd shift by a 16-bit
+// funnel shift), so no LDS read is misaligned.  The partials go to
+// part[blockIdx.x][co][t * cin + ci], the layout wgrad_reduce_kernel sums.
+struct WgradLdsArgs {
+  const uint16_t* dz;   // [V][cout] BF16
+  int32_t cout;
+  const uint16_t* in0;
+  const uint16_t* in1;
+  int32_t c0, c1;
+  int32_t B, X, Y, Z;
+  int64_t per_chunk;    // boxes per block
+  float* part;          // [nchunk][cout][27 cin]
+};
+
+constexpr int WL_ZP = 24;  // padded halo row (18 z)
+
+__global__ __launch_bounds__(192) void wgrad_lds_kernel(WgradLdsArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t xt[32 * CL_HX * CL_HY * WL_ZP];  // [ci][hx][hy][z]
+  __shared__ __attribute__((aligned(16))) uint16_t dt[32 * CL_TX * CL_TY * CL_TZ];  // [co][bx][by][z]
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4, l16 = lane & 15;
+  const int cin = a.c0 + a.c1;
+  const int co0 = blockIdx.y * 32, ci0 = blockIdx.z * 32;
+  const bool first = ci0 < a.c0;
+  const uint16_t* src = first ? a.in0 : a.in1;
+  const int cs = first ? a.c0 : a.c1;
+  const int cc = first ? ci0 : ci0 - a.c0;
+  const int nbx = a.X / CL_TX, nby = a.Y / CL_TY, nbz = a.Z / CL_TZ;
+  const int64_t nbox = (int64_t)a.B * nbx * nby * nbz;
+  const int64_t YZ = (int64_t)a.Y * a.Z;
+  const int64_t bx0 = (int64_t)blockIdx.x * a.per_chunk;
+  const int64_t bx1 = bx0 + a.per_chunk < nbox ? bx0 + a.per_chunk : nbox;
+  f32x4 acc[3][3][2][2];  // [pair][dz][co tile][ci tile]
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) acc[p][d][m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t box = bx0; box < bx1; ++box) {
+    int64_t bi = box;
+    const int bz = (int)(bi % nbz); bi /= nbz;
+    const int by = (int)(bi % nby); bi /= nby;
+    const int bxx = (int)(bi % nbx);
+    const int64_t b = bi / nbx;
+    const int x0 = bxx * CL_TX, y0 = by * CL_TY, z0 = bz * CL_TZ;
+    const int64_t sbase = b * a.X * YZ;
+    // input halo, two z-consecutive voxels per item: 8 channels each,
+    // written as 8 (z, z + 1) pairs of the transposed rows
+    for (int e = t; e < CL_HX * CL_HY * (CL_HZ / 2) * 4; e += 192) {
+      const int q = e & 3, r = e >> 2;
+      const int hzp = r % (CL_HZ / 2), hy = (r / (CL_HZ / 2)) % CL_HY, hx = r / ((CL_HZ / 2) * CL_HY);
+      const int gx = x0 + hx - 1, gy = y0 + hy - 1;
+      uint4 v0 = uint4{0u, 0u, 0u, 0u}, v1 = uint4{0u, 0u, 0u, 0u};
+      if (gx >= 0 && gx < a.X && gy >= 0 && gy < a.Y) {
+        const int gz = z0 + 2 * hzp - 1;
+        const uint16_t* row = src + (sbase + gx * YZ + (int64_t)gy * a.Z) * cs + cc + 8 * q;
+        if (gz >= 0 && gz < a.Z) v0 = *(const uint4*)(row + (int64_t)gz * cs);
+        if (gz + 1 >= 0 && gz + 1 < a.Z) v1 = *(const uint4*)(row + (int64_t)(gz + 1) * cs);
+      }
+      const uint32_t u0[4] = {v0.x, v0.y, v0.z, v0.w}, u1[4] = {v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t lo = (u0[j >> 1] >> (16 * (j & 1))) & 0xffffu, hi = (u1[j >> 1] >> (16 * (j & 1))) & 0xffffu;
+        *(uint32_t*)(xt + (((8 * q + j) * CL_HX + hx) * CL_HY + hy) * WL_ZP + 2 * hzp) = lo | (hi << 16);
+      }
+    }
+    // dz of the box, likewise
+    for (int e = t; e < CL_TX * CL_TY * (CL_TZ / 2) * 4; e += 192) {
+      const int q = e & 3, r = e >> 2;
+      const int zp = r % (CL_TZ / 2), yy = (r / (CL_TZ / 2)) % CL_TY, xx = r / ((CL_TZ / 2) * CL_TY);
+      const uint16_t* row = a.dz + (sbase + (int64_t)(x0 + xx) * YZ + (int64_t)(y0 + yy) * a.Z + z0 + 2 * zp) * a.cout +
+                            co0 + 8 * q;
+      const uint4 v0 = *(const uint4*)row, v1 = *(const uint4*)(row + a.cout);
+      const uint32_t u0[4] = {v0.x, v0.y, v0.z, v0.w}, u1[4] = {v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t lo = (u0[j >> 1] >> (16 * (j & 1))) & 0xffffu, hi = (u1[j >> 1] >> (16 * (j & 1))) & 0xffffu;
+        *(uint32_t*)(dt + (((8 * q + j) * CL_TX + xx) * CL_TY + yy) * CL_TZ + 2 * zp) = lo | (hi << 16);
+      }
+    }
+    __syncthreads();
+    // k steps of 32 voxels: rows 2s and 2s + 1 of the 16 (x, y) rows, z
+    // halves 0 and 8; lane group g takes row 2s + (g >> 1), z half 8 (g & 1)
+#pragma unroll 1
+    for (int s = 0; s < 8; ++s) {
+      const int row = 2 * s + (g >> 1), zh = 8 * (g & 1);
+      const int rx = row >> 2, ry = row & 3;
+      bf16x8 av[2];
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+        av[m] = *(const bf16x8*)(dt + (((16 * m + l16) * CL_TX + rx) * CL_TY + ry) * CL_TZ + zh);
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        const int pr = wave + 3 * p, dx = pr / 3, dy = pr % 3;
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+          const uint16_t* w = xt + (((16 * n + l16) * CL_HX + rx + dx) * CL_HY + ry + dy) * WL_ZP + zh;
+          const uint4 lo = *(const uint4*)w, hi = *(const uint4*)(w + 8);
+          const uint32_t d[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+          uint32_t s1[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) s1[i] = __builtin_amdgcn_alignbit(d[i + 1], d[i], 16);
+          const uint4 b0 = uint4{d[0], d[1], d[2], d[3]}, b1 = uint4{s1[0], s1[1], s1[2], s1[3]},
+                      b2 = uint4{d[1], d[2], d[3], d[4]};
+          const bf16x8 bv[3] = {__builtin_bit_cast(bf16x8, b0), __builtin_bit_cast(bf16x8, b1),
+                                __builtin_bit_cast(bf16x8, b2)};
+#pragma unroll
+          for (int dzi = 0; dzi < 3; ++dzi)
+#pragma unroll
+            for (int m = 0; m < 2; ++m) acc[p][dzi][m][n] = mfma16(av[m], bv[dzi], acc[p][dzi][m][n]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // D[co][ci]: co = co0 + 16m + 4g + r, ci = ci0 + 16n + l16
+  const int64_t K = (int64_t)27 * cin;
+  float* part = a.part + (int64_t)blockIdx.x * a.cout * K;
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const int pr = wave + 3 * p, dx = pr / 3, dy = pr % 3;
+#pragma unroll
+    for (int dzi = 0; dzi < 3; ++dzi) {
+      const int tap = 9 * dx + 3 * dy + dzi;
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            part[(int64_t)(co0 + 16 * m + 4 * g + r) * K + (int64_t)tap * cin + ci0 + 16 * n + l16] =
+                acc[p][dzi][m][n][r];
+    }
+  }
+}
+
 // dW[co][ci][t] (the parameter layout) = sum over chunks of
 // part[.][co][t * cinp + ci] for co < cout, ci < cin (cinp: the device
 // channel count the convolution ran with; coutp: the partials' row count)
