@@ -354,20 +354,30 @@ extern "C" int unet_bn_stats(unet_net* n, float* host, int64_t count) {
 }
 
 // A convolution of a block (or its input-gradient adjoint) with rows
-// padded output channels: the LDS-tiled kernel where its tiling applies
-// (input channels in multiples of 32, the grid in 4 x 4 x 16 boxes), else
+// padded output channels: the LDS-tiled kernel where one of its boxes and
+// channel chunks applies (inputs in multiples of 32 channels, or the
+// 8-channel input layer; the grid in 4 x 4 x 16 or 4 x 8 x 8 boxes), else
 // the direct one.  Returns the number of blocks along x, the number of
 // per-block statistics partials.
+template <int CC, int TY, int TZ>
+static void launch_conv_lds(unet_net* n, const ConvArgs& a, int rows, unsigned gx) {
+  if (rows % 64 == 0)
+    hipLaunchKernelGGL((conv_lds_kernel<64, CC, TY, TZ>), dim3(gx, (unsigned)(rows / 64)), dim3(256), 0, n->st, a);
+  else
+    hipLaunchKernelGGL((conv_lds_kernel<32, CC, TY, TZ>), dim3(gx, (unsigned)(rows / 32)), dim3(256), 0, n->st, a);
+}
+
 static unsigned conv(unet_net* n, const ConvArgs& a, int rows) {
   const int64_t V = (int64_t)a.B * a.X * a.Y * a.Z;
-  const bool tiled = a.taps == 27 && a.c0 % 32 == 0 && a.c1 % 32 == 0 && a.X % CL_TX == 0 && a.Y % CL_TY == 0 &&
-                     a.Z % CL_TZ == 0;
-  if (tiled) {
-    const unsigned gx = (unsigned)(V / (CL_TX * CL_TY * CL_TZ));
-    if (rows % 64 == 0)
-      hipLaunchKernelGGL(conv_lds_kernel<64>, dim3(gx, (unsigned)(rows / 64)), dim3(256), 0, n->st, a);
-    else
-      hipLaunchKernelGGL(conv_lds_kernel<32>, dim3(gx, (unsigned)(rows / 32)), dim3(256), 0, n->st, a);
+  const int cc = a.c0 % 32 == 0 && a.c1 % 32 == 0 ? 32 : (a.c0 == 8 && a.c1 == 0 ? 8 : 0);
+  const bool box16 = a.X % CL_TX == 0 && a.Y % 4 == 0 && a.Z % 16 == 0;
+  const bool box8 = a.X % CL_TX == 0 && a.Y % 8 == 0 && a.Z % 8 == 0;
+  if (a.taps == 27 && cc && (box16 || box8)) {
+    const unsigned gx = (unsigned)(V / 256);
+    if (cc == 32 && box16) launch_conv_lds<32, 4, 16>(n, a, rows, gx);
+    else if (cc == 32) launch_conv_lds<32, 8, 8>(n, a, rows, gx);
+    else if (box16) launch_conv_lds<8, 4, 16>(n, a, rows, gx);
+    else launch_conv_lds<8, 8, 8>(n, a, rows, gx);
     return gx;
   }
   const unsigned gx = (unsigned)((V + CV_VOX - 1) / CV_VOX);

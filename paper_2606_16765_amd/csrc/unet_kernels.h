@@ -184,40 +184,47 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
 }
 
 // ------------------------------------------------ convolution through LDS
-// The same convolution for inputs whose channel counts are multiples of 32
-// on grids with Z % 16 == 0, Y % 4 == 0 and X % 4 == 0.  A block owns a
-// 4 x 4 x 16 (x, y, z) box of output voxels of one sample and COB output
-// channels.  Per 32-channel chunk of the input it stages the box's 6 x 6 x 18
-// halo once in LDS (rows of 32 channels padded to 40, so that the 16 lanes
-// of an MFMA column group, on 16 consecutive z, read disjoint banks), then
-// runs all 27 taps from there: each staged value feeds up to 27 taps
-// instead of being re-read through the caches per tap.  Wave w computes
-// the voxels of x-slice w (4 y-rows of 16 z: four 16-voxel MFMA column
-// groups) for all COB channels.  Outputs, statistics and the weight operand
-// are those of conv_kernel; the per-block statistics cover the block's 256
-// voxels (blockIdx.x enumerates the boxes).
-constexpr int CL_TX = 4, CL_TY = 4, CL_TZ = 16;
-constexpr int CL_HX = CL_TX + 2, CL_HY = CL_TY + 2, CL_HZ = CL_TZ + 2;
-constexpr int CL_HALO = CL_HX * CL_HY * CL_HZ;  // 648 voxels
-constexpr int CL_CP = 40;                       // LDS row: 32 channels + 8
+// The same convolution through LDS.  A block owns a 4 x TY x TZ box of
+// output voxels of one sample (TY TZ = 64: 4 x 16 on the fine levels, 8 x 8
+// on the 8-cell level) and COB output channels.  Per chunk of CC input
+// channels it stages the box's (4 + 2) x (TY + 2) x (TZ + 2) halo once in
+// LDS and runs all 27 taps from there: each staged value feeds up to 27
+// taps instead of being re-read through the caches per tap.  Wave w
+// computes the voxels of x-slice w (its 64 voxels, v = 16 c + l: y = v / TZ,
+// z = v % TZ, as four 16-voxel MFMA column groups) for all COB channels.
+//   CC = 32: inputs in multiples of 32 channels; an MFMA k step is one tap
+//            and 32 channels; LDS rows of 40 (the 16 lanes of a column
+//            group read disjoint banks).
+//   CC = 8:  the 8-channel input layer; a k step is four taps of 8
+//            channels (lane group g takes tap 4 s + g), the weight rows'
+//            k = tap * 8 + ci order; past tap 26 the weights are zero and
+//            the lanes read the centre tap's (finite) values.
+// Outputs, statistics and the weight operand are those of conv_kernel; the
+// per-block statistics cover the block's 256 voxels (blockIdx.x enumerates
+// the boxes).
+constexpr int CL_TX = 4;
 
-template <int COB>
+template <int COB, int CC, int TY, int TZ>
 __global__ __launch_bounds__(256) void conv_lds_kernel(ConvArgs a) {
   constexpr int MT = COB / 16;
-  __shared__ __attribute__((aligned(16))) uint16_t halo[CL_HALO * CL_CP];
+  constexpr int HX = CL_TX + 2, HY = TY + 2, HZ = TZ + 2, HALO = HX * HY * HZ;
+  constexpr int CP = CC == 32 ? 40 : 8;  // LDS row (channels + padding)
+  constexpr int Q = CC / 8;              // 16-byte groups per staged voxel
+  static_assert(TY * TZ == 64 && (CC == 32 || CC == 8), "box and chunk");
+  __shared__ __attribute__((aligned(16))) uint16_t halo[HALO * CP];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int nbx = a.X / CL_TX, nby = a.Y / CL_TY, nbz = a.Z / CL_TZ;
+  const int nbx = a.X / CL_TX, nby = a.Y / TY, nbz = a.Z / TZ;
   int64_t bi = blockIdx.x;
   const int bz = (int)(bi % nbz); bi /= nbz;
   const int by = (int)(bi % nby); bi /= nby;
   const int bx = (int)(bi % nbx);
   const int64_t b = bi / nbx;
-  const int x0 = bx * CL_TX, y0 = by * CL_TY, z0 = bz * CL_TZ;
+  const int x0 = bx * CL_TX, y0 = by * TY, z0 = bz * TZ;
   const int64_t YZ = (int64_t)a.Y * a.Z;
   const int64_t sbase = b * a.X * YZ;  // first voxel of the sample
   const int cin = a.c0 + a.c1;
   const int co0 = blockIdx.y * COB;
-  const int kl = 8 * (lane >> 4);
+  const int g = lane >> 4, l16 = lane & 15, kl = 8 * g;
   f32x4 acc[MT][4];
 #pragma unroll
   for (int m = 0; m < MT; ++m)
@@ -225,46 +232,73 @@ __global__ __launch_bounds__(256) void conv_lds_kernel(ConvArgs a) {
     for (int c = 0; c < 4; ++c) acc[m][c] = f32x4{0.f, 0.f, 0.f, 0.f};
   const uint16_t* wrow[MT];
 #pragma unroll
-  for (int m = 0; m < MT; ++m) wrow[m] = a.wt + (int64_t)(co0 + 16 * m + (lane & 15)) * a.kp + kl;
-  for (int cb = 0; cb < cin; cb += 32) {
+  for (int m = 0; m < MT; ++m) wrow[m] = a.wt + (int64_t)(co0 + 16 * m + l16) * a.kp + kl;
+  // halo index of this lane's voxel in column group c at tap offsets (0, 0, 0)
+  int hv[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int v = 16 * c + l16;
+    hv[c] = (wave * HY + v / TZ) * HZ + v % TZ;
+  }
+  for (int cb = 0; cb < cin; cb += CC) {
     const bool first = cb < a.c0;
     const uint16_t* src = first ? a.in0 : a.in1;
     const int cs = first ? a.c0 : a.c1;
     const int cc = first ? cb : cb - a.c0;
-    // stage the halo: 648 voxels x 4 groups of 8 channels
-    for (int e = t; e < CL_HALO * 4; e += 256) {
-      const int q = e & 3, h = e >> 2;
-      const int hz = h % CL_HZ, hy = (h / CL_HZ) % CL_HY, hx = h / (CL_HZ * CL_HY);
+    // stage the halo: HALO voxels x Q groups of 8 channels
+    for (int e = t; e < HALO * Q; e += 256) {
+      const int q = e % Q, h = e / Q;
+      const int hz = h % HZ, hy = (h / HZ) % HY, hx = h / (HZ * HY);
       const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
       uint4 v = uint4{0u, 0u, 0u, 0u};
       if (gx >= 0 && gx < a.X && gy >= 0 && gy < a.Y && gz >= 0 && gz < a.Z)
         v = *(const uint4*)(src + (sbase + gx * YZ + (int64_t)gy * a.Z + gz) * cs + cc + 8 * q);
-      *(uint4*)(halo + h * CL_CP + 8 * q) = v;
+      *(uint4*)(halo + h * CP + 8 * q) = v;
     }
     __syncthreads();
-    for (int tp = 0; tp < 27; ++tp) {
-      const int dx = tp / 9, dy = (tp / 3) % 3, dz = tp % 3;  // offsets + 1
-      bf16x8 av[MT];
+    if (CC == 32) {
+#pragma unroll 3
+      for (int tp = 0; tp < 27; ++tp) {
+        const int dx = tp / 9, dy = (tp / 3) % 3, dz = tp % 3;  // offsets + 1
+        const int ho = (dx * HY + dy) * HZ + dz;
+        bf16x8 av[MT];
 #pragma unroll
-      for (int m = 0; m < MT; ++m) av[m] = *(const bf16x8*)(wrow[m] + tp * cin + cb);
-      const int hb = ((wave + dx) * CL_HY + dy) * CL_HZ + (lane & 15) + dz;
+        for (int m = 0; m < MT; ++m) av[m] = *(const bf16x8*)(wrow[m] + tp * cin + cb);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const bf16x8 bv = *(const bf16x8*)(halo + (hb + c * CL_HZ) * CL_CP + kl);
+        for (int c = 0; c < 4; ++c) {
+          const bf16x8 bv = *(const bf16x8*)(halo + (hv[c] + ho) * CP + kl);
 #pragma unroll
-        for (int m = 0; m < MT; ++m) acc[m][c] = mfma16(av[m], bv, acc[m][c]);
+          for (int m = 0; m < MT; ++m) acc[m][c] = mfma16(av[m], bv, acc[m][c]);
+        }
+      }
+    } else {
+#pragma unroll 1
+      for (int s = 0; s < 7; ++s) {
+        const int tp = 4 * s + g < 27 ? 4 * s + g : 13;
+        const int dx = tp / 9, dy = (tp / 3) % 3, dz = tp % 3;
+        const int ho = (dx * HY + dy) * HZ + dz;
+        bf16x8 av[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) av[m] = *(const bf16x8*)(wrow[m] + 32 * s);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const bf16x8 bv = *(const bf16x8*)(halo + (hv[c] + ho) * CP);
+#pragma unroll
+          for (int m = 0; m < MT; ++m) acc[m][c] = mfma16(av[m], bv, acc[m][c]);
+        }
       }
     }
     __syncthreads();
   }
-  // lane holds out[voxel (x0 + wave, y0 + c, z0 + (lane & 15))][co0 + 16m + 4 (lane >> 4) + r]
+  // lane holds out[voxel (x0 + wave, y0 + v / TZ, z0 + v % TZ), v = 16 c + l16][co0 + 16m + 4g + r]
 #pragma unroll
   for (int m = 0; m < MT; ++m) {
-    const int cbase = co0 + 16 * m + 4 * (lane >> 4);
+    const int cbase = co0 + 16 * m + 4 * g;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const int64_t v = sbase + (int64_t)(x0 + wave) * YZ + (int64_t)(y0 + c) * a.Z + z0 + (lane & 15);
-      float* o = a.out + v * a.cout + cbase;
+      const int v = 16 * c + l16;
+      const int64_t vox = sbase + (int64_t)(x0 + wave) * YZ + (int64_t)(y0 + v / TZ) * a.Z + z0 + v % TZ;
+      float* o = a.out + vox * a.cout + cbase;
       if (cbase + 3 < a.cout) {
         *(float4*)o = float4{acc[m][c][0], acc[m][c][1], acc[m][c][2], acc[m][c][3]};
       } else {
@@ -291,9 +325,9 @@ __global__ __launch_bounds__(256) void conv_lds_kernel(ConvArgs a) {
           s += __shfl_xor(s, o);
           q += __shfl_xor(q, o);
         }
-        if ((lane & 15) == 0) {
-          red[wave][16 * m + 4 * (lane >> 4) + r][0] = s;
-          red[wave][16 * m + 4 * (lane >> 4) + r][1] = q;
+        if (l16 == 0) {
+          red[wave][16 * m + 4 * g + r][0] = s;
+          red[wave][16 * m + 4 * g + r][1] = q;
         }
       }
     __syncthreads();
@@ -304,6 +338,10 @@ __global__ __launch_bounds__(256) void conv_lds_kernel(ConvArgs a) {
     }
   }
 }
+
+// the box of the weight-gradient kernel (the fine levels' box)
+constexpr int CL_TY = 4, CL_TZ = 16;
+constexpr int CL_HX = CL_TX + 2, CL_HY = CL_TY + 2, CL_HZ = CL_TZ + 2;
 
 // --------------------------------------------------------- weight gradient
 // part[chunk][co][k] = sum over the chunk's voxels v of
