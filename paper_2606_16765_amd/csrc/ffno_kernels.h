@@ -33,13 +33,16 @@ constexpr int FFNO_NCHUNK = 64;  // most blocks (row chunks) of the weight gradi
 
 // Y[row][n] = sum_kk E[k][n][kk] V[row][kk] for every mode k of a tile of 16
 // rows.  IN == 1 or IN % 16 == 0; M in {4, 8, 16}.  Dynamic LDS:
-// M * 16 * (2W + 8) BF16 for the input tile, reused for the output tile.
+// M * (16 * (2W + 8) + 8) BF16 for the input tile, reused for the output
+// tile.
 template <int W>
 __global__ __launch_bounds__(256) void axis_mix_kernel(AxisMixArgs a) {
-  constexpr int KK = 2 * W, KP = KK + 8, NT = KK / 16, KS = KK / 32;
+  // KM: the stride of one mode's tile, padded by 16 bytes so that the
+  // lanes of a staging store, which differ in the mode, hit different banks
+  constexpr int KK = 2 * W, KP = KK + 8, NT = KK / 16, KS = KK / 32, KM = AX_TR * KP + 8;
   extern __shared__ __attribute__((aligned(16))) uint16_t ax_lds[];
   const int M = a.M, OUT = a.OUT, IN = a.IN, t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  uint16_t* tin = ax_lds;   // [M][16][KP]: rows of kk = 2 c + part
+  uint16_t* tin = ax_lds;   // [M][16][KP] (mode stride KM): rows of kk = 2 c + part
   uint16_t* tout = ax_lds;  // after the MFMAs: [c][part][k][16], ((c * 2 + part) * M + k) * 16 + r
   const int64_t rows = (int64_t)OUT * IN;
   const int64_t tile = blockIdx.x;
@@ -57,7 +60,7 @@ __global__ __launch_bounds__(256) void axis_mix_kernel(AxisMixArgs a) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int pk = 8 * q + j, part = pk >= M, k = pk - part * M;
-        tin[(k * AX_TR + r) * KP + 2 * c + part] = (uint16_t)(u[j >> 1] >> (16 * (j & 1)));
+        tin[k * KM + r * KP + 2 * c + part] = (uint16_t)(u[j >> 1] >> (16 * (j & 1)));
       }
     }
   } else {
@@ -70,7 +73,7 @@ __global__ __launch_bounds__(256) void axis_mix_kernel(AxisMixArgs a) {
       const uint32_t u[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
       for (int j = 0; j < 8; ++j)
-        tin[(k * AX_TR + 8 * h + j) * KP + 2 * c + part] = (uint16_t)(u[j >> 1] >> (16 * (j & 1)));
+        tin[k * KM + (8 * h + j) * KP + 2 * c + part] = (uint16_t)(u[j >> 1] >> (16 * (j & 1)));
     }
   }
   __syncthreads();
@@ -84,7 +87,7 @@ __global__ __launch_bounds__(256) void axis_mix_kernel(AxisMixArgs a) {
     for (int nt = 0; nt < NT; ++nt) acc[i][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const bf16x8 bv = *(const bf16x8*)(tin + (k * AX_TR + (lane & 15)) * KP + ks * 32 + akk);
+      const bf16x8 bv = *(const bf16x8*)(tin + k * KM + (lane & 15) * KP + ks * 32 + akk);
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         const bf16x8 av = *(const bf16x8*)(a.e + ((int64_t)k * KK + nt * 16 + (lane & 15)) * KK + ks * 32 + akk);
@@ -210,6 +213,63 @@ __global__ __launch_bounds__(256) void axis_mix_grad_kernel(AxisGradArgs a) {
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         out[(nt * 16 + 4 * (lane >> 4) + j) * KK + mt * 16 + (lane & 15)] = acc[nt][mt][j];
+}
+
+// The y and z inverses of one layer in one pass, added to the x inverse:
+// for every plane (b, o, x) of Y x Z outputs
+//   S[y][z] = bf16(sx[y][z] + sum_pk Yz[y][pk] Iz[pk][z] + sum_pk Iy[pk][y] Yy[pk][z])
+// with Yz the z modes [B][W][X Y][2 mz] and Yy the y modes [B][W][X][2 my][Z]
+// (the per-axis layouts), Iz and Iy the c2r operands given transposed
+// (gt[n][k], rows of kp >= 32, zero padded), sx the FP32 x inverse.  Both
+// sums are one MFMA k step each (2 m <= 32), on the same accumulators; the
+// y modes are transposed through LDS.  One block per plane; Y, Z in
+// {32, 64}.
+struct AxisYzArgs {
+  const uint16_t* yz;
+  const uint16_t* yy;
+  const uint16_t* iz;  // [Z][kpz]
+  const uint16_t* iy;  // [Y][kpy]
+  int32_t kpz, kpy;
+  const float* sx;     // [B][W][P]
+  uint16_t* s;         // [B][W][P]
+  int32_t Y, Z, MY2, MZ2;  // 2 my, 2 mz
+};
+
+__global__ __launch_bounds__(256) void axis_inverse_yz_kernel(AxisYzArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t yyt[64 * 40];  // [z][pk], pk padded to 40
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4, l16 = lane & 15;
+  const int64_t plane = blockIdx.x;  // (b, o, x)
+  const int Y = a.Y, Z = a.Z;
+  const uint16_t* yz = a.yz + plane * Y * a.MZ2;
+  const uint16_t* yy = a.yy + plane * a.MY2 * Z;
+  // stage Yy transposed: yyt[z][pk] = Yy[pk][z], zero for pk in [2 my, 32)
+  for (int e = t; e < 32 * Z; e += 256) {
+    const int pk = e / Z, z = e - pk * Z;
+    yyt[z * 40 + pk] = pk < a.MY2 ? yy[pk * Z + z] : (uint16_t)0;
+  }
+  __syncthreads();
+  const int ctn = Z / 16, tiles = (Y / 16) * ctn, per = tiles / 4;
+  const int64_t obase = plane * Y * Z;
+  for (int j = 0; j < per; ++j) {
+    const int i = wave * per + j, rt = i / ctn, ct = i - rt * ctn;
+    const int y = 16 * rt + l16, z = 16 * ct + l16;
+    // z inverse: A = Yz rows y (k = pk), B = Iz^T rows z
+    bf16x8 a1 = bf16x8{};
+    if (8 * g < a.MZ2) a1 = *(const bf16x8*)(yz + (int64_t)y * a.MZ2 + 8 * g);
+    const bf16x8 b1 = *(const bf16x8*)(a.iz + (int64_t)z * a.kpz + 8 * g);
+    // y inverse: A = Iy^T rows y, B = Yy^T rows z (from LDS)
+    const bf16x8 a2 = *(const bf16x8*)(a.iy + (int64_t)y * a.kpy + 8 * g);
+    const bf16x8 b2 = *(const bf16x8*)(yyt + z * 40 + 8 * g);
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    acc = mfma16(a1, b1, acc);
+    acc = mfma16(a2, b2, acc);
+    // D[16 rt + 4 g + r][16 ct + l16]
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t o = obase + (int64_t)(16 * rt + 4 * g + r) * Z + z;
+      a.s[o] = f2bf(acc[r] + a.sx[o]);
+    }
+  }
 }
 
 // Weight gradient of the complex mixing from the Gram partials, summed over

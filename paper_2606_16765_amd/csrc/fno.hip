@@ -89,6 +89,7 @@ struct fno_net {
   Axis ax[3];
   std::vector<uint16_t*> Emix, ETmix;
   float* fpart = nullptr;  // Gram partials of the mixing gradient
+  uint16_t* Yh2 = nullptr;  // second mode buffer of the fused y/z inverse (null: unfused)
   int64_t fpart_elems = 0;
   float *theta = nullptr, *grad = nullptr, *am = nullptr, *av = nullptr;
   int adam_t = 0;
@@ -466,7 +467,7 @@ static void axis_mix(fno_net* n, int d, int B, const uint16_t* in, const uint16_
   AxisMixArgs m{};
   m.in = in; m.out = out; m.e = e; m.OUT = (int)a.OUT; m.IN = (int)a.IN; m.M = a.m;
   m.tiles = (int64_t)B * a.OUT * a.IN / AX_TR;
-  const size_t lds = (size_t)a.m * AX_TR * (2 * n->W + 8) * 2;
+  const size_t lds = (size_t)a.m * (AX_TR * (2 * n->W + 8) + 8) * 2;
   if (n->W == 16) hipLaunchKernelGGL(axis_mix_kernel<16>, dim3((unsigned)m.tiles), dim3(256), lds, n->st, m);
   else hipLaunchKernelGGL(axis_mix_kernel<32>, dim3((unsigned)m.tiles), dim3(256), lds, n->st, m);
 }
@@ -490,10 +491,29 @@ static void axis_mix_grad(fno_net* n, int d, int B, const uint16_t* v, const uin
 
 // s = sum over the axes of R_d(W_d . T_d(v[l])) into S (BF16), summed in
 // FP32 in the buffer of dL/ds (unused in the forward pass); the modes of
-// each axis are kept in Vh[l] when training
+// each axis are kept in Vh[l] when training.  Where the y and z extents are
+// 32 or 64, the x inverse is stored first and one pass adds the y and z
+// inverses to it (axis_inverse_yz_kernel): the FP32 sum is written once and
+// read once.
 static int ffno_spectral(fno_net* n, int l, int B, bool training, uint16_t* S) {
   int rc;
   float* sacc = n->gs;
+  if (n->Yh2) {
+    for (int d = 0; d < 3; ++d) {
+      auto& a = n->ax[d];
+      uint16_t* V = training ? n->Vh[l] + a.voff : n->Vg;
+      if ((rc = axis_dft(n, d, B, n->v[l], true, a.F, V, true, true, false))) return rc;
+      uint16_t* Y = d == 1 ? n->Yh2 : n->Yh;
+      axis_mix(n, d, B, V, n->Emix[3 * l + d], Y);
+      if (d == 0 && (rc = axis_dft(n, 0, B, n->Yh, true, a.I, sacc, false, false, false))) return rc;
+    }
+    AxisYzArgs y{};
+    y.yz = n->Yh; y.yy = n->Yh2; y.iz = n->ax[2].I.d; y.kpz = n->ax[2].I.kp; y.iy = n->ax[1].I.d;
+    y.kpy = n->ax[1].I.kp; y.sx = sacc; y.s = S; y.Y = n->Y; y.Z = n->Z; y.MY2 = 2 * n->ax[1].m;
+    y.MZ2 = 2 * n->ax[2].m;
+    hipLaunchKernelGGL(axis_inverse_yz_kernel, dim3((unsigned)((int64_t)B * n->W * n->X)), dim3(256), 0, n->st, y);
+    return LBM_OK;
+  }
   const int order[3] = {2, 1, 0};
   for (int i = 0; i < 3; ++i) {
     const int d = order[i];
@@ -882,6 +902,8 @@ extern "C" int fno_create(const fno_params* pin, uint64_t seed, void* hip_stream
   n->q2_in_bwd = n->fused_proj && p.cout <= 8 && (int64_t)B * P / 256 * p.cout * n->H <= n->part_elems &&
                  64 * (int64_t)p.cout * n->H <= n->part2_elems;
   if (n->ffno) {
+    // the fused y/z inverse: y and z extents of 32 or 64
+    if ((n->Y == 32 || n->Y == 64) && (n->Z == 32 || n->Z == 64)) ok = ok && A((void**)&n->Yh2, (size_t)ax_max * 2);
     n->fpart_elems = (int64_t)FFNO_NCHUNK * 16 * (2 * W) * (2 * W);
     n->Emix.assign(3 * n->L, nullptr);
     n->ETmix.assign(3 * n->L, nullptr);
