@@ -68,8 +68,9 @@ def read_surrogate_result():
     training, held-out errors, time-to-field), committed under profiles/ by
     the runs that produced them; None when absent.  Both runs use the same
     seeds, hence the same LBM fields: the first trains the FNO with both
-    projections and the hybrid, the second the FNO and the U-Net."""
-    files = ("fno_surrogate_c4.json", "surrogate_c4_unet.json")
+    projections and the hybrid, the second the FNO, the U-Net and the
+    factorized FNO."""
+    files = ("fno_surrogate_c4.json", "surrogate_c4_nets.json")
     keep = None
     for name in files:
         path = os.path.join(ROOT, "profiles", name)
