@@ -379,6 +379,8 @@ def main():
     ap.add_argument("--no-precision", action="store_true", help="skip the FP32/FP16/BF16 storage study")
     ap.add_argument("--copy-calib", action="store_true", help="only run a plain device copy of known size")
     ap.add_argument("--fno-only", action="store_true", help="only time the FNO forward and training step at batch 16")
+    ap.add_argument("--fno-forward-reps", type=int, default=0,
+                    help="only run this many timed FNO forward passes at batch 16 (a profiling target)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the x-slab "
@@ -400,6 +402,11 @@ def main():
                           "copy_GBps": copy_rate()}), flush=True)
         return
 
+    if args.fno_forward_reps:
+        # a profiling target: only FNO forward passes at batch 16
+        from paper_2606_16765_amd import fno as pfno
+        print(json.dumps({"fno_forward": pfno.bench_inference(batch=16, reps=args.fno_forward_reps)}), flush=True)
+        return
     if args.fno_only:
         print(json.dumps({"fno": fno_leg()}), flush=True)
         return
