@@ -235,7 +235,9 @@ struct CSpec {
 
 template <typename InT, typename OutT, int LM>
 static void launch_contract_ep(const ContractArgs& a, int ep, dim3 grid, hipStream_t st) {
-  if (ep == EP_NFAST) hipLaunchKernelGGL((contract_kernel<InT, OutT, LM, EP_NFAST>), grid, dim3(256), 0, st, a);
+  if (ep == EP_JVEC) hipLaunchKernelGGL((contract_kernel<InT, OutT, LM, EP_JVEC>), grid, dim3(256), 0, st, a);
+  else if (ep == EP_NVEC) hipLaunchKernelGGL((contract_kernel<InT, OutT, LM, EP_NVEC>), grid, dim3(256), 0, st, a);
+  else if (ep == EP_NFAST) hipLaunchKernelGGL((contract_kernel<InT, OutT, LM, EP_NFAST>), grid, dim3(256), 0, st, a);
   else if (ep == EP_JFAST) hipLaunchKernelGGL((contract_kernel<InT, OutT, LM, EP_JFAST>), grid, dim3(256), 0, st, a);
   else hipLaunchKernelGGL((contract_kernel<InT, OutT, LM, EP_DIRECT>), grid, dim3(256), 0, st, a);
 }
@@ -282,6 +284,16 @@ static int contract(fno_net* n, const CSpec& c) {
   int ep = EP_DIRECT;
   if (c.nd == 1 && c.out_sn1 == 1) ep = EP_NFAST;
   else if (c.out_si == 1 && c.I >= 16) ep = EP_JFAST;
+  // the vector forms: four consecutive outputs per access, every address a
+  // multiple of 4 elements (strides, bases, the contiguous extent)
+  auto al4 = [](const void* p, size_t esz) { return p == nullptr || ((uintptr_t)p % (4 * esz)) == 0; };
+  const size_t oesz = c.out_bf16 ? 2 : 4;
+  const bool bases4 = al4(c.out, oesz) && al4(c.act, 2) && al4(c.gmul, 4);
+  if (ep == EP_JFAST && bases4 && c.cols % 4 == 0 && c.out_so % 4 == 0 && c.out_sn1 % 4 == 0 &&
+      (c.nd == 1 || c.out_sn2 % 4 == 0))
+    ep = EP_JVEC;
+  else if (ep == EP_NFAST && bases4 && c.g->N % 4 == 0 && c.out_so % 4 == 0 && c.out_si % 4 == 0)
+    ep = EP_NVEC;
   const int nblocks = c.g->np / CT_N;
   const dim3 grid((unsigned)((c.cols + CT_J - 1) / CT_J), (unsigned)(a.K <= CT_KT ? 1 : nblocks));
   if (c.in_bf16 && c.out_bf16) launch_contract<uint16_t, uint16_t>(a, lm, ep, grid, n->st);

@@ -124,7 +124,33 @@ __device__ __forceinline__ float gelu_grad(float x) {
 // outputs); EP_NFAST and EP_JFAST stage the 64 x 64 result tile in LDS and
 // store it with consecutive threads on consecutive n (outputs contiguous
 // along n) or on consecutive columns (outputs contiguous along columns).
-enum { EP_DIRECT = 0, EP_NFAST = 1, EP_JFAST = 2 };
+// EP_JVEC and EP_NVEC are the two staged orders with four consecutive
+// outputs per thread along the contiguous dimension (one vector access for
+// the store, the accumulated value, the GELU' factor and the activation)
+// and the address of the fixed index hoisted out of the loop; they need
+// 4-element alignment of every address (checked by the host).
+enum { EP_DIRECT = 0, EP_NFAST = 1, EP_JFAST = 2, EP_JVEC = 3, EP_NVEC = 4 };
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> {
+  static __device__ __forceinline__ void load(const float* p, float (&v)[4]) {
+    const float4 x = *(const float4*)p;
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+  }
+  static __device__ __forceinline__ void store(float* p, const float (&v)[4]) {
+    *(float4*)p = float4{v[0], v[1], v[2], v[3]};
+  }
+};
+template <> struct Vec4<uint16_t> {
+  static __device__ __forceinline__ void load(const uint16_t* p, float (&v)[4]) {
+    const uint2 x = *(const uint2*)p;
+    v[0] = bf2f((uint16_t)(x.x & 0xffffu)); v[1] = bf2f((uint16_t)(x.x >> 16));
+    v[2] = bf2f((uint16_t)(x.y & 0xffffu)); v[3] = bf2f((uint16_t)(x.y >> 16));
+  }
+  static __device__ __forceinline__ void store(uint16_t* p, const float (&v)[4]) {
+    *(uint2*)p = uint2{f2bf2(v[0], v[1]), f2bf2(v[2], v[3])};
+  }
+};
 
 constexpr int CT_KT = 64;            // k held in LDS per pass (two MFMA steps)
 constexpr int CT_TS = CT_KT + 8;     // padded LDS row of the input tile
@@ -234,6 +260,33 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs a) {
       if (a.store_out) out[addr] = from_f<OutT>(v);
       if (a.act) a.act[addr] = f2bf(a.act_gelu ? gelu(v) : v);
     };
+    // four consecutive outputs from the staged tile: bias (one per n or per
+    // output), accumulation, GELU' factor, store and activation as vectors
+    auto finish4 = [&](int64_t addr, const int (&nn)[4], float (&v)[4]) {
+      if (a.bias) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] += a.bias[nn[q]];
+      }
+      if (a.accumulate) {
+        float o[4];
+        Vec4<OutT>::load(out + addr, o);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] += o[q];
+      }
+      if (a.gmul) {
+        float h[4];
+        Vec4<float>::load(a.gmul + addr, h);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] *= gelu_grad(h[q]);
+      }
+      if (a.store_out) Vec4<OutT>::store(out + addr, v);
+      if (a.act) {
+        float g[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g[q] = a.act_gelu ? gelu(v[q]) : v[q];
+        Vec4<uint16_t>::store(a.act + addr, g);
+      }
+    };
     if (EP == EP_DIRECT) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
@@ -252,13 +305,44 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs a) {
         for (int r = 0; r < 4; ++r)
           dst[(wave * 16 + 4 * (lane >> 4) + r) * CT_DS + c * 16 + (lane & 15)] = a.alpha * acc[c][r];
       __syncthreads();
-#pragma unroll 4
-      for (int e = t; e < CT_N * CT_J; e += 256) {
-        const int nl = EP == EP_NFAST ? (e & 63) : (e >> 6);
-        const int jl = EP == EP_NFAST ? (e >> 6) : (e & 63);
-        const int n = n0 + nl;
+      if (EP == EP_JVEC) {
+        // columns jl .. jl + 3 (contiguous outputs, out_si = 1), rows nl
+        const int jl = 4 * (t & 15);
         const int64_t j = j0 + jl;
-        if (n < a.N && j < a.cols) finish(n, j, dst[nl * CT_DS + jl]);
+        const int64_t cb = (j >> a.lgI) * a.out_so + (j & Imask);
+        for (int nl = t >> 4; nl < CT_N; nl += 16) {
+          const int n = n0 + nl;
+          if (n >= a.N || j >= a.cols) continue;
+          const int64_t addr = cb + (int64_t)(n >> a.lgnd) * a.out_sn1 + (int64_t)(n & ndm) * a.out_sn2;
+          float v[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = dst[nl * CT_DS + jl + q];
+          const int nn[4] = {n, n, n, n};
+          finish4(addr, nn, v);
+        }
+      } else if (EP == EP_NVEC) {
+        // rows nl .. nl + 3 (contiguous outputs, out_sn1 = 1, nd = 1), columns jl
+        const int nl = 4 * (t & 15);
+        const int n = n0 + nl;
+        for (int jl = t >> 4; jl < CT_J; jl += 16) {
+          const int64_t j = j0 + jl;
+          if (n >= a.N || j >= a.cols) continue;
+          const int64_t addr = (j >> a.lgI) * a.out_so + (j & Imask) * a.out_si + n;
+          float v[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = dst[(nl + q) * CT_DS + jl];
+          const int nn[4] = {n, n + 1, n + 2, n + 3};
+          finish4(addr, nn, v);
+        }
+      } else {
+#pragma unroll 4
+        for (int e = t; e < CT_N * CT_J; e += 256) {
+          const int nl = EP == EP_NFAST ? (e & 63) : (e >> 6);
+          const int jl = EP == EP_NFAST ? (e >> 6) : (e & 63);
+          const int n = n0 + nl;
+          const int64_t j = j0 + jl;
+          if (n < a.N && j < a.cols) finish(n, j, dst[nl * CT_DS + jl]);
+        }
       }
       __syncthreads();
     }
