@@ -381,6 +381,8 @@ def main():
     ap.add_argument("--fno-only", action="store_true", help="only time the FNO forward and training step at batch 16")
     ap.add_argument("--fno-forward-reps", type=int, default=0,
                     help="only run this many timed FNO forward passes at batch 16 (a profiling target)")
+    ap.add_argument("--unet-forward-reps", type=int, default=0,
+                    help="only run this many timed U-Net forward passes at batch 16 (a profiling target)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the x-slab "
@@ -402,6 +404,11 @@ def main():
                           "copy_GBps": copy_rate()}), flush=True)
         return
 
+    if args.unet_forward_reps:
+        # a profiling target: only U-Net forward passes at batch 16
+        from paper_2606_16765_amd import unet as punet
+        print(json.dumps({"unet_forward": punet.bench_inference(batch=16, reps=args.unet_forward_reps)}), flush=True)
+        return
     if args.fno_forward_reps:
         # a profiling target: only FNO forward passes at batch 16
         from paper_2606_16765_amd import fno as pfno

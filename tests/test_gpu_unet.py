@@ -115,6 +115,32 @@ def test_gradients_match_oracle_with_open_relus(cfg):
     assert worst[0] < 4e-2, worst
 
 
+# the network the surrogate trains, at its full shape (batch 1: the FP64
+# oracle's forward pass takes seconds, its backward pass about three times
+# that); every level runs the kernels it runs in training
+FULL = dict(nx=128, ny=64, nz=64, cin=4, cout=4, widths=(32, 64, 128, 256), bottleneck=512)
+
+
+def test_full_size_forward_and_open_relu_gradients():
+    """128x64x64 with the App. A.2 widths: the training-mode forward pass,
+    then every parameter group's gradient with the ReLUs held open.  Bounds
+    at about twice the measured errors: forward 6.9e-3, loss 9.8e-5, worst
+    group 2.4e-2 (enc0a.gamma)."""
+    net, x, _, _ = _setup(FULL, 1, seed=4)
+    y = net.forward(x, training=True).cpu().numpy()
+    s = _shape(FULL)
+    p = U.unpack(net.get_params().astype(np.float64), s)
+    yo = U.forward(p, x.float().cpu().numpy().astype(np.float64), s, U.running_stats(s), training=True).numpy()
+    net.close()
+    err = rel_l2(y, yo)
+    print("full-size forward (train)", err, flush=True)
+    assert err < 1.4e-2
+    errs = _grad_errors(FULL, 1, seed=4, beta=10.0)
+    assert errs["loss"] < 2e-4
+    worst = max((v, k) for k, v in errs.items())
+    assert worst[0] < 5e-2, worst
+
+
 def test_gradients_at_initialisation_agree_on_the_head_side():
     """At the initialisation (shifts 0) the loss and the gradients of the
     head and of the last decoder block's normalisation agree with FP64; the
