@@ -468,9 +468,9 @@ static void wgrad(unet_net* n, int level, int B, const uint16_t* dz, int coutp_r
     nchunk = wgrad_lds_chunks(V / (CL_TX * CL_TY * CL_TZ), coutp_rows, cind, a.per_chunk);
     hipLaunchKernelGGL(wgrad_lds_kernel, dim3((unsigned)nchunk, (unsigned)(coutp_rows / 32), (unsigned)(cind / 32)),
                        dim3(192), 0, n->st, a);
-    const int64_t ne = (int64_t)cout_param * cin_param * taps;
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(nb256(ne)), dim3(256), 0, n->st, n->part, nchunk, coutp_rows,
-                       cout_param, cin_param, cind, taps, dW);
+    const int64_t ncol = (int64_t)cout_param * K;
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((ncol + WR_COLS - 1) / WR_COLS)), dim3(256), 0, n->st,
+                       n->part, nchunk, coutp_rows, cout_param, cin_param, cind, taps, dW);
     return;
   }
   wgrad_chunks(V, coutp_rows, K, nchunk, chunk);
@@ -479,9 +479,9 @@ static void wgrad(unet_net* n, int level, int B, const uint16_t* dz, int coutp_r
   a.B = B; a.X = d[0]; a.Y = d[1]; a.Z = d[2]; a.chunk = chunk; a.part = n->part;
   hipLaunchKernelGGL(wgrad_kernel, dim3((unsigned)((coutp_rows + 63) / 64), (unsigned)((K + 63) / 64), (unsigned)nchunk),
                      dim3(256), 0, n->st, a);
-  const int64_t ne = (int64_t)cout_param * cin_param * taps;
-  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(nb256(ne)), dim3(256), 0, n->st, n->part, nchunk, coutp_rows,
-                     cout_param, cin_param, cind, taps, dW);
+  const int64_t ncol = (int64_t)cout_param * K;
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((ncol + WR_COLS - 1) / WR_COLS)), dim3(256), 0, n->st,
+                     n->part, nchunk, coutp_rows, cout_param, cin_param, cind, taps, dW);
 }
 
 // adjoint of one block: from k.g (dL/da) to dL/dz, the parameter gradients
@@ -519,7 +519,7 @@ extern "C" int unet_loss_grad(unet_net* n, const uint16_t* x, const float* targe
   hipLaunchKernelGGL(head_kernel, dim3(nb256(V0)), dim3(256), 0, n->st, last.a, P, B, p.widths[0],
                      n->theta + n->head_w, n->theta + n->head_b, p.cout, n->y);
   // dscal[0]: mask cells, [2]: the loss denominator B * cout * cells, [1]: the loss
-  hipLaunchKernelGGL(mask_count_kernel, dim3(1), dim3(256), 0, n->st, mask, P, (double)B * p.cout, n->dscal);
+  hipLaunchKernelGGL(mask_count_kernel, dim3(1), dim3(1024), 0, n->st, mask, P, (double)B * p.cout, n->dscal);
   hipLaunchKernelGGL(head_bwd_kernel, dim3(nb256(V0)), dim3(256), 0, n->st, last.a, n->y, target, mask, n->dscal + 2,
                      P, B, p.widths[0], n->theta + n->head_w, p.cout, last.g, n->dlog, n->hpart);
   hipLaunchKernelGGL(head_reduce_kernel, dim3((unsigned)(1 + p.cout)), dim3(256), 0, n->st, n->hpart,

@@ -240,22 +240,38 @@ __global__ __launch_bounds__(256) void conv_lds_kernel(ConvArgs a) {
     const int v = 16 * c + l16;
     hv[c] = (wave * HY + v / TZ) * HZ + v % TZ;
   }
-  for (int cb = 0; cb < cin; cb += CC) {
+  // The halo of a channel chunk is loaded into registers (NI 16-byte
+  // items per thread) while the previous chunk computes, and written to
+  // LDS once that chunk's taps are done: the global loads of chunk c + 1
+  // overlap the MFMA work of chunk c.
+  constexpr int NI = (HALO * Q + 255) / 256;
+  uint4 pre[NI];
+  auto load_chunk = [&](int cb) {
     const bool first = cb < a.c0;
     const uint16_t* src = first ? a.in0 : a.in1;
     const int cs = first ? a.c0 : a.c1;
     const int cc = first ? cb : cb - a.c0;
-    // stage the halo: HALO voxels x Q groups of 8 channels
-    for (int e = t; e < HALO * Q; e += 256) {
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int e = t + 256 * i;
       const int q = e % Q, h = e / Q;
       const int hz = h % HZ, hy = (h / HZ) % HY, hx = h / (HZ * HY);
       const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
-      uint4 v = uint4{0u, 0u, 0u, 0u};
-      if (gx >= 0 && gx < a.X && gy >= 0 && gy < a.Y && gz >= 0 && gz < a.Z)
-        v = *(const uint4*)(src + (sbase + gx * YZ + (int64_t)gy * a.Z + gz) * cs + cc + 8 * q);
-      *(uint4*)(halo + h * CP + 8 * q) = v;
+      pre[i] = uint4{0u, 0u, 0u, 0u};
+      if (e < HALO * Q && gx >= 0 && gx < a.X && gy >= 0 && gy < a.Y && gz >= 0 && gz < a.Z)
+        pre[i] = *(const uint4*)(src + (sbase + gx * YZ + (int64_t)gy * a.Z + gz) * cs + cc + 8 * q);
+    }
+  };
+  load_chunk(0);
+  for (int cb = 0; cb < cin; cb += CC) {
+    // stage the halo: HALO voxels x Q groups of 8 channels
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int e = t + 256 * i;
+      if (e < HALO * Q) *(uint4*)(halo + (e / Q) * CP + 8 * (e % Q)) = pre[i];
     }
     __syncthreads();
+    if (cb + CC < cin) load_chunk(cb + CC);
     if (CC == 32) {
 #pragma unroll 3
       for (int tp = 0; tp < 27; ++tp) {
@@ -488,49 +504,89 @@ __global__ __launch_bounds__(192) void wgrad_lds_kernel(WgradLdsArgs a) {
       for (int m = 0; m < 2; ++m)
 #pragma unroll
         for (int n = 0; n < 2; ++n) acc[p][d][m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t box = bx0; box < bx1; ++box) {
+  // The first NP of the next box's NH input-halo items per thread are
+  // loaded into registers while the current box computes; the rest of the
+  // halo and the box's dz are loaded when the box starts.  (Holding more
+  // would take the kernel past 256 registers, to one wave per SIMD.)
+  constexpr int HITEMS = CL_HX * CL_HY * (CL_HZ / 2) * 4, DITEMS = CL_TX * CL_TY * (CL_TZ / 2) * 4;
+  constexpr int NH = (HITEMS + 191) / 192, NP = 3;
+  uint4 ph[NP][2];
+  auto box_origin = [&](int64_t box, int& x0, int& y0, int& z0, int64_t& sbase) {
     int64_t bi = box;
     const int bz = (int)(bi % nbz); bi /= nbz;
     const int by = (int)(bi % nby); bi /= nby;
     const int bxx = (int)(bi % nbx);
     const int64_t b = bi / nbx;
-    const int x0 = bxx * CL_TX, y0 = by * CL_TY, z0 = bz * CL_TZ;
-    const int64_t sbase = b * a.X * YZ;
-    // input halo, two z-consecutive voxels per item: 8 channels each,
-    // written as 8 (z, z + 1) pairs of the transposed rows
-    for (int e = t; e < CL_HX * CL_HY * (CL_HZ / 2) * 4; e += 192) {
-      const int q = e & 3, r = e >> 2;
-      const int hzp = r % (CL_HZ / 2), hy = (r / (CL_HZ / 2)) % CL_HY, hx = r / ((CL_HZ / 2) * CL_HY);
-      const int gx = x0 + hx - 1, gy = y0 + hy - 1;
-      uint4 v0 = uint4{0u, 0u, 0u, 0u}, v1 = uint4{0u, 0u, 0u, 0u};
-      if (gx >= 0 && gx < a.X && gy >= 0 && gy < a.Y) {
-        const int gz = z0 + 2 * hzp - 1;
-        const uint16_t* row = src + (sbase + gx * YZ + (int64_t)gy * a.Z) * cs + cc + 8 * q;
-        if (gz >= 0 && gz < a.Z) v0 = *(const uint4*)(row + (int64_t)gz * cs);
-        if (gz + 1 >= 0 && gz + 1 < a.Z) v1 = *(const uint4*)(row + (int64_t)(gz + 1) * cs);
-      }
-      const uint32_t u0[4] = {v0.x, v0.y, v0.z, v0.w}, u1[4] = {v1.x, v1.y, v1.z, v1.w};
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const uint32_t lo = (u0[j >> 1] >> (16 * (j & 1))) & 0xffffu, hi = (u1[j >> 1] >> (16 * (j & 1))) & 0xffffu;
-        *(uint32_t*)(xt + (((8 * q + j) * CL_HX + hx) * CL_HY + hy) * WL_ZP + 2 * hzp) = lo | (hi << 16);
-      }
+    x0 = bxx * CL_TX; y0 = by * CL_TY; z0 = bz * CL_TZ;
+    sbase = b * a.X * YZ;
+  };
+  // halo item e of a box (origin x0, y0, z0, sample base sbase) into v0, v1
+  auto halo_item = [&](int e, int x0, int y0, int z0, int64_t sbase, uint4& v0, uint4& v1) {
+    const int q = e & 3, r = e >> 2;
+    const int hzp = r % (CL_HZ / 2), hy = (r / (CL_HZ / 2)) % CL_HY, hx = r / ((CL_HZ / 2) * CL_HY);
+    const int gx = x0 + hx - 1, gy = y0 + hy - 1;
+    v0 = uint4{0u, 0u, 0u, 0u};
+    v1 = uint4{0u, 0u, 0u, 0u};
+    if (e < HITEMS && gx >= 0 && gx < a.X && gy >= 0 && gy < a.Y) {
+      const int gz = z0 + 2 * hzp - 1;
+      const uint16_t* row = src + (sbase + gx * YZ + (int64_t)gy * a.Z) * cs + cc + 8 * q;
+      if (gz >= 0 && gz < a.Z) v0 = *(const uint4*)(row + (int64_t)gz * cs);
+      if (gz + 1 >= 0 && gz + 1 < a.Z) v1 = *(const uint4*)(row + (int64_t)(gz + 1) * cs);
     }
-    // dz of the box, likewise
-    for (int e = t; e < CL_TX * CL_TY * (CL_TZ / 2) * 4; e += 192) {
+  };
+  auto prefetch = [&](int64_t box) {
+    int x0, y0, z0;
+    int64_t sbase;
+    box_origin(box, x0, y0, z0, sbase);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) halo_item(t + 192 * i, x0, y0, z0, sbase, ph[i][0], ph[i][1]);
+  };
+  // one item's 8 channels at voxels z, z + 1 -> (z, z + 1) pairs of the
+  // 8 transposed rows (row stride: stride elements)
+  auto put_pairs = [](uint16_t* dst, int stride, const uint4& v0, const uint4& v1) {
+    const uint32_t u0[4] = {v0.x, v0.y, v0.z, v0.w}, u1[4] = {v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t lo = (u0[j >> 1] >> (16 * (j & 1))) & 0xffffu, hi = (u1[j >> 1] >> (16 * (j & 1))) & 0xffffu;
+      *(uint32_t*)(dst + j * stride) = lo | (hi << 16);
+    }
+  };
+  // the halo item's LDS destination: rows (8 q + j, hx, hy), z pair hzp
+  auto put_halo = [&](int e, const uint4& v0, const uint4& v1) {
+    const int q = e & 3, r = e >> 2;
+    const int hzp = r % (CL_HZ / 2), hy = (r / (CL_HZ / 2)) % CL_HY, hx = r / ((CL_HZ / 2) * CL_HY);
+    put_pairs(xt + (((8 * q) * CL_HX + hx) * CL_HY + hy) * WL_ZP + 2 * hzp, CL_HX * CL_HY * WL_ZP, v0, v1);
+  };
+  if (bx0 < bx1) prefetch(bx0);
+  for (int64_t box = bx0; box < bx1; ++box) {
+    int x0, y0, z0;
+    int64_t sbase;
+    box_origin(box, x0, y0, z0, sbase);
+    // the rest of the halo and the dz of the box (two z-consecutive voxels
+    // of 8 channels per item)
+#pragma unroll
+    for (int i = NP; i < NH; ++i) {
+      const int e = t + 192 * i;
+      uint4 v0, v1;
+      halo_item(e, x0, y0, z0, sbase, v0, v1);
+      if (e < HITEMS) put_halo(e, v0, v1);
+    }
+    for (int e = t; e < DITEMS; e += 192) {
       const int q = e & 3, r = e >> 2;
       const int zp = r % (CL_TZ / 2), yy = (r / (CL_TZ / 2)) % CL_TY, xx = r / ((CL_TZ / 2) * CL_TY);
-      const uint16_t* row = a.dz + (sbase + (int64_t)(x0 + xx) * YZ + (int64_t)(y0 + yy) * a.Z + z0 + 2 * zp) * a.cout +
+      const uint16_t* row = a.dz +
+                            (sbase + (int64_t)(x0 + xx) * YZ + (int64_t)(y0 + yy) * a.Z + z0 + 2 * zp) * a.cout +
                             co0 + 8 * q;
-      const uint4 v0 = *(const uint4*)row, v1 = *(const uint4*)(row + a.cout);
-      const uint32_t u0[4] = {v0.x, v0.y, v0.z, v0.w}, u1[4] = {v1.x, v1.y, v1.z, v1.w};
+      put_pairs(dt + (((8 * q) * CL_TX + xx) * CL_TY + yy) * CL_TZ + 2 * zp, CL_TX * CL_TY * CL_TZ,
+                *(const uint4*)row, *(const uint4*)(row + a.cout));
+    }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const uint32_t lo = (u0[j >> 1] >> (16 * (j & 1))) & 0xffffu, hi = (u1[j >> 1] >> (16 * (j & 1))) & 0xffffu;
-        *(uint32_t*)(dt + (((8 * q + j) * CL_TX + xx) * CL_TY + yy) * CL_TZ + 2 * zp) = lo | (hi << 16);
-      }
+    for (int i = 0; i < NP; ++i) {
+      const int e = t + 192 * i;
+      if (e < HITEMS) put_halo(e, ph[i][0], ph[i][1]);
     }
     __syncthreads();
+    if (box + 1 < bx1) prefetch(box + 1);
     // k steps of 32 voxels: rows 2s and 2s + 1 of the 16 (x, y) rows, z
     // halves 0 and 8; lane group g takes row 2s + (g >> 1), z half 8 (g & 1)
 #pragma unroll 1
@@ -588,20 +644,34 @@ __global__ __launch_bounds__(192) void wgrad_lds_kernel(WgradLdsArgs a) {
 
 // dW[co][ci][t] (the parameter layout) = sum over chunks of
 // part[.][co][t * cinp + ci] for co < cout, ci < cin (cinp: the device
-// channel count the convolution ran with; coutp: the partials' row count)
+// channel count the convolution ran with; coutp: the partials' row count).
+// A block sums 64 consecutive partial columns (one coalesced 256-byte row
+// segment per wave and chunk); its four waves take every fourth chunk and
+// the four sums are added in a fixed order.
+constexpr int WR_COLS = 64;
+
 __global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* part, int nchunk, int coutp, int cout, int cin,
                                                            int cinp, int taps, float* dW) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t n = (int64_t)cout * cin * taps;
-  if (i >= n) return;
-  const int t = (int)(i % taps);
-  const int ci = (int)((i / taps) % cin);
-  const int co = (int)(i / ((int64_t)taps * cin));
+  __shared__ float sm[4][WR_COLS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t K = (int64_t)taps * cinp;
-  const int64_t col = (int64_t)co * K + (int64_t)t * cinp + ci;
+  const int64_t col = (int64_t)blockIdx.x * WR_COLS + lane;  // co * K + t * cinp + ci
+  const int64_t ncol = (int64_t)cout * K;
   float s = 0.f;
-  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * coutp * K + col];
-  dW[i] = s;
+  if (col < ncol) {
+    const float* p = part + col;
+    const int64_t cs = (int64_t)coutp * K;
+#pragma unroll 4
+    for (int c = wave; c < nchunk; c += 4) s += p[c * cs];
+  }
+  sm[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && col < ncol) {
+    const int co = (int)(col / K);
+    const int r = (int)(col % K);
+    const int t = r / cinp, ci = r % cinp;
+    if (ci < cin) dW[((int64_t)co * cin + ci) * taps + t] = (sm[0][lane] + sm[1][lane]) + (sm[2][lane] + sm[3][lane]);
+  }
 }
 
 // --------------------------------------------------------- batch norm
@@ -967,21 +1037,38 @@ __global__ __launch_bounds__(256) void head_kernel(const uint16_t* act, int64_t 
   for (int o = 0; o < cout; ++o) y[(b * cout + o) * P + p] = 1.f / (1.f + expf(-s[o]));
 }
 
-// number of nonzero mask cells (one block, fixed order) to out[0], times
-// mul (samples x channels: the loss denominator) to out[2]
-__global__ __launch_bounds__(256) void mask_count_kernel(const uint8_t* mask, int64_t P, double mul, double* out) {
-  __shared__ double r[256];
-  double s = 0.0;
-  for (int64_t p = threadIdx.x; p < P; p += 256) s += mask[p] ? 1.0 : 0.0;
+// number of nonzero mask cells (one block; integer counts, so the result
+// does not depend on the order) to out[0], times mul (samples x channels:
+// the loss denominator) to out[2].  A 16-byte aligned mask is read sixteen
+// cells per load.
+__global__ __launch_bounds__(1024) void mask_count_kernel(const uint8_t* mask, int64_t P, double mul, double* out) {
+  __shared__ unsigned long long r[1024];
+  unsigned long long s = 0;
+  int64_t done = 0;
+  if (((uintptr_t)mask & 15) == 0) {
+    const int64_t n16 = P / 16;
+    const uint4* m4 = (const uint4*)mask;
+#pragma unroll 4
+    for (int64_t i = threadIdx.x; i < n16; i += 1024) {
+      const uint4 v = m4[i];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) s += ((w[k] >> (8 * j)) & 0xffu) != 0u;
+    }
+    done = n16 * 16;
+  }
+  for (int64_t p = done + threadIdx.x; p < P; p += 1024) s += mask[p] != 0;
   r[threadIdx.x] = s;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = 512; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) r[threadIdx.x] += r[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[0] = r[0];
-    out[2] = r[0] * mul;
+    out[0] = (double)r[0];
+    out[2] = (double)r[0] * mul;
   }
 }
 
