@@ -171,7 +171,6 @@ static int64_t vox(const unet_net* n, int level, int B) {
   return (int64_t)B * n->dims[level][0] * n->dims[level][1] * n->dims[level][2];
 }
 
-// chunking of a weight-gradient reduction over V voxels for a (cout, K) tile grid
 // chunking of the LDS weight-gradient kernel: about 1024 blocks over the
 // (chunk, 32 output channels, 32 input channels) grid
 static int wgrad_lds_chunks(int64_t nbox, int cout, int cind, int64_t& per_chunk) {
@@ -182,10 +181,14 @@ static int wgrad_lds_chunks(int64_t nbox, int cout, int cind, int64_t& per_chunk
   return (int)((nbox + per_chunk - 1) / per_chunk);
 }
 
-static bool lds_tiling(int c0, int c1, const int* d) {
-  return c0 % 32 == 0 && c1 % 32 == 0 && d[0] % CL_TX == 0 && d[1] % CL_TY == 0 && d[2] % CL_TZ == 0;
+// box depth of the LDS weight gradient for inputs of c0 + c1 channels on a
+// grid d (16 or 8), or 0 where it does not apply
+static int lds_tiling(int c0, int c1, const int* d) {
+  if (c0 % 32 || c1 % 32 || d[0] % CL_TX || d[1] % WL_TY) return 0;
+  return d[2] % 16 == 0 ? 16 : (d[2] % 8 == 0 ? 8 : 0);
 }
 
+// chunking of a weight-gradient reduction over V voxels for a (cout, K) tile grid
 static void wgrad_chunks(int64_t V, int cout, int K, int& nchunk, int64_t& chunk) {
   const int tiles = ((cout + 63) / 64) * ((K + 63) / 64);
   const int64_t steps = (V + 63) / 64;
@@ -193,6 +196,16 @@ static void wgrad_chunks(int64_t V, int cout, int K, int& nchunk, int64_t& chunk
   nc = std::min<int64_t>(nc, steps);
   chunk = 64 * ((steps + nc - 1) / nc);
   nchunk = (int)((V + chunk - 1) / chunk);
+}
+
+// k splits of the direct convolution over V voxels with rows output rows
+// and kp k: a grid of fewer than 512 blocks (the bottleneck) is split over
+// k towards 1024 blocks, at least 16 k steps of 32 per split
+static int conv_splits(int64_t V, int rows, int kp) {
+  const int64_t blocks = ((V + CV_VOX - 1) / CV_VOX) * (rows / CV_CO);
+  if (blocks >= 512) return 1;
+  const int64_t ks = std::min<int64_t>((1024 + blocks - 1) / blocks, (kp / 32) / 16);
+  return (int)std::max<int64_t>(ks, 1);
 }
 
 // re-derive the BF16 operands of every convolution from the FP32 parameters
@@ -258,14 +271,21 @@ extern "C" int unet_create(const unet_params* pin, uint64_t seed, void* hip_stre
     k.rmean = rsbuf + k.rs_off;
     k.rvar = rsbuf + n->nbn + k.rs_off;
     stats_cap = std::max<int64_t>(stats_cap, (int64_t)nb256(V) * k.cout * 2);
+    // statistics per CSR_VOX voxels after a k split (at any batch: one
+    // sample has the fewest blocks)
+    if (conv_splits(V / B, k.coutp, k.kp) > 1)
+      stats_cap = std::max<int64_t>(stats_cap, (V + CSR_VOX - 1) / CSR_VOX * k.cout * 2);
     int nc;
     int64_t ch;
     wgrad_chunks(V, k.cout, 27 * k.cind, nc, ch);
     n->part_cap = std::max<int64_t>(n->part_cap, (int64_t)nc * k.cout * 27 * k.cind);
-    if (k.cout % 32 == 0 && lds_tiling(k.cind, 0, n->dims[k.level])) {
-      nc = wgrad_lds_chunks(V / (CL_TX * CL_TY * CL_TZ), k.cout, k.cind, ch);
+    if (const int tz = k.cout % 32 == 0 ? lds_tiling(k.cind, 0, n->dims[k.level]) : 0) {
+      nc = wgrad_lds_chunks(V / (CL_TX * WL_TY * tz), k.cout, k.cind, ch);
       n->part_cap = std::max<int64_t>(n->part_cap, (int64_t)nc * k.cout * 27 * k.cind);
     }
+    // the k-split partials of the direct convolution (forward and input gradient)
+    n->part_cap = std::max<int64_t>(n->part_cap, (int64_t)conv_splits(V, k.coutp, k.kp) * V * k.cout);
+    n->part_cap = std::max<int64_t>(n->part_cap, (int64_t)conv_splits(V, k.rowsb, k.kpb) * V * k.cind);
   }
   const int64_t V0 = vox(n, 0, B);
   {
@@ -381,7 +401,24 @@ static unsigned conv(unet_net* n, const ConvArgs& a, int rows) {
     return gx;
   }
   const unsigned gx = (unsigned)((V + CV_VOX - 1) / CV_VOX);
-  hipLaunchKernelGGL(conv_kernel, dim3(gx, (unsigned)(rows / CV_CO)), dim3(256), 0, n->st, a);
+  const int ksteps = a.kp / 32;
+  int ks = conv_splits(V, rows, a.kp);
+  if (ks > 1) ks = (int)std::min<int64_t>(ks, n->part_cap / (V * a.cout));  // batches below max_batch
+  ConvArgs b = a;
+  if (ks > 1) {
+    const int per = (ksteps + ks - 1) / ks;
+    ks = (ksteps + per - 1) / per;
+    b.kchunk = 32 * per;
+    b.out = n->part;
+    b.stats = nullptr;
+    hipLaunchKernelGGL(conv_kernel, dim3(gx, (unsigned)(rows / CV_CO), (unsigned)ks), dim3(256), 0, n->st, b);
+    const unsigned gr = (unsigned)((V + CSR_VOX - 1) / CSR_VOX);
+    hipLaunchKernelGGL(conv_split_reduce_kernel, dim3(gr, (unsigned)((a.cout + 31) / 32)), dim3(256), 0, n->st,
+                       n->part, ks, V, a.cout, a.out, a.stats);
+    return gr;
+  }
+  b.kchunk = a.kp;
+  hipLaunchKernelGGL(conv_kernel, dim3(gx, (unsigned)(rows / CV_CO)), dim3(256), 0, n->st, b);
   return gx;
 }
 
@@ -461,13 +498,15 @@ static void wgrad(unet_net* n, int level, int B, const uint16_t* dz, int coutp_r
   const int K = taps * cind;
   int nchunk;
   int64_t chunk;
-  if (taps == 27 && coutp_rows % 32 == 0 && lds_tiling(c0, c1, d)) {
+  const int tz = taps == 27 && coutp_rows % 32 == 0 ? lds_tiling(c0, c1, d) : 0;
+  if (tz) {
     WgradLdsArgs a{};
     a.dz = dz; a.cout = coutp_rows; a.in0 = in0; a.in1 = in1; a.c0 = c0; a.c1 = c1;
     a.B = B; a.X = d[0]; a.Y = d[1]; a.Z = d[2]; a.part = n->part;
-    nchunk = wgrad_lds_chunks(V / (CL_TX * CL_TY * CL_TZ), coutp_rows, cind, a.per_chunk);
-    hipLaunchKernelGGL(wgrad_lds_kernel, dim3((unsigned)nchunk, (unsigned)(coutp_rows / 32), (unsigned)(cind / 32)),
-                       dim3(192), 0, n->st, a);
+    nchunk = wgrad_lds_chunks(V / (CL_TX * WL_TY * tz), coutp_rows, cind, a.per_chunk);
+    const dim3 grid((unsigned)nchunk, (unsigned)(coutp_rows / 32), (unsigned)(cind / 32));
+    if (tz == 16) hipLaunchKernelGGL(wgrad_lds_kernel<16>, grid, dim3(192), 0, n->st, a);
+    else hipLaunchKernelGGL(wgrad_lds_kernel<8>, grid, dim3(192), 0, n->st, a);
     const int64_t ncol = (int64_t)cout_param * K;
     hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((ncol + WR_COLS - 1) / WR_COLS)), dim3(256), 0, n->st,
                        n->part, nchunk, coutp_rows, cout_param, cin_param, cind, taps, dW);

@@ -55,7 +55,11 @@ __device__ __forceinline__ uint4 pack8(const float* f) {
 //
 // Block: four waves, each an MFMA tile of 32 output channels x 64 voxels
 // (2 x 4 tiles of 16 x 16); operands are loaded straight from global memory
-// (the 27 taps re-read each input row through the caches).
+// (the 27 taps re-read each input row through the caches).  Split over k
+// (grids with few voxels and long k, the bottleneck): blockIdx.z takes
+// k in [z kchunk, (z + 1) kchunk) and writes its partial sums to
+// out + z V cout, without statistics; conv_split_reduce_kernel adds the
+// splits.
 struct ConvArgs {
   const uint16_t* in0;
   const uint16_t* in1;
@@ -67,6 +71,7 @@ struct ConvArgs {
   int32_t taps;
   int32_t B, X, Y, Z;
   float* stats;
+  int32_t kchunk;  // conv_kernel: k per blockIdx.z (a multiple of 32)
 };
 
 constexpr int CV_VOX = 256;  // voxels per block (4 waves x 64)
@@ -99,7 +104,8 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
   const int kl = 8 * (lane >> 4);
   const uint16_t* w0 = a.wt + (int64_t)(co0 + (lane & 15)) * a.kp + kl;
   const uint16_t* w1 = w0 + (int64_t)16 * a.kp;
-  for (int k0 = 0; k0 < a.kp; k0 += 32) {
+  const int kb = blockIdx.z * a.kchunk, ke = kb + a.kchunk < a.kp ? kb + a.kchunk : a.kp;
+  for (int k0 = kb; k0 < ke; k0 += 32) {
     const int k = k0 + kl;
     bf16x8 bv[4];
     if (k < K) {
@@ -135,13 +141,14 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
     }
   }
   // lane holds out[voxel vb0 + 16c + (lane & 15)][co0 + 16m + 4 (lane >> 4) + r]
+  float* out = a.out + (int64_t)blockIdx.z * V * a.cout;
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
     const int cb = co0 + 16 * m + 4 * (lane >> 4);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       if (vv[c] < 0) continue;
-      float* o = a.out + vv[c] * a.cout + cb;
+      float* o = out + vv[c] * a.cout + cb;
       if (cb + 3 < a.cout) {
         *(float4*)o = float4{acc[m][c][0], acc[m][c][1], acc[m][c][2], acc[m][c][3]};
       } else {
@@ -180,6 +187,47 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
       const float v = red[0][col][h] + red[1][col][h] + red[2][col][h] + red[3][col][h];
       if (co0 + col < a.cout) a.stats[((int64_t)blockIdx.x * a.cout + co0 + col) * 2 + h] = v;
     }
+  }
+}
+
+// Sum of the k splits of conv_kernel: out[v][c] = sum over z (in order) of
+// part[z][v][c], and per-block statistics of the sums as conv_kernel writes
+// them, over blocks of CSR_VOX voxels: block (blockIdx.x, blockIdx.y) covers
+// voxels [CSR_VOX x, CSR_VOX (x + 1)) and channels [32 y, 32 y + 32); thread
+// (column t & 31, row t >> 5) takes every eighth voxel;
+// stats[blockIdx.x][c][2] (when stats is set).
+constexpr int CSR_VOX = 32;
+
+__global__ __launch_bounds__(256) void conv_split_reduce_kernel(const float* part, int ns, int64_t V, int cout,
+                                                                float* out, float* stats) {
+  __shared__ float red[8][32][2];
+  const int col = threadIdx.x & 31, row = threadIdx.x >> 5;
+  const int c = blockIdx.y * 32 + col;
+  const int64_t vb = (int64_t)blockIdx.x * CSR_VOX;
+  float s = 0.f, q = 0.f;
+  if (c < cout)
+#pragma unroll
+    for (int j = row; j < CSR_VOX; j += 8) {
+      const int64_t v = vb + j;
+      if (v < V) {
+        float acc = 0.f;
+#pragma unroll 4
+        for (int z = 0; z < ns; ++z) acc += part[((int64_t)z * V + v) * cout + c];
+        out[v * cout + c] = acc;
+        s += acc;
+        q += acc * acc;
+      }
+    }
+  if (!stats) return;
+  red[row][col][0] = s;
+  red[row][col][1] = q;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int cl = threadIdx.x >> 1, h = threadIdx.x & 1;
+    float v = 0.f;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v += red[r][cl][h];
+    if (blockIdx.y * 32 + cl < cout) stats[((int64_t)blockIdx.x * cout + blockIdx.y * 32 + cl) * 2 + h] = v;
   }
 }
 
@@ -355,9 +403,10 @@ __global__ __launch_bounds__(256) void conv_lds_kernel(ConvArgs a) {
   }
 }
 
-// the box of the weight-gradient kernel (the fine levels' box)
-constexpr int CL_TY = 4, CL_TZ = 16;
-constexpr int CL_HX = CL_TX + 2, CL_HY = CL_TY + 2, CL_HZ = CL_TZ + 2;
+// the box of the LDS weight-gradient kernel: 4 x 4 x TZ voxels, TZ = 16 on
+// the fine levels and 8 on the 8-cell level
+constexpr int WL_TY = 4;
+constexpr int WL_HX = CL_TX + 2, WL_HY = WL_TY + 2;
 
 // --------------------------------------------------------- weight gradient
 // part[chunk][co][k] = sum over the chunk's voxels v of
@@ -431,13 +480,15 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
       for (int j = 0; j < 8; ++j) sx[(8 * g + j) * WG_VS + vl] = xv[j];
     }
     __syncthreads();
+    if (co0 + 16 * wave < a.cout) {  // a wave whose 16 rows are all padding skips its products
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const bf16x8 av = *(const bf16x8*)(sd + (16 * wave + (lane & 15)) * WG_VS + 32 * s + 8 * (lane >> 4));
+      for (int s = 0; s < 2; ++s) {
+        const bf16x8 av = *(const bf16x8*)(sd + (16 * wave + (lane & 15)) * WG_VS + 32 * s + 8 * (lane >> 4));
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const bf16x8 bv = *(const bf16x8*)(sx + (16 * c + (lane & 15)) * WG_VS + 32 * s + 8 * (lane >> 4));
-        acc[c] = mfma16(av, bv, acc[c]);
+        for (int c = 0; c < 4; ++c) {
+          const bf16x8 bv = *(const bf16x8*)(sx + (16 * c + (lane & 15)) * WG_VS + 32 * s + 8 * (lane >> 4));
+          acc[c] = mfma16(av, bv, acc[c]);
+        }
       }
     }
     __syncthreads();
@@ -454,18 +505,18 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
   }
 }
 
-// Weight gradient through LDS, for the convolutions conv_lds_kernel runs
-// (input channels in multiples of 32, the grid in 4 x 4 x 16 boxes) with
-// cout % 32 == 0.  Grid (nchunk, cout / 32, cin / 32); three waves.  A
-// block owns 32 output channels x 32 input channels x all 27 taps and
-// walks the boxes [blockIdx.x * per_chunk, ...).  Per box it stages the
-// box's dz [32 co][4][4][16 z] and the input halo [32 ci][6][6][24 z]
+// Weight gradient through LDS, for convolutions with input channels in
+// multiples of 32 and cout % 32 == 0 on a grid of 4 x 4 x TZ boxes (TZ = 16
+// or 8).  Grid (nchunk, cout / 32, cin / 32); three waves.  A block owns 32
+// output channels x 32 input channels x all 27 taps and walks the boxes
+// [blockIdx.x * per_chunk, ...).  Per box it stages the box's dz
+// [32 co][4][4][TZ] and the input halo [32 ci][6][6][ZP] (TZ + 2 z, padded)
 // transposed in LDS, z contiguous, so that an MFMA lane's k slots are 8
-// z-consecutive voxels (a 32-voxel k step is two (x, y) rows of 16 z).
-// Wave w owns the (dx, dy) tap pairs w, w + 3, w + 6 and all three dz of
-// each: from one aligned 16-voxel window of the halo row it forms the
-// operands of the three z shifts in registers (the odd shift by a 16-bit
-// funnel shift), so no LDS read is misaligned.  The partials go to
+// z-consecutive voxels (a 32-voxel k step is two (x, y) rows of 16 z, or
+// four rows of 8).  Wave w owns the (dx, dy) tap pairs w, w + 3, w + 6 and
+// all three dz of each: from one aligned 16-voxel window of the halo row it
+// forms the operands of the three z shifts in registers (the odd shift by
+// a 16-bit funnel shift), so no LDS read is misaligned.  The partials go to
 // part[blockIdx.x][co][t * cin + ci], the layout wgrad_reduce_kernel sums.
 struct WgradLdsArgs {
   const uint16_t* dz;   // [V][cout] BF16
@@ -478,11 +529,14 @@ struct WgradLdsArgs {
   float* part;          // [nchunk][cout][27 cin]
 };
 
-constexpr int WL_ZP = 24;  // padded halo row (18 z)
-
+template <int TZ>
 __global__ __launch_bounds__(192) void wgrad_lds_kernel(WgradLdsArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t xt[32 * CL_HX * CL_HY * WL_ZP];  // [ci][hx][hy][z]
-  __shared__ __attribute__((aligned(16))) uint16_t dt[32 * CL_TX * CL_TY * CL_TZ];  // [co][bx][by][z]
+  static_assert(TZ == 16 || TZ == 8, "box depth");
+  constexpr int HZ = TZ + 2;                // halo row
+  constexpr int ZP = TZ == 16 ? 24 : 16;    // padded halo row: the 16-voxel windows stay inside
+  constexpr int NS = CL_TX * WL_TY * TZ / 32;  // k steps per box
+  __shared__ __attribute__((aligned(16))) uint16_t xt[32 * WL_HX * WL_HY * ZP];  // [ci][hx][hy][z]
+  __shared__ __attribute__((aligned(16))) uint16_t dt[32 * CL_TX * WL_TY * TZ];  // [co][bx][by][z]
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4, l16 = lane & 15;
   const int cin = a.c0 + a.c1;
   const int co0 = blockIdx.y * 32, ci0 = blockIdx.z * 32;
@@ -490,7 +544,7 @@ __global__ __launch_bounds__(192) void wgrad_lds_kernel(WgradLdsArgs a) {
   const uint16_t* src = first ? a.in0 : a.in1;
   const int cs = first ? a.c0 : a.c1;
   const int cc = first ? ci0 : ci0 - a.c0;
-  const int nbx = a.X / CL_TX, nby = a.Y / CL_TY, nbz = a.Z / CL_TZ;
+  const int nbx = a.X / CL_TX, nby = a.Y / WL_TY, nbz = a.Z / TZ;
   const int64_t nbox = (int64_t)a.B * nbx * nby * nbz;
   const int64_t YZ = (int64_t)a.Y * a.Z;
   const int64_t bx0 = (int64_t)blockIdx.x * a.per_chunk;
@@ -508,8 +562,8 @@ __global__ __launch_bounds__(192) void wgrad_lds_kernel(WgradLdsArgs a) {
   // loaded into registers while the current box computes; the rest of the
   // halo and the box's dz are loaded when the box starts.  (Holding more
   // would take the kernel past 256 registers, to one wave per SIMD.)
-  constexpr int HITEMS = CL_HX * CL_HY * (CL_HZ / 2) * 4, DITEMS = CL_TX * CL_TY * (CL_TZ / 2) * 4;
-  constexpr int NH = (HITEMS + 191) / 192, NP = 3;
+  constexpr int HITEMS = WL_HX * WL_HY * (HZ / 2) * 4, DITEMS = CL_TX * WL_TY * (TZ / 2) * 4;
+  constexpr int NH = (HITEMS + 191) / 192, NP = NH < 3 ? NH : 3;
   uint4 ph[NP][2];
   auto box_origin = [&](int64_t box, int& x0, int& y0, int& z0, int64_t& sbase) {
     int64_t bi = box;
@@ -517,13 +571,13 @@ __global__ __launch_bounds__(192) void wgrad_lds_kernel(WgradLdsArgs a) {
     const int by = (int)(bi % nby); bi /= nby;
     const int bxx = (int)(bi % nbx);
     const int64_t b = bi / nbx;
-    x0 = bxx * CL_TX; y0 = by * CL_TY; z0 = bz * CL_TZ;
+    x0 = bxx * CL_TX; y0 = by * WL_TY; z0 = bz * TZ;
     sbase = b * a.X * YZ;
   };
   // halo item e of a box (origin x0, y0, z0, sample base sbase) into v0, v1
   auto halo_item = [&](int e, int x0, int y0, int z0, int64_t sbase, uint4& v0, uint4& v1) {
     const int q = e & 3, r = e >> 2;
-    const int hzp = r % (CL_HZ / 2), hy = (r / (CL_HZ / 2)) % CL_HY, hx = r / ((CL_HZ / 2) * CL_HY);
+    const int hzp = r % (HZ / 2), hy = (r / (HZ / 2)) % WL_HY, hx = r / ((HZ / 2) * WL_HY);
     const int gx = x0 + hx - 1, gy = y0 + hy - 1;
     v0 = uint4{0u, 0u, 0u, 0u};
     v1 = uint4{0u, 0u, 0u, 0u};
@@ -554,8 +608,8 @@ __global__ __launch_bounds__(192) void wgrad_lds_kernel(WgradLdsArgs a) {
   // the halo item's LDS destination: rows (8 q + j, hx, hy), z pair hzp
   auto put_halo = [&](int e, const uint4& v0, const uint4& v1) {
     const int q = e & 3, r = e >> 2;
-    const int hzp = r % (CL_HZ / 2), hy = (r / (CL_HZ / 2)) % CL_HY, hx = r / ((CL_HZ / 2) * CL_HY);
-    put_pairs(xt + (((8 * q) * CL_HX + hx) * CL_HY + hy) * WL_ZP + 2 * hzp, CL_HX * CL_HY * WL_ZP, v0, v1);
+    const int hzp = r % (HZ / 2), hy = (r / (HZ / 2)) % WL_HY, hx = r / ((HZ / 2) * WL_HY);
+    put_pairs(xt + (((8 * q) * WL_HX + hx) * WL_HY + hy) * ZP + 2 * hzp, WL_HX * WL_HY * ZP, v0, v1);
   };
   if (bx0 < bx1) prefetch(bx0);
   for (int64_t box = bx0; box < bx1; ++box) {
@@ -573,11 +627,11 @@ __global__ __launch_bounds__(192) void wgrad_lds_kernel(WgradLdsArgs a) {
     }
     for (int e = t; e < DITEMS; e += 192) {
       const int q = e & 3, r = e >> 2;
-      const int zp = r % (CL_TZ / 2), yy = (r / (CL_TZ / 2)) % CL_TY, xx = r / ((CL_TZ / 2) * CL_TY);
+      const int zp = r % (TZ / 2), yy = (r / (TZ / 2)) % WL_TY, xx = r / ((TZ / 2) * WL_TY);
       const uint16_t* row = a.dz +
                             (sbase + (int64_t)(x0 + xx) * YZ + (int64_t)(y0 + yy) * a.Z + z0 + 2 * zp) * a.cout +
                             co0 + 8 * q;
-      put_pairs(dt + (((8 * q) * CL_TX + xx) * CL_TY + yy) * CL_TZ + 2 * zp, CL_TX * CL_TY * CL_TZ,
+      put_pairs(dt + (((8 * q) * CL_TX + xx) * WL_TY + yy) * TZ + 2 * zp, CL_TX * WL_TY * TZ,
                 *(const uint4*)row, *(const uint4*)(row + a.cout));
     }
 #pragma unroll
@@ -587,22 +641,23 @@ __global__ __launch_bounds__(192) void wgrad_lds_kernel(WgradLdsArgs a) {
     }
     __syncthreads();
     if (box + 1 < bx1) prefetch(box + 1);
-    // k steps of 32 voxels: rows 2s and 2s + 1 of the 16 (x, y) rows, z
-    // halves 0 and 8; lane group g takes row 2s + (g >> 1), z half 8 (g & 1)
+    // k steps of 32 voxels: TZ = 16: rows 2s and 2s + 1 of the 16 (x, y)
+    // rows, z halves 0 and 8, lane group g takes row 2s + (g >> 1), z half
+    // 8 (g & 1); TZ = 8: rows 4s .. 4s + 3, lane group g takes row 4s + g
 #pragma unroll 1
-    for (int s = 0; s < 8; ++s) {
-      const int row = 2 * s + (g >> 1), zh = 8 * (g & 1);
+    for (int s = 0; s < NS; ++s) {
+      const int row = TZ == 16 ? 2 * s + (g >> 1) : 4 * s + g, zh = TZ == 16 ? 8 * (g & 1) : 0;
       const int rx = row >> 2, ry = row & 3;
       bf16x8 av[2];
 #pragma unroll
       for (int m = 0; m < 2; ++m)
-        av[m] = *(const bf16x8*)(dt + (((16 * m + l16) * CL_TX + rx) * CL_TY + ry) * CL_TZ + zh);
+        av[m] = *(const bf16x8*)(dt + (((16 * m + l16) * CL_TX + rx) * WL_TY + ry) * TZ + zh);
 #pragma unroll
       for (int p = 0; p < 3; ++p) {
         const int pr = wave + 3 * p, dx = pr / 3, dy = pr % 3;
 #pragma unroll
         for (int n = 0; n < 2; ++n) {
-          const uint16_t* w = xt + (((16 * n + l16) * CL_HX + rx + dx) * CL_HY + ry + dy) * WL_ZP + zh;
+          const uint16_t* w = xt + (((16 * n + l16) * WL_HX + rx + dx) * WL_HY + ry + dy) * ZP + zh;
           const uint4 lo = *(const uint4*)w, hi = *(const uint4*)(w + 8);
           const uint32_t d[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
           uint32_t s1[4];
@@ -956,53 +1011,102 @@ __global__ __launch_bounds__(256) void upsample_kernel(const uint16_t* in, int B
   *(uint4*)(out + e * 8) = pack8(o);
 }
 
-// adjoint weights of one axis: the input index i receives from the outputs
-// 2i, 2i + 1 (3/4 each), 2i - 1 and 2i + 2 (1/4 each, where they exist) and
-// at a face from the clamped output (1/4 more)
-__device__ __forceinline__ int up_adj(int i, int n, int* o, float* w) {
-  int k = 0;
-  o[k] = 2 * i; w[k++] = 0.75f;
-  o[k] = 2 * i + 1; w[k++] = 0.75f;
-  o[k] = i > 0 ? 2 * i - 1 : 0; w[k++] = 0.25f;
-  o[k] = i < n - 1 ? 2 * i + 2 : 2 * n - 1; w[k++] = 0.25f;
-  return k;
+// Adjoint weight of one axis: what output 2 i0 - 1 + j (j = 0..5, the
+// window of the input pair i0, i0 + 1) contributes to input x = i0 + i of
+// n.  The input x receives from the outputs 2x and 2x + 1 (3/4 each), 2x - 1
+// and 2x + 2 (1/4 each, where they exist) and at a face from the clamped
+// output (1/4 more): the adjoint of up_taps.
+__device__ __forceinline__ float up_adj_w(int j, int i, int x, int n) {
+  if (x >= n) return 0.f;
+  float w = 0.f;
+  if (j == 2 * i + 1) w += x == 0 ? 1.f : 0.75f;
+  if (j == 2 * i + 2) w += x == n - 1 ? 1.f : 0.75f;
+  if (j == 2 * i && x > 0) w += 0.25f;
+  if (j == 2 * i + 3 && x < n - 1) w += 0.25f;
+  return w;
 }
 
 // Adjoint of upsample_kernel: gin [B][X][Y][Z][C] (FP32) from gout
 // [B][2X][2Y][2Z][*] read with row stride sout from channel 0 (the upsampled
-// part of a concatenation's gradient)
+// part of a concatenation's gradient).  A thread takes 2 x 2 x 2 inputs
+// (x0 = 2 xp, ...) and 8 channels: it reads the 6 x 6 x 6 outputs they draw
+// on once (instead of 4 x 4 x 4 per input), contracting z into two partial
+// sums per (x, y) output row and those into the eight inputs.
 __global__ __launch_bounds__(256) void upsample_bwd_kernel(const float* gout, int sout, int B, int X, int Y, int Z,
                                                            int C, float* gin) {
   const int g = C / 8;
+  const int Xp = (X + 1) / 2, Yp = (Y + 1) / 2, Zp = (Z + 1) / 2;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t n = (int64_t)B * X * Y * Z * g;
+  const int64_t n = (int64_t)B * Xp * Yp * Zp * g;
   if (e >= n) return;
   const int c0 = (int)(e % g) * 8;
   int64_t r = e / g;
-  const int z = (int)(r % Z); r /= Z;
-  const int y = (int)(r % Y); r /= Y;
-  const int x = (int)(r % X);
-  const int b = (int)(r / X);
-  int ox[4], oy[4], oz[4];
-  float wx[4], wy[4], wz[4];
-  up_adj(x, X, ox, wx);
-  up_adj(y, Y, oy, wy);
-  up_adj(z, Z, oz, wz);
+  const int z0 = 2 * (int)(r % Zp); r /= Zp;
+  const int y0 = 2 * (int)(r % Yp); r /= Yp;
+  const int x0 = 2 * (int)(r % Xp);
+  const int b = (int)(r / Xp);
   const int Xo = 2 * X, Yo = 2 * Y, Zo = 2 * Z;
-  float o[8];
+  float acc[2][2][2][8];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) o[j] = 0.f;
-  for (int a = 0; a < 4; ++a)
-    for (int bb = 0; bb < 4; ++bb)
-      for (int c = 0; c < 4; ++c) {
-        const float wt = wx[a] * wy[bb] * wz[c];
-        const float* gp = gout + ((((int64_t)b * Xo + ox[a]) * Yo + oy[bb]) * Zo + oz[c]) * sout + c0;
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) o[j] += wt * gp[j];
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[i][j][k][c] = 0.f;
+#pragma unroll 1
+  for (int jx = 0; jx < 6; ++jx) {
+    const int ox = 2 * x0 - 1 + jx;
+    if (ox < 0 || ox >= Xo) continue;
+    const float wx[2] = {up_adj_w(jx, 0, x0, X), up_adj_w(jx, 1, x0 + 1, X)};
+#pragma unroll
+    for (int jy = 0; jy < 6; ++jy) {
+      const int oy = 2 * y0 - 1 + jy;
+      if (oy < 0 || oy >= Yo) continue;
+      const float wy[2] = {up_adj_w(jy, 0, y0, Y), up_adj_w(jy, 1, y0 + 1, Y)};
+      const float* row = gout + (((int64_t)b * Xo + ox) * Yo + oy) * Zo * sout + c0;
+      float tz[2][8];
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) tz[k][c] = 0.f;
+#pragma unroll
+      for (int jz = 0; jz < 6; ++jz) {
+        const int oz = 2 * z0 - 1 + jz;
+        if (oz < 0 || oz >= Zo) continue;
+        const float4 p = *(const float4*)(row + (int64_t)oz * sout), q = *(const float4*)(row + (int64_t)oz * sout + 4);
+        const float gv[8] = {p.x, p.y, p.z, p.w, q.x, q.y, q.z, q.w};
+        const float w0 = up_adj_w(jz, 0, z0, Z), w1 = up_adj_w(jz, 1, z0 + 1, Z);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          tz[0][c] += w0 * gv[c];
+          tz[1][c] += w1 * gv[c];
+        }
       }
-  float* gi = gin + e * 8;
-  *(float4*)gi = float4{o[0], o[1], o[2], o[3]};
-  *(float4*)(gi + 4) = float4{o[4], o[5], o[6], o[7]};
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const float w = wx[i] * wy[j];
+#pragma unroll
+          for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc[i][j][k][c] += w * tz[k][c];
+        }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        if (x0 + i >= X || y0 + j >= Y || z0 + k >= Z) continue;
+        float* gi = gin + ((((int64_t)b * X + x0 + i) * Y + y0 + j) * Z + z0 + k) * C + c0;
+        *(float4*)gi = float4{acc[i][j][k][0], acc[i][j][k][1], acc[i][j][k][2], acc[i][j][k][3]};
+        *(float4*)(gi + 4) = float4{acc[i][j][k][4], acc[i][j][k][5], acc[i][j][k][6], acc[i][j][k][7]};
+      }
 }
 
 // ------------------------------------------------------------------- I/O
