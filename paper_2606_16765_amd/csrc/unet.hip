@@ -172,20 +172,24 @@ static int64_t vox(const unet_net* n, int level, int B) {
 }
 
 // chunking of the LDS weight-gradient kernel: about 1024 blocks over the
-// (chunk, 32 output channels, 32 input channels) grid
-static int wgrad_lds_chunks(int64_t nbox, int cout, int cind, int64_t& per_chunk) {
-  const int64_t tiles = (int64_t)(cout / 32) * (cind / 32);
+// (chunk, 32 output channels, citiles input-channel tiles) grid
+static int wgrad_lds_chunks(int64_t nbox, int cout, int citiles, int64_t& per_chunk) {
+  const int64_t tiles = (int64_t)(cout / 32) * citiles;
   int64_t nc = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
   nc = std::min<int64_t>(nc, nbox);
   per_chunk = (nbox + nc - 1) / nc;
   return (int)((nbox + per_chunk - 1) / per_chunk);
 }
 
-// box depth of the LDS weight gradient for inputs of c0 + c1 channels on a
-// grid d (16 or 8), or 0 where it does not apply
-static int lds_tiling(int c0, int c1, const int* d) {
-  if (c0 % 32 || c1 % 32 || d[0] % CL_TX || d[1] % WL_TY) return 0;
-  return d[2] % 16 == 0 ? 16 : (d[2] % 8 == 0 ? 8 : 0);
+// tiling of the LDS weight gradient for inputs of c0 + c1 channels on a
+// grid d: the box depth (16 or 8; 0 where the kernel does not apply) and
+// the input-channel tile ci (32, or 8 for the 8-channel input layer, which
+// has an instance for 16-deep boxes only)
+static int lds_tiling(int c0, int c1, const int* d, int& ci) {
+  ci = c0 % 32 == 0 && c1 % 32 == 0 ? 32 : (c0 == 8 && c1 == 0 ? 8 : 0);
+  if (!ci || d[0] % CL_TX || d[1] % WL_TY) return 0;
+  const int tz = d[2] % 16 == 0 ? 16 : (d[2] % 8 == 0 ? 8 : 0);
+  return ci == 8 && tz != 16 ? 0 : tz;
 }
 
 // chunking of a weight-gradient reduction over V voxels for a (cout, K) tile grid
@@ -279,8 +283,9 @@ extern "C" int unet_create(const unet_params* pin, uint64_t seed, void* hip_stre
     int64_t ch;
     wgrad_chunks(V, k.cout, 27 * k.cind, nc, ch);
     n->part_cap = std::max<int64_t>(n->part_cap, (int64_t)nc * k.cout * 27 * k.cind);
-    if (const int tz = k.cout % 32 == 0 ? lds_tiling(k.cind, 0, n->dims[k.level]) : 0) {
-      nc = wgrad_lds_chunks(V / (CL_TX * WL_TY * tz), k.cout, k.cind, ch);
+    int ci = 0;
+    if (const int tz = k.cout % 32 == 0 ? lds_tiling(k.cind, 0, n->dims[k.level], ci) : 0) {
+      nc = wgrad_lds_chunks(V / (CL_TX * WL_TY * tz), k.cout, k.cind / ci, ch);
       n->part_cap = std::max<int64_t>(n->part_cap, (int64_t)nc * k.cout * 27 * k.cind);
     }
     // the k-split partials of the direct convolution (forward and input gradient)
@@ -498,15 +503,17 @@ static void wgrad(unet_net* n, int level, int B, const uint16_t* dz, int coutp_r
   const int K = taps * cind;
   int nchunk;
   int64_t chunk;
-  const int tz = taps == 27 && coutp_rows % 32 == 0 ? lds_tiling(c0, c1, d) : 0;
+  int ci = 0;
+  const int tz = taps == 27 && coutp_rows % 32 == 0 ? lds_tiling(c0, c1, d, ci) : 0;
   if (tz) {
     WgradLdsArgs a{};
     a.dz = dz; a.cout = coutp_rows; a.in0 = in0; a.in1 = in1; a.c0 = c0; a.c1 = c1;
     a.B = B; a.X = d[0]; a.Y = d[1]; a.Z = d[2]; a.part = n->part;
-    nchunk = wgrad_lds_chunks(V / (CL_TX * WL_TY * tz), coutp_rows, cind, a.per_chunk);
-    const dim3 grid((unsigned)nchunk, (unsigned)(coutp_rows / 32), (unsigned)(cind / 32));
-    if (tz == 16) hipLaunchKernelGGL(wgrad_lds_kernel<16>, grid, dim3(192), 0, n->st, a);
-    else hipLaunchKernelGGL(wgrad_lds_kernel<8>, grid, dim3(192), 0, n->st, a);
+    nchunk = wgrad_lds_chunks(V / (CL_TX * WL_TY * tz), coutp_rows, cind / ci, a.per_chunk);
+    const dim3 grid((unsigned)nchunk, (unsigned)(coutp_rows / 32), (unsigned)(cind / ci));
+    if (ci == 8) hipLaunchKernelGGL((wgrad_lds_kernel<16, 8>), grid, dim3(192), 0, n->st, a);
+    else if (tz == 16) hipLaunchKernelGGL((wgrad_lds_kernel<16, 32>), grid, dim3(192), 0, n->st, a);
+    else hipLaunchKernelGGL((wgrad_lds_kernel<8, 32>), grid, dim3(192), 0, n->st, a);
     const int64_t ncol = (int64_t)cout_param * K;
     hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((ncol + WR_COLS - 1) / WR_COLS)), dim3(256), 0, n->st,
                        n->part, nchunk, coutp_rows, cout_param, cin_param, cind, taps, dW);

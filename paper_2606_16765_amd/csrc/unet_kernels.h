@@ -505,18 +505,22 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
   }
 }
 
-// Weight gradient through LDS, for convolutions with input channels in
-// multiples of 32 and cout % 32 == 0 on a grid of 4 x 4 x TZ boxes (TZ = 16
-// or 8).  Grid (nchunk, cout / 32, cin / 32); three waves.  A block owns 32
-// output channels x 32 input channels x all 27 taps and walks the boxes
-// [blockIdx.x * per_chunk, ...).  Per box it stages the box's dz
-// [32 co][4][4][TZ] and the input halo [32 ci][6][6][ZP] (TZ + 2 z, padded)
-// transposed in LDS, z contiguous, so that an MFMA lane's k slots are 8
-// z-consecutive voxels (a 32-voxel k step is two (x, y) rows of 16 z, or
-// four rows of 8).  Wave w owns the (dx, dy) tap pairs w, w + 3, w + 6 and
-// all three dz of each: from one aligned 16-voxel window of the halo row it
-// forms the operands of the three z shifts in registers (the odd shift by
-// a 16-bit funnel shift), so no LDS read is misaligned.  The partials go to
+// Weight gradient through LDS, for convolutions with cout % 32 == 0 and
+// input channels in multiples of 32 (CI = 32) or the 8-channel input layer
+// (CI = 8), on a grid of 4 x 4 x TZ boxes (TZ = 16 or 8).  Grid (nchunk,
+// cout / 32, cin / CI); three waves.  A block owns 32 output channels x CI
+// input channels x all 27 taps and walks the boxes [blockIdx.x *
+// per_chunk, ...).  Per box it stages the box's dz [32 co][4][4][TZ] and
+// the input halo [CI][6][6][ZP] (TZ + 2 z, padded) transposed in LDS, z
+// contiguous, so that an MFMA lane's k slots are 8 z-consecutive voxels (a
+// 32-voxel k step is two (x, y) rows of 16 z, or four rows of 8).  The
+// product's 16 columns are (tap pair (dx, dy), input channel) pairs: CI =
+// 32: wave w owns the pairs w, w + 3, w + 6, each as two 16-channel column
+// tiles; CI = 8: column tile j holds pairs 2j and 2j + 1 x 8 channels, and
+// wave w owns the tiles w and w + 3 (of five).  Each lane forms the
+// operands of the three dz shifts of its column from one aligned 16-voxel
+// window of its halo row in registers (the odd shift by a 16-bit funnel
+// shift), so no LDS read is misaligned.  The partials go to
 // part[blockIdx.x][co][t * cin + ci], the layout wgrad_reduce_kernel sums.
 struct WgradLdsArgs {
   const uint16_t* dz;   // [V][cout] BF16
@@ -529,17 +533,19 @@ struct WgradLdsArgs {
   float* part;          // [nchunk][cout][27 cin]
 };
 
-template <int TZ>
+template <int TZ, int CI>
 __global__ __launch_bounds__(192) void wgrad_lds_kernel(WgradLdsArgs a) {
-  static_assert(TZ == 16 || TZ == 8, "box depth");
+  static_assert((TZ == 16 || TZ == 8) && (CI == 32 || CI == 8), "box depth, channel tile");
+  constexpr int Q = CI / 8;                 // 16-byte groups per staged voxel
+  constexpr int NT = CI == 32 ? 6 : 2;      // column tiles per wave
   constexpr int HZ = TZ + 2;                // halo row
   constexpr int ZP = TZ == 16 ? 24 : 16;    // padded halo row: the 16-voxel windows stay inside
   constexpr int NS = CL_TX * WL_TY * TZ / 32;  // k steps per box
-  __shared__ __attribute__((aligned(16))) uint16_t xt[32 * WL_HX * WL_HY * ZP];  // [ci][hx][hy][z]
+  __shared__ __attribute__((aligned(16))) uint16_t xt[CI * WL_HX * WL_HY * ZP];  // [ci][hx][hy][z]
   __shared__ __attribute__((aligned(16))) uint16_t dt[32 * CL_TX * WL_TY * TZ];  // [co][bx][by][z]
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4, l16 = lane & 15;
   const int cin = a.c0 + a.c1;
-  const int co0 = blockIdx.y * 32, ci0 = blockIdx.z * 32;
+  const int co0 = blockIdx.y * 32, ci0 = blockIdx.z * CI;
   const bool first = ci0 < a.c0;
   const uint16_t* src = first ? a.in0 : a.in1;
   const int cs = first ? a.c0 : a.c1;
@@ -549,20 +555,34 @@ __global__ __launch_bounds__(192) void wgrad_lds_kernel(WgradLdsArgs a) {
   const int64_t YZ = (int64_t)a.Y * a.Z;
   const int64_t bx0 = (int64_t)blockIdx.x * a.per_chunk;
   const int64_t bx1 = bx0 + a.per_chunk < nbox ? bx0 + a.per_chunk : nbox;
-  f32x4 acc[3][3][2][2];  // [pair][dz][co tile][ci tile]
+  f32x4 acc[NT][3][2];  // [column tile][dz][co tile]
 #pragma unroll
-  for (int p = 0; p < 3; ++p)
+  for (int p = 0; p < NT; ++p)
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
-      for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int n = 0; n < 2; ++n) acc[p][d][m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int m = 0; m < 2; ++m) acc[p][d][m] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // column tile tau of this wave: the lane's tap pair pr and input channel
+  // ci (CI = 8: tiles past the fifth, and the second half of the fifth,
+  // hold no pair: live is false there)
+  auto column = [&](int tau, int& pr, int& ci, bool& live) {
+    if (CI == 32) {
+      pr = wave + 3 * (tau >> 1);
+      ci = 16 * (tau & 1) + l16;
+      live = true;
+    } else {
+      const int j = wave + 3 * tau;
+      pr = 2 * j + (l16 >> 3);
+      ci = l16 & 7;
+      live = pr < 9;
+      if (pr > 8) pr = 8;
+    }
+  };
   // The first NP of the next box's NH input-halo items per thread are
   // loaded into registers while the current box computes; the rest of the
   // halo and the box's dz are loaded when the box starts.  (Holding more
   // would take the kernel past 256 registers, to one wave per SIMD.)
-  constexpr int HITEMS = WL_HX * WL_HY * (HZ / 2) * 4, DITEMS = CL_TX * WL_TY * (TZ / 2) * 4;
+  constexpr int HITEMS = WL_HX * WL_HY * (HZ / 2) * Q, DITEMS = CL_TX * WL_TY * (TZ / 2) * 4;
   constexpr int NH = (HITEMS + 191) / 192, NP = NH < 3 ? NH : 3;
   uint4 ph[NP][2];
   auto box_origin = [&](int64_t box, int& x0, int& y0, int& z0, int64_t& sbase) {
@@ -576,7 +596,7 @@ __global__ __launch_bounds__(192) void wgrad_lds_kernel(WgradLdsArgs a) {
   };
   // halo item e of a box (origin x0, y0, z0, sample base sbase) into v0, v1
   auto halo_item = [&](int e, int x0, int y0, int z0, int64_t sbase, uint4& v0, uint4& v1) {
-    const int q = e & 3, r = e >> 2;
+    const int q = e % Q, r = e / Q;
     const int hzp = r % (HZ / 2), hy = (r / (HZ / 2)) % WL_HY, hx = r / ((HZ / 2) * WL_HY);
     const int gx = x0 + hx - 1, gy = y0 + hy - 1;
     v0 = uint4{0u, 0u, 0u, 0u};
@@ -607,7 +627,7 @@ __global__ __launch_bounds__(192) void wgrad_lds_kernel(WgradLdsArgs a) {
   };
   // the halo item's LDS destination: rows (8 q + j, hx, hy), z pair hzp
   auto put_halo = [&](int e, const uint4& v0, const uint4& v1) {
-    const int q = e & 3, r = e >> 2;
+    const int q = e % Q, r = e / Q;
     const int hzp = r % (HZ / 2), hy = (r / (HZ / 2)) % WL_HY, hx = r / ((HZ / 2) * WL_HY);
     put_pairs(xt + (((8 * q) * WL_HX + hx) * WL_HY + hy) * ZP + 2 * hzp, WL_HX * WL_HY * ZP, v0, v1);
   };
@@ -653,11 +673,15 @@ __global__ __launch_bounds__(192) void wgrad_lds_kernel(WgradLdsArgs a) {
       for (int m = 0; m < 2; ++m)
         av[m] = *(const bf16x8*)(dt + (((16 * m + l16) * CL_TX + rx) * WL_TY + ry) * TZ + zh);
 #pragma unroll
-      for (int p = 0; p < 3; ++p) {
-        const int pr = wave + 3 * p, dx = pr / 3, dy = pr % 3;
-#pragma unroll
-        for (int n = 0; n < 2; ++n) {
-          const uint16_t* w = xt + (((16 * n + l16) * WL_HX + rx + dx) * WL_HY + ry + dy) * ZP + zh;
+      for (int tau = 0; tau < NT; ++tau) {
+        if (CI == 8 && wave + 3 * tau >= 5) continue;  // wave-uniform: no such tile
+        int pr, ci;
+        bool live;
+        column(tau, pr, ci, live);
+        (void)live;
+        const int dx = pr / 3, dy = pr % 3;
+        {
+          const uint16_t* w = xt + ((ci * WL_HX + rx + dx) * WL_HY + ry + dy) * ZP + zh;
           const uint4 lo = *(const uint4*)w, hi = *(const uint4*)(w + 8);
           const uint32_t d[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
           uint32_t s1[4];
@@ -670,29 +694,31 @@ __global__ __launch_bounds__(192) void wgrad_lds_kernel(WgradLdsArgs a) {
 #pragma unroll
           for (int dzi = 0; dzi < 3; ++dzi)
 #pragma unroll
-            for (int m = 0; m < 2; ++m) acc[p][dzi][m][n] = mfma16(av[m], bv[dzi], acc[p][dzi][m][n]);
+            for (int m = 0; m < 2; ++m) acc[tau][dzi][m] = mfma16(av[m], bv[dzi], acc[tau][dzi][m]);
         }
       }
     }
     __syncthreads();
   }
-  // D[co][ci]: co = co0 + 16m + 4g + r, ci = ci0 + 16n + l16
+  // D[co][column]: co = co0 + 16m + 4g + r, the lane's column (pr, ci)
   const int64_t K = (int64_t)27 * cin;
   float* part = a.part + (int64_t)blockIdx.x * a.cout * K;
 #pragma unroll
-  for (int p = 0; p < 3; ++p) {
-    const int pr = wave + 3 * p, dx = pr / 3, dy = pr % 3;
+  for (int tau = 0; tau < NT; ++tau) {
+    if (CI == 8 && wave + 3 * tau >= 5) continue;
+    int pr, ci;
+    bool live;
+    column(tau, pr, ci, live);
+    if (!live) continue;
+    const int dx = pr / 3, dy = pr % 3;
 #pragma unroll
     for (int dzi = 0; dzi < 3; ++dzi) {
       const int tap = 9 * dx + 3 * dy + dzi;
 #pragma unroll
       for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int n = 0; n < 2; ++n)
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            part[(int64_t)(co0 + 16 * m + 4 * g + r) * K + (int64_t)tap * cin + ci0 + 16 * n + l16] =
-                acc[p][dzi][m][n][r];
+        for (int r = 0; r < 4; ++r)
+          part[(int64_t)(co0 + 16 * m + 4 * g + r) * K + (int64_t)tap * cin + ci0 + ci] = acc[tau][dzi][m][r];
     }
   }
 }
