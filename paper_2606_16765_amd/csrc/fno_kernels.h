@@ -765,16 +765,17 @@ template <int ACT>
 __device__ __forceinline__ float proj_act_grad(float h, float w0) {
   return ACT == 1 ? w0 * cos_w(w0 * h) : gelu_grad(h);
 }
-// the activation and its derivative together (one erf for GELU)
+// the activation and its derivative together (one CDF evaluation for GELU)
 template <int ACT>
 __device__ __forceinline__ void proj_act_both(float h, float w0, float& a, float& da) {
   if (ACT == 1) {
     a = sin_w(w0 * h);
     da = w0 * cos_w(w0 * h);
   } else {
-    const float e = erff(h * 0.70710678118654752f);
-    a = 0.5f * h * (1.0f + e);
-    da = 0.5f * (1.0f + e) + h * expf(-0.5f * h * h) * 0.39894228040143268f;
+    const float cdf = norm_cdf_fit(h);
+    const float hc = __builtin_amdgcn_fmed3f(h, -6.f, 6.f);
+    a = h * cdf;
+    da = fmaf(h * 0.39894228f, __builtin_amdgcn_exp2f(-0.72134752f * hc * hc), cdf);
   }
 }
 template <int NT, int KS, bool STORE_A = false, int ACT = 0, bool RES = false>

@@ -386,6 +386,14 @@ extern "C" int unet_bn_stats(unet_net* n, float* host, int64_t count) {
 // per-block statistics partials.
 template <int CC, int TY, int TZ>
 static void launch_conv_lds(unet_net* n, const ConvArgs& a, int rows, unsigned gx) {
+  // 96 rows per block (the input gradients of the decoder's concatenating
+  // convolutions): each staged halo value feeds six MFMA row tiles
+  if constexpr (CC == 32) {
+    if (rows % 96 == 0) {
+      hipLaunchKernelGGL((conv_lds_kernel<96, CC, TY, TZ>), dim3(gx, (unsigned)(rows / 96)), dim3(256), 0, n->st, a);
+      return;
+    }
+  }
   if (rows % 64 == 0)
     hipLaunchKernelGGL((conv_lds_kernel<64, CC, TY, TZ>), dim3(gx, (unsigned)(rows / 64)), dim3(256), 0, n->st, a);
   else
