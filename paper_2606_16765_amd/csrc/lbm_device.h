@@ -46,12 +46,8 @@ __device__ __forceinline__ float f16_to_f32(uint16_t h) { return (float)__builti
 // v_cvt_f16_f32 rounds to nearest even in the default mode
 __device__ __forceinline__ uint16_t f32_to_f16(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
-__device__ __forceinline__ uint16_t f32_to_bf16(float v) {
-  uint32_t b = __float_as_uint(v);
-  // round to nearest, ties to even; quiet NaN stays NaN
-  uint32_t r = ((b & 0x7fffffffu) > 0x7f800000u) ? (0x7fc00000u) : (b + 0x7fffu + ((b >> 16) & 1u));
-  return (uint16_t)(r >> 16);
-}
+// v_cvt_pk_bf16_f32 rounds to nearest even; a NaN stays a (quiet) NaN
+__device__ __forceinline__ uint16_t f32_to_bf16(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 template <> struct Storage<f16s> {
   using T = float;
   static __device__ __forceinline__ float load(const f16s* p) { return f16_to_f32(*(const uint16_t*)p); }
