@@ -41,10 +41,10 @@ def _shape(cfg):
                    widths=tuple(cfg["widths"]), bottleneck=cfg["bottleneck"])
 
 
-def _setup(cfg, B, seed=1):
+def _setup(cfg, B, seed=1, max_batch=None):
     import torch
     from paper_2606_16765_amd import Unet
-    net = Unet(max_batch=B, seed=seed, **cfg)
+    net = Unet(max_batch=max_batch or B, seed=seed, **cfg)
     g = torch.Generator(device="cuda").manual_seed(seed)
     x = torch.randn((B, cfg["cin"], cfg["nx"], cfg["ny"], cfg["nz"]), device="cuda", generator=g).to(torch.bfloat16)
     t = torch.rand((B, cfg["cout"], cfg["nx"], cfg["ny"], cfg["nz"]), device="cuda", generator=g)
@@ -67,11 +67,12 @@ def test_forward_matches_oracle_small(training):
     net.close()
 
 
-def _grad_errors(cfg, B, seed=2, beta=None):
+def _grad_errors(cfg, B, seed=2, beta=None, max_batch=None):
     """Per-group relative L2 gradient errors against the oracle (beta: set
-    every batch-norm shift to this value first)."""
+    every batch-norm shift to this value first; max_batch: the batch the
+    network is created for, default B)."""
     import torch
-    net, x, t, mask = _setup(cfg, B, seed)
+    net, x, t, mask = _setup(cfg, B, seed, max_batch)
     s = _shape(cfg)
     theta = net.get_params()
     if beta is not None:
@@ -139,6 +140,34 @@ def test_full_size_forward_and_open_relu_gradients():
     assert errs["loss"] < 2e-4
     worst = max((v, k) for k, v in errs.items())
     assert worst[0] < 5e-2, worst
+
+
+# a 3 x 2 x 2 bottleneck grid: odd extents below the coarsest pooling
+ODD = dict(nx=48, ny=32, nz=32, cin=4, cout=4, widths=(8, 16, 32, 64), bottleneck=128)
+
+
+def test_odd_bottleneck_grid_below_the_sizing_batch():
+    """48 x 32 x 32 at batch 1 on a network created for batch 3: the
+    upsampling adjoint's 2 x 2 x 2 input blocks reach past the odd face of
+    the 3 x 2 x 2 bottleneck grid, and the bottleneck's k-split convolution
+    and its per-32-voxel statistics run at a batch below the one its buffers
+    were sized for.  Forward (both batch-norm modes) and every gradient
+    group with the ReLUs held open, at the bounds of the other small cases."""
+    net, x, _, _ = _setup(ODD, 1, seed=6, max_batch=3)
+    s = _shape(ODD)
+    p = U.unpack(net.get_params().astype(np.float64), s)
+    for training in (False, True):  # evaluation first: training passes move the running statistics
+        y = net.forward(x, training=training).cpu().numpy()
+        yo = U.forward(p, x.float().cpu().numpy().astype(np.float64), s, U.running_stats(s),
+                       training=training).numpy()
+        err = rel_l2(y, yo)
+        print("odd grid forward", training, err, flush=True)
+        assert err < 1e-2
+    net.close()
+    errs = _grad_errors(ODD, 1, seed=6, beta=10.0, max_batch=3)
+    assert errs["loss"] < 1e-4
+    worst = max((v, k) for k, v in errs.items())
+    assert worst[0] < 4e-2, worst
 
 
 def test_gradients_at_initialisation_agree_on_the_head_side():
