@@ -172,6 +172,13 @@ constexpr int CT_KT = 64;            // k held in LDS per pass (two MFMA steps)
 constexpr int CT_TS = CT_KT + 8;     // padded LDS row of the input tile
 constexpr int CT_DS = CT_J + 1;      // padded LDS row of the result tile
 
+// LDS element of the input tile at (column row r, k in [0, 64)): the eight
+// 16-byte k chunks of a row are permuted by XOR with (r / 8) mod 8, so that
+// the transposing store of LOAD_JRUN (lanes writing rows 8 apart at one k)
+// spreads over all banks instead of one; a chunk stays whole and 16-byte
+// aligned for the MFMA operand reads.
+__device__ __forceinline__ int ct_idx(int r, int k) { return r * CT_TS + (((k >> 3) ^ ((r >> 3) & 7)) << 3) + (k & 7); }
+
 template <typename InT, typename OutT, int LM, int EP>
 __global__ __launch_bounds__(256) void contract_kernel(ContractArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t tile[CT_J * CT_TS];
@@ -212,7 +219,7 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs a) {
         const int k = k0 + lk[q];
         uint16_t v = 0;
         if (cb[q] >= 0 && k < a.K) v = to_bf(in[cb[q] + kaddr(k)]);
-        tile[lj[q] * CT_TS + h * 32 + lk[q]] = v;
+        tile[ct_idx(lj[q], h * 32 + lk[q])] = v;
       }
     } else if (LM == LOAD_KRUN) {
       uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -221,13 +228,13 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs a) {
       uint4 w;
       w.x = v[0] | ((uint32_t)v[1] << 16); w.y = v[2] | ((uint32_t)v[3] << 16);
       w.z = v[4] | ((uint32_t)v[5] << 16); w.w = v[6] | ((uint32_t)v[7] << 16);
-      *(uint4*)(tile + lj[0] * CT_TS + h * 32 + lk[0]) = w;
+      *(uint4*)(tile + ct_idx(lj[0], h * 32 + lk[0])) = w;
     } else {
       uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       const int k = k0 + lk[0];
       if (cb[0] >= 0 && k < a.K) Vec8<InT>::load(in + cb[0] + kaddr(k), v);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) tile[(lj[0] + q) * CT_TS + h * 32 + lk[0]] = v[q];
+      for (int q = 0; q < 8; ++q) tile[ct_idx(lj[0] + q, h * 32 + lk[0])] = v[q];
     }
   };
 
@@ -261,7 +268,7 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs a) {
         const bf16x8 av = *(const bf16x8*)(a.gt + (int64_t)arow * a.kp + k0 + h * CT_K + akk);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const bf16x8 bv = *(const bf16x8*)(tile + (c * 16 + (lane & 15)) * CT_TS + h * 32 + akk);
+          const bf16x8 bv = *(const bf16x8*)(tile + ct_idx(c * 16 + (lane & 15), h * 32 + akk));
           acc[c] = mfma16(av, bv, acc[c]);
         }
       }
