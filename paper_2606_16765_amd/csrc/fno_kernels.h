@@ -580,15 +580,29 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
   // row tile h: every lane loads (from row 0 where its row or k range does
   // not exist) and selects at use, so no divergent branch feeds the MFMA
   uint4 rq[4][NT];
+  // (x, y) row and first z of column tile c, from block-uniform values (the
+  // wave index made scalar, so no per-lane 64-bit division is formed)
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const int64_t xyb = p0 / a.Z;
+  const int zr = (int)(p0 - xyb * a.Z);
+  const int64_t XYn = a.P / a.Z;
+  int64_t xyc[4];
+  int zbc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int o = zr + wv * 64 + c * 16;
+    const int q = o / a.Z;
+    xyc[c] = xyb + q;
+    zbc[c] = o - q * a.Z;
+  }
   if (C2R) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const int64_t xy = (p0 + wave * 64 + c * 16) / a.Z;  // (x, y) row index within the sample
 #pragma unroll
       for (int h = 0; h < NT; ++h) {
         const int w = h * 16 + (lane & 15);
         const bool ok = w < a.W && 8 * g < a.K2;
-        rq[c][h] = *(const uint4*)(a.r2 + (ok ? ((b * a.W + w) * (a.P / a.Z) + xy) * a.K2 + 8 * g : 0));
+        rq[c][h] = *(const uint4*)(a.r2 + (ok ? ((b * a.W + w) * XYn + xyc[c]) * a.K2 + 8 * g : 0));
       }
     }
   }
@@ -630,7 +644,7 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
     for (int c = 0; c < 4; ++c) acc2[h][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int c = 0; c < 4 * C2R; ++c) {
-    const int zb = (int)((p0 + wave * 64 + c * 16) % a.Z);  // first z of the tile
+    const int zb = zbc[c];  // first z of the tile
     const bf16x8 bv = *(const bf16x8*)(a.gi1 + (int64_t)(zb + (lane & 15)) * a.gi1_kp + 8 * g);
 #pragma unroll
     for (int h = 0; h < NT; ++h) {
