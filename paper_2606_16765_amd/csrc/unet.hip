@@ -587,7 +587,8 @@ extern "C" int unet_loss_grad(unet_net* n, const uint16_t* x, const float* targe
     const Blk& prev = l == 3 ? n->blk[ibot(1)] : n->blk[idec(l + 1, 1)];
     block_bwd(n, ka, B, n->up[l], prev.cout, n->blk[ienc(l, 1)].a, p.widths[l], n->gcat[l]);
     const int* dc = n->dims[l + 1];
-    const int64_t nin = vox(n, l + 1, B) * prev.cout / 8;
+    // one thread per 2 x 2 x 2 block of inputs and 8 channels
+    const int64_t nin = (int64_t)B * ((dc[0] + 1) / 2) * ((dc[1] + 1) / 2) * ((dc[2] + 1) / 2) * (prev.cout / 8);
     hipLaunchKernelGGL(upsample_bwd_kernel, dim3(nb256(nin)), dim3(256), 0, n->st, n->gcat[l], prev.cout + p.widths[l],
                        B, dc[0], dc[1], dc[2], prev.cout, n->blk[l == 3 ? ibot(1) : idec(l + 1, 1)].g);
   }
