@@ -863,7 +863,8 @@ __global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ 
       }
   if (RES) __syncthreads();  // every wave has its operand: the Q2 rows become the output tiles
   // (unrolled in the residual form, whose prefetched values are indexed by ct)
-#pragma unroll(RES ? 4 : 1)
+  constexpr int CT_UNROLL = RES ? 4 : 1;
+#pragma unroll CT_UNROLL
   for (int ct = 0; ct < 4; ++ct) {
     const int pt = wave * 64 + ct * 16 + (lane & 15);
     f32x4 acc[NT];
