@@ -568,6 +568,14 @@ static int forward_dft(fno_net* n, int B, const void* v, bool v_bf16, const GtMa
     c.out_so = 2 * MZ; c.out_sn1 = 1; c.nd = 1; c.alpha = 1.f; c.kcontig = true;
     if ((rc = contract(n, c))) return rc;
   }
+  // y and x in one pass where the shapes are the fused kernel's (Y = 64,
+  // 32 x 32 y/x modes, 16 z modes) and there are enough slabs to fill the chip
+  if (Y == 64 && MY == 32 && n->MX == 32 && MZ == 16 && X % 16 == 0 && n->F2.kp == 128 &&
+      n->F3.kp == 2 * X && (int64_t)B * W >= 256) {
+    hipLaunchKernelGGL(dft_yx_kernel, dim3((unsigned)(B * W)), dim3(512), 0, n->st, n->A1, n->F2.d, n->F3.d,
+                       (int)X, modes);
+    return LBM_OK;
+  }
   // y: cols (b,w,x) x kz, k = (y, part) at stride MZ -> A2[bwx][part][ky][kz]
   c = CSpec{};
   c.in = n->A1; c.in_bf16 = true; c.out = n->A2; c.out_bf16 = true; c.g = &n->F2;

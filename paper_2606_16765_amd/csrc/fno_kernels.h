@@ -497,6 +497,110 @@ __global__ __launch_bounds__(256) void pw_kernel(PwArgs a) {
   }
 }
 
+// ------------------------------------------- fused y and x forward stages
+// The y and x stages of the truncated forward DFT in one pass over one
+// (b, w) slab, for Y = 64, 2 my = 2 mx = 32 (64 real rows of each DFT
+// operand) and mz = 16:
+//   A2[x][n1][kz] = sum_k1 F2[k1][n1] A1[x][k1][kz],  k1 = 2 y + part,
+//                                                     n1 = 2 ky + part'
+//   modes[n2][ky][kz] = sum_k2 F3[k2][n2] A2[x][2 ky + p][kz],  k2 = 2 x + p
+// The y-stage output stays on chip (in LDS, rounded to BF16 as the
+// two-pass form stores it), so its 0.27 GB round trip per layer at batch 16
+// is gone; both stages accumulate their k steps in the two-pass order, so
+// the modes are bitwise those of the separate contractions.  Per chunk of
+// 16 x: two halves of 8 x are staged transposed in LDS (t1 [(x, kz)][k1]);
+// the y-stage rows are formed in 16-row tiles (the F2 operand held in
+// registers for the whole slab) and written as x-stage operands (t2
+// [(ky, kz)][k2]); then one x-stage k step of 32.  Eight waves: each owns
+// one 16-row tile and half the columns of both stages.
+constexpr int DYX_T1 = 136;  // t1 row: 128 k1 + 8
+constexpr int DYX_T2 = 40;   // t2 row: 32 k2 + 8
+
+// t2 element (row, k2): the four 16-byte k2 chunks permuted by XOR with
+// (ky / 2) mod 4, so that the four lane groups of a stage-1 store (ky two
+// apart) hit different banks
+__device__ __forceinline__ int dyx_t2(int row, int ky, int k) {
+  return row * DYX_T2 + ((((k >> 3) ^ ((ky >> 1) & 3))) << 3) + (k & 7);
+}
+
+__global__ __launch_bounds__(512) void dft_yx_kernel(const uint16_t* __restrict__ a1, const uint16_t* __restrict__ f2,
+                                                     const uint16_t* __restrict__ f3, int X,
+                                                     uint16_t* __restrict__ modes) {
+  __shared__ __attribute__((aligned(16))) uint16_t t1[128 * DYX_T1];
+  __shared__ __attribute__((aligned(16))) uint16_t t2[512 * DYX_T2];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4, l16 = lane & 15, kl = 8 * g;
+  // eight waves: row tile rt = wave % 4 of both stages; column half ch =
+  // wave / 4 (y stage: x columns 4 ch .. 4 ch + 3; x stage: ky 16 ch .. + 15)
+  const int rt = wave & 3, ch = wave >> 2;
+  const int64_t bw = blockIdx.x;
+  const uint16_t* src = a1 + bw * (int64_t)X * 2048;  // [x][y][part][kz]: 2048 values per x
+  bf16x8 af2[4];  // F2^T rows 16 rt + l16, the four k steps
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) af2[ks] = *(const bf16x8*)(f2 + (16 * rt + l16) * 128 + 32 * ks + kl);
+  f32x4 acc2[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc2[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int x0 = 0; x0 < X; x0 += 16) {
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      // x in [x0 + 8 h, x0 + 8 h + 8): 16384 contiguous values, item e =
+      // ((xl * 64 + y) * 2 + part) * 2 + q holds kz 8 q .. 8 q + 7
+      const uint16_t* hs = src + (int64_t)(x0 + 8 * h) * 2048;
+      uint4 v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = *(const uint4*)(hs + 8 * (t + 512 * i));
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int e = t + 512 * i;
+        const int q = e & 1, part = (e >> 1) & 1, y = (e >> 2) & 63, xl = e >> 8;
+        const uint32_t u[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          t1[(xl * 16 + 8 * q + j) * DYX_T1 + 2 * y + part] = (uint16_t)(u[j >> 1] >> (16 * (j & 1)));
+      }
+      __syncthreads();
+      f32x4 acc1[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc1[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const bf16x8 bv = *(const bf16x8*)(t1 + (16 * (4 * ch + c) + l16) * DYX_T1 + 32 * ks + kl);
+          acc1[c] = mfma16(af2[ks], bv, acc1[c]);
+        }
+      // lane holds rows n1 = 16 rt + 4 g + r (ky = 8 rt + 2 g + r / 2,
+      // part' = r % 2) of column (x = x0 + 8 h + 4 ch + c, kz = l16); the two
+      // parts are adjacent x-stage k values (k2 = 2 x + part')
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int k2 = 2 * (8 * h + 4 * ch + c);
+#pragma unroll
+        for (int rp = 0; rp < 2; ++rp) {
+          const int ky = 8 * rt + 2 * g + rp;
+          *(uint32_t*)(t2 + dyx_t2(ky * 16 + l16, ky, k2)) = f2bf2(acc1[c][2 * rp], acc1[c][2 * rp + 1]);
+        }
+      }
+      __syncthreads();
+    }
+    // x-stage k step x0 / 16 for rows n2 = 16 rt .. + 15 and the columns
+    // (ky = 16 ch + i, kz = l16)
+    const bf16x8 af3 = *(const bf16x8*)(f3 + (int64_t)(16 * rt + l16) * (2 * X) + 2 * x0 + kl);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int ky = 16 * ch + i;
+      const bf16x8 bv = *(const bf16x8*)(t2 + dyx_t2(16 * ky + l16, ky, kl));
+      acc2[i] = mfma16(af3, bv, acc2[i]);
+    }
+  }
+  // modes[bw][n2][ky][kz], n2 = 16 rt + 4 g + r, ky = 16 ch + i, kz = l16
+  uint16_t* mo = modes + bw * 64 * 512;
+#pragma unroll
+  for (int i = 0; i < 16; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) mo[(16 * rt + 4 * g + r) * 512 + (16 * ch + i) * 16 + l16] = f2bf(acc2[i][r]);
+}
+
 // ------------------------------------------------- fused layer completion
 // The end of a Fourier layer in one pass over 256 points of one sample:
 //   h[b][w][p] = sum_c Wp[w][c] v[b][c][p]                  (channel map)
