@@ -602,6 +602,12 @@ static int inverse_dft(fno_net* n, int B, const uint16_t* modes, const GtMat& Gz
   const int64_t W = n->W, X = n->X, Y = n->Y, Z = n->Z, MY = n->MY, MZ = n->MZ;
   int rc;
   CSpec c{};
+  // x and y in one pass where the shapes are the fused kernel's
+  if (Y == 64 && MY == 32 && n->MX == 32 && MZ == 16 && X % 8 == 0 && n->I3.kp == 64 && n->I2.kp == 64 &&
+      (int64_t)B * W >= 256) {
+    hipLaunchKernelGGL(idft_xy_kernel, dim3((unsigned)(B * W)), dim3(512), 0, n->st, modes, n->I3.d, n->I2.d,
+                       (int)X, n->R2);
+  } else {
   // x: cols (b,w) x (ky,kz); k = (kx, part) at stride MY*MZ (mode-minor)
   c.in = modes; c.in_bf16 = true; c.out = n->R3; c.out_bf16 = true; c.g = &n->I3;
   c.cols = (int64_t)B * W * MY * MZ; c.I = MY * MZ; c.in_so = (int64_t)n->MX * 2 * MY * MZ; c.in_si = 1;
@@ -614,6 +620,7 @@ static int inverse_dft(fno_net* n, int B, const uint16_t* modes, const GtMat& Gz
   c.cols = (int64_t)B * W * X * MZ; c.I = MZ; c.in_so = 2 * MY * MZ; c.in_si = 1; c.in_sk1 = MZ; c.in_sk2 = MY * MZ;
   c.kd = 2; c.out_so = Y * 2 * MZ; c.out_si = 1; c.out_sn1 = MZ; c.nd = 1; c.alpha = 1.f;
   if ((rc = contract(n, c))) return rc;
+  }
   if (!out) return LBM_OK;
   // z (c2r): rows (b,w,x,y), k = (part, kz) contiguous
   c = CSpec{};

@@ -601,6 +601,103 @@ __global__ __launch_bounds__(512) void dft_yx_kernel(const uint16_t* __restrict_
     for (int r = 0; r < 4; ++r) mo[(16 * rt + 4 * g + r) * 512 + (16 * ch + i) * 16 + l16] = f2bf(acc2[i][r]);
 }
 
+// ----------------------------------------- fused x and y inverse stages
+// The x and y stages of the truncated inverse DFT in one pass over one
+// (b, w) slab, for the same shapes as dft_yx_kernel:
+//   R3[n3][ky][kz] = sum_k3 I3[k3][n3] modes[k3][ky][kz],  k3 = 2 kx + part,
+//                                                          n3 = 2 x + part'
+//   R2[x][n2][kz] = sum_k2 I2[k2][n2] R3[2 x + p][ky][kz],  k2 = 2 ky + p,
+//                                                          n2 = 2 y + part'
+// The slab's modes (64 KB) are staged once in LDS, transposed
+// (t0 [(ky, kz)][k3]); per chunk of 8 x the x-stage rows (16 of them) are
+// formed for all 512 (ky, kz) columns, rounded to BF16 as the two-pass form
+// stores them and staged as y-stage operands (t3 [(x, kz)][k2]); the y stage
+// then writes R2 for those 8 x.  R3's round trip through memory is gone;
+// the k steps run in the two-pass order, so R2 is bitwise the same.  Eight
+// waves: x stage, four column tiles each; y stage, one 16-row tile each.
+constexpr int IXY_T0 = 72;   // t0 row: 64 k3 + 8
+constexpr int IXY_T3 = 72;   // t3 row: 64 k2 + 8
+
+// t3 element (row = (x - x0) * 16 + kz, k2): the eight 16-byte k2 chunks
+// permuted by XOR with x - x0, so that the x-stage stores of the four lane
+// groups (x two apart) hit different banks
+__device__ __forceinline__ int ixy_t3(int row, int k) {
+  return row * IXY_T3 + ((((k >> 3) ^ ((row >> 4) & 7))) << 3) + (k & 7);
+}
+
+__global__ __launch_bounds__(512) void idft_xy_kernel(const uint16_t* __restrict__ modes,
+                                                      const uint16_t* __restrict__ i3,
+                                                      const uint16_t* __restrict__ i2, int X,
+                                                      uint16_t* __restrict__ r2) {
+  __shared__ __attribute__((aligned(16))) uint16_t t0[512 * IXY_T0];
+  __shared__ __attribute__((aligned(16))) uint16_t t3[128 * IXY_T3];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4, l16 = lane & 15, kl = 8 * g;
+  const int64_t bw = blockIdx.x;
+  // modes[bw][k3][ky][kz]: 64 rows of 512; item e = (col / 8) * 64 + k3, so
+  // that the 64 lanes of a wave store one t0 row's 64 k3 values together
+  const uint16_t* mi = modes + bw * 64 * 512;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int e = t + 512 * i;
+    const int k3 = e & 63, col0 = 8 * (e >> 6);
+    const uint4 v = *(const uint4*)(mi + k3 * 512 + col0);
+    const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 8; ++j) t0[(col0 + j) * IXY_T0 + k3] = (uint16_t)(u[j >> 1] >> (16 * (j & 1)));
+  }
+  // y-stage A operand: I2^T rows 16 wave + l16 (n2 = 2 y + part'), both k steps
+  bf16x8 ai2[2];
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks) ai2[ks] = *(const bf16x8*)(i2 + (16 * wave + l16) * 64 + 32 * ks + kl);
+  __syncthreads();
+  for (int x0 = 0; x0 < X; x0 += 8) {
+    // x stage: rows n3 = 2 x0 .. 2 x0 + 15, columns (ky = 4 wave + c, kz = l16)
+    bf16x8 ai3[2];
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) ai3[ks] = *(const bf16x8*)(i3 + (2 * x0 + l16) * 64 + 32 * ks + kl);
+    f32x4 a3[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a3[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const bf16x8 bv = *(const bf16x8*)(t0 + ((4 * wave + c) * 16 + l16) * IXY_T0 + 32 * ks + kl);
+        a3[c] = mfma16(ai3[ks], bv, a3[c]);
+      }
+    // lane holds n3 = 2 x0 + 4 g + r (x = x0 + 2 g + r / 2, part = r % 2) of
+    // column (ky, kz): y-stage operand t3 [(x - x0, kz)][2 ky + part]
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int ky = 4 * wave + c;
+#pragma unroll
+      for (int rp = 0; rp < 2; ++rp) {
+        const int xl = 2 * g + rp;
+        *(uint32_t*)(t3 + ixy_t3(xl * 16 + l16, 2 * ky)) = f2bf2(a3[c][2 * rp], a3[c][2 * rp + 1]);
+      }
+    }
+    __syncthreads();
+    // y stage: rows n2 = 16 wave .. + 15, columns (x = x0 + c, kz = l16)
+    f32x4 a2[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) a2[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const bf16x8 bv = *(const bf16x8*)(t3 + ixy_t3(16 * c + l16, 32 * ks + kl));
+        a2[c] = mfma16(ai2[ks], bv, a2[c]);
+      }
+    // R2[bw][x][n2][kz] = [x][y][part][kz]: n2 = 16 wave + 4 g + r
+    uint16_t* ro = r2 + (bw * X + x0) * 128 * 16;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) ro[((int64_t)c * 128 + 16 * wave + 4 * g + r) * 16 + l16] = f2bf(a2[c][r]);
+    __syncthreads();  // t3 is read: the next chunk may write it
+  }
+}
+
 // ------------------------------------------------- fused layer completion
 // The end of a Fourier layer in one pass over 256 points of one sample:
 //   h[b][w][p] = sum_c Wp[w][c] v[b][c][p]                  (channel map)
