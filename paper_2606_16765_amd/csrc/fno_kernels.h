@@ -1672,15 +1672,33 @@ __global__ __launch_bounds__(256) void gram2_kernel(const XT* __restrict__ X, co
   }
 }
 
+// sum over j = 0 .. n - 1 of p[j * step], added in increasing j from 0 (the
+// order of the plain loop, so the result is that loop's to the bit), with
+// sixteen loads in flight at a time instead of one
+template <typename T>
+__device__ __forceinline__ float ordered_sum(const T* p, int64_t n, int64_t step) {
+  constexpr int U = 16;
+  float acc = 0.f;
+  int64_t j = 0;
+  for (; j + U <= n; j += U) {
+    float x[U];
+#pragma unroll
+    for (int i = 0; i < U; ++i) x[i] = to_f(p[(j + i) * step]);
+#pragma unroll
+    for (int i = 0; i < U; ++i) acc += x[i];
+  }
+  for (; j < n; ++j) acc += to_f(p[j * step]);
+  return acc;
+}
+
 // part2[s][e] = sum over parts k = s, s + S, s + 2S, ... of part[k][e]
 __global__ __launch_bounds__(256) void reduce_slices_kernel(const float* part, int64_t nparts, int64_t E, int S,
                                                             float* part2) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int s = blockIdx.y;
   if (e >= E) return;
-  float acc = 0.f;
-  for (int64_t k = s; k < nparts; k += S) acc += part[k * E + e];
-  part2[(int64_t)s * E + e] = acc;
+  const int64_t n = s < nparts ? (nparts - s + S - 1) / S : 0;  // k = s, s + S, ... below nparts
+  part2[(int64_t)s * E + e] = ordered_sum(part + (int64_t)s * E + e, n, (int64_t)S * E);
 }
 
 // out[e] (+)= sum_s part[s][e], fixed order
@@ -1688,8 +1706,7 @@ __global__ __launch_bounds__(256) void reduce_parts_kernel(const float* part, in
                                                            int accumulate) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= E) return;
-  float s = 0.f;
-  for (int64_t k = 0; k < nparts; ++k) s += part[k * E + e];
+  const float s = ordered_sum(part + e, nparts, E);
   out[e] = accumulate ? out[e] + s : s;
 }
 
@@ -1702,8 +1719,8 @@ __global__ __launch_bounds__(256) void colsum_kernel(const XT* X, int A, int64_t
   const int64_t per_b = P / chunk;
   const int64_t b = blockIdx.x / per_b, p0 = (blockIdx.x % per_b) * chunk;
   const XT* x = X + (b * A + a) * P + p0;
-  float s = 0.f;
-  for (int64_t p = threadIdx.x; p < chunk; p += 256) s += to_f(x[p]);
+  const int64_t n = threadIdx.x < chunk ? (chunk - threadIdx.x + 255) / 256 : 0;
+  const float s = ordered_sum(x + threadIdx.x, n, (int64_t)256);
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
