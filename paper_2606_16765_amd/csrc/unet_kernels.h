@@ -742,8 +742,16 @@ __global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* part, in
   if (col < ncol) {
     const float* p = part + col;
     const int64_t cs = (int64_t)coutp * K;
-#pragma unroll 4
-    for (int c = wave; c < nchunk; c += 4) s += p[c * cs];
+    // chunks wave, wave + 4, ... added in that order, eight loads in flight
+    int c = wave;
+    for (; c + 28 < nchunk; c += 32) {
+      float x[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) x[i] = p[(int64_t)(c + 4 * i) * cs];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s += x[i];
+    }
+    for (; c < nchunk; c += 4) s += p[(int64_t)c * cs];
   }
   sm[wave][lane] = s;
   __syncthreads();
@@ -752,6 +760,30 @@ __global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* part, in
     const int r = (int)(col % K);
     const int t = r / cinp, ci = r % cinp;
     if (ci < cin) dW[((int64_t)co * cin + ci) * taps + t] = (sm[0][lane] + sm[1][lane]) + (sm[2][lane] + sm[3][lane]);
+  }
+}
+
+// FP64 sums of the (first, second) float pairs at p[(b * C + c) * 2] over
+// b = b0, b0 + 256, ... below nblk, added in increasing b (the order of the
+// plain strided loop, so the sums are that loop's to the bit), with eight
+// 8-byte loads in flight at a time
+__device__ __forceinline__ void strided_pair_sums(const float* p, int64_t b0, int64_t nblk, int C, int c, double& s,
+                                                  double& q) {
+  int64_t b = b0;
+  for (; b + 7 * 256 < nblk; b += 8 * 256) {
+    float2 x[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i] = *(const float2*)(p + ((b + i * 256) * C + c) * 2);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      s += (double)x[i].x;
+      q += (double)x[i].y;
+    }
+  }
+  for (; b < nblk; b += 256) {
+    const float2 x = *(const float2*)(p + (b * C + c) * 2);
+    s += (double)x.x;
+    q += (double)x.y;
   }
 }
 
@@ -769,11 +801,7 @@ __global__ __launch_bounds__(256) void bn_finalize_kernel(const float* stats, in
   const int c = blockIdx.x;
   __shared__ double rs[256], rq[256];
   double s = 0.0, q = 0.0;
-  if (train)
-    for (int64_t b = threadIdx.x; b < nblk; b += 256) {
-      s += (double)stats[(b * C + c) * 2];
-      q += (double)stats[(b * C + c) * 2 + 1];
-    }
+  if (train) strided_pair_sums(stats, threadIdx.x, nblk, C, c, s, q);
   rs[threadIdx.x] = s;
   rq[threadIdx.x] = q;
   __syncthreads();
@@ -871,10 +899,7 @@ __global__ __launch_bounds__(256) void bn_bwd_finalize_kernel(const float* parti
   const int c = blockIdx.x;
   __shared__ double rs[256], rq[256];
   double s = 0.0, q = 0.0;
-  for (int64_t b = threadIdx.x; b < nblk; b += 256) {
-    s += (double)partial[(b * C + c) * 2];
-    q += (double)partial[(b * C + c) * 2 + 1];
-  }
+  strided_pair_sums(partial, threadIdx.x, nblk, C, c, s, q);
   rs[threadIdx.x] = s;
   rq[threadIdx.x] = q;
   __syncthreads();
@@ -1256,7 +1281,15 @@ __global__ __launch_bounds__(256) void head_reduce_kernel(const float* part, int
   const int i = blockIdx.x;
   __shared__ double r[256];
   double s = 0.0;
-  for (int64_t b = threadIdx.x; b < nblk; b += 256) s += (double)part[b * 9 + i];
+  int64_t b = threadIdx.x;
+  for (; b + 7 * 256 < nblk; b += 8 * 256) {
+    float x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = part[(b + k * 256) * 9 + i];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += (double)x[k];
+  }
+  for (; b < nblk; b += 256) s += (double)part[b * 9 + i];
   r[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
