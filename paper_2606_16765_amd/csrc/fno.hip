@@ -1131,6 +1131,13 @@ static void mix_grad(fno_net* n, int B, const uint16_t* v, const uint16_t* gy, f
                        gw, B, (int)n->W, n->MX, Q, 0);
 }
 
+// layer_end_kernel with the one-row c2r operands where Z = 64
+template <int NT, typename InT, bool C2R = true>
+static void launch_le(const LayerEndArgs& e, dim3 grid, hipStream_t st) {
+  if (e.Z == 64) hipLaunchKernelGGL((layer_end_kernel<NT, InT, C2R, true>), grid, dim3(256), 0, st, e);
+  else hipLaunchKernelGGL((layer_end_kernel<NT, InT, C2R, false>), grid, dim3(256), 0, st, e);
+}
+
 static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout, bool training) {
   const int64_t W = n->W;
   int rc;
@@ -1145,8 +1152,7 @@ static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout, bool 
     e.bias = n->theta + n->off_p; e.h = nullptr; e.act = n->v[0];
     e.P = n->P; e.W = (int)W; e.Win = n->p.cin; e.Z = n->Z; e.K2 = 2 * n->MZ; e.act_gelu = 0;
     e.gz = n->F1.d; e.gz_kp = n->F1.kp; e.a1 = n->A1;
-    hipLaunchKernelGGL((layer_end_kernel<2, uint16_t, false>), dim3((unsigned)((int64_t)B * n->P / PW_J)), dim3(256),
-                       0, n->st, e);
+    launch_le<2, uint16_t, false>(e, dim3((unsigned)((int64_t)B * n->P / PW_J)), n->st);
     z_done = true;
   } else if ((rc = pointwise(n, B, x, true, n->p.cin, nullptr, false, (int)W, &n->Glift, n->theta + n->off_p, false,
                              false, n->v[0], false))) {
@@ -1173,8 +1179,8 @@ static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout, bool 
       e.bias = nullptr; e.h = nullptr; e.act = sl;
       e.P = n->P; e.W = (int)W; e.Win = 0; e.Z = n->Z; e.K2 = 2 * n->MZ; e.act_gelu = 0;
       const dim3 grid((unsigned)((int64_t)B * n->P / PW_J));
-      if (W <= 16) hipLaunchKernelGGL((layer_end_kernel<1, uint16_t>), grid, dim3(256), 0, n->st, e);
-      else hipLaunchKernelGGL((layer_end_kernel<2, uint16_t>), grid, dim3(256), 0, n->st, e);
+      if (W <= 16) launch_le<1, uint16_t>(e, grid, n->st);
+      else launch_le<2, uint16_t>(e, grid, n->st);
       launch_ffn(n, l, B, sl, n->v[l], n->v[l + 1], training ? n->Aff[l] : nullptr);
       continue;
     }
@@ -1190,8 +1196,8 @@ static int forward_impl(fno_net* n, const uint16_t* x, int B, float* yout, bool 
         z_done = true;
       }
       const dim3 grid((unsigned)((int64_t)B * n->P / PW_J));
-      if (W <= 16) hipLaunchKernelGGL((layer_end_kernel<1, uint16_t>), grid, dim3(256), 0, n->st, e);
-      else hipLaunchKernelGGL((layer_end_kernel<2, uint16_t>), grid, dim3(256), 0, n->st, e);
+      if (W <= 16) launch_le<1, uint16_t>(e, grid, n->st);
+      else launch_le<2, uint16_t>(e, grid, n->st);
     } else {
       if ((rc = inverse_dft(n, B, n->Yh, n->I1, n->h[l], false))) return rc;
       if ((rc = pointwise(n, B, n->v[l], true, (int)W, n->h[l], false, (int)W, &n->Gwp[l], n->theta + n->off_bp[l],
@@ -1302,8 +1308,8 @@ extern "C" int fno_loss_grad(fno_net* n, const uint16_t* x, const float* target,
     e.bias = nullptr; e.h = n->gvn; e.act = nullptr; e.gmul = nullptr; e.resid = n->gv;
     e.P = n->P; e.W = (int)W; e.Win = 0; e.Z = n->Z; e.K2 = 2 * n->MZ; e.act_gelu = 0;
     const dim3 grid((unsigned)((int64_t)B * n->P / PW_J));
-    if (W <= 16) hipLaunchKernelGGL((layer_end_kernel<1, float>), grid, dim3(256), 0, n->st, e);
-    else hipLaunchKernelGGL((layer_end_kernel<2, float>), grid, dim3(256), 0, n->st, e);
+    if (W <= 16) launch_le<1, float>(e, grid, n->st);
+    else launch_le<2, float>(e, grid, n->st);
     std::swap(n->gv, n->gvn);
   }
   for (int l = n->L - 1; l >= 0 && !n->hybrid; --l) {
@@ -1323,8 +1329,8 @@ extern "C" int fno_loss_grad(fno_net* n, const uint16_t* x, const float* target,
       e.bias = nullptr; e.h = n->gvn; e.act = nullptr; e.gmul = gmul;
       e.P = n->P; e.W = (int)W; e.Win = (int)W; e.Z = n->Z; e.K2 = 2 * n->MZ; e.act_gelu = 0;
       const dim3 grid((unsigned)((int64_t)B * n->P / PW_J));
-      if (W <= 16) hipLaunchKernelGGL((layer_end_kernel<1, float>), grid, dim3(256), 0, n->st, e);
-      else hipLaunchKernelGGL((layer_end_kernel<2, float>), grid, dim3(256), 0, n->st, e);
+      if (W <= 16) launch_le<1, float>(e, grid, n->st);
+      else launch_le<2, float>(e, grid, n->st);
     } else {
       if ((rc = pointwise(n, B, n->gv, false, (int)W, n->gvn, false, (int)W, &n->Gwpt[l], nullptr, false)))
         return rc;

@@ -752,14 +752,22 @@ template <> __device__ __forceinline__ uint4 load8_bf<float>(const float* p) {
   return uint4{f2bf2(x.x, x.y), f2bf2(x.z, x.w), f2bf2(y.x, y.y), f2bf2(y.z, y.w)};
 }
 
-template <int NT, typename InT, bool C2R = true>  // NT = ceil(W / 16), W <= 32; C2R: r2 term present
+// Column of the layer end's FP32 result tile [32 rows][256 points]: the
+// 16-point groups are XOR-permuted by row / 4, so the four row groups of
+// one accumulator store fall in disjoint banks without padding the rows,
+// and the four consecutive points a thread reads stay contiguous.
+__device__ __forceinline__ int le_col(int row, int p) { return p ^ (((row >> 2) & 3) << 4); }
+
+// NT = ceil(W / 16), W <= 32; C2R: r2 term present; ROW64: Z = 64, so each
+// wave's 64 points are one (x, y) row and its c2r operands are one R2 row
+template <int NT, typename InT, bool C2R = true, bool ROW64 = false>
 __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
   // one LDS region holds in turn the v tile [256 points][PW_TS], the FP32
-  // result tile [32][PW_DS] and the BF16 activation tile [32][PW_J + 8] of
-  // the fused z-DFT (33 KB, so 4 blocks fit a CU)
+  // result tile [32][PW_J] and the BF16 activation tile [32][PW_J + 8] of
+  // the fused z-DFT (32 KB, so 5 blocks fit a CU)
   constexpr int AP = PW_J + 8;
-  static_assert(32 * AP * 2 <= 32 * PW_DS * 4 && 256 * PW_TS * 2 <= 32 * PW_DS * 4, "LDS reuse");
-  __shared__ __attribute__((aligned(16))) float lds[32 * PW_DS];
+  static_assert(32 * AP * 2 <= 32 * PW_J * 4 && 256 * PW_TS * 2 <= 32 * PW_J * 4, "LDS reuse");
+  __shared__ __attribute__((aligned(16))) float lds[32 * PW_J];
   uint16_t* tile = (uint16_t*)lds;
   float* dst = lds;
   uint16_t* at = (uint16_t*)lds;
@@ -780,7 +788,7 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
   // c2r operand of column tile c (points pp .. pp + 15 of one (x, y) row) and
   // row tile h: every lane loads (from row 0 where its row or k range does
   // not exist) and selects at use, so no divergent branch feeds the MFMA
-  uint4 rq[4][NT];
+  uint4 rq[ROW64 ? 1 : 4][NT];
   // (x, y) row and first z of column tile c, from block-uniform values (the
   // wave index made scalar, so no per-lane 64-bit division is formed)
   const int wv = __builtin_amdgcn_readfirstlane(wave);
@@ -798,7 +806,7 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
   }
   if (C2R) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < (ROW64 ? 1 : 4); ++c) {
 #pragma unroll
       for (int h = 0; h < NT; ++h) {
         const int w = h * 16 + (lane & 15);
@@ -851,8 +859,8 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
     for (int h = 0; h < NT; ++h) {
       const int w = h * 16 + (lane & 15);
       const bool ok = w < a.W && 8 * g < a.K2;
-      const uint32_t e[4] = {ok ? rq[c][h].x : 0u, ok ? rq[c][h].y : 0u, ok ? rq[c][h].z : 0u,
-                             ok ? rq[c][h].w : 0u};
+      const uint4 rr = rq[ROW64 ? 0 : c][h];
+      const uint32_t e[4] = {ok ? rr.x : 0u, ok ? rr.y : 0u, ok ? rr.z : 0u, ok ? rr.w : 0u};
       bf16x8 av;
 #pragma unroll
       for (int j = 0; j < 8; ++j) av[j] = __builtin_bit_cast(__bf16, (uint16_t)(e[j >> 1] >> (16 * (j & 1))));
@@ -867,7 +875,8 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
     for (int c = 0; c < 4; ++c)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        dst[(h * 16 + 4 * g + r) * PW_DS + wave * 64 + c * 16 + l16] = acc[h][c][r] + acc2[h][c][r];
+        dst[(h * 16 + 4 * g + r) * PW_J + le_col(h * 16 + 4 * g + r, wave * 64 + c * 16 + l16)] =
+            acc[h][c][r] + acc2[h][c][r];
   __syncthreads();
   float* hout = a.h ? a.h + b * a.W * a.P + p0 : nullptr;
   uint16_t* act = a.act ? a.act + b * a.W * a.P + p0 : nullptr;
@@ -881,7 +890,7 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
     const int n = e >> 6, p4 = (e & 63) * 4;
     wz[q] = uint2{0u, 0u};
     if (n >= a.W) continue;
-    float4 v = *(const float4*)(dst + n * PW_DS + p4);
+    float4 v = *(const float4*)(dst + n * PW_J + le_col(n, p4));
     const int64_t off = (int64_t)n * a.P + p4;
     if (a.bias) {
       const float bb = a.bias[n];
