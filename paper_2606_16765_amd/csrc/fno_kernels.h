@@ -761,13 +761,13 @@ __device__ __forceinline__ int le_col(int row, int p) { return p ^ (((row >> 2) 
 // NT = ceil(W / 16), W <= 32; C2R: r2 term present; ROW64: Z = 64, so each
 // wave's 64 points are one (x, y) row and its c2r operands are one R2 row
 template <int NT, typename InT, bool C2R = true, bool ROW64 = false>
-__global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void layer_end_kernel(LayerEndArgs a) {
   // one LDS region holds in turn the v tile [256 points][PW_TS], the FP32
-  // result tile [32][PW_J] and the BF16 activation tile [32][PW_J + 8] of
-  // the fused z-DFT (32 KB, so 5 blocks fit a CU)
-  constexpr int AP = PW_J + 8;
-  static_assert(32 * AP * 2 <= 32 * PW_J * 4 && 256 * PW_TS * 2 <= 32 * PW_J * 4, "LDS reuse");
-  __shared__ __attribute__((aligned(16))) float lds[32 * PW_J];
+  // result tile 16 rows at a time [16][PW_J] and the BF16 activation tile
+  // [32][PW_J + 8] of the fused z-DFT (20 KB)
+  constexpr int AP = PW_J + 8, LDS_BYTES = PW_J * PW_TS * 2;
+  static_assert(32 * AP * 2 <= LDS_BYTES && 16 * PW_J * 4 <= LDS_BYTES, "LDS reuse");
+  __shared__ __attribute__((aligned(16))) float lds[LDS_BYTES / 4];
   uint16_t* tile = (uint16_t*)lds;
   float* dst = lds;
   uint16_t* at = (uint16_t*)lds;
@@ -867,17 +867,7 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
       acc2[h][c] = mfma16(av, bv, acc2[h][c]);
     }
   }
-  __syncthreads();  // the v tile is dead: its LDS becomes the result tile
   const int l16 = lane & 15;
-#pragma unroll
-  for (int h = 0; h < NT; ++h)
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        dst[(h * 16 + 4 * g + r) * PW_J + le_col(h * 16 + 4 * g + r, wave * 64 + c * 16 + l16)] =
-            acc[h][c][r] + acc2[h][c][r];
-  __syncthreads();
   float* hout = a.h ? a.h + b * a.W * a.P + p0 : nullptr;
   uint16_t* act = a.act ? a.act + b * a.W * a.P + p0 : nullptr;
   const float* gm = a.gmul ? a.gmul + b * a.W * a.P + p0 : nullptr;
@@ -885,12 +875,34 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
   // written over the result tile once every thread has read its values
   uint2 wz[8];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
+  for (int q = 0; q < 8; ++q) wz[q] = uint2{0u, 0u};
+  // the two products' sum, formed before the staging so the second half
+  // waits in 16 registers rather than 32
+  f32x4 sum[NT][4];
+#pragma unroll
+  for (int h = 0; h < NT; ++h)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sum[h][c][r] = acc[h][c][r] + acc2[h][c][r];
+  // the result passes through LDS one 16-row half (channel tile hh) at a
+  // time; thread t reads rows wave + 4 qq of the half
+#pragma unroll
+  for (int hh = 0; hh < NT; ++hh) {
+    __syncthreads();  // the v tile, or the previous half, is dead
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        dst[(4 * g + r) * PW_J + le_col(4 * g + r, wave * 64 + c * 16 + l16)] = sum[hh][c][r];
+    __syncthreads();
+#pragma unroll
+  for (int qq = 0; qq < 4; ++qq) {
+    const int q = 4 * hh + qq;
     const int e = t + 256 * q;
-    const int n = e >> 6, p4 = (e & 63) * 4;
-    wz[q] = uint2{0u, 0u};
+    const int n = e >> 6, p4 = (e & 63) * 4, nl = n - 16 * hh;
     if (n >= a.W) continue;
-    float4 v = *(const float4*)(dst + n * PW_J + le_col(n, p4));
+    float4 v = *(const float4*)(dst + nl * PW_J + le_col(nl, p4));
     const int64_t off = (int64_t)n * a.P + p4;
     if (a.bias) {
       const float bb = a.bias[n];
@@ -916,6 +928,7 @@ __global__ __launch_bounds__(256) void layer_end_kernel(LayerEndArgs a) {
     }
     *(uint2*)(act + off) = w;
     wz[q] = w;
+  }
   }
   if (a.a1) {
     __syncthreads();  // the result tile is read: its region becomes the activation tile
