@@ -523,9 +523,10 @@ __device__ __forceinline__ int dyx_t2(int row, int ky, int k) {
   return row * DYX_T2 + ((((k >> 3) ^ ((ky >> 1) & 3))) << 3) + (k & 7);
 }
 
-__global__ __launch_bounds__(512) void dft_yx_kernel(const uint16_t* __restrict__ a1, const uint16_t* __restrict__ f2,
-                                                     const uint16_t* __restrict__ f3, int X,
-                                                     uint16_t* __restrict__ modes) {
+// (four waves per SIMD, 128 registers: two blocks per CU)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void dft_yx_kernel(
+    const uint16_t* __restrict__ a1, const uint16_t* __restrict__ f2, const uint16_t* __restrict__ f3, int X,
+    uint16_t* __restrict__ modes) {
   __shared__ __attribute__((aligned(16))) uint16_t t1[128 * DYX_T1];
   __shared__ __attribute__((aligned(16))) uint16_t t2[512 * DYX_T2];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4, l16 = lane & 15, kl = 8 * g;
@@ -760,6 +761,7 @@ __device__ __forceinline__ int le_col(int row, int p) { return p ^ (((row >> 2) 
 
 // NT = ceil(W / 16), W <= 32; C2R: r2 term present; ROW64: Z = 64, so each
 // wave's 64 points are one (x, y) row and its c2r operands are one R2 row
+// (six waves per SIMD, 80 registers: with 20 KB of LDS, six blocks per CU)
 template <int NT, typename InT, bool C2R = true, bool ROW64 = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void layer_end_kernel(LayerEndArgs a) {
   // one LDS region holds in turn the v tile [256 points][PW_TS], the FP32
@@ -1022,14 +1024,14 @@ __device__ __forceinline__ void proj_act_both(float h, float w0, float& a, float
     da = fmaf(h * 0.39894228f, __builtin_amdgcn_exp2f(-0.72134752f * hc * hc), cdf);
   }
 }
+// (the GELU instances with one k step and no stored activation: four waves
+// per SIMD, 128 registers)
 template <int NT, int KS, bool STORE_A = false, int ACT = 0, bool RES = false>
-__global__ __launch_bounds__(256) void proj_kernel(const uint16_t* __restrict__ v, int W, int64_t P,
-                                                   const uint16_t* __restrict__ Q1p, const float* __restrict__ q1p,
-                                                   const uint16_t* __restrict__ Q2p, const float* __restrict__ q2,
-                                                   int cout, float* __restrict__ y, int H = 0,
-                                                   uint16_t* __restrict__ aout = nullptr, float w0 = 0.f,
-                                                   const uint16_t* __restrict__ resid = nullptr,
-                                                   uint16_t* __restrict__ vout = nullptr) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ACT == 0 && KS == 1 && !STORE_A ? 4 : 1)))
+void proj_kernel(const uint16_t* __restrict__ v, int W, int64_t P, const uint16_t* __restrict__ Q1p,
+                 const float* __restrict__ q1p, const uint16_t* __restrict__ Q2p, const float* __restrict__ q2,
+                 int cout, float* __restrict__ y, int H = 0, uint16_t* __restrict__ aout = nullptr, float w0 = 0.f,
+                 const uint16_t* __restrict__ resid = nullptr, uint16_t* __restrict__ vout = nullptr) {
   constexpr int WP = 32 * KS, VS = WP + 8, HP = 16 * NT, OT = RES ? 2 : 1;
   // Q2 rows padded by 8: the gather of the second-stage operand reads one
   // column of 16 rows at a time, which with unpadded rows of 64 words would
