@@ -252,8 +252,10 @@ __global__ __launch_bounds__(256) void conv_split_reduce_kernel(const float* par
 // the boxes).
 constexpr int CL_TX = 4;
 
+// (the 32-channel instances: three waves per SIMD, 168 registers)
 template <int COB, int CC, int TY, int TZ>
-__global__ __launch_bounds__(256) void conv_lds_kernel(ConvArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(COB == 32 && CC == 32 ? 3 : 1)))
+void conv_lds_kernel(ConvArgs a) {
   constexpr int MT = COB / 16;
   constexpr int HX = CL_TX + 2, HY = TY + 2, HZ = TZ + 2, HALO = HX * HY * HZ;
   constexpr int CP = CC == 32 ? 40 : 8;  // LDS row (channels + padding)
