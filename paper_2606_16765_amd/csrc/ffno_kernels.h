@@ -35,8 +35,10 @@ constexpr int FFNO_NCHUNK = 64;  // most blocks (row chunks) of the weight gradi
 // rows.  IN == 1 or IN % 16 == 0; M in {4, 8, 16}.  Dynamic LDS:
 // M * (16 * (2W + 8) + 8) BF16 for the input tile, reused for the output
 // tile.
+// (at least four waves per SIMD: the register budget the 37 KB tile of
+// W = 32 leaves room for)
 template <int W>
-__global__ __launch_bounds__(256) void axis_mix_kernel(AxisMixArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void axis_mix_kernel(AxisMixArgs a) {
   // KM: the stride of one mode's tile, padded by 16 bytes so that the
   // lanes of a staging store, which differ in the mode, hit different banks
   constexpr int KK = 2 * W, KP = KK + 8, NT = KK / 16, KS = KK / 32, KM = AX_TR * KP + 8;

@@ -405,8 +405,9 @@ constexpr int PW_DS = PW_J + 4;  // padded LDS row of the result tile
 __device__ __forceinline__ int tile_row(int p) { return (p & 7) * 32 + (p >> 3); }
 __device__ __forceinline__ int tile_col(int k, int p) { return ((((k >> 3) ^ (p & 3))) << 3) | (k & 7); }
 
+// (four waves per SIMD, 128 registers: with 33 KB of LDS, four blocks per CU)
 template <typename InT>
-__global__ __launch_bounds__(256) void pw_kernel(PwArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void pw_kernel(PwArgs a) {
   // one LDS buffer: the input tile during the products, then the result
   // tile for the epilogue (33 KB: four blocks per CU)
   __shared__ __attribute__((aligned(16))) float lds[32 * PW_DS];
