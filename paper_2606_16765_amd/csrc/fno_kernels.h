@@ -617,20 +617,28 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void d
 // then writes R2 for those 8 x.  R3's round trip through memory is gone;
 // the k steps run in the two-pass order, so R2 is bitwise the same.  Eight
 // waves: x stage, four column tiles each; y stage, one 16-row tile each.
-constexpr int IXY_T0 = 72;   // t0 row: 64 k3 + 8
-constexpr int IXY_T3 = 72;   // t3 row: 64 k2 + 8
+// Both LDS tiles have unpadded 128-byte rows (80 KB in all, so two blocks
+// share a CU's 160 KB); their eight 16-byte k chunks are XOR-permuted by
+// row / 2, so the 16-byte operand reads of 16 consecutive rows cover all
+// banks.
+constexpr int IXY_T0 = 64;   // t0 row: 64 k3
+constexpr int IXY_T3 = 64;   // t3 row: 64 k2
 
-// t3 element (row = (x - x0) * 16 + kz, k2): the eight 16-byte k2 chunks
+// t0 element (row = (ky, kz), k3)
+__device__ __forceinline__ int ixy_t0(int row, int k) {
+  return row * IXY_T0 + ((((k >> 3) ^ ((row >> 1) & 7))) << 3) + (k & 7);
+}
+// t3 element (row = (x - x0) * 16 + kz, k2): the chunks are further
 // permuted by XOR with x - x0, so that the x-stage stores of the four lane
-// groups (x two apart) hit different banks
+// groups (x two apart) spread over the banks
 __device__ __forceinline__ int ixy_t3(int row, int k) {
-  return row * IXY_T3 + ((((k >> 3) ^ ((row >> 4) & 7))) << 3) + (k & 7);
+  return row * IXY_T3 + ((((k >> 3) ^ ((row >> 1) & 7) ^ ((row >> 4) & 7))) << 3) + (k & 7);
 }
 
-__global__ __launch_bounds__(512) void idft_xy_kernel(const uint16_t* __restrict__ modes,
-                                                      const uint16_t* __restrict__ i3,
-                                                      const uint16_t* __restrict__ i2, int X,
-                                                      uint16_t* __restrict__ r2) {
+// (four waves per SIMD, 128 registers)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void idft_xy_kernel(
+    const uint16_t* __restrict__ modes, const uint16_t* __restrict__ i3, const uint16_t* __restrict__ i2, int X,
+    uint16_t* __restrict__ r2) {
   __shared__ __attribute__((aligned(16))) uint16_t t0[512 * IXY_T0];
   __shared__ __attribute__((aligned(16))) uint16_t t3[128 * IXY_T3];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4, l16 = lane & 15, kl = 8 * g;
@@ -645,7 +653,7 @@ __global__ __launch_bounds__(512) void idft_xy_kernel(const uint16_t* __restrict
     const uint4 v = *(const uint4*)(mi + k3 * 512 + col0);
     const uint32_t u[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-    for (int j = 0; j < 8; ++j) t0[(col0 + j) * IXY_T0 + k3] = (uint16_t)(u[j >> 1] >> (16 * (j & 1)));
+    for (int j = 0; j < 8; ++j) t0[ixy_t0(col0 + j, k3)] = (uint16_t)(u[j >> 1] >> (16 * (j & 1)));
   }
   // y-stage A operand: I2^T rows 16 wave + l16 (n2 = 2 y + part'), both k steps
   bf16x8 ai2[2];
@@ -664,7 +672,7 @@ __global__ __launch_bounds__(512) void idft_xy_kernel(const uint16_t* __restrict
     for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const bf16x8 bv = *(const bf16x8*)(t0 + ((4 * wave + c) * 16 + l16) * IXY_T0 + 32 * ks + kl);
+        const bf16x8 bv = *(const bf16x8*)(t0 + ixy_t0((4 * wave + c) * 16 + l16, 32 * ks + kl));
         a3[c] = mfma16(ai3[ks], bv, a3[c]);
       }
     // lane holds n3 = 2 x0 + 4 g + r (x = x0 + 2 g + r / 2, part = r % 2) of
