@@ -546,19 +546,29 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void d
 #pragma unroll 1
     for (int h = 0; h < 2; ++h) {
       // x in [x0 + 8 h, x0 + 8 h + 8): 16384 contiguous values, item e =
-      // ((xl * 64 + y) * 2 + part) * 2 + q holds kz 8 q .. 8 q + 7
+      // ((xl * 64 + y) * 2 + part) * 2 + q holds kz 8 q .. 8 q + 7; a thread
+      // takes both parts of (xl, y, q), so each t1 store is one 4-byte word
+      // (k1 = 2 y and 2 y + 1)
       const uint16_t* hs = src + (int64_t)(x0 + 8 * h) * 2048;
-      uint4 v[4];
+      uint4 v[2][2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) v[i] = *(const uint4*)(hs + 8 * (t + 512 * i));
+      for (int i = 0; i < 2; ++i) {
+        const int pi = t + 512 * i, q = pi & 1, y = (pi >> 1) & 63, xl = pi >> 7;
+        const int e0 = ((xl * 64 + y) * 2) * 2 + q;  // part 0; part 1 is e0 + 2
+        v[i][0] = *(const uint4*)(hs + 8 * e0);
+        v[i][1] = *(const uint4*)(hs + 8 * (e0 + 2));
+      }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int e = t + 512 * i;
-        const int q = e & 1, part = (e >> 1) & 1, y = (e >> 2) & 63, xl = e >> 8;
-        const uint32_t u[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
+      for (int i = 0; i < 2; ++i) {
+        const int pi = t + 512 * i, q = pi & 1, y = (pi >> 1) & 63, xl = pi >> 7;
+        const uint32_t u0[4] = {v[i][0].x, v[i][0].y, v[i][0].z, v[i][0].w};
+        const uint32_t u1[4] = {v[i][1].x, v[i][1].y, v[i][1].z, v[i][1].w};
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-          t1[(xl * 16 + 8 * q + j) * DYX_T1 + 2 * y + part] = (uint16_t)(u[j >> 1] >> (16 * (j & 1)));
+        for (int j = 0; j < 8; ++j) {
+          const uint32_t a = u0[j >> 1], b = u1[j >> 1];
+          *(uint32_t*)(t1 + (xl * 16 + 8 * q + j) * DYX_T1 + 2 * y) =
+              (j & 1) ? (a >> 16) | (b & 0xffff0000u) : (a & 0xffffu) | (b << 16);
+        }
       }
       __syncthreads();
       f32x4 acc1[4];
