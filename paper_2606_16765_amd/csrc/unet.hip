@@ -474,8 +474,13 @@ static void run_forward(unet_net* n, const uint16_t* x, int B, bool train) {
   for (int l = 3; l >= 0; --l) {
     const int* dc = n->dims[l + 1];
     const int64_t nout = vox(n, l, B) * prev->cout / 8;
-    hipLaunchKernelGGL(upsample_kernel, dim3(nb256(nout)), dim3(256), 0, n->st, prev->a, B, dc[0], dc[1], dc[2],
-                       prev->cout, n->up[l]);
+    const int64_t zg = (int64_t)dc[2] * (prev->cout / 8), ny = dc[1], nbx = 2 * (int64_t)B * dc[0];
+    if (ny <= 65535 && nbx <= 65535)
+      hipLaunchKernelGGL(upsample_block_kernel, dim3((unsigned)((zg + 255) / 256), (unsigned)ny, (unsigned)nbx),
+                         dim3(256), 0, n->st, prev->a, B, dc[0], dc[1], dc[2], prev->cout, n->up[l]);
+    else
+      hipLaunchKernelGGL(upsample_kernel, dim3(nb256(nout)), dim3(256), 0, n->st, prev->a, B, dc[0], dc[1], dc[2],
+                         prev->cout, n->up[l]);
     Blk& ka = n->blk[idec(l, 0)];
     block_fwd(n, ka, B, n->up[l], prev->cout, n->blk[ienc(l, 1)].a, p.widths[l], train);
     Blk& kb = n->blk[idec(l, 1)];

@@ -1064,6 +1064,61 @@ __global__ __launch_bounds__(256) void upsample_kernel(const uint16_t* in, int B
   *(uint4*)(out + e * 8) = pack8(o);
 }
 
+// The same upsampling with each thread on a 2 x 2 block of outputs in
+// (y, z) for one x and 8 channels: the block draws on a 2 x 3 x 3 input
+// neighbourhood (18 loads for 4 outputs instead of 32), loaded once; each
+// output then sums its eight terms in upsample_kernel's order, so the
+// results are the same to the bit.  Grid: (z pair and channel group,
+// y pair, (b, xo)); the host checks B * 2X and Y against the grid limits.
+__global__ __launch_bounds__(256) void upsample_block_kernel(const uint16_t* in, int B, int X, int Y, int Z, int C,
+                                                             uint16_t* out) {
+  const int Xo = 2 * X, Yo = 2 * Y, Zo = 2 * Z, g = C / 8;
+  const int zg = blockIdx.x * 256 + threadIdx.x;
+  if (zg >= Z * g) return;
+  const int zi = zg / g, c0 = (zg - zi * g) * 8;
+  const int yi = blockIdx.y, bx = blockIdx.z;
+  const int b = bx / Xo, xo = bx - b * Xo;
+  int xt[2];
+  up_taps(xo, X, xt[0], xt[1]);
+  // neighbourhood rows: index 0 the lower neighbour, 1 the centre, 2 the
+  // upper neighbour (clamped at the faces as up_taps does)
+  const int ys[3] = {yi > 0 ? yi - 1 : 0, yi, yi + 1 < Y ? yi + 1 : Y - 1};
+  const int zs[3] = {zi > 0 ? zi - 1 : 0, zi, zi + 1 < Z ? zi + 1 : Z - 1};
+  uint4 v[2][3][3];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        v[a][p][q] = *(const uint4*)(in + ((((int64_t)b * X + xt[a]) * Y + ys[p]) * Z + zs[q]) * C + c0);
+  const float w[2] = {0.75f, 0.25f};
+#pragma unroll
+  for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+      // taps of up_taps: the centre first, then the neighbour on this side
+      const int ty[2] = {1, dy ? 2 : 0}, tz[2] = {1, dz ? 2 : 0};
+      float o[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) o[j] = 0.f;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            float f[8];
+            unpack8(v[a][ty[bb]][tz[c]], f);
+            const float wt = w[a] * w[bb] * w[c];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) o[j] += wt * f[j];
+          }
+      const int yo = 2 * yi + dy, zo = 2 * zi + dz;
+      *(uint4*)(out + (((int64_t)bx * Yo + yo) * Zo + zo) * C + c0) = pack8(o);
+    }
+}
+
 // Adjoint weight of one axis: what output 2 i0 - 1 + j (j = 0..5, the
 // window of the input pair i0, i0 + 1) contributes to input x = i0 + i of
 // n.  The input x receives from the outputs 2x and 2x + 1 (3/4 each), 2x - 1
