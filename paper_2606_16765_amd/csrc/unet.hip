@@ -489,6 +489,17 @@ static void run_forward(unet_net* n, const uint16_t* x, int B, bool train) {
   }
 }
 
+// head over the last decoder block's activation a: y [B][cout][P] FP32
+static void launch_head(unet_net* n, const uint16_t* a, int B, float* y) {
+  const unet_params& p = n->p;
+  const int64_t P = (int64_t)p.nx * p.ny * p.nz;
+  if (p.cout == 4)
+    hipLaunchKernelGGL(head_kernel<4>, dim3(nb256(B * P)), dim3(256), 0, n->st, a, P, B, p.widths[0],
+                       n->theta + n->head_w, n->theta + n->head_b, p.cout, y);
+  else
+    hipLaunchKernelGGL(head_kernel<0>, dim3(nb256(B * P)), dim3(256), 0, n->st, a, P, B, p.widths[0],
+                       n->theta + n->head_w, n->theta + n->head_b, p.cout, y);
+}
 static int check_batch(unet_net* n, int B) {
   if (B < 1 || B > n->p.max_batch) return ufail(n, LBM_EINVAL, "batch outside [1, max_batch]");
   return LBM_OK;
@@ -500,8 +511,7 @@ extern "C" int unet_forward(unet_net* n, const uint16_t* x, int32_t B, int32_t t
   run_forward(n, x, B, training != 0);
   const unet_params& p = n->p;
   const int64_t P = (int64_t)p.nx * p.ny * p.nz;
-  hipLaunchKernelGGL(head_kernel, dim3(nb256(B * P)), dim3(256), 0, n->st, n->blk[idec(0, 1)].a, P, B, p.widths[0],
-                     n->theta + n->head_w, n->theta + n->head_b, p.cout, y);
+  launch_head(n, n->blk[idec(0, 1)].a, B, y);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return ufail(n, LBM_EDEVICE, hipGetErrorString(e));
   return LBM_OK;
@@ -575,12 +585,15 @@ extern "C" int unet_loss_grad(unet_net* n, const uint16_t* x, const float* targe
   const int64_t V0 = (int64_t)B * P;
   run_forward(n, x, B, true);
   Blk& last = n->blk[idec(0, 1)];
-  hipLaunchKernelGGL(head_kernel, dim3(nb256(V0)), dim3(256), 0, n->st, last.a, P, B, p.widths[0],
-                     n->theta + n->head_w, n->theta + n->head_b, p.cout, n->y);
+  launch_head(n, last.a, B, n->y);
   // dscal[0]: mask cells, [2]: the loss denominator B * cout * cells, [1]: the loss
   hipLaunchKernelGGL(mask_count_kernel, dim3(1), dim3(1024), 0, n->st, mask, P, (double)B * p.cout, n->dscal);
-  hipLaunchKernelGGL(head_bwd_kernel, dim3(nb256(V0)), dim3(256), 0, n->st, last.a, n->y, target, mask, n->dscal + 2,
-                     P, B, p.widths[0], n->theta + n->head_w, p.cout, last.g, n->dlog, n->hpart);
+  if (p.cout == 4)
+    hipLaunchKernelGGL(head_bwd_kernel<4>, dim3(nb256(V0)), dim3(256), 0, n->st, last.a, n->y, target, mask,
+                       n->dscal + 2, P, B, p.widths[0], n->theta + n->head_w, p.cout, last.g, n->dlog, n->hpart);
+  else
+    hipLaunchKernelGGL(head_bwd_kernel<0>, dim3(nb256(V0)), dim3(256), 0, n->st, last.a, n->y, target, mask,
+                       n->dscal + 2, P, B, p.widths[0], n->theta + n->head_w, p.cout, last.g, n->dlog, n->hpart);
   hipLaunchKernelGGL(head_reduce_kernel, dim3((unsigned)(1 + p.cout)), dim3(256), 0, n->st, n->hpart,
                      (int64_t)nb256(V0), n->dscal + 2, n->dscal + 1, n->grad + n->head_b);
   wgrad(n, 0, B, n->dlog, 8, p.cout, last.a, p.widths[0], nullptr, 0, 1, p.widths[0], n->grad + n->head_w);

@@ -1231,22 +1231,29 @@ __global__ __launch_bounds__(256) void input_kernel(const uint16_t* x, int64_t P
 }
 
 // head: y[b][o][p] = sigmoid(sum_c W[o][c] a[v][c] + bias[o]), FP32
-// channels-first output, W FP32 [cout][C] (C % 8 == 0, cout <= 8)
+// channels-first output, W FP32 [cout][C] (C % 8 == 0, cout <= 8).  CO:
+// cout fixed at compile time (the loops over outputs unrolled, the sums in
+// registers), or 0 for any cout.
+template <int CO>
 __global__ __launch_bounds__(256) void head_kernel(const uint16_t* act, int64_t P, int B, int C, const float* W,
                                                    const float* bias, int cout, float* y) {
+  const int co = CO ? CO : cout;
   const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (v >= (int64_t)B * P) return;
   float s[8];
-  for (int o = 0; o < cout; ++o) s[o] = bias[o];
+#pragma unroll
+  for (int o = 0; o < co; ++o) s[o] = bias[o];
   for (int c0 = 0; c0 < C; c0 += 8) {
     float f[8];
     unpack8(*(const uint4*)(act + v * C + c0), f);
-    for (int o = 0; o < cout; ++o)
+#pragma unroll
+    for (int o = 0; o < co; ++o)
 #pragma unroll
       for (int j = 0; j < 8; ++j) s[o] += W[o * C + c0 + j] * f[j];
   }
   const int64_t b = v / P, p = v % P;
-  for (int o = 0; o < cout; ++o) y[(b * cout + o) * P + p] = 1.f / (1.f + expf(-s[o]));
+#pragma unroll
+  for (int o = 0; o < co; ++o) y[(b * co + o) * P + p] = 1.f / (1.f + expf(-s[o]));
 }
 
 // number of nonzero mask cells (one block; integer counts, so the result
@@ -1289,10 +1296,12 @@ __global__ __launch_bounds__(1024) void mask_count_kernel(const uint8_t* mask, i
 // (zero beyond cout; the operand of the head's weight gradient);
 // gact[v][c] = sum_o W[o][c] dlogit[o] (FP32); per block partials of the
 // loss numerator and of the bias gradient: part[blk][0], part[blk][1 + o].
+template <int CO>  // as for head_kernel
 __global__ __launch_bounds__(256) void head_bwd_kernel(const uint16_t* act, const float* y, const float* t,
                                                        const uint8_t* mask, const double* cnt, int64_t P, int B, int C,
-                                                       const float* W, int cout, float* gact, uint16_t* dlog,
+                                                       const float* W, int cout_rt, float* gact, uint16_t* dlog,
                                                        float* part) {
+  const int cout = CO ? CO : cout_rt;
   __shared__ float sm[256][9];
   const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
   for (int i = 0; i < 9; ++i) sm[threadIdx.x][i] = 0.f;
@@ -1302,6 +1311,7 @@ __global__ __launch_bounds__(256) void head_bwd_kernel(const uint16_t* act, cons
     const bool in = mask[p] != 0;
     float dl[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float loss = 0.f;
+#pragma unroll
     for (int o = 0; o < cout; ++o) {
       const float yy = y[(b * cout + o) * P + p];
       const float d = in ? yy - t[(b * cout + o) * P + p] : 0.f;
@@ -1315,6 +1325,7 @@ __global__ __launch_bounds__(256) void head_bwd_kernel(const uint16_t* act, cons
       float g[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) g[j] = 0.f;
+#pragma unroll
       for (int o = 0; o < cout; ++o)
 #pragma unroll
         for (int j = 0; j < 8; ++j) g[j] += W[o * C + c0 + j] * dl[o];

@@ -103,12 +103,14 @@ def _grad_errors(cfg, B, seed=2, beta=None, max_batch=None):
     return errs
 
 
-@pytest.mark.parametrize("cfg", [SMALL, PROD], ids=["small", "prod_widths"])
+@pytest.mark.parametrize("cfg", [SMALL, PROD, dict(SMALL, cout=3)], ids=["small", "prod_widths", "three_outputs"])
 def test_gradients_match_oracle_with_open_relus(cfg):
     """Every parameter group element by element with the ReLUs held open
     (batch-norm shifts +10), plus the running statistics after the
     training pass.  PROD: the App. A.2 widths (32 ... 256, bottleneck 512),
-    every convolution and batch-norm kernel instance the surrogate trains."""
+    every convolution and batch-norm kernel instance the surrogate trains.
+    Three outputs: the head kernels' path for an output count other than
+    the four fields."""
     errs = _grad_errors(cfg, 2, beta=10.0)
     assert errs["loss"] < 1e-4
     assert errs["running_mean"] < 4e-3 and errs["running_var"] < 4e-3
