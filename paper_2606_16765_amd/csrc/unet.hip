@@ -588,7 +588,10 @@ extern "C" int unet_loss_grad(unet_net* n, const uint16_t* x, const float* targe
   launch_head(n, last.a, B, n->y);
   // dscal[0]: mask cells, [2]: the loss denominator B * cout * cells, [1]: the loss
   hipLaunchKernelGGL(mask_count_kernel, dim3(1), dim3(1024), 0, n->st, mask, P, (double)B * p.cout, n->dscal);
-  if (p.cout == 4)
+  if (p.cout == 4 && p.widths[0] == 32)
+    hipLaunchKernelGGL((head_bwd_grouped_kernel<4, 4>), dim3(nb256(V0)), dim3(1024), 0, n->st, last.a, n->y, target,
+                       mask, n->dscal + 2, P, B, n->theta + n->head_w, last.g, n->dlog, n->hpart);
+  else if (p.cout == 4)
     hipLaunchKernelGGL(head_bwd_kernel<4>, dim3(nb256(V0)), dim3(256), 0, n->st, last.a, n->y, target, mask,
                        n->dscal + 2, P, B, p.widths[0], n->theta + n->head_w, p.cout, last.g, n->dlog, n->hpart);
   else

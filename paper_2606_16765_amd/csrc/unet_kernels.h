@@ -1342,6 +1342,61 @@ __global__ __launch_bounds__(256) void head_bwd_kernel(const uint16_t* act, cons
   }
 }
 
+// The same adjoint with G = C / 8 threads per voxel (256 voxels per block
+// of 256 G threads), thread cg of a voxel forming channels 8 cg .. 8 cg + 7
+// of gact: a wave's stores cover whole contiguous rows instead of one
+// 16-byte piece per 128-byte row.  Every value and partial is formed as in
+// head_bwd_kernel (the partials over the same 256 voxels, in the same order).
+template <int CO, int G>
+__global__ __launch_bounds__(256 * G) void head_bwd_grouped_kernel(const uint16_t* act, const float* y, const float* t,
+                                                                   const uint8_t* mask, const double* cnt, int64_t P,
+                                                                   int B, const float* W, float* gact, uint16_t* dlog,
+                                                                   float* part) {
+  constexpr int C = 8 * G;
+  __shared__ float sm[256][9];
+  const int vl = threadIdx.x / G, cg = threadIdx.x % G;
+  const int64_t v = (int64_t)blockIdx.x * 256 + vl;
+  if (cg == 0)
+    for (int i = 0; i < 9; ++i) sm[vl][i] = 0.f;
+  if (v < (int64_t)B * P) {
+    const int64_t b = v / P, p = v % P;
+    const float inv = cnt[0] > 0.0 ? (float)(2.0 / cnt[0]) : 0.f;
+    const bool in = mask[p] != 0;
+    float dl[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float loss = 0.f;
+#pragma unroll
+    for (int o = 0; o < CO; ++o) {
+      const float yy = y[(b * CO + o) * P + p];
+      const float d = in ? yy - t[(b * CO + o) * P + p] : 0.f;
+      loss += d * d;
+      dl[o] = d * inv * yy * (1.f - yy);
+    }
+    if (cg == 0) {
+#pragma unroll
+      for (int o = 0; o < CO; ++o) sm[vl][1 + o] = dl[o];
+      sm[vl][0] = loss;
+      *(uint4*)(dlog + v * 8) = pack8(dl);
+    }
+    const int c0 = 8 * cg;
+    float g[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) g[j] = 0.f;
+#pragma unroll
+    for (int o = 0; o < CO; ++o)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) g[j] += W[o * C + c0 + j] * dl[o];
+    float* gp = gact + v * C + c0;
+    *(float4*)gp = float4{g[0], g[1], g[2], g[3]};
+    *(float4*)(gp + 4) = float4{g[4], g[5], g[6], g[7]};
+  }
+  __syncthreads();
+  if (threadIdx.x < 1 + CO) {
+    float s = 0.f;
+    for (int k = 0; k < 256; ++k) s += sm[k][threadIdx.x];
+    part[(int64_t)blockIdx.x * 9 + threadIdx.x] = s;
+  }
+}
+
 // sums of the head partials over blocks in a fixed order: the loss (divided
 // by cnt) and the bias gradient; one block per entry (entry 0 the loss)
 __global__ __launch_bounds__(256) void head_reduce_kernel(const float* part, int64_t nblk, const double* cnt,
